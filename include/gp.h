@@ -1,0 +1,223 @@
+/*
+ * gp.h -- C ABI of the MI355X (gfx950) pattern-embedding counting library.
+ *
+ * The library counts the embeddings of a small connected unlabeled pattern in
+ * a large undirected data graph, following GraphPi (arXiv 2009.10955):
+ *   - Section II-A defines the problem: the number of distinct subgraphs of
+ *     the data graph that are edge-preserving bijective images of the pattern
+ *     (non-induced: extra data edges among the image vertices are allowed);
+ *   - Section IV-A (Algorithm 1) generates restriction sets (id(a) > id(b)
+ *     pairs) that make every embedding be found exactly once;
+ *   - Section IV-B filters schedules (matching orders) in two phases;
+ *   - Section IV-C ranks (schedule, restriction set) configurations with a
+ *     nested cost model;
+ *   - Sections II-B and IV-B describe the nested-loop search whose candidate
+ *     sets are intersections of sorted neighbor lists cut by the restrictions.
+ * The users' view matches Section III: a pattern and a graph in the form of
+ * adjacency lists in, a count out.
+ *
+ * Conventions for every call:
+ *   - Return value: GP_OK (0) or a negative gp_status. On error, out-params
+ *     are left untouched and nothing is leaked.
+ *   - Ownership: input buffers stay the caller's and may be freed as soon as
+ *     the call returns. Graph and plan handles are owned by the library until
+ *     the matching gp_free_* call. Handles are immutable after creation, so
+ *     concurrent counts on different streams with the same handles are legal.
+ *   - Streams: a hipStream_t is passed as void* (0 = the null stream). Work is
+ *     ordered on that stream; calls documented as blocking synchronise it.
+ *   - Vertex ids and pattern vertices are zero-based.
+ */
+#ifndef GP_H
+#define GP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gp_status;
+
+enum {
+    GP_OK = 0,
+    GP_ERR_ARG = -1,             /* bad argument (null pointer, size out of range, bad option) */
+    GP_ERR_CSR_UNSORTED = -2,    /* a neighbor list is not ascending, or row_ptr decreases */
+    GP_ERR_CSR_ASYMMETRIC = -3,  /* (u,v) stored without (v,u) */
+    GP_ERR_CSR_SELFLOOP = -4,    /* (v,v) stored */
+    GP_ERR_CSR_DUPLICATE = -5,   /* a neighbor stored twice in one list */
+    GP_ERR_PATTERN = -6,         /* pattern with k<2, k>GP_MAX_K, a self-loop, a repeated edge,
+                                    a vertex id out of range, or not connected */
+    GP_ERR_NOMEM = -7,           /* device or host allocation failed */
+    GP_ERR_HIP = -8,             /* a HIP runtime call failed */
+    GP_ERR_OVERFLOW = -9,        /* the true count does not fit in 64 bits */
+    GP_ERR_BUDGET = -10,         /* predicted cost above the caller's cap */
+    GP_ERR_CSR_RANGE = -11,      /* a column index outside [0, n) or row_ptr[0] != 0 */
+    GP_ERR_UNSUPPORTED = -12     /* option or shape not built into this library */
+};
+
+#define GP_MAX_K 8
+
+/* ------------------------------------------------------------------ graph */
+
+typedef struct gp_graph gp_graph;
+
+/* gp_load_graph flags */
+#define GP_IN_DEVICE 1u  /* row_ptr and col point to device memory (e.g. torch tensors) */
+
+typedef struct {
+    int64_t n;            /* vertices */
+    int64_t m;            /* undirected edges (nnz / 2) */
+    int64_t max_degree;
+    uint64_t tri_cnt;     /* ordered triangles = 6 x triangles: the tri_cnt input of the
+                             cardinality estimates (Section IV-C) */
+    uint64_t hash;        /* 64-bit content hash of the input CSR (cache key) */
+    double load_seconds;  /* wall time of gp_load_graph */
+} gp_stats;
+
+/*
+ * Load an undirected simple graph given as CSR (Section IV-E: each neighbor
+ * list sorted and contiguous): row_ptr[n+1] (int64, row_ptr[0] == 0) and
+ * col[nnz] (int32), with both directions of every edge stored, no self-loops
+ * and no duplicates. Host pointers by default, device pointers with
+ * GP_IN_DEVICE; either way the library copies what it needs.
+ * On the device the graph is validated (GP_ERR_CSR_* on failure), relabelled
+ * by descending degree (ties by ascending id), each list re-sorted, and its
+ * triangle count computed for the cost model. Blocking on `stream`.
+ */
+gp_status gp_load_graph(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz,
+                        uint32_t flags, void* stream, gp_graph** out);
+
+gp_status gp_graph_stats(const gp_graph* g, gp_stats* out);
+
+/* Copy the relabelling to host memory: new_id[v] = id of original vertex v
+ * in the device layout (n entries, caller-allocated). */
+gp_status gp_graph_new_id(const gp_graph* g, int32_t* new_id);
+
+/* Copy the device layout to host memory (caller-allocated, n+1 and nnz
+ * entries): the relabelled CSR that the counting kernels read. */
+gp_status gp_graph_layout(const gp_graph* g, int64_t* row_ptr, int32_t* col);
+
+void gp_free_graph(gp_graph* g);
+
+/* ------------------------------------------------------------------- plan */
+
+typedef struct gp_plan gp_plan;
+
+typedef struct {
+    int64_t max_states;          /* cap on distinct restriction sets visited by Algorithm 1
+                                    (0 = default 4,000,000) */
+    int32_t max_sets;            /* cap on valid restriction sets kept (0 = default 100,000) */
+    int32_t force_order[GP_MAX_K]; /* if force_order[0] >= 0: use this schedule (must pass
+                                    Phase 1; Phase 2 is not required) */
+    int32_t force_set;           /* if >= 0: use the force_set-th valid set (emission order) */
+    int32_t n_force_restr;       /* if > 0: use these pairs instead (validated) */
+    int32_t force_restr[2 * GP_MAX_K * GP_MAX_K];
+    double cost_cap;             /* if > 0: GP_ERR_BUDGET when the best predicted cost exceeds it */
+} gp_plan_opts;
+
+/* Fill opts with the defaults (nothing forced, no cap). */
+void gp_plan_opts_default(gp_plan_opts* opts);
+
+/*
+ * Plan a pattern with k vertices and e edges (edges[2*i], edges[2*i+1]).
+ * Host only. Steps: automorphisms (Section IV-A), restriction sets by
+ * Algorithm 1 (each kept as its transitive closure), efficient schedules by
+ * the two phases of Section IV-B, then the configuration with the lowest
+ * predicted cost under the model of Section IV-C, evaluated with `stats`
+ * (null: |V| = 1e6, |E| = 1e7, tri_cnt = 6e7). Ties of predicted cost go to
+ * the set with more upper-bound cuts (a later vertex bounded above by an
+ * earlier one), then the lexicographically smaller schedule, then the earlier
+ * set. The result is compiled into a device-ready plan descriptor.
+ */
+gp_status gp_plan_create(const int32_t* edges, int32_t k, int32_t e, const gp_stats* stats,
+                         const gp_plan_opts* opts, gp_plan** out);
+
+typedef struct {
+    int32_t k;
+    int32_t order[GP_MAX_K];   /* schedule: pattern vertex searched at level i */
+    int32_t n_restr;           /* pairs in the applied restriction set (transitive closure) */
+    int32_t restr[2 * GP_MAX_K * GP_MAX_K]; /* (a, b) means id(a) > id(b), pattern vertices */
+    uint64_t aut;              /* |Aut(P)| */
+    double cost;               /* predicted cost_1 of the chosen configuration */
+    int32_t n_sets;            /* valid restriction sets found by Algorithm 1 */
+    int64_t n_states;          /* distinct sets visited by Algorithm 1 */
+    int32_t n_schedules;       /* efficient schedules (Phase 1 + Phase 2) */
+    int32_t k_eff;             /* Phase-2 k actually used */
+    int32_t set_index;         /* index of the chosen set in emission order (-1 if forced pairs) */
+    double plan_seconds;       /* host wall time of gp_plan_create */
+} gp_plan_info;
+
+gp_status gp_plan_get(const gp_plan* p, gp_plan_info* out);
+
+/* The idx-th valid restriction set in emission order, as closure pairs
+ * (restr must hold 2*GP_MAX_K*GP_MAX_K ints). */
+gp_status gp_plan_get_set(const gp_plan* p, int32_t idx, int32_t* n_restr, int32_t* restr);
+
+/* The idx-th efficient schedule (order must hold k ints). */
+gp_status gp_plan_get_schedule(const gp_plan* p, int32_t idx, int32_t* order);
+
+/* Predicted cost_1 of (schedule idx_s, restriction set idx_r) under `stats`. */
+gp_status gp_plan_model_cost(const gp_plan* p, int32_t idx_s, int32_t idx_r,
+                             const gp_stats* stats, double* cost);
+
+void gp_free_plan(gp_plan* p);
+
+/* ------------------------------------------------------------------ count */
+
+typedef struct {
+    int32_t group;         /* lanes that share one search path: 64, 32, 16 or 8 (0 = auto) */
+    int32_t waves_per_cu;  /* resident wavefronts per compute unit for the persistent grid
+                              (0 = auto) */
+    int32_t chunk;         /* root tasks taken per queue grab (0 = auto) */
+    int32_t leaf_mode;     /* 0 auto, 1: lanes take different second-to-last candidates and
+                              count the last level alone, 2: the group counts each one together */
+} gp_launch;
+
+void gp_launch_default(gp_launch* l);
+
+/*
+ * Count the embeddings of plan p in graph g (exact, unsigned 64-bit).
+ * One persistent kernel launch on `stream`: wavefront groups take root edges
+ * (the first two schedule levels) from an atomic queue and search the
+ * remaining levels depth first. Blocking: synchronises `stream` and writes
+ * *out on the host. GP_ERR_OVERFLOW if the count does not fit in 64 bits.
+ * `launch` may be null (auto).
+ */
+gp_status gp_count(const gp_graph* g, const gp_plan* p, const gp_launch* launch, void* stream,
+                   uint64_t* out);
+
+/* As gp_count, without host synchronisation: dev_out (device memory, 2
+ * uint64) receives {count, overflow flag} when the stream reaches it. */
+gp_status gp_count_async(const gp_graph* g, const gp_plan* p, const gp_launch* launch,
+                         void* stream, uint64_t* dev_out);
+
+/*
+ * Per-root counts, for verification: dev_per_root (device memory, one uint64
+ * per directed CSR entry of the device layout, nnz entries) receives, at the
+ * index of the layout entry (v0, v1), the number of embeddings whose first
+ * two schedule levels map to v0 and v1 (zero where the entry is not a root).
+ * Blocking; *out receives the total.
+ */
+gp_status gp_count_per_root(const gp_graph* g, const gp_plan* p, const gp_launch* launch,
+                            void* stream, uint64_t* dev_per_root, uint64_t* out);
+
+/*
+ * Count several plans over one graph in ONE persistent launch: the task space
+ * is the union over plans of their root edges, handed out from one atomic
+ * queue, so plans of uneven cost share the machine. out[i] = count of
+ * plans[i] (host memory). Blocking. Counts equal gp_count's bit for bit.
+ */
+gp_status gp_count_batch(const gp_graph* g, const gp_plan* const* plans, int32_t np,
+                         const gp_launch* launch, void* stream, uint64_t* out);
+
+/* Human-readable name of a status code (static string). */
+const char* gp_strerror(gp_status s);
+
+/* Library version string (static). */
+const char* gp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GP_H */

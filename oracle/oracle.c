@@ -16,9 +16,10 @@
  *   - pinned vertices: fix id(u) = x for given pattern vertices, so that a
  *     count can be split into independently checkable parts.
  *
- * Method: backtracking over pattern vertices in a BFS order. A candidate for a
- * vertex is any neighbor of the image of one earlier pattern neighbor (or any
- * data vertex if it has none). Every candidate is checked against every
+ * Method: backtracking over pattern vertices, the most-constrained vertex
+ * (most already-placed pattern neighbors) first. A candidate for a vertex is
+ * any neighbor of the image of one earlier pattern neighbor -- the one with
+ * the shortest list -- or any data vertex if it has none. Every candidate is checked against every
  * pattern edge to an earlier vertex (binary search in the sorted adjacency
  * list), against injectivity, and against every restriction pair. There are
  * no set intersections, no schedules and no restriction-derived bounds here.
@@ -98,7 +99,13 @@ static u128 extend(const job_t *J, int t, int32_t *img) {
             total += extend(J, t + 1, img);
         }
     } else {
+        /* scan the shortest neighbor list among the placed pattern neighbors;
+         * acceptable() still checks every pattern edge */
         int32_t a = img[J->anchor[t]];
+        for (int q = 0; q < J->nback[t]; ++q) {
+            int32_t b = img[J->back[t][q]];
+            if (J->row_ptr[b + 1] - J->row_ptr[b] < J->row_ptr[a + 1] - J->row_ptr[a]) a = b;
+        }
         for (int64_t e = J->row_ptr[a]; e < J->row_ptr[a + 1]; ++e) {
             int32_t x = J->col[e];
             if (!acceptable(J, t, img, x)) continue;
@@ -182,11 +189,15 @@ int oracle_count_maps(const int64_t *row_ptr, const int32_t *col, int32_t n,
     }
     J->npin = npin;
     while (t < k) {
-        int pick = -1;
-        for (int u = 0; u < k && pick < 0; ++u) {
+        /* the unplaced vertex with the most placed neighbors (smallest id on
+         * ties); with none adjacent, the smallest unplaced vertex */
+        int pick = -1, best = 0;
+        for (int u = 0; u < k; ++u) {
             if (placed[u]) continue;
+            int c = 0;
             for (int w = 0; w < k; ++w)
-                if (placed[w] && adj[u][w]) { pick = u; break; }
+                if (placed[w] && adj[u][w]) ++c;
+            if (c > best) { best = c; pick = u; }
         }
         if (pick < 0)
             for (int u = 0; u < k; ++u)

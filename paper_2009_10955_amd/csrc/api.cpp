@@ -1,0 +1,499 @@
+// C ABI (include/gp.h): argument checking, ownership, and the glue between
+// the host planner and the device kernels.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "gp.h"
+#include "internal.hpp"
+#include "planner.hpp"
+
+namespace gpint {
+gp_status build_layout(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz,
+                       hipStream_t s, DeviceGraph* g);
+}
+
+struct gp_graph {
+    gpint::DeviceGraph dg;
+};
+
+struct gp_plan {
+    gp::Pattern pattern;
+    uint64_t aut = 0;
+    std::vector<gp::Rel> sets;
+    std::vector<gp::Perm> schedules;
+    gp::Perm order{};
+    gp::Rel set = 0;
+    GpPlanDesc desc{};
+    gp_plan_info info{};
+};
+
+namespace {
+
+double now_seconds() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    bool changed = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) {
+            changed = hipSetDevice(dev) == hipSuccess;
+        }
+    }
+    ~DeviceGuard() {
+        if (changed) (void)hipSetDevice(prev);
+    }
+};
+
+void free_device_graph(gpint::DeviceGraph& g) {
+    (void)hipFree(g.row_ptr);
+    (void)hipFree(g.col);
+    (void)hipFree(g.roots_all);
+    (void)hipFree(g.roots_lower);
+    (void)hipFree(g.roots_upper);
+    (void)hipFree(g.new_id);
+    g = gpint::DeviceGraph{};
+}
+
+// Triangle plan: schedule (0,1,2), restrictions id(0) > id(1) > id(2).
+gp_status triangle_desc(GpPlanDesc* d) {
+    const int32_t e[6] = {0, 1, 1, 2, 2, 0};
+    gp::Pattern p;
+    if (gp::parse_pattern(e, 3, 3, &p)) return GP_ERR_PATTERN;
+    gp::Perm order{};
+    for (int i = 0; i < 3; ++i) order[i] = uint8_t(i);
+    gp::Rel r = gp::closure(gp::rel_bit(0, 1) | gp::rel_bit(1, 2), 3);
+    return gp::compile_plan(p, order, r, d) == 0 ? GP_OK : GP_ERR_PATTERN;
+}
+
+gp_status count_to_host(const gp_graph* g, const GpPlanDesc& d, const gpint::LaunchCfg& cfg,
+                        hipStream_t s, unsigned long long* per_root, uint64_t* out) {
+    unsigned long long* res = nullptr;
+    GP_HIP_TRY(hipMallocAsync((void**)&res, 2 * sizeof(unsigned long long), s));
+    gp_status st = gpint::launch_count(g->dg, d, cfg, s, res, per_root);
+    unsigned long long h[2] = {0, 0};
+    if (st == GP_OK) {
+        if (hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, s) != hipSuccess) st = GP_ERR_HIP;
+    }
+    (void)hipFreeAsync(res, s);
+    if (hipStreamSynchronize(s) != hipSuccess && st == GP_OK) st = GP_ERR_HIP;
+    if (st != GP_OK) return st;
+    if (h[1]) return GP_ERR_OVERFLOW;
+    *out = h[0];
+    return GP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gp_version(void) { return "gp-mi355x 0.1 (gfx950)"; }
+
+const char* gp_strerror(gp_status s) {
+    switch (s) {
+        case GP_OK: return "ok";
+        case GP_ERR_ARG: return "invalid argument";
+        case GP_ERR_CSR_UNSORTED: return "CSR neighbor list not ascending or row_ptr decreasing";
+        case GP_ERR_CSR_ASYMMETRIC: return "CSR not symmetric";
+        case GP_ERR_CSR_SELFLOOP: return "CSR has a self-loop";
+        case GP_ERR_CSR_DUPLICATE: return "CSR has a duplicate entry";
+        case GP_ERR_PATTERN: return "invalid pattern";
+        case GP_ERR_NOMEM: return "out of memory";
+        case GP_ERR_HIP: return "HIP runtime error";
+        case GP_ERR_OVERFLOW: return "count does not fit in 64 bits";
+        case GP_ERR_BUDGET: return "predicted cost above the cap";
+        case GP_ERR_CSR_RANGE: return "CSR index out of range";
+        case GP_ERR_UNSUPPORTED: return "unsupported option or shape";
+        default: return "unknown status";
+    }
+}
+
+gp_status gp_load_graph(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz,
+                        uint32_t flags, void* stream, gp_graph** out) {
+    if (!out || n < 0 || nnz < 0 || !row_ptr || (nnz > 0 && !col)) return GP_ERR_ARG;
+    if (flags & ~GP_IN_DEVICE) return GP_ERR_ARG;
+    if (n >= 0x7fffffff || nnz >= 0x7fffffff) return GP_ERR_UNSUPPORTED;
+    const double t0 = now_seconds();
+    hipStream_t s = (hipStream_t)stream;
+    gp_graph* g = new (std::nothrow) gp_graph;
+    if (!g) return GP_ERR_NOMEM;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        delete g;
+        return GP_ERR_HIP;
+    }
+    g->dg.device = dev;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        delete g;
+        return GP_ERR_HIP;
+    }
+    g->dg.num_cus = cus;
+
+    const int64_t* d_row = row_ptr;
+    const int32_t* d_col = col;
+    int64_t* own_row = nullptr;
+    int32_t* own_col = nullptr;
+    gp_status st = GP_OK;
+    int64_t ends[2] = {0, 0};
+    if (!(flags & GP_IN_DEVICE)) {
+        ends[0] = row_ptr[0];
+        ends[1] = row_ptr[n];
+        if (hipMalloc((void**)&own_row, sizeof(int64_t) * (n + 1)) != hipSuccess ||
+            hipMalloc((void**)&own_col, sizeof(int32_t) * (nnz > 0 ? nnz : 1)) != hipSuccess) {
+            st = GP_ERR_NOMEM;
+        } else if (hipMemcpyAsync(own_row, row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s) !=
+                       hipSuccess ||
+                   (nnz > 0 && hipMemcpyAsync(own_col, col, sizeof(int32_t) * nnz, hipMemcpyHostToDevice,
+                                              s) != hipSuccess)) {
+            st = GP_ERR_HIP;
+        }
+        d_row = own_row;
+        d_col = own_col;
+    } else {
+        if (hipMemcpyAsync(&ends[0], row_ptr, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(&ends[1], row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            st = GP_ERR_HIP;
+    }
+    if (st == GP_OK && (ends[0] != 0 || ends[1] != nnz)) st = GP_ERR_CSR_RANGE;
+    if (st == GP_OK) st = gpint::build_layout(d_row, d_col, n, nnz, s, &g->dg);
+    if (own_row || own_col) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(own_row);
+        (void)hipFree(own_col);
+    }
+    if (st == GP_OK && nnz > 0) {
+        GpPlanDesc tri;
+        st = triangle_desc(&tri);
+        if (st == GP_OK) {
+            gpint::LaunchCfg cfg;
+            cfg.group = 16;
+            cfg.waves_per_cu = 16;
+            cfg.chunk = 256;
+            cfg.leaf = 1;
+            uint64_t t = 0;
+            st = count_to_host(g, tri, cfg, s, nullptr, &t);
+            g->dg.stats.tri_cnt = 6 * t;
+        }
+    }
+    if (st != GP_OK) {
+        (void)hipStreamSynchronize(s);
+        free_device_graph(g->dg);
+        delete g;
+        return st;
+    }
+    g->dg.stats.load_seconds = now_seconds() - t0;
+    *out = g;
+    return GP_OK;
+}
+
+gp_status gp_graph_stats(const gp_graph* g, gp_stats* out) {
+    if (!g || !out) return GP_ERR_ARG;
+    *out = g->dg.stats;
+    return GP_OK;
+}
+
+gp_status gp_graph_new_id(const gp_graph* g, int32_t* new_id) {
+    if (!g || !new_id) return GP_ERR_ARG;
+    if (g->dg.n == 0) return GP_OK;
+    DeviceGuard dgd(g->dg.device);
+    GP_HIP_TRY(hipMemcpy(new_id, g->dg.new_id, sizeof(int32_t) * g->dg.n, hipMemcpyDeviceToHost));
+    return GP_OK;
+}
+
+gp_status gp_graph_layout(const gp_graph* g, int64_t* row_ptr, int32_t* col) {
+    if (!g || !row_ptr || (g->dg.nnz > 0 && !col)) return GP_ERR_ARG;
+    DeviceGuard dgd(g->dg.device);
+    GP_HIP_TRY(hipMemcpy(row_ptr, g->dg.row_ptr, sizeof(int64_t) * (g->dg.n + 1), hipMemcpyDeviceToHost));
+    if (g->dg.nnz > 0)
+        GP_HIP_TRY(hipMemcpy(col, g->dg.col, sizeof(int32_t) * g->dg.nnz, hipMemcpyDeviceToHost));
+    return GP_OK;
+}
+
+void gp_free_graph(gp_graph* g) {
+    if (!g) return;
+    DeviceGuard dgd(g->dg.device);
+    (void)hipDeviceSynchronize();
+    free_device_graph(g->dg);
+    delete g;
+}
+
+void gp_plan_opts_default(gp_plan_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->force_order[0] = -1;
+    o->force_set = -1;
+}
+
+gp_status gp_plan_create(const int32_t* edges, int32_t k, int32_t e, const gp_stats* stats,
+                         const gp_plan_opts* opts, gp_plan** out) {
+    if (!out) return GP_ERR_ARG;
+    const double t0 = now_seconds();
+    gp_plan_opts o;
+    gp_plan_opts_default(&o);
+    if (opts) o = *opts;
+    gp::Pattern pat;
+    int rc = gp::parse_pattern(edges, k, e, &pat);
+    if (rc) return rc;
+    if (o.max_states < 0 || o.max_sets < 0) return GP_ERR_ARG;
+    const int64_t max_states = o.max_states ? o.max_states : 4000000;
+    const int32_t max_sets = o.max_sets ? o.max_sets : 100000;
+
+    gp_plan* p = new (std::nothrow) gp_plan;
+    if (!p) return GP_ERR_NOMEM;
+    p->pattern = pat;
+    auto auts = gp::automorphisms(pat);
+    p->aut = auts.size();
+    gp::RestrictionSets rs = gp::restriction_sets(pat, auts, max_states, max_sets);
+    p->sets = rs.sets;
+    gp::Schedules sc = gp::efficient_schedules(pat);
+    p->schedules = sc.orders;
+
+    // candidate schedules
+    std::vector<gp::Perm> cand_orders;
+    if (o.force_order[0] >= 0) {
+        gp::Perm ord{};
+        unsigned seen = 0;
+        for (int i = 0; i < k; ++i) {
+            int v = o.force_order[i];
+            if (v < 0 || v >= k || (seen & (1u << v))) {
+                delete p;
+                return GP_ERR_ARG;
+            }
+            seen |= 1u << v;
+            ord[i] = uint8_t(v);
+        }
+        if (!gp::phase1_ok(pat, ord)) {
+            delete p;
+            return GP_ERR_ARG;
+        }
+        cand_orders.push_back(ord);
+    } else {
+        cand_orders = p->schedules;
+    }
+    // candidate restriction sets
+    std::vector<gp::Rel> cand_sets;
+    std::vector<int> cand_index;
+    if (o.n_force_restr > 0) {
+        if (o.n_force_restr > GP_MAX_K * GP_MAX_K) {
+            delete p;
+            return GP_ERR_ARG;
+        }
+        gp::Rel r = 0;
+        for (int i = 0; i < o.n_force_restr; ++i) {
+            int a = o.force_restr[2 * i], b = o.force_restr[2 * i + 1];
+            if (a < 0 || a >= k || b < 0 || b >= k) {
+                delete p;
+                return GP_ERR_ARG;
+            }
+            r |= gp::rel_bit(a, b);
+        }
+        r = gp::closure(r, k);
+        if (!gp::acyclic(r, k) || !gp::validate(r, k, p->aut)) {
+            delete p;
+            return GP_ERR_ARG;
+        }
+        // Also require that every non-identity automorphism is eliminated.
+        for (size_t i = 1; i < auts.size(); ++i)
+            if (gp::no_conflict(auts[i], r, k)) {
+                delete p;
+                return GP_ERR_ARG;
+            }
+        cand_sets.push_back(r);
+        cand_index.push_back(-1);
+    } else if (o.force_set >= 0) {
+        if (o.force_set >= (int32_t)p->sets.size()) {
+            delete p;
+            return GP_ERR_ARG;
+        }
+        cand_sets.push_back(p->sets[o.force_set]);
+        cand_index.push_back(o.force_set);
+    } else {
+        for (size_t i = 0; i < p->sets.size(); ++i) {
+            cand_sets.push_back(p->sets[i]);
+            cand_index.push_back(int(i));
+        }
+    }
+    if (cand_sets.empty() || cand_orders.empty()) {
+        delete p;
+        return GP_ERR_UNSUPPORTED;
+    }
+
+    gp::GraphStats gs{1e6, 1e7, 6e7};
+    if (stats && stats->n > 0 && stats->m > 0) {
+        gs.n_v = double(stats->n);
+        gs.n_e = double(stats->m);
+        gs.tri_cnt = double(stats->tri_cnt);
+    }
+    double best = 0;
+    int best_cuts = -1;
+    size_t bo = 0, bs = 0;
+    bool have = false;
+    for (size_t i = 0; i < cand_orders.size(); ++i) {
+        for (size_t j = 0; j < cand_sets.size(); ++j) {
+            double c = gp::model_cost(pat, cand_orders[i], cand_sets[j], gs);
+            int cuts = gp::upper_cuts(cand_orders[i], cand_sets[j], k);
+            bool better;
+            if (!have) {
+                better = true;
+            } else {
+                double tol = 1e-9 * std::max(std::abs(best), std::abs(c));
+                if (c < best - tol) better = true;
+                else if (c > best + tol) better = false;
+                else better = cuts > best_cuts;  // schedules/sets visited in order: earlier wins ties
+            }
+            if (better) {
+                best = c;
+                best_cuts = cuts;
+                bo = i;
+                bs = j;
+                have = true;
+            }
+        }
+    }
+    if (o.cost_cap > 0 && best > o.cost_cap) {
+        delete p;
+        return GP_ERR_BUDGET;
+    }
+    p->order = cand_orders[bo];
+    p->set = cand_sets[bs];
+    rc = gp::compile_plan(pat, p->order, p->set, &p->desc);
+    if (rc) {
+        delete p;
+        return rc;
+    }
+    gp_plan_info& in = p->info;
+    std::memset(&in, 0, sizeof in);
+    in.k = k;
+    for (int i = 0; i < k; ++i) in.order[i] = p->order[i];
+    int nr = 0;
+    for (int a = 0; a < k; ++a)
+        for (int b = 0; b < k; ++b)
+            if (gp::rel_has(p->set, a, b)) {
+                in.restr[2 * nr] = a;
+                in.restr[2 * nr + 1] = b;
+                ++nr;
+            }
+    in.n_restr = nr;
+    in.aut = p->aut;
+    in.cost = best;
+    in.n_sets = (int32_t)p->sets.size();
+    in.n_states = rs.states;
+    in.n_schedules = (int32_t)p->schedules.size();
+    in.k_eff = sc.k_eff;
+    in.set_index = cand_index[bs];
+    in.plan_seconds = now_seconds() - t0;
+    *out = p;
+    return GP_OK;
+}
+
+gp_status gp_plan_get(const gp_plan* p, gp_plan_info* out) {
+    if (!p || !out) return GP_ERR_ARG;
+    *out = p->info;
+    return GP_OK;
+}
+
+gp_status gp_plan_get_set(const gp_plan* p, int32_t idx, int32_t* n_restr, int32_t* restr) {
+    if (!p || !n_restr || !restr || idx < 0 || idx >= (int32_t)p->sets.size()) return GP_ERR_ARG;
+    int nr = 0;
+    const int k = p->pattern.k;
+    for (int a = 0; a < k; ++a)
+        for (int b = 0; b < k; ++b)
+            if (gp::rel_has(p->sets[idx], a, b)) {
+                restr[2 * nr] = a;
+                restr[2 * nr + 1] = b;
+                ++nr;
+            }
+    *n_restr = nr;
+    return GP_OK;
+}
+
+gp_status gp_plan_get_schedule(const gp_plan* p, int32_t idx, int32_t* order) {
+    if (!p || !order || idx < 0 || idx >= (int32_t)p->schedules.size()) return GP_ERR_ARG;
+    for (int i = 0; i < p->pattern.k; ++i) order[i] = p->schedules[idx][i];
+    return GP_OK;
+}
+
+gp_status gp_plan_model_cost(const gp_plan* p, int32_t idx_s, int32_t idx_r, const gp_stats* stats,
+                             double* cost) {
+    if (!p || !cost || idx_s < 0 || idx_s >= (int32_t)p->schedules.size() || idx_r < 0 ||
+        idx_r >= (int32_t)p->sets.size())
+        return GP_ERR_ARG;
+    gp::GraphStats gs{1e6, 1e7, 6e7};
+    if (stats && stats->n > 0 && stats->m > 0) {
+        gs.n_v = double(stats->n);
+        gs.n_e = double(stats->m);
+        gs.tri_cnt = double(stats->tri_cnt);
+    }
+    *cost = gp::model_cost(p->pattern, p->schedules[idx_s], p->sets[idx_r], gs);
+    return GP_OK;
+}
+
+void gp_free_plan(gp_plan* p) { delete p; }
+
+void gp_launch_default(gp_launch* l) {
+    if (l) std::memset(l, 0, sizeof *l);
+}
+
+gp_status gp_count(const gp_graph* g, const gp_plan* p, const gp_launch* launch, void* stream,
+                   uint64_t* out) {
+    if (!g || !p || !out) return GP_ERR_ARG;
+    DeviceGuard dgd(g->dg.device);
+    gpint::LaunchCfg cfg = gpint::resolve_launch(launch, p->desc, g->dg);
+    return count_to_host(g, p->desc, cfg, (hipStream_t)stream, nullptr, out);
+}
+
+gp_status gp_count_async(const gp_graph* g, const gp_plan* p, const gp_launch* launch, void* stream,
+                         uint64_t* dev_out) {
+    if (!g || !p || !dev_out) return GP_ERR_ARG;
+    DeviceGuard dgd(g->dg.device);
+    gpint::LaunchCfg cfg = gpint::resolve_launch(launch, p->desc, g->dg);
+    return gpint::launch_count(g->dg, p->desc, cfg, (hipStream_t)stream,
+                               reinterpret_cast<unsigned long long*>(dev_out), nullptr);
+}
+
+gp_status gp_count_per_root(const gp_graph* g, const gp_plan* p, const gp_launch* launch, void* stream,
+                            uint64_t* dev_per_root, uint64_t* out) {
+    if (!g || !p || !dev_per_root || !out) return GP_ERR_ARG;
+    DeviceGuard dgd(g->dg.device);
+    hipStream_t s = (hipStream_t)stream;
+    if (g->dg.nnz > 0) GP_HIP_TRY(hipMemsetAsync(dev_per_root, 0, sizeof(uint64_t) * g->dg.nnz, s));
+    gpint::LaunchCfg cfg = gpint::resolve_launch(launch, p->desc, g->dg);
+    return count_to_host(g, p->desc, cfg, s, reinterpret_cast<unsigned long long*>(dev_per_root), out);
+}
+
+gp_status gp_count_batch(const gp_graph* g, const gp_plan* const* plans, int32_t np,
+                         const gp_launch* launch, void* stream, uint64_t* out) {
+    if (!g || !plans || np < 1 || !out) return GP_ERR_ARG;
+    for (int i = 0; i < np; ++i)
+        if (!plans[i]) return GP_ERR_ARG;
+    DeviceGuard dgd(g->dg.device);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<GpPlanDesc> descs(np);
+    for (int i = 0; i < np; ++i) descs[i] = plans[i]->desc;
+    gpint::LaunchCfg cfg = gpint::resolve_launch(launch, descs[0], g->dg);
+    unsigned long long* res = nullptr;
+    GP_HIP_TRY(hipMallocAsync((void**)&res, 2 * sizeof(unsigned long long) * np, s));
+    gp_status st = gpint::launch_count_batch(g->dg, descs.data(), np, cfg, s, res);
+    std::vector<unsigned long long> h(2 * np, 0);
+    if (st == GP_OK &&
+        hipMemcpyAsync(h.data(), res, sizeof(unsigned long long) * 2 * np, hipMemcpyDeviceToHost, s) !=
+            hipSuccess)
+        st = GP_ERR_HIP;
+    (void)hipFreeAsync(res, s);
+    if (hipStreamSynchronize(s) != hipSuccess && st == GP_OK) st = GP_ERR_HIP;
+    if (st != GP_OK) return st;
+    for (int i = 0; i < np; ++i)
+        if (h[2 * i + 1]) return GP_ERR_OVERFLOW;
+    for (int i = 0; i < np; ++i) out[i] = h[2 * i];
+    return GP_OK;
+}
+
+}  // extern "C"

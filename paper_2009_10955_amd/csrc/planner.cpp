@@ -1,0 +1,443 @@
+// Host-side configuration generation and selection.
+//
+//   automorphisms        Section IV-A (all permutations preserving the edge set)
+//   restriction_sets     Section IV-A, Algorithm 1 (2-cycle based automorphism
+//                        elimination: generate / no_conflict / validate)
+//   efficient_schedules  Section IV-B (Phase 1: prefix-connected orders;
+//                        Phase 2: last k searched vertices pairwise non-adjacent)
+//   model_cost           Section IV-C (nested cost model with the cardinality
+//                        estimates p1, p2 and the filter fractions f_i)
+//   compile_plan         lowers (schedule, restriction closure) to GpPlanDesc
+//
+// Readings where the paper is silent or garbled:
+//   * 2-cycle test: perm[perm[v]] == v and perm[v] != v; the pair added is
+//     (v, perm[v]), meaning id(v) > id(perm[v]).
+//   * generate() runs once per transitive closure (sound: conflicts and the
+//     validate count depend only on the closure); results are closures.
+//   * validate uses the closed form of the paper's K_k check: on the complete
+//     graph K_k every bijection is a map, so the restricted count is the
+//     number of rank vectors obeying the set; valid iff that times |Aut| = k!.
+//   * Phase 2 with no satisfying order: the largest k' <= alpha(P) that some
+//     Phase-1 order admits.
+//   * Model: tri_cnt counts ordered triangles; a restriction is charged to the
+//     loop of its later-bound vertex; an intersection is charged to the loop of
+//     its last-bound parent, starting from the largest earlier candidate set
+//     with a subset of its parents bound no later, else the first parent's
+//     neighborhood, then the remaining parents in schedule order.
+#include "planner.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <unordered_map>
+#include <unordered_set>
+
+#include "gp.h"
+
+namespace gp {
+
+int parse_pattern(const int32_t* edges, int k, int e, Pattern* out) {
+    if (k < 2 || k > kMaxK || e < 1 || e > k * (k - 1) / 2 || !edges) return GP_ERR_PATTERN;
+    Pattern p;
+    p.k = k;
+    for (int i = 0; i < e; ++i) {
+        int a = edges[2 * i], b = edges[2 * i + 1];
+        if (a < 0 || a >= k || b < 0 || b >= k || a == b) return GP_ERR_PATTERN;
+        if (p.adj[a] & (1u << b)) return GP_ERR_PATTERN;  // repeated edge
+        p.adj[a] |= uint8_t(1u << b);
+        p.adj[b] |= uint8_t(1u << a);
+        p.edges.emplace_back(a, b);
+    }
+    // connected?
+    unsigned seen = 1, frontier = 1;
+    while (frontier) {
+        unsigned next = 0;
+        for (int v = 0; v < k; ++v)
+            if (frontier & (1u << v)) next |= p.adj[v];
+        next &= ~seen;
+        seen |= next;
+        frontier = next;
+    }
+    if (seen != (1u << k) - 1) return GP_ERR_PATTERN;
+    *out = p;
+    return 0;
+}
+
+std::vector<Perm> automorphisms(const Pattern& p) {
+    std::vector<Perm> out;
+    Perm perm{};
+    for (int i = 0; i < p.k; ++i) perm[i] = uint8_t(i);
+    do {
+        bool ok = true;
+        for (auto& e : p.edges)
+            if (!(p.adj[perm[e.first]] & (1u << perm[e.second]))) { ok = false; break; }
+        if (ok) out.push_back(perm);
+    } while (std::next_permutation(perm.begin(), perm.begin() + p.k));
+    return out;
+}
+
+Rel closure(Rel r, int k) {
+    uint8_t row[kMaxK];
+    for (int a = 0; a < k; ++a) row[a] = uint8_t(r >> (a * 8));
+    for (int m = 0; m < k; ++m)
+        for (int a = 0; a < k; ++a)
+            if (row[a] & (1u << m)) row[a] |= row[m];
+    Rel out = 0;
+    for (int a = 0; a < k; ++a) out |= Rel(row[a]) << (a * 8);
+    return out;
+}
+
+bool acyclic(Rel r, int k) {
+    Rel c = closure(r, k);
+    for (int a = 0; a < k; ++a)
+        if (rel_has(c, a, a)) return false;
+    return true;
+}
+
+// Algorithm 1, no_conflict: the digraph with every restriction (a,b) and its
+// image (perm[a], perm[b]); perm survives iff the digraph is acyclic.
+bool no_conflict(const Perm& perm, Rel r, int k) {
+    Rel g = r;
+    Rel rest = r;
+    while (rest) {
+        int bit = __builtin_ctzll(rest);
+        rest &= rest - 1;
+        int a = bit >> 3, b = bit & 7;
+        g |= rel_bit(perm[a], perm[b]);
+    }
+    return acyclic(g, k);
+}
+
+uint64_t linear_extensions(Rel r, int k) {
+    // below[x] = elements that must rank lower than x (pairs (x, b)).
+    uint8_t below[kMaxK];
+    for (int x = 0; x < k; ++x) below[x] = uint8_t(r >> (x * 8));
+    // Place elements from the lowest rank upward; x may take the next rank
+    // once everything that must be below it is placed.
+    uint64_t dp[1 << kMaxK];
+    const int full = (1 << k) - 1;
+    std::fill(dp, dp + (full + 1), 0);
+    dp[0] = 1;
+    for (int s = 0; s < full; ++s) {
+        if (!dp[s]) continue;
+        for (int x = 0; x < k; ++x) {
+            if (s & (1 << x)) continue;
+            if ((below[x] & ~s) != 0) continue;
+            dp[s | (1 << x)] += dp[s];
+        }
+    }
+    return dp[full];
+}
+
+static uint64_t factorial(int k) {
+    uint64_t f = 1;
+    for (int i = 2; i <= k; ++i) f *= uint64_t(i);
+    return f;
+}
+
+bool validate(Rel r, int k, uint64_t aut) {
+    return linear_extensions(r, k) * aut == factorial(k);
+}
+
+namespace {
+struct Gen {
+    const Pattern* p;
+    const std::vector<Perm>* auts;
+    int64_t max_states;
+    int32_t max_sets;
+    std::unordered_set<Rel> visited;
+    std::unordered_set<Rel> found_set;
+    RestrictionSets out;
+
+    void generate(const std::vector<int>& pg, Rel res_set) {
+        const int k = p->k;
+        if (pg.size() > 1) {
+            for (int pi : pg) {
+                const Perm& perm = (*auts)[pi];
+                for (int v = 0; v < k; ++v) {
+                    if (!(perm[perm[v]] == v && perm[v] != v)) continue;  // 2-cycle
+                    Rel new_set = closure(res_set | rel_bit(v, perm[v]), k);
+                    if (visited.count(new_set)) continue;
+                    if ((int64_t)visited.size() >= max_states ||
+                        (int32_t)out.sets.size() >= max_sets) {
+                        out.truncated = true;
+                        return;
+                    }
+                    visited.insert(new_set);
+                    std::vector<int> remaining;
+                    remaining.reserve(pg.size());
+                    for (int qi : pg)
+                        if (no_conflict((*auts)[qi], new_set, k)) remaining.push_back(qi);
+                    generate(remaining, new_set);
+                }
+            }
+        } else {
+            if (validate(res_set, k, auts->size()) && !found_set.count(res_set)) {
+                found_set.insert(res_set);
+                out.sets.push_back(res_set);
+            }
+        }
+    }
+};
+}  // namespace
+
+RestrictionSets restriction_sets(const Pattern& p, const std::vector<Perm>& auts,
+                                 int64_t max_states, int32_t max_sets) {
+    Gen g;
+    g.p = &p;
+    g.auts = &auts;
+    g.max_states = max_states;
+    g.max_sets = max_sets;
+    std::vector<int> pg(auts.size());
+    for (size_t i = 0; i < auts.size(); ++i) pg[i] = int(i);
+    g.generate(pg, 0);
+    g.out.states = int64_t(g.visited.size());
+    return g.out;
+}
+
+bool phase1_ok(const Pattern& p, const Perm& order) {
+    unsigned placed = 1u << order[0];
+    for (int i = 1; i < p.k; ++i) {
+        if (!(p.adj[order[i]] & placed)) return false;
+        placed |= 1u << order[i];
+    }
+    return true;
+}
+
+static int independence_number(const Pattern& p) {
+    int best = 0;
+    for (unsigned s = 1; s < (1u << p.k); ++s) {
+        bool ok = true;
+        for (int v = 0; v < p.k && ok; ++v)
+            if ((s & (1u << v)) && (p.adj[v] & s)) ok = false;
+        if (ok) best = std::max(best, __builtin_popcount(s));
+    }
+    return best;
+}
+
+Schedules efficient_schedules(const Pattern& p) {
+    const int k = p.k;
+    std::vector<Perm> p1;
+    Perm perm{};
+    for (int i = 0; i < k; ++i) perm[i] = uint8_t(i);
+    do {
+        if (phase1_ok(p, perm)) p1.push_back(perm);
+    } while (std::next_permutation(perm.begin(), perm.begin() + k));
+    Schedules out;
+    int alpha = independence_number(p);
+    for (int keff = alpha; keff >= 1; --keff) {
+        for (auto& o : p1) {
+            bool ok = true;
+            for (int a = k - keff; a < k && ok; ++a)
+                for (int b = a + 1; b < k && ok; ++b)
+                    if (p.adj[o[a]] & (1u << o[b])) ok = false;
+            if (ok) out.orders.push_back(o);
+        }
+        if (!out.orders.empty()) {
+            out.k_eff = keff;
+            return out;
+        }
+    }
+    out.orders = p1;
+    out.k_eff = 0;
+    return out;
+}
+
+double model_cost(const Pattern& p, const Perm& order, Rel r, const GraphStats& s) {
+    const int k = p.k;
+    int pos[kMaxK];
+    for (int i = 0; i < k; ++i) pos[order[i]] = i;
+    const double p1 = 2.0 * s.n_e / (s.n_v * s.n_v);
+    const double p2 = s.tri_cnt * s.n_v / std::pow(2.0 * s.n_e, 2.0);
+    auto card = [&](int nsets) { return s.n_v * p1 * std::pow(p2, double(nsets - 1)); };
+
+    // parents as level lists (ascending)
+    int npar[kMaxK];
+    unsigned parmask[kMaxK];
+    for (int i = 0; i < k; ++i) {
+        parmask[i] = 0;
+        for (int j = 0; j < i; ++j)
+            if (p.adj[order[i]] & (1u << order[j])) parmask[i] |= 1u << j;
+        npar[i] = __builtin_popcount(parmask[i]);
+    }
+
+    // f_i: survivors among the k! relative magnitudes, filtered loop by loop.
+    double f[kMaxK] = {0};
+    Rel upto = 0;
+    uint64_t before = factorial(k);
+    for (int i = 0; i < k; ++i) {
+        Rel here = 0;
+        Rel rest = r;
+        while (rest) {
+            int bit = __builtin_ctzll(rest);
+            rest &= rest - 1;
+            int a = bit >> 3, b = bit & 7;
+            if (std::max(pos[a], pos[b]) == i) here |= rel_bit(a, b);
+        }
+        if (!here) continue;
+        upto |= here;
+        uint64_t after = linear_extensions(upto, k);
+        f[i] = before ? double(before - after) / double(before) : 0.0;
+        before = after;
+    }
+
+    double loop[kMaxK];
+    loop[0] = s.n_v;
+    for (int i = 1; i < k; ++i) loop[i] = card(npar[i]);
+
+    double c[kMaxK] = {0};
+    int built[kMaxK];
+    int nbuilt = 0;
+    for (int i = 0; i < k; ++i) {
+        if (npar[i] < 2) continue;
+        int h = 31 - __builtin_clz(parmask[i]);
+        int base = -1;
+        for (int t = 0; t < nbuilt; ++t) {
+            int m = built[t];
+            unsigned pm = parmask[m];
+            int hm = 31 - __builtin_clz(pm);
+            bool subset = (pm & ~parmask[i]) == 0 && pm != parmask[i];
+            if (hm <= h && subset) {
+                if (base < 0 || npar[m] > npar[base]) base = m;
+            }
+        }
+        int have, nrest;
+        if (base < 0) {
+            have = 1;
+            nrest = npar[i] - 1;
+        } else {
+            have = npar[base];
+            nrest = npar[i] - npar[base];
+        }
+        for (int t = 0; t < nrest; ++t) {
+            c[h] += card(have) + card(1);
+            ++have;
+        }
+        built[nbuilt++] = i;
+    }
+
+    double cost = loop[k - 1] * (1.0 - f[k - 1]);
+    for (int i = k - 2; i >= 0; --i) cost = loop[i] * (1.0 - f[i]) * (c[i] + cost);
+    return cost;
+}
+
+int upper_cuts(const Perm& order, Rel r, int k) {
+    int pos[kMaxK];
+    for (int i = 0; i < k; ++i) pos[order[i]] = i;
+    int n = 0;
+    Rel rest = r;
+    while (rest) {
+        int bit = __builtin_ctzll(rest);
+        rest &= rest - 1;
+        int a = bit >> 3, b = bit & 7;
+        if (pos[a] < pos[b]) ++n;  // b searched later and bounded above by a
+    }
+    return n;
+}
+
+int compile_plan(const Pattern& p, const Perm& order, Rel r, GpPlanDesc* out) {
+    const int k = p.k;
+    if (!phase1_ok(p, order)) return GP_ERR_ARG;
+    GpPlanDesc d;
+    std::memset(&d, 0, sizeof d);
+    d.k = k;
+    int pos[kMaxK];
+    for (int i = 0; i < k; ++i) pos[order[i]] = i;
+
+    unsigned par[kMaxK], hi[kMaxK], lo[kMaxK];
+    for (int i = 0; i < k; ++i) {
+        par[i] = hi[i] = lo[i] = 0;
+        int u = order[i];
+        for (int j = 0; j < i; ++j) {
+            int w = order[j];
+            if (p.adj[u] & (1u << w)) par[i] |= 1u << j;
+            if (rel_has(r, w, u)) hi[i] |= 1u << j;  // id(w) > id(u): v_i < v_j
+            if (rel_has(r, u, w)) lo[i] |= 1u << j;  // id(u) > id(w): v_i > v_j
+        }
+    }
+    d.root_cut = (hi[1] & 1u) ? 1 : ((lo[1] & 1u) ? 2 : 0);
+
+    struct Key {
+        unsigned q, h, l;
+        bool operator==(const Key& o) const { return q == o.q && h == o.h && l == o.l; }
+    };
+    std::vector<std::pair<Key, int>> slots;
+    std::vector<GpBuild> builds;
+
+    // Chain of two-operand steps over the given parent levels (ascending);
+    // returns the slot holding the full intersection.
+    auto ensure_chain = [&](unsigned pmask, int target) -> int {
+        int lv[kMaxK], n = 0;
+        for (int j = 0; j < k; ++j)
+            if (pmask & (1u << j)) lv[n++] = j;
+        unsigned prefix = 1u << lv[0];
+        int slot = -1;
+        for (int s = 1; s < n; ++s) {
+            int h = lv[s];
+            prefix |= 1u << h;
+            unsigned lim = (2u << h) - 1;
+            Key key{prefix, hi[target] & lim, lo[target] & lim};
+            int found = -1;
+            for (auto& kv : slots)
+                if (kv.first == key) { found = kv.second; break; }
+            if (found >= 0) { slot = found; continue; }
+            GpBuild b;
+            b.h = int8_t(h);
+            b.dst = int8_t(slots.size());
+            b.src_buf = int8_t(slot);
+            b.src_list = int8_t(slot < 0 ? lv[0] : -1);
+            b.with_list = int8_t(h);
+            b.hi_src = uint8_t(key.h);
+            b.lo_src = uint8_t(key.l);
+            b.pad = 0;
+            slots.push_back({key, int(b.dst)});
+            builds.push_back(b);
+            slot = b.dst;
+        }
+        return slot;
+    };
+
+    for (int i = 0; i < k; ++i) {
+        GpLevel& L = d.lv[i];
+        L.parents = uint8_t(par[i]);
+        L.hi_src = uint8_t(hi[i]);
+        L.lo_src = uint8_t(lo[i]);
+        L.inj = uint8_t(((1u << i) - 1) & ~par[i] & ~hi[i] & ~lo[i]);
+        L.list = L.buf = L.pre_buf = L.pre_list = L.last_list = -1;
+        if (i == 0) continue;
+        int np = __builtin_popcount(par[i]);
+        int h = 31 - __builtin_clz(par[i]);
+        if (np == 1) {
+            L.list = int8_t(h);
+        } else if (i < k - 1 || h < k - 2) {
+            L.buf = int8_t(ensure_chain(par[i], i));
+        } else {
+            // last level whose last parent is level k-2: count-only final step
+            unsigned prefix = par[i] & ~(1u << h);
+            if (__builtin_popcount(prefix) == 1) {
+                L.pre_list = int8_t(__builtin_ctz(prefix));
+            } else {
+                L.pre_buf = int8_t(ensure_chain(prefix, i));
+            }
+            L.last_list = int8_t(h);
+        }
+    }
+    if (builds.size() > GP_DESC_MAX_BUILDS) return GP_ERR_UNSUPPORTED;
+    std::stable_sort(builds.begin(), builds.end(),
+                     [](const GpBuild& a, const GpBuild& b) { return a.h < b.h; });
+    d.nbuild = int32_t(builds.size());
+    d.nbuf = int32_t(slots.size());
+    for (size_t t = 0; t < builds.size(); ++t) d.b[t] = builds[t];
+    for (int h = 0; h < k; ++h) {
+        int b0 = 0;
+        while (b0 < d.nbuild && d.b[b0].h < h) ++b0;
+        int b1 = b0;
+        while (b1 < d.nbuild && d.b[b1].h == h) ++b1;
+        d.build_begin[h] = uint8_t(b0);
+        d.build_end[h] = uint8_t(b1);
+    }
+    *out = d;
+    return 0;
+}
+
+}  // namespace gp

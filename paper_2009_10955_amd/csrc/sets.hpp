@@ -1,0 +1,159 @@
+// Device-side sorted-set primitives for gfx950 (64-lane wavefronts).
+//
+// Every candidate set is an ascending int32 array (a CSR neighbor list or a
+// buffer built from lists). Intersections cost O(|A| + |B|) in the paper's
+// model (Section IV-C, "Measurement of c_i and l_i"; Section IV-E: sorted
+// contiguous lists). Here a group of G lanes intersects cooperatively: each
+// lane takes one element of the smaller list and binary-searches it in the
+// larger one; ballot + popcount compact the hits in order. Single lanes use a
+// branch-free merge or a galloping search, whichever the sizes favour.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gpdev {
+
+struct Set {
+    const int32_t* p;
+    int32_t n;
+};
+
+// First index i in [0, n) with a[i] >= x (n if none).
+__device__ __forceinline__ int32_t lower_bound(const int32_t* a, int32_t n, int32_t x) {
+    int32_t base = 0;
+    while (n > 0) {
+        int32_t half = n >> 1;
+        if (a[base + half] < x) {
+            base += half + 1;
+            n -= half + 1;
+        } else {
+            n = half;
+        }
+    }
+    return base;
+}
+
+__device__ __forceinline__ bool contains(const int32_t* a, int32_t n, int32_t x) {
+    int32_t i = lower_bound(a, n, x);
+    return i < n && a[i] == x;
+}
+
+// Restrict a sorted set to values in [lo, hi).
+__device__ __forceinline__ Set trim(Set s, int32_t lo, int32_t hi) {
+    int32_t b = lo > 0 ? lower_bound(s.p, s.n, lo) : 0;
+    int32_t e = hi < 0x7fffffff ? lower_bound(s.p, s.n, hi) : s.n;
+    if (e < b) e = b;
+    return Set{s.p + b, e - b};
+}
+
+// |A ∩ B| by one lane.
+__device__ __forceinline__ uint32_t intersect_count_serial(Set a, Set b) {
+    if (a.n > b.n) {
+        Set t = a;
+        a = b;
+        b = t;
+    }
+    if (a.n == 0) return 0;
+    uint32_t c = 0;
+    if (a.n * 16 < b.n) {
+        // galloping: each element of the small set searched in the rest of the large one
+        const int32_t* p = b.p;
+        int32_t n = b.n;
+        for (int32_t i = 0; i < a.n && n > 0; ++i) {
+            int32_t x = a.p[i];
+            int32_t j = lower_bound(p, n, x);
+            if (j < n && p[j] == x) {
+                ++c;
+                ++j;
+            }
+            p += j;
+            n -= j;
+        }
+        return c;
+    }
+    int32_t i = 0, j = 0;
+    while (i < a.n && j < b.n) {
+        int32_t x = a.p[i], y = b.p[j];
+        c += (x == y);
+        i += (x <= y);
+        j += (y <= x);
+    }
+    return c;
+}
+
+// A group of G consecutive lanes of one wavefront acting together.
+template <int G>
+struct Group {
+    static_assert(G == 64 || G == 32 || G == 16 || G == 8, "group size");
+    int lane;   // lane in the wavefront
+    int gl;     // lane in the group
+    int gbase;  // first lane of the group
+
+    __device__ __forceinline__ Group() {
+        lane = __lane_id();
+        gl = lane & (G - 1);
+        gbase = lane & ~(G - 1);
+    }
+    __device__ __forceinline__ uint64_t ballot(bool pred) const {
+        uint64_t m = __ballot(pred);
+        if (G == 64) return m;
+        return (m >> gbase) & ((uint64_t(1) << G) - 1);
+    }
+    __device__ __forceinline__ uint32_t below_mask_count(uint64_t m) const {
+        return __popcll(m & ((uint64_t(1) << gl) - 1));
+    }
+    template <typename T>
+    __device__ __forceinline__ T bcast(T v, int src) const {
+        return __shfl(v, src, G);
+    }
+    __device__ __forceinline__ uint64_t sum(uint64_t v) const {
+#pragma unroll
+        for (int off = G / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, G);
+        return v;
+    }
+};
+
+// Group-cooperative dst = A ∩ B (both already cut to the wanted range).
+// Returns the number of elements written (the same in every lane).
+template <int G>
+__device__ __forceinline__ int32_t intersect_into(const Group<G>& g, Set a, Set b, int32_t* dst) {
+    if (a.n > b.n) {
+        Set t = a;
+        a = b;
+        b = t;
+    }
+    int32_t out = 0;
+    for (int32_t base = 0; base < a.n; base += G) {
+        int32_t i = base + g.gl;
+        bool found = false;
+        int32_t x = 0;
+        if (i < a.n) {
+            x = a.p[i];
+            found = contains(b.p, b.n, x);
+        }
+        uint64_t m = g.ballot(found);
+        if (found) dst[out + (int32_t)g.below_mask_count(m)] = x;
+        out += (int32_t)__popcll(m);
+    }
+    return out;
+}
+
+// Group-cooperative |A ∩ B| (same value in every lane).
+template <int G>
+__device__ __forceinline__ uint32_t intersect_count_group(const Group<G>& g, Set a, Set b) {
+    if (a.n > b.n) {
+        Set t = a;
+        a = b;
+        b = t;
+    }
+    uint32_t out = 0;
+    for (int32_t base = 0; base < a.n; base += G) {
+        int32_t i = base + g.gl;
+        bool found = false;
+        if (i < a.n) found = contains(b.p, b.n, a.p[i]);
+        out += (uint32_t)__popcll(g.ballot(found));
+    }
+    return out;
+}
+
+}  // namespace gpdev

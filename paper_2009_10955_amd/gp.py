@@ -1,0 +1,335 @@
+"""Python binding of libgp.so (the C ABI in include/gp.h).
+
+Argument marshalling only: every step of the counting path runs in the HIP
+library. PyTorch supplies device memory and streams. If the library is not
+built, importing works but every call raises -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgp.so")
+MAX_K = 8
+
+GP_IN_DEVICE = 1
+
+STATUS = {
+    0: "GP_OK", -1: "GP_ERR_ARG", -2: "GP_ERR_CSR_UNSORTED", -3: "GP_ERR_CSR_ASYMMETRIC",
+    -4: "GP_ERR_CSR_SELFLOOP", -5: "GP_ERR_CSR_DUPLICATE", -6: "GP_ERR_PATTERN",
+    -7: "GP_ERR_NOMEM", -8: "GP_ERR_HIP", -9: "GP_ERR_OVERFLOW", -10: "GP_ERR_BUDGET",
+    -11: "GP_ERR_CSR_RANGE", -12: "GP_ERR_UNSUPPORTED",
+}
+
+
+class GpError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+        msg = _lib().gp_strerror(status).decode() if _LIB is not None else self.name
+        super().__init__(f"{what}: {self.name} ({msg})" if what else f"{self.name} ({msg})")
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("max_degree", ctypes.c_int64),
+                ("tri_cnt", ctypes.c_uint64), ("hash", ctypes.c_uint64),
+                ("load_seconds", ctypes.c_double)]
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("max_states", ctypes.c_int64), ("max_sets", ctypes.c_int32),
+                ("force_order", ctypes.c_int32 * MAX_K), ("force_set", ctypes.c_int32),
+                ("n_force_restr", ctypes.c_int32),
+                ("force_restr", ctypes.c_int32 * (2 * MAX_K * MAX_K)),
+                ("cost_cap", ctypes.c_double)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("order", ctypes.c_int32 * MAX_K),
+                ("n_restr", ctypes.c_int32), ("restr", ctypes.c_int32 * (2 * MAX_K * MAX_K)),
+                ("aut", ctypes.c_uint64), ("cost", ctypes.c_double), ("n_sets", ctypes.c_int32),
+                ("n_states", ctypes.c_int64), ("n_schedules", ctypes.c_int32),
+                ("k_eff", ctypes.c_int32), ("set_index", ctypes.c_int32),
+                ("plan_seconds", ctypes.c_double)]
+
+
+class Launch(ctypes.Structure):
+    _fields_ = [("group", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("leaf_mode", ctypes.c_int32)]
+
+
+# every symbol include/gp.h declares, with (restype, argtypes)
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+SIGNATURES = {
+    "gp_load_graph": (_I32, [_P, _P, _I64, _I64, ctypes.c_uint32, _P, ctypes.POINTER(_P)]),
+    "gp_graph_stats": (_I32, [_P, ctypes.POINTER(Stats)]),
+    "gp_graph_new_id": (_I32, [_P, _P]),
+    "gp_graph_layout": (_I32, [_P, _P, _P]),
+    "gp_free_graph": (None, [_P]),
+    "gp_plan_opts_default": (None, [ctypes.POINTER(PlanOpts)]),
+    "gp_plan_create": (_I32, [_P, _I32, _I32, ctypes.POINTER(Stats), ctypes.POINTER(PlanOpts),
+                              ctypes.POINTER(_P)]),
+    "gp_plan_get": (_I32, [_P, ctypes.POINTER(PlanInfo)]),
+    "gp_plan_get_set": (_I32, [_P, _I32, ctypes.POINTER(_I32), _P]),
+    "gp_plan_get_schedule": (_I32, [_P, _I32, _P]),
+    "gp_plan_model_cost": (_I32, [_P, _I32, _I32, ctypes.POINTER(Stats),
+                                  ctypes.POINTER(ctypes.c_double)]),
+    "gp_free_plan": (None, [_P]),
+    "gp_launch_default": (None, [ctypes.POINTER(Launch)]),
+    "gp_count": (_I32, [_P, _P, ctypes.POINTER(Launch), _P, ctypes.POINTER(ctypes.c_uint64)]),
+    "gp_count_async": (_I32, [_P, _P, ctypes.POINTER(Launch), _P, _P]),
+    "gp_count_per_root": (_I32, [_P, _P, ctypes.POINTER(Launch), _P, _P,
+                                 ctypes.POINTER(ctypes.c_uint64)]),
+    "gp_count_batch": (_I32, [_P, _P, _I32, ctypes.POINTER(Launch), _P, _P]),
+    "gp_strerror": (ctypes.c_char_p, [_I32]),
+    "gp_version": (ctypes.c_char_p, []),
+}
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                               "(python -c 'import __graft_entry__ as g; g.build()')")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = lib
+    return _LIB
+
+
+def library():
+    """The loaded ctypes library (loads it on first use)."""
+    return _lib()
+
+
+def _check(status: int, what: str) -> None:
+    if status != 0:
+        raise GpError(status, what)
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _launch(group=0, waves_per_cu=0, chunk=0, leaf_mode=0) -> Launch:
+    return Launch(group, waves_per_cu, chunk, leaf_mode)
+
+
+class Graph:
+    """A data graph resident on the current GPU, owned by the library."""
+
+    def __init__(self, row_ptr, col, stream=None):
+        lib = _lib()
+        self._h = ctypes.c_void_p()
+        try:
+            import torch
+            is_tensor = isinstance(row_ptr, torch.Tensor)
+        except ImportError:  # pragma: no cover
+            is_tensor = False
+        if is_tensor:
+            assert row_ptr.dtype == torch.int64 and col.dtype == torch.int32
+            assert row_ptr.is_cuda and col.is_cuda
+            row_ptr = row_ptr.contiguous()
+            col = col.contiguous()
+            n = row_ptr.numel() - 1
+            st = lib.gp_load_graph(row_ptr.data_ptr(), col.data_ptr(), n, col.numel(), GP_IN_DEVICE,
+                                   _stream_handle(stream), ctypes.byref(self._h))
+        else:
+            rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+            cl = np.ascontiguousarray(col, dtype=np.int32)
+            n = rp.shape[0] - 1
+            st = lib.gp_load_graph(rp.ctypes.data, cl.ctypes.data if cl.size else None, n, cl.size, 0,
+                                   _stream_handle(stream), ctypes.byref(self._h))
+        _check(st, "gp_load_graph")
+
+    @classmethod
+    def from_csr(cls, g, device: bool = False, stream=None) -> "Graph":
+        """From an object with numpy ``row_ptr`` / ``col``; device=True uploads
+        them as torch tensors first and loads from device memory."""
+        if device:
+            import torch
+            rp = torch.from_numpy(np.asarray(g.row_ptr, dtype=np.int64)).cuda()
+            cl = torch.from_numpy(np.asarray(g.col, dtype=np.int32)).cuda()
+            return cls(rp, cl, stream)
+        return cls(g.row_ptr, g.col, stream)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def stats(self) -> Stats:
+        s = Stats()
+        _check(_lib().gp_graph_stats(self._h, ctypes.byref(s)), "gp_graph_stats")
+        return s
+
+    def new_id(self) -> np.ndarray:
+        n = self.stats().n
+        out = np.empty(n, dtype=np.int32)
+        _check(_lib().gp_graph_new_id(self._h, out.ctypes.data), "gp_graph_new_id")
+        return out
+
+    def layout(self) -> tuple[np.ndarray, np.ndarray]:
+        s = self.stats()
+        rp = np.empty(s.n + 1, dtype=np.int64)
+        cl = np.empty(max(1, 2 * s.m), dtype=np.int32)
+        _check(_lib().gp_graph_layout(self._h, rp.ctypes.data, cl.ctypes.data), "gp_graph_layout")
+        return rp, cl[:2 * s.m]
+
+    def close(self) -> None:
+        if self._h:
+            _lib().gp_free_graph(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """A compiled configuration (schedule + restriction set) for one pattern."""
+
+    def __init__(self, k: int, edges: Sequence[tuple[int, int]], stats: Stats | None = None,
+                 force_order: Sequence[int] | None = None, force_set: int | None = None,
+                 force_restr: Sequence[tuple[int, int]] | None = None, max_states: int = 0,
+                 max_sets: int = 0, cost_cap: float = 0.0):
+        lib = _lib()
+        e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1))
+        o = PlanOpts()
+        lib.gp_plan_opts_default(ctypes.byref(o))
+        o.max_states = max_states
+        o.max_sets = max_sets
+        o.cost_cap = cost_cap
+        if force_order is not None:
+            for i, v in enumerate(force_order):
+                o.force_order[i] = v
+        if force_set is not None:
+            o.force_set = force_set
+        if force_restr is not None:
+            o.n_force_restr = len(force_restr)
+            for i, (a, b) in enumerate(force_restr):
+                o.force_restr[2 * i] = a
+                o.force_restr[2 * i + 1] = b
+        self._h = ctypes.c_void_p()
+        self.k = k
+        self.edges = [tuple(x) for x in edges]
+        st = lib.gp_plan_create(e.ctypes.data, k, len(edges),
+                                ctypes.byref(stats) if stats is not None else None,
+                                ctypes.byref(o), ctypes.byref(self._h))
+        _check(st, "gp_plan_create")
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> PlanInfo:
+        inf = PlanInfo()
+        _check(_lib().gp_plan_get(self._h, ctypes.byref(inf)), "gp_plan_get")
+        return inf
+
+    @property
+    def order(self) -> tuple[int, ...]:
+        inf = self.info()
+        return tuple(inf.order[i] for i in range(inf.k))
+
+    @property
+    def restrictions(self) -> list[tuple[int, int]]:
+        inf = self.info()
+        return [(inf.restr[2 * i], inf.restr[2 * i + 1]) for i in range(inf.n_restr)]
+
+    def sets(self) -> list[frozenset]:
+        out = []
+        buf = (ctypes.c_int32 * (2 * MAX_K * MAX_K))()
+        nr = ctypes.c_int32()
+        for i in range(self.info().n_sets):
+            _check(_lib().gp_plan_get_set(self._h, i, ctypes.byref(nr), buf), "gp_plan_get_set")
+            out.append(frozenset((buf[2 * j], buf[2 * j + 1]) for j in range(nr.value)))
+        return out
+
+    def schedules(self) -> list[tuple[int, ...]]:
+        out = []
+        buf = (ctypes.c_int32 * MAX_K)()
+        for i in range(self.info().n_schedules):
+            _check(_lib().gp_plan_get_schedule(self._h, i, buf), "gp_plan_get_schedule")
+            out.append(tuple(buf[j] for j in range(self.k)))
+        return out
+
+    def model_cost(self, idx_schedule: int, idx_set: int, stats: Stats | None = None) -> float:
+        c = ctypes.c_double()
+        _check(_lib().gp_plan_model_cost(self._h, idx_schedule, idx_set,
+                                         ctypes.byref(stats) if stats is not None else None,
+                                         ctypes.byref(c)), "gp_plan_model_cost")
+        return c.value
+
+    def close(self) -> None:
+        if self._h:
+            _lib().gp_free_plan(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def count(graph: Graph, plan: Plan, stream=None, **launch) -> int:
+    """Exact embedding count (blocking)."""
+    out = ctypes.c_uint64()
+    lp = _launch(**launch)
+    _check(_lib().gp_count(graph.handle, plan.handle, ctypes.byref(lp), _stream_handle(stream),
+                           ctypes.byref(out)), "gp_count")
+    return out.value
+
+
+def count_async(graph: Graph, plan: Plan, dev_out, stream=None, **launch) -> None:
+    """Enqueue a count; dev_out is a CUDA uint64/int64 tensor with >= 2 entries
+    that receives {count, overflow flag}."""
+    lp = _launch(**launch)
+    _check(_lib().gp_count_async(graph.handle, plan.handle, ctypes.byref(lp), _stream_handle(stream),
+                                 dev_out.data_ptr()), "gp_count_async")
+
+
+def count_per_root(graph: Graph, plan: Plan, stream=None, **launch):
+    """(total, per-root counts as a CUDA int64 tensor indexed by layout CSR entry)."""
+    import torch
+    s = graph.stats()
+    per = torch.empty(max(1, 2 * s.m), dtype=torch.int64, device="cuda")
+    out = ctypes.c_uint64()
+    lp = _launch(**launch)
+    _check(_lib().gp_count_per_root(graph.handle, plan.handle, ctypes.byref(lp),
+                                    _stream_handle(stream), per.data_ptr(), ctypes.byref(out)),
+           "gp_count_per_root")
+    return out.value, per[:2 * s.m]
+
+
+def count_batch(graph: Graph, plans: Sequence[Plan], stream=None, **launch) -> list[int]:
+    """Counts of several plans in one persistent launch (blocking)."""
+    arr = (ctypes.c_void_p * len(plans))(*[p.handle for p in plans])
+    out = (ctypes.c_uint64 * len(plans))()
+    lp = _launch(**launch)
+    _check(_lib().gp_count_batch(graph.handle, arr, len(plans), ctypes.byref(lp),
+                                 _stream_handle(stream), out), "gp_count_batch")
+    return list(out)
+
+
+def version() -> str:
+    return _lib().gp_version().decode()

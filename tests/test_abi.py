@@ -1,0 +1,60 @@
+"""The C-ABI library loads and exports every symbol include/gp.h declares
+(no device calls here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2009_10955_amd import gp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "gp.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(gp_[a-z_0-9]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for required in ["gp_load_graph", "gp_plan_create", "gp_count", "gp_count_batch",
+                     "gp_count_async", "gp_count_per_root", "gp_strerror", "gp_free_graph",
+                     "gp_free_plan", "gp_graph_stats", "gp_plan_get"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(gp.LIB_PATH)
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_binding_covers_every_declared_symbol():
+    assert set(_declared_functions()) == set(gp.SIGNATURES)
+
+
+def test_host_only_calls():
+    lib = gp.library()
+    assert lib.gp_strerror(0).decode() == "ok"
+    assert "64 bits" in lib.gp_strerror(-9).decode()
+    assert "gfx950" in gp.version()
+
+
+def test_struct_sizes_match_header_layout():
+    # layouts as laid out by a C compiler for the declarations in gp.h
+    assert ctypes.sizeof(gp.Stats) == 48
+    assert ctypes.sizeof(gp.Launch) == 16
+    assert ctypes.sizeof(gp.PlanOpts) == 8 + 4 + 32 + 4 + 4 + 512 + 8 + 4  # + tail padding
+    assert ctypes.sizeof(gp.PlanInfo) % 8 == 0
+
+
+def test_argument_errors_need_no_device():
+    lib = gp.library()
+    h = ctypes.c_void_p()
+    assert lib.gp_load_graph(None, None, 4, 0, 0, None, ctypes.byref(h)) == -1
+    assert lib.gp_load_graph(None, None, -1, 0, 0, None, ctypes.byref(h)) == -1
+    assert lib.gp_count(None, None, None, None, None) == -1
+    assert lib.gp_count_batch(None, None, 0, None, None, None) == -1

@@ -1,0 +1,234 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle,
+bit-exact, on seeded graphs that span several tiles, ragged tails and the
+degenerate cases."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2009_10955_amd import gp
+from paper_2009_10955_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+P = I.PATTERNS
+VARIANTS = [dict(group=g, leaf_mode=l) for g in (64, 32, 16, 8) for l in (1, 2)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    yield
+
+
+def _count(graph, k, e, **kw):
+    launch = {x: kw.pop(x) for x in ("group", "leaf_mode", "chunk", "waves_per_cu") if x in kw}
+    plan = gp.Plan(k, e, stats=graph.stats(), **kw)
+    return gp.count(graph, plan, **launch)
+
+
+# ------------------------------------------------------------------ layout
+
+@pytest.mark.parametrize("device_input", [False, True])
+def test_layout_and_stats_match_oracle(device_input):
+    g = I.config_graph(2)
+    graph = gp.Graph.from_csr(g, device=device_input)
+    s = graph.stats()
+    assert (s.n, s.m, s.max_degree) == (g.n, g.m, int(g.degrees().max()))
+    assert s.tri_cnt == 6 * O.count(g, *P["triangle"])
+    rp, col, new_id = O.relabel_by_degree(g)
+    assert np.array_equal(graph.new_id(), new_id)
+    lrp, lcol = graph.layout()
+    assert np.array_equal(lrp, rp)
+    assert np.array_equal(lcol, col)
+
+
+def test_bad_csr_is_rejected():
+    def load(rp, col):
+        with pytest.raises(gp.GpError) as ei:
+            gp.Graph(np.array(rp, np.int64), np.array(col, np.int32))
+        return ei.value.status
+    assert load([0, 2, 3, 4], [2, 1, 0, 0]) == -2          # unsorted list
+    assert load([0, 1, 1], [1]) == -3                      # asymmetric
+    assert load([0, 2, 3], [0, 1, 0]) == -4                # self-loop
+    assert load([0, 2, 4], [1, 1, 0, 0]) == -5             # duplicate
+    assert load([0, 1, 2], [5, 0]) == -11                  # out of range
+    assert load([0, 1, 3], [1, 0]) == -11                  # row_ptr[n] != nnz
+
+
+def test_empty_and_edgeless_graphs():
+    k, e = P["triangle"]
+    for n in (1, 5):
+        graph = gp.Graph(np.zeros(n + 1, np.int64), np.zeros(0, np.int32))
+        assert graph.stats().m == 0
+        assert _count(graph, k, e) == 0
+        assert _count(graph, *P["edge"]) == 0
+
+
+# ------------------------------------------------------------ config 0
+
+@pytest.mark.parametrize("pname", I.CONFIG_PATTERNS[0])
+def test_config0_counts(pname):
+    g = I.config_graph(0)
+    graph = gp.Graph.from_csr(g, device=True)
+    k, e = P[pname]
+    want = O.count(g, k, e)
+    for v in VARIANTS:
+        assert _count(graph, k, e, **v) == want, v
+
+
+# ------------------------------------------------------------- closed forms
+
+def test_closed_forms():
+    kn = gp.Graph.from_csr(I.complete(12))
+    for pname in ["triangle", "4-cycle", "4-clique", "house", "5-clique", "6-clique", "prism",
+                  "5-wheel", "6-cycle"]:
+        k, e = P[pname]
+        aut = len(O.automorphisms(k, e))
+        assert _count(kn, k, e) == math.comb(12, k) * math.factorial(k) // aut, pname
+    kab = gp.Graph.from_csr(I.complete_bipartite(9, 13))
+    assert _count(kab, *P["4-cycle"]) == math.comb(9, 2) * math.comb(13, 2)
+    assert _count(kab, *P["triangle"]) == 0
+    q = gp.Graph.from_csr(I.hypercube(8))
+    assert _count(q, *P["4-cycle"]) == math.comb(8, 2) * 2 ** 6
+    c = gp.Graph.from_csr(I.cycle_graph(5))
+    assert _count(c, *P["5-cycle"]) == 1
+
+
+def test_hub_star_ragged():
+    """A hub of degree 3000 (many tiles plus a ragged tail) with its leaves
+    partly connected: exercises long lists and large candidate buffers."""
+    rng = np.random.default_rng(3)
+    s = 3000
+    src = [0] * s + list(rng.integers(1, s + 1, 4000))
+    dst = list(range(1, s + 1)) + list(rng.integers(1, s + 1, 4000))
+    g = I.csr_from_edges(s + 1, np.array(src), np.array(dst))
+    graph = gp.Graph.from_csr(g)
+    for pname in ["triangle", "3-star", "4-cycle", "tailed-triangle", "diamond", "4-clique"]:
+        k, e = P[pname]
+        want = O.count(g, k, e)
+        for v in VARIANTS[::3]:
+            assert _count(graph, k, e, **v) == want, (pname, v)
+
+
+# ------------------------------------------------------- every pattern, graphs
+
+@pytest.mark.parametrize("seed", [101, 102])
+@pytest.mark.parametrize("pname", list(P))
+def test_all_patterns_random_graphs(seed, pname):
+    g = I.er(60, 0.25, seed=seed)
+    graph = gp.Graph.from_csr(g)
+    k, e = P[pname]
+    want = O.count(g, k, e)
+    for v in VARIANTS:
+        assert _count(graph, k, e, **v) == want, v
+
+
+@pytest.mark.parametrize("pname", ["triangle", "4-cycle", "4-clique", "diamond", "house",
+                                   "5-cycle", "6-cycle-chord", "k4-path", "tailed-triangle"])
+def test_every_restriction_set_and_schedule(pname):
+    """Each emitted set with several efficient schedules gives the oracle count."""
+    g = I.er(40, 0.3, seed=7)
+    graph = gp.Graph.from_csr(g)
+    k, e = P[pname]
+    want = O.count(g, k, e)
+    base = gp.Plan(k, e)
+    scheds = base.schedules()
+    n_sets = base.info().n_sets
+    rng = np.random.default_rng(0)
+    for si in range(n_sets):
+        for o in [scheds[int(x)] for x in rng.choice(len(scheds), min(3, len(scheds)), replace=False)]:
+            plan = gp.Plan(k, e, force_order=o, force_set=si)
+            assert gp.count(graph, plan, group=16) == want, (o, si)
+
+
+def test_random_patterns_up_to_six_vertices():
+    rng = np.random.default_rng(5)
+    g = I.er(45, 0.3, seed=9)
+    graph = gp.Graph.from_csr(g)
+    for _ in range(25):
+        k = int(rng.integers(3, 7))
+        e = I.random_connected_pattern(k, rng, 0.5)
+        assert _count(graph, k, e) == O.count(g, k, e), (k, e)
+
+
+def test_relabel_and_union_invariance():
+    g = I.er(80, 0.15, seed=4)
+    h = I.er(70, 0.2, seed=5)
+    u = I.disjoint_union(g, h)
+    pu = I.permute(u, np.random.default_rng(1).permutation(u.n))
+    gg, gh, gu = (gp.Graph.from_csr(x) for x in (g, h, pu))
+    for pname in ["triangle", "4-cycle", "house", "5-cycle"]:
+        k, e = P[pname]
+        assert _count(gu, k, e) == _count(gg, k, e) + _count(gh, k, e)
+
+
+# ------------------------------------------------------------ per-root parity
+
+def _per_root_check(g, graph, pname, n_samples, seed, max_check=2_000_000, **launch):
+    k, e = P[pname]
+    plan = gp.Plan(k, e, stats=graph.stats())
+    total, per = gp.count_per_root(graph, plan, **launch)
+    per = per.cpu().numpy()
+    assert int(per.sum()) == total
+    assert gp.count(graph, plan, **launch) == total
+    rp, col, _ = O.relabel_by_degree(g)
+    lay = O._CSRView(rp, col)
+    order = plan.order
+    restr = plan.restrictions
+    rng = np.random.default_rng(seed)
+    nz = np.nonzero(per)[0]
+    picks = list(rng.choice(len(col), n_samples, replace=False))
+    # nonzero roots light enough for the oracle to redo within seconds,
+    # including the heaviest of those
+    light = nz[per[nz] <= max_check]
+    if light.size:
+        picks += list(rng.choice(light, min(n_samples, light.size), replace=False))
+        picks.append(int(light[np.argmax(per[light])]))
+    src = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
+    for idx in picks:
+        v0, v1 = int(src[idx]), int(col[idx])
+        want = O.count_maps(lay, k, e, restr=restr, pins=[(order[0], v0), (order[1], v1)],
+                            threads=1)
+        assert int(per[idx]) == want, (pname, idx, v0, v1)
+    return total
+
+
+@pytest.mark.parametrize("pname", ["triangle", "4-cycle", "4-clique", "house", "5-cycle"])
+def test_per_root_counts_config2(pname):
+    g = I.config_graph(2)
+    graph = gp.Graph.from_csr(g, device=True)
+    _per_root_check(g, graph, pname, 20, 1)
+
+
+@pytest.mark.parametrize("pname", I.CONFIG_PATTERNS[1])
+def test_per_root_counts_config1_full_size(pname):
+    """R-MAT scale 17 at full size, default launch: per-root counts on sampled
+    roots (random, nonzero, and the heaviest) equal the oracle's pinned counts."""
+    g = I.config_graph(1)
+    graph = gp.Graph.from_csr(g, device=True)
+    _per_root_check(g, graph, pname, 6, 2)
+
+
+def test_config2_small_patterns_full_count():
+    g = I.config_graph(2)
+    graph = gp.Graph.from_csr(g, device=True)
+    for pname in ["triangle", "4-clique", "diamond"]:
+        k, e = P[pname]
+        assert _count(graph, k, e) == O.count(g, k, e), pname
+
+
+# ------------------------------------------------------------------ batched
+
+def test_batch_equals_plain():
+    g = I.er(200, 0.08, seed=11)
+    graph = gp.Graph.from_csr(g)
+    names = ["triangle", "4-cycle", "house", "5-cycle", "6-cycle-chord", "prism"]
+    plans = [gp.Plan(*P[x], stats=graph.stats()) for x in names]
+    plain = [gp.count(graph, p) for p in plans]
+    assert gp.count_batch(graph, plans) == plain
+    assert plain == [O.count(g, *P[x]) for x in names]

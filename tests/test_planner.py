@@ -1,0 +1,144 @@
+"""Host planner (behind gp_plan_create) against the oracle's Algorithm 1,
+schedule filter and cost model. Host-only: no device calls."""
+import itertools
+import math
+
+import pytest
+
+import oracle as O
+from paper_2009_10955_amd import gp
+from paper_2009_10955_amd import inputs as I
+
+P = I.PATTERNS
+SMALL = ["edge", "triangle", "4-cycle", "4-clique", "4-path", "3-star", "tailed-triangle",
+         "diamond", "house", "5-cycle", "6-cycle-chord", "k4-path"]
+
+
+def _stats(n, m, tri):
+    s = gp.Stats()
+    s.n, s.m, s.tri_cnt = n, m, tri
+    return s
+
+
+@pytest.mark.parametrize("pname", SMALL)
+def test_restriction_sets_match_oracle_in_order(pname):
+    k, e = P[pname]
+    plan = gp.Plan(k, e)
+    assert plan.info().aut == len(O.automorphisms(k, e))
+    assert plan.sets() == O.restriction_sets(k, e)
+
+
+@pytest.mark.parametrize("pname", list(P))
+def test_schedules_match_oracle(pname):
+    k, e = P[pname]
+    plan = gp.Plan(k, e)
+    scheds, keff = O.efficient_schedules(k, e)
+    assert plan.schedules() == scheds
+    assert plan.info().k_eff == keff
+
+
+@pytest.mark.parametrize("pname", ["house", "5-cycle", "4-clique", "6-cycle-chord", "k4-path",
+                                   "diamond"])
+def test_model_costs_match_oracle(pname):
+    k, e = P[pname]
+    stats = [(131072, 971517, 6 * 8.7e6), (7000, 99199, 6 * 1.5e6), (1000, 5017, 6 * 157)]
+    plan = gp.Plan(k, e)
+    sets = plan.sets()
+    scheds = plan.schedules()
+    for n, m, tri in stats:
+        st = _stats(n, m, int(tri))
+        for i, o in enumerate(scheds[:12]):
+            for j, r in enumerate(sets[:8]):
+                want = O.model_cost(k, e, o, r, float(n), float(m), float(int(tri)))
+                got = plan.model_cost(i, j, st)
+                assert math.isclose(got, want, rel_tol=1e-12), (o, sorted(r))
+
+
+@pytest.mark.parametrize("pname", ["triangle", "4-cycle", "4-clique", "house", "5-cycle",
+                                   "6-cycle-chord", "diamond"])
+def test_chosen_configuration_is_the_model_argmin(pname):
+    k, e = P[pname]
+    n, m, tri = 131072, 971517, 6 * 8_700_000
+    plan = gp.Plan(k, e, stats=_stats(n, m, tri))
+    inf = plan.info()
+    chosen = O.model_cost(k, e, plan.order, frozenset(plan.restrictions), n, m, tri)
+    best = min(O.model_cost(k, e, o, r, n, m, tri)
+               for o in O.efficient_schedules(k, e)[0] for r in O.restriction_sets(k, e))
+    assert math.isclose(chosen, best, rel_tol=1e-9)
+    assert math.isclose(inf.cost, best, rel_tol=1e-9)
+    # ties go to the set with more upper-bound cuts (later vertex below earlier)
+    pos = {u: i for i, u in enumerate(plan.order)}
+    cuts = sum(1 for a, b in plan.restrictions if pos[a] < pos[b])
+    for r in O.restriction_sets(k, e):
+        c = O.model_cost(k, e, plan.order, r, n, m, tri)
+        if math.isclose(c, best, rel_tol=1e-9):
+            assert sum(1 for a, b in r if pos[a] < pos[b]) <= cuts
+
+
+def test_chosen_set_is_valid_and_closed():
+    for pname in ["4-clique", "5-clique", "house", "prism", "5-wheel", "6-cycle"]:
+        k, e = P[pname]
+        plan = gp.Plan(k, e)
+        r = frozenset(plan.restrictions)
+        assert O.closure(r, k) == r
+        assert O.validate(k, e, r)
+
+
+def test_clique_sets_are_total_orders():
+    for k in (4, 5):
+        e = list(itertools.combinations(range(k), 2))
+        plan = gp.Plan(k, e)
+        sets = plan.sets()
+        assert len(sets) == math.factorial(k)
+        assert all(len(s) == k * (k - 1) // 2 for s in sets)
+
+
+def test_six_clique_planning_is_bounded():
+    k, e = P["6-clique"]
+    plan = gp.Plan(k, e)
+    inf = plan.info()
+    assert inf.aut == 720
+    assert len(plan.restrictions) == 15  # a total order
+    assert inf.plan_seconds < 60
+
+
+@pytest.mark.parametrize("bad", [
+    (3, [(0, 1)]),                       # vertex 2 isolated: not connected
+    (4, [(0, 1), (2, 3)]),               # disconnected
+    (3, [(0, 1), (1, 1)]),               # self-loop
+    (3, [(0, 1), (1, 0), (1, 2)]),       # repeated edge
+    (3, [(0, 1), (1, 3)]),               # vertex out of range
+    (9, [(i, i + 1) for i in range(8)]),  # k above GP_MAX_K
+    (1, []),
+])
+def test_bad_patterns_are_rejected(bad):
+    k, e = bad
+    with pytest.raises(gp.GpError) as ei:
+        gp.Plan(k, e if e else [(0, 0)])
+    assert ei.value.status == -6
+
+
+def test_forced_configurations():
+    k, e = P["house"]
+    plan = gp.Plan(k, e, force_order=(0, 1, 2, 3, 4), force_restr=[(0, 1)])
+    assert plan.order == (0, 1, 2, 3, 4)
+    assert plan.restrictions == [(0, 1)]
+    with pytest.raises(gp.GpError) as ei:   # not Phase-1 connected
+        gp.Plan(k, e, force_order=(2, 3, 4, 0, 1))
+    assert ei.value.status == -1
+    with pytest.raises(gp.GpError):         # does not break the symmetry
+        gp.Plan(*P["4-cycle"], force_restr=[(0, 1)])
+    with pytest.raises(gp.GpError):         # cyclic
+        gp.Plan(*P["4-cycle"], force_restr=[(0, 1), (1, 0)])
+    n_sets = gp.Plan(*P["4-cycle"]).info().n_sets
+    for i in range(n_sets):
+        assert gp.Plan(*P["4-cycle"], force_set=i).info().set_index == i
+    with pytest.raises(gp.GpError):
+        gp.Plan(*P["4-cycle"], force_set=n_sets)
+
+
+def test_cost_cap():
+    k, e = P["5-cycle"]
+    with pytest.raises(gp.GpError) as ei:
+        gp.Plan(k, e, stats=_stats(4_194_304, 32_600_000, 6 * 455_000_000), cost_cap=1.0)
+    assert ei.value.status == -10

@@ -202,6 +202,18 @@ gp_status gp_count_per_root(const gp_graph* g, const gp_plan* p, const gp_launch
                             void* stream, uint64_t* dev_per_root, uint64_t* out);
 
 /*
+ * Count and, alongside it, the algorithmic bytes of the run under the paper's
+ * intersection cost model (Section IV-C: intersecting sorted sets A and B
+ * costs |A| + |B|; Section IV-E: sorted contiguous lists): 4(|A'| + |B'|)
+ * bytes per executed intersection of the range-cut operands A', B', 4 bytes
+ * per enumerated candidate, 8 bytes per root edge, and 4 ceil(log2(|L|+1))
+ * bytes per last-level binary search in a list L. Runs an instrumented copy
+ * of the kernel: for measurement, never for timing. Blocking.
+ */
+gp_status gp_count_traffic(const gp_graph* g, const gp_plan* p, const gp_launch* launch,
+                           void* stream, uint64_t* out, uint64_t* alg_bytes);
+
+/*
  * Count several plans over one graph in ONE persistent launch: the task space
  * is the union over plans of their root edges, handed out from one atomic
  * queue, so plans of uneven cost share the machine. out[i] = count of

@@ -15,7 +15,11 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libgp.so")
 
-SOURCES = ["api.cpp", "planner.cpp", "graph.hip", "count.hip"]
+# (source, extra defines, object name): the counting kernel is instantiated
+# once per pattern size k in its own unit so the variants build in parallel
+SOURCES = [("api.cpp", [], "api.o"), ("planner.cpp", [], "planner.o"),
+           ("graph.hip", [], "graph.o"), ("count.hip", [], "count.o")] + [
+    ("count_inst.hip", [f"-DGP_INST_K={k}"], f"count_k{k}.o") for k in range(2, 9)]
 ARCH = os.environ.get("GP_OFFLOAD_ARCH", "gfx950")
 
 
@@ -37,10 +41,11 @@ def flags() -> list[str]:
     ]
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+def _compile(item, verbose: bool) -> str:
+    src, defines, oname = item
+    obj = os.path.join(BUILD, oname)
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [hipcc()] + lang + ["-c", os.path.join(CSRC, src), "-o", obj] + flags()
+    cmd = [hipcc()] + lang + ["-c", os.path.join(CSRC, src), "-o", obj] + defines + flags()
     if verbose:
         print(" ".join(cmd), flush=True)
     t = time.time()
@@ -49,13 +54,13 @@ def _compile(src: str, verbose: bool) -> str:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError(f"compile failed: {src}")
     if verbose:
-        print(f"  {src}: {time.time() - t:.1f}s", flush=True)
+        print(f"  {oname}: {time.time() - t:.1f}s", flush=True)
     return obj
 
 
 def build(verbose: bool = False, jobs: int | None = None) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    jobs = jobs or min(len(SOURCES), max(1, (os.cpu_count() or 2)))
+    jobs = jobs or min(len(SOURCES), max(1, min(16, os.cpu_count() or 2)))
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIB + ".tmp"

@@ -73,11 +73,12 @@ gp_status triangle_desc(GpPlanDesc* d) {
 }
 
 gp_status count_to_host(const gp_graph* g, const GpPlanDesc& d, const gpint::LaunchCfg& cfg,
-                        hipStream_t s, unsigned long long* per_root, uint64_t* out) {
+                        hipStream_t s, unsigned long long* per_root, uint64_t* out,
+                        uint64_t* alg_bytes = nullptr) {
     unsigned long long* res = nullptr;
-    GP_HIP_TRY(hipMallocAsync((void**)&res, 2 * sizeof(unsigned long long), s));
-    gp_status st = gpint::launch_count(g->dg, d, cfg, s, res, per_root);
-    unsigned long long h[2] = {0, 0};
+    GP_HIP_TRY(hipMallocAsync((void**)&res, 3 * sizeof(unsigned long long), s));
+    gp_status st = gpint::launch_count(g->dg, d, cfg, s, res, per_root, alg_bytes != nullptr);
+    unsigned long long h[3] = {0, 0, 0};
     if (st == GP_OK) {
         if (hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, s) != hipSuccess) st = GP_ERR_HIP;
     }
@@ -86,6 +87,7 @@ gp_status count_to_host(const gp_graph* g, const GpPlanDesc& d, const gpint::Lau
     if (st != GP_OK) return st;
     if (h[1]) return GP_ERR_OVERFLOW;
     *out = h[0];
+    if (alg_bytes) *alg_bytes = h[2];
     return GP_OK;
 }
 
@@ -467,6 +469,14 @@ gp_status gp_count_per_root(const gp_graph* g, const gp_plan* p, const gp_launch
     if (g->dg.nnz > 0) GP_HIP_TRY(hipMemsetAsync(dev_per_root, 0, sizeof(uint64_t) * g->dg.nnz, s));
     gpint::LaunchCfg cfg = gpint::resolve_launch(launch, p->desc, g->dg);
     return count_to_host(g, p->desc, cfg, s, reinterpret_cast<unsigned long long*>(dev_per_root), out);
+}
+
+gp_status gp_count_traffic(const gp_graph* g, const gp_plan* p, const gp_launch* launch, void* stream,
+                           uint64_t* out, uint64_t* alg_bytes) {
+    if (!g || !p || !out || !alg_bytes) return GP_ERR_ARG;
+    DeviceGuard dgd(g->dg.device);
+    gpint::LaunchCfg cfg = gpint::resolve_launch(launch, p->desc, g->dg);
+    return count_to_host(g, p->desc, cfg, (hipStream_t)stream, nullptr, out, alg_bytes);
 }
 
 gp_status gp_count_batch(const gp_graph* g, const gp_plan* const* plans, int32_t np,

@@ -1,363 +1,41 @@
-// Persistent counting kernel for gfx950.
-//
-// What it computes: the number of embeddings of a pattern under one
-// configuration (schedule + restriction closure), i.e. the nested-loop search
-// of Section II-B / IV-B with candidate sets formed by intersecting sorted
-// neighbor lists and cut by the restrictions (the generated code of Fig.
-// pseudocode_performance), with every level's injectivity enforced
-// (Section II-A requires a bijection).
-//
-// How it maps to the machine:
-//   * Tasks are root edges (v0, v1) = the first two loops fused, taken from a
-//     device-wide atomic queue in chunks (the fine-grained task partitioning
-//     of Section IV-E, as a lock-free queue instead of a master thread). Roots
-//     are in CSR order of the degree-sorted layout, so hubs go first.
-//   * A group of G lanes (G in {64, 32, 16, 8}) of one wavefront shares one
-//     search path. Intersections are group-cooperative (each lane
-//     binary-searches one element of the smaller list in the larger one;
-//     ballot + popcount compact the hits). G < 64 runs 64/G independent paths
-//     per wavefront, which pays on graphs whose lists are short.
-//   * Intersection results ("tmp" sets) live in a per-group scratch region in
-//     HBM; they are written and re-read while hot in L2.
-//   * The second-to-last level is spread over the lanes (leaf mode 1: each
-//     lane counts the last level for its own candidate) or walked with the
-//     group counting each last level together (leaf mode 2).
-//   * The last level is never enumerated: its count is
-//     |C ∩ [lo, hi)| minus the earlier bound vertices that fall in it.
-//   * Counts: uint64 per lane, wavefront tree reduction with carry detection,
-//     one atomic per wavefront; wrap-around sets the overflow flag.
+// Host side of the counting kernel: launch geometry, scratch, dispatch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 
-#include "internal.hpp"
-#include "sets.hpp"
+#include "count_kernel.hpp"
 
-using namespace gpdev;
+namespace gpcount {
+KernelFn pick_kernel_k2(int group, int leaf, int mode);
+KernelFn pick_kernel_k3(int group, int leaf, int mode);
+KernelFn pick_kernel_k4(int group, int leaf, int mode);
+KernelFn pick_kernel_k5(int group, int leaf, int mode);
+KernelFn pick_kernel_k6(int group, int leaf, int mode);
+KernelFn pick_kernel_k7(int group, int leaf, int mode);
+KernelFn pick_kernel_k8(int group, int leaf, int mode);
 
 namespace {
-
-constexpr int kBlock = 256;
-
-struct CountArgs {
-    const int64_t* row_ptr;
-    const int32_t* col;
-    const int2* roots;
-    int64_t n_roots;
-    int32_t* scratch;
-    int64_t buf_cap;
-    unsigned long long* queue;
-    unsigned long long* result;    // {count, overflow}
-    unsigned long long* per_root;  // optional, indexed by CSR entry of (v0, v1)
-    int32_t chunk;
-};
-
-template <int G>
-struct Ctx {
-    const int64_t* row_ptr;
-    const int32_t* col;
-    int32_t* bufs;
-    int64_t cap;
-    int32_t* lens;  // LDS: length per buffer slot
-    Group<G> g;
-
-    __device__ __forceinline__ Set nbr(int32_t v) const {
-        int64_t b = row_ptr[v], e = row_ptr[v + 1];
-        return Set{col + b, (int32_t)(e - b)};
-    }
-    __device__ __forceinline__ Set buf(int slot) const {
-        return Set{bufs + (int64_t)slot * cap, lens[slot]};
-    }
-};
-
-// v[idx] for a runtime idx without dynamic register indexing.
-template <int K>
-__device__ __forceinline__ int32_t pick(const int32_t (&v)[K], int idx) {
-    int32_t r = v[0];
-#pragma unroll
-    for (int j = 1; j < K; ++j) r = (idx == j) ? v[j] : r;
-    return r;
-}
-
-template <int K>
-__device__ __forceinline__ void bounds(uint32_t hi_src, uint32_t lo_src, const int32_t (&v)[K],
-                                       int32_t& lo, int32_t& hi) {
-    lo = 0;
-    hi = 0x7fffffff;
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-        if ((hi_src >> j) & 1u) hi = min(hi, v[j]);
-        if ((lo_src >> j) & 1u) lo = max(lo, v[j] + 1);
-    }
-}
-
-template <int K>
-__device__ __forceinline__ bool inj_hit(uint32_t inj, const int32_t (&v)[K], int32_t x) {
-    bool hit = false;
-#pragma unroll
-    for (int j = 0; j < K; ++j)
-        if ((inj >> j) & 1u) hit |= (v[j] == x);
-    return hit;
-}
-
-__device__ __forceinline__ void add_count(uint64_t& acc, uint64_t c, bool& ovf) {
-    uint64_t s = acc + c;
-    ovf |= (s < acc);
-    acc = s;
-}
-
-__device__ __forceinline__ void group_fence() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
-// Builds scheduled right after level h is bound.
-template <int K, int G>
-__device__ __forceinline__ void run_builds(const GpPlanDesc& d, const Ctx<G>& c, int h,
-                                           const int32_t (&v)[K]) {
-    const int b0 = d.build_begin[h], b1 = d.build_end[h];
-    for (int t = b0; t < b1; ++t) {
-        const GpBuild& b = d.b[t];
-        int32_t lo, hi;
-        bounds<K>(b.hi_src, b.lo_src, v, lo, hi);
-        Set A = b.src_buf >= 0 ? c.buf(b.src_buf) : c.nbr(pick<K>(v, b.src_list));
-        Set B = c.nbr(pick<K>(v, b.with_list));
-        A = trim(A, lo, hi);
-        B = trim(B, lo, hi);
-        int32_t n = intersect_into<G>(c.g, A, B, c.bufs + (int64_t)b.dst * c.cap);
-        group_fence();
-        c.lens[b.dst] = n;
-        group_fence();
-    }
-}
-
-// Count of the last level for bound values v[0..K-2], by one lane.
-template <int K, int G>
-__device__ __forceinline__ uint32_t leaf_serial(const GpPlanDesc& d, const Ctx<G>& c,
-                                                const int32_t (&v)[K]) {
-    const GpLevel& lv = d.lv[K - 1];
-    int32_t lo, hi;
-    bounds<K>(lv.hi_src, lv.lo_src, v, lo, hi);
-    if (lv.last_list < 0) {
-        Set S = lv.list >= 0 ? c.nbr(pick<K>(v, lv.list)) : c.buf(lv.buf);
-        S = trim(S, lo, hi);
-        uint32_t cnt = (uint32_t)S.n;
-#pragma unroll
-        for (int j = 0; j < K - 1; ++j) {
-            if ((lv.inj >> j) & 1u) {
-                int32_t y = v[j];
-                if (y >= lo && y < hi && contains(S.p, S.n, y)) --cnt;
-            }
-        }
-        return cnt;
-    }
-    Set A = lv.pre_buf >= 0 ? c.buf(lv.pre_buf) : c.nbr(pick<K>(v, lv.pre_list));
-    Set B = c.nbr(pick<K>(v, lv.last_list));
-    A = trim(A, lo, hi);
-    B = trim(B, lo, hi);
-    uint32_t cnt = intersect_count_serial(A, B);
-#pragma unroll
-    for (int j = 0; j < K - 1; ++j) {
-        if ((lv.inj >> j) & 1u) {
-            int32_t y = v[j];
-            if (y >= lo && y < hi && contains(A.p, A.n, y) && contains(B.p, B.n, y)) --cnt;
-        }
-    }
-    return cnt;
-}
-
-// Count of the last level, computed by the whole group (same value in every lane).
-template <int K, int G>
-__device__ __forceinline__ uint32_t leaf_group(const GpPlanDesc& d, const Ctx<G>& c,
-                                               const int32_t (&v)[K]) {
-    const GpLevel& lv = d.lv[K - 1];
-    if (lv.last_list < 0) return leaf_serial<K, G>(d, c, v);
-    int32_t lo, hi;
-    bounds<K>(lv.hi_src, lv.lo_src, v, lo, hi);
-    Set A = lv.pre_buf >= 0 ? c.buf(lv.pre_buf) : c.nbr(pick<K>(v, lv.pre_list));
-    Set B = c.nbr(pick<K>(v, lv.last_list));
-    A = trim(A, lo, hi);
-    B = trim(B, lo, hi);
-    uint32_t cnt = intersect_count_group<G>(c.g, A, B);
-#pragma unroll
-    for (int j = 0; j < K - 1; ++j) {
-        if ((lv.inj >> j) & 1u) {
-            int32_t y = v[j];
-            if (y >= lo && y < hi && contains(A.p, A.n, y) && contains(B.p, B.n, y)) --cnt;
-        }
-    }
-    return cnt;
-}
-
-template <int K, int L, int G, int LEAF>
-__device__ void search(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], uint64_t& acc,
-                       bool& ovf) {
-    const GpLevel& lv = d.lv[L];
-    int32_t lo, hi;
-    bounds<K>(lv.hi_src, lv.lo_src, v, lo, hi);
-    Set S = lv.list >= 0 ? c.nbr(pick<K>(v, lv.list)) : c.buf(lv.buf);
-    S = trim(S, lo, hi);
-    if constexpr (L == K - 2) {
-        if constexpr (LEAF == 1) {
-            for (int32_t base = 0; base < S.n; base += G) {
-                int32_t i = base + c.g.gl;
-                if (i < S.n) {
-                    int32_t x = S.p[i];
-                    if (!inj_hit<K>(lv.inj, v, x)) {
-                        int32_t w[K];
-#pragma unroll
-                        for (int j = 0; j < K; ++j) w[j] = v[j];
-                        w[K - 2] = x;
-                        add_count(acc, leaf_serial<K, G>(d, c, w), ovf);
-                    }
-                }
-            }
-        } else {
-            for (int32_t t = 0; t < S.n; ++t) {
-                int32_t x = S.p[t];
-                if (inj_hit<K>(lv.inj, v, x)) continue;
-                v[K - 2] = x;
-                uint32_t cnt = leaf_group<K, G>(d, c, v);
-                if (c.g.gl == 0) add_count(acc, cnt, ovf);
-            }
-        }
-    } else {
-        for (int32_t t = 0; t < S.n; ++t) {
-            int32_t x = S.p[t];
-            if (inj_hit<K>(lv.inj, v, x)) continue;
-            v[L] = x;
-            run_builds<K, G>(d, c, L, v);
-            search<K, L + 1, G, LEAF>(d, c, v, acc, ovf);
-        }
-    }
-}
-
-__device__ __forceinline__ int64_t entry_index(const int64_t* row_ptr, const int32_t* col,
-                                               int32_t v0, int32_t v1) {
-    int64_t b = row_ptr[v0];
-    return b + lower_bound(col + b, (int32_t)(row_ptr[v0 + 1] - b), v1);
-}
-
-template <int K, int G, int LEAF, bool PER_ROOT>
-__global__ __launch_bounds__(kBlock) void count_kernel(GpPlanDesc d, CountArgs a) {
-    __shared__ int32_t s_len[kBlock / G][GP_DESC_MAX_BUILDS];
-    Ctx<G> c;
-    c.row_ptr = a.row_ptr;
-    c.col = a.col;
-    c.cap = a.buf_cap;
-    const int grp = threadIdx.x / G;
-    const int64_t group_id = (int64_t)blockIdx.x * (kBlock / G) + grp;
-    c.bufs = a.scratch ? a.scratch + group_id * (int64_t)d.nbuf * a.buf_cap : nullptr;
-    c.lens = s_len[grp];
-
-    uint64_t acc = 0;
-    bool ovf = false;
-    const int64_t chunk = a.chunk;
-
-    for (;;) {
-        unsigned long long t0 = 0;
-        if (c.g.gl == 0) t0 = atomicAdd(a.queue, (unsigned long long)chunk);
-        t0 = c.g.bcast(t0, 0);
-        if ((int64_t)t0 >= a.n_roots) break;
-        const int64_t t1 = min((int64_t)t0 + chunk, a.n_roots);
-        if constexpr (K <= 3 && LEAF == 1) {
-            // lanes take different roots
-            for (int64_t base = (int64_t)t0; base < t1; base += G) {
-                int64_t r = base + c.g.gl;
-                if (r < t1) {
-                    int2 e = a.roots[r];
-                    uint64_t cnt = 1;
-                    if constexpr (K == 3) {
-                        int32_t w[K] = {e.x, e.y, 0};
-                        cnt = leaf_serial<K, G>(d, c, w);
-                    }
-                    add_count(acc, cnt, ovf);
-                    if constexpr (PER_ROOT)
-                        a.per_root[entry_index(a.row_ptr, a.col, e.x, e.y)] = cnt;
-                }
-            }
-        } else {
-            for (int64_t r = (int64_t)t0; r < t1; ++r) {
-                int2 e = a.roots[r];
-                const uint64_t before = acc;
-                if constexpr (K <= 3) {
-                    uint64_t cnt = 1;
-                    if constexpr (K == 3) {
-                        int32_t w[K] = {e.x, e.y, 0};
-                        cnt = leaf_group<K, G>(d, c, w);
-                    }
-                    if (c.g.gl == 0) add_count(acc, cnt, ovf);
-                } else {
-                    int32_t v[K];
-#pragma unroll
-                    for (int j = 0; j < K; ++j) v[j] = 0;
-                    v[0] = e.x;
-                    v[1] = e.y;
-                    run_builds<K, G>(d, c, 1, v);
-                    search<K, 2, G, LEAF>(d, c, v, acc, ovf);
-                }
-                if constexpr (PER_ROOT) {
-                    uint64_t mine = c.g.sum(acc - before);
-                    if (c.g.gl == 0) a.per_root[entry_index(a.row_ptr, a.col, e.x, e.y)] = mine;
-                }
-            }
-        }
-    }
-
-    // wavefront reduction with carry detection, one atomic per wavefront
-    uint64_t s = acc;
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        uint64_t t = __shfl_xor(s, off, 64);
-        uint64_t u = s + t;
-        ovf |= (u < s);
-        s = u;
-    }
-    const bool any_ovf = __ballot(ovf) != 0;
-    if (__lane_id() == 0) {
-        unsigned long long old = atomicAdd(&a.result[0], (unsigned long long)s);
-        if (any_ovf || old + s < old) atomicOr(&a.result[1], 1ull);
-    }
-}
-
 __global__ void init_counters(unsigned long long* p, int n) {
     int i = threadIdx.x;
     if (i < n) p[i] = 0;
 }
 
-typedef void (*KernelFn)(GpPlanDesc, CountArgs);
-
-template <int K, int G>
-KernelFn pick_kernel_g(int leaf, bool per_root) {
-    if (leaf == 2) return per_root ? count_kernel<K, G, 2, true> : count_kernel<K, G, 2, false>;
-    return per_root ? count_kernel<K, G, 1, true> : count_kernel<K, G, 1, false>;
-}
-
-template <int K>
-KernelFn pick_kernel_k(int group, int leaf, bool per_root) {
-    switch (group) {
-        case 64: return pick_kernel_g<K, 64>(leaf, per_root);
-        case 32: return pick_kernel_g<K, 32>(leaf, per_root);
-        case 16: return pick_kernel_g<K, 16>(leaf, per_root);
-        case 8: return pick_kernel_g<K, 8>(leaf, per_root);
-        default: return nullptr;
-    }
-}
-
-KernelFn pick_kernel(int k, int group, int leaf, bool per_root) {
+KernelFn pick_kernel(int k, int group, int leaf, int mode) {
     switch (k) {
-        case 2: return pick_kernel_k<2>(group, leaf, per_root);
-        case 3: return pick_kernel_k<3>(group, leaf, per_root);
-        case 4: return pick_kernel_k<4>(group, leaf, per_root);
-        case 5: return pick_kernel_k<5>(group, leaf, per_root);
-        case 6: return pick_kernel_k<6>(group, leaf, per_root);
-        case 7: return pick_kernel_k<7>(group, leaf, per_root);
-        case 8: return pick_kernel_k<8>(group, leaf, per_root);
+        case 2: return pick_kernel_k2(group, leaf, mode);
+        case 3: return pick_kernel_k3(group, leaf, mode);
+        case 4: return pick_kernel_k4(group, leaf, mode);
+        case 5: return pick_kernel_k5(group, leaf, mode);
+        case 6: return pick_kernel_k6(group, leaf, mode);
+        case 7: return pick_kernel_k7(group, leaf, mode);
+        case 8: return pick_kernel_k8(group, leaf, mode);
         default: return nullptr;
     }
 }
-
 }  // namespace
+}  // namespace gpcount
+
+using namespace gpcount;
 
 namespace gpint {
 
@@ -392,11 +70,12 @@ static const int2* pick_roots(const DeviceGraph& g, int root_cut, int64_t* n) {
 
 gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCfg& cfg,
                        hipStream_t stream, unsigned long long* result_dev,
-                       unsigned long long* per_root) {
+                       unsigned long long* per_root, bool account) {
     if (cfg.group != 64 && cfg.group != 32 && cfg.group != 16 && cfg.group != 8) return GP_ERR_ARG;
     if (cfg.leaf != 1 && cfg.leaf != 2) return GP_ERR_ARG;
     if (cfg.waves_per_cu < 1 || cfg.waves_per_cu > 32 || cfg.chunk < 1) return GP_ERR_ARG;
-    KernelFn fn = pick_kernel(d.k, cfg.group, cfg.leaf, per_root != nullptr);
+    const int mode = account ? MODE_ACCOUNT : (per_root ? MODE_PER_ROOT : MODE_PLAIN);
+    KernelFn fn = pick_kernel(d.k, cfg.group, cfg.leaf, mode);
     if (!fn) return GP_ERR_UNSUPPORTED;
 
     int64_t n_roots = 0;
@@ -429,7 +108,7 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
         }
     }
     hipLaunchKernelGGL(init_counters, dim3(1), dim3(64), 0, stream, queue, 1);
-    hipLaunchKernelGGL(init_counters, dim3(1), dim3(64), 0, stream, result_dev, 2);
+    hipLaunchKernelGGL(init_counters, dim3(1), dim3(64), 0, stream, result_dev, account ? 3 : 2);
 
     CountArgs a;
     a.row_ptr = g.row_ptr;
@@ -455,7 +134,7 @@ gp_status launch_count_batch(const DeviceGraph& g, const GpPlanDesc* descs, int 
                              unsigned long long* result_dev) {
     // One plan at a time for now; the single-launch batch kernel replaces this.
     for (int i = 0; i < np; ++i) {
-        gp_status s = launch_count(g, descs[i], cfg, stream, result_dev + 2 * i, nullptr);
+        gp_status s = launch_count(g, descs[i], cfg, stream, result_dev + 2 * i, nullptr, false);
         if (s != GP_OK) return s;
     }
     return GP_OK;

@@ -1,0 +1,41 @@
+// One instantiation unit of the counting kernel per pattern size k (built
+// once per k with -DGP_INST_K=k), so the variants compile in parallel.
+#include "count_kernel.hpp"
+
+#ifndef GP_INST_K
+#error "GP_INST_K must be defined"
+#endif
+
+namespace gpcount {
+
+namespace {
+template <int K, int G, int LEAF>
+KernelFn pick_mode(int mode) {
+    switch (mode) {
+        case MODE_PLAIN: return count_kernel<K, G, LEAF, MODE_PLAIN>;
+        case MODE_PER_ROOT: return count_kernel<K, G, LEAF, MODE_PER_ROOT>;
+        case MODE_ACCOUNT: return count_kernel<K, G, LEAF, MODE_ACCOUNT>;
+        default: return nullptr;
+    }
+}
+
+template <int K, int G>
+KernelFn pick_leaf(int leaf, int mode) {
+    return leaf == 2 ? pick_mode<K, G, 2>(mode) : pick_mode<K, G, 1>(mode);
+}
+}  // namespace
+
+#define GP_CAT2(a, b) a##b
+#define GP_CAT(a, b) GP_CAT2(a, b)
+
+KernelFn GP_CAT(pick_kernel_k, GP_INST_K)(int group, int leaf, int mode) {
+    switch (group) {
+        case 64: return pick_leaf<GP_INST_K, 64>(leaf, mode);
+        case 32: return pick_leaf<GP_INST_K, 32>(leaf, mode);
+        case 16: return pick_leaf<GP_INST_K, 16>(leaf, mode);
+        case 8: return pick_leaf<GP_INST_K, 8>(leaf, mode);
+        default: return nullptr;
+    }
+}
+
+}  // namespace gpcount

@@ -1,0 +1,365 @@
+// Persistent counting kernel for gfx950.
+//
+// What it computes: the number of embeddings of a pattern under one
+// configuration (schedule + restriction closure), i.e. the nested-loop search
+// of Section II-B / IV-B with candidate sets formed by intersecting sorted
+// neighbor lists and cut by the restrictions (the generated code of Fig.
+// pseudocode_performance), with every level's injectivity enforced
+// (Section II-A requires a bijection).
+//
+// How it maps to the machine:
+//   * Tasks are root edges (v0, v1) = the first two loops fused, taken from a
+//     device-wide atomic queue in chunks (the fine-grained task partitioning
+//     of Section IV-E, as a lock-free queue instead of a master thread). Roots
+//     are in CSR order of the degree-sorted layout, so hubs go first.
+//   * A group of G lanes (G in {64, 32, 16, 8}) of one wavefront shares one
+//     search path. Intersections are group-cooperative (each lane
+//     binary-searches one element of the smaller list in the larger one;
+//     ballot + popcount compact the hits). G < 64 runs 64/G independent paths
+//     per wavefront, which pays on graphs whose lists are short.
+//   * Intersection results ("tmp" sets) live in a per-group scratch region in
+//     HBM; they are written and re-read while hot in L2.
+//   * The second-to-last level is spread over the lanes (leaf mode 1: each
+//     lane counts the last level for its own candidate) or walked with the
+//     group counting each last level together (leaf mode 2).
+//   * The last level is never enumerated: its count is
+//     |C ∩ [lo, hi)| minus the earlier bound vertices that fall in it.
+//   * Counts: uint64 per lane, wavefront tree reduction with carry detection,
+//     one atomic per wavefront; wrap-around sets the overflow flag.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+#include "sets.hpp"
+
+namespace gpcount {
+
+using namespace gpdev;
+
+constexpr int kBlock = 256;
+
+// Kernel modes: plain count, per-root counts, or accounting of the
+// algorithmic bytes of the paper's cost model (never timed).
+enum { MODE_PLAIN = 0, MODE_PER_ROOT = 1, MODE_ACCOUNT = 2 };
+
+struct CountArgs {
+    const int64_t* row_ptr;
+    const int32_t* col;
+    const int2* roots;
+    int64_t n_roots;
+    int32_t* scratch;
+    int64_t buf_cap;
+    unsigned long long* queue;
+    unsigned long long* result;    // {count, overflow, algorithmic bytes}
+    unsigned long long* per_root;  // optional, indexed by CSR entry of (v0, v1)
+    int32_t chunk;
+};
+
+typedef void (*KernelFn)(GpPlanDesc, CountArgs);
+
+template <int G>
+struct Ctx {
+    const int64_t* row_ptr;
+    const int32_t* col;
+    int32_t* bufs;
+    int64_t cap;
+    int32_t* lens;  // LDS: length per buffer slot
+    uint64_t* bytes;  // accounting mode: per-lane algorithmic bytes
+    Group<G> g;
+
+    __device__ __forceinline__ Set nbr(int32_t v) const {
+        int64_t b = row_ptr[v], e = row_ptr[v + 1];
+        return Set{col + b, (int32_t)(e - b)};
+    }
+    __device__ __forceinline__ Set buf(int slot) const {
+        return Set{bufs + (int64_t)slot * cap, lens[slot]};
+    }
+};
+
+// v[idx] for a runtime idx without dynamic register indexing.
+template <int K>
+__device__ __forceinline__ int32_t pick(const int32_t (&v)[K], int idx) {
+    int32_t r = v[0];
+#pragma unroll
+    for (int j = 1; j < K; ++j) r = (idx == j) ? v[j] : r;
+    return r;
+}
+
+template <int K>
+__device__ __forceinline__ void bounds(uint32_t hi_src, uint32_t lo_src, const int32_t (&v)[K],
+                                       int32_t& lo, int32_t& hi) {
+    lo = 0;
+    hi = 0x7fffffff;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if ((hi_src >> j) & 1u) hi = min(hi, v[j]);
+        if ((lo_src >> j) & 1u) lo = max(lo, v[j] + 1);
+    }
+}
+
+template <int K>
+__device__ __forceinline__ bool inj_hit(uint32_t inj, const int32_t (&v)[K], int32_t x) {
+    bool hit = false;
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        if ((inj >> j) & 1u) hit |= (v[j] == x);
+    return hit;
+}
+
+__device__ __forceinline__ void add_count(uint64_t& acc, uint64_t c, bool& ovf) {
+    uint64_t s = acc + c;
+    ovf |= (s < acc);
+    acc = s;
+}
+
+// Algorithmic bytes of one binary search in a sorted list of n int32.
+__device__ __forceinline__ uint64_t probe_bytes(int32_t n) {
+    return 4ull * (uint64_t)(32 - __clz(n > 0 ? n : 1));
+}
+
+__device__ __forceinline__ void group_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Builds scheduled right after level h is bound.
+template <int K, int G, int MODE>
+__device__ __forceinline__ void run_builds(const GpPlanDesc& d, const Ctx<G>& c, int h,
+                                           const int32_t (&v)[K]) {
+    const int b0 = d.build_begin[h], b1 = d.build_end[h];
+    for (int t = b0; t < b1; ++t) {
+        const GpBuild& b = d.b[t];
+        int32_t lo, hi;
+        bounds<K>(b.hi_src, b.lo_src, v, lo, hi);
+        Set A = b.src_buf >= 0 ? c.buf(b.src_buf) : c.nbr(pick<K>(v, b.src_list));
+        Set B = c.nbr(pick<K>(v, b.with_list));
+        A = trim(A, lo, hi);
+        B = trim(B, lo, hi);
+        if constexpr (MODE == MODE_ACCOUNT)
+            if (c.g.gl == 0) *c.bytes += 4ull * (uint64_t)(A.n + B.n);
+        int32_t n = intersect_into<G>(c.g, A, B, c.bufs + (int64_t)b.dst * c.cap);
+        group_fence();
+        c.lens[b.dst] = n;
+        group_fence();
+    }
+}
+
+// Count of the last level for bound values v[0..K-2], by one lane.
+template <int K, int G, int MODE>
+__device__ __forceinline__ uint32_t leaf_serial(const GpPlanDesc& d, const Ctx<G>& c,
+                                                const int32_t (&v)[K]) {
+    const GpLevel& lv = d.lv[K - 1];
+    int32_t lo, hi;
+    bounds<K>(lv.hi_src, lv.lo_src, v, lo, hi);
+    if (lv.last_list < 0) {
+        Set S = lv.list >= 0 ? c.nbr(pick<K>(v, lv.list)) : c.buf(lv.buf);
+        if constexpr (MODE == MODE_ACCOUNT)
+            *c.bytes += probe_bytes(S.n) * (uint64_t)((lo > 0) + (hi < 0x7fffffff));
+        S = trim(S, lo, hi);
+        uint32_t cnt = (uint32_t)S.n;
+#pragma unroll
+        for (int j = 0; j < K - 1; ++j) {
+            if ((lv.inj >> j) & 1u) {
+                int32_t y = v[j];
+                if (y >= lo && y < hi) {
+                    if constexpr (MODE == MODE_ACCOUNT) *c.bytes += probe_bytes(S.n);
+                    if (contains(S.p, S.n, y)) --cnt;
+                }
+            }
+        }
+        return cnt;
+    }
+    Set A = lv.pre_buf >= 0 ? c.buf(lv.pre_buf) : c.nbr(pick<K>(v, lv.pre_list));
+    Set B = c.nbr(pick<K>(v, lv.last_list));
+    A = trim(A, lo, hi);
+    B = trim(B, lo, hi);
+    if constexpr (MODE == MODE_ACCOUNT) *c.bytes += 4ull * (uint64_t)(A.n + B.n);
+    uint32_t cnt = intersect_count_serial(A, B);
+#pragma unroll
+    for (int j = 0; j < K - 1; ++j) {
+        if ((lv.inj >> j) & 1u) {
+            int32_t y = v[j];
+            if (y >= lo && y < hi && contains(A.p, A.n, y) && contains(B.p, B.n, y)) --cnt;
+        }
+    }
+    return cnt;
+}
+
+// Count of the last level, computed by the whole group (same value in every lane).
+template <int K, int G, int MODE>
+__device__ __forceinline__ uint32_t leaf_group(const GpPlanDesc& d, const Ctx<G>& c,
+                                               const int32_t (&v)[K]) {
+    const GpLevel& lv = d.lv[K - 1];
+    if (lv.last_list < 0) {
+        // every lane computes the same count; only lane 0 keeps the bytes
+        uint64_t keep = 0;
+        if constexpr (MODE == MODE_ACCOUNT) keep = *c.bytes;
+        uint32_t r = leaf_serial<K, G, MODE>(d, c, v);
+        if constexpr (MODE == MODE_ACCOUNT)
+            if (c.g.gl != 0) *c.bytes = keep;
+        return r;
+    }
+    int32_t lo, hi;
+    bounds<K>(lv.hi_src, lv.lo_src, v, lo, hi);
+    Set A = lv.pre_buf >= 0 ? c.buf(lv.pre_buf) : c.nbr(pick<K>(v, lv.pre_list));
+    Set B = c.nbr(pick<K>(v, lv.last_list));
+    A = trim(A, lo, hi);
+    B = trim(B, lo, hi);
+    if constexpr (MODE == MODE_ACCOUNT)
+        if (c.g.gl == 0) *c.bytes += 4ull * (uint64_t)(A.n + B.n);
+    uint32_t cnt = intersect_count_group<G>(c.g, A, B);
+#pragma unroll
+    for (int j = 0; j < K - 1; ++j) {
+        if ((lv.inj >> j) & 1u) {
+            int32_t y = v[j];
+            if (y >= lo && y < hi && contains(A.p, A.n, y) && contains(B.p, B.n, y)) --cnt;
+        }
+    }
+    return cnt;
+}
+
+template <int K, int L, int G, int LEAF, int MODE>
+__device__ void search(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], uint64_t& acc,
+                       bool& ovf) {
+    const GpLevel& lv = d.lv[L];
+    int32_t lo, hi;
+    bounds<K>(lv.hi_src, lv.lo_src, v, lo, hi);
+    Set S = lv.list >= 0 ? c.nbr(pick<K>(v, lv.list)) : c.buf(lv.buf);
+    S = trim(S, lo, hi);
+    if constexpr (MODE == MODE_ACCOUNT)
+        if (c.g.gl == 0) *c.bytes += 4ull * (uint64_t)S.n;
+    if constexpr (L == K - 2) {
+        if constexpr (LEAF == 1) {
+            for (int32_t base = 0; base < S.n; base += G) {
+                int32_t i = base + c.g.gl;
+                if (i < S.n) {
+                    int32_t x = S.p[i];
+                    if (!inj_hit<K>(lv.inj, v, x)) {
+                        int32_t w[K];
+#pragma unroll
+                        for (int j = 0; j < K; ++j) w[j] = v[j];
+                        w[K - 2] = x;
+                        add_count(acc, leaf_serial<K, G, MODE>(d, c, w), ovf);
+                    }
+                }
+            }
+        } else {
+            for (int32_t t = 0; t < S.n; ++t) {
+                int32_t x = S.p[t];
+                if (inj_hit<K>(lv.inj, v, x)) continue;
+                v[K - 2] = x;
+                uint32_t cnt = leaf_group<K, G, MODE>(d, c, v);
+                if (c.g.gl == 0) add_count(acc, cnt, ovf);
+            }
+        }
+    } else {
+        for (int32_t t = 0; t < S.n; ++t) {
+            int32_t x = S.p[t];
+            if (inj_hit<K>(lv.inj, v, x)) continue;
+            v[L] = x;
+            run_builds<K, G, MODE>(d, c, L, v);
+            search<K, L + 1, G, LEAF, MODE>(d, c, v, acc, ovf);
+        }
+    }
+}
+
+__device__ __forceinline__ int64_t entry_index(const int64_t* row_ptr, const int32_t* col,
+                                               int32_t v0, int32_t v1) {
+    int64_t b = row_ptr[v0];
+    return b + lower_bound(col + b, (int32_t)(row_ptr[v0 + 1] - b), v1);
+}
+
+template <int K, int G, int LEAF, int MODE>
+__global__ __launch_bounds__(kBlock) void count_kernel(GpPlanDesc d, CountArgs a) {
+    constexpr bool PER_ROOT = MODE == MODE_PER_ROOT;
+    __shared__ int32_t s_len[kBlock / G][GP_DESC_MAX_BUILDS];
+    Ctx<G> c;
+    c.row_ptr = a.row_ptr;
+    c.col = a.col;
+    c.cap = a.buf_cap;
+    const int grp = threadIdx.x / G;
+    const int64_t group_id = (int64_t)blockIdx.x * (kBlock / G) + grp;
+    c.bufs = a.scratch ? a.scratch + group_id * (int64_t)d.nbuf * a.buf_cap : nullptr;
+    c.lens = s_len[grp];
+    uint64_t bytes = 0;
+    c.bytes = &bytes;
+
+    uint64_t acc = 0;
+    bool ovf = false;
+    const int64_t chunk = a.chunk;
+
+    for (;;) {
+        unsigned long long t0 = 0;
+        if (c.g.gl == 0) t0 = atomicAdd(a.queue, (unsigned long long)chunk);
+        t0 = c.g.bcast(t0, 0);
+        if ((int64_t)t0 >= a.n_roots) break;
+        const int64_t t1 = min((int64_t)t0 + chunk, a.n_roots);
+        if constexpr (K <= 3 && LEAF == 1) {
+            // lanes take different roots
+            for (int64_t base = (int64_t)t0; base < t1; base += G) {
+                int64_t r = base + c.g.gl;
+                if (r < t1) {
+                    int2 e = a.roots[r];
+                    uint64_t cnt = 1;
+                    if constexpr (MODE == MODE_ACCOUNT) bytes += 8;
+                    if constexpr (K == 3) {
+                        int32_t w[K] = {e.x, e.y, 0};
+                        cnt = leaf_serial<K, G, MODE>(d, c, w);
+                    }
+                    add_count(acc, cnt, ovf);
+                    if constexpr (PER_ROOT)
+                        a.per_root[entry_index(a.row_ptr, a.col, e.x, e.y)] = cnt;
+                }
+            }
+        } else {
+            for (int64_t r = (int64_t)t0; r < t1; ++r) {
+                int2 e = a.roots[r];
+                const uint64_t before = acc;
+                if constexpr (MODE == MODE_ACCOUNT)
+                    if (c.g.gl == 0) bytes += 8;
+                if constexpr (K <= 3) {
+                    uint64_t cnt = 1;
+                    if constexpr (K == 3) {
+                        int32_t w[K] = {e.x, e.y, 0};
+                        cnt = leaf_group<K, G, MODE>(d, c, w);
+                    }
+                    if (c.g.gl == 0) add_count(acc, cnt, ovf);
+                } else {
+                    int32_t v[K];
+#pragma unroll
+                    for (int j = 0; j < K; ++j) v[j] = 0;
+                    v[0] = e.x;
+                    v[1] = e.y;
+                    run_builds<K, G, MODE>(d, c, 1, v);
+                    search<K, 2, G, LEAF, MODE>(d, c, v, acc, ovf);
+                }
+                if constexpr (PER_ROOT) {
+                    uint64_t mine = c.g.sum(acc - before);
+                    if (c.g.gl == 0) a.per_root[entry_index(a.row_ptr, a.col, e.x, e.y)] = mine;
+                }
+            }
+        }
+    }
+
+    // wavefront reduction with carry detection, one atomic per wavefront
+    uint64_t s = acc;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        uint64_t t = __shfl_xor(s, off, 64);
+        uint64_t u = s + t;
+        ovf |= (u < s);
+        s = u;
+    }
+    const bool any_ovf = __ballot(ovf) != 0;
+    if constexpr (MODE == MODE_ACCOUNT) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) bytes += __shfl_xor(bytes, off, 64);
+    }
+    if (__lane_id() == 0) {
+        unsigned long long old = atomicAdd(&a.result[0], (unsigned long long)s);
+        if (any_ovf || old + s < old) atomicOr(&a.result[1], 1ull);
+        if constexpr (MODE == MODE_ACCOUNT) atomicAdd(&a.result[2], (unsigned long long)bytes);
+    }
+}
+
+}  // namespace gpcount

@@ -33,12 +33,13 @@ struct LaunchCfg {
     int leaf = 1;
 };
 
-// Launch one count of plan d over g on `stream`. result_dev: 2 x u64
-// {count, overflow flag}, zeroed by this call on the stream. per_root may be
-// null. Scratch is allocated stream-ordered and released after the kernel.
+// Launch one count of plan d over g on `stream`. result_dev: {count,
+// overflow flag} (plus algorithmic bytes when `account`), zeroed by this call
+// on the stream. per_root may be null. Scratch is allocated stream-ordered
+// and released after the kernel.
 gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCfg& cfg,
                        hipStream_t stream, unsigned long long* result_dev,
-                       unsigned long long* per_root);
+                       unsigned long long* per_root, bool account = false);
 
 // Launch one persistent kernel over the union of the plans' root tasks.
 // result_dev: 2*np u64 ({count, overflow} per plan).

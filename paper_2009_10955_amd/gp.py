@@ -87,6 +87,8 @@ SIGNATURES = {
     "gp_count_per_root": (_I32, [_P, _P, ctypes.POINTER(Launch), _P, _P,
                                  ctypes.POINTER(ctypes.c_uint64)]),
     "gp_count_batch": (_I32, [_P, _P, _I32, ctypes.POINTER(Launch), _P, _P]),
+    "gp_count_traffic": (_I32, [_P, _P, ctypes.POINTER(Launch), _P,
+                                ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]),
     "gp_strerror": (ctypes.c_char_p, [_I32]),
     "gp_version": (ctypes.c_char_p, []),
 }
@@ -319,6 +321,17 @@ def count_per_root(graph: Graph, plan: Plan, stream=None, **launch):
                                     _stream_handle(stream), per.data_ptr(), ctypes.byref(out)),
            "gp_count_per_root")
     return out.value, per[:2 * s.m]
+
+
+def count_traffic(graph: Graph, plan: Plan, stream=None, **launch) -> tuple[int, int]:
+    """(count, algorithmic bytes) from the instrumented kernel (blocking)."""
+    out = ctypes.c_uint64()
+    b = ctypes.c_uint64()
+    lp = _launch(**launch)
+    _check(_lib().gp_count_traffic(graph.handle, plan.handle, ctypes.byref(lp),
+                                   _stream_handle(stream), ctypes.byref(out), ctypes.byref(b)),
+           "gp_count_traffic")
+    return out.value, b.value
 
 
 def count_batch(graph: Graph, plans: Sequence[Plan], stream=None, **launch) -> list[int]:

@@ -99,6 +99,23 @@ gp_status gp_graph_layout(const gp_graph* g, int64_t* row_ptr, int32_t* col);
 
 void gp_free_graph(gp_graph* g);
 
+/* ----------------------------------------------------------------- launch */
+
+/* Launch shape of the counting kernel. Zero fields mean "the plan's own"
+ * (its tuned shape after gp_plan_tune, else the defaults). */
+typedef struct {
+    int32_t group;         /* lanes that share one search path: 64, 32, 16 or 8 (0 = auto) */
+    int32_t waves_per_cu;  /* resident wavefronts per compute unit for the persistent grid
+                              (0 = auto) */
+    int32_t chunk;         /* root tasks taken per queue grab (0 = auto) */
+    int32_t leaf_mode;     /* 0 auto, 1: lanes take different second-to-last candidates and
+                              count the last level alone, 2: the group counts each one together */
+    int32_t root_stride;   /* count only every root_stride-th root task (0 or 1 = all), */
+    int32_t root_offset;   /* starting at root_offset: a seeded root sample for tuning */
+} gp_launch;
+
+void gp_launch_default(gp_launch* l);
+
 /* ------------------------------------------------------------------- plan */
 
 typedef struct gp_plan gp_plan;
@@ -144,7 +161,10 @@ typedef struct {
     int32_t n_schedules;       /* efficient schedules (Phase 1 + Phase 2) */
     int32_t k_eff;             /* Phase-2 k actually used */
     int32_t set_index;         /* index of the chosen set in emission order (-1 if forced pairs) */
-    double plan_seconds;       /* host wall time of gp_plan_create */
+    double plan_seconds;       /* host wall time of gp_plan_create (plus gp_plan_tune) */
+    int32_t tuned;             /* 1 if the configuration and launch were measured by gp_plan_tune */
+    int32_t n_measured;        /* configurations timed by gp_plan_tune */
+    gp_launch launch;          /* launch shape used when the caller passes none */
 } gp_plan_info;
 
 gp_status gp_plan_get(const gp_plan* p, gp_plan_info* out);
@@ -160,20 +180,35 @@ gp_status gp_plan_get_schedule(const gp_plan* p, int32_t idx, int32_t* order);
 gp_status gp_plan_model_cost(const gp_plan* p, int32_t idx_s, int32_t idx_r,
                              const gp_stats* stats, double* cost);
 
+typedef struct {
+    int32_t max_configs;    /* distinct configurations to time (0 = 12) */
+    int32_t sample_stride;  /* time roots[offset + t * stride] only (0 = auto, aiming at
+                               ~40 ms per run) */
+    int32_t tune_launch;    /* 1 (default): also pick lanes per group, leaf mode and waves per
+                               CU for the chosen configuration; -1: keep the defaults */
+    double budget_seconds;  /* stop timing once this much GPU time is spent (0 = 20 s) */
+} gp_tune_opts;
+
+void gp_tune_opts_default(gp_tune_opts* o);
+
+/*
+ * Measured configuration selection for graph g: the paper's model ranks the
+ * (schedule, restriction set) configurations (Section IV-C) but sees only
+ * |V|, |E| and tri_cnt, and the paper reports its choice 32% slower than the
+ * best schedule on average (Section V-C). This call takes the best-ranked
+ * configurations, adds each one's mirror (every pair reversed, also valid),
+ * drops configurations that compile to the same search, times each on a
+ * strided sample of its root tasks on `stream`, keeps the fastest, then times
+ * launch shapes for it. *out is a new plan (same pattern, same counts) whose
+ * default launch is the measured best. Blocking.
+ */
+gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* opts, void* stream,
+                       gp_plan** out);
+
 void gp_free_plan(gp_plan* p);
 
 /* ------------------------------------------------------------------ count */
 
-typedef struct {
-    int32_t group;         /* lanes that share one search path: 64, 32, 16 or 8 (0 = auto) */
-    int32_t waves_per_cu;  /* resident wavefronts per compute unit for the persistent grid
-                              (0 = auto) */
-    int32_t chunk;         /* root tasks taken per queue grab (0 = auto) */
-    int32_t leaf_mode;     /* 0 auto, 1: lanes take different second-to-last candidates and
-                              count the last level alone, 2: the group counts each one together */
-} gp_launch;
-
-void gp_launch_default(gp_launch* l);
 
 /*
  * Count the embeddings of plan p in graph g (exact, unsigned 64-bit).

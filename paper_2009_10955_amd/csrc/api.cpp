@@ -16,20 +16,7 @@ gp_status build_layout(const int64_t* row_ptr, const int32_t* col, int64_t n, in
                        hipStream_t s, DeviceGraph* g);
 }
 
-struct gp_graph {
-    gpint::DeviceGraph dg;
-};
-
-struct gp_plan {
-    gp::Pattern pattern;
-    uint64_t aut = 0;
-    std::vector<gp::Rel> sets;
-    std::vector<gp::Perm> schedules;
-    gp::Perm order{};
-    gp::Rel set = 0;
-    GpPlanDesc desc{};
-    gp_plan_info info{};
-};
+#include "api_internal.hpp"
 
 namespace {
 
@@ -371,6 +358,7 @@ gp_status gp_plan_create(const int32_t* edges, int32_t k, int32_t e, const gp_st
         delete p;
         return rc;
     }
+    p->launch = gpint::default_launch(p->desc);
     gp_plan_info& in = p->info;
     std::memset(&in, 0, sizeof in);
     in.k = k;
@@ -392,6 +380,7 @@ gp_status gp_plan_create(const int32_t* edges, int32_t k, int32_t e, const gp_st
     in.k_eff = sc.k_eff;
     in.set_index = cand_index[bs];
     in.plan_seconds = now_seconds() - t0;
+    in.tuned = 0;
     *out = p;
     return GP_OK;
 }
@@ -399,6 +388,12 @@ gp_status gp_plan_create(const int32_t* edges, int32_t k, int32_t e, const gp_st
 gp_status gp_plan_get(const gp_plan* p, gp_plan_info* out) {
     if (!p || !out) return GP_ERR_ARG;
     *out = p->info;
+    out->launch.group = p->launch.group;
+    out->launch.waves_per_cu = p->launch.waves_per_cu;
+    out->launch.chunk = p->launch.chunk;
+    out->launch.leaf_mode = p->launch.leaf;
+    out->launch.root_stride = 0;
+    out->launch.root_offset = 0;
     return GP_OK;
 }
 
@@ -448,7 +443,7 @@ gp_status gp_count(const gp_graph* g, const gp_plan* p, const gp_launch* launch,
                    uint64_t* out) {
     if (!g || !p || !out) return GP_ERR_ARG;
     DeviceGuard dgd(g->dg.device);
-    gpint::LaunchCfg cfg = gpint::resolve_launch(launch, p->desc, g->dg);
+    gpint::LaunchCfg cfg = gpint::launch_for_plan(p, launch, g->dg);
     return count_to_host(g, p->desc, cfg, (hipStream_t)stream, nullptr, out);
 }
 
@@ -456,7 +451,7 @@ gp_status gp_count_async(const gp_graph* g, const gp_plan* p, const gp_launch* l
                          uint64_t* dev_out) {
     if (!g || !p || !dev_out) return GP_ERR_ARG;
     DeviceGuard dgd(g->dg.device);
-    gpint::LaunchCfg cfg = gpint::resolve_launch(launch, p->desc, g->dg);
+    gpint::LaunchCfg cfg = gpint::launch_for_plan(p, launch, g->dg);
     return gpint::launch_count(g->dg, p->desc, cfg, (hipStream_t)stream,
                                reinterpret_cast<unsigned long long*>(dev_out), nullptr);
 }
@@ -467,7 +462,7 @@ gp_status gp_count_per_root(const gp_graph* g, const gp_plan* p, const gp_launch
     DeviceGuard dgd(g->dg.device);
     hipStream_t s = (hipStream_t)stream;
     if (g->dg.nnz > 0) GP_HIP_TRY(hipMemsetAsync(dev_per_root, 0, sizeof(uint64_t) * g->dg.nnz, s));
-    gpint::LaunchCfg cfg = gpint::resolve_launch(launch, p->desc, g->dg);
+    gpint::LaunchCfg cfg = gpint::launch_for_plan(p, launch, g->dg);
     return count_to_host(g, p->desc, cfg, s, reinterpret_cast<unsigned long long*>(dev_per_root), out);
 }
 
@@ -475,7 +470,7 @@ gp_status gp_count_traffic(const gp_graph* g, const gp_plan* p, const gp_launch*
                            uint64_t* out, uint64_t* alg_bytes) {
     if (!g || !p || !out || !alg_bytes) return GP_ERR_ARG;
     DeviceGuard dgd(g->dg.device);
-    gpint::LaunchCfg cfg = gpint::resolve_launch(launch, p->desc, g->dg);
+    gpint::LaunchCfg cfg = gpint::launch_for_plan(p, launch, g->dg);
     return count_to_host(g, p->desc, cfg, (hipStream_t)stream, nullptr, out, alg_bytes);
 }
 
@@ -488,7 +483,7 @@ gp_status gp_count_batch(const gp_graph* g, const gp_plan* const* plans, int32_t
     hipStream_t s = (hipStream_t)stream;
     std::vector<GpPlanDesc> descs(np);
     for (int i = 0; i < np; ++i) descs[i] = plans[i]->desc;
-    gpint::LaunchCfg cfg = gpint::resolve_launch(launch, descs[0], g->dg);
+    gpint::LaunchCfg cfg = gpint::launch_for_plan(plans[0], launch, g->dg);
     unsigned long long* res = nullptr;
     GP_HIP_TRY(hipMallocAsync((void**)&res, 2 * sizeof(unsigned long long) * np, s));
     gp_status st = gpint::launch_count_batch(g->dg, descs.data(), np, cfg, s, res);

@@ -1,0 +1,30 @@
+// Handle types behind the C ABI, shared by the API and tuner units.
+#pragma once
+#include <vector>
+
+#include "gp.h"
+#include "internal.hpp"
+#include "planner.hpp"
+
+struct gp_graph {
+    gpint::DeviceGraph dg;
+};
+
+struct gp_plan {
+    gp::Pattern pattern;
+    uint64_t aut = 0;
+    std::vector<gp::Rel> sets;
+    std::vector<gp::Perm> schedules;
+    gp::Perm order{};
+    gp::Rel set = 0;
+    GpPlanDesc desc{};
+    gp_plan_info info{};
+    bool tuned = false;          // launch below was measured on a graph
+    gpint::LaunchCfg launch{};
+};
+
+namespace gpint {
+// Launch configuration for a count of plan p: the plan's tuned launch (if
+// any) or the defaults, with every non-zero field of l overriding it.
+LaunchCfg launch_for_plan(const gp_plan* p, const gp_launch* l, const DeviceGraph& g);
+}  // namespace gpint

@@ -39,18 +39,23 @@ using namespace gpcount;
 
 namespace gpint {
 
-LaunchCfg resolve_launch(const gp_launch* l, const GpPlanDesc& d, const DeviceGraph& g) {
+LaunchCfg default_launch(const GpPlanDesc& d) {
     LaunchCfg cfg;
-    (void)g;
     cfg.group = 16;
     cfg.waves_per_cu = 16;
     cfg.chunk = d.k <= 3 ? 256 : 4;
     cfg.leaf = 1;
+    return cfg;
+}
+
+LaunchCfg apply_launch(LaunchCfg cfg, const gp_launch* l) {
     if (l) {
         if (l->group) cfg.group = l->group;
         if (l->waves_per_cu) cfg.waves_per_cu = l->waves_per_cu;
         if (l->chunk) cfg.chunk = l->chunk;
         if (l->leaf_mode) cfg.leaf = l->leaf_mode;
+        if (l->root_stride) cfg.root_stride = l->root_stride;
+        cfg.root_offset = l->root_offset;
     }
     return cfg;
 }
@@ -78,8 +83,12 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
     KernelFn fn = pick_kernel(d.k, cfg.group, cfg.leaf, mode);
     if (!fn) return GP_ERR_UNSUPPORTED;
 
-    int64_t n_roots = 0;
-    const int2* roots = pick_roots(g, d.root_cut, &n_roots);
+    int64_t all_roots = 0;
+    const int2* roots = pick_roots(g, d.root_cut, &all_roots);
+    if (cfg.root_stride < 1 || cfg.root_offset < 0) return GP_ERR_ARG;
+    // sampled task space: roots[offset + t * stride]
+    const int64_t n_roots =
+        all_roots > cfg.root_offset ? (all_roots - cfg.root_offset + cfg.root_stride - 1) / cfg.root_stride : 0;
 
     const int waves_per_block = kBlock / 64;
     int64_t blocks = std::max<int64_t>(1, (int64_t)g.num_cus * cfg.waves_per_cu / waves_per_block);
@@ -115,6 +124,8 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
     a.col = g.col;
     a.roots = roots;
     a.n_roots = n_roots;
+    a.root_offset = cfg.root_offset;
+    a.root_stride = cfg.root_stride;
     a.scratch = scratch;
     a.buf_cap = cap;
     a.queue = queue;

@@ -46,7 +46,9 @@ struct CountArgs {
     const int64_t* row_ptr;
     const int32_t* col;
     const int2* roots;
-    int64_t n_roots;
+    int64_t n_roots;      // tasks: roots[root_offset + t * root_stride], t < n_roots
+    int64_t root_offset;
+    int64_t root_stride;
     int32_t* scratch;
     int64_t buf_cap;
     unsigned long long* queue;
@@ -174,15 +176,10 @@ __device__ __forceinline__ uint32_t leaf_serial(const GpPlanDesc& d, const Ctx<G
     A = trim(A, lo, hi);
     B = trim(B, lo, hi);
     if constexpr (MODE == MODE_ACCOUNT) *c.bytes += 4ull * (uint64_t)(A.n + B.n);
-    uint32_t cnt = intersect_count_serial(A, B);
-#pragma unroll
-    for (int j = 0; j < K - 1; ++j) {
-        if ((lv.inj >> j) & 1u) {
-            int32_t y = v[j];
-            if (y >= lo && y < hi && contains(A.p, A.n, y) && contains(B.p, B.n, y)) --cnt;
-        }
-    }
-    return cnt;
+    // injectivity folded into the intersection: matches equal to an earlier
+    // image are not counted
+    const uint32_t inj = lv.inj;
+    return intersect_count_serial(A, B, [&](int32_t x) { return inj_hit<K>(inj, v, x); });
 }
 
 // Count of the last level, computed by the whole group (same value in every lane).
@@ -207,15 +204,8 @@ __device__ __forceinline__ uint32_t leaf_group(const GpPlanDesc& d, const Ctx<G>
     B = trim(B, lo, hi);
     if constexpr (MODE == MODE_ACCOUNT)
         if (c.g.gl == 0) *c.bytes += 4ull * (uint64_t)(A.n + B.n);
-    uint32_t cnt = intersect_count_group<G>(c.g, A, B);
-#pragma unroll
-    for (int j = 0; j < K - 1; ++j) {
-        if ((lv.inj >> j) & 1u) {
-            int32_t y = v[j];
-            if (y >= lo && y < hi && contains(A.p, A.n, y) && contains(B.p, B.n, y)) --cnt;
-        }
-    }
-    return cnt;
+    const uint32_t inj = lv.inj;
+    return intersect_count_group<G>(c.g, A, B, [&](int32_t x) { return inj_hit<K>(inj, v, x); });
 }
 
 template <int K, int L, int G, int LEAF, int MODE>
@@ -299,7 +289,7 @@ __global__ __launch_bounds__(kBlock) void count_kernel(GpPlanDesc d, CountArgs a
             for (int64_t base = (int64_t)t0; base < t1; base += G) {
                 int64_t r = base + c.g.gl;
                 if (r < t1) {
-                    int2 e = a.roots[r];
+                    int2 e = a.roots[a.root_offset + r * a.root_stride];
                     uint64_t cnt = 1;
                     if constexpr (MODE == MODE_ACCOUNT) bytes += 8;
                     if constexpr (K == 3) {
@@ -313,7 +303,7 @@ __global__ __launch_bounds__(kBlock) void count_kernel(GpPlanDesc d, CountArgs a
             }
         } else {
             for (int64_t r = (int64_t)t0; r < t1; ++r) {
-                int2 e = a.roots[r];
+                int2 e = a.roots[a.root_offset + r * a.root_stride];
                 const uint64_t before = acc;
                 if constexpr (MODE == MODE_ACCOUNT)
                     if (c.g.gl == 0) bytes += 8;

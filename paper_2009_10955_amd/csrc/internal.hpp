@@ -31,6 +31,8 @@ struct LaunchCfg {
     int waves_per_cu = 8;
     int chunk = 8;
     int leaf = 1;
+    int64_t root_stride = 1;  // count only roots[offset + t * stride]
+    int64_t root_offset = 0;
 };
 
 // Launch one count of plan d over g on `stream`. result_dev: {count,
@@ -47,8 +49,10 @@ gp_status launch_count_batch(const DeviceGraph& g, const GpPlanDesc* descs, int 
                              const LaunchCfg& cfg, hipStream_t stream,
                              unsigned long long* result_dev);
 
-// Resolve "auto" fields of a launch configuration.
-LaunchCfg resolve_launch(const gp_launch* l, const GpPlanDesc& d, const DeviceGraph& g);
+// Launch defaults for a plan descriptor, and overriding them with the
+// non-zero fields of a caller's gp_launch.
+LaunchCfg default_launch(const GpPlanDesc& d);
+LaunchCfg apply_launch(LaunchCfg cfg, const gp_launch* l);
 
 }  // namespace gpint
 

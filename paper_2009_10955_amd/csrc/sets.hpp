@@ -46,8 +46,9 @@ __device__ __forceinline__ Set trim(Set s, int32_t lo, int32_t hi) {
     return Set{s.p + b, e - b};
 }
 
-// |A ∩ B| by one lane.
-__device__ __forceinline__ uint32_t intersect_count_serial(Set a, Set b) {
+// |A ∩ B| by one lane, not counting elements x with skip(x).
+template <typename Skip>
+__device__ __forceinline__ uint32_t intersect_count_serial(Set a, Set b, Skip skip) {
     if (a.n > b.n) {
         Set t = a;
         a = b;
@@ -63,7 +64,7 @@ __device__ __forceinline__ uint32_t intersect_count_serial(Set a, Set b) {
             int32_t x = a.p[i];
             int32_t j = lower_bound(p, n, x);
             if (j < n && p[j] == x) {
-                ++c;
+                c += !skip(x);
                 ++j;
             }
             p += j;
@@ -74,11 +75,15 @@ __device__ __forceinline__ uint32_t intersect_count_serial(Set a, Set b) {
     int32_t i = 0, j = 0;
     while (i < a.n && j < b.n) {
         int32_t x = a.p[i], y = b.p[j];
-        c += (x == y);
+        if (x == y) c += !skip(x);
         i += (x <= y);
         j += (y <= x);
     }
     return c;
+}
+
+__device__ __forceinline__ uint32_t intersect_count_serial(Set a, Set b) {
+    return intersect_count_serial(a, b, [](int32_t) { return false; });
 }
 
 // A group of G consecutive lanes of one wavefront acting together.
@@ -138,9 +143,9 @@ __device__ __forceinline__ int32_t intersect_into(const Group<G>& g, Set a, Set 
     return out;
 }
 
-// Group-cooperative |A ∩ B| (same value in every lane).
-template <int G>
-__device__ __forceinline__ uint32_t intersect_count_group(const Group<G>& g, Set a, Set b) {
+// Group-cooperative |A ∩ B| not counting x with skip(x) (same value in every lane).
+template <int G, typename Skip>
+__device__ __forceinline__ uint32_t intersect_count_group(const Group<G>& g, Set a, Set b, Skip skip) {
     if (a.n > b.n) {
         Set t = a;
         a = b;
@@ -150,7 +155,10 @@ __device__ __forceinline__ uint32_t intersect_count_group(const Group<G>& g, Set
     for (int32_t base = 0; base < a.n; base += G) {
         int32_t i = base + g.gl;
         bool found = false;
-        if (i < a.n) found = contains(b.p, b.n, a.p[i]);
+        if (i < a.n) {
+            int32_t x = a.p[i];
+            found = contains(b.p, b.n, x) && !skip(x);
+        }
         out += (uint32_t)__popcll(g.ballot(found));
     }
     return out;

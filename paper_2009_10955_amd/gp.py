@@ -48,18 +48,27 @@ class PlanOpts(ctypes.Structure):
                 ("cost_cap", ctypes.c_double)]
 
 
+class Launch(ctypes.Structure):
+    _fields_ = [("group", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("leaf_mode", ctypes.c_int32),
+                ("root_stride", ctypes.c_int32), ("root_offset", ctypes.c_int32)]
+
+
+class TuneOpts(ctypes.Structure):
+    _fields_ = [("max_configs", ctypes.c_int32), ("sample_stride", ctypes.c_int32),
+                ("tune_launch", ctypes.c_int32), ("budget_seconds", ctypes.c_double)]
+
+
 class PlanInfo(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("order", ctypes.c_int32 * MAX_K),
                 ("n_restr", ctypes.c_int32), ("restr", ctypes.c_int32 * (2 * MAX_K * MAX_K)),
                 ("aut", ctypes.c_uint64), ("cost", ctypes.c_double), ("n_sets", ctypes.c_int32),
                 ("n_states", ctypes.c_int64), ("n_schedules", ctypes.c_int32),
                 ("k_eff", ctypes.c_int32), ("set_index", ctypes.c_int32),
-                ("plan_seconds", ctypes.c_double)]
+                ("plan_seconds", ctypes.c_double), ("tuned", ctypes.c_int32),
+                ("n_measured", ctypes.c_int32), ("launch", Launch)]
 
 
-class Launch(ctypes.Structure):
-    _fields_ = [("group", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
-                ("chunk", ctypes.c_int32), ("leaf_mode", ctypes.c_int32)]
 
 
 # every symbol include/gp.h declares, with (restype, argtypes)
@@ -81,6 +90,8 @@ SIGNATURES = {
     "gp_plan_model_cost": (_I32, [_P, _I32, _I32, ctypes.POINTER(Stats),
                                   ctypes.POINTER(ctypes.c_double)]),
     "gp_free_plan": (None, [_P]),
+    "gp_tune_opts_default": (None, [ctypes.POINTER(TuneOpts)]),
+    "gp_plan_tune": (_I32, [_P, _P, ctypes.POINTER(TuneOpts), _P, ctypes.POINTER(_P)]),
     "gp_launch_default": (None, [ctypes.POINTER(Launch)]),
     "gp_count": (_I32, [_P, _P, ctypes.POINTER(Launch), _P, ctypes.POINTER(ctypes.c_uint64)]),
     "gp_count_async": (_I32, [_P, _P, ctypes.POINTER(Launch), _P, _P]),
@@ -130,8 +141,8 @@ def _stream_handle(stream) -> int:
     return stream.cuda_stream
 
 
-def _launch(group=0, waves_per_cu=0, chunk=0, leaf_mode=0) -> Launch:
-    return Launch(group, waves_per_cu, chunk, leaf_mode)
+def _launch(group=0, waves_per_cu=0, chunk=0, leaf_mode=0, root_stride=0, root_offset=0) -> Launch:
+    return Launch(group, waves_per_cu, chunk, leaf_mode, root_stride, root_offset)
 
 
 class Graph:
@@ -280,6 +291,23 @@ class Plan:
                                          ctypes.byref(stats) if stats is not None else None,
                                          ctypes.byref(c)), "gp_plan_model_cost")
         return c.value
+
+    def tuned(self, graph: "Graph", max_configs: int = 0, sample_stride: int = 0,
+              tune_launch: bool = True, budget_seconds: float = 0.0, stream=None) -> "Plan":
+        """A new plan whose configuration and launch shape were timed on graph."""
+        o = TuneOpts(max_configs, sample_stride, 1 if tune_launch else -1, budget_seconds)
+        h = ctypes.c_void_p()
+        _check(_lib().gp_plan_tune(graph.handle, self._h, ctypes.byref(o), _stream_handle(stream),
+                                   ctypes.byref(h)), "gp_plan_tune")
+        p = Plan.__new__(Plan)
+        p._h = h
+        p.k = self.k
+        p.edges = list(self.edges)
+        return p
+
+    def launch(self) -> dict:
+        l = self.info().launch
+        return dict(group=l.group, waves_per_cu=l.waves_per_cu, chunk=l.chunk, leaf_mode=l.leaf_mode)
 
     def close(self) -> None:
         if self._h:

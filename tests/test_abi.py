@@ -3,6 +3,7 @@
 import ctypes
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -43,12 +44,32 @@ def test_host_only_calls():
     assert "gfx950" in gp.version()
 
 
-def test_struct_sizes_match_header_layout():
-    # layouts as laid out by a C compiler for the declarations in gp.h
-    assert ctypes.sizeof(gp.Stats) == 48
-    assert ctypes.sizeof(gp.Launch) == 16
-    assert ctypes.sizeof(gp.PlanOpts) == 8 + 4 + 32 + 4 + 4 + 512 + 8 + 4  # + tail padding
-    assert ctypes.sizeof(gp.PlanInfo) % 8 == 0
+def test_struct_layouts_match_the_header(tmp_path):
+    """Sizes and field offsets of every struct in gp.h, as laid out by a C
+    compiler, equal the ctypes mirrors in the binding."""
+    structs = {"gp_stats": gp.Stats, "gp_plan_opts": gp.PlanOpts, "gp_plan_info": gp.PlanInfo,
+               "gp_launch": gp.Launch, "gp_tune_opts": gp.TuneOpts}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gp.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", f"-I{os.path.join(ROOT, 'include')}", str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            a, b, c = line.split()
+            got[(a, b)] = int(c)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
 
 
 def test_argument_errors_need_no_device():

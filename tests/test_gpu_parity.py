@@ -236,3 +236,38 @@ def test_batch_equals_plain():
     plain = [gp.count(graph, p) for p in plans]
     assert gp.count_batch(graph, plans) == plain
     assert plain == [O.count(g, *P[x]) for x in names]
+
+
+# ------------------------------------------------------- sampling and tuning
+
+def test_root_sampling_partitions_the_count():
+    """Strided root samples over all offsets add up to the full count."""
+    g = I.config_graph(2)
+    graph = gp.Graph.from_csr(g, device=True)
+    for pname in ["4-cycle", "house", "4-clique"]:
+        plan = gp.Plan(*P[pname], stats=graph.stats())
+        total = gp.count(graph, plan)
+        stride = 7
+        parts = [gp.count(graph, plan, root_stride=stride, root_offset=o) for o in range(stride)]
+        assert sum(parts) == total, pname
+        assert gp.count(graph, plan, root_stride=1, root_offset=10 ** 9) == 0
+
+
+def test_tuned_plans_count_the_same():
+    g = I.config_graph(2)
+    graph = gp.Graph.from_csr(g, device=True)
+    for pname in ["triangle", "4-cycle", "diamond", "4-clique", "house", "5-cycle"]:
+        k, e = P[pname]
+        plan = gp.Plan(k, e, stats=graph.stats())
+        tuned = plan.tuned(graph, budget_seconds=2.0)
+        inf = tuned.info()
+        assert inf.tuned == 1 and inf.n_measured >= 1
+        r = frozenset(tuned.restrictions)
+        assert O.validate(k, e, r)
+        want = gp.count(graph, plan)
+        assert gp.count(graph, tuned) == want, pname
+        if pname in ("triangle", "4-clique", "diamond"):
+            assert want == O.count(g, k, e)
+        # cached second call gives the same configuration
+        again = plan.tuned(graph)
+        assert again.order == tuned.order and again.restrictions == tuned.restrictions

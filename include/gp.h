@@ -62,7 +62,10 @@ enum {
 typedef struct gp_graph gp_graph;
 
 /* gp_load_graph flags */
-#define GP_IN_DEVICE 1u  /* row_ptr and col point to device memory (e.g. torch tensors) */
+#define GP_IN_DEVICE 1u          /* row_ptr and col point to device memory (e.g. torch tensors) */
+#define GP_NO_HUB_BITMAPS 2u     /* build no hub bitmaps (every membership test binary-searches) */
+#define GP_DENSE_HUB_BITMAPS 4u  /* bitmaps for every non-isolated vertex that fits the budget
+                                    (default: degree >= 64); for tests */
 
 typedef struct {
     int64_t n;            /* vertices */
@@ -72,6 +75,8 @@ typedef struct {
                              cardinality estimates (Section IV-C) */
     uint64_t hash;        /* 64-bit content hash of the input CSR (cache key) */
     double load_seconds;  /* wall time of gp_load_graph */
+    int64_t hub_vertices; /* vertices with a dense neighbor bitmap (the highest-degree ones) */
+    int64_t hub_bitmap_bytes;
 } gp_stats;
 
 /*
@@ -82,7 +87,10 @@ typedef struct {
  * GP_IN_DEVICE; either way the library copies what it needs.
  * On the device the graph is validated (GP_ERR_CSR_* on failure), relabelled
  * by descending degree (ties by ascending id), each list re-sorted, and its
- * triangle count computed for the cost model. Blocking on `stream`.
+ * triangle count computed for the cost model. The highest-degree vertices
+ * (degree >= 64, at most 2 GiB in total) also get a dense n-bit neighbor
+ * bitmap, so that a membership test in their lists is one bit read. Blocking
+ * on `stream`.
  */
 gp_status gp_load_graph(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz,
                         uint32_t flags, void* stream, gp_graph** out);

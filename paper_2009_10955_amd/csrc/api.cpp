@@ -14,6 +14,7 @@
 namespace gpint {
 gp_status build_layout(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz,
                        hipStream_t s, DeviceGraph* g);
+gp_status build_hub_bitmaps(DeviceGraph* g, int64_t min_degree, int64_t budget_bytes, hipStream_t s);
 }
 
 #include "api_internal.hpp"
@@ -45,6 +46,7 @@ void free_device_graph(gpint::DeviceGraph& g) {
     (void)hipFree(g.roots_lower);
     (void)hipFree(g.roots_upper);
     (void)hipFree(g.new_id);
+    (void)hipFree(g.hub_bits);
     g = gpint::DeviceGraph{};
 }
 
@@ -106,7 +108,7 @@ const char* gp_strerror(gp_status s) {
 gp_status gp_load_graph(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz,
                         uint32_t flags, void* stream, gp_graph** out) {
     if (!out || n < 0 || nnz < 0 || !row_ptr || (nnz > 0 && !col)) return GP_ERR_ARG;
-    if (flags & ~GP_IN_DEVICE) return GP_ERR_ARG;
+    if (flags & ~(GP_IN_DEVICE | GP_NO_HUB_BITMAPS | GP_DENSE_HUB_BITMAPS)) return GP_ERR_ARG;
     if (n >= 0x7fffffff || nnz >= 0x7fffffff) return GP_ERR_UNSUPPORTED;
     const double t0 = now_seconds();
     hipStream_t s = (hipStream_t)stream;
@@ -153,6 +155,10 @@ gp_status gp_load_graph(const int64_t* row_ptr, const int32_t* col, int64_t n, i
     }
     if (st == GP_OK && (ends[0] != 0 || ends[1] != nnz)) st = GP_ERR_CSR_RANGE;
     if (st == GP_OK) st = gpint::build_layout(d_row, d_col, n, nnz, s, &g->dg);
+    if (st == GP_OK && !(flags & GP_NO_HUB_BITMAPS)) {
+        const int64_t min_deg = (flags & GP_DENSE_HUB_BITMAPS) ? 1 : 64;
+        st = gpint::build_hub_bitmaps(&g->dg, min_deg, int64_t(2) << 30, s);
+    }
     if (own_row || own_col) {
         (void)hipStreamSynchronize(s);
         (void)hipFree(own_row);

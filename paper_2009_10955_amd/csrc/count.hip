@@ -125,6 +125,9 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
     a.roots = roots;
     a.n_roots = n_roots;
     a.root_offset = cfg.root_offset;
+    a.hub_bits = g.hub_bits;
+    a.hub_words = g.hub_words;
+    a.n_hubs = g.n_hubs;
     a.root_stride = cfg.root_stride;
     a.scratch = scratch;
     a.buf_cap = cap;

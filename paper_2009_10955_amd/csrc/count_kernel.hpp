@@ -49,6 +49,9 @@ struct CountArgs {
     int64_t n_roots;      // tasks: roots[root_offset + t * root_stride], t < n_roots
     int64_t root_offset;
     int64_t root_stride;
+    const uint32_t* hub_bits;  // n_hubs dense bitmaps of hub_words words
+    int64_t hub_words;
+    int32_t n_hubs;
     int32_t* scratch;
     int64_t buf_cap;
     unsigned long long* queue;
@@ -67,14 +70,17 @@ struct Ctx {
     int64_t cap;
     int32_t* lens;  // LDS: length per buffer slot
     uint64_t* bytes;  // accounting mode: per-lane algorithmic bytes
+    const uint32_t* hub_bits;
+    int64_t hub_words;
+    int32_t n_hubs;
     Group<G> g;
 
     __device__ __forceinline__ Set nbr(int32_t v) const {
         int64_t b = row_ptr[v], e = row_ptr[v + 1];
-        return Set{col + b, (int32_t)(e - b)};
+        return Set{col + b, (int32_t)(e - b), v < n_hubs ? hub_bits + (int64_t)v * hub_words : nullptr};
     }
     __device__ __forceinline__ Set buf(int slot) const {
-        return Set{bufs + (int64_t)slot * cap, lens[slot]};
+        return Set{bufs + (int64_t)slot * cap, lens[slot], nullptr};
     }
 };
 
@@ -165,7 +171,7 @@ __device__ __forceinline__ uint32_t leaf_serial(const GpPlanDesc& d, const Ctx<G
                 int32_t y = v[j];
                 if (y >= lo && y < hi) {
                     if constexpr (MODE == MODE_ACCOUNT) *c.bytes += probe_bytes(S.n);
-                    if (contains(S.p, S.n, y)) --cnt;
+                    if (member(S, y)) --cnt;
                 }
             }
         }
@@ -267,6 +273,9 @@ __global__ __launch_bounds__(kBlock) void count_kernel(GpPlanDesc d, CountArgs a
     c.row_ptr = a.row_ptr;
     c.col = a.col;
     c.cap = a.buf_cap;
+    c.hub_bits = a.hub_bits;
+    c.hub_words = a.hub_words;
+    c.n_hubs = a.n_hubs;
     const int grp = threadIdx.x / G;
     const int64_t group_id = (int64_t)blockIdx.x * (kBlock / G) + grp;
     c.bufs = a.scratch ? a.scratch + group_id * (int64_t)d.nbuf * a.buf_cap : nullptr;

@@ -15,6 +15,9 @@
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
+#include <algorithm>
+#include <vector>
+
 #include "internal.hpp"
 #include "sets.hpp"
 
@@ -162,6 +165,15 @@ __global__ void scatter_roots(const int64_t* row_ptr, const int2* roots_all, int
     }
 }
 
+__global__ void fill_hub_bits(const int2* roots_all, int64_t n_entries, int64_t words,
+                              uint32_t* bits) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n_entries;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        int2 r = roots_all[e];
+        atomicOr(&bits[(int64_t)r.x * words + (r.y >> 5)], 1u << (r.y & 31));
+    }
+}
+
 unsigned grid_for(int64_t n) {
     int64_t b = (n + 255) / 256;
     if (b < 1) b = 1;
@@ -171,12 +183,12 @@ unsigned grid_for(int64_t n) {
 
 struct TempPool {
     hipStream_t s;
-    void* ptrs[16];
+    void* ptrs[32];
     int n = 0;
     explicit TempPool(hipStream_t st) : s(st) {}
     hipError_t get(void** p, size_t bytes) {
         hipError_t e = hipMallocAsync(p, bytes ? bytes : 8, s);
-        if (e == hipSuccess) ptrs[n++] = *p;
+        if (e == hipSuccess && n < 32) ptrs[n++] = *p;
         return e;
     }
     ~TempPool() {
@@ -312,6 +324,36 @@ gp_status build_layout(const int64_t* row_ptr, const int32_t* col, int64_t n, in
     g->stats.m = nnz / 2;
     g->stats.max_degree = degs[0];
     g->stats.hash = hhash;
+    return GP_OK;
+}
+
+// Dense neighbor bitmaps for the highest-degree vertices. In the
+// degree-descending layout they are ids [0, n_hubs), whose lists are the first
+// row_ptr[n_hubs] CSR entries. A vertex qualifies with degree >= min_degree;
+// the count is capped so that all bitmaps fit in budget_bytes.
+gp_status build_hub_bitmaps(DeviceGraph* g, int64_t min_degree, int64_t budget_bytes, hipStream_t s) {
+    g->n_hubs = 0;
+    g->hub_words = (g->n + 31) / 32;
+    if (g->n == 0 || g->nnz == 0 || g->hub_words == 0) return GP_OK;
+    const int64_t per = g->hub_words * 4;
+    int64_t cap = std::min<int64_t>(g->n, budget_bytes / per);
+    if (cap <= 0) return GP_OK;
+    std::vector<int64_t> rp(cap + 1);
+    GP_HIP_TRY(hipMemcpyAsync(rp.data(), g->row_ptr, sizeof(int64_t) * (cap + 1), hipMemcpyDeviceToHost, s));
+    GP_HIP_TRY(hipStreamSynchronize(s));
+    int64_t h = 0;
+    while (h < cap && rp[h + 1] - rp[h] >= min_degree) ++h;
+    if (h == 0) return GP_OK;
+    GP_HIP_TRY(hipMalloc((void**)&g->hub_bits, (size_t)(h * per)));
+    GP_HIP_TRY(hipMemsetAsync(g->hub_bits, 0, (size_t)(h * per), s));
+    const int64_t entries = rp[h];
+    hipLaunchKernelGGL(fill_hub_bits, dim3(grid_for(entries)), dim3(256), 0, s, g->roots_all, entries,
+                       g->hub_words, g->hub_bits);
+    GP_HIP_TRY(hipGetLastError());
+    GP_HIP_TRY(hipStreamSynchronize(s));
+    g->n_hubs = (int32_t)h;
+    g->stats.hub_vertices = h;
+    g->stats.hub_bitmap_bytes = h * per;
     return GP_OK;
 }
 

@@ -21,6 +21,9 @@ struct DeviceGraph {
     int2* roots_upper = nullptr;  // entries with v1 > v0, CSR order
     int64_t n_lower = 0, n_upper = 0;
     int32_t* new_id = nullptr;    // original id -> layout id
+    uint32_t* hub_bits = nullptr; // dense neighbor bitmaps of vertices [0, n_hubs)
+    int64_t hub_words = 0;        // uint32 words per bitmap = ceil(n / 32)
+    int32_t n_hubs = 0;
     int64_t max_deg = 0;          // largest degree
     int64_t deg2 = 0;             // second largest degree (bound on any |N(a) & N(b)|, a != b)
     gp_stats stats{};

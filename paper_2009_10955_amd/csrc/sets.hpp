@@ -6,7 +6,9 @@
 // contiguous lists). Here a group of G lanes intersects cooperatively: each
 // lane takes one element of the smaller list and binary-searches it in the
 // larger one; ballot + popcount compact the hits in order. Single lanes use a
-// branch-free merge or a galloping search, whichever the sizes favour.
+// branch-free merge or a galloping search, whichever the sizes favour. When
+// the larger operand is a hub's list, membership is one bit test in the hub's
+// dense bitmap instead of a binary search (one cache line instead of ~log2 n).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -16,6 +18,10 @@ namespace gpdev {
 struct Set {
     const int32_t* p;
     int32_t n;
+    // Dense membership bitmap of the whole (uncut) neighbor list when the
+    // list belongs to a hub, else null. A bit test replaces the binary search
+    // for values inside the range the set was cut to.
+    const uint32_t* bits;
 };
 
 // First index i in [0, n) with a[i] >= x (n if none).
@@ -43,7 +49,13 @@ __device__ __forceinline__ Set trim(Set s, int32_t lo, int32_t hi) {
     int32_t b = lo > 0 ? lower_bound(s.p, s.n, lo) : 0;
     int32_t e = hi < 0x7fffffff ? lower_bound(s.p, s.n, hi) : s.n;
     if (e < b) e = b;
-    return Set{s.p + b, e - b};
+    return Set{s.p + b, e - b, s.bits};
+}
+
+// x in s, for an x inside the value range that s was cut to.
+__device__ __forceinline__ bool member(const Set& s, int32_t x) {
+    if (s.bits) return (s.bits[x >> 5] >> (x & 31)) & 1u;
+    return contains(s.p, s.n, x);
 }
 
 // |A ∩ B| by one lane, not counting elements x with skip(x).
@@ -56,6 +68,14 @@ __device__ __forceinline__ uint32_t intersect_count_serial(Set a, Set b, Skip sk
     }
     if (a.n == 0) return 0;
     uint32_t c = 0;
+    if (b.bits) {
+        // hub on the long side: one bit test per element of the short side
+        for (int32_t i = 0; i < a.n; ++i) {
+            int32_t x = a.p[i];
+            if ((b.bits[x >> 5] >> (x & 31)) & 1u) c += !skip(x);
+        }
+        return c;
+    }
     if (a.n * 16 < b.n) {
         // galloping: each element of the small set searched in the rest of the large one
         const int32_t* p = b.p;
@@ -134,7 +154,7 @@ __device__ __forceinline__ int32_t intersect_into(const Group<G>& g, Set a, Set 
         int32_t x = 0;
         if (i < a.n) {
             x = a.p[i];
-            found = contains(b.p, b.n, x);
+            found = member(b, x);
         }
         uint64_t m = g.ballot(found);
         if (found) dst[out + (int32_t)g.below_mask_count(m)] = x;
@@ -157,7 +177,7 @@ __device__ __forceinline__ uint32_t intersect_count_group(const Group<G>& g, Set
         bool found = false;
         if (i < a.n) {
             int32_t x = a.p[i];
-            found = contains(b.p, b.n, x) && !skip(x);
+            found = member(b, x) && !skip(x);
         }
         out += (uint32_t)__popcll(g.ballot(found));
     }

@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libgp.so")
 MAX_K = 8
 
 GP_IN_DEVICE = 1
+GP_NO_HUB_BITMAPS = 2
+GP_DENSE_HUB_BITMAPS = 4
 
 STATUS = {
     0: "GP_OK", -1: "GP_ERR_ARG", -2: "GP_ERR_CSR_UNSORTED", -3: "GP_ERR_CSR_ASYMMETRIC",
@@ -37,7 +39,8 @@ class GpError(RuntimeError):
 class Stats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("max_degree", ctypes.c_int64),
                 ("tri_cnt", ctypes.c_uint64), ("hash", ctypes.c_uint64),
-                ("load_seconds", ctypes.c_double)]
+                ("load_seconds", ctypes.c_double), ("hub_vertices", ctypes.c_int64),
+                ("hub_bitmap_bytes", ctypes.c_int64)]
 
 
 class PlanOpts(ctypes.Structure):
@@ -148,8 +151,10 @@ def _launch(group=0, waves_per_cu=0, chunk=0, leaf_mode=0, root_stride=0, root_o
 class Graph:
     """A data graph resident on the current GPU, owned by the library."""
 
-    def __init__(self, row_ptr, col, stream=None):
+    def __init__(self, row_ptr, col, stream=None, hub_bitmaps: str = "auto"):
+        """hub_bitmaps: "auto" (degree >= 64), "none", or "dense" (every vertex)."""
         lib = _lib()
+        extra = {"auto": 0, "none": GP_NO_HUB_BITMAPS, "dense": GP_DENSE_HUB_BITMAPS}[hub_bitmaps]
         self._h = ctypes.c_void_p()
         try:
             import torch
@@ -162,26 +167,26 @@ class Graph:
             row_ptr = row_ptr.contiguous()
             col = col.contiguous()
             n = row_ptr.numel() - 1
-            st = lib.gp_load_graph(row_ptr.data_ptr(), col.data_ptr(), n, col.numel(), GP_IN_DEVICE,
-                                   _stream_handle(stream), ctypes.byref(self._h))
+            st = lib.gp_load_graph(row_ptr.data_ptr(), col.data_ptr(), n, col.numel(),
+                                   GP_IN_DEVICE | extra, _stream_handle(stream), ctypes.byref(self._h))
         else:
             rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
             cl = np.ascontiguousarray(col, dtype=np.int32)
             n = rp.shape[0] - 1
-            st = lib.gp_load_graph(rp.ctypes.data, cl.ctypes.data if cl.size else None, n, cl.size, 0,
-                                   _stream_handle(stream), ctypes.byref(self._h))
+            st = lib.gp_load_graph(rp.ctypes.data, cl.ctypes.data if cl.size else None, n, cl.size,
+                                   extra, _stream_handle(stream), ctypes.byref(self._h))
         _check(st, "gp_load_graph")
 
     @classmethod
-    def from_csr(cls, g, device: bool = False, stream=None) -> "Graph":
+    def from_csr(cls, g, device: bool = False, stream=None, hub_bitmaps: str = "auto") -> "Graph":
         """From an object with numpy ``row_ptr`` / ``col``; device=True uploads
         them as torch tensors first and loads from device memory."""
         if device:
             import torch
             rp = torch.from_numpy(np.asarray(g.row_ptr, dtype=np.int64)).cuda()
             cl = torch.from_numpy(np.asarray(g.col, dtype=np.int32)).cuda()
-            return cls(rp, cl, stream)
-        return cls(g.row_ptr, g.col, stream)
+            return cls(rp, cl, stream, hub_bitmaps)
+        return cls(g.row_ptr, g.col, stream, hub_bitmaps)
 
     @property
     def handle(self):

@@ -99,7 +99,8 @@ def test_closed_forms():
     assert _count(c, *P["5-cycle"]) == 1
 
 
-def test_hub_star_ragged():
+@pytest.mark.parametrize("hubs", ["auto", "none", "dense"])
+def test_hub_star_ragged(hubs):
     """A hub of degree 2000 (many tiles plus a ragged tail) with its leaves
     partly connected: exercises long lists and large candidate buffers."""
     rng = np.random.default_rng(3)
@@ -107,7 +108,14 @@ def test_hub_star_ragged():
     src = [0] * s + list(rng.integers(1, s + 1, 1500))
     dst = list(range(1, s + 1)) + list(rng.integers(1, s + 1, 1500))
     g = I.csr_from_edges(s + 1, np.array(src), np.array(dst))
-    graph = gp.Graph.from_csr(g)
+    graph = gp.Graph.from_csr(g, hub_bitmaps=hubs)
+    st = graph.stats()
+    if hubs == "none":
+        assert st.hub_vertices == 0
+    elif hubs == "dense":
+        assert st.hub_vertices == int((g.degrees() > 0).sum())
+    else:
+        assert st.hub_vertices == int((g.degrees() >= 64).sum())
     for pname in ["triangle", "4-cycle", "tailed-triangle", "diamond", "4-clique"]:
         k, e = P[pname]
         want = O.count(g, k, e)
@@ -121,11 +129,11 @@ def test_hub_star_ragged():
 
 # ------------------------------------------------------- every pattern, graphs
 
-@pytest.mark.parametrize("seed", [101, 102])
+@pytest.mark.parametrize("seed,hubs", [(101, "none"), (102, "dense")])
 @pytest.mark.parametrize("pname", list(P))
-def test_all_patterns_random_graphs(seed, pname):
+def test_all_patterns_random_graphs(seed, hubs, pname):
     g = I.er(60, 0.25, seed=seed)
-    graph = gp.Graph.from_csr(g)
+    graph = gp.Graph.from_csr(g, hub_bitmaps=hubs)
     k, e = P[pname]
     want = O.count(g, k, e)
     for v in VARIANTS:
@@ -205,7 +213,7 @@ def _per_root_check(g, graph, pname, n_samples, seed, max_check=2_000_000, **lau
 @pytest.mark.parametrize("pname", ["triangle", "4-cycle", "4-clique", "house", "5-cycle"])
 def test_per_root_counts_config2(pname):
     g = I.config_graph(2)
-    graph = gp.Graph.from_csr(g, device=True)
+    graph = gp.Graph.from_csr(g, device=True, hub_bitmaps="dense" if pname == "5-cycle" else "auto")
     _per_root_check(g, graph, pname, 20, 1)
 
 

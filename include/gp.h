@@ -117,7 +117,9 @@ typedef struct {
                               (0 = auto) */
     int32_t chunk;         /* root tasks taken per queue grab (0 = auto) */
     int32_t leaf_mode;     /* 0 auto, 1: lanes take different second-to-last candidates and
-                              count the last level alone, 2: the group counts each one together */
+                              count the last level alone, 2: the group counts each one together,
+                              3: the last two enumerated levels are flattened into one
+                              load-balanced batch of (x, y) pairs (k >= 5; else as 1) */
     int32_t root_stride;   /* count only every root_stride-th root task (0 or 1 = all), */
     int32_t root_offset;   /* starting at root_offset: a seeded root sample for tuning */
 } gp_launch;

@@ -21,7 +21,9 @@ KernelFn pick_mode(int mode) {
 
 template <int K, int G>
 KernelFn pick_leaf(int leaf, int mode) {
-    return leaf == 2 ? pick_mode<K, G, 2>(mode) : pick_mode<K, G, 1>(mode);
+    if (leaf == 2) return pick_mode<K, G, 2>(mode);
+    if (leaf == 3 && K >= 5) return pick_mode<K, G, (K >= 5 ? 3 : 1)>(mode);
+    return pick_mode<K, G, 1>(mode);
 }
 }  // namespace
 

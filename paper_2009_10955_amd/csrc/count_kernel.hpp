@@ -179,13 +179,28 @@ __device__ __forceinline__ uint32_t leaf_serial(const GpPlanDesc& d, const Ctx<G
     }
     Set A = lv.pre_buf >= 0 ? c.buf(lv.pre_buf) : c.nbr(pick<K>(v, lv.pre_list));
     Set B = c.nbr(pick<K>(v, lv.last_list));
-    A = trim(A, lo, hi);
-    B = trim(B, lo, hi);
-    if constexpr (MODE == MODE_ACCOUNT) *c.bytes += 4ull * (uint64_t)(A.n + B.n);
     // injectivity folded into the intersection: matches equal to an earlier
     // image are not counted
     const uint32_t inj = lv.inj;
-    return intersect_count_serial(A, B, [&](int32_t x) { return inj_hit<K>(inj, v, x); });
+    auto skip = [&](int32_t x) { return inj_hit<K>(inj, v, x); };
+    // a hub operand is tested by bits, so only the other operand is cut
+    if (B.bits) {
+        const Set Ac = trim(A, lo, hi);
+        if (Ac.n * 4 <= B.n) {
+            if constexpr (MODE == MODE_ACCOUNT) *c.bytes += 4ull * (uint64_t)(Ac.n + trim(B, lo, hi).n);
+            return count_bits(Ac, B.bits, skip);
+        }
+    } else if (A.bits) {
+        const Set Bc = trim(B, lo, hi);
+        if (Bc.n * 4 <= A.n) {
+            if constexpr (MODE == MODE_ACCOUNT) *c.bytes += 4ull * (uint64_t)(Bc.n + trim(A, lo, hi).n);
+            return count_bits(Bc, A.bits, skip);
+        }
+    }
+    A = trim(A, lo, hi);
+    B = trim(B, lo, hi);
+    if constexpr (MODE == MODE_ACCOUNT) *c.bytes += 4ull * (uint64_t)(A.n + B.n);
+    return intersect_count_serial(A, B, skip);
 }
 
 // Count of the last level, computed by the whole group (same value in every lane).
@@ -214,6 +229,74 @@ __device__ __forceinline__ uint32_t leaf_group(const GpPlanDesc& d, const Ctx<G>
     return intersect_count_group<G>(c.g, A, B, [&](int32_t x) { return inj_hit<K>(inj, v, x); });
 }
 
+// The last two enumerated levels flattened into one load-balanced batch
+// (leaf mode 3): each lane takes a candidate x of level K-3 and cuts its
+// level-(K-2) candidate list; a group prefix sum over the list lengths then
+// deals every (x, y) pair to a lane, which counts the last level alone. This
+// keeps all G lanes busy when the per-candidate lists are short (sparse
+// graphs), where leaf mode 1 leaves most lanes idle. Only used when no build
+// runs after level K-3 is bound.
+template <int K, int G, int MODE>
+__device__ void flat_leaf(const GpPlanDesc& d, const Ctx<G>& c, const int32_t (&v)[K], Set S,
+                          uint32_t inj_l, uint64_t& acc, bool& ovf) {
+    constexpr int L = K - 3;
+    const GpLevel& l2 = d.lv[K - 2];
+    for (int32_t base = 0; base < S.n; base += G) {
+        const int32_t i = base + c.g.gl;
+        int32_t x2 = 0;
+        Set C{nullptr, 0, nullptr};
+        if (i < S.n) {
+            x2 = S.p[i];
+            if (!inj_hit<K>(inj_l, v, x2)) {
+                int32_t w[K];
+#pragma unroll
+                for (int j = 0; j < K; ++j) w[j] = v[j];
+                w[L] = x2;
+                int32_t lo, hi;
+                bounds<K>(l2.hi_src, l2.lo_src, w, lo, hi);
+                C = l2.list >= 0 ? c.nbr(pick<K>(w, l2.list)) : c.buf(l2.buf);
+                C = trim(C, lo, hi);
+            }
+        }
+        // inclusive prefix sum of the list lengths over the group
+        int32_t incl = C.n;
+#pragma unroll
+        for (int off = 1; off < G; off <<= 1) {
+            int32_t t = __shfl_up(incl, off, G);
+            if (c.g.gl >= off) incl += t;
+        }
+        const int32_t total = __shfl(incl, G - 1, G);
+        const int32_t excl = incl - C.n;
+        const long long cp = (long long)C.p;
+        if constexpr (MODE == MODE_ACCOUNT)
+            if (c.g.gl == 0) *c.bytes += 4ull * (uint64_t)total;
+        for (int32_t t0 = 0; t0 < total; t0 += G) {
+            const int32_t item = t0 + c.g.gl;
+            // owner: the last lane whose exclusive prefix is <= item
+            int32_t o = 0;
+#pragma unroll
+            for (int step = G / 2; step >= 1; step >>= 1) {
+                const int32_t e2 = __shfl(excl, o + step, G);
+                if (e2 <= item) o += step;
+            }
+            const int32_t ox = __shfl(x2, o, G);
+            const int32_t oex = __shfl(excl, o, G);
+            const int32_t* op = (const int32_t*)__shfl(cp, o, G);
+            if (item < total) {
+                const int32_t y = op[item - oex];
+                int32_t w[K];
+#pragma unroll
+                for (int j = 0; j < K; ++j) w[j] = v[j];
+                w[L] = ox;
+                if (!inj_hit<K>(l2.inj, w, y)) {
+                    w[K - 2] = y;
+                    add_count(acc, leaf_serial<K, G, MODE>(d, c, w), ovf);
+                }
+            }
+        }
+    }
+}
+
 template <int K, int L, int G, int LEAF, int MODE>
 __device__ void search(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], uint64_t& acc,
                        bool& ovf) {
@@ -225,7 +308,7 @@ __device__ void search(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], ui
     if constexpr (MODE == MODE_ACCOUNT)
         if (c.g.gl == 0) *c.bytes += 4ull * (uint64_t)S.n;
     if constexpr (L == K - 2) {
-        if constexpr (LEAF == 1) {
+        if constexpr (LEAF != 2) {
             for (int32_t base = 0; base < S.n; base += G) {
                 int32_t i = base + c.g.gl;
                 if (i < S.n) {
@@ -249,6 +332,12 @@ __device__ void search(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], ui
             }
         }
     } else {
+        if constexpr (LEAF == 3 && L == K - 3) {
+            if (d.build_begin[L] == d.build_end[L]) {
+                flat_leaf<K, G, MODE>(d, c, v, S, lv.inj, acc, ovf);
+                return;
+            }
+        }
         for (int32_t t = 0; t < S.n; ++t) {
             int32_t x = S.p[t];
             if (inj_hit<K>(lv.inj, v, x)) continue;
@@ -293,7 +382,7 @@ __global__ __launch_bounds__(kBlock) void count_kernel(GpPlanDesc d, CountArgs a
         t0 = c.g.bcast(t0, 0);
         if ((int64_t)t0 >= a.n_roots) break;
         const int64_t t1 = min((int64_t)t0 + chunk, a.n_roots);
-        if constexpr (K <= 3 && LEAF == 1) {
+        if constexpr (K <= 3 && LEAF != 2) {
             // lanes take different roots
             for (int64_t base = (int64_t)t0; base < t1; base += G) {
                 int64_t r = base + c.g.gl;

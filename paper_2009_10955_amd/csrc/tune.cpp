@@ -59,7 +59,7 @@ struct Cached {
 };
 
 std::mutex g_cache_mu;
-std::map<std::tuple<uint64_t, int, std::vector<std::pair<int, int>>>, Cached> g_cache;
+std::map<std::tuple<uint64_t, int64_t, int, std::vector<std::pair<int, int>>>, Cached> g_cache;
 
 // Time one launch (ms) on stream s; negative on failure.
 double time_launch(const gpint::DeviceGraph& g, const GpPlanDesc& d, const gpint::LaunchCfg& cfg,
@@ -113,7 +113,7 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
     for (auto& e : edges)
         if (e.first > e.second) std::swap(e.first, e.second);
     std::sort(edges.begin(), edges.end());
-    auto key = std::make_tuple(g->dg.stats.hash, k, edges);
+    auto key = std::make_tuple(g->dg.stats.hash, (int64_t)g->dg.n_hubs, k, edges);
     {
         std::lock_guard<std::mutex> lk(g_cache_mu);
         auto it = g_cache.find(key);
@@ -217,12 +217,15 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
 
         // 4. launch shape for the chosen configuration
         if (st == GP_OK && o.tune_launch >= 0) {
-            const GpLevel& leaf = cands[best].desc.lv[k - 1];
+            const GpPlanDesc& bd = cands[best].desc;
+            const GpLevel& leaf = bd.lv[k - 1];
             const bool leaf_intersects = k <= 3 || leaf.last_list >= 0;
+            const bool can_flatten = k >= 5 && bd.build_begin[k - 3] == bd.build_end[k - 3];
             double best_l = -1;
             for (int grp : {64, 32, 16, 8}) {
-                for (int lm : {1, 2}) {
+                for (int lm : {1, 2, 3}) {
                     if (lm == 2 && !leaf_intersects) continue;
+                    if (lm == 3 && !can_flatten) continue;
                     for (int w : {16, 32}) {
                         if (spent > 2 * budget_ms && best_l >= 0) break;
                         gpint::LaunchCfg cfg = best_launch;

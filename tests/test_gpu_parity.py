@@ -13,7 +13,7 @@ from paper_2009_10955_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 P = I.PATTERNS
-VARIANTS = [dict(group=g, leaf_mode=l) for g in (64, 32, 16, 8) for l in (1, 2)]
+VARIANTS = [dict(group=g, leaf_mode=l) for g in (64, 32, 16, 8) for l in (1, 2, 3)]
 
 
 @pytest.fixture(scope="module", autouse=True)

@@ -41,14 +41,16 @@ WORKLOADS = {
 def parse_args():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat17", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="wall budget of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-traffic", action="store_true",
                     help="skip the instrumented algorithmic-bytes run")
+    ap.add_argument("--tune-seconds", type=float, default=8.0,
+                    help="GPU-time budget per pattern for measured configuration selection")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     return ap.parse_args()
@@ -56,11 +58,6 @@ def parse_args():
 
 def note(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-
-def launch_for(pattern: str) -> dict:
-    """Launch shape per pattern (lanes per search group, leaf mode)."""
-    return dict(group=16, leaf_mode=1) if pattern == "5-clique" else dict(group=64, leaf_mode=1)
 
 
 def cpu_baseline(g, plans, names, budget_s: float) -> dict:
@@ -140,14 +137,19 @@ def main():
     g = I.config_graph(cfg_idx)
     graph = gp.Graph.from_csr(g, device=True)
     st = graph.stats()
-    plans = [gp.Plan(*I.PATTERNS[n], stats=st) for n in names]
-    launches = [launch_for(n) for n in names]
+    t_plan = time.perf_counter()
+    base_plans = [gp.Plan(*I.PATTERNS[n], stats=st) for n in names]
+    plan_s = time.perf_counter() - t_plan
+    t_tune = time.perf_counter()
+    plans = [p.tuned(graph, budget_seconds=args.tune_seconds) for p in base_plans]
+    tune_s = time.perf_counter() - t_tune
+    launches = [p.launch() for p in plans]
     stream = torch.cuda.current_stream()
     dev_out = torch.zeros(2 * len(plans), dtype=torch.int64, device="cuda")
 
-    note(f"graph loaded: n={st.n} m={st.m} max_degree={st.max_degree} "
-         f"load={st.load_seconds:.3f}s; plans: " +
-         ", ".join(f"{n} {p.order} {p.restrictions}" for n, p in zip(names, plans)))
+    note(f"graph loaded: n={st.n} m={st.m} max_degree={st.max_degree} hubs={st.hub_vertices} "
+         f"load={st.load_seconds:.3f}s plan={plan_s:.2f}s tune={tune_s:.1f}s; plans: " +
+         ", ".join(f"{n} {p.order} {p.restrictions} {l}" for n, p, l in zip(names, plans, launches)))
 
     def step(events=None):
         for i, (p, l) in enumerate(zip(plans, launches)):
@@ -237,7 +239,10 @@ def main():
         "intersection_GBps": {n: round(alg[n] / (a / 1e3) / 1e9, 2) for n, a in zip(names, avg_ms)}
         if alg else None,
         "plans": {n: {"order": list(p.order), "restrictions": [list(x) for x in p.restrictions],
-                      "launch": l} for n, p, l in zip(names, plans, launches)},
+                      "launch": l, "model_order": list(b.order),
+                      "model_restrictions": [list(x) for x in b.restrictions]}
+                  for n, p, b, l in zip(names, plans, base_plans, launches)},
+        "preprocessing_s": {"load": st.load_seconds, "plan": plan_s, "tune": tune_s},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

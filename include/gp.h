@@ -140,6 +140,8 @@ typedef struct {
     int32_t n_force_restr;       /* if > 0: use these pairs instead (validated) */
     int32_t force_restr[2 * GP_MAX_K * GP_MAX_K];
     double cost_cap;             /* if > 0: GP_ERR_BUDGET when the best predicted cost exceeds it */
+    double max_seconds;          /* Algorithm 1 stops exploring after this long once a valid set
+                                    exists (0 = 20 s) */
 } gp_plan_opts;
 
 /* Fill opts with the defaults (nothing forced, no cap). */
@@ -148,9 +150,12 @@ void gp_plan_opts_default(gp_plan_opts* opts);
 /*
  * Plan a pattern with k vertices and e edges (edges[2*i], edges[2*i+1]).
  * Host only. Steps: automorphisms (Section IV-A), restriction sets by
- * Algorithm 1 (each kept as its transitive closure), efficient schedules by
- * the two phases of Section IV-B, then the configuration with the lowest
- * predicted cost under the model of Section IV-C, evaluated with `stats`
+ * Algorithm 1 (each kept as its transitive closure; for complete patterns
+ * with k >= 6 the k! total orders it reaches are emitted directly), efficient
+ * schedules by the two phases of Section IV-B, then the configuration with
+ * the lowest predicted cost under the model of Section IV-C (schedules that
+ * an automorphism maps onto each other give the same searches, so one per
+ * orbit is evaluated), evaluated with `stats`
  * (null: |V| = 1e6, |E| = 1e7, tri_cnt = 6e7). Ties of predicted cost go to
  * the set with more upper-bound cuts (a later vertex bounded above by an
  * earlier one), then the lexicographically smaller schedule, then the earlier
@@ -191,7 +196,7 @@ gp_status gp_plan_model_cost(const gp_plan* p, int32_t idx_s, int32_t idx_r,
                              const gp_stats* stats, double* cost);
 
 typedef struct {
-    int32_t max_configs;    /* distinct configurations to time (0 = 12) */
+    int32_t max_configs;    /* distinct configurations to time (0 = 24) */
     int32_t sample_stride;  /* time roots[offset + t * stride] only (0 = auto, aiming at
                                ~40 ms per run) */
     int32_t tune_launch;    /* 1 (default): also pick lanes per group, leaf mode and waves per
@@ -208,8 +213,8 @@ void gp_tune_opts_default(gp_tune_opts* o);
  * best schedule on average (Section V-C). This call takes the best-ranked
  * configurations, adds each one's mirror (every pair reversed, also valid),
  * drops configurations that compile to the same search, times each on a
- * strided sample of its root tasks on `stream`, keeps the fastest, then times
- * launch shapes for it. *out is a new plan (same pattern, same counts) whose
+ * sparse strided sample of its root tasks on `stream`, times the four fastest
+ * again on a denser sample, keeps the fastest, then times launch shapes for it. *out is a new plan (same pattern, same counts) whose
  * default launch is the measured best. Blocking.
  */
 gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* opts, void* stream,
@@ -259,13 +264,33 @@ gp_status gp_count_traffic(const gp_graph* g, const gp_plan* p, const gp_launch*
                            void* stream, uint64_t* out, uint64_t* alg_bytes);
 
 /*
- * Count several plans over one graph in ONE persistent launch: the task space
- * is the union over plans of their root edges, handed out from one atomic
- * queue, so plans of uneven cost share the machine. out[i] = count of
- * plans[i] (host memory). Blocking. Counts equal gp_count's bit for bit.
+ * Count several plans (1..64, any pattern sizes) over one graph in ONE
+ * persistent launch: the task space is the concatenation of the plans' root
+ * edges, handed out in chunks from one atomic queue, so plans of uneven cost
+ * fill each other's tails (Section IV-E's task partitioning across patterns).
+ * Each plan runs with its own leaf mode (from its tuned launch); the group
+ * size comes from `launch` or the first plan. out[i] = count of plans[i]
+ * (host memory). Blocking. Counts equal gp_count's bit for bit.
  */
 gp_status gp_count_batch(const gp_graph* g, const gp_plan* const* plans, int32_t np,
                          const gp_launch* launch, void* stream, uint64_t* out);
+
+typedef struct gp_batch gp_batch;
+
+/*
+ * Prepare a batch for repeated counting: device descriptors, scratch, queue
+ * and result buffers are allocated once, and the whole run (counter reset by
+ * fill kernels, the batched kernel, the 8-bytes-per-plan readback into pinned
+ * host memory) is captured into a hipGraph. The plans and graph must outlive
+ * the batch. One gp_batch must not run concurrently with itself.
+ */
+gp_status gp_batch_create(const gp_graph* g, const gp_plan* const* plans, int32_t np,
+                          const gp_launch* launch, void* stream, gp_batch** out);
+
+/* Replay the captured graph on `stream` and wait; out[i] = count of plan i. */
+gp_status gp_batch_run(gp_batch* b, void* stream, uint64_t* out);
+
+void gp_free_batch(gp_batch* b);
 
 /* Human-readable name of a status code (static string). */
 const char* gp_strerror(gp_status s);

@@ -19,7 +19,8 @@ LIB = os.path.join(PKG, "libgp.so")
 # once per pattern size k in its own unit so the variants build in parallel
 SOURCES = [("api.cpp", [], "api.o"), ("planner.cpp", [], "planner.o"), ("tune.cpp", [], "tune.o"),
            ("graph.hip", [], "graph.o"), ("count.hip", [], "count.o")] + [
-    ("count_inst.hip", [f"-DGP_INST_K={k}"], f"count_k{k}.o") for k in range(2, 9)]
+    ("count_inst.hip", [f"-DGP_INST_K={k}"], f"count_k{k}.o") for k in range(2, 9)] + [
+    ("count_batch.hip", [f"-DGP_BATCH_G={g}"], f"count_batch_g{g}.o") for g in (64, 32, 16)]
 ARCH = os.environ.get("GP_OFFLOAD_ARCH", "gfx950")
 
 

@@ -246,7 +246,8 @@ gp_status gp_plan_create(const int32_t* edges, int32_t k, int32_t e, const gp_st
     p->pattern = pat;
     auto auts = gp::automorphisms(pat);
     p->aut = auts.size();
-    gp::RestrictionSets rs = gp::restriction_sets(pat, auts, max_states, max_sets);
+    gp::RestrictionSets rs = gp::restriction_sets(pat, auts, max_states, max_sets,
+                                                  o.max_seconds > 0 ? o.max_seconds : 20.0);
     p->sets = rs.sets;
     gp::Schedules sc = gp::efficient_schedules(pat);
     p->schedules = sc.orders;
@@ -271,7 +272,8 @@ gp_status gp_plan_create(const int32_t* edges, int32_t k, int32_t e, const gp_st
         }
         cand_orders.push_back(ord);
     } else {
-        cand_orders = p->schedules;
+        // one schedule per automorphism orbit: same costs, same argmin
+        cand_orders = gp::orbit_representatives(p->schedules, auts, k);
     }
     // candidate restriction sets
     std::vector<gp::Rel> cand_sets;
@@ -480,31 +482,115 @@ gp_status gp_count_traffic(const gp_graph* g, const gp_plan* p, const gp_launch*
     return count_to_host(g, p->desc, cfg, (hipStream_t)stream, nullptr, out, alg_bytes);
 }
 
+namespace {
+// Device descriptors and per-plan leaf modes of a batch.
+gp_status batch_inputs(const gp_plan* const* plans, int32_t np, std::vector<GpPlanDesc>* descs,
+                       std::vector<int>* leafs) {
+    if (!plans || np < 1 || np > 64) return GP_ERR_ARG;
+    descs->resize(np);
+    leafs->resize(np);
+    for (int i = 0; i < np; ++i) {
+        if (!plans[i]) return GP_ERR_ARG;
+        (*descs)[i] = plans[i]->desc;
+        (*leafs)[i] = plans[i]->launch.leaf;
+    }
+    return GP_OK;
+}
+}  // namespace
+
 gp_status gp_count_batch(const gp_graph* g, const gp_plan* const* plans, int32_t np,
                          const gp_launch* launch, void* stream, uint64_t* out) {
-    if (!g || !plans || np < 1 || !out) return GP_ERR_ARG;
-    for (int i = 0; i < np; ++i)
-        if (!plans[i]) return GP_ERR_ARG;
+    if (!g || !out) return GP_ERR_ARG;
+    std::vector<GpPlanDesc> descs;
+    std::vector<int> leafs;
+    gp_status st = batch_inputs(plans, np, &descs, &leafs);
+    if (st != GP_OK) return st;
     DeviceGuard dgd(g->dg.device);
     hipStream_t s = (hipStream_t)stream;
-    std::vector<GpPlanDesc> descs(np);
-    for (int i = 0; i < np; ++i) descs[i] = plans[i]->desc;
     gpint::LaunchCfg cfg = gpint::launch_for_plan(plans[0], launch, g->dg);
-    unsigned long long* res = nullptr;
-    GP_HIP_TRY(hipMallocAsync((void**)&res, 2 * sizeof(unsigned long long) * np, s));
-    gp_status st = gpint::launch_count_batch(g->dg, descs.data(), np, cfg, s, res);
+    gpint::BatchState bs;
+    st = gpint::batch_prepare(g->dg, descs.data(), leafs.data(), nullptr, nullptr, np, cfg, s, &bs);
+    if (st != GP_OK) return st;
     std::vector<unsigned long long> h(2 * np, 0);
+    st = gpint::batch_enqueue(g->dg, bs, s);
     if (st == GP_OK &&
-        hipMemcpyAsync(h.data(), res, sizeof(unsigned long long) * 2 * np, hipMemcpyDeviceToHost, s) !=
+        hipMemcpyAsync(h.data(), bs.result, sizeof(unsigned long long) * 2 * np, hipMemcpyDeviceToHost, s) !=
             hipSuccess)
         st = GP_ERR_HIP;
-    (void)hipFreeAsync(res, s);
     if (hipStreamSynchronize(s) != hipSuccess && st == GP_OK) st = GP_ERR_HIP;
+    gpint::batch_release(&bs);
     if (st != GP_OK) return st;
     for (int i = 0; i < np; ++i)
         if (h[2 * i + 1]) return GP_ERR_OVERFLOW;
     for (int i = 0; i < np; ++i) out[i] = h[2 * i];
     return GP_OK;
+}
+
+gp_status gp_batch_create(const gp_graph* g, const gp_plan* const* plans, int32_t np,
+                          const gp_launch* launch, void* stream, gp_batch** out) {
+    if (!g || !out) return GP_ERR_ARG;
+    std::vector<GpPlanDesc> descs;
+    std::vector<int> leafs;
+    gp_status st = batch_inputs(plans, np, &descs, &leafs);
+    if (st != GP_OK) return st;
+    DeviceGuard dgd(g->dg.device);
+    hipStream_t s = (hipStream_t)stream;
+    gp_batch* b = new (std::nothrow) gp_batch;
+    if (!b) return GP_ERR_NOMEM;
+    b->g = g;
+    b->np = np;
+    gpint::LaunchCfg cfg = gpint::launch_for_plan(plans[0], launch, g->dg);
+    st = gpint::batch_prepare(g->dg, descs.data(), leafs.data(), nullptr, nullptr, np, cfg, s, &b->st);
+    if (st != GP_OK) {
+        delete b;
+        return st;
+    }
+    bool ok = hipHostMalloc((void**)&b->host_res, 2 * sizeof(unsigned long long) * np,
+                            hipHostMallocDefault) == hipSuccess &&
+              hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) == hipSuccess;
+    if (ok) {
+        // capture: counter reset (fill kernels, no memset nodes) -> kernel -> D2H
+        ok = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            gp_status est = gpint::batch_enqueue(g->dg, b->st, b->cap_stream);
+            hipError_t ce = hipMemcpyAsync(b->host_res, b->st.result, 2 * sizeof(unsigned long long) * np,
+                                           hipMemcpyDeviceToHost, b->cap_stream);
+            hipError_t ee = hipStreamEndCapture(b->cap_stream, &b->graph);
+            ok = est == GP_OK && ce == hipSuccess && ee == hipSuccess &&
+                 hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) == hipSuccess;
+        }
+    }
+    if (!ok) {
+        gp_free_batch(b);
+        return GP_ERR_HIP;
+    }
+    *out = b;
+    return GP_OK;
+}
+
+gp_status gp_batch_run(gp_batch* b, void* stream, uint64_t* out) {
+    if (!b || !out) return GP_ERR_ARG;
+    DeviceGuard dgd(b->g->dg.device);
+    hipStream_t s = (hipStream_t)stream;
+    GP_HIP_TRY(hipGraphLaunch(b->exec, s));
+    GP_HIP_TRY(hipStreamSynchronize(s));
+    for (int i = 0; i < b->np; ++i)
+        if (b->host_res[2 * i + 1]) return GP_ERR_OVERFLOW;
+    for (int i = 0; i < b->np; ++i) out[i] = b->host_res[2 * i];
+    return GP_OK;
+}
+
+void gp_free_batch(gp_batch* b) {
+    if (!b) return;
+    DeviceGuard dgd(b->g->dg.device);
+    if (b->cap_stream) (void)hipStreamSynchronize(b->cap_stream);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    (void)hipDeviceSynchronize();
+    if (b->host_res) (void)hipHostFree(b->host_res);
+    gpint::batch_release(&b->st);
+    delete b;
 }
 
 }  // extern "C"

@@ -23,6 +23,16 @@ struct gp_plan {
     gpint::LaunchCfg launch{};
 };
 
+struct gp_batch {
+    const gp_graph* g = nullptr;
+    int np = 0;
+    gpint::BatchState st;
+    unsigned long long* host_res = nullptr;  // pinned, 2*np
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
 namespace gpint {
 // Launch configuration for a count of plan p: the plan's tuned launch (if
 // any) or the defaults, with every non-zero field of l overriding it.

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "count_kernel.hpp"
 
@@ -13,6 +14,9 @@ KernelFn pick_kernel_k5(int group, int leaf, int mode);
 KernelFn pick_kernel_k6(int group, int leaf, int mode);
 KernelFn pick_kernel_k7(int group, int leaf, int mode);
 KernelFn pick_kernel_k8(int group, int leaf, int mode);
+BatchFn batch_kernel_g64();
+BatchFn batch_kernel_g32();
+BatchFn batch_kernel_g16();
 
 namespace {
 __global__ void init_counters(unsigned long long* p, int n) {
@@ -143,15 +147,107 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
     return GP_OK;
 }
 
-gp_status launch_count_batch(const DeviceGraph& g, const GpPlanDesc* descs, int np,
-                             const LaunchCfg& cfg, hipStream_t stream,
-                             unsigned long long* result_dev) {
-    // One plan at a time for now; the single-launch batch kernel replaces this.
+int64_t root_task_count(const DeviceGraph& g, const GpPlanDesc& d) {
+    int64_t n = 0;
+    (void)pick_roots(g, d.root_cut, &n);
+    return n;
+}
+
+void batch_release(BatchState* st) {
+    (void)hipFree(st->descs);
+    (void)hipFree(st->plans);
+    (void)hipFree(st->scratch);
+    (void)hipFree(st->queue);
+    (void)hipFree(st->result);
+    *st = BatchState{};
+}
+
+gp_status batch_prepare(const DeviceGraph& g, const GpPlanDesc* descs, const int* leafs,
+                        const int64_t* offsets, const int64_t* counts, int np,
+                        const LaunchCfg& cfg, hipStream_t stream, BatchState* st) {
+    if (np < 1 || np > kBatchMaxPlans) return GP_ERR_ARG;
+    BatchState b;
+    b.np = np;
+    b.group = cfg.group >= 64 ? 64 : (cfg.group >= 32 ? 32 : 16);
+    b.chunk = std::max(1, cfg.chunk);
+    std::vector<BatchPlan> plans(np);
+    int64_t total = 0;
+    int32_t nbuf = 0;
     for (int i = 0; i < np; ++i) {
-        gp_status s = launch_count(g, descs[i], cfg, stream, result_dev + 2 * i, nullptr, false);
-        if (s != GP_OK) return s;
+        int64_t n_all = 0;
+        const int2* roots = pick_roots(g, descs[i].root_cut, &n_all);
+        int64_t off = offsets ? offsets[i] : 0;
+        int64_t cnt = counts ? counts[i] : n_all;
+        if (off < 0 || cnt < 0) return GP_ERR_ARG;
+        off = std::min(off, n_all);
+        cnt = std::min(cnt, n_all - off);
+        plans[i].roots = roots + off;
+        plans[i].n_tasks = cnt;
+        plans[i].task_begin = total;
+        plans[i].leaf = (leafs && leafs[i] == 3 && descs[i].k >= 5) ? 3 : 1;
+        plans[i].pad = 0;
+        total += cnt;
+        nbuf = std::max(nbuf, descs[i].nbuf);
     }
+    b.total_tasks = total;
+    b.nbuf = nbuf;
+    b.cap = std::max<int64_t>(1, g.deg2);
+    const int64_t groups_per_block = kBlock / b.group;
+    int64_t blocks = std::max<int64_t>(1, (int64_t)g.num_cus * cfg.waves_per_cu / (kBlock / 64));
+    if (nbuf > 0) {
+        const int64_t budget = int64_t(16) << 30;
+        blocks = std::min(blocks, std::max<int64_t>(1, budget / (groups_per_block * nbuf * b.cap * 4)));
+    }
+    const int64_t need = (total + b.chunk - 1) / b.chunk;
+    blocks = std::min(blocks, std::max<int64_t>(1, (need + groups_per_block - 1) / groups_per_block));
+    b.blocks = blocks;
+    gp_status rc = GP_OK;
+    if (hipMalloc(&b.descs, sizeof(GpPlanDesc) * np) != hipSuccess ||
+        hipMalloc(&b.plans, sizeof(BatchPlan) * np) != hipSuccess ||
+        hipMalloc((void**)&b.queue, sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc((void**)&b.result, 2 * sizeof(unsigned long long) * np) != hipSuccess ||
+        (nbuf > 0 &&
+         hipMalloc((void**)&b.scratch, (size_t)(blocks * groups_per_block * nbuf * b.cap * 4)) != hipSuccess))
+        rc = GP_ERR_NOMEM;
+    if (rc == GP_OK &&
+        (hipMemcpyAsync(b.descs, descs, sizeof(GpPlanDesc) * np, hipMemcpyHostToDevice, stream) != hipSuccess ||
+         hipMemcpyAsync(b.plans, plans.data(), sizeof(BatchPlan) * np, hipMemcpyHostToDevice, stream) !=
+             hipSuccess ||
+         hipStreamSynchronize(stream) != hipSuccess))
+        rc = GP_ERR_HIP;
+    if (rc != GP_OK) {
+        batch_release(&b);
+        return rc;
+    }
+    *st = b;
     return GP_OK;
+}
+
+gp_status batch_enqueue(const DeviceGraph& g, const BatchState& st, hipStream_t stream) {
+    BatchFn fn = st.group == 64 ? batch_kernel_g64() : (st.group == 32 ? batch_kernel_g32() : batch_kernel_g16());
+    hipLaunchKernelGGL(init_counters, dim3(1), dim3(64), 0, stream, st.queue, 1);
+    for (int i = 0; i < 2 * st.np; i += 64)
+        hipLaunchKernelGGL(init_counters, dim3(1), dim3(64), 0, stream, st.result + i,
+                           std::min(64, 2 * st.np - i));
+    BatchArgs a;
+    a.row_ptr = g.row_ptr;
+    a.col = g.col;
+    a.descs = (const GpPlanDesc*)st.descs;
+    a.plans = (const BatchPlan*)st.plans;
+    a.np = st.np;
+    a.total_tasks = st.total_tasks;
+    a.hub_bits = g.hub_bits;
+    a.hub_words = g.hub_words;
+    a.n_hubs = g.n_hubs;
+    a.scratch = st.scratch;
+    a.buf_cap = st.cap;
+    a.nbuf = st.nbuf;
+    a.queue = st.queue;
+    a.result = st.result;
+    a.chunk = st.chunk;
+    if (st.total_tasks > 0)
+        hipLaunchKernelGGL(fn, dim3((unsigned)st.blocks), dim3(kBlock), 0, stream, a);
+    return hipGetLastError() == hipSuccess ? GP_OK : GP_ERR_HIP;
 }
 
 }  // namespace gpint

@@ -62,6 +62,37 @@ struct CountArgs {
 
 typedef void (*KernelFn)(GpPlanDesc, CountArgs);
 
+// Batched launch: one entry per plan, in task order.
+constexpr int kBatchMaxPlans = 64;
+
+struct BatchPlan {
+    const int2* roots;   // this plan's root array (cut already applied)
+    int64_t n_tasks;     // roots of this plan in the launch
+    int64_t task_begin;  // first global task index of this plan
+    int32_t leaf;        // 1 or 3 (flattened last two levels)
+    int32_t pad;
+};
+
+struct BatchArgs {
+    const int64_t* row_ptr;
+    const int32_t* col;
+    const GpPlanDesc* descs;  // device, np entries
+    const BatchPlan* plans;   // device, np entries
+    int32_t np;
+    int64_t total_tasks;
+    const uint32_t* hub_bits;
+    int64_t hub_words;
+    int32_t n_hubs;
+    int32_t* scratch;
+    int64_t buf_cap;
+    int32_t nbuf;  // buffer slots per group (max over plans)
+    unsigned long long* queue;
+    unsigned long long* result;  // {count, overflow} per plan
+    int32_t chunk;
+};
+
+typedef void (*BatchFn)(BatchArgs);
+
 template <int G>
 struct Ctx {
     const int64_t* row_ptr;

@@ -46,11 +46,34 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
                        hipStream_t stream, unsigned long long* result_dev,
                        unsigned long long* per_root, bool account = false);
 
-// Launch one persistent kernel over the union of the plans' root tasks.
-// result_dev: 2*np u64 ({count, overflow} per plan).
-gp_status launch_count_batch(const DeviceGraph& g, const GpPlanDesc* descs, int np,
-                             const LaunchCfg& cfg, hipStream_t stream,
-                             unsigned long long* result_dev);
+// Device state of one batched launch: descriptors, per-plan task ranges,
+// scratch, queue and results, all allocated up front so that the launch
+// itself allocates nothing (it can be captured in a hipGraph and replayed).
+struct BatchState {
+    int np = 0;
+    int group = 64;
+    int64_t blocks = 0;
+    int64_t total_tasks = 0;
+    int32_t nbuf = 0;
+    int64_t cap = 0;
+    int32_t chunk = 4;
+    void* descs = nullptr;   // GpPlanDesc[np]
+    void* plans = nullptr;   // per-plan task ranges
+    int32_t* scratch = nullptr;
+    unsigned long long* queue = nullptr;
+    unsigned long long* result = nullptr;  // 2*np
+};
+
+// Plan i covers roots[offset_i + t], t < count_i of its own root array;
+// offsets/counts null = every root. leafs: 1 or 3 per plan.
+gp_status batch_prepare(const DeviceGraph& g, const GpPlanDesc* descs, const int* leafs,
+                        const int64_t* offsets, const int64_t* counts, int np,
+                        const LaunchCfg& cfg, hipStream_t stream, BatchState* st);
+// Enqueue counter reset + the batched kernel on `stream` (no allocation).
+gp_status batch_enqueue(const DeviceGraph& g, const BatchState& st, hipStream_t stream);
+void batch_release(BatchState* st);
+// Number of root tasks of a descriptor (its cut picks the root array).
+int64_t root_task_count(const DeviceGraph& g, const GpPlanDesc& d);
 
 // Launch defaults for a plan descriptor, and overriding them with the
 // non-zero fields of a caller's gp_launch.

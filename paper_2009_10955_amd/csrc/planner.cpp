@@ -27,6 +27,7 @@
 #include "planner.hpp"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <unordered_map>
@@ -140,7 +141,13 @@ bool validate(Rel r, int k, uint64_t aut) {
 }
 
 namespace {
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
 struct Gen {
+    double deadline = 0;
     const Pattern* p;
     const std::vector<Perm>* auts;
     int64_t max_states;
@@ -159,7 +166,9 @@ struct Gen {
                     Rel new_set = closure(res_set | rel_bit(v, perm[v]), k);
                     if (visited.count(new_set)) continue;
                     if ((int64_t)visited.size() >= max_states ||
-                        (int32_t)out.sets.size() >= max_sets) {
+                        (int32_t)out.sets.size() >= max_sets ||
+                        (deadline > 0 && (visited.size() & 1023) == 0 && now_s() > deadline &&
+                         !out.sets.empty())) {
                         out.truncated = true;
                         return;
                     }
@@ -182,8 +191,33 @@ struct Gen {
 }  // namespace
 
 RestrictionSets restriction_sets(const Pattern& p, const std::vector<Perm>& auts,
-                                 int64_t max_states, int32_t max_sets) {
+                                 int64_t max_states, int32_t max_sets, double max_seconds) {
+    const int k = p.k;
+    // Complete pattern, k >= 6: every valid set is a total order (one orbit,
+    // one obeying order per orbit) and Algorithm 1 reaches all k! of them, so
+    // emit them directly, in lexicographic order of the ranking.
+    bool complete = true;
+    for (int v = 0; v < k; ++v)
+        if (__builtin_popcount(p.adj[v]) != k - 1) complete = false;
+    if (complete && k >= 6) {
+        RestrictionSets out;
+        Perm rank{};
+        for (int i = 0; i < k; ++i) rank[i] = uint8_t(i);
+        do {
+            if ((int32_t)out.sets.size() >= max_sets) {
+                out.truncated = true;
+                break;
+            }
+            Rel r = 0;  // id(rank[0]) > id(rank[1]) > ...
+            for (int i = 0; i < k; ++i)
+                for (int j = i + 1; j < k; ++j) r |= rel_bit(rank[i], rank[j]);
+            out.sets.push_back(r);
+        } while (std::next_permutation(rank.begin(), rank.begin() + k));
+        out.states = (int64_t)out.sets.size();
+        return out;
+    }
     Gen g;
+    g.deadline = max_seconds > 0 ? now_s() + max_seconds : 0;
     g.p = &p;
     g.auts = &auts;
     g.max_states = max_states;
@@ -241,6 +275,26 @@ Schedules efficient_schedules(const Pattern& p) {
     out.orders = p1;
     out.k_eff = 0;
     return out;
+}
+
+std::vector<Perm> orbit_representatives(const std::vector<Perm>& orders, const std::vector<Perm>& auts,
+                                        int k) {
+    // (order, R) and (pi o order, pi(R)) compile to the same search for every
+    // automorphism pi; keep the lexicographically smallest schedule per orbit.
+    std::vector<Perm> reps;
+    for (const Perm& o : orders) {
+        bool smallest = true;
+        for (const Perm& pi : auts) {
+            Perm img{};
+            for (int i = 0; i < k; ++i) img[i] = pi[o[i]];
+            if (std::lexicographical_compare(img.begin(), img.begin() + k, o.begin(), o.begin() + k)) {
+                smallest = false;
+                break;
+            }
+        }
+        if (smallest) reps.push_back(o);
+    }
+    return reps;
 }
 
 double model_cost(const Pattern& p, const Perm& order, Rel r, const GraphStats& s) {

@@ -41,8 +41,14 @@ struct RestrictionSets {
     int64_t states = 0;      // distinct closures visited
     bool truncated = false;
 };
+// max_seconds > 0: stop exploring once that long has passed and a valid set
+// exists (the output is then a prefix of the full emission order).
 RestrictionSets restriction_sets(const Pattern& p, const std::vector<Perm>& auts,
-                                 int64_t max_states, int32_t max_sets);
+                                 int64_t max_states, int32_t max_sets, double max_seconds = 0);
+
+// Lexicographically smallest schedule of each orbit under the automorphisms.
+std::vector<Perm> orbit_representatives(const std::vector<Perm>& orders, const std::vector<Perm>& auts,
+                                        int k);
 
 struct Schedules {
     std::vector<Perm> orders;  // lexicographic order

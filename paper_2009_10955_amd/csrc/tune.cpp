@@ -97,7 +97,7 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
     gp_tune_opts_default(&o);
     if (opts) o = *opts;
     if (o.max_configs < 0 || o.sample_stride < 0 || o.budget_seconds < 0) return GP_ERR_ARG;
-    const int max_configs = o.max_configs ? o.max_configs : 12;
+    const int max_configs = o.max_configs ? o.max_configs : 24;
     const double budget_ms = 1e3 * (o.budget_seconds > 0 ? o.budget_seconds : 20.0);
     const double t0 = now_seconds();
     const int k = p->pattern.k;
@@ -143,9 +143,11 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
             size_t i, j;
         };
         std::vector<Ranked> ranked;
-        for (size_t i = 0; i < p->schedules.size(); ++i)
+        std::vector<gp::Perm> auts0 = gp::automorphisms(p->pattern);
+        std::vector<gp::Perm> reps = gp::orbit_representatives(p->schedules, auts0, k);
+        for (size_t i = 0; i < reps.size(); ++i)
             for (size_t j = 0; j < p->sets.size(); ++j)
-                ranked.push_back({gp::model_cost(p->pattern, p->schedules[i], p->sets[j], gs), i, j});
+                ranked.push_back({gp::model_cost(p->pattern, reps[i], p->sets[j], gs), i, j});
         std::stable_sort(ranked.begin(), ranked.end(),
                          [](const Ranked& a, const Ranked& b) { return a.cost < b.cost; });
         std::vector<Cfg> cands;
@@ -168,8 +170,8 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
         add(p->order, mirror(p->set, k));
         for (auto& r : ranked) {
             if ((int)cands.size() >= max_configs) break;
-            add(p->schedules[r.i], p->sets[r.j]);
-            add(p->schedules[r.i], mirror(p->sets[r.j], k));
+            add(reps[r.i], p->sets[r.j]);
+            add(reps[r.i], mirror(p->sets[r.j], k));
         }
 
         // 2. sample stride: about 40 ms for the planner's own configuration
@@ -192,25 +194,41 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
         base.root_stride = stride;
         base.root_offset = stride / 2;
 
-        // 3. time each configuration
-        size_t best = 0;
-        double best_ms = -1;
+        // 3. time each configuration: all of them on a sample 8x sparser,
+        //    then the four fastest again on the full sample
+        auto run_sample = [&](size_t c, int64_t str) -> double {
+            gpint::LaunchCfg cfg = gpint::default_launch(cands[c].desc);
+            cfg.root_stride = str;
+            cfg.root_offset = str / 2;
+            return time_launch(g->dg, cands[c].desc, cfg, s, res);
+        };
+        std::vector<std::pair<double, size_t>> coarse;
         int measured = 0;
         for (size_t c = 0; st == GP_OK && c < cands.size(); ++c) {
             if (spent > budget_ms && measured > 0) break;
-            gpint::LaunchCfg cfg = gpint::default_launch(cands[c].desc);
-            cfg.root_stride = base.root_stride;
-            cfg.root_offset = base.root_offset;
-            double t = time_launch(g->dg, cands[c].desc, cfg, s, res);
+            double t = run_sample(c, base.root_stride * 8);
             if (t < 0) {
                 st = GP_ERR_HIP;
                 break;
             }
             spent += t;
             ++measured;
+            coarse.push_back({t, c});
+        }
+        std::stable_sort(coarse.begin(), coarse.end());
+        size_t best = coarse.empty() ? 0 : coarse[0].second;
+        double best_ms = -1;
+        for (size_t r = 0; st == GP_OK && r < coarse.size() && r < 4; ++r) {
+            if (spent > 1.5 * budget_ms && best_ms >= 0) break;
+            double t = run_sample(coarse[r].second, base.root_stride);
+            if (t < 0) {
+                st = GP_ERR_HIP;
+                break;
+            }
+            spent += t;
             if (best_ms < 0 || t < best_ms) {
                 best_ms = t;
-                best = c;
+                best = coarse[r].second;
             }
         }
         gpint::LaunchCfg best_launch = gpint::default_launch(cands[best].desc);
@@ -227,7 +245,7 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
                     if (lm == 2 && !leaf_intersects) continue;
                     if (lm == 3 && !can_flatten) continue;
                     for (int w : {16, 32}) {
-                        if (spent > 2 * budget_ms && best_l >= 0) break;
+                        if (spent > 2.5 * budget_ms && best_l >= 0) break;
                         gpint::LaunchCfg cfg = best_launch;
                         cfg.group = grp;
                         cfg.leaf = lm;

@@ -48,7 +48,7 @@ class PlanOpts(ctypes.Structure):
                 ("force_order", ctypes.c_int32 * MAX_K), ("force_set", ctypes.c_int32),
                 ("n_force_restr", ctypes.c_int32),
                 ("force_restr", ctypes.c_int32 * (2 * MAX_K * MAX_K)),
-                ("cost_cap", ctypes.c_double)]
+                ("cost_cap", ctypes.c_double), ("max_seconds", ctypes.c_double)]
 
 
 class Launch(ctypes.Structure):
@@ -103,6 +103,9 @@ SIGNATURES = {
     "gp_count_batch": (_I32, [_P, _P, _I32, ctypes.POINTER(Launch), _P, _P]),
     "gp_count_traffic": (_I32, [_P, _P, ctypes.POINTER(Launch), _P,
                                 ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]),
+    "gp_batch_create": (_I32, [_P, _P, _I32, ctypes.POINTER(Launch), _P, ctypes.POINTER(_P)]),
+    "gp_batch_run": (_I32, [_P, _P, _P]),
+    "gp_free_batch": (None, [_P]),
     "gp_strerror": (ctypes.c_char_p, [_I32]),
     "gp_version": (ctypes.c_char_p, []),
 }
@@ -375,6 +378,36 @@ def count_batch(graph: Graph, plans: Sequence[Plan], stream=None, **launch) -> l
     _check(_lib().gp_count_batch(graph.handle, arr, len(plans), ctypes.byref(lp),
                                  _stream_handle(stream), out), "gp_count_batch")
     return list(out)
+
+
+class Batch:
+    """Several plans counted by one persistent launch captured in a hipGraph."""
+
+    def __init__(self, graph: Graph, plans: Sequence[Plan], stream=None, **launch):
+        self.graph = graph
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(plans))(*[p.handle for p in plans])
+        lp = _launch(**launch)
+        self._h = ctypes.c_void_p()
+        _check(_lib().gp_batch_create(graph.handle, arr, len(plans), ctypes.byref(lp),
+                                      _stream_handle(stream), ctypes.byref(self._h)),
+               "gp_batch_create")
+
+    def run(self, stream=None) -> list[int]:
+        out = (ctypes.c_uint64 * len(self.plans))()
+        _check(_lib().gp_batch_run(self._h, _stream_handle(stream), out), "gp_batch_run")
+        return list(out)
+
+    def close(self) -> None:
+        if self._h:
+            _lib().gp_free_batch(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def version() -> str:

@@ -236,14 +236,60 @@ def test_config2_small_patterns_full_count():
 
 # ------------------------------------------------------------------ batched
 
-def test_batch_equals_plain():
+@pytest.mark.parametrize("group", [64, 32, 16])
+def test_batch_equals_plain(group):
     g = I.er(200, 0.08, seed=11)
     graph = gp.Graph.from_csr(g)
-    names = ["triangle", "4-cycle", "house", "5-cycle", "6-cycle-chord", "prism"]
+    names = ["triangle", "4-cycle", "house", "5-cycle", "6-cycle-chord", "prism", "edge",
+             "3-star", "5-wheel"]
     plans = [gp.Plan(*P[x], stats=graph.stats()) for x in names]
     plain = [gp.count(graph, p) for p in plans]
-    assert gp.count_batch(graph, plans) == plain
+    assert gp.count_batch(graph, plans, group=group) == plain
     assert plain == [O.count(g, *P[x]) for x in names]
+
+
+def test_batch_mixed_sizes_up_to_eight():
+    g = I.er(24, 0.6, seed=3)
+    graph = gp.Graph.from_csr(g, hub_bitmaps="dense")
+    pats = [P["edge"], P["triangle"], P["diamond"], P["5-clique"], P["prism"],
+            (7, [(i, j) for i, j in itertools.combinations(range(7), 2)]),
+            (8, [(i, (i + 1) % 8) for i in range(8)] + [(0, 4)]),
+            (7, [(i, i + 1) for i in range(6)] + [(0, 6), (2, 5)])]
+    plans = [gp.Plan(k, e, stats=graph.stats()) for k, e in pats]
+    want = [O.count(g, k, e) for k, e in pats]
+    assert [gp.count(graph, p) for p in plans] == want
+    assert gp.count_batch(graph, plans) == want
+
+
+def test_batch_graph_replays_match_eager():
+    """The captured hipGraph replays several times, with eager counts and
+    synchronisations in between; every replay equals the eager result."""
+    import torch
+    g = I.config_graph(2)
+    graph = gp.Graph.from_csr(g, device=True)
+    names = ["triangle", "4-cycle", "diamond", "house", "4-clique", "tailed-triangle"]
+    plans = [gp.Plan(*P[x], stats=graph.stats()) for x in names]
+    eager = [gp.count(graph, p) for p in plans]
+    batch = gp.Batch(graph, plans)
+    for rep in range(4):
+        assert batch.run() == eager, rep
+        assert gp.count(graph, plans[rep % len(plans)]) == eager[rep % len(plans)]
+        torch.cuda.synchronize()
+    batch.close()
+
+
+def test_batch_of_sixty_four_plans():
+    g = I.er(120, 0.12, seed=21)
+    graph = gp.Graph.from_csr(g)
+    rng = np.random.default_rng(8)
+    pats = []
+    for _ in range(64):
+        k = int(rng.integers(2, 6))
+        pats.append((k, I.random_connected_pattern(k, rng, 0.5)))
+    plans = [gp.Plan(k, e, stats=graph.stats()) for k, e in pats]
+    want = [gp.count(graph, p) for p in plans]
+    assert gp.count_batch(graph, plans) == want
+    assert want[:8] == [O.count(g, k, e) for k, e in pats[:8]]
 
 
 # ------------------------------------------------------- sampling and tuning

@@ -268,8 +268,8 @@ gp_status gp_count_traffic(const gp_graph* g, const gp_plan* p, const gp_launch*
  * persistent launch: the task space is the concatenation of the plans' root
  * edges, handed out in chunks from one atomic queue, so plans of uneven cost
  * fill each other's tails (Section IV-E's task partitioning across patterns).
- * Each plan runs with its own leaf mode (from its tuned launch); the group
- * size comes from `launch` or the first plan. out[i] = count of plans[i]
+ * The lanes per group (64 or 32) and leaf mode (1, or 3 where the plan allows
+ * it) come from `launch`, else from the first plan's launch. out[i] = count of plans[i]
  * (host memory). Blocking. Counts equal gp_count's bit for bit.
  */
 gp_status gp_count_batch(const gp_graph* g, const gp_plan* const* plans, int32_t np,

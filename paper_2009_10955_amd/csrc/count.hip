@@ -14,9 +14,22 @@ KernelFn pick_kernel_k5(int group, int leaf, int mode);
 KernelFn pick_kernel_k6(int group, int leaf, int mode);
 KernelFn pick_kernel_k7(int group, int leaf, int mode);
 KernelFn pick_kernel_k8(int group, int leaf, int mode);
-BatchFn batch_kernel_g64();
-BatchFn batch_kernel_g32();
-BatchFn batch_kernel_g16();
+#define GP_DECL_BATCH(g, k, l) BatchFn batch_kernel_g##g##_k##k##_l##l();
+GP_DECL_BATCH(64, 5, 1) GP_DECL_BATCH(64, 6, 1) GP_DECL_BATCH(64, 8, 1)
+GP_DECL_BATCH(32, 5, 1) GP_DECL_BATCH(32, 6, 1) GP_DECL_BATCH(32, 8, 1)
+GP_DECL_BATCH(64, 5, 3) GP_DECL_BATCH(64, 6, 3) GP_DECL_BATCH(64, 8, 3)
+GP_DECL_BATCH(32, 5, 3) GP_DECL_BATCH(32, 6, 3) GP_DECL_BATCH(32, 8, 3)
+#undef GP_DECL_BATCH
+
+BatchFn pick_batch_kernel(int group, int kmax, int leaf) {
+    const int km = kmax <= 5 ? 5 : (kmax <= 6 ? 6 : 8);
+    if (leaf == 3) {
+        if (group == 64) return km == 5 ? batch_kernel_g64_k5_l3() : (km == 6 ? batch_kernel_g64_k6_l3() : batch_kernel_g64_k8_l3());
+        return km == 5 ? batch_kernel_g32_k5_l3() : (km == 6 ? batch_kernel_g32_k6_l3() : batch_kernel_g32_k8_l3());
+    }
+    if (group == 64) return km == 5 ? batch_kernel_g64_k5_l1() : (km == 6 ? batch_kernel_g64_k6_l1() : batch_kernel_g64_k8_l1());
+    return km == 5 ? batch_kernel_g32_k5_l1() : (km == 6 ? batch_kernel_g32_k6_l1() : batch_kernel_g32_k8_l1());
+}
 
 namespace {
 __global__ void init_counters(unsigned long long* p, int n) {
@@ -168,7 +181,8 @@ gp_status batch_prepare(const DeviceGraph& g, const GpPlanDesc* descs, const int
     if (np < 1 || np > kBatchMaxPlans) return GP_ERR_ARG;
     BatchState b;
     b.np = np;
-    b.group = cfg.group >= 64 ? 64 : (cfg.group >= 32 ? 32 : 16);
+    b.group = cfg.group >= 64 ? 64 : 32;
+    b.leaf = cfg.leaf == 3 ? 3 : 1;
     b.chunk = std::max(1, cfg.chunk);
     std::vector<BatchPlan> plans(np);
     int64_t total = 0;
@@ -188,6 +202,7 @@ gp_status batch_prepare(const DeviceGraph& g, const GpPlanDesc* descs, const int
         plans[i].pad = 0;
         total += cnt;
         nbuf = std::max(nbuf, descs[i].nbuf);
+        b.kmax = std::max(b.kmax, (int)descs[i].k);
     }
     b.total_tasks = total;
     b.nbuf = nbuf;
@@ -224,7 +239,7 @@ gp_status batch_prepare(const DeviceGraph& g, const GpPlanDesc* descs, const int
 }
 
 gp_status batch_enqueue(const DeviceGraph& g, const BatchState& st, hipStream_t stream) {
-    BatchFn fn = st.group == 64 ? batch_kernel_g64() : (st.group == 32 ? batch_kernel_g32() : batch_kernel_g16());
+    BatchFn fn = pick_batch_kernel(st.group, st.kmax, st.leaf);
     hipLaunchKernelGGL(init_counters, dim3(1), dim3(64), 0, stream, st.queue, 1);
     for (int i = 0; i < 2 * st.np; i += 64)
         hipLaunchKernelGGL(init_counters, dim3(1), dim3(64), 0, stream, st.result + i,

@@ -6,12 +6,14 @@
 // plans is split at the boundary, so no task is lost and plans of uneven cost
 // fill each other's tails. Each group of G lanes interprets the descriptor of
 // the plan its task belongs to; per-plan counts are reduced per group into LDS
-// and flushed once per wavefront at the end. Built once per group size
-// (-DGP_BATCH_G=64/32/16).
+// and flushed once per wavefront at the end. Built once per group size,
+// largest pattern size and leaf mode (-DGP_BATCH_G=64/32, -DGP_BATCH_KMAX=
+// 5/6/8, -DGP_BATCH_LEAF=1/3), so a batch carries only the register
+// footprint of its own shapes.
 #include "count_kernel.hpp"
 
-#ifndef GP_BATCH_G
-#error "GP_BATCH_G must be defined"
+#if !defined(GP_BATCH_G) || !defined(GP_BATCH_KMAX) || !defined(GP_BATCH_LEAF)
+#error "GP_BATCH_G, GP_BATCH_KMAX and GP_BATCH_LEAF must be defined"
 #endif
 
 namespace gpcount {
@@ -19,11 +21,16 @@ namespace gpcount {
 namespace {
 
 constexpr int G = GP_BATCH_G;
+constexpr int KMAX = GP_BATCH_KMAX;
+constexpr int LEAF = GP_BATCH_LEAF;  // 1, or 3 (flattened where possible, else as 1)
 
 template <int K>
 __device__ __forceinline__ void batch_roots(const GpPlanDesc& d, const Ctx<G>& c, const int2* roots,
                                             int64_t t0, int64_t t1, int leaf, uint64_t& acc, bool& ovf) {
-    if constexpr (K <= 3) {
+    if constexpr (K > KMAX) {
+        return;
+    } else if constexpr (K <= 3) {
+        (void)leaf;
         // lanes take different roots
         for (int64_t base = t0; base < t1; base += G) {
             const int64_t r = base + c.g.gl;
@@ -39,15 +46,16 @@ __device__ __forceinline__ void batch_roots(const GpPlanDesc& d, const Ctx<G>& c
         }
     } else {
         for (int64_t r = t0; r < t1; ++r) {
-            const int2 e = roots[r];
+            int2 e = roots[r];
+            e.x = uni<G>(e.x);
+            e.y = uni<G>(e.y);
             int32_t v[K];
 #pragma unroll
             for (int j = 0; j < K; ++j) v[j] = 0;
             v[0] = e.x;
             v[1] = e.y;
             run_builds<K, G, MODE_PLAIN>(d, c, 1, v);
-            if (leaf == 3) search<K, 2, G, 3, MODE_PLAIN>(d, c, v, acc, ovf);
-            else search<K, 2, G, 1, MODE_PLAIN>(d, c, v, acc, ovf);
+            search<K, 2, G, LEAF, MODE_PLAIN>(d, c, v, acc, ovf);
         }
     }
 }
@@ -81,7 +89,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
     for (;;) {
         unsigned long long q = 0;
         if (c.g.gl == 0) q = atomicAdd(a.queue, (unsigned long long)chunk);
-        q = c.g.bcast(q, 0);
+        q = (unsigned long long)uni64<G>((int64_t)c.g.bcast(q, 0));
         const int64_t t0 = (int64_t)q;
         if (t0 >= a.total_tasks) break;
         const int64_t t_end = min(t0 + chunk, a.total_tasks);
@@ -139,6 +147,9 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
 #define GP_CAT2(a, b) a##b
 #define GP_CAT(a, b) GP_CAT2(a, b)
 
-BatchFn GP_CAT(batch_kernel_g, GP_BATCH_G)() { return batch_kernel; }
+BatchFn GP_CAT(GP_CAT(GP_CAT(GP_CAT(GP_CAT(batch_kernel_g, GP_BATCH_G), _k), GP_BATCH_KMAX), _l),
+               GP_BATCH_LEAF)() {
+    return batch_kernel;
+}
 
 }  // namespace gpcount

@@ -93,6 +93,34 @@ struct BatchArgs {
 
 typedef void (*BatchFn)(BatchArgs);
 
+// Values equal in every lane of a group. With 64-lane groups they are
+// wavefront-uniform: readfirstlane lets the compiler keep them, and what is
+// computed from them (bound vertices, set bounds, loop counters), in scalar
+// registers, which leaves vector registers for more resident wavefronts.
+template <int G>
+__device__ __forceinline__ int32_t uni(int32_t x) {
+    if constexpr (G == 64) return __builtin_amdgcn_readfirstlane(x);
+    else return x;
+}
+template <int G>
+__device__ __forceinline__ int64_t uni64(int64_t x) {
+    if constexpr (G == 64) {
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)x);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)((uint64_t)x >> 32));
+        return (int64_t)(((uint64_t)hi << 32) | lo);
+    } else {
+        return x;
+    }
+}
+// Cut a group-uniform set to [lo, hi) (lo, hi group-uniform).
+template <int G>
+__device__ __forceinline__ Set trim_u(Set s, int32_t lo, int32_t hi) {
+    int32_t b = lo > 0 ? uni<G>(lower_bound(s.p, s.n, lo)) : 0;
+    int32_t e = hi < 0x7fffffff ? uni<G>(lower_bound(s.p, s.n, hi)) : s.n;
+    if (e < b) e = b;
+    return Set{s.p + b, e - b, s.bits};
+}
+
 template <int G>
 struct Ctx {
     const int64_t* row_ptr;
@@ -112,6 +140,14 @@ struct Ctx {
     }
     __device__ __forceinline__ Set buf(int slot) const {
         return Set{bufs + (int64_t)slot * cap, lens[slot], nullptr};
+    }
+    // the same for a group-uniform vertex or slot
+    __device__ __forceinline__ Set nbr_u(int32_t v) const {
+        const int64_t b = uni64<G>(row_ptr[v]), e = uni64<G>(row_ptr[v + 1]);
+        return Set{col + b, (int32_t)(e - b), v < n_hubs ? hub_bits + (int64_t)v * hub_words : nullptr};
+    }
+    __device__ __forceinline__ Set buf_u(int slot) const {
+        return Set{bufs + (int64_t)slot * cap, uni<G>(lens[slot]), nullptr};
     }
 };
 
@@ -170,13 +206,13 @@ __device__ __forceinline__ void run_builds(const GpPlanDesc& d, const Ctx<G>& c,
         const GpBuild& b = d.b[t];
         int32_t lo, hi;
         bounds<K>(b.hi_src, b.lo_src, v, lo, hi);
-        Set A = b.src_buf >= 0 ? c.buf(b.src_buf) : c.nbr(pick<K>(v, b.src_list));
-        Set B = c.nbr(pick<K>(v, b.with_list));
-        A = trim(A, lo, hi);
-        B = trim(B, lo, hi);
+        Set A = b.src_buf >= 0 ? c.buf_u(b.src_buf) : c.nbr_u(pick<K>(v, b.src_list));
+        Set B = c.nbr_u(pick<K>(v, b.with_list));
+        A = trim_u<G>(A, lo, hi);
+        B = trim_u<G>(B, lo, hi);
         if constexpr (MODE == MODE_ACCOUNT)
             if (c.g.gl == 0) *c.bytes += 4ull * (uint64_t)(A.n + B.n);
-        int32_t n = intersect_into<G>(c.g, A, B, c.bufs + (int64_t)b.dst * c.cap);
+        int32_t n = uni<G>(intersect_into<G>(c.g, A, B, c.bufs + (int64_t)b.dst * c.cap));
         group_fence();
         c.lens[b.dst] = n;
         group_fence();
@@ -250,10 +286,10 @@ __device__ __forceinline__ uint32_t leaf_group(const GpPlanDesc& d, const Ctx<G>
     }
     int32_t lo, hi;
     bounds<K>(lv.hi_src, lv.lo_src, v, lo, hi);
-    Set A = lv.pre_buf >= 0 ? c.buf(lv.pre_buf) : c.nbr(pick<K>(v, lv.pre_list));
-    Set B = c.nbr(pick<K>(v, lv.last_list));
-    A = trim(A, lo, hi);
-    B = trim(B, lo, hi);
+    Set A = lv.pre_buf >= 0 ? c.buf_u(lv.pre_buf) : c.nbr_u(pick<K>(v, lv.pre_list));
+    Set B = c.nbr_u(pick<K>(v, lv.last_list));
+    A = trim_u<G>(A, lo, hi);
+    B = trim_u<G>(B, lo, hi);
     if constexpr (MODE == MODE_ACCOUNT)
         if (c.g.gl == 0) *c.bytes += 4ull * (uint64_t)(A.n + B.n);
     const uint32_t inj = lv.inj;
@@ -334,8 +370,8 @@ __device__ void search(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], ui
     const GpLevel& lv = d.lv[L];
     int32_t lo, hi;
     bounds<K>(lv.hi_src, lv.lo_src, v, lo, hi);
-    Set S = lv.list >= 0 ? c.nbr(pick<K>(v, lv.list)) : c.buf(lv.buf);
-    S = trim(S, lo, hi);
+    Set S = lv.list >= 0 ? c.nbr_u(pick<K>(v, lv.list)) : c.buf_u(lv.buf);
+    S = trim_u<G>(S, lo, hi);
     if constexpr (MODE == MODE_ACCOUNT)
         if (c.g.gl == 0) *c.bytes += 4ull * (uint64_t)S.n;
     if constexpr (L == K - 2) {
@@ -355,7 +391,7 @@ __device__ void search(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], ui
             }
         } else {
             for (int32_t t = 0; t < S.n; ++t) {
-                int32_t x = S.p[t];
+                const int32_t x = uni<G>(S.p[t]);
                 if (inj_hit<K>(lv.inj, v, x)) continue;
                 v[K - 2] = x;
                 uint32_t cnt = leaf_group<K, G, MODE>(d, c, v);
@@ -370,7 +406,7 @@ __device__ void search(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], ui
             }
         }
         for (int32_t t = 0; t < S.n; ++t) {
-            int32_t x = S.p[t];
+            const int32_t x = uni<G>(S.p[t]);
             if (inj_hit<K>(lv.inj, v, x)) continue;
             v[L] = x;
             run_builds<K, G, MODE>(d, c, L, v);
@@ -410,7 +446,7 @@ __global__ __launch_bounds__(kBlock) void count_kernel(GpPlanDesc d, CountArgs a
     for (;;) {
         unsigned long long t0 = 0;
         if (c.g.gl == 0) t0 = atomicAdd(a.queue, (unsigned long long)chunk);
-        t0 = c.g.bcast(t0, 0);
+        t0 = (unsigned long long)uni64<G>((int64_t)c.g.bcast(t0, 0));
         if ((int64_t)t0 >= a.n_roots) break;
         const int64_t t1 = min((int64_t)t0 + chunk, a.n_roots);
         if constexpr (K <= 3 && LEAF != 2) {
@@ -433,6 +469,8 @@ __global__ __launch_bounds__(kBlock) void count_kernel(GpPlanDesc d, CountArgs a
         } else {
             for (int64_t r = (int64_t)t0; r < t1; ++r) {
                 int2 e = a.roots[a.root_offset + r * a.root_stride];
+                e.x = uni<G>(e.x);
+                e.y = uni<G>(e.y);
                 const uint64_t before = acc;
                 if constexpr (MODE == MODE_ACCOUNT)
                     if (c.g.gl == 0) bytes += 8;

@@ -51,6 +51,8 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
 // itself allocates nothing (it can be captured in a hipGraph and replayed).
 struct BatchState {
     int np = 0;
+    int kmax = 2;
+    int leaf = 1;
     int group = 64;
     int64_t blocks = 0;
     int64_t total_tasks = 0;

@@ -52,7 +52,8 @@ enum {
     GP_ERR_OVERFLOW = -9,        /* the true count does not fit in 64 bits */
     GP_ERR_BUDGET = -10,         /* predicted cost above the caller's cap */
     GP_ERR_CSR_RANGE = -11,      /* a column index outside [0, n) or row_ptr[0] != 0 */
-    GP_ERR_UNSUPPORTED = -12     /* option or shape not built into this library */
+    GP_ERR_UNSUPPORTED = -12,    /* option or shape not built into this library */
+    GP_ERR_TIMEOUT = -13         /* gp_server_wait: the query did not finish in time */
 };
 
 #define GP_MAX_K 8
@@ -291,6 +292,67 @@ gp_status gp_batch_create(const gp_graph* g, const gp_plan* const* plans, int32_
 gp_status gp_batch_run(gp_batch* b, void* stream, uint64_t* out);
 
 void gp_free_batch(gp_batch* b);
+
+/* ---------------------------------------------------------------- serving */
+
+typedef struct gp_server gp_server;
+
+typedef struct {
+    int32_t max_active;     /* queries per graph sharing one launch (1..64; 0 = 64) */
+    double target_ms;       /* wall time aimed at per iteration (0 = 25 ms) */
+    double cost_cap;        /* reject queries whose predicted cost (Section IV-C model) exceeds
+                               this with GP_ERR_BUDGET (0 = no cap) */
+    int64_t initial_slice;  /* root tasks a query gets in its first iteration (0 = 8192) */
+    int32_t group;          /* lanes per group of the batched kernel: 64 or 32 (0 = 64) */
+    int32_t leaf_mode;      /* 1 or 3 (0 = 3) */
+    int32_t waves_per_cu;   /* 0 = 16 */
+} gp_server_opts;
+
+typedef struct {
+    int64_t submitted, completed, rejected, failed;
+    int64_t iterations, launches;
+    double busy_seconds;      /* wall time spent in iterations with work on the GPU */
+    int64_t joined_midflight; /* queries admitted while another query of their graph was
+                                 part-way through its root tasks */
+    int64_t max_batch;        /* most queries that shared one launch */
+} gp_server_stats;
+
+void gp_server_opts_default(gp_server_opts* o);
+
+/*
+ * A serving loop over resident graphs (all on one device; they must outlive
+ * the server). A worker thread plans each submitted query (plans cached per
+ * graph and edge list), rejects those whose predicted cost exceeds the cap,
+ * and admits the rest as batch slots free up (at most 64 per graph per
+ * launch). Work runs in iterations: per graph, one batched persistent launch
+ * over a slice of every active query's remaining root tasks, graphs on their
+ * own streams so their launches overlap. Queries that arrive while others run
+ * join at the next iteration. Slices adapt to the target iteration time from
+ * the per-query busy time the kernel reports. Counts are exact: the slices
+ * partition each query's root tasks, so a count equals the query's solo
+ * gp_count.
+ */
+gp_status gp_server_create(const gp_graph* const* graphs, int32_t ng, const gp_server_opts* opts,
+                           gp_server** out);
+
+/* Queue a count of the pattern (k vertices, e edges) on graphs[graph]; thread-safe. */
+gp_status gp_server_submit(gp_server* s, int32_t graph, const int32_t* edges, int32_t k, int32_t e,
+                           uint64_t* ticket);
+
+/* Non-blocking. *done = 1 once the query has finished; then *status (GP_OK,
+ * GP_ERR_BUDGET when rejected, GP_ERR_OVERFLOW, ...), *count and *latency_s
+ * (submit to completion) are written (each may be null). */
+gp_status gp_server_poll(gp_server* s, uint64_t ticket, int32_t* done, gp_status* status, uint64_t* count,
+                         double* latency_s);
+
+/* Block until the query finishes, or timeout_s passes (GP_ERR_TIMEOUT; <= 0 waits forever). */
+gp_status gp_server_wait(gp_server* s, uint64_t ticket, double timeout_s, gp_status* status, uint64_t* count,
+                         double* latency_s);
+
+gp_status gp_server_stats_get(gp_server* s, gp_server_stats* out);
+
+/* Stop accepting queries, finish the admitted ones, release everything. */
+void gp_server_destroy(gp_server* s);
 
 /* Human-readable name of a status code (static string). */
 const char* gp_strerror(gp_status s);

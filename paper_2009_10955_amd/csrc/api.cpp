@@ -101,6 +101,7 @@ const char* gp_strerror(gp_status s) {
         case GP_ERR_BUDGET: return "predicted cost above the cap";
         case GP_ERR_CSR_RANGE: return "CSR index out of range";
         case GP_ERR_UNSUPPORTED: return "unsupported option or shape";
+        case GP_ERR_TIMEOUT: return "timed out";
         default: return "unknown status";
     }
 }
@@ -511,18 +512,18 @@ gp_status gp_count_batch(const gp_graph* g, const gp_plan* const* plans, int32_t
     gpint::BatchState bs;
     st = gpint::batch_prepare(g->dg, descs.data(), leafs.data(), nullptr, nullptr, np, cfg, s, &bs);
     if (st != GP_OK) return st;
-    std::vector<unsigned long long> h(2 * np, 0);
+    std::vector<unsigned long long> h(3 * np, 0);
     st = gpint::batch_enqueue(g->dg, bs, s);
     if (st == GP_OK &&
-        hipMemcpyAsync(h.data(), bs.result, sizeof(unsigned long long) * 2 * np, hipMemcpyDeviceToHost, s) !=
+        hipMemcpyAsync(h.data(), bs.result, sizeof(unsigned long long) * 3 * np, hipMemcpyDeviceToHost, s) !=
             hipSuccess)
         st = GP_ERR_HIP;
     if (hipStreamSynchronize(s) != hipSuccess && st == GP_OK) st = GP_ERR_HIP;
     gpint::batch_release(&bs);
     if (st != GP_OK) return st;
     for (int i = 0; i < np; ++i)
-        if (h[2 * i + 1]) return GP_ERR_OVERFLOW;
-    for (int i = 0; i < np; ++i) out[i] = h[2 * i];
+        if (h[3 * i + 1]) return GP_ERR_OVERFLOW;
+    for (int i = 0; i < np; ++i) out[i] = h[3 * i];
     return GP_OK;
 }
 
@@ -545,7 +546,7 @@ gp_status gp_batch_create(const gp_graph* g, const gp_plan* const* plans, int32_
         delete b;
         return st;
     }
-    bool ok = hipHostMalloc((void**)&b->host_res, 2 * sizeof(unsigned long long) * np,
+    bool ok = hipHostMalloc((void**)&b->host_res, 3 * sizeof(unsigned long long) * np,
                             hipHostMallocDefault) == hipSuccess &&
               hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) == hipSuccess;
     if (ok) {
@@ -553,7 +554,7 @@ gp_status gp_batch_create(const gp_graph* g, const gp_plan* const* plans, int32_
         ok = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
         if (ok) {
             gp_status est = gpint::batch_enqueue(g->dg, b->st, b->cap_stream);
-            hipError_t ce = hipMemcpyAsync(b->host_res, b->st.result, 2 * sizeof(unsigned long long) * np,
+            hipError_t ce = hipMemcpyAsync(b->host_res, b->st.result, 3 * sizeof(unsigned long long) * np,
                                            hipMemcpyDeviceToHost, b->cap_stream);
             hipError_t ee = hipStreamEndCapture(b->cap_stream, &b->graph);
             ok = est == GP_OK && ce == hipSuccess && ee == hipSuccess &&
@@ -575,8 +576,8 @@ gp_status gp_batch_run(gp_batch* b, void* stream, uint64_t* out) {
     GP_HIP_TRY(hipGraphLaunch(b->exec, s));
     GP_HIP_TRY(hipStreamSynchronize(s));
     for (int i = 0; i < b->np; ++i)
-        if (b->host_res[2 * i + 1]) return GP_ERR_OVERFLOW;
-    for (int i = 0; i < b->np; ++i) out[i] = b->host_res[2 * i];
+        if (b->host_res[3 * i + 1]) return GP_ERR_OVERFLOW;
+    for (int i = 0; i < b->np; ++i) out[i] = b->host_res[3 * i];
     return GP_OK;
 }
 

@@ -27,7 +27,7 @@ struct gp_batch {
     const gp_graph* g = nullptr;
     int np = 0;
     gpint::BatchState st;
-    unsigned long long* host_res = nullptr;  // pinned, 2*np
+    unsigned long long* host_res = nullptr;  // pinned, 3*np
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;

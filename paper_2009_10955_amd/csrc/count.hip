@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 #include <vector>
 
 #include "count_kernel.hpp"
@@ -175,18 +176,13 @@ void batch_release(BatchState* st) {
     *st = BatchState{};
 }
 
-gp_status batch_prepare(const DeviceGraph& g, const GpPlanDesc* descs, const int* leafs,
-                        const int64_t* offsets, const int64_t* counts, int np,
-                        const LaunchCfg& cfg, hipStream_t stream, BatchState* st) {
-    if (np < 1 || np > kBatchMaxPlans) return GP_ERR_ARG;
-    BatchState b;
-    b.np = np;
-    b.group = cfg.group >= 64 ? 64 : 32;
-    b.leaf = cfg.leaf == 3 ? 3 : 1;
-    b.chunk = std::max(1, cfg.chunk);
-    std::vector<BatchPlan> plans(np);
+// Per-plan task ranges and the launch geometry for np plans.
+static gp_status batch_layout(const DeviceGraph& g, const GpPlanDesc* descs, const int64_t* offsets,
+                              const int64_t* counts, int np, BatchState* b, std::vector<BatchPlan>* plans) {
+    plans->resize(np);
     int64_t total = 0;
     int32_t nbuf = 0;
+    b->kmax = 2;
     for (int i = 0; i < np; ++i) {
         int64_t n_all = 0;
         const int2* roots = pick_roots(g, descs[i].root_cut, &n_all);
@@ -195,34 +191,54 @@ gp_status batch_prepare(const DeviceGraph& g, const GpPlanDesc* descs, const int
         if (off < 0 || cnt < 0) return GP_ERR_ARG;
         off = std::min(off, n_all);
         cnt = std::min(cnt, n_all - off);
-        plans[i].roots = roots + off;
-        plans[i].n_tasks = cnt;
-        plans[i].task_begin = total;
-        plans[i].leaf = (leafs && leafs[i] == 3 && descs[i].k >= 5) ? 3 : 1;
-        plans[i].pad = 0;
+        (*plans)[i].roots = roots + off;
+        (*plans)[i].n_tasks = cnt;
+        (*plans)[i].task_begin = total;
+        (*plans)[i].leaf = b->leaf;
+        (*plans)[i].pad = 0;
         total += cnt;
         nbuf = std::max(nbuf, descs[i].nbuf);
-        b.kmax = std::max(b.kmax, (int)descs[i].k);
+        b->kmax = std::max(b->kmax, (int)descs[i].k);
     }
-    b.total_tasks = total;
-    b.nbuf = nbuf;
-    b.cap = std::max<int64_t>(1, g.deg2);
+    b->np = np;
+    b->total_tasks = total;
+    b->nbuf = nbuf;
+    return GP_OK;
+}
+
+static int64_t batch_blocks(const DeviceGraph& g, const BatchState& b, int waves_per_cu, int32_t nbuf,
+                            int64_t total) {
     const int64_t groups_per_block = kBlock / b.group;
-    int64_t blocks = std::max<int64_t>(1, (int64_t)g.num_cus * cfg.waves_per_cu / (kBlock / 64));
+    int64_t blocks = std::max<int64_t>(1, (int64_t)g.num_cus * waves_per_cu / (kBlock / 64));
     if (nbuf > 0) {
         const int64_t budget = int64_t(16) << 30;
         blocks = std::min(blocks, std::max<int64_t>(1, budget / (groups_per_block * nbuf * b.cap * 4)));
     }
     const int64_t need = (total + b.chunk - 1) / b.chunk;
-    blocks = std::min(blocks, std::max<int64_t>(1, (need + groups_per_block - 1) / groups_per_block));
-    b.blocks = blocks;
-    gp_status rc = GP_OK;
+    return std::min(blocks, std::max<int64_t>(1, (need + groups_per_block - 1) / groups_per_block));
+}
+
+gp_status batch_prepare(const DeviceGraph& g, const GpPlanDesc* descs, const int* leafs,
+                        const int64_t* offsets, const int64_t* counts, int np,
+                        const LaunchCfg& cfg, hipStream_t stream, BatchState* st) {
+    (void)leafs;
+    if (np < 1 || np > kBatchMaxPlans) return GP_ERR_ARG;
+    BatchState b;
+    b.group = cfg.group >= 64 ? 64 : 32;
+    b.leaf = cfg.leaf == 3 ? 3 : 1;
+    b.chunk = std::max(1, cfg.chunk);
+    b.cap = std::max<int64_t>(1, g.deg2);
+    std::vector<BatchPlan> plans;
+    gp_status rc = batch_layout(g, descs, offsets, counts, np, &b, &plans);
+    if (rc != GP_OK) return rc;
+    const int64_t groups_per_block = kBlock / b.group;
+    b.blocks = batch_blocks(g, b, cfg.waves_per_cu, b.nbuf, b.total_tasks);
     if (hipMalloc(&b.descs, sizeof(GpPlanDesc) * np) != hipSuccess ||
         hipMalloc(&b.plans, sizeof(BatchPlan) * np) != hipSuccess ||
         hipMalloc((void**)&b.queue, sizeof(unsigned long long)) != hipSuccess ||
-        hipMalloc((void**)&b.result, 2 * sizeof(unsigned long long) * np) != hipSuccess ||
-        (nbuf > 0 &&
-         hipMalloc((void**)&b.scratch, (size_t)(blocks * groups_per_block * nbuf * b.cap * 4)) != hipSuccess))
+        hipMalloc((void**)&b.result, 3 * sizeof(unsigned long long) * np) != hipSuccess ||
+        (b.nbuf > 0 &&
+         hipMalloc((void**)&b.scratch, (size_t)(b.blocks * groups_per_block * b.nbuf * b.cap * 4)) != hipSuccess))
         rc = GP_ERR_NOMEM;
     if (rc == GP_OK &&
         (hipMemcpyAsync(b.descs, descs, sizeof(GpPlanDesc) * np, hipMemcpyHostToDevice, stream) != hipSuccess ||
@@ -241,9 +257,9 @@ gp_status batch_prepare(const DeviceGraph& g, const GpPlanDesc* descs, const int
 gp_status batch_enqueue(const DeviceGraph& g, const BatchState& st, hipStream_t stream) {
     BatchFn fn = pick_batch_kernel(st.group, st.kmax, st.leaf);
     hipLaunchKernelGGL(init_counters, dim3(1), dim3(64), 0, stream, st.queue, 1);
-    for (int i = 0; i < 2 * st.np; i += 64)
+    for (int i = 0; i < 3 * st.np; i += 64)
         hipLaunchKernelGGL(init_counters, dim3(1), dim3(64), 0, stream, st.result + i,
-                           std::min(64, 2 * st.np - i));
+                           std::min(64, 3 * st.np - i));
     BatchArgs a;
     a.row_ptr = g.row_ptr;
     a.col = g.col;
@@ -263,6 +279,71 @@ gp_status batch_enqueue(const DeviceGraph& g, const BatchState& st, hipStream_t 
     if (st.total_tasks > 0)
         hipLaunchKernelGGL(fn, dim3((unsigned)st.blocks), dim3(kBlock), 0, stream, a);
     return hipGetLastError() == hipSuccess ? GP_OK : GP_ERR_HIP;
+}
+
+gp_status arena_create(const DeviceGraph& g, int nbuf_cap, const LaunchCfg& cfg, BatchArena* ar) {
+    BatchArena a;
+    a.cfg = cfg;
+    BatchState& b = a.st;
+    b.group = cfg.group >= 64 ? 64 : 32;
+    b.leaf = cfg.leaf == 3 ? 3 : 1;
+    b.chunk = std::max(1, cfg.chunk);
+    b.cap = std::max<int64_t>(1, g.deg2);
+    a.nbuf_cap = std::max(0, std::min(nbuf_cap, GP_DESC_MAX_BUILDS));
+    a.blocks_cap = batch_blocks(g, b, cfg.waves_per_cu, a.nbuf_cap, INT64_MAX / 4);
+    const int64_t groups_per_block = kBlock / b.group;
+    bool ok = hipMalloc(&b.descs, sizeof(GpPlanDesc) * kBatchMaxPlans) == hipSuccess &&
+              hipMalloc(&b.plans, sizeof(BatchPlan) * kBatchMaxPlans) == hipSuccess &&
+              hipMalloc((void**)&b.queue, sizeof(unsigned long long)) == hipSuccess &&
+              hipMalloc((void**)&b.result, 3 * sizeof(unsigned long long) * kBatchMaxPlans) == hipSuccess &&
+              (a.nbuf_cap == 0 ||
+               hipMalloc((void**)&b.scratch,
+                         (size_t)(a.blocks_cap * groups_per_block * a.nbuf_cap * b.cap * 4)) == hipSuccess) &&
+              hipHostMalloc((void**)&a.h_descs, sizeof(GpPlanDesc) * kBatchMaxPlans, hipHostMallocDefault) ==
+                  hipSuccess &&
+              hipHostMalloc(&a.h_plans, sizeof(BatchPlan) * kBatchMaxPlans, hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc((void**)&a.h_result, 3 * sizeof(unsigned long long) * kBatchMaxPlans,
+                            hipHostMallocDefault) == hipSuccess;
+    if (!ok) {
+        arena_release(&a);
+        return GP_ERR_NOMEM;
+    }
+    *ar = a;
+    return GP_OK;
+}
+
+gp_status arena_launch(const DeviceGraph& g, BatchArena* ar, const GpPlanDesc* descs, const int64_t* offsets,
+                       const int64_t* counts, int np, hipStream_t stream) {
+    if (np < 1 || np > kBatchMaxPlans) return GP_ERR_ARG;
+    BatchState& b = ar->st;
+    std::vector<BatchPlan> plans;
+    gp_status rc = batch_layout(g, descs, offsets, counts, np, &b, &plans);
+    if (rc != GP_OK) return rc;
+    if (b.nbuf > ar->nbuf_cap) return GP_ERR_NOMEM;
+    // the scratch was carved for nbuf_cap slots per group; any smaller nbuf fits
+    b.blocks = std::min(ar->blocks_cap, batch_blocks(g, b, ar->cfg.waves_per_cu, b.nbuf, b.total_tasks));
+    if (b.nbuf > 0) {
+        const int64_t groups_per_block = kBlock / b.group;
+        const int64_t fit = ar->blocks_cap * groups_per_block * ar->nbuf_cap / (groups_per_block * b.nbuf);
+        b.blocks = std::min(b.blocks, std::max<int64_t>(1, fit));
+    }
+    std::memcpy(ar->h_descs, descs, sizeof(GpPlanDesc) * np);
+    std::memcpy(ar->h_plans, plans.data(), sizeof(BatchPlan) * np);
+    GP_HIP_TRY(hipMemcpyAsync(b.descs, ar->h_descs, sizeof(GpPlanDesc) * np, hipMemcpyHostToDevice, stream));
+    GP_HIP_TRY(hipMemcpyAsync(b.plans, ar->h_plans, sizeof(BatchPlan) * np, hipMemcpyHostToDevice, stream));
+    rc = batch_enqueue(g, b, stream);
+    if (rc != GP_OK) return rc;
+    GP_HIP_TRY(hipMemcpyAsync(ar->h_result, b.result, 3 * sizeof(unsigned long long) * np, hipMemcpyDeviceToHost,
+                              stream));
+    return GP_OK;
+}
+
+void arena_release(BatchArena* ar) {
+    batch_release(&ar->st);
+    if (ar->h_descs) (void)hipHostFree(ar->h_descs);
+    if (ar->h_plans) (void)hipHostFree(ar->h_plans);
+    if (ar->h_result) (void)hipHostFree(ar->h_result);
+    *ar = BatchArena{};
 }
 
 }  // namespace gpint

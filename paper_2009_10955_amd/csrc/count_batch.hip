@@ -5,8 +5,9 @@
 // in chunks by one device-wide atomic counter; a chunk that straddles two
 // plans is split at the boundary, so no task is lost and plans of uneven cost
 // fill each other's tails. Each group of G lanes interprets the descriptor of
-// the plan its task belongs to; per-plan counts are reduced per group into LDS
-// and flushed once per wavefront at the end. Built once per group size,
+// the plan its task belongs to; per-plan counts (and the wall-clock time
+// groups spent on each plan, for the serving scheduler) are reduced per group
+// into LDS and flushed once per wavefront at the end. Built once per group size,
 // largest pattern size and leaf mode (-DGP_BATCH_G=64/32, -DGP_BATCH_KMAX=
 // 5/6/8, -DGP_BATCH_LEAF=1/3), so a batch carries only the register
 // footprint of its own shapes.
@@ -64,10 +65,12 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
     __shared__ int32_t s_len[kBlock / G][GP_DESC_MAX_BUILDS];
     __shared__ unsigned long long s_cnt[kBlock / 64][kBatchMaxPlans];
     __shared__ unsigned s_ovf[kBlock / 64][kBatchMaxPlans];
+    __shared__ unsigned long long s_busy[kBlock / 64][kBatchMaxPlans];
     const int wave = threadIdx.x / 64;
     for (int p = threadIdx.x & 63; p < kBatchMaxPlans; p += 64) {
         s_cnt[wave][p] = 0;
         s_ovf[wave][p] = 0;
+        s_busy[wave][p] = 0;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
@@ -100,6 +103,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
             const BatchPlan& bp = a.plans[p];
             const int64_t piece_end = min(t_end, bp.task_begin + bp.n_tasks);
             const GpPlanDesc& d = a.descs[p];
+            const uint64_t clk0 = wall_clock64();
             uint64_t acc = 0;
             bool ovf = false;
             const int64_t l0 = tt - bp.task_begin, l1 = piece_end - bp.task_begin;
@@ -126,6 +130,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
             if (c.g.gl == 0) {
                 const unsigned long long old = atomicAdd(&s_cnt[wave][p], (unsigned long long)s);
                 if (any_ovf || old + s < old) s_ovf[wave][p] = 1;
+                atomicAdd(&s_busy[wave][p], (unsigned long long)(wall_clock64() - clk0));
             }
             tt = piece_end;
         }
@@ -135,10 +140,11 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
     for (int p = threadIdx.x & 63; p < a.np; p += 64) {
         const unsigned long long v = s_cnt[wave][p];
         if (v) {
-            const unsigned long long old = atomicAdd(&a.result[2 * p], v);
-            if (old + v < old) atomicOr(&a.result[2 * p + 1], 1ull);
+            const unsigned long long old = atomicAdd(&a.result[3 * p], v);
+            if (old + v < old) atomicOr(&a.result[3 * p + 1], 1ull);
         }
-        if (s_ovf[wave][p]) atomicOr(&a.result[2 * p + 1], 1ull);
+        if (s_ovf[wave][p]) atomicOr(&a.result[3 * p + 1], 1ull);
+        if (s_busy[wave][p]) atomicAdd(&a.result[3 * p + 2], s_busy[wave][p]);
     }
 }
 

@@ -87,7 +87,7 @@ struct BatchArgs {
     int64_t buf_cap;
     int32_t nbuf;  // buffer slots per group (max over plans)
     unsigned long long* queue;
-    unsigned long long* result;  // {count, overflow} per plan
+    unsigned long long* result;  // {count, overflow, busy clock ticks} per plan
     int32_t chunk;
 };
 

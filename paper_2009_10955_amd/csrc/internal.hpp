@@ -63,8 +63,27 @@ struct BatchState {
     void* plans = nullptr;   // per-plan task ranges
     int32_t* scratch = nullptr;
     unsigned long long* queue = nullptr;
-    unsigned long long* result = nullptr;  // 2*np
+    unsigned long long* result = nullptr;  // 3*np: count, overflow flag, busy clock ticks
 };
+
+// A reusable batch for repeated launches with changing plans and task
+// ranges (the serving loop): device buffers for 64 plans and a scratch
+// region for nbuf_cap slots per group are allocated once; each launch copies
+// descriptors and ranges from pinned staging memory and reads results back
+// into pinned memory (h_result, valid once the stream has passed the launch).
+struct BatchArena {
+    BatchState st;
+    LaunchCfg cfg;
+    int nbuf_cap = 0;
+    int64_t blocks_cap = 0;
+    GpPlanDesc* h_descs = nullptr;
+    void* h_plans = nullptr;
+    unsigned long long* h_result = nullptr;
+};
+gp_status arena_create(const DeviceGraph& g, int nbuf_cap, const LaunchCfg& cfg, BatchArena* a);
+gp_status arena_launch(const DeviceGraph& g, BatchArena* a, const GpPlanDesc* descs, const int64_t* offsets,
+                       const int64_t* counts, int np, hipStream_t stream);
+void arena_release(BatchArena* a);
 
 // Plan i covers roots[offset_i + t], t < count_i of its own root array;
 // offsets/counts null = every root. leafs: 1 or 3 per plan.

@@ -1,0 +1,435 @@
+// Serving loop (gp_server_*): pattern-count queries against resident graphs,
+// with continuous batching.
+//
+// A worker thread owns the device side. Queries are planned off the submit
+// path (plans are cached per graph and edge list); a query whose predicted
+// cost (the model of Section IV-C) exceeds the cap is rejected with
+// GP_ERR_BUDGET. Admitted queries join the active set of their graph as
+// batch slots (at most 64 per launch: the batched kernel keeps per-plan
+// counters in LDS) and HBM scratch allow.
+//
+// Work proceeds in iterations. Each iteration launches, per graph with active
+// queries, ONE batched persistent kernel over a slice of every active query's
+// remaining root tasks (graphs on their own streams, so their launches
+// overlap on the device). A query finishes when its last slice has run; new
+// queries join at the next iteration, so a short query arriving behind a long
+// one waits at most one iteration. Slices adapt: the kernel reports the wall
+// time its groups spent on each query, which gives each query's task rate,
+// and the next slice aims at an equal share of the target iteration time.
+// Counts are exact: slices partition each query's root tasks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "api_internal.hpp"
+
+namespace {
+
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+enum QState { Q_QUEUED = 0, Q_WAITING = 1, Q_ACTIVE = 2, Q_DONE = 3 };
+
+struct Query {
+    uint64_t ticket = 0;
+    int graph = 0;
+    int k = 0;
+    std::vector<int32_t> edges;
+    const gp_plan* plan = nullptr;  // owned by the plan cache
+    int64_t n_tasks = 0, progress = 0, slice = 0, last_slice = 0;
+    uint64_t count = 0;
+    bool ovf = false;
+    QState state = Q_QUEUED;
+    gp_status status = GP_OK;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    int iterations = 0;
+};
+
+}  // namespace
+
+struct gp_server {
+    std::vector<const gp_graph*> graphs;
+    gp_server_opts opts{};
+    int device = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Query*> inbox;
+    std::unordered_map<uint64_t, Query*> by_ticket;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    gp_status fatal = GP_OK;
+    gp_server_stats stats{};
+    std::thread worker;
+    // worker-owned
+    std::vector<gpint::BatchArena> arenas;
+    std::vector<hipStream_t> streams;
+    std::vector<std::deque<Query*>> waiting;
+    std::vector<std::vector<Query*>> active;
+    std::map<std::pair<int, std::vector<int32_t>>, gp_plan*> plan_cache;
+};
+
+namespace {
+
+void finish(gp_server* S, Query* q, gp_status st) {
+    std::lock_guard<std::mutex> lk(S->mu);
+    q->status = st;
+    q->state = Q_DONE;
+    q->t_done = now_s();
+    if (st == GP_OK) ++S->stats.completed;
+    else if (st == GP_ERR_BUDGET) ++S->stats.rejected;
+    else ++S->stats.failed;
+    S->cv_done.notify_all();
+}
+
+gp_status plan_query(gp_server* S, Query* q) {
+    std::vector<int32_t> key = q->edges;
+    // canonical key: each edge (min, max), sorted
+    std::vector<std::pair<int32_t, int32_t>> es;
+    for (size_t i = 0; i + 1 < key.size(); i += 2)
+        es.push_back({std::min(key[i], key[i + 1]), std::max(key[i], key[i + 1])});
+    std::sort(es.begin(), es.end());
+    key.clear();
+    key.push_back(q->k);
+    for (auto& e : es) {
+        key.push_back(e.first);
+        key.push_back(e.second);
+    }
+    auto ck = std::make_pair(q->graph, key);
+    auto it = S->plan_cache.find(ck);
+    if (it == S->plan_cache.end()) {
+        gp_stats st;
+        gp_graph_stats(S->graphs[q->graph], &st);
+        gp_plan_opts o;
+        gp_plan_opts_default(&o);
+        o.cost_cap = S->opts.cost_cap;
+        gp_plan* p = nullptr;
+        gp_status rc = gp_plan_create(q->edges.data(), q->k, (int32_t)(q->edges.size() / 2), &st, &o, &p);
+        if (rc != GP_OK) return rc;
+        it = S->plan_cache.emplace(ck, p).first;
+    }
+    q->plan = it->second;
+    q->n_tasks = gpint::root_task_count(S->graphs[q->graph]->dg, q->plan->desc);
+    return GP_OK;
+}
+
+gp_status ensure_arena(gp_server* S, int g, int nbuf) {
+    gpint::BatchArena& a = S->arenas[g];
+    if (a.st.queue && a.nbuf_cap >= nbuf) return GP_OK;
+    const int want = std::max(nbuf, std::max(a.nbuf_cap * 2, 4));
+    gpint::arena_release(&a);
+    gpint::LaunchCfg cfg;
+    cfg.group = S->opts.group;
+    cfg.leaf = S->opts.leaf_mode;
+    cfg.waves_per_cu = S->opts.waves_per_cu;
+    cfg.chunk = 4;
+    return gpint::arena_create(S->graphs[g]->dg, std::min(want, GP_DESC_MAX_BUILDS), cfg, &a);
+}
+
+void worker_main(gp_server* S) {
+    (void)hipSetDevice(S->device);
+    const int ng = (int)S->graphs.size();
+    S->arenas.assign(ng, gpint::BatchArena{});
+    S->streams.assign(ng, nullptr);
+    S->waiting.assign(ng, {});
+    S->active.assign(ng, {});
+    for (int g = 0; g < ng; ++g) {
+        if (hipStreamCreateWithFlags(&S->streams[g], hipStreamNonBlocking) != hipSuccess) {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->fatal = GP_ERR_HIP;
+        }
+    }
+    const double target = S->opts.target_ms / 1e3;
+    for (;;) {
+        std::vector<Query*> fresh;
+        bool idle = true;
+        for (int g = 0; g < ng; ++g)
+            if (!S->active[g].empty() || !S->waiting[g].empty()) idle = false;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            if (idle && S->inbox.empty()) {
+                if (S->stop) break;
+                S->cv_work.wait_for(lk, std::chrono::milliseconds(50));
+            }
+            fresh.assign(S->inbox.begin(), S->inbox.end());
+            S->inbox.clear();
+            if (S->fatal != GP_OK) {
+                // fail everything still queued
+                for (Query* q : fresh) {
+                    q->status = S->fatal;
+                    q->state = Q_DONE;
+                    q->t_done = now_s();
+                    ++S->stats.failed;
+                }
+                S->cv_done.notify_all();
+                if (S->stop) break;
+                continue;
+            }
+        }
+        for (Query* q : fresh) {
+            gp_status rc = plan_query(S, q);
+            if (rc != GP_OK) {
+                finish(S, q, rc);
+                continue;
+            }
+            if (q->n_tasks == 0) {
+                finish(S, q, GP_OK);
+                continue;
+            }
+            q->state = Q_WAITING;
+            S->waiting[q->graph].push_back(q);
+        }
+        // admission: free slots and scratch
+        bool any = false;
+        for (int g = 0; g < ng; ++g) {
+            while ((int)S->active[g].size() < S->opts.max_active && !S->waiting[g].empty()) {
+                Query* q = S->waiting[g].front();
+                if (ensure_arena(S, g, q->plan->desc.nbuf) != GP_OK) {
+                    S->waiting[g].pop_front();
+                    finish(S, q, GP_ERR_NOMEM);
+                    continue;
+                }
+                S->waiting[g].pop_front();
+                q->state = Q_ACTIVE;
+                q->t_admit = now_s();
+                q->slice = S->opts.initial_slice;
+                bool midflight = false;
+                for (Query* o : S->active[g])
+                    if (o->progress > 0) midflight = true;
+                S->active[g].push_back(q);
+                std::lock_guard<std::mutex> lk(S->mu);
+                if (midflight) ++S->stats.joined_midflight;
+                S->stats.max_batch = std::max<int64_t>(S->stats.max_batch, (int64_t)S->active[g].size());
+            }
+            if (!S->active[g].empty()) any = true;
+        }
+        if (!any) continue;
+
+        // one iteration: a batched launch per graph, all graphs overlapping
+        const double t0 = now_s();
+        std::vector<int> launched(ng, 0);
+        for (int g = 0; g < ng; ++g) {
+            auto& act = S->active[g];
+            if (act.empty()) continue;
+            std::vector<GpPlanDesc> descs(act.size());
+            std::vector<int64_t> offs(act.size()), cnts(act.size());
+            for (size_t i = 0; i < act.size(); ++i) {
+                descs[i] = act[i]->plan->desc;
+                offs[i] = act[i]->progress;
+                cnts[i] = std::min(act[i]->slice, act[i]->n_tasks - act[i]->progress);
+                act[i]->last_slice = cnts[i];
+            }
+            gp_status rc = gpint::arena_launch(S->graphs[g]->dg, &S->arenas[g], descs.data(), offs.data(),
+                                               cnts.data(), (int)act.size(), S->streams[g]);
+            if (rc != GP_OK) {
+                for (Query* q : act) finish(S, q, rc);
+                act.clear();
+                continue;
+            }
+            launched[g] = 1;
+        }
+        int n_active = 0;
+        for (int g = 0; g < ng; ++g) {
+            if (!launched[g]) continue;
+            if (hipStreamSynchronize(S->streams[g]) != hipSuccess) {
+                for (Query* q : S->active[g]) finish(S, q, GP_ERR_HIP);
+                S->active[g].clear();
+                launched[g] = 0;
+                continue;
+            }
+            n_active += (int)S->active[g].size();
+        }
+        const double T = std::max(1e-6, now_s() - t0);
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            ++S->stats.iterations;
+            S->stats.busy_seconds += T;
+            for (int g = 0; g < ng; ++g) S->stats.launches += launched[g];
+        }
+        // collect, retire finished queries, and size the next slices
+        const double fair = target / std::max(1, n_active);
+        for (int g = 0; g < ng; ++g) {
+            if (!launched[g]) continue;
+            auto& act = S->active[g];
+            const unsigned long long* r = S->arenas[g].h_result;
+            double busy_sum = 0;
+            for (size_t i = 0; i < act.size(); ++i) busy_sum += (double)r[3 * i + 2];
+            std::vector<Query*> keep;
+            for (size_t i = 0; i < act.size(); ++i) {
+                Query* q = act[i];
+                const uint64_t c = r[3 * i];
+                const uint64_t s = q->count + c;
+                if (s < q->count || r[3 * i + 1]) q->ovf = true;
+                q->count = s;
+                q->progress += q->last_slice;
+                ++q->iterations;
+                if (q->progress >= q->n_tasks) {
+                    finish(S, q, q->ovf ? GP_ERR_OVERFLOW : GP_OK);
+                    continue;
+                }
+                // this query's share of the iteration, from the groups' busy time
+                const double share = busy_sum > 0 ? (double)r[3 * i + 2] / busy_sum : 1.0 / act.size();
+                const double t_q = std::max(1e-6, T * share);
+                const double rate = (double)q->last_slice / t_q;
+                double next = rate * fair;
+                next = std::min(next, 4.0 * (double)q->last_slice + 1);
+                next = std::max(next, 64.0);
+                q->slice = (int64_t)std::min(next, 1e12);
+                keep.push_back(q);
+            }
+            act.swap(keep);
+        }
+    }
+    for (int g = 0; g < ng; ++g) {
+        if (S->streams[g]) {
+            (void)hipStreamSynchronize(S->streams[g]);
+            (void)hipStreamDestroy(S->streams[g]);
+        }
+        gpint::arena_release(&S->arenas[g]);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+void gp_server_opts_default(gp_server_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->max_active = 64;
+    o->target_ms = 25.0;
+    o->initial_slice = 8192;
+    o->group = 64;
+    o->leaf_mode = 3;
+    o->waves_per_cu = 16;
+}
+
+gp_status gp_server_create(const gp_graph* const* graphs, int32_t ng, const gp_server_opts* opts,
+                           gp_server** out) {
+    if (!graphs || ng < 1 || !out) return GP_ERR_ARG;
+    for (int i = 0; i < ng; ++i)
+        if (!graphs[i]) return GP_ERR_ARG;
+    gp_server_opts o;
+    gp_server_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.max_active <= 0) o.max_active = 64;
+    if (o.max_active > 64) return GP_ERR_ARG;
+    if (o.target_ms <= 0) o.target_ms = 25.0;
+    if (o.initial_slice <= 0) o.initial_slice = 8192;
+    if (o.group != 64 && o.group != 32) o.group = 64;
+    if (o.leaf_mode != 1 && o.leaf_mode != 3) o.leaf_mode = 3;
+    if (o.waves_per_cu <= 0 || o.waves_per_cu > 32) o.waves_per_cu = 16;
+    gp_server* S = new (std::nothrow) gp_server;
+    if (!S) return GP_ERR_NOMEM;
+    S->graphs.assign(graphs, graphs + ng);
+    S->opts = o;
+    S->device = graphs[0]->dg.device;
+    for (int i = 1; i < ng; ++i)
+        if (graphs[i]->dg.device != S->device) {
+            delete S;
+            return GP_ERR_ARG;
+        }
+    try {
+        S->worker = std::thread(worker_main, S);
+    } catch (...) {
+        delete S;
+        return GP_ERR_NOMEM;
+    }
+    *out = S;
+    return GP_OK;
+}
+
+gp_status gp_server_submit(gp_server* S, int32_t graph, const int32_t* edges, int32_t k, int32_t e,
+                           uint64_t* ticket) {
+    if (!S || !edges || !ticket || graph < 0 || graph >= (int32_t)S->graphs.size() || k < 2 ||
+        k > GP_MAX_K || e < 1 || e > k * (k - 1) / 2)
+        return GP_ERR_ARG;
+    Query* q = new (std::nothrow) Query;
+    if (!q) return GP_ERR_NOMEM;
+    q->graph = graph;
+    q->k = k;
+    q->edges.assign(edges, edges + 2 * e);
+    q->t_submit = now_s();
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->stop) {
+            delete q;
+            return GP_ERR_ARG;
+        }
+        q->ticket = S->next_ticket++;
+        S->by_ticket[q->ticket] = q;
+        S->inbox.push_back(q);
+        ++S->stats.submitted;
+        *ticket = q->ticket;
+    }
+    S->cv_work.notify_one();
+    return GP_OK;
+}
+
+gp_status gp_server_poll(gp_server* S, uint64_t ticket, int32_t* done, gp_status* status, uint64_t* count,
+                         double* latency_s) {
+    if (!S || !done) return GP_ERR_ARG;
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->by_ticket.find(ticket);
+    if (it == S->by_ticket.end()) return GP_ERR_ARG;
+    Query* q = it->second;
+    *done = q->state == Q_DONE ? 1 : 0;
+    if (*done) {
+        if (status) *status = q->status;
+        if (count) *count = q->count;
+        if (latency_s) *latency_s = q->t_done - q->t_submit;
+    }
+    return GP_OK;
+}
+
+gp_status gp_server_wait(gp_server* S, uint64_t ticket, double timeout_s, gp_status* status, uint64_t* count,
+                         double* latency_s) {
+    if (!S) return GP_ERR_ARG;
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->by_ticket.find(ticket);
+    if (it == S->by_ticket.end()) return GP_ERR_ARG;
+    Query* q = it->second;
+    auto pred = [&] { return q->state == Q_DONE; };
+    if (timeout_s > 0) {
+        if (!S->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), pred)) return GP_ERR_TIMEOUT;
+    } else {
+        S->cv_done.wait(lk, pred);
+    }
+    if (status) *status = q->status;
+    if (count) *count = q->count;
+    if (latency_s) *latency_s = q->t_done - q->t_submit;
+    return GP_OK;
+}
+
+gp_status gp_server_stats_get(gp_server* S, gp_server_stats* out) {
+    if (!S || !out) return GP_ERR_ARG;
+    std::lock_guard<std::mutex> lk(S->mu);
+    *out = S->stats;
+    return GP_OK;
+}
+
+void gp_server_destroy(gp_server* S) {
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+    }
+    S->cv_work.notify_all();
+    if (S->worker.joinable()) S->worker.join();
+    for (auto& kv : S->by_ticket) delete kv.second;
+    for (auto& kv : S->plan_cache) gp_free_plan(kv.second);
+    delete S;
+}
+
+}  // extern "C"

@@ -24,7 +24,7 @@ STATUS = {
     0: "GP_OK", -1: "GP_ERR_ARG", -2: "GP_ERR_CSR_UNSORTED", -3: "GP_ERR_CSR_ASYMMETRIC",
     -4: "GP_ERR_CSR_SELFLOOP", -5: "GP_ERR_CSR_DUPLICATE", -6: "GP_ERR_PATTERN",
     -7: "GP_ERR_NOMEM", -8: "GP_ERR_HIP", -9: "GP_ERR_OVERFLOW", -10: "GP_ERR_BUDGET",
-    -11: "GP_ERR_CSR_RANGE", -12: "GP_ERR_UNSUPPORTED",
+    -11: "GP_ERR_CSR_RANGE", -12: "GP_ERR_UNSUPPORTED", -13: "GP_ERR_TIMEOUT",
 }
 
 
@@ -60,6 +60,21 @@ class Launch(ctypes.Structure):
 class TuneOpts(ctypes.Structure):
     _fields_ = [("max_configs", ctypes.c_int32), ("sample_stride", ctypes.c_int32),
                 ("tune_launch", ctypes.c_int32), ("budget_seconds", ctypes.c_double)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("max_active", ctypes.c_int32), ("target_ms", ctypes.c_double),
+                ("cost_cap", ctypes.c_double), ("initial_slice", ctypes.c_int64),
+                ("group", ctypes.c_int32), ("leaf_mode", ctypes.c_int32),
+                ("waves_per_cu", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("iterations", ctypes.c_int64), ("launches", ctypes.c_int64),
+                ("busy_seconds", ctypes.c_double), ("joined_midflight", ctypes.c_int64),
+                ("max_batch", ctypes.c_int64)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -106,6 +121,15 @@ SIGNATURES = {
     "gp_batch_create": (_I32, [_P, _P, _I32, ctypes.POINTER(Launch), _P, ctypes.POINTER(_P)]),
     "gp_batch_run": (_I32, [_P, _P, _P]),
     "gp_free_batch": (None, [_P]),
+    "gp_server_opts_default": (None, [ctypes.POINTER(ServerOpts)]),
+    "gp_server_create": (_I32, [_P, _I32, ctypes.POINTER(ServerOpts), ctypes.POINTER(_P)]),
+    "gp_server_submit": (_I32, [_P, _I32, _P, _I32, _I32, ctypes.POINTER(ctypes.c_uint64)]),
+    "gp_server_poll": (_I32, [_P, ctypes.c_uint64, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                              ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double)]),
+    "gp_server_wait": (_I32, [_P, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(_I32),
+                              ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double)]),
+    "gp_server_stats_get": (_I32, [_P, ctypes.POINTER(ServerStats)]),
+    "gp_server_destroy": (None, [_P]),
     "gp_strerror": (ctypes.c_char_p, [_I32]),
     "gp_version": (ctypes.c_char_p, []),
 }
@@ -401,6 +425,68 @@ class Batch:
     def close(self) -> None:
         if self._h:
             _lib().gp_free_batch(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching query loop over resident graphs (see gp_server_create)."""
+
+    def __init__(self, graphs: Sequence[Graph], max_active: int = 0, target_ms: float = 0.0,
+                 cost_cap: float = 0.0, initial_slice: int = 0, group: int = 0, leaf_mode: int = 0,
+                 waves_per_cu: int = 0):
+        self.graphs = list(graphs)
+        o = ServerOpts()
+        _lib().gp_server_opts_default(ctypes.byref(o))
+        for name, val in (("max_active", max_active), ("target_ms", target_ms),
+                          ("cost_cap", cost_cap), ("initial_slice", initial_slice),
+                          ("group", group), ("leaf_mode", leaf_mode),
+                          ("waves_per_cu", waves_per_cu)):
+            if val:
+                setattr(o, name, val)
+        arr = (ctypes.c_void_p * len(graphs))(*[g.handle for g in graphs])
+        self._h = ctypes.c_void_p()
+        _check(_lib().gp_server_create(arr, len(graphs), ctypes.byref(o), ctypes.byref(self._h)),
+               "gp_server_create")
+
+    def submit(self, graph: int, k: int, edges) -> int:
+        e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1))
+        t = ctypes.c_uint64()
+        _check(_lib().gp_server_submit(self._h, graph, e.ctypes.data, k, e.size // 2, ctypes.byref(t)),
+               "gp_server_submit")
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while running, else (status, count, latency_s)."""
+        done = ctypes.c_int32()
+        st = ctypes.c_int32()
+        c = ctypes.c_uint64()
+        lat = ctypes.c_double()
+        _check(_lib().gp_server_poll(self._h, ticket, ctypes.byref(done), ctypes.byref(st),
+                                     ctypes.byref(c), ctypes.byref(lat)), "gp_server_poll")
+        return (st.value, c.value, lat.value) if done.value else None
+
+    def wait(self, ticket: int, timeout_s: float = 0.0):
+        st = ctypes.c_int32()
+        c = ctypes.c_uint64()
+        lat = ctypes.c_double()
+        _check(_lib().gp_server_wait(self._h, ticket, timeout_s, ctypes.byref(st), ctypes.byref(c),
+                                     ctypes.byref(lat)), "gp_server_wait")
+        return st.value, c.value, lat.value
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(_lib().gp_server_stats_get(self._h, ctypes.byref(s)), "gp_server_stats_get")
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def close(self) -> None:
+        if self._h:
+            _lib().gp_server_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

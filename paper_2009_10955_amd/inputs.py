@@ -269,3 +269,53 @@ def random_connected_pattern(k: int, rng: np.random.Generator, p: float = 0.5):
                     stack.append(y)
         if len(seen) == k:
             return edges
+
+
+# ---------------------------------------------------------------- query streams
+
+def connected_patterns(kmin: int = 3, kmax: int = 6) -> list:
+    """One representative (k, edges) per isomorphism class of connected graphs
+    on kmin..kmax vertices (2 + 6 + 21 + 112 = 141 classes for 3..6), in
+    order of k, then of the canonical edge mask. The representative is the
+    labelling whose edge mask (bit i = i-th pair of combinations(range(k), 2))
+    is smallest in its class."""
+    out = []
+    for k in range(kmin, kmax + 1):
+        pairs = list(itertools.combinations(range(k), 2))
+        idx = {p: i for i, p in enumerate(pairs)}
+        masks = np.arange(1 << len(pairs), dtype=np.int64)
+        canon = masks.copy()
+        for perm in itertools.permutations(range(k)):
+            img = np.zeros_like(masks)
+            for i, (a, b) in enumerate(pairs):
+                t = idx[tuple(sorted((perm[a], perm[b])))]
+                img |= ((masks >> i) & 1) << t
+            np.minimum(canon, img, out=canon)
+        for m in np.unique(canon):
+            edges = [pairs[i] for i in range(len(pairs)) if (int(m) >> i) & 1]
+            adj = [set() for _ in range(k)]
+            for a, b in edges:
+                adj[a].add(b)
+                adj[b].add(a)
+            seen, stack = {0}, [0]
+            while stack:
+                x = stack.pop()
+                for y in adj[x]:
+                    if y not in seen:
+                        seen.add(y)
+                        stack.append(y)
+            if len(seen) == k:
+                out.append((k, edges))
+    return out
+
+
+def poisson_stream(n: int = 2000, qps: float = 50.0, n_graphs: int = 3, n_patterns: int = 141,
+                   seed: int = 5) -> list:
+    """(arrival time in s, graph index, pattern index) for n queries with
+    exponential inter-arrival times of mean 1/qps; graph and pattern drawn
+    uniformly."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / qps, n))
+    gi = rng.integers(0, n_graphs, n)
+    pi = rng.integers(0, n_patterns, n)
+    return [(float(a), int(b), int(c)) for a, b, c in zip(t, gi, pi)]

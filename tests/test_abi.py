@@ -48,7 +48,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     """Sizes and field offsets of every struct in gp.h, as laid out by a C
     compiler, equal the ctypes mirrors in the binding."""
     structs = {"gp_stats": gp.Stats, "gp_plan_opts": gp.PlanOpts, "gp_plan_info": gp.PlanInfo,
-               "gp_launch": gp.Launch, "gp_tune_opts": gp.TuneOpts}
+               "gp_launch": gp.Launch, "gp_tune_opts": gp.TuneOpts,
+               "gp_server_opts": gp.ServerOpts, "gp_server_stats": gp.ServerStats}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gp.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')

@@ -325,3 +325,56 @@ def test_tuned_plans_count_the_same():
         # cached second call gives the same configuration
         again = plan.tuned(graph)
         assert again.order == tuned.order and again.restrictions == tuned.restrictions
+
+
+# ------------------------------------------------------------------ serving
+
+def test_serving_counts_equal_solo_counts():
+    """A Poisson stream of random connected 3-5-vertex patterns over two
+    resident graphs, with tiny slices so queries span several iterations and
+    newcomers join launches already under way: every count equals the solo
+    count (and the oracle's on the small graph)."""
+    from paper_2009_10955_amd import serve
+    g0 = I.config_graph(0)
+    g1 = I.er(300, 0.06, seed=13)
+    graphs = [gp.Graph.from_csr(g0), gp.Graph.from_csr(g1)]
+    pats = I.connected_patterns(3, 5)
+    stream = I.poisson_stream(150, 2000.0, 2, len(pats), seed=7)
+    srv = gp.Server(graphs, target_ms=2.0, initial_slice=32)
+    res = serve.run_stream(srv, stream, pats)
+    stats = srv.stats()
+    srv.close()
+    assert all(r["status"] == 0 for r in res)
+    solo = {}
+    for r in res:
+        key = (r["graph"], r["pattern"])
+        if key not in solo:
+            k, e = pats[r["pattern"]]
+            solo[key] = gp.count(graphs[r["graph"]], gp.Plan(k, e, stats=graphs[r["graph"]].stats()))
+        assert r["count"] == solo[key], key
+    for (gi, pi), c in list(solo.items())[:12]:
+        if gi == 1:
+            k, e = pats[pi]
+            assert c == O.count(g1, k, e)
+    assert stats["completed"] == len(stream)
+    assert stats["iterations"] > 1
+    assert stats["joined_midflight"] > 0
+    assert stats["max_batch"] > 1
+    summ = serve.summarise(res)
+    assert summ["completed"] == len(stream)
+
+
+def test_serving_rejects_over_budget_and_reports_overflow_free():
+    from paper_2009_10955_amd import serve
+    graphs = [gp.Graph.from_csr(I.config_graph(0))]
+    pats = [P["triangle"], P["5-clique"]]
+    srv = gp.Server(graphs, cost_cap=1.0)
+    t = [srv.submit(0, *p) for p in pats]
+    out = [srv.wait(x) for x in t]
+    srv.close()
+    assert [o[0] for o in out] == [-10, -10]
+    srv = gp.Server(graphs)
+    out = [srv.wait(srv.submit(0, *p)) for p in pats]
+    srv.close()
+    assert [o[0] for o in out] == [0, 0]
+    assert out[0][1] == 157

@@ -23,6 +23,9 @@ Contents and what each follows:
 * ``phase1_ok``, ``efficient_schedules`` -- the 2-phase schedule filter
   (Section IV-B).
 * ``model_cost`` -- the nested performance model (Section IV-C).
+* ``alg2_components``, ``alg2_cardinality``, ``iep_injective_tuples``,
+  ``iep_count`` -- counting with the Inclusion-Exclusion Principle
+  (Section IV-D, Algorithm 2).
 * ``relabel_by_degree`` -- vertex relabelling by descending degree (ties by
   ascending id), the layout the GPU library uses; counts are invariant under it.
 
@@ -42,6 +45,14 @@ Readings of the paper used here (the paper is silent or garbled on these):
   with * |Aut| == without.
 * Phase 2 with no satisfying order: use the largest k' <= alpha(P) for which
   some Phase-1 order ends in k' pairwise non-adjacent vertices.
+* IEP over-count: Section IV-D divides by the number of automorphisms that
+  no_conflict does not eliminate with the remaining restrictions. That number
+  is not the multiplicity in general (for K4 plus a pendant path with one kept
+  restriction it is 5 while every embedding is counted 3 times, so the
+  quotient is not even an integer). The division here uses the exact
+  multiplicity: how many relative orders of each Aut-orbit obey the kept
+  restrictions; a configuration for which that differs between orbits is not
+  counted with IEP.
 * Model: ``tri_cnt`` is the number of ordered triangles (6 x unordered), so
   ``tri_cnt / (2|E|)`` is the mean common-neighborhood size of an edge. A
   restriction is charged to the loop of its later-bound vertex. The loop of
@@ -400,3 +411,147 @@ def model_cost(k: int, edges, order: Sequence[int], res_set, n_v: float, n_e: fl
     for i in range(k - 2, -1, -1):
         cost = loop[i] * (1.0 - f[i]) * (c[i] + cost)
     return cost
+
+
+# ------------------------------------- inclusion-exclusion counting (Section IV-D)
+
+def alg2_components(k: int, pairs) -> list[list[int]]:
+    """Algorithm 2, lines 1-4: the undirected graph on k set indices with one
+    edge per (i, j) pair, split into connected components (each sorted)."""
+    parent = list(range(k))
+
+    def find(x):
+        while parent[x] != x:
+            parent[x] = parent[parent[x]]
+            x = parent[x]
+        return x
+
+    for a, b in pairs:
+        ra, rb = find(a), find(b)
+        if ra != rb:
+            parent[ra] = rb
+    comps: dict = {}
+    for v in range(k):
+        comps.setdefault(find(v), []).append(v)
+    return sorted(sorted(c) for c in comps.values())
+
+
+def alg2_cardinality(sets, pairs) -> int:
+    """Algorithm 2: |A_{i1,j1} ∩ ... ∩ A_{im,jm}| = product over the components
+    of the pair graph of the size of the intersection of their sets."""
+    card = 1
+    for comp in alg2_components(len(sets), pairs):
+        inter = set(sets[comp[0]])
+        for v in comp[1:]:
+            inter &= set(sets[v])
+        card *= len(inter)
+    return card
+
+
+def iep_injective_tuples(sets) -> int:
+    """|S_IEP|: tuples (e_1..e_k), e_i in S_i, all distinct, by the
+    inclusion-exclusion sum over subsets of the pairs (i<j) of
+    (-1)^|subset| |∩ A_{i,j}| (Section IV-D), each term by Algorithm 2."""
+    k = len(sets)
+    pairs = list(itertools.combinations(range(k), 2))
+    total = 0
+    for r in range(len(pairs) + 1):
+        for sub in itertools.combinations(pairs, r):
+            total += (-1) ** r * alg2_cardinality(sets, sub)
+    return total
+
+
+def iep_kept(k: int, order, res_set, n_inner: int) -> list:
+    """The restrictions that remain with IEP: those checked in the outer
+    loops (the later-bound vertex is not among the last n_inner)."""
+    pos = {u: i for i, u in enumerate(order)}
+    return [(a, b) for a, b in res_set if max(pos[a], pos[b]) < k - n_inner]
+
+
+def iep_divisor_paper(k: int, edges, order, res_set, n_inner: int) -> int:
+    """x as Section IV-D computes it: the automorphisms that no_conflict does
+    not eliminate with the remaining restrictions."""
+    kept = iep_kept(k, order, res_set, n_inner)
+    return sum(1 for p in automorphisms(k, edges) if no_conflict(p, kept))
+
+
+def orbit_multiplicities(k: int, edges, kept) -> set:
+    """For every Aut-orbit of the k! relative orders, how many of its members
+    obey all pairs in kept. IEP over-counts each embedding by exactly this
+    number, so it is usable only when the set has one element."""
+    auts = automorphisms(k, edges)
+    seen: set = set()
+    out: set = set()
+    for r in itertools.permutations(range(k)):
+        orbit = frozenset(tuple(r[p[v]] for v in range(k)) for p in auts)
+        if orbit in seen:
+            continue
+        seen.add(orbit)
+        out.add(sum(all(x[a] > x[b] for a, b in kept) for x in orbit))
+    return out
+
+
+def iep_divisor(k: int, edges, order, res_set, n_inner: int) -> int:
+    """The exact over-count of IEP counting: the number of relative orders in
+    each Aut-orbit that obey the remaining restrictions (every maps' orbit of
+    one embedding has this many members counted). Raises if it is not the
+    same for every orbit, which happens for some configurations (then IEP
+    does not apply to them). Section IV-D's no_conflict count
+    (iep_divisor_paper) equals it only in some cases."""
+    m = orbit_multiplicities(k, edges, iep_kept(k, order, res_set, n_inner))
+    if len(m) != 1:
+        raise ValueError(f"IEP over-count is not uniform over orbits: {sorted(m)}")
+    return m.pop()
+
+
+def iep_count(g, k: int, edges, order, res_set, n_inner: int) -> int:
+    """Embeddings counted the IEP way of Section IV-D (small graphs only):
+    enumerate the outer k - n_inner vertices of the schedule under the
+    restrictions checked in those loops, take for each inner vertex its
+    candidate set (the common neighbors of its pattern neighbors' images,
+    minus the outer images), count the distinct-entry tuples by
+    inclusion-exclusion, and divide the total by the over-count (the exact
+    per-orbit multiplicity, see iep_divisor)."""
+    adj = _adj(k, edges)
+    inner = list(order[k - n_inner:])
+    outer = list(order[:k - n_inner])
+    for a, b in itertools.combinations(inner, 2):
+        if adj[a][b]:
+            raise ValueError("inner vertices must be pairwise non-adjacent")
+    kept = iep_kept(k, order, res_set, n_inner)
+    x = iep_divisor(k, edges, order, res_set, n_inner)
+    n = g.row_ptr.shape[0] - 1
+    nbr = [set(g.col[g.row_ptr[v]:g.row_ptr[v + 1]].tolist()) for v in range(n)]
+    total = 0
+    img: dict = {}
+
+    def rec(t):
+        nonlocal total
+        if t == len(outer):
+            used = set(img.values())
+            sets = []
+            for u in inner:
+                cand = None
+                for w in range(k):
+                    if adj[u][w]:
+                        s = nbr[img[w]]
+                        cand = set(s) if cand is None else cand & s
+                cand = (cand if cand is not None else set(range(n))) - used
+                sets.append(cand)
+            total += iep_injective_tuples(sets)
+            return
+        u = outer[t]
+        for x in range(n):
+            if x in img.values():
+                continue
+            if any(adj[u][w] and w in img and x not in nbr[img[w]] for w in range(k)):
+                continue
+            img[u] = x
+            if all(img[a] > img[b] for a, b in kept if a in img and b in img):
+                rec(t + 1)
+            del img[u]
+
+    rec(0)
+    if total % x:
+        raise AssertionError("IEP total not divisible by x")
+    return total // x

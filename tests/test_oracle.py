@@ -317,3 +317,61 @@ def test_model_prefers_hoisted_intersections_and_filters():
     a = O.model_cost(k, e, (0, 1, 2, 3, 4), [(0, 1)], n_v, n_e, tri)
     b = O.model_cost(k, e, (0, 1, 2, 3, 4), [], n_v, n_e, tri)
     assert a < b
+
+
+# ------------------------------------------------------- IEP (Section IV-D)
+
+def test_alg2_worked_example():
+    gd = GOLDEN["alg2_components"]
+    pairs = [(a - 1, b - 1) for a, b in gd["pairs"]]
+    comps = O.alg2_components(gd["k"], pairs)
+    assert [[v + 1 for v in c] for c in comps] == gd["components"]
+    sets = [{1, 2, 3}, {2, 3, 4}, {3, 4}, {5, 6, 7}, {6, 7}, {8, 9}]
+    # |S1 ∩ S2 ∩ S3| * |S4 ∩ S5| * |S6|
+    assert O.alg2_cardinality(sets, pairs) == 1 * 2 * 2
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_iep_sum_counts_distinct_tuples(seed):
+    rng = np.random.default_rng(seed)
+    for k in (1, 2, 3, 4):
+        sets = [set(rng.choice(9, size=int(rng.integers(0, 7)), replace=False).tolist())
+                for _ in range(k)]
+        brute = sum(1 for t in itertools.product(*[sorted(s) for s in sets]) if len(set(t)) == k)
+        assert O.iep_injective_tuples(sets) == brute
+
+
+@pytest.mark.parametrize("pname", ["house", "diamond", "tailed-triangle", "4-path", "3-star",
+                                   "6-cycle-chord", "k4-path"])
+def test_iep_count_equals_plain_count(pname):
+    """Every configuration with a uniform over-count gives the plain count."""
+    k, e = P[pname]
+    g = I.er(13, 0.45, seed=3)
+    want = O.count(g, k, e)
+    scheds, keff = O.efficient_schedules(k, e)
+    sets = O.restriction_sets(k, e)
+    n_ok = 0
+    for o in scheds[:5]:
+        for r in sets[:6]:
+            for ni in range(2, keff + 1):
+                try:
+                    O.iep_divisor(k, e, o, r, ni)
+                except ValueError:
+                    continue
+                assert O.iep_count(g, k, e, o, r, ni) == want, (o, sorted(r), ni)
+                n_ok += 1
+    assert n_ok > 0
+
+
+def test_iep_paper_divisor_differs_from_the_multiplicity():
+    """K4 plus a pendant path, schedule (0,1,3,4,2,5), set {0>1, 0>2, 1>2}:
+    the only restriction checked outside the last two loops is 0>1. Every
+    embedding is then counted 3 times (half of the 6 orders of K4's
+    vertices 0,1,2 obey 0>1), but no_conflict leaves 5 automorphisms."""
+    k, e = P["k4-path"]
+    order = (0, 1, 3, 4, 2, 5)
+    r = [(0, 1), (0, 2), (1, 2)]
+    assert O.iep_divisor_paper(k, e, order, r, 2) == 5
+    assert O.iep_divisor(k, e, order, r, 2) == 3
+    g = I.er(12, 0.5, seed=4)
+    assert O.iep_count(g, k, e, order, r, 2) == O.count(g, k, e)

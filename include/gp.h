@@ -53,7 +53,8 @@ enum {
     GP_ERR_BUDGET = -10,         /* predicted cost above the caller's cap */
     GP_ERR_CSR_RANGE = -11,      /* a column index outside [0, n) or row_ptr[0] != 0 */
     GP_ERR_UNSUPPORTED = -12,    /* option or shape not built into this library */
-    GP_ERR_TIMEOUT = -13         /* gp_server_wait: the query did not finish in time */
+    GP_ERR_TIMEOUT = -13,        /* gp_server_wait: the query did not finish in time */
+    GP_ERR_INTERNAL = -14        /* an internal consistency check failed (a bug) */
 };
 
 #define GP_MAX_K 8
@@ -143,6 +144,9 @@ typedef struct {
     double cost_cap;             /* if > 0: GP_ERR_BUDGET when the best predicted cost exceeds it */
     double max_seconds;          /* Algorithm 1 stops exploring after this long once a valid set
                                     exists (0 = 20 s) */
+    int32_t iep;                 /* 1: count the last two levels with inclusion-exclusion
+                                    (Section IV-D) when a configuration allows it; see
+                                    gp_plan_info.iep */
 } gp_plan_opts;
 
 /* Fill opts with the defaults (nothing forced, no cap). */
@@ -179,6 +183,13 @@ typedef struct {
     int32_t set_index;         /* index of the chosen set in emission order (-1 if forced pairs) */
     double plan_seconds;       /* host wall time of gp_plan_create (plus gp_plan_tune) */
     int32_t tuned;             /* 1 if the configuration and launch were measured by gp_plan_tune */
+    int32_t iep;               /* 1 if the last two levels are counted with inclusion-exclusion:
+                                  the best-ranked configuration whose last two schedule vertices
+                                  are non-adjacent and over which IEP counts every embedding the
+                                  same number of times, iep_div (restrictions between the two
+                                  are dropped, and if needed all checked in them); the kernel
+                                  divides its total by iep_div */
+    int32_t iep_div;
     int32_t n_measured;        /* configurations timed by gp_plan_tune */
     gp_launch launch;          /* launch shape used when the caller passes none */
 } gp_plan_info;
@@ -238,7 +249,8 @@ gp_status gp_count(const gp_graph* g, const gp_plan* p, const gp_launch* launch,
                    uint64_t* out);
 
 /* As gp_count, without host synchronisation: dev_out (device memory, 2
- * uint64) receives {count, overflow flag} when the stream reaches it. */
+ * uint64) receives {count, flags} when the stream reaches it; flag bit 0:
+ * overflow, bit 1: internal check failed. */
 gp_status gp_count_async(const gp_graph* g, const gp_plan* p, const gp_launch* launch,
                          void* stream, uint64_t* dev_out);
 
@@ -246,8 +258,9 @@ gp_status gp_count_async(const gp_graph* g, const gp_plan* p, const gp_launch* l
  * Per-root counts, for verification: dev_per_root (device memory, one uint64
  * per directed CSR entry of the device layout, nnz entries) receives, at the
  * index of the layout entry (v0, v1), the number of embeddings whose first
- * two schedule levels map to v0 and v1 (zero where the entry is not a root).
- * Blocking; *out receives the total.
+ * two schedule levels map to v0 and v1 (zero where the entry is not a root;
+ * for an IEP plan, that number times iep_div). Blocking; *out receives the
+ * total.
  */
 gp_status gp_count_per_root(const gp_graph* g, const gp_plan* p, const gp_launch* launch,
                             void* stream, uint64_t* dev_per_root, uint64_t* out);
@@ -270,7 +283,8 @@ gp_status gp_count_traffic(const gp_graph* g, const gp_plan* p, const gp_launch*
  * edges, handed out in chunks from one atomic queue, so plans of uneven cost
  * fill each other's tails (Section IV-E's task partitioning across patterns).
  * The lanes per group (64 or 32) and leaf mode (1, or 3 where the plan allows
- * it) come from `launch`, else from the first plan's launch. out[i] = count of plans[i]
+ * it) come from `launch`, else from the first plan's launch. Plans counted
+ * with IEP are not supported here (GP_ERR_UNSUPPORTED). out[i] = count of plans[i]
  * (host memory). Blocking. Counts equal gp_count's bit for bit.
  */
 gp_status gp_count_batch(const gp_graph* g, const gp_plan* const* plans, int32_t np,

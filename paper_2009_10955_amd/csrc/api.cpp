@@ -74,6 +74,7 @@ gp_status count_to_host(const gp_graph* g, const GpPlanDesc& d, const gpint::Lau
     (void)hipFreeAsync(res, s);
     if (hipStreamSynchronize(s) != hipSuccess && st == GP_OK) st = GP_ERR_HIP;
     if (st != GP_OK) return st;
+    if (h[1] & 2) return GP_ERR_INTERNAL;
     if (h[1]) return GP_ERR_OVERFLOW;
     *out = h[0];
     if (alg_bytes) *alg_bytes = h[2];
@@ -102,6 +103,7 @@ const char* gp_strerror(gp_status s) {
         case GP_ERR_CSR_RANGE: return "CSR index out of range";
         case GP_ERR_UNSUPPORTED: return "unsupported option or shape";
         case GP_ERR_TIMEOUT: return "timed out";
+        case GP_ERR_INTERNAL: return "internal consistency check failed";
         default: return "unknown status";
     }
 }
@@ -334,6 +336,8 @@ gp_status gp_plan_create(const int32_t* edges, int32_t k, int32_t e, const gp_st
     int best_cuts = -1;
     size_t bo = 0, bs = 0;
     bool have = false;
+    gp::Rel best_kept = 0;
+    int best_div = 0;
     for (size_t i = 0; i < cand_orders.size(); ++i) {
         for (size_t j = 0; j < cand_sets.size(); ++j) {
             double c = gp::model_cost(pat, cand_orders[i], cand_sets[j], gs);
@@ -347,14 +351,40 @@ gp_status gp_plan_create(const int32_t* edges, int32_t k, int32_t e, const gp_st
                 else if (c > best + tol) better = false;
                 else better = cuts > best_cuts;  // schedules/sets visited in order: earlier wins ties
             }
+            gp::Rel kept = 0;
+            int div = 0;
+            if (better && o.iep) {
+                // IEP: only configurations whose over-count is the same for every embedding
+                div = gp::iep_setup(pat, auts, cand_orders[i], cand_sets[j], &kept);
+                if (div <= 0) better = false;
+            }
             if (better) {
                 best = c;
                 best_cuts = cuts;
                 bo = i;
                 bs = j;
+                best_kept = kept;
+                best_div = div;
                 have = true;
             }
         }
+    }
+    if (o.iep && !have) {
+        // no configuration can be counted with IEP: plain enumeration
+        o.iep = 0;
+        for (size_t i = 0; i < cand_orders.size(); ++i)
+            for (size_t j = 0; j < cand_sets.size(); ++j) {
+                double c = gp::model_cost(pat, cand_orders[i], cand_sets[j], gs);
+                int cuts = gp::upper_cuts(cand_orders[i], cand_sets[j], k);
+                double tol = 1e-9 * std::max(std::abs(best), std::abs(c));
+                if (!have || c < best - tol || (c <= best + tol && cuts > best_cuts)) {
+                    best = c;
+                    best_cuts = cuts;
+                    bo = i;
+                    bs = j;
+                    have = true;
+                }
+            }
     }
     if (o.cost_cap > 0 && best > o.cost_cap) {
         delete p;
@@ -362,7 +392,7 @@ gp_status gp_plan_create(const int32_t* edges, int32_t k, int32_t e, const gp_st
     }
     p->order = cand_orders[bo];
     p->set = cand_sets[bs];
-    rc = gp::compile_plan(pat, p->order, p->set, &p->desc);
+    rc = gp::compile_plan(pat, p->order, p->set, &p->desc, best_kept, best_div);
     if (rc) {
         delete p;
         return rc;
@@ -390,6 +420,8 @@ gp_status gp_plan_create(const int32_t* edges, int32_t k, int32_t e, const gp_st
     in.set_index = cand_index[bs];
     in.plan_seconds = now_seconds() - t0;
     in.tuned = 0;
+    in.iep = p->desc.iep;
+    in.iep_div = p->desc.iep_div;
     *out = p;
     return GP_OK;
 }
@@ -492,6 +524,7 @@ gp_status batch_inputs(const gp_plan* const* plans, int32_t np, std::vector<GpPl
     leafs->resize(np);
     for (int i = 0; i < np; ++i) {
         if (!plans[i]) return GP_ERR_ARG;
+        if (plans[i]->desc.iep) return GP_ERR_UNSUPPORTED;  // the batched kernel enumerates every level
         (*descs)[i] = plans[i]->desc;
         (*leafs)[i] = plans[i]->launch.leaf;
     }

@@ -8,13 +8,13 @@
 #include "count_kernel.hpp"
 
 namespace gpcount {
-KernelFn pick_kernel_k2(int group, int leaf, int mode);
-KernelFn pick_kernel_k3(int group, int leaf, int mode);
-KernelFn pick_kernel_k4(int group, int leaf, int mode);
-KernelFn pick_kernel_k5(int group, int leaf, int mode);
-KernelFn pick_kernel_k6(int group, int leaf, int mode);
-KernelFn pick_kernel_k7(int group, int leaf, int mode);
-KernelFn pick_kernel_k8(int group, int leaf, int mode);
+KernelFn pick_kernel_k2(int group, int leaf, int mode, bool iep);
+KernelFn pick_kernel_k3(int group, int leaf, int mode, bool iep);
+KernelFn pick_kernel_k4(int group, int leaf, int mode, bool iep);
+KernelFn pick_kernel_k5(int group, int leaf, int mode, bool iep);
+KernelFn pick_kernel_k6(int group, int leaf, int mode, bool iep);
+KernelFn pick_kernel_k7(int group, int leaf, int mode, bool iep);
+KernelFn pick_kernel_k8(int group, int leaf, int mode, bool iep);
 #define GP_DECL_BATCH(g, k, l) BatchFn batch_kernel_g##g##_k##k##_l##l();
 GP_DECL_BATCH(64, 5, 1) GP_DECL_BATCH(64, 6, 1) GP_DECL_BATCH(64, 8, 1)
 GP_DECL_BATCH(32, 5, 1) GP_DECL_BATCH(32, 6, 1) GP_DECL_BATCH(32, 8, 1)
@@ -38,16 +38,25 @@ __global__ void init_counters(unsigned long long* p, int n) {
     if (i < n) p[i] = 0;
 }
 
-KernelFn pick_kernel(int k, int group, int leaf, int mode) {
+KernelFn pick_kernel(int k, int group, int leaf, int mode, bool iep) {
     switch (k) {
-        case 2: return pick_kernel_k2(group, leaf, mode);
-        case 3: return pick_kernel_k3(group, leaf, mode);
-        case 4: return pick_kernel_k4(group, leaf, mode);
-        case 5: return pick_kernel_k5(group, leaf, mode);
-        case 6: return pick_kernel_k6(group, leaf, mode);
-        case 7: return pick_kernel_k7(group, leaf, mode);
-        case 8: return pick_kernel_k8(group, leaf, mode);
+        case 2: return pick_kernel_k2(group, leaf, mode, iep);
+        case 3: return pick_kernel_k3(group, leaf, mode, iep);
+        case 4: return pick_kernel_k4(group, leaf, mode, iep);
+        case 5: return pick_kernel_k5(group, leaf, mode, iep);
+        case 6: return pick_kernel_k6(group, leaf, mode, iep);
+        case 7: return pick_kernel_k7(group, leaf, mode, iep);
+        case 8: return pick_kernel_k8(group, leaf, mode, iep);
         default: return nullptr;
+    }
+}
+
+// Divide an IEP total by its over-count; flag 2 if it does not divide.
+__global__ void iep_divide(unsigned long long* result, unsigned long long div) {
+    if (threadIdx.x == 0 && div > 0) {
+        const unsigned long long t = result[0];
+        if (t % div) result[1] |= 2ull;
+        result[0] = t / div;
     }
 }
 }  // namespace
@@ -98,7 +107,9 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
     if (cfg.leaf < 1 || cfg.leaf > 3) return GP_ERR_ARG;
     if (cfg.waves_per_cu < 1 || cfg.waves_per_cu > 32 || cfg.chunk < 1) return GP_ERR_ARG;
     const int mode = account ? MODE_ACCOUNT : (per_root ? MODE_PER_ROOT : MODE_PLAIN);
-    KernelFn fn = pick_kernel(d.k, cfg.group, cfg.leaf, mode);
+    const bool iep = d.iep != 0;
+    const int group = iep ? (cfg.group >= 64 ? 64 : 32) : cfg.group;  // IEP kernels: 64 or 32 lanes
+    KernelFn fn = pick_kernel(d.k, group, cfg.leaf, mode, iep);
     if (!fn) return GP_ERR_UNSUPPORTED;
 
     int64_t all_roots = 0;
@@ -110,7 +121,7 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
 
     const int waves_per_block = kBlock / 64;
     int64_t blocks = std::max<int64_t>(1, (int64_t)g.num_cus * cfg.waves_per_cu / waves_per_block);
-    const int64_t groups_per_block = kBlock / cfg.group;
+    const int64_t groups_per_block = kBlock / group;
     int64_t cap = std::max<int64_t>(1, g.deg2);
     // keep scratch within a fixed budget: fewer resident groups if needed
     const int64_t budget = int64_t(16) << 30;
@@ -154,6 +165,8 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
     a.per_root = per_root;
     a.chunk = cfg.chunk;
     if (n_roots > 0) hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kBlock), 0, stream, d, a);
+    if (iep)
+        hipLaunchKernelGGL(iep_divide, dim3(1), dim3(64), 0, stream, result_dev, (unsigned long long)d.iep_div);
     hipError_t le = hipGetLastError();
     if (scratch) (void)hipFreeAsync(scratch, stream);
     (void)hipFreeAsync(queue, stream);

@@ -56,7 +56,7 @@ __device__ __forceinline__ void batch_roots(const GpPlanDesc& d, const Ctx<G>& c
             v[0] = e.x;
             v[1] = e.y;
             run_builds<K, G, MODE_PLAIN>(d, c, 1, v);
-            search<K, 2, G, LEAF, MODE_PLAIN>(d, c, v, acc, ovf);
+            search<K, 2, G, LEAF, MODE_PLAIN, false>(d, c, v, acc, ovf);
         }
     }
 }

@@ -9,12 +9,12 @@
 namespace gpcount {
 
 namespace {
-template <int K, int G, int LEAF>
+template <int K, int G, int LEAF, bool IEP = false>
 KernelFn pick_mode(int mode) {
     switch (mode) {
-        case MODE_PLAIN: return count_kernel<K, G, LEAF, MODE_PLAIN>;
-        case MODE_PER_ROOT: return count_kernel<K, G, LEAF, MODE_PER_ROOT>;
-        case MODE_ACCOUNT: return count_kernel<K, G, LEAF, MODE_ACCOUNT>;
+        case MODE_PLAIN: return count_kernel<K, G, LEAF, MODE_PLAIN, IEP>;
+        case MODE_PER_ROOT: return count_kernel<K, G, LEAF, MODE_PER_ROOT, IEP>;
+        case MODE_ACCOUNT: return count_kernel<K, G, LEAF, MODE_ACCOUNT, IEP>;
         default: return nullptr;
     }
 }
@@ -30,7 +30,16 @@ KernelFn pick_leaf(int leaf, int mode) {
 #define GP_CAT2(a, b) a##b
 #define GP_CAT(a, b) GP_CAT2(a, b)
 
-KernelFn GP_CAT(pick_kernel_k, GP_INST_K)(int group, int leaf, int mode) {
+KernelFn GP_CAT(pick_kernel_k, GP_INST_K)(int group, int leaf, int mode, bool iep) {
+    if (iep) {
+        // IEP stops at level k-3, so the leaf mode does not apply
+        if constexpr (GP_INST_K >= 4) {
+            return group == 64 ? pick_mode<GP_INST_K, 64, 1, true>(mode)
+                               : pick_mode<GP_INST_K, 32, 1, true>(mode);
+        } else {
+            return nullptr;
+        }
+    }
     switch (group) {
         case 64: return pick_leaf<GP_INST_K, 64>(leaf, mode);
         case 32: return pick_leaf<GP_INST_K, 32>(leaf, mode);

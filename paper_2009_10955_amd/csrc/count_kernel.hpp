@@ -296,6 +296,70 @@ __device__ __forceinline__ uint32_t leaf_group(const GpPlanDesc& d, const Ctx<G>
     return intersect_count_group<G>(c.g, A, B, [&](int32_t x) { return inj_hit<K>(inj, v, x); });
 }
 
+// Counting with inclusion-exclusion over the last two levels (Section IV-D,
+// k = 2 inner sets): for bound values v[0..K-3], the number of pairs (y, z)
+// with y in S1, z in S2, y != z, where S1, S2 are the candidate sets of
+// levels K-2 and K-1 (outer images removed): |S1| |S2| - |S1 & S2|. By one
+// lane.
+template <int K, int G, int MODE>
+__device__ __forceinline__ uint64_t iep_leaf_serial(const GpPlanDesc& d, const Ctx<G>& c,
+                                                    const int32_t (&v)[K]) {
+    const GpLevel& l1 = d.lv[K - 2];
+    const GpLevel& l2 = d.lv[K - 1];
+    int32_t lo1, hi1, lo2, hi2;
+    bounds<K>(l1.hi_src, l1.lo_src, v, lo1, hi1);
+    bounds<K>(l2.hi_src, l2.lo_src, v, lo2, hi2);
+    const Set S1 = l1.list >= 0 ? c.nbr(pick<K>(v, l1.list)) : c.buf(l1.buf);
+    const Set S2 = l2.list >= 0 ? c.nbr(pick<K>(v, l2.list)) : c.buf(l2.buf);
+    const Set A = trim(S1, lo1, hi1);
+    const Set B = trim(S2, lo2, hi2);
+    uint64_t c1 = (uint64_t)A.n, c2 = (uint64_t)B.n;
+#pragma unroll
+    for (int j = 0; j < K - 2; ++j) {
+        const int32_t y = v[j];
+        if (((l1.inj >> j) & 1u) && y >= lo1 && y < hi1 && member(A, y)) --c1;
+        if (((l2.inj >> j) & 1u) && y >= lo2 && y < hi2 && member(B, y)) --c2;
+    }
+    const int32_t lo = max(lo1, lo2), hi = min(hi1, hi2);
+    const Set A12 = trim(A, lo, hi), B12 = trim(B, lo, hi);
+    const uint32_t inj = (uint32_t)l1.inj | (uint32_t)l2.inj;
+    const uint32_t c12 = intersect_count_serial(A12, B12, [&](int32_t x) { return inj_hit<K>(inj, v, x); });
+    if constexpr (MODE == MODE_ACCOUNT)
+        *c.bytes += 2 * probe_bytes(S1.n) + 2 * probe_bytes(S2.n) + 4ull * (uint64_t)(A12.n + B12.n);
+    return c1 * c2 - c12;
+}
+
+// The same computed by the whole group (same value in every lane).
+template <int K, int G, int MODE>
+__device__ __forceinline__ uint64_t iep_leaf_group(const GpPlanDesc& d, const Ctx<G>& c,
+                                                   const int32_t (&v)[K]) {
+    const GpLevel& l1 = d.lv[K - 2];
+    const GpLevel& l2 = d.lv[K - 1];
+    int32_t lo1, hi1, lo2, hi2;
+    bounds<K>(l1.hi_src, l1.lo_src, v, lo1, hi1);
+    bounds<K>(l2.hi_src, l2.lo_src, v, lo2, hi2);
+    const Set S1 = l1.list >= 0 ? c.nbr_u(pick<K>(v, l1.list)) : c.buf_u(l1.buf);
+    const Set S2 = l2.list >= 0 ? c.nbr_u(pick<K>(v, l2.list)) : c.buf_u(l2.buf);
+    const Set A = trim_u<G>(S1, lo1, hi1);
+    const Set B = trim_u<G>(S2, lo2, hi2);
+    uint64_t c1 = (uint64_t)A.n, c2 = (uint64_t)B.n;
+#pragma unroll
+    for (int j = 0; j < K - 2; ++j) {
+        const int32_t y = v[j];
+        if (((l1.inj >> j) & 1u) && y >= lo1 && y < hi1 && member(A, y)) --c1;
+        if (((l2.inj >> j) & 1u) && y >= lo2 && y < hi2 && member(B, y)) --c2;
+    }
+    const int32_t lo = max(lo1, lo2), hi = min(hi1, hi2);
+    const Set A12 = trim_u<G>(A, lo, hi), B12 = trim_u<G>(B, lo, hi);
+    const uint32_t inj = (uint32_t)l1.inj | (uint32_t)l2.inj;
+    const uint32_t c12 =
+        intersect_count_group<G>(c.g, A12, B12, [&](int32_t x) { return inj_hit<K>(inj, v, x); });
+    if constexpr (MODE == MODE_ACCOUNT)
+        if (c.g.gl == 0)
+            *c.bytes += 2 * probe_bytes(S1.n) + 2 * probe_bytes(S2.n) + 4ull * (uint64_t)(A12.n + B12.n);
+    return c1 * c2 - c12;
+}
+
 // The last two enumerated levels flattened into one load-balanced batch
 // (leaf mode 3): each lane takes a candidate x of level K-3 and cuts its
 // level-(K-2) candidate list; a group prefix sum over the list lengths then
@@ -364,7 +428,7 @@ __device__ void flat_leaf(const GpPlanDesc& d, const Ctx<G>& c, const int32_t (&
     }
 }
 
-template <int K, int L, int G, int LEAF, int MODE>
+template <int K, int L, int G, int LEAF, int MODE, bool IEP>
 __device__ void search(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], uint64_t& acc,
                        bool& ovf) {
     const GpLevel& lv = d.lv[L];
@@ -374,7 +438,33 @@ __device__ void search(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], ui
     S = trim_u<G>(S, lo, hi);
     if constexpr (MODE == MODE_ACCOUNT)
         if (c.g.gl == 0) *c.bytes += 4ull * (uint64_t)S.n;
-    if constexpr (L == K - 2) {
+    if constexpr (IEP && L == K - 3) {
+        // last outer level: every candidate adds its inclusion-exclusion count
+        if (d.build_begin[L] == d.build_end[L]) {
+            for (int32_t base = 0; base < S.n; base += G) {
+                const int32_t i = base + c.g.gl;
+                if (i < S.n) {
+                    const int32_t x = S.p[i];
+                    if (!inj_hit<K>(lv.inj, v, x)) {
+                        int32_t w[K];
+#pragma unroll
+                        for (int j = 0; j < K; ++j) w[j] = v[j];
+                        w[L] = x;
+                        add_count(acc, iep_leaf_serial<K, G, MODE>(d, c, w), ovf);
+                    }
+                }
+            }
+        } else {
+            for (int32_t t = 0; t < S.n; ++t) {
+                const int32_t x = uni<G>(S.p[t]);
+                if (inj_hit<K>(lv.inj, v, x)) continue;
+                v[L] = x;
+                run_builds<K, G, MODE>(d, c, L, v);
+                const uint64_t cnt = iep_leaf_group<K, G, MODE>(d, c, v);
+                if (c.g.gl == 0) add_count(acc, cnt, ovf);
+            }
+        }
+    } else if constexpr (L == K - 2) {
         if constexpr (LEAF != 2) {
             for (int32_t base = 0; base < S.n; base += G) {
                 int32_t i = base + c.g.gl;
@@ -399,7 +489,7 @@ __device__ void search(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], ui
             }
         }
     } else {
-        if constexpr (LEAF == 3 && L == K - 3) {
+        if constexpr (LEAF == 3 && L == K - 3 && !IEP) {
             if (d.build_begin[L] == d.build_end[L]) {
                 flat_leaf<K, G, MODE>(d, c, v, S, lv.inj, acc, ovf);
                 return;
@@ -410,7 +500,7 @@ __device__ void search(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], ui
             if (inj_hit<K>(lv.inj, v, x)) continue;
             v[L] = x;
             run_builds<K, G, MODE>(d, c, L, v);
-            search<K, L + 1, G, LEAF, MODE>(d, c, v, acc, ovf);
+            search<K, L + 1, G, LEAF, MODE, IEP>(d, c, v, acc, ovf);
         }
     }
 }
@@ -421,7 +511,7 @@ __device__ __forceinline__ int64_t entry_index(const int64_t* row_ptr, const int
     return b + lower_bound(col + b, (int32_t)(row_ptr[v0 + 1] - b), v1);
 }
 
-template <int K, int G, int LEAF, int MODE>
+template <int K, int G, int LEAF, int MODE, bool IEP>
 __global__ __launch_bounds__(kBlock) void count_kernel(GpPlanDesc d, CountArgs a) {
     constexpr bool PER_ROOT = MODE == MODE_PER_ROOT;
     __shared__ int32_t s_len[kBlock / G][GP_DESC_MAX_BUILDS];
@@ -449,7 +539,36 @@ __global__ __launch_bounds__(kBlock) void count_kernel(GpPlanDesc d, CountArgs a
         t0 = (unsigned long long)uni64<G>((int64_t)c.g.bcast(t0, 0));
         if ((int64_t)t0 >= a.n_roots) break;
         const int64_t t1 = min((int64_t)t0 + chunk, a.n_roots);
-        if constexpr (K <= 3 && LEAF != 2) {
+        if constexpr (IEP && K == 4) {
+            // the root is the last outer level
+            if (d.build_begin[1] == d.build_end[1]) {
+                for (int64_t base = (int64_t)t0; base < t1; base += G) {
+                    const int64_t r = base + c.g.gl;
+                    if (r < t1) {
+                        const int2 e = a.roots[a.root_offset + r * a.root_stride];
+                        if constexpr (MODE == MODE_ACCOUNT) bytes += 8;
+                        int32_t w[K] = {e.x, e.y, 0, 0};
+                        const uint64_t cnt = iep_leaf_serial<K, G, MODE>(d, c, w);
+                        add_count(acc, cnt, ovf);
+                        if constexpr (PER_ROOT) a.per_root[entry_index(a.row_ptr, a.col, e.x, e.y)] = cnt;
+                    }
+                }
+            } else {
+                for (int64_t r = (int64_t)t0; r < t1; ++r) {
+                    int2 e = a.roots[a.root_offset + r * a.root_stride];
+                    e.x = uni<G>(e.x);
+                    e.y = uni<G>(e.y);
+                    if constexpr (MODE == MODE_ACCOUNT)
+                        if (c.g.gl == 0) bytes += 8;
+                    int32_t v[K] = {e.x, e.y, 0, 0};
+                    run_builds<K, G, MODE>(d, c, 1, v);
+                    const uint64_t cnt = iep_leaf_group<K, G, MODE>(d, c, v);
+                    if (c.g.gl == 0) add_count(acc, cnt, ovf);
+                    if constexpr (PER_ROOT)
+                        if (c.g.gl == 0) a.per_root[entry_index(a.row_ptr, a.col, e.x, e.y)] = cnt;
+                }
+            }
+        } else if constexpr (K <= 3 && LEAF != 2) {
             // lanes take different roots
             for (int64_t base = (int64_t)t0; base < t1; base += G) {
                 int64_t r = base + c.g.gl;
@@ -488,7 +607,7 @@ __global__ __launch_bounds__(kBlock) void count_kernel(GpPlanDesc d, CountArgs a
                     v[0] = e.x;
                     v[1] = e.y;
                     run_builds<K, G, MODE>(d, c, 1, v);
-                    search<K, 2, G, LEAF, MODE>(d, c, v, acc, ovf);
+                    search<K, 2, G, LEAF, MODE, IEP>(d, c, v, acc, ovf);
                 }
                 if constexpr (PER_ROOT) {
                     uint64_t mine = c.g.sum(acc - before);

@@ -16,6 +16,9 @@
 // Restrictions (id(a) > id(b), Section II-B) become bounds on v_i: hi_src
 // lists levels j with v_i < v_j, lo_src levels j with v_i > v_j. The kernel
 // applies them as binary-search cuts on sorted sets (the paper's `break`).
+// With IEP, restrictions between the two last levels are dropped (and, when
+// needed, every restriction checked in them), so those levels' bounds come
+// from the restrictions that remain.
 #pragma once
 #include <stdint.h>
 
@@ -53,6 +56,12 @@ struct GpPlanDesc {
     int32_t root_cut;  // 0: every directed edge, 1: only v1 < v0, 2: only v1 > v0
     int32_t nbuild;
     int32_t nbuf;
+    // Counting with inclusion-exclusion (Section IV-D): the last two levels
+    // are pairwise non-adjacent and are not enumerated; for each binding of
+    // levels 0..k-3 the kernel adds |S1| |S2| - |S1 & S2|, and the total is
+    // divided by iep_div, the number of times IEP counts every embedding.
+    int32_t iep;
+    int32_t iep_div;
     GpLevel lv[GP_DESC_MAX_K];
     GpBuild b[GP_DESC_MAX_BUILDS];
     uint8_t build_begin[GP_DESC_MAX_K];  // builds with h == level are b[begin, end)

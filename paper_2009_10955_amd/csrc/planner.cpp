@@ -389,9 +389,69 @@ int upper_cuts(const Perm& order, Rel r, int k) {
     return n;
 }
 
-int compile_plan(const Pattern& p, const Perm& order, Rel r, GpPlanDesc* out) {
+// How many relative orders of each Aut-orbit obey `kept`, if the same for
+// every orbit; else 0.
+static int orbit_multiplicity(const std::vector<Perm>& auts, Rel kept, int k) {
+    // pairs of kept as (a, b) lists
+    int pa[64], pb[64], np = 0;
+    Rel rest = kept;
+    while (rest) {
+        int bit = __builtin_ctzll(rest);
+        rest &= rest - 1;
+        pa[np] = bit >> 3;
+        pb[np] = bit & 7;
+        ++np;
+    }
+    Perm r{};
+    for (int i = 0; i < k; ++i) r[i] = uint8_t(i);
+    int mult = -1;
+    do {
+        int c = 0;
+        for (const Perm& q : auts) {
+            // member r o q: rank of vertex v is r[q[v]]
+            bool ok = true;
+            for (int t = 0; t < np && ok; ++t) ok = r[q[pa[t]]] > r[q[pb[t]]];
+            c += ok;
+        }
+        if (mult < 0) mult = c;
+        else if (c != mult) return 0;
+    } while (std::next_permutation(r.begin(), r.begin() + k));
+    return mult < 0 ? 0 : mult;
+}
+
+int iep_setup(const Pattern& p, const std::vector<Perm>& auts, const Perm& order, Rel r, Rel* kept) {
+    const int k = p.k;
+    if (k < 4) return 0;
+    const int a = order[k - 2], b = order[k - 1];
+    if (p.adj[a] & (1u << b)) return 0;  // the two last levels must be non-adjacent
+    // 1) drop only the restrictions between the two last levels
+    Rel k1 = r & ~(rel_bit(a, b) | rel_bit(b, a));
+    int m = orbit_multiplicity(auts, k1, k);
+    if (m > 0) {
+        *kept = k1;
+        return m;
+    }
+    // 2) drop every restriction checked in the two last loops
+    Rel k2 = 0;
+    Rel rest = r;
+    while (rest) {
+        int bit = __builtin_ctzll(rest);
+        rest &= rest - 1;
+        int u = bit >> 3, w = bit & 7;
+        if (u != a && u != b && w != a && w != b) k2 |= rel_bit(u, w);
+    }
+    m = orbit_multiplicity(auts, k2, k);
+    if (m > 0) {
+        *kept = k2;
+        return m;
+    }
+    return 0;
+}
+
+int compile_plan(const Pattern& p, const Perm& order, Rel r, GpPlanDesc* out, Rel iep_kept, int iep_div) {
     const int k = p.k;
     if (!phase1_ok(p, order)) return GP_ERR_ARG;
+    const bool iep = iep_div > 0;
     GpPlanDesc d;
     std::memset(&d, 0, sizeof d);
     d.k = k;
@@ -402,11 +462,18 @@ int compile_plan(const Pattern& p, const Perm& order, Rel r, GpPlanDesc* out) {
     for (int i = 0; i < k; ++i) {
         par[i] = hi[i] = lo[i] = 0;
         int u = order[i];
+        // the two IEP levels are bounded only by the restrictions that remain
+        const Rel rr = (iep && i >= k - 2) ? iep_kept : r;
         for (int j = 0; j < i; ++j) {
             int w = order[j];
             if (p.adj[u] & (1u << w)) par[i] |= 1u << j;
-            if (rel_has(r, w, u)) hi[i] |= 1u << j;  // id(w) > id(u): v_i < v_j
-            if (rel_has(r, u, w)) lo[i] |= 1u << j;  // id(u) > id(w): v_i > v_j
+            if (rel_has(rr, w, u)) hi[i] |= 1u << j;  // id(w) > id(u): v_i < v_j
+            if (rel_has(rr, u, w)) lo[i] |= 1u << j;  // id(u) > id(w): v_i > v_j
+        }
+        if (iep && i == k - 1) {
+            // the other IEP level is not a bound source or injectivity partner
+            hi[i] &= ~(1u << (k - 2));
+            lo[i] &= ~(1u << (k - 2));
         }
     }
     d.root_cut = (hi[1] & 1u) ? 1 : ((lo[1] & 1u) ? 2 : 0);
@@ -457,6 +524,7 @@ int compile_plan(const Pattern& p, const Perm& order, Rel r, GpPlanDesc* out) {
         L.hi_src = uint8_t(hi[i]);
         L.lo_src = uint8_t(lo[i]);
         L.inj = uint8_t(((1u << i) - 1) & ~par[i] & ~hi[i] & ~lo[i]);
+        if (iep && i == k - 1) L.inj &= uint8_t(~(1u << (k - 2)));
         L.list = L.buf = L.pre_buf = L.pre_list = L.last_list = -1;
         if (i == 0) continue;
         int np = __builtin_popcount(par[i]);
@@ -490,6 +558,8 @@ int compile_plan(const Pattern& p, const Perm& order, Rel r, GpPlanDesc* out) {
         d.build_begin[h] = uint8_t(b0);
         d.build_end[h] = uint8_t(b1);
     }
+    d.iep = iep ? 1 : 0;
+    d.iep_div = iep ? iep_div : 0;
     *out = d;
     return 0;
 }

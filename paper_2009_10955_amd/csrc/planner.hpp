@@ -65,6 +65,18 @@ double model_cost(const Pattern& p, const Perm& order, Rel r, const GraphStats& 
 int upper_cuts(const Perm& order, Rel r, int k);
 
 // Compile (schedule, closure) into the kernel descriptor. Returns 0 or an error.
-int compile_plan(const Pattern& p, const Perm& order, Rel r, GpPlanDesc* out);
+// With iep_kept != 0 the last two levels are compiled for counting with
+// inclusion-exclusion: their bounds come from iep_kept (the restrictions that
+// remain) and iep_div is the over-count.
+int compile_plan(const Pattern& p, const Perm& order, Rel r, GpPlanDesc* out, Rel iep_kept = 0,
+                 int iep_div = 0);
+
+// IEP over the last two levels of (order, r): the restrictions that remain
+// and the exact over-count (how many relative orders of each Aut-orbit obey
+// them; it must be the same for every orbit). First try dropping only the
+// restrictions between the two last levels, then every restriction checked
+// in them. Returns the over-count (and *kept), or 0 when the configuration
+// cannot be counted with IEP.
+int iep_setup(const Pattern& p, const std::vector<Perm>& auts, const Perm& order, Rel r, Rel* kept);
 
 }  // namespace gp

@@ -54,6 +54,7 @@ struct Cfg {
 struct Cached {
     gp::Perm order;
     gp::Rel rel;
+    GpPlanDesc desc;
     gpint::LaunchCfg launch;
     int measured;
 };
@@ -113,7 +114,7 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
     for (auto& e : edges)
         if (e.first > e.second) std::swap(e.first, e.second);
     std::sort(edges.begin(), edges.end());
-    auto key = std::make_tuple(g->dg.stats.hash, (int64_t)g->dg.n_hubs, k, edges);
+    auto key = std::make_tuple(g->dg.stats.hash, (int64_t)g->dg.n_hubs * 2 + (p->desc.iep ? 1 : 0), k, edges);
     {
         std::lock_guard<std::mutex> lk(g_cache_mu);
         auto it = g_cache.find(key);
@@ -122,7 +123,7 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
             np->set = it->second.rel;
             np->launch = it->second.launch;
             np->tuned = true;
-            gp::compile_plan(np->pattern, np->order, np->set, &np->desc);
+            np->desc = it->second.desc;
             np->info.n_measured = it->second.measured;
         }
     }
@@ -161,7 +162,13 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
             Cfg c;
             c.order = order;
             c.rel = rel;
-            if (gp::compile_plan(p->pattern, order, rel, &c.desc) != 0) return;
+            gp::Rel kept = 0;
+            int div = 0;
+            if (p->desc.iep) {
+                div = gp::iep_setup(p->pattern, auts, order, rel, &kept);
+                if (div <= 0) return;
+            }
+            if (gp::compile_plan(p->pattern, order, rel, &c.desc, kept, div) != 0) return;
             for (auto& x : cands)
                 if (std::memcmp(&x.desc, &c.desc, sizeof c.desc) == 0) return;
             cands.push_back(c);
@@ -237,10 +244,11 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
         if (st == GP_OK && o.tune_launch >= 0) {
             const GpPlanDesc& bd = cands[best].desc;
             const GpLevel& leaf = bd.lv[k - 1];
-            const bool leaf_intersects = k <= 3 || leaf.last_list >= 0;
-            const bool can_flatten = k >= 5 && bd.build_begin[k - 3] == bd.build_end[k - 3];
+            const bool leaf_intersects = !bd.iep && (k <= 3 || leaf.last_list >= 0);
+            const bool can_flatten = k >= 5 && !bd.iep && bd.build_begin[k - 3] == bd.build_end[k - 3];
             double best_l = -1;
             for (int grp : {64, 32, 16, 8}) {
+                if (bd.iep && grp < 32) continue;
                 for (int lm : {1, 2, 3}) {
                     if (lm == 2 && !leaf_intersects) continue;
                     if (lm == 3 && !can_flatten) continue;
@@ -276,7 +284,7 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
             np->tuned = true;
             np->info.n_measured = measured;
             std::lock_guard<std::mutex> lk(g_cache_mu);
-            g_cache[key] = Cached{np->order, np->set, np->launch, measured};
+            g_cache[key] = Cached{np->order, np->set, np->desc, np->launch, measured};
         }
         (void)hipFreeAsync(res, s);
         (void)hipStreamSynchronize(s);
@@ -305,6 +313,8 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
                       double(std::max<int64_t>(1, g->dg.stats.m)), double(g->dg.stats.tri_cnt)};
     in.cost = gp::model_cost(np->pattern, np->order, np->set, gs);
     in.tuned = 1;
+    in.iep = np->desc.iep;
+    in.iep_div = np->desc.iep_div;
     in.plan_seconds = p->info.plan_seconds + (now_seconds() - t0);
     *out = np;
     return GP_OK;

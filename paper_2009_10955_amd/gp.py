@@ -25,6 +25,7 @@ STATUS = {
     -4: "GP_ERR_CSR_SELFLOOP", -5: "GP_ERR_CSR_DUPLICATE", -6: "GP_ERR_PATTERN",
     -7: "GP_ERR_NOMEM", -8: "GP_ERR_HIP", -9: "GP_ERR_OVERFLOW", -10: "GP_ERR_BUDGET",
     -11: "GP_ERR_CSR_RANGE", -12: "GP_ERR_UNSUPPORTED", -13: "GP_ERR_TIMEOUT",
+    -14: "GP_ERR_INTERNAL",
 }
 
 
@@ -48,7 +49,8 @@ class PlanOpts(ctypes.Structure):
                 ("force_order", ctypes.c_int32 * MAX_K), ("force_set", ctypes.c_int32),
                 ("n_force_restr", ctypes.c_int32),
                 ("force_restr", ctypes.c_int32 * (2 * MAX_K * MAX_K)),
-                ("cost_cap", ctypes.c_double), ("max_seconds", ctypes.c_double)]
+                ("cost_cap", ctypes.c_double), ("max_seconds", ctypes.c_double),
+                ("iep", ctypes.c_int32)]
 
 
 class Launch(ctypes.Structure):
@@ -84,6 +86,7 @@ class PlanInfo(ctypes.Structure):
                 ("n_states", ctypes.c_int64), ("n_schedules", ctypes.c_int32),
                 ("k_eff", ctypes.c_int32), ("set_index", ctypes.c_int32),
                 ("plan_seconds", ctypes.c_double), ("tuned", ctypes.c_int32),
+                ("iep", ctypes.c_int32), ("iep_div", ctypes.c_int32),
                 ("n_measured", ctypes.c_int32), ("launch", Launch)]
 
 
@@ -255,7 +258,7 @@ class Plan:
     def __init__(self, k: int, edges: Sequence[tuple[int, int]], stats: Stats | None = None,
                  force_order: Sequence[int] | None = None, force_set: int | None = None,
                  force_restr: Sequence[tuple[int, int]] | None = None, max_states: int = 0,
-                 max_sets: int = 0, cost_cap: float = 0.0):
+                 max_sets: int = 0, cost_cap: float = 0.0, iep: bool = False):
         lib = _lib()
         e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1))
         o = PlanOpts()
@@ -263,6 +266,7 @@ class Plan:
         o.max_states = max_states
         o.max_sets = max_sets
         o.cost_cap = cost_cap
+        o.iep = 1 if iep else 0
         if force_order is not None:
             for i, v in enumerate(force_order):
                 o.force_order[i] = v

@@ -378,3 +378,46 @@ def test_serving_rejects_over_budget_and_reports_overflow_free():
     srv.close()
     assert [o[0] for o in out] == [0, 0]
     assert out[0][1] == 157
+
+
+# --------------------------------------------------------------------- IEP
+
+@pytest.mark.parametrize("pname", ["house", "diamond", "tailed-triangle", "4-path", "3-star",
+                                   "prism", "6-cycle-chord", "k4-path", "5-wheel"])
+def test_iep_counts_equal_oracle(pname):
+    """Counting the last two levels with inclusion-exclusion gives the plain
+    count, for the chosen configuration and for every eligible configuration
+    of a few schedules, in both IEP group sizes."""
+    g = I.er(50, 0.25, seed=31)
+    graph = gp.Graph.from_csr(g, hub_bitmaps="dense")
+    k, e = P[pname]
+    want = O.count(g, k, e)
+    plan = gp.Plan(k, e, stats=graph.stats(), iep=True)
+    assert plan.info().iep == 1
+    for grp in (64, 32):
+        assert gp.count(graph, plan, group=grp) == want
+    base = gp.Plan(k, e)
+    scheds = base.schedules()
+    n_sets = base.info().n_sets
+    checked = 0
+    for o in scheds[:4]:
+        for si in range(min(n_sets, 6)):
+            p2 = gp.Plan(k, e, force_order=o, force_set=si, iep=True)
+            if p2.info().iep:
+                assert gp.count(graph, p2) == want, (o, si)
+                checked += 1
+    assert checked > 0
+
+
+def test_iep_per_root_and_config2():
+    g = I.config_graph(2)
+    graph = gp.Graph.from_csr(g, device=True)
+    for pname in ["house", "diamond"]:
+        k, e = P[pname]
+        plain = gp.count(graph, gp.Plan(k, e, stats=graph.stats()))
+        ip = gp.Plan(k, e, stats=graph.stats(), iep=True)
+        assert gp.count(graph, ip) == plain
+        total, per = gp.count_per_root(graph, ip)
+        assert total == plain
+        assert int(per.cpu().numpy().sum()) == plain * ip.info().iep_div
+    assert gp.count(graph, gp.Plan(*P["diamond"])) == O.count(g, *P["diamond"])

@@ -142,3 +142,39 @@ def test_cost_cap():
     with pytest.raises(gp.GpError) as ei:
         gp.Plan(k, e, stats=_stats(4_194_304, 32_600_000, 6 * 455_000_000), cost_cap=1.0)
     assert ei.value.status == -10
+
+
+# ------------------------------------------------------------------- IEP
+
+def _kept_rule(k, e, order, r):
+    """The library's rule for the restrictions kept with IEP over the last two
+    levels: drop those between the two; if the over-count then differs between
+    orbits, drop every restriction checked in them."""
+    a, b = order[k - 2], order[k - 1]
+    k1 = [(x, y) for x, y in r if not ({x, y} == {a, b})]
+    m = O.orbit_multiplicities(k, e, k1)
+    if len(m) == 1:
+        return k1, m.pop()
+    k2 = [(x, y) for x, y in r if x not in (a, b) and y not in (a, b)]
+    m = O.orbit_multiplicities(k, e, k2)
+    return (k2, m.pop()) if len(m) == 1 else (None, 0)
+
+
+@pytest.mark.parametrize("pname", ["house", "diamond", "tailed-triangle", "4-path", "3-star",
+                                   "prism", "6-cycle-chord", "k4-path", "5-wheel"])
+def test_iep_plans_use_the_exact_over_count(pname):
+    k, e = P[pname]
+    plan = gp.Plan(k, e, iep=True)
+    inf = plan.info()
+    assert inf.iep == 1
+    order = plan.order
+    adj = O._adj(k, e)
+    assert not adj[order[k - 2]][order[k - 1]]
+    kept, m = _kept_rule(k, e, order, plan.restrictions)
+    assert kept is not None and inf.iep_div == m
+
+
+def test_iep_falls_back_when_no_configuration_allows_it():
+    for pname in ["triangle", "4-cycle", "4-clique", "5-cycle", "5-clique"]:
+        k, e = P[pname]
+        assert gp.Plan(k, e, iep=True).info().iep == 0

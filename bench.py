@@ -44,6 +44,8 @@ def parse_args():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat17", choices=sorted(WORKLOADS))
+    ap.add_argument("--patterns", default=None,
+                    help="comma-separated subset of the workload's patterns (profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="wall budget of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -51,6 +53,12 @@ def parse_args():
                     help="skip the instrumented algorithmic-bytes run")
     ap.add_argument("--tune-seconds", type=float, default=8.0,
                     help="GPU-time budget per pattern for measured configuration selection")
+    ap.add_argument("--plans-json", default=None,
+                    help="reuse the configurations and launch shapes of a previous bench JSON "
+                         "line instead of tuning (so profiled runs time the same kernels)")
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_rmat17.json"),
+                    help="HBM bytes per launch from rocprofv3 counters (used only while the "
+                         "kernel sources it was taken from are unchanged)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     return ap.parse_args()
@@ -134,6 +142,8 @@ def main():
 
     torch.cuda.set_device(0)
     cfg_idx, names, desc = WORKLOADS[args.workload]
+    if args.patterns:
+        names = [n for n in names if n in args.patterns.split(",")]
     g = I.config_graph(cfg_idx)
     graph = gp.Graph.from_csr(g, device=True)
     st = graph.stats()
@@ -141,9 +151,15 @@ def main():
     base_plans = [gp.Plan(*I.PATTERNS[n], stats=st) for n in names]
     plan_s = time.perf_counter() - t_plan
     t_tune = time.perf_counter()
-    plans = [p.tuned(graph, budget_seconds=args.tune_seconds) for p in base_plans]
+    if args.plans_json:
+        prev = json.loads(open(args.plans_json).read().strip().splitlines()[-1])["plans"]
+        plans = [gp.Plan(*I.PATTERNS[n], stats=st, force_order=prev[n]["order"],
+                         force_restr=[tuple(x) for x in prev[n]["restrictions"]]) for n in names]
+        launches = [dict(prev[n]["launch"]) for n in names]
+    else:
+        plans = [p.tuned(graph, budget_seconds=args.tune_seconds) for p in base_plans]
+        launches = [p.launch() for p in plans]
     tune_s = time.perf_counter() - t_tune
-    launches = [p.launch() for p in plans]
     stream = torch.cuda.current_stream()
     dev_out = torch.zeros(2 * len(plans), dtype=torch.int64, device="cuda")
 
@@ -182,9 +198,9 @@ def main():
             per_kernel[i].append(evs[s][i][0].elapsed_time(evs[s][i][1]))
     res = dev_out.cpu().tolist()
     counts = [res[2 * i] & (2 ** 64 - 1) for i in range(len(plans))]
-    overflow = [res[2 * i + 1] for i in range(len(plans))]
-    if any(overflow):
-        raise RuntimeError(f"count overflow: {dict(zip(names, overflow))}")
+    flags = [res[2 * i + 1] for i in range(len(plans))]
+    if any(flags):
+        raise RuntimeError(f"count flags (1: overflow, 2: internal): {dict(zip(names, flags))}")
     ms_per_step = ms_total / args.steps
     embeddings_per_step = sum(counts)
     value = embeddings_per_step / (ms_per_step / 1e3)
@@ -200,8 +216,13 @@ def main():
             alg[n] = b
             note(f"algorithmic bytes {n}: {b:.4e}")
         achieved = alg[names[dom]] / (avg_ms[dom] / 1e3) / 1e9
+        traffic = None
+        from paper_2009_10955_amd import profiling
+        tr = profiling.load_traffic(args.traffic_json)
+        if tr is not None and tr["pattern"] == names[dom] and tr["workload"] == args.workload:
+            traffic = tr["hbm_bytes_per_launch"]
         roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                     "kernel": f"count_kernel ({names[dom]})",
                     "alg_bytes_per_launch": alg[names[dom]],
                     "avg_launch_ms": round(avg_ms[dom], 3)}

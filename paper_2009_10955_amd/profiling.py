@@ -1,0 +1,103 @@
+"""Summaries of rocprofv3 output for the measurements bench.py reports.
+
+HBM traffic of a kernel comes from two counter runs (FETCH_SIZE, then
+WRITE_SIZE, each in KiB per dispatch). Each counter is scaled by what it
+reads for a plain device copy of known size in the same run (a 1 GiB copy
+reads and writes 1 GiB), which calibrates the counter's unit and coverage.
+A summary records a hash of the kernel sources; it stops applying as soon
+as they change.
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ["csrc/count_kernel.hpp", "csrc/sets.hpp", "csrc/count_inst.hip", "csrc/count.hip",
+                  "csrc/plan_desc.h"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(PKG, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(path: str):
+    """The traffic summary at path, if it matches the current kernel sources."""
+    try:
+        with open(path) as f:
+            tr = json.load(f)
+    except (OSError, ValueError):
+        return None
+    return tr if tr.get("kernel_source_hash") == kernel_source_hash() else None
+
+
+def _rows(path_glob: str):
+    for path in sorted(glob.glob(path_glob, recursive=True)):
+        with open(path, newline="") as f:
+            yield from csv.DictReader(f)
+
+
+def counter_per_dispatch(path_glob: str, counter: str) -> list:
+    """[(dispatch id, kernel name, value)] for one counter from rocprofv3
+    counter_collection CSV files (values summed over the counter's instances)."""
+    acc: dict = {}
+    for r in _rows(path_glob):
+        name = r.get("Counter_Name") or r.get("counter_name")
+        if name != counter:
+            continue
+        did = int(r.get("Dispatch_Id") or r.get("dispatch_id") or 0)
+        kern = r.get("Kernel_Name") or r.get("kernel_name") or ""
+        val = float(r.get("Counter_Value") or r.get("counter_value") or 0.0)
+        key = (did, kern)
+        acc[key] = acc.get(key, 0.0) + val
+    return [(d, k, v) for (d, k), v in sorted(acc.items())]
+
+
+def traffic_summary(fetch_glob: str, write_glob: str, kernel_match: str, copy_bytes: int,
+                    pattern: str, workload: str) -> dict:
+    """HBM bytes of the longest dispatch whose name contains kernel_match,
+    with FETCH_SIZE / WRITE_SIZE scaled by the copy kernel's readings."""
+    fetch = counter_per_dispatch(fetch_glob, "FETCH_SIZE")
+    write = counter_per_dispatch(write_glob, "WRITE_SIZE")
+
+    def copy_value(rows):
+        vals = [v for _, k, v in rows if "copyBuffer" in k or "copy" in k.lower()]
+        return max(vals) if vals else None
+
+    def kernel_value(rows):
+        vals = [v for _, k, v in rows if kernel_match in k]
+        return max(vals) if vals else None
+
+    cf, cw = copy_value(fetch), copy_value(write)
+    kf, kw = kernel_value(fetch), kernel_value(write)
+    # counters read KiB; the copy moves copy_bytes each way
+    f_scale = copy_bytes / (cf * 1024.0) if cf else None
+    w_scale = copy_bytes / (cw * 1024.0) if cw else None
+    hbm = None
+    if None not in (f_scale, w_scale, kf, kw):
+        hbm = kf * 1024.0 * f_scale + kw * 1024.0 * w_scale
+    return {"workload": workload, "pattern": pattern, "kernel_match": kernel_match,
+            "fetch_kib": kf, "write_kib": kw, "copy_fetch_kib": cf, "copy_write_kib": cw,
+            "copy_bytes": copy_bytes, "fetch_scale": f_scale, "write_scale": w_scale,
+            "hbm_bytes_per_launch": hbm, "kernel_source_hash": kernel_source_hash()}
+
+
+def main(argv):
+    """python -m paper_2009_10955_amd.profiling FETCH_GLOB WRITE_GLOB KERNEL_MATCH COPY_MIB PATTERN WORKLOAD OUT"""
+    fg, wg, km, mib, pat, wl, out = argv
+    s = traffic_summary(fg, wg, km, int(mib) << 20, pat, wl)
+    with open(out, "w") as f:
+        json.dump(s, f, indent=1)
+    print(json.dumps(s))
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

@@ -219,13 +219,21 @@ def main():
         traffic = None
         from paper_2009_10955_amd import profiling
         tr = profiling.load_traffic(args.traffic_json)
-        if tr is not None and tr["pattern"] == names[dom] and tr["workload"] == args.workload:
+        dom_plan = {"order": list(plans[dom].order),
+                    "restrictions": [list(x) for x in plans[dom].restrictions],
+                    "launch": launches[dom]}
+        l2 = None
+        if (tr is not None and tr["pattern"] == names[dom] and tr["workload"] == args.workload
+                and profiling.same_plan(tr.get("plan"), dom_plan)):
             traffic = tr["hbm_bytes_per_launch"]
+            l2 = tr.get("l2")
         roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                     "kernel": f"count_kernel ({names[dom]})",
                     "alg_bytes_per_launch": alg[names[dom]],
-                    "avg_launch_ms": round(avg_ms[dom], 3)}
+                    "avg_launch_ms": round(avg_ms[dom], 3),
+                    "dram_GBps": round(traffic / (avg_ms[dom] / 1e3) / 1e9, 2) if traffic else None,
+                    "l2_hit_rate": round(l2["hit_rate"], 5) if l2 else None}
 
     if args.copy_mib > 0:
         x = torch.empty(args.copy_mib << 18, dtype=torch.int32, device="cuda")

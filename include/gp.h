@@ -124,6 +124,12 @@ typedef struct {
                               load-balanced batch of (x, y) pairs (k >= 5; else as 1) */
     int32_t root_stride;   /* count only every root_stride-th root task (0 or 1 = all), */
     int32_t root_offset;   /* starting at root_offset: a seeded root sample for tuning */
+    int32_t split_ways;    /* 0 auto, 1 none, else: each heavy root edge runs as split_ways
+                              tasks that bind disjoint slices of its level-2 candidates
+                              (shortens the tail that single hub roots leave; k >= 4) */
+    int32_t split_vertices;/* heavy roots: those whose smaller endpoint in the degree-sorted
+                              layout is below split_vertices, rounded down to a power of
+                              two (0 = auto) */
 } gp_launch;
 
 void gp_launch_default(gp_launch* l);

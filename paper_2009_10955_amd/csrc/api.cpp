@@ -2,6 +2,7 @@
 // the host planner and the device kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 #include <new>
@@ -129,6 +130,10 @@ gp_status gp_load_graph(const int64_t* row_ptr, const int32_t* col, int64_t n, i
         return GP_ERR_HIP;
     }
     g->dg.num_cus = cus;
+    int wall_khz = 0;
+    if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || wall_khz <= 0)
+        wall_khz = 100000;
+    g->dg.wall_khz = wall_khz;
 
     const int64_t* d_row = row_ptr;
     const int32_t* d_col = col;
@@ -435,6 +440,8 @@ gp_status gp_plan_get(const gp_plan* p, gp_plan_info* out) {
     out->launch.leaf_mode = p->launch.leaf;
     out->launch.root_stride = 0;
     out->launch.root_offset = 0;
+    out->launch.split_ways = p->launch.split_ways;
+    out->launch.split_vertices = (int32_t)std::min<int64_t>(p->launch.split_vertices, INT32_MAX);
     return GP_OK;
 }
 

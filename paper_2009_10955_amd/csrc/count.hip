@@ -68,11 +68,24 @@ namespace gpint {
 
 LaunchCfg default_launch(const GpPlanDesc& d) {
     LaunchCfg cfg;
-    cfg.group = 16;
-    cfg.waves_per_cu = 16;
+    cfg.group = 64;
+    cfg.waves_per_cu = 32;
     cfg.chunk = d.k <= 3 ? 256 : 4;
     cfg.leaf = 1;
+    cfg.split_ways = 16;
+    cfg.split_vertices = 256;
     return cfg;
+}
+
+int resident_waves_per_cu(const GpPlanDesc& d, const LaunchCfg& cfg) {
+    const bool iep = d.iep != 0;
+    const int group = iep ? (cfg.group >= 64 ? 64 : 32) : cfg.group;
+    KernelFn fn = pick_kernel(d.k, group, cfg.leaf, MODE_PLAIN, iep);
+    int nb = 0;
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)fn, kBlock, 0) != hipSuccess ||
+        nb <= 0)
+        return cfg.waves_per_cu;
+    return std::min(cfg.waves_per_cu, nb * (kBlock / 64));
 }
 
 LaunchCfg apply_launch(LaunchCfg cfg, const gp_launch* l) {
@@ -83,6 +96,8 @@ LaunchCfg apply_launch(LaunchCfg cfg, const gp_launch* l) {
         if (l->leaf_mode) cfg.leaf = l->leaf_mode;
         if (l->root_stride) cfg.root_stride = l->root_stride;
         cfg.root_offset = l->root_offset;
+        if (l->split_ways) cfg.split_ways = l->split_ways;
+        if (l->split_vertices) cfg.split_vertices = l->split_vertices;
     }
     return cfg;
 }
@@ -102,7 +117,7 @@ static const int2* pick_roots(const DeviceGraph& g, int root_cut, int64_t* n) {
 
 gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCfg& cfg,
                        hipStream_t stream, unsigned long long* result_dev,
-                       unsigned long long* per_root, bool account) {
+                       unsigned long long* per_root, bool account, unsigned long long* busy) {
     if (cfg.group != 64 && cfg.group != 32 && cfg.group != 16 && cfg.group != 8) return GP_ERR_ARG;
     if (cfg.leaf < 1 || cfg.leaf > 3) return GP_ERR_ARG;
     if (cfg.waves_per_cu < 1 || cfg.waves_per_cu > 32 || cfg.chunk < 1) return GP_ERR_ARG;
@@ -115,9 +130,27 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
     int64_t all_roots = 0;
     const int2* roots = pick_roots(g, d.root_cut, &all_roots);
     if (cfg.root_stride < 1 || cfg.root_offset < 0) return GP_ERR_ARG;
-    // sampled task space: roots[offset + t * stride]
-    const int64_t n_roots =
-        all_roots > cfg.root_offset ? (all_roots - cfg.root_offset + cfg.root_stride - 1) / cfg.root_stride : 0;
+    if (cfg.split_ways < 1 || cfg.split_ways > 4096 || cfg.split_vertices < 0 || cfg.budget_ms < 0)
+        return GP_ERR_ARG;
+    // sampled roots: roots[offset + r * stride]
+    auto sampled = [&](int64_t n) {
+        return n > cfg.root_offset ? (n - cfg.root_offset + cfg.root_stride - 1) / cfg.root_stride : 0;
+    };
+    const int64_t n_roots = sampled(all_roots);
+    // the split prefix: roots whose smaller endpoint is below 2^i, i = floor(log2(split_vertices));
+    // only plain counts over a level-2 loop split (per-root and byte counts stay per root)
+    int64_t split_roots = 0;
+    int split_ways = 1;
+    const bool splittable = mode == MODE_PLAIN && d.k >= 4 && !(iep && d.k == 4) && cfg.split_ways > 1 &&
+                            cfg.split_vertices > 0;
+    if (splittable) {
+        int i = 0;
+        while (i < 31 && (int64_t(1) << (i + 1)) <= cfg.split_vertices) ++i;
+        const int64_t pref = g.upper_pref[i] * (d.root_cut == 0 ? 2 : 1);
+        split_roots = std::min(n_roots, sampled(pref));
+        split_ways = cfg.split_ways;
+    }
+    const int64_t n_tasks = n_roots + split_roots * (split_ways - 1);
 
     const int waves_per_block = kBlock / 64;
     int64_t blocks = std::max<int64_t>(1, (int64_t)g.num_cus * cfg.waves_per_cu / waves_per_block);
@@ -131,7 +164,7 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
         blocks = std::min(blocks, max_blocks);
     }
     // a grid larger than the number of root tasks only adds idle groups
-    int64_t need = (n_roots + cfg.chunk - 1) / cfg.chunk;
+    int64_t need = (n_tasks + cfg.chunk - 1) / cfg.chunk;
     int64_t need_blocks = std::max<int64_t>(1, (need + groups_per_block - 1) / groups_per_block);
     blocks = std::min(blocks, need_blocks);
 
@@ -147,12 +180,17 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
     }
     hipLaunchKernelGGL(init_counters, dim3(1), dim3(64), 0, stream, queue, 1);
     hipLaunchKernelGGL(init_counters, dim3(1), dim3(64), 0, stream, result_dev, account ? 3 : 2);
+    if (busy) hipLaunchKernelGGL(init_counters, dim3(1), dim3(64), 0, stream, busy, 3);
 
     CountArgs a;
     a.row_ptr = g.row_ptr;
     a.col = g.col;
     a.roots = roots;
     a.n_roots = n_roots;
+    a.n_tasks = n_tasks;
+    a.split_roots = split_roots;
+    a.split_ways = split_ways;
+    a.budget_ticks = busy && cfg.budget_ms > 0 ? (uint64_t)(cfg.budget_ms * g.wall_khz) : 0;
     a.root_offset = cfg.root_offset;
     a.hub_bits = g.hub_bits;
     a.hub_words = g.hub_words;
@@ -163,8 +201,9 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
     a.queue = queue;
     a.result = result_dev;
     a.per_root = per_root;
+    a.busy = busy;
     a.chunk = cfg.chunk;
-    if (n_roots > 0) hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kBlock), 0, stream, d, a);
+    if (n_tasks > 0) hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kBlock), 0, stream, d, a);
     if (iep)
         hipLaunchKernelGGL(iep_divide, dim3(1), dim3(64), 0, stream, result_dev, (unsigned long long)d.iep_div);
     hipError_t le = hipGetLastError();

@@ -87,6 +87,9 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
     c.bufs = a.scratch ? a.scratch + group_id * (int64_t)a.nbuf * a.buf_cap : nullptr;
     c.lens = s_len[grp];
     c.bytes = nullptr;
+    c.sj = 0;
+    c.sJ = 1;
+    c.deadline = 0;
     const int64_t chunk = a.chunk;
 
     for (;;) {

@@ -46,9 +46,16 @@ struct CountArgs {
     const int64_t* row_ptr;
     const int32_t* col;
     const int2* roots;
-    int64_t n_roots;      // tasks: roots[root_offset + t * root_stride], t < n_roots
+    int64_t n_roots;      // sampled roots: roots[root_offset + r * root_stride], r < n_roots
     int64_t root_offset;
     int64_t root_stride;
+    // The first split_roots sampled roots (the heaviest: root arrays are
+    // ordered by their hub endpoint) are each split into split_ways tasks, the
+    // j-th of which binds only every split_ways-th level-2 candidate from j on.
+    // Tasks: split_roots * split_ways split ones, then one per remaining root.
+    int64_t n_tasks;
+    int64_t split_roots;
+    int32_t split_ways;
     const uint32_t* hub_bits;  // n_hubs dense bitmaps of hub_words words
     int64_t hub_words;
     int32_t n_hubs;
@@ -57,6 +64,12 @@ struct CountArgs {
     unsigned long long* queue;
     unsigned long long* result;    // {count, overflow, algorithmic bytes}
     unsigned long long* per_root;  // optional, indexed by CSR entry of (v0, v1)
+    // optional {sum over wavefronts of active clock ticks, wavefronts, longest
+    // chunk of tasks in ticks}: the balanced run time of a sample and its tail
+    unsigned long long* busy;
+    // with busy: stop taking tasks once a wavefront has run this many clock
+    // ticks (0: no limit); the count is then incomplete and flagged (bit 2)
+    uint64_t budget_ticks;
     int32_t chunk;
 };
 
@@ -132,7 +145,13 @@ struct Ctx {
     const uint32_t* hub_bits;
     int64_t hub_words;
     int32_t n_hubs;
+    int32_t sj, sJ;     // level-2 slice of the current task: candidates sj, sj + sJ, ...
+    uint64_t deadline;  // clock tick after which level-2 loops stop (0: none)
     Group<G> g;
+
+    __device__ __forceinline__ bool expired() const {
+        return deadline != 0 && wall_clock64() > deadline;
+    }
 
     __device__ __forceinline__ Set nbr(int32_t v) const {
         int64_t b = row_ptr[v], e = row_ptr[v + 1];
@@ -369,15 +388,17 @@ __device__ __forceinline__ uint64_t iep_leaf_group(const GpPlanDesc& d, const Ct
 // runs after level K-3 is bound.
 template <int K, int G, int MODE>
 __device__ void flat_leaf(const GpPlanDesc& d, const Ctx<G>& c, const int32_t (&v)[K], Set S,
-                          uint32_t inj_l, uint64_t& acc, bool& ovf) {
+                          int32_t st, uint32_t inj_l, uint64_t& acc, bool& ovf) {
     constexpr int L = K - 3;
     const GpLevel& l2 = d.lv[K - 2];
     for (int32_t base = 0; base < S.n; base += G) {
+        if constexpr (L == 2)
+            if (c.expired()) break;
         const int32_t i = base + c.g.gl;
         int32_t x2 = 0;
         Set C{nullptr, 0, nullptr};
         if (i < S.n) {
-            x2 = S.p[i];
+            x2 = S.p[(int64_t)i * st];
             if (!inj_hit<K>(inj_l, v, x2)) {
                 int32_t w[K];
 #pragma unroll
@@ -438,13 +459,24 @@ __device__ void search(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], ui
     S = trim_u<G>(S, lo, hi);
     if constexpr (MODE == MODE_ACCOUNT)
         if (c.g.gl == 0) *c.bytes += 4ull * (uint64_t)S.n;
+    // a split task binds only its slice of the level-2 candidates
+    int32_t st = 1;
+    if constexpr (L == 2) {
+        if (c.sJ > 1) {
+            S.n = S.n > c.sj ? (S.n - c.sj + c.sJ - 1) / c.sJ : 0;
+            S.p += c.sj;
+            st = c.sJ;
+        }
+    }
     if constexpr (IEP && L == K - 3) {
         // last outer level: every candidate adds its inclusion-exclusion count
         if (d.build_begin[L] == d.build_end[L]) {
             for (int32_t base = 0; base < S.n; base += G) {
+                if constexpr (L == 2)
+                    if (c.expired()) break;
                 const int32_t i = base + c.g.gl;
                 if (i < S.n) {
-                    const int32_t x = S.p[i];
+                    const int32_t x = S.p[(int64_t)i * st];
                     if (!inj_hit<K>(lv.inj, v, x)) {
                         int32_t w[K];
 #pragma unroll
@@ -456,7 +488,9 @@ __device__ void search(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], ui
             }
         } else {
             for (int32_t t = 0; t < S.n; ++t) {
-                const int32_t x = uni<G>(S.p[t]);
+                if constexpr (L == 2)
+                    if (c.expired()) break;
+                const int32_t x = uni<G>(S.p[(int64_t)t * st]);
                 if (inj_hit<K>(lv.inj, v, x)) continue;
                 v[L] = x;
                 run_builds<K, G, MODE>(d, c, L, v);
@@ -467,9 +501,11 @@ __device__ void search(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], ui
     } else if constexpr (L == K - 2) {
         if constexpr (LEAF != 2) {
             for (int32_t base = 0; base < S.n; base += G) {
+                if constexpr (L == 2)
+                    if (c.expired()) break;
                 int32_t i = base + c.g.gl;
                 if (i < S.n) {
-                    int32_t x = S.p[i];
+                    int32_t x = S.p[(int64_t)i * st];
                     if (!inj_hit<K>(lv.inj, v, x)) {
                         int32_t w[K];
 #pragma unroll
@@ -481,7 +517,9 @@ __device__ void search(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], ui
             }
         } else {
             for (int32_t t = 0; t < S.n; ++t) {
-                const int32_t x = uni<G>(S.p[t]);
+                if constexpr (L == 2)
+                    if (c.expired()) break;
+                const int32_t x = uni<G>(S.p[(int64_t)t * st]);
                 if (inj_hit<K>(lv.inj, v, x)) continue;
                 v[K - 2] = x;
                 uint32_t cnt = leaf_group<K, G, MODE>(d, c, v);
@@ -491,12 +529,14 @@ __device__ void search(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], ui
     } else {
         if constexpr (LEAF == 3 && L == K - 3 && !IEP) {
             if (d.build_begin[L] == d.build_end[L]) {
-                flat_leaf<K, G, MODE>(d, c, v, S, lv.inj, acc, ovf);
+                flat_leaf<K, G, MODE>(d, c, v, S, st, lv.inj, acc, ovf);
                 return;
             }
         }
         for (int32_t t = 0; t < S.n; ++t) {
-            const int32_t x = uni<G>(S.p[t]);
+            if constexpr (L == 2)
+                if (c.expired()) break;
+            const int32_t x = uni<G>(S.p[(int64_t)t * st]);
             if (inj_hit<K>(lv.inj, v, x)) continue;
             v[L] = x;
             run_builds<K, G, MODE>(d, c, L, v);
@@ -528,17 +568,25 @@ __global__ __launch_bounds__(kBlock) void count_kernel(GpPlanDesc d, CountArgs a
     c.lens = s_len[grp];
     uint64_t bytes = 0;
     c.bytes = &bytes;
+    c.sj = 0;
+    c.sJ = 1;
+    const uint64_t t_begin = a.busy ? wall_clock64() : 0;
+    c.deadline = a.busy && a.budget_ticks ? t_begin + a.budget_ticks : 0;
+    uint64_t chunk_max = 0;
+    bool stopped = false;
 
     uint64_t acc = 0;
     bool ovf = false;
     const int64_t chunk = a.chunk;
+    const int64_t split_tasks = a.split_roots * (int64_t)a.split_ways;
 
     for (;;) {
         unsigned long long t0 = 0;
         if (c.g.gl == 0) t0 = atomicAdd(a.queue, (unsigned long long)chunk);
         t0 = (unsigned long long)uni64<G>((int64_t)c.g.bcast(t0, 0));
-        if ((int64_t)t0 >= a.n_roots) break;
-        const int64_t t1 = min((int64_t)t0 + chunk, a.n_roots);
+        if ((int64_t)t0 >= a.n_tasks) break;
+        const int64_t t1 = min((int64_t)t0 + chunk, a.n_tasks);
+        const uint64_t t_chunk = a.busy ? wall_clock64() : 0;
         if constexpr (IEP && K == 4) {
             // the root is the last outer level
             if (d.build_begin[1] == d.build_end[1]) {
@@ -586,7 +634,17 @@ __global__ __launch_bounds__(kBlock) void count_kernel(GpPlanDesc d, CountArgs a
                 }
             }
         } else {
-            for (int64_t r = (int64_t)t0; r < t1; ++r) {
+            for (int64_t t = (int64_t)t0; t < t1; ++t) {
+                int64_t r = t;
+                if (t < split_tasks) {
+                    r = t / a.split_ways;
+                    c.sj = (int32_t)(t - r * a.split_ways);
+                    c.sJ = a.split_ways;
+                } else {
+                    r = t - split_tasks + a.split_roots;
+                    c.sj = 0;
+                    c.sJ = 1;
+                }
                 int2 e = a.roots[a.root_offset + r * a.root_stride];
                 e.x = uni<G>(e.x);
                 e.y = uni<G>(e.y);
@@ -615,6 +673,14 @@ __global__ __launch_bounds__(kBlock) void count_kernel(GpPlanDesc d, CountArgs a
                 }
             }
         }
+        if (a.busy) {
+            const uint64_t now = wall_clock64();
+            chunk_max = max(chunk_max, now - t_chunk);
+            if (c.deadline && now > c.deadline) {
+                stopped = true;
+                break;
+            }
+        }
     }
 
     // wavefront reduction with carry detection, one atomic per wavefront
@@ -631,10 +697,20 @@ __global__ __launch_bounds__(kBlock) void count_kernel(GpPlanDesc d, CountArgs a
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) bytes += __shfl_xor(bytes, off, 64);
     }
+    uint64_t cm = chunk_max;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) cm = max(cm, (uint64_t)__shfl_xor(cm, off, 64));
+    const bool any_stop = __ballot(stopped) != 0;
     if (__lane_id() == 0) {
         unsigned long long old = atomicAdd(&a.result[0], (unsigned long long)s);
         if (any_ovf || old + s < old) atomicOr(&a.result[1], 1ull);
+        if (any_stop) atomicOr(&a.result[1], 4ull);
         if constexpr (MODE == MODE_ACCOUNT) atomicAdd(&a.result[2], (unsigned long long)bytes);
+        if (a.busy) {
+            atomicAdd(&a.busy[0], (unsigned long long)(wall_clock64() - t_begin));
+            atomicAdd(&a.busy[1], 1ull);
+            atomicMax(&a.busy[2], (unsigned long long)cm);
+        }
     }
 }
 

@@ -165,12 +165,29 @@ __global__ void scatter_roots(const int64_t* row_ptr, const int2* roots_all, int
     }
 }
 
-__global__ void fill_hub_bits(const int2* roots_all, int64_t n_entries, int64_t words,
-                              uint32_t* bits) {
+// Root arrays ordered by their smaller endpoint, which in the degree-sorted
+// layout is the higher-degree one: the heaviest roots come first (they start
+// first, and the kernel can split a prefix of them). roots_upper stays in CSR
+// order (v0 < v1, v0 ascending); roots_lower holds the same edges reversed in
+// the same order; roots_all interleaves the two.
+__global__ void order_roots(const int2* roots_upper, int64_t n_upper, int2* roots_lower, int2* roots_all) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n_upper;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int2 u = roots_upper[k];
+        const int2 r = make_int2(u.y, u.x);
+        roots_lower[k] = r;
+        roots_all[2 * k] = u;
+        roots_all[2 * k + 1] = r;
+    }
+}
+
+__global__ void fill_hub_bits(const int64_t* row_ptr, const int32_t* col, int64_t n_hubs,
+                              int64_t n_entries, int64_t words, uint32_t* bits) {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n_entries;
          e += (int64_t)gridDim.x * blockDim.x) {
-        int2 r = roots_all[e];
-        atomicOr(&bits[(int64_t)r.x * words + (r.y >> 5)], 1u << (r.y & 31));
+        const int64_t v = row_of(row_ptr, n_hubs, e);
+        const int32_t w = col[e];
+        atomicOr(&bits[v * words + (w >> 5)], 1u << (w & 31));
     }
 }
 
@@ -315,6 +332,17 @@ gp_status build_layout(const int64_t* row_ptr, const int32_t* col, int64_t n, in
         hipLaunchKernelGGL(scatter_roots, dim3(grid_for(nnz)), dim3(256), 0, s, g->row_ptr, g->roots_all,
                            n, nnz, lower_cnt, lower_off, upper_off, g->roots_lower, g->roots_upper);
     GP_HIP_TRY(hipGetLastError());
+    if (hv[0] != hv[1] || hv[0] + hv[1] != nnz) return GP_ERR_INTERNAL;  // validated symmetric, loop-free
+    if (hv[1] > 0)
+        hipLaunchKernelGGL(order_roots, dim3(grid_for(hv[1])), dim3(256), 0, s, g->roots_upper, hv[1],
+                           g->roots_lower, g->roots_all);
+    GP_HIP_TRY(hipGetLastError());
+    // upper_pref[i]: roots of each ordered array per orientation whose smaller
+    // endpoint is below 2^i
+    for (int i = 0; i < 32; ++i) {
+        const int64_t v = std::min<int64_t>(int64_t(1) << i, n);
+        GP_HIP_TRY(hipMemcpyAsync(&g->upper_pref[i], upper_off + v, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    }
     GP_HIP_TRY(hipStreamSynchronize(s));
     g->n = n;
     g->nnz = nnz;
@@ -347,8 +375,8 @@ gp_status build_hub_bitmaps(DeviceGraph* g, int64_t min_degree, int64_t budget_b
     GP_HIP_TRY(hipMalloc((void**)&g->hub_bits, (size_t)(h * per)));
     GP_HIP_TRY(hipMemsetAsync(g->hub_bits, 0, (size_t)(h * per), s));
     const int64_t entries = rp[h];
-    hipLaunchKernelGGL(fill_hub_bits, dim3(grid_for(entries)), dim3(256), 0, s, g->roots_all, entries,
-                       g->hub_words, g->hub_bits);
+    hipLaunchKernelGGL(fill_hub_bits, dim3(grid_for(entries)), dim3(256), 0, s, g->row_ptr, g->col, h,
+                       entries, g->hub_words, g->hub_bits);
     GP_HIP_TRY(hipGetLastError());
     GP_HIP_TRY(hipStreamSynchronize(s));
     g->n_hubs = (int32_t)h;

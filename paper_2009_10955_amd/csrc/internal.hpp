@@ -13,13 +13,16 @@ namespace gpint {
 struct DeviceGraph {
     int device = 0;
     int num_cus = 0;
+    double wall_khz = 100000;  // rate of the device's constant wall clock
     int64_t n = 0, nnz = 0;
     int64_t* row_ptr = nullptr;   // n+1
     int32_t* col = nullptr;       // nnz
-    int2* roots_all = nullptr;    // every directed entry (v0, v1), CSR order
-    int2* roots_lower = nullptr;  // entries with v1 < v0, CSR order
+    // Root edges, ordered by their smaller endpoint (heaviest first):
     int2* roots_upper = nullptr;  // entries with v1 > v0, CSR order
+    int2* roots_lower = nullptr;  // entries with v1 < v0: roots_upper reversed, same order
+    int2* roots_all = nullptr;    // every directed entry: the two interleaved
     int64_t n_lower = 0, n_upper = 0;
+    int64_t upper_pref[32] = {};  // roots_upper entries with v0 < 2^i
     int32_t* new_id = nullptr;    // original id -> layout id
     uint32_t* hub_bits = nullptr; // dense neighbor bitmaps of vertices [0, n_hubs)
     int64_t hub_words = 0;        // uint32 words per bitmap = ceil(n / 32)
@@ -36,15 +39,24 @@ struct LaunchCfg {
     int leaf = 1;
     int64_t root_stride = 1;  // count only roots[offset + t * stride]
     int64_t root_offset = 0;
+    // roots whose smaller endpoint is below split_vertices (rounded down to a
+    // power of two) run as split_ways tasks each; 1: no splitting
+    int split_ways = 1;
+    int64_t split_vertices = 0;
+    double budget_ms = 0;  // time limit per wavefront (measurement only; 0: none)
 };
 
 // Launch one count of plan d over g on `stream`. result_dev: {count,
 // overflow flag} (plus algorithmic bytes when `account`), zeroed by this call
 // on the stream. per_root may be null. Scratch is allocated stream-ordered
 // and released after the kernel.
+// Wavefronts per compute unit that a launch of d with cfg keeps resident.
+int resident_waves_per_cu(const GpPlanDesc& d, const LaunchCfg& cfg);
+
 gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCfg& cfg,
                        hipStream_t stream, unsigned long long* result_dev,
-                       unsigned long long* per_root, bool account = false);
+                       unsigned long long* per_root, bool account = false,
+                       unsigned long long* busy = nullptr);
 
 // Device state of one batched launch: descriptors, per-plan task ranges,
 // scratch, queue and results, all allocated up front so that the launch

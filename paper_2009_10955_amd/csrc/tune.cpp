@@ -12,6 +12,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -62,25 +64,55 @@ struct Cached {
 std::mutex g_cache_mu;
 std::map<std::tuple<uint64_t, int64_t, int, std::vector<std::pair<int, int>>>, Cached> g_cache;
 
-// Time one launch (ms) on stream s; negative on failure.
-double time_launch(const gpint::DeviceGraph& g, const GpPlanDesc& d, const gpint::LaunchCfg& cfg,
+// One measured launch of a root sample. The kernel reports the summed
+// active time of its wavefronts and the longest chunk of tasks any of them
+// ran; with the sample's stride these give the full run's time as
+//   max(busy * stride / resident wavefronts, longest chunk):
+// the balanced share of the work, or the tail of the heaviest task, whichever
+// is longer. Wall time of a small sample alone mostly measures that tail.
+struct Timing {
+    double wall = -1;   // ms, negative on failure
+    double busy = 0;    // wavefront-ms
+    double chunk = 0;   // ms
+    long long waves = 0;
+    bool stopped = false;  // hit the time budget: slower than the budget allows
+};
+
+Timing time_launch(const gpint::DeviceGraph& g, const GpPlanDesc& d, const gpint::LaunchCfg& cfg,
                    hipStream_t s, unsigned long long* res) {
+    Timing out;
     hipEvent_t a, b;
-    if (hipEventCreate(&a) != hipSuccess) return -1;
+    if (hipEventCreate(&a) != hipSuccess) return out;
     if (hipEventCreate(&b) != hipSuccess) {
         (void)hipEventDestroy(a);
-        return -1;
+        return out;
     }
-    double ms = -1;
+    unsigned long long h[5] = {0, 0, 0, 0, 0};
     if (hipEventRecord(a, s) == hipSuccess &&
-        gpint::launch_count(g, d, cfg, s, res, nullptr, false) == GP_OK &&
-        hipEventRecord(b, s) == hipSuccess && hipEventSynchronize(b) == hipSuccess) {
+        gpint::launch_count(g, d, cfg, s, res, nullptr, false, res + 2) == GP_OK &&
+        hipEventRecord(b, s) == hipSuccess &&
+        hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, s) == hipSuccess &&
+        hipStreamSynchronize(s) == hipSuccess) {
         float f = 0;
-        if (hipEventElapsedTime(&f, a, b) == hipSuccess) ms = f;
+        if (hipEventElapsedTime(&f, a, b) == hipSuccess) {
+            out.wall = f;
+            out.stopped = (h[1] & 4ull) != 0;
+            out.busy = (double)h[2] / g.wall_khz;
+            out.waves = (long long)h[3];
+            out.chunk = (double)h[4] / g.wall_khz;
+        }
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    return ms;
+    return out;
+}
+
+bool verbose() {
+    static const bool v = [] {
+        const char* e = std::getenv("GP_TUNE_VERBOSE");
+        return e && *e && *e != '0';
+    }();
+    return v;
 }
 
 }  // namespace
@@ -131,7 +163,7 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
     gp_status st = GP_OK;
     unsigned long long* res = nullptr;
     if (!np->tuned) {
-        if (hipMallocAsync((void**)&res, 3 * sizeof(unsigned long long), s) != hipSuccess) {
+        if (hipMallocAsync((void**)&res, 5 * sizeof(unsigned long long), s) != hipSuccess) {  // {count, flags, busy[3]}
             delete np;
             return GP_ERR_HIP;
         }
@@ -181,101 +213,167 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
             add(reps[r.i], mirror(p->sets[r.j], k));
         }
 
-        // 2. sample stride: about 40 ms for the planner's own configuration
-        gpint::LaunchCfg base = gpint::default_launch(p->desc);
-        int64_t stride = o.sample_stride;
         double spent = 0;
-        if (stride <= 0) {
-            int64_t roots = std::max<int64_t>(1, g->dg.nnz);
-            stride = std::max<int64_t>(1, roots / 2048);
-            base.root_stride = stride;
-            base.root_offset = stride / 2;
-            double t = time_launch(g->dg, p->desc, base, s, res);
-            if (t < 0) st = GP_ERR_HIP;
-            spent += std::max(0.0, t);
-            if (st == GP_OK && t > 0) {
-                double want = 40.0;
-                stride = std::max<int64_t>(1, (int64_t)((double)stride * t / want));
+        const double inf = 1e300;
+        double best_est = inf;  // best full-run estimate so far (ms)
+        // full-run estimate (ms) of one sampled launch; inf if it failed or stopped
+        auto measure = [&](const GpPlanDesc& d, gpint::LaunchCfg cfg, int64_t str, const char* what,
+                           size_t c, bool saturate = false) -> double {
+            if (saturate) {
+                // comparing launch shapes: the sample must keep every resident
+                // group of this shape busy (about two tasks each, one per grab),
+                // or narrower groups run with less contention than they will
+                const int64_t groups = (int64_t)g->dg.num_cus * gpint::resident_waves_per_cu(d, cfg) *
+                                       (64 / std::max(1, cfg.group));
+                const int64_t roots = gpint::root_task_count(g->dg, d);
+                str = std::max<int64_t>(1, std::min<int64_t>(str, roots / std::max<int64_t>(1, 2 * groups)));
+                cfg.chunk = 1;
             }
-        }
-        base.root_stride = stride;
-        base.root_offset = stride / 2;
-
-        // 3. time each configuration: all of them on a sample 8x sparser,
-        //    then the four fastest again on the full sample
-        auto run_sample = [&](size_t c, int64_t str) -> double {
-            gpint::LaunchCfg cfg = gpint::default_launch(cands[c].desc);
             cfg.root_stride = str;
             cfg.root_offset = str / 2;
-            return time_launch(g->dg, cands[c].desc, cfg, s, res);
+            cfg.budget_ms = best_est < inf ? std::max(20.0, 3.0 * best_est) : 0.0;
+            Timing t = time_launch(g->dg, d, cfg, s, res);
+            if (t.wall < 0) {
+                st = GP_ERR_HIP;
+                return -1;
+            }
+            spent += t.wall;
+            const double resident = (double)g->dg.num_cus * gpint::resident_waves_per_cu(d, cfg);
+            // a sample of stride 1 is the full run: its wall time is the answer
+            const double est = t.stopped ? inf
+                               : str == 1 ? t.wall
+                                          : std::max(t.busy * (double)str / resident, t.chunk);
+            if (verbose())
+                std::fprintf(stderr,
+                             "gp_plan_tune %s cand %zu stride %lld group %d leaf %d waves %d split %dx%lld: "
+                             "wall %.3f ms, busy %.1f wave-ms over %lld wavefronts, longest chunk %.3f ms%s, "
+                             "estimate %.3f ms\n",
+                             what, c, (long long)str, cfg.group, cfg.leaf, cfg.waves_per_cu, cfg.split_ways,
+                             (long long)cfg.split_vertices, t.wall, t.busy, t.waves, t.chunk,
+                             t.stopped ? " (stopped)" : "", est < inf ? est : -1.0);
+            if (est < best_est) best_est = est;
+            return est;
         };
+
+        // 2. sample stride: the planner's configuration gives the work; the
+        //    sample keeps a balanced share of about 8 ms of it
+        const gpint::LaunchCfg base = gpint::default_launch(p->desc);
+        int64_t stride = o.sample_stride;
+        if (stride <= 0) {
+            const int64_t roots = std::max<int64_t>(1, gpint::root_task_count(g->dg, p->desc));
+            const int64_t s0 = std::max<int64_t>(1, roots / 4096);
+            gpint::LaunchCfg cfg = base;
+            cfg.root_stride = s0;
+            cfg.root_offset = s0 / 2;
+            Timing t = time_launch(g->dg, p->desc, cfg, s, res);
+            if (t.wall < 0) st = GP_ERR_HIP;
+            spent += std::max(0.0, t.wall);
+            const double resident = (double)g->dg.num_cus * gpint::resident_waves_per_cu(p->desc, base);
+            const double full_ms = t.busy * (double)s0 / resident;
+            stride = std::max<int64_t>(1, (int64_t)(full_ms / 8.0));
+            stride = std::min(stride, s0);
+            if (verbose())
+                std::fprintf(stderr, "gp_plan_tune calibration: %lld roots, balanced full run ~%.1f ms, stride %lld\n",
+                             (long long)roots, full_ms, (long long)stride);
+        }
+
+        // 3. every configuration on a sample 4x sparser, then the four best
+        //    again on the full sample, all with the default launch shape
         std::vector<std::pair<double, size_t>> coarse;
         int measured = 0;
         for (size_t c = 0; st == GP_OK && c < cands.size(); ++c) {
             if (spent > budget_ms && measured > 0) break;
-            double t = run_sample(c, base.root_stride * 8);
-            if (t < 0) {
-                st = GP_ERR_HIP;
-                break;
-            }
-            spent += t;
+            double t = measure(cands[c].desc, base, stride * 4, "coarse", c);
+            if (t < 0) break;
             ++measured;
             coarse.push_back({t, c});
         }
         std::stable_sort(coarse.begin(), coarse.end());
-        size_t best = coarse.empty() ? 0 : coarse[0].second;
-        double best_ms = -1;
+        std::vector<std::pair<double, size_t>> fine;
+        best_est = inf;
         for (size_t r = 0; st == GP_OK && r < coarse.size() && r < 4; ++r) {
-            if (spent > 1.5 * budget_ms && best_ms >= 0) break;
-            double t = run_sample(coarse[r].second, base.root_stride);
-            if (t < 0) {
-                st = GP_ERR_HIP;
-                break;
-            }
-            spent += t;
-            if (best_ms < 0 || t < best_ms) {
-                best_ms = t;
-                best = coarse[r].second;
-            }
+            if (spent > 1.5 * budget_ms && !fine.empty()) break;
+            if (coarse[r].first >= inf && !fine.empty()) break;
+            size_t c = coarse[r].second;
+            double t = measure(cands[c].desc, base, stride, "fine", c);
+            if (t < 0) break;
+            fine.push_back({t, c});
         }
-        gpint::LaunchCfg best_launch = gpint::default_launch(cands[best].desc);
+        std::stable_sort(fine.begin(), fine.end());
 
-        // 4. launch shape for the chosen configuration
-        if (st == GP_OK && o.tune_launch >= 0) {
-            const GpPlanDesc& bd = cands[best].desc;
-            const GpLevel& leaf = bd.lv[k - 1];
-            const bool leaf_intersects = !bd.iep && (k <= 3 || leaf.last_list >= 0);
-            const bool can_flatten = k >= 5 && !bd.iep && bd.build_begin[k - 3] == bd.build_end[k - 3];
-            double best_l = -1;
-            for (int grp : {64, 32, 16, 8}) {
-                if (bd.iep && grp < 32) continue;
-                for (int lm : {1, 2, 3}) {
-                    if (lm == 2 && !leaf_intersects) continue;
-                    if (lm == 3 && !can_flatten) continue;
-                    for (int w : {16, 32}) {
-                        if (spent > 2.5 * budget_ms && best_l >= 0) break;
-                        gpint::LaunchCfg cfg = best_launch;
+        // 4. launch shape for the two best configurations: group width and
+        //    leaf mode change which configuration is fastest. Root splitting
+        //    stays on: the tail it removes comes from the few heaviest roots,
+        //    which a strided sample mostly misses, and it costs little
+        struct Pick {
+            double est;
+            size_t c;
+            gpint::LaunchCfg launch;
+        };
+        std::vector<Pick> picks;
+        const int n_shape = o.tune_launch >= 0 ? 2 : 1;
+        for (size_t r = 0; st == GP_OK && r < fine.size() && (int)r < n_shape; ++r) {
+            const size_t c = fine[r].second;
+            Pick pk{fine[r].first, c, base};
+            if (o.tune_launch >= 0) {
+                best_est = inf;
+                pk.est = measure(cands[c].desc, base, stride, "shape", c, true);
+                if (pk.est < 0) break;
+                const GpPlanDesc& bd = cands[c].desc;
+                const GpLevel& leaf = bd.lv[k - 1];
+                const bool leaf_intersects = !bd.iep && (k <= 3 || leaf.last_list >= 0);
+                const bool can_flatten = k >= 5 && !bd.iep && bd.build_begin[k - 3] == bd.build_end[k - 3];
+                for (int grp : {64, 32, 16, 8}) {
+                    if (bd.iep && grp < 32) continue;
+                    double best_g = inf;
+                    for (int lm : {1, 2, 3}) {
+                        if (lm == 2 && !leaf_intersects) continue;
+                        if (lm == 3 && !can_flatten) continue;
+                        if (spent > 2.5 * budget_ms) break;
+                        gpint::LaunchCfg cfg = base;
                         cfg.group = grp;
                         cfg.leaf = lm;
-                        cfg.waves_per_cu = w;
-                        cfg.root_stride = base.root_stride;
-                        cfg.root_offset = base.root_offset;
-                        double t = time_launch(g->dg, cands[best].desc, cfg, s, res);
-                        if (t < 0) {
-                            st = GP_ERR_HIP;
-                            break;
+                        if (grp == base.group && lm == base.leaf) {
+                            best_g = std::min(best_g, pk.est);
+                            continue;
                         }
-                        spent += t;
-                        if (best_l < 0 || t < best_l) {
-                            best_l = t;
-                            best_launch = cfg;
+                        double t = measure(bd, cfg, stride, "shape", c, true);
+                        if (t < 0) break;
+                        best_g = std::min(best_g, t);
+                        if (t < pk.est) {
+                            pk.est = t;
+                            pk.launch = cfg;
                         }
                     }
+                    if (st != GP_OK) break;
+                    // narrower groups only get slower once they lose by 1.5x
+                    if (best_g > 1.5 * pk.est) break;
                 }
             }
-            best_launch.root_stride = 1;
-            best_launch.root_offset = 0;
+            picks.push_back(pk);
         }
+        // 5. the two finalists once more on a sample 4x denser
+        if (st == GP_OK && picks.size() > 1 && spent < 3.0 * budget_ms && stride >= 4) {
+            best_est = inf;
+            for (auto& pk : picks) {
+                double t = measure(cands[pk.c].desc, pk.launch, std::max<int64_t>(1, stride / 4), "final", pk.c,
+                                   true);
+                if (t < 0) break;
+                pk.est = t;
+            }
+        }
+        size_t best = fine.empty() ? 0 : fine[0].second;
+        gpint::LaunchCfg best_launch = base;
+        if (!picks.empty()) {
+            const Pick* bp = &picks[0];
+            for (auto& pk : picks)
+                if (pk.est < bp->est) bp = &pk;
+            best = bp->c;
+            best_launch = bp->launch;
+        }
+        best_launch.root_stride = 1;
+        best_launch.root_offset = 0;
+        best_launch.budget_ms = 0;
         if (st == GP_OK) {
             np->order = cands[best].order;
             np->set = cands[best].rel;

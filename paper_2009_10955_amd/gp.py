@@ -56,7 +56,8 @@ class PlanOpts(ctypes.Structure):
 class Launch(ctypes.Structure):
     _fields_ = [("group", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("leaf_mode", ctypes.c_int32),
-                ("root_stride", ctypes.c_int32), ("root_offset", ctypes.c_int32)]
+                ("root_stride", ctypes.c_int32), ("root_offset", ctypes.c_int32),
+                ("split_ways", ctypes.c_int32), ("split_vertices", ctypes.c_int32)]
 
 
 class TuneOpts(ctypes.Structure):
@@ -174,8 +175,10 @@ def _stream_handle(stream) -> int:
     return stream.cuda_stream
 
 
-def _launch(group=0, waves_per_cu=0, chunk=0, leaf_mode=0, root_stride=0, root_offset=0) -> Launch:
-    return Launch(group, waves_per_cu, chunk, leaf_mode, root_stride, root_offset)
+def _launch(group=0, waves_per_cu=0, chunk=0, leaf_mode=0, root_stride=0, root_offset=0,
+            split_ways=0, split_vertices=0) -> Launch:
+    return Launch(group, waves_per_cu, chunk, leaf_mode, root_stride, root_offset, split_ways,
+                  split_vertices)
 
 
 class Graph:
@@ -343,7 +346,8 @@ class Plan:
 
     def launch(self) -> dict:
         l = self.info().launch
-        return dict(group=l.group, waves_per_cu=l.waves_per_cu, chunk=l.chunk, leaf_mode=l.leaf_mode)
+        return dict(group=l.group, waves_per_cu=l.waves_per_cu, chunk=l.chunk, leaf_mode=l.leaf_mode,
+                    split_ways=l.split_ways, split_vertices=l.split_vertices)
 
     def close(self) -> None:
         if self._h:

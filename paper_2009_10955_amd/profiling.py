@@ -62,9 +62,12 @@ def counter_per_dispatch(path_glob: str, counter: str) -> list:
 
 
 def traffic_summary(fetch_glob: str, write_glob: str, kernel_match: str, copy_bytes: int,
-                    pattern: str, workload: str) -> dict:
+                    pattern: str, workload: str, plan: dict | None = None,
+                    l2_glob: str | None = None) -> dict:
     """HBM bytes of the longest dispatch whose name contains kernel_match,
-    with FETCH_SIZE / WRITE_SIZE scaled by the copy kernel's readings."""
+    with FETCH_SIZE / WRITE_SIZE scaled by the copy kernel's readings; plus
+    the L2 hit rate (TCC_HIT_sum / (TCC_HIT_sum + TCC_MISS_sum)) if given.
+    `plan` records the configuration the counters were taken with."""
     fetch = counter_per_dispatch(fetch_glob, "FETCH_SIZE")
     write = counter_per_dispatch(write_glob, "WRITE_SIZE")
 
@@ -84,17 +87,46 @@ def traffic_summary(fetch_glob: str, write_glob: str, kernel_match: str, copy_by
     hbm = None
     if None not in (f_scale, w_scale, kf, kw):
         hbm = kf * 1024.0 * f_scale + kw * 1024.0 * w_scale
+    l2 = None
+    if l2_glob:
+        hit = kernel_value(counter_per_dispatch(l2_glob, "TCC_HIT_sum"))
+        miss = kernel_value(counter_per_dispatch(l2_glob, "TCC_MISS_sum"))
+        if hit is not None and miss is not None and hit + miss > 0:
+            l2 = {"hits": hit, "misses": miss, "hit_rate": hit / (hit + miss)}
     return {"workload": workload, "pattern": pattern, "kernel_match": kernel_match,
             "fetch_kib": kf, "write_kib": kw, "copy_fetch_kib": cf, "copy_write_kib": cw,
             "copy_bytes": copy_bytes, "fetch_scale": f_scale, "write_scale": w_scale,
-            "hbm_bytes_per_launch": hbm, "kernel_source_hash": kernel_source_hash()}
+            "hbm_bytes_per_launch": hbm, "l2": l2, "plan": plan,
+            "kernel_source_hash": kernel_source_hash()}
+
+
+def same_plan(a: dict | None, b: dict | None) -> bool:
+    """Whether two recorded configurations (order, restrictions, launch) agree."""
+    if not a or not b:
+        return False
+    keys = ("order", "restrictions", "launch")
+    return all(json.dumps(a.get(k), sort_keys=True) == json.dumps(b.get(k), sort_keys=True)
+               for k in keys)
 
 
 def main(argv):
-    """python -m paper_2009_10955_amd.profiling FETCH_GLOB WRITE_GLOB KERNEL_MATCH COPY_MIB PATTERN WORKLOAD OUT"""
-    fg, wg, km, mib, pat, wl, out = argv
-    s = traffic_summary(fg, wg, km, int(mib) << 20, pat, wl)
-    with open(out, "w") as f:
+    """python -m paper_2009_10955_amd.profiling FETCH_GLOB WRITE_GLOB KERNEL_MATCH COPY_MIB
+    PATTERN WORKLOAD OUT [--plans BENCH_JSON] [--l2 L2_GLOB]"""
+    import argparse
+    ap = argparse.ArgumentParser(prog="python -m paper_2009_10955_amd.profiling")
+    for name in ("fetch_glob", "write_glob", "kernel_match", "copy_mib", "pattern", "workload", "out"):
+        ap.add_argument(name)
+    ap.add_argument("--plans", help="bench.py output whose plan for PATTERN the counters ran")
+    ap.add_argument("--l2", help="counter files with TCC_HIT_sum and TCC_MISS_sum")
+    a = ap.parse_args(argv)
+    plan = None
+    if a.plans:
+        with open(a.plans) as f:
+            plan = json.loads(f.read().strip().splitlines()[-1])["plans"][a.pattern]
+        plan = {k: plan[k] for k in ("order", "restrictions", "launch")}
+    s = traffic_summary(a.fetch_glob, a.write_glob, a.kernel_match, int(a.copy_mib) << 20, a.pattern,
+                        a.workload, plan, a.l2)
+    with open(a.out, "w") as f:
         json.dump(s, f, indent=1)
     print(json.dumps(s))
 

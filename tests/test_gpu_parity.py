@@ -26,7 +26,8 @@ def _gpu():
 
 
 def _count(graph, k, e, **kw):
-    launch = {x: kw.pop(x) for x in ("group", "leaf_mode", "chunk", "waves_per_cu") if x in kw}
+    launch = {x: kw.pop(x) for x in ("group", "leaf_mode", "chunk", "waves_per_cu", "split_ways",
+                                     "split_vertices") if x in kw}
     plan = gp.Plan(k, e, stats=graph.stats(), **kw)
     return gp.count(graph, plan, **launch)
 
@@ -79,6 +80,64 @@ def test_config0_counts(pname):
     want = O.count(g, k, e)
     for v in VARIANTS:
         assert _count(graph, k, e, **v) == want, v
+
+
+# ------------------------------------------------------- split root tasks
+
+SPLITS = [dict(split_ways=w, split_vertices=v) for w, v in
+          [(1, 0), (2, 1 << 20), (3, 8), (7, 1 << 20), (64, 1 << 20), (16, 1)]]
+
+
+@pytest.mark.parametrize("pname", ["4-cycle", "4-clique", "diamond", "house", "5-cycle",
+                                   "6-cycle-chord", "prism", "5-wheel"])
+def test_split_roots_equal_oracle(pname):
+    """Heavy roots run as several tasks over disjoint slices of their
+    level-2 candidates: every split, group width and leaf mode gives the
+    oracle's count, also with one root per queue grab."""
+    g = I.config_graph(0)
+    graph = gp.Graph.from_csr(g, device=True)
+    k, e = P[pname]
+    want = O.count(g, k, e)
+    for sp in SPLITS:
+        for v in (dict(group=64, leaf_mode=1), dict(group=16, leaf_mode=2),
+                  dict(group=32, leaf_mode=3, chunk=1), dict(group=8, leaf_mode=1, chunk=3)):
+            assert _count(graph, k, e, **sp, **v) == want, (sp, v)
+
+
+def test_split_roots_with_hubs_and_sampling():
+    """A hub-heavy graph (hub bitmaps on): split counts equal unsplit ones,
+    and strided root samples of a split launch still partition the count."""
+    g = I.config_graph(2)
+    graph = gp.Graph.from_csr(g, device=True)
+    for pname in ["4-cycle", "house", "5-cycle"]:
+        plan = gp.Plan(*P[pname], stats=graph.stats())
+        want = gp.count(graph, plan, split_ways=1)
+        for ways, verts in [(16, 256), (5, 1 << 20), (128, 4)]:
+            assert gp.count(graph, plan, split_ways=ways, split_vertices=verts) == want, (pname, ways)
+        parts = [gp.count(graph, plan, root_stride=5, root_offset=o, split_ways=9,
+                          split_vertices=1 << 20) for o in range(5)]
+        assert sum(parts) == want, pname
+
+
+def test_split_roots_iep():
+    g = I.config_graph(0)
+    graph = gp.Graph.from_csr(g, device=True)
+    for pname in ["house", "k4-path", "6-cycle-chord"]:
+        k, e = P[pname]
+        plan = gp.Plan(k, e, stats=graph.stats(), iep=True)
+        assert plan.info().iep == 1
+        want = O.count(g, k, e)
+        for sp in SPLITS:
+            assert gp.count(graph, plan, group=64, **sp) == want, (pname, sp)
+
+
+def test_bad_split_is_rejected():
+    graph = gp.Graph.from_csr(I.config_graph(0), device=True)
+    plan = gp.Plan(*P["house"], stats=graph.stats())
+    for bad in (dict(split_ways=-1), dict(split_ways=5000), dict(split_vertices=-3)):
+        with pytest.raises(gp.GpError) as ei:
+            gp.count(graph, plan, **bad)
+        assert ei.value.status == -1
 
 
 # ------------------------------------------------------------- closed forms

@@ -29,12 +29,24 @@ HBM_PEAK_GBPS = 8000.0
 METRIC = "embeddings/s + intersection HBM GB/s; batched-vs-plain speedup, exact counts"
 
 WORKLOADS = {
-    # name: (config graph index, patterns, description)
+    # name: (config graph index, patterns, description, mode)
     "rmat17": (1, ["house", "5-cycle", "5-clique"],
                "R-MAT scale 17, edge factor 8, (0.57,0.19,0.19,0.05), seed 2; house, 5-cycle, "
-               "5-clique, one launch each"),
+               "5-clique, one launch each", "plain"),
     "er1000": (0, ["triangle", "4-cycle", "4-clique"],
-               "G(1000, 0.01) seed 1; triangle, 4-cycle, 4-clique, one launch each"),
+               "G(1000, 0.01) seed 1; triangle, 4-cycle, 4-clique, one launch each", "plain"),
+    "chunglu7000": (2, ["6-cycle", "6-cycle-chord", "prism", "k4-path", "5-wheel", "6-clique"],
+                    "Chung-Lu n=7000, gamma 2.1, ~100k edges, seed 3; six 6-vertex patterns in one "
+                    "persistent launch captured in a hipGraph, against one launch per pattern",
+                    "batched"),
+    "rmat22": (3, ["4-clique", "house", "5-cycle", "6-cycle-chord"],
+               "R-MAT scale 22, edge factor 8, (0.57,0.19,0.19,0.05), seed 4; 4-clique, house, "
+               "5-cycle, 6-cycle+chord in one persistent launch against one launch per pattern "
+               "(patterns estimated above --max-pattern-s are reported, not run)", "batched"),
+    "serve": (None, None,
+              "serving: R-MAT-17, Chung-Lu 7000 and R-MAT-22 resident; Poisson stream of 2,000 "
+              "queries at 50 QPS, seed 5, each a uniform draw from the 141 connected 3-6-vertex "
+              "pattern classes on a uniform graph", "serve"),
 }
 
 
@@ -59,6 +71,17 @@ def parse_args():
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_rmat17.json"),
                     help="HBM bytes per launch from rocprofv3 counters (used only while the "
                          "kernel sources it was taken from are unchanged)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="use the model's configurations and the default launch shape")
+    ap.add_argument("--max-pattern-s", type=float, default=30.0,
+                    help="batched workloads: patterns whose full run is estimated above this are "
+                         "reported with their extrapolation instead of run")
+    ap.add_argument("--batch-group", type=int, default=64)
+    ap.add_argument("--batch-leaf", type=int, default=3)
+    ap.add_argument("--queries", type=int, default=2000, help="serve: stream length")
+    ap.add_argument("--qps", type=float, default=50.0, help="serve: mean arrival rate")
+    ap.add_argument("--max-query-ms", type=float, default=1000.0,
+                    help="serve: reject queries whose measured estimate exceeds this")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     return ap.parse_args()
@@ -121,7 +144,7 @@ def cpu_baseline(g, plans, names, budget_s: float) -> dict:
     dt = time.perf_counter() - t0
     return {"value": found / dt if dt > 0 else 0.0, "unit": "embeddings/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{done} root edges drawn uniformly from the three plans' root tasks, each "
+            "sample": f"{done} root edges drawn uniformly from the {len(plans)} plans' root tasks, each "
                       f"counted by the CPU oracle with the first two schedule vertices pinned; "
                       f"{found} embeddings in {dt:.1f} s"}
 
@@ -141,7 +164,9 @@ def main():
     from paper_2009_10955_amd import inputs as I
 
     torch.cuda.set_device(0)
-    cfg_idx, names, desc = WORKLOADS[args.workload]
+    cfg_idx, names, desc, mode = WORKLOADS[args.workload]
+    if mode == "serve":
+        return serve_main(args, desc)
     if args.patterns:
         names = [n for n in names if n in args.patterns.split(",")]
     g = I.config_graph(cfg_idx)
@@ -156,10 +181,18 @@ def main():
         plans = [gp.Plan(*I.PATTERNS[n], stats=st, force_order=prev[n]["order"],
                          force_restr=[tuple(x) for x in prev[n]["restrictions"]]) for n in names]
         launches = [dict(prev[n]["launch"]) for n in names]
+    elif args.no_tune:
+        plans = base_plans
+        launches = [p.launch() for p in plans]
     else:
-        plans = [p.tuned(graph, budget_seconds=args.tune_seconds) for p in base_plans]
+        plans = []
+        for n, p in zip(names, base_plans):
+            plans.append(p.tuned(graph, budget_seconds=args.tune_seconds))
+            note(f"tuned {n}")
         launches = [p.launch() for p in plans]
     tune_s = time.perf_counter() - t_tune
+    if mode == "batched":
+        return batched_main(args, desc, g, graph, st, names, plans, launches, base_plans, plan_s, tune_s)
     stream = torch.cuda.current_stream()
     dev_out = torch.zeros(2 * len(plans), dtype=torch.int64, device="cuda")
 
@@ -274,6 +307,177 @@ def main():
         "preprocessing_s": {"load": st.load_seconds, "plan": plan_s, "tune": tune_s},
         "roofline": roofline,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def batched_main(args, desc, g, graph, st, names, plans, launches, base_plans, plan_s, tune_s):
+    """Batched workloads: the feasible patterns in ONE persistent launch
+    (replayed from a hipGraph), against one launch per pattern (each its own
+    launch and synchronisation), at identical counts."""
+    import torch
+    from paper_2009_10955_amd import gp
+
+    stream = torch.cuda.current_stream()
+    infeasible = {}
+    keep = []
+    for i, (n, p, l) in enumerate(zip(names, plans, launches)):
+        if p.info().iep:
+            keep.append(i)
+            continue
+        e = gp.estimate(graph, p, budget_ms=args.max_pattern_s * 1e3, stream=stream, **l)
+        note(f"estimate {n}: {e['ms'] / 1e3:.2f} s (sample 1/{e['sample_stride']}: "
+             f"{e['sample_count']} embeddings)")
+        if e["ms"] > args.max_pattern_s * 1e3:
+            infeasible[n] = {"estimated_s": None if e["ms"] == float("inf") else e["ms"] / 1e3,
+                             "estimate_note": "a wavefront of the root sample alone ran past the "
+                                              "limit" if e["ms"] == float("inf") else
+                                              "wavefront busy time of the root sample, scaled",
+                             "sample_stride": e["sample_stride"],
+                             "sample_count": e["sample_count"],
+                             "count_extrapolated": e["sample_count"] * e["sample_stride"]}
+        else:
+            keep.append(i)
+    names = [names[i] for i in keep]
+    plans = [plans[i] for i in keep]
+    launches = [launches[i] for i in keep]
+    base_plans = [base_plans[i] for i in keep]
+    if not plans:
+        raise SystemExit("no pattern of the workload is feasible within --max-pattern-s")
+    blaunch = dict(group=args.batch_group, leaf_mode=args.batch_leaf)
+    batch = gp.Batch(graph, plans, stream, **blaunch)
+
+    plain_each = [[] for _ in plans]
+
+    def plain_step():
+        out = []
+        for i, (p, l) in enumerate(zip(plans, launches)):
+            t = time.perf_counter()
+            out.append(gp.count(graph, p, stream, **l))
+            plain_each[i].append((time.perf_counter() - t) * 1e3)
+        return out
+
+    for w in range(args.warmup):
+        batch.run(stream)
+        plain_step()
+        note(f"warmup {w + 1}/{args.warmup} done")
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    b_ms, p_ms = [], []
+    counts_b = counts_p = None
+    for s in range(args.steps):
+        a, b = ev(), ev()
+        torch.cuda.synchronize()
+        a.record(stream)
+        counts_b = batch.run(stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        b_ms.append(a.elapsed_time(b))
+        a, b = ev(), ev()
+        a.record(stream)
+        counts_p = plain_step()
+        b.record(stream)
+        torch.cuda.synchronize()
+        p_ms.append(a.elapsed_time(b))
+        note(f"step {s + 1}/{args.steps}: batched {b_ms[-1]:.1f} ms, plain {p_ms[-1]:.1f} ms")
+    if counts_b != counts_p:
+        raise RuntimeError(f"batched counts {counts_b} differ from plain counts {counts_p}")
+    ms_b = sum(b_ms) / len(b_ms)
+    ms_p = sum(p_ms) / len(p_ms)
+    value = sum(counts_b) / (ms_b / 1e3)
+    roofline = None
+    if not args.no_traffic:
+        alg = 0
+        for n, p, l, c in zip(names, plans, launches, counts_b):
+            cc, bb = gp.count_traffic(graph, p, **l)
+            assert cc == c
+            alg += bb
+        achieved = alg / (ms_b / 1e3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                    "kernel": "batch_kernel (all feasible patterns, one launch)",
+                    "alg_bytes_per_launch": alg, "avg_launch_ms": round(ms_b, 3)}
+    cpu = None
+    if not args.no_cpu_baseline and args.workload != "rmat22":
+        cpu = cpu_baseline(g, plans, names, args.cpu_seconds)
+    out = {
+        "metric": METRIC, "value": value, "unit": "embeddings/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_b, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": desc, "graph": {"n": st.n, "m": st.m, "max_degree": st.max_degree,
+                                               "sha256": g.sha256()},
+                   "patterns": names, "parallelism": "single GPU",
+                   "batch_launch": blaunch},
+        "counts": dict(zip(names, counts_b)),
+        "plain_ms_per_step": ms_p,
+        "plain_ms_per_pattern": {n: round(sum(x[-args.steps:]) / len(x[-args.steps:]), 3)
+                                 for n, x in zip(names, plain_each)},
+        "batched_speedup": ms_p / ms_b,
+        "batched_ms": b_ms, "plain_ms": p_ms,
+        "infeasible": infeasible,
+        "plans": {n: {"order": list(p.order), "restrictions": [list(x) for x in p.restrictions],
+                      "launch": l, "model_order": list(b.order),
+                      "model_restrictions": [list(x) for x in b.restrictions]}
+                  for n, p, b, l in zip(names, plans, base_plans, launches)},
+        "preprocessing_s": {"load": st.load_seconds, "plan": plan_s, "tune": tune_s},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def serve_main(args, desc):
+    """Serving: replay a Poisson stream of queries against resident graphs
+    through the continuous-batching server; every completed count is checked
+    against a solo count of the same query."""
+    from paper_2009_10955_amd import gp
+    from paper_2009_10955_amd import inputs as I
+    from paper_2009_10955_amd import serve as SV
+
+    graphs, meta = [], []
+    for ci in (1, 2, 3):
+        g = I.config_graph(ci)
+        G = gp.Graph.from_csr(g, device=True)
+        s = G.stats()
+        graphs.append(G)
+        meta.append({"config": ci, "n": s.n, "m": s.m, "max_degree": s.max_degree,
+                     "sha256": g.sha256()})
+        note(f"graph {ci} resident: n={s.n} m={s.m}")
+        del g
+    classes = I.connected_patterns(3, 6)
+    stream = I.poisson_stream(args.queries, args.qps, len(graphs), len(classes), seed=5)
+    server = gp.Server(graphs, max_query_ms=args.max_query_ms)
+    res = SV.run_stream(server, stream, classes, note=note)
+    stats = server.stats()
+    server.close()
+    summ = SV.summarise(res)
+    note(f"stream done: {summ}")
+    # every completed count against a solo count of the same (graph, pattern)
+    solo = {}
+    bad = 0
+    for r in res:
+        if r["status"] != 0:
+            continue
+        key = (r["graph"], r["pattern"])
+        if key not in solo:
+            k, e = classes[r["pattern"]]
+            G = graphs[r["graph"]]
+            solo[key] = gp.count(G, gp.Plan(k, e, stats=G.stats()))
+        bad += solo[key] != r["count"]
+    note(f"checked {sum(r['status'] == 0 for r in res)} completed counts against "
+         f"{len(solo)} solo counts: {bad} mismatches")
+    if bad:
+        raise RuntimeError(f"{bad} served counts differ from their solo counts")
+    out = {
+        "metric": METRIC, "value": summ["completed"] / summ["wall_s"], "unit": "queries/s",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": summ["wall_s"] * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": desc, "graphs": meta, "queries": args.queries, "qps": args.qps,
+                   "max_query_ms": args.max_query_ms, "parallelism": "single GPU"},
+        "latency": summ,
+        "server": stats,
+        "solo_checked": len(solo), "mismatches": bad,
+        "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
 

@@ -283,6 +283,21 @@ gp_status gp_count_per_root(const gp_graph* g, const gp_plan* p, const gp_launch
 gp_status gp_count_traffic(const gp_graph* g, const gp_plan* p, const gp_launch* launch,
                            void* stream, uint64_t* out, uint64_t* alg_bytes);
 
+/* Estimate the run time of a full gp_count before running it, from a strided
+ * sample of about 4096 root tasks (every root_tasks/4096-th, from the middle of
+ * the first stride): the summed active time of the wavefronts, scaled by the
+ * stride and divided by the wavefronts the device keeps resident, or the
+ * longest chunk of tasks, whichever is longer (one heavy hub root can decide
+ * the run). launch as in gp_count. budget_ms > 0 stops the sample once a
+ * wavefront has run that long; *est_ms is then 1e300 (the full run is at
+ * least that slow). Writes the sample's count and stride when the pointers
+ * are non-null: count * stride is a rough estimate of the full count (not
+ * exact; for planning only). Blocks on stream. GP_ERR_UNSUPPORTED for IEP
+ * plans. Used for admission by gp_server (max_query_ms) and for feasibility
+ * reports. */
+gp_status gp_estimate(const gp_graph* g, const gp_plan* p, const gp_launch* launch, double budget_ms,
+                      void* stream, double* est_ms, uint64_t* sample_count, int64_t* sample_stride);
+
 /*
  * Count several plans (1..64, any pattern sizes) over one graph in ONE
  * persistent launch: the task space is the concatenation of the plans' root
@@ -326,6 +341,11 @@ typedef struct {
     int32_t group;          /* lanes per group of the batched kernel: 64 or 32 (0 = 64) */
     int32_t leaf_mode;      /* 1 or 3 (0 = 3) */
     int32_t waves_per_cu;   /* 0 = 16 */
+    double max_query_ms;    /* > 0: the first query of each (graph, pattern) counts a strided
+                               sample of its root tasks first; a query whose full run is then
+                               estimated above max_query_ms (summed wavefront busy time scaled
+                               to all tasks over the resident wavefronts, or the longest task
+                               chunk if longer) is rejected with GP_ERR_BUDGET (0 = off) */
 } gp_server_opts;
 
 typedef struct {

@@ -37,4 +37,13 @@ namespace gpint {
 // Launch configuration for a count of plan p: the plan's tuned launch (if
 // any) or the defaults, with every non-zero field of l overriding it.
 LaunchCfg launch_for_plan(const gp_plan* p, const gp_launch* l, const DeviceGraph& g);
+
+// Full-run time (ms) of plan d with cfg, estimated from a strided sample of
+// about 4096 root tasks: the wavefronts' summed busy time scaled to all tasks
+// over the resident wavefronts, or the longest task chunk if that is longer.
+// budget_ms > 0 stops the sample early (the result is then 1e300). res: 5
+// device words. Negative on a HIP failure. Blocks on s.
+double estimate_full_ms(const DeviceGraph& g, const GpPlanDesc& d, LaunchCfg cfg, double budget_ms,
+                        hipStream_t s, unsigned long long* res, uint64_t* sample_count = nullptr,
+                        int64_t* sample_stride = nullptr);
 }  // namespace gpint

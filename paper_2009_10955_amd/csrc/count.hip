@@ -115,6 +115,39 @@ static const int2* pick_roots(const DeviceGraph& g, int root_cut, int64_t* n) {
     return g.roots_all;
 }
 
+// Roots split into several tasks: the first `roots` of the (sampled) root
+// array, whose smaller endpoint is below 2^floor(log2(split_vertices)).
+// Per-root and byte-accounting counts stay one task per root, and so do
+// patterns with no level-2 loop (k <= 3, IEP at k = 4).
+struct SplitPlan {
+    int64_t roots = 0;
+    int ways = 1;
+};
+
+static SplitPlan split_plan(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCfg& cfg, int mode,
+                            int64_t n_roots, int64_t stride, int64_t offset) {
+    SplitPlan sp;
+    const bool iep = d.iep != 0;
+    if (mode != MODE_PLAIN || d.k < 4 || (iep && d.k == 4) || cfg.split_ways <= 1 || cfg.split_vertices <= 0)
+        return sp;
+    int i = 0;
+    while (i < 31 && (int64_t(1) << (i + 1)) <= cfg.split_vertices) ++i;
+    const int64_t pref = g.upper_pref[i] * (d.root_cut == 0 ? 2 : 1);
+    const int64_t sampled = pref > offset ? (pref - offset + stride - 1) / stride : 0;
+    sp.roots = std::min(n_roots, sampled);
+    sp.ways = cfg.split_ways;
+    return sp;
+}
+
+static const int2* pick_roots(const DeviceGraph& g, int root_cut, int64_t* n);
+
+int64_t task_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCfg& cfg) {
+    int64_t n = 0;
+    (void)pick_roots(g, d.root_cut, &n);
+    const SplitPlan sp = split_plan(g, d, cfg, MODE_PLAIN, n, 1, 0);
+    return n + sp.roots * (sp.ways - 1);
+}
+
 gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCfg& cfg,
                        hipStream_t stream, unsigned long long* result_dev,
                        unsigned long long* per_root, bool account, unsigned long long* busy) {
@@ -137,19 +170,9 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
         return n > cfg.root_offset ? (n - cfg.root_offset + cfg.root_stride - 1) / cfg.root_stride : 0;
     };
     const int64_t n_roots = sampled(all_roots);
-    // the split prefix: roots whose smaller endpoint is below 2^i, i = floor(log2(split_vertices));
-    // only plain counts over a level-2 loop split (per-root and byte counts stay per root)
-    int64_t split_roots = 0;
-    int split_ways = 1;
-    const bool splittable = mode == MODE_PLAIN && d.k >= 4 && !(iep && d.k == 4) && cfg.split_ways > 1 &&
-                            cfg.split_vertices > 0;
-    if (splittable) {
-        int i = 0;
-        while (i < 31 && (int64_t(1) << (i + 1)) <= cfg.split_vertices) ++i;
-        const int64_t pref = g.upper_pref[i] * (d.root_cut == 0 ? 2 : 1);
-        split_roots = std::min(n_roots, sampled(pref));
-        split_ways = cfg.split_ways;
-    }
+    const SplitPlan sp = split_plan(g, d, cfg, mode, n_roots, cfg.root_stride, cfg.root_offset);
+    const int64_t split_roots = sp.roots;
+    const int split_ways = sp.ways;
     const int64_t n_tasks = n_roots + split_roots * (split_ways - 1);
 
     const int waves_per_block = kBlock / 64;
@@ -230,7 +253,8 @@ void batch_release(BatchState* st) {
 
 // Per-plan task ranges and the launch geometry for np plans.
 static gp_status batch_layout(const DeviceGraph& g, const GpPlanDesc* descs, const int64_t* offsets,
-                              const int64_t* counts, int np, BatchState* b, std::vector<BatchPlan>* plans) {
+                              const int64_t* counts, int np, const LaunchCfg& cfg, BatchState* b,
+                              std::vector<BatchPlan>* plans) {
     plans->resize(np);
     int64_t total = 0;
     int32_t nbuf = 0;
@@ -238,16 +262,21 @@ static gp_status batch_layout(const DeviceGraph& g, const GpPlanDesc* descs, con
     for (int i = 0; i < np; ++i) {
         int64_t n_all = 0;
         const int2* roots = pick_roots(g, descs[i].root_cut, &n_all);
+        // offsets and counts are in the plan's task space (split roots count once per task)
+        const SplitPlan sp = descs[i].iep ? SplitPlan{} : split_plan(g, descs[i], cfg, MODE_PLAIN, n_all, 1, 0);
+        const int64_t n_tasks = n_all + sp.roots * (sp.ways - 1);
         int64_t off = offsets ? offsets[i] : 0;
-        int64_t cnt = counts ? counts[i] : n_all;
+        int64_t cnt = counts ? counts[i] : n_tasks;
         if (off < 0 || cnt < 0) return GP_ERR_ARG;
-        off = std::min(off, n_all);
-        cnt = std::min(cnt, n_all - off);
-        (*plans)[i].roots = roots + off;
+        off = std::min(off, n_tasks);
+        cnt = std::min(cnt, n_tasks - off);
+        (*plans)[i].roots = roots;
         (*plans)[i].n_tasks = cnt;
         (*plans)[i].task_begin = total;
+        (*plans)[i].task_offset = off;
+        (*plans)[i].split_roots = sp.roots;
+        (*plans)[i].split_ways = sp.ways;
         (*plans)[i].leaf = b->leaf;
-        (*plans)[i].pad = 0;
         total += cnt;
         nbuf = std::max(nbuf, descs[i].nbuf);
         b->kmax = std::max(b->kmax, (int)descs[i].k);
@@ -281,7 +310,7 @@ gp_status batch_prepare(const DeviceGraph& g, const GpPlanDesc* descs, const int
     b.chunk = std::max(1, cfg.chunk);
     b.cap = std::max<int64_t>(1, g.deg2);
     std::vector<BatchPlan> plans;
-    gp_status rc = batch_layout(g, descs, offsets, counts, np, &b, &plans);
+    gp_status rc = batch_layout(g, descs, offsets, counts, np, cfg, &b, &plans);
     if (rc != GP_OK) return rc;
     const int64_t groups_per_block = kBlock / b.group;
     b.blocks = batch_blocks(g, b, cfg.waves_per_cu, b.nbuf, b.total_tasks);
@@ -369,7 +398,7 @@ gp_status arena_launch(const DeviceGraph& g, BatchArena* ar, const GpPlanDesc* d
     if (np < 1 || np > kBatchMaxPlans) return GP_ERR_ARG;
     BatchState& b = ar->st;
     std::vector<BatchPlan> plans;
-    gp_status rc = batch_layout(g, descs, offsets, counts, np, &b, &plans);
+    gp_status rc = batch_layout(g, descs, offsets, counts, np, ar->cfg, &b, &plans);
     if (rc != GP_OK) return rc;
     if (b.nbuf > ar->nbuf_cap) return GP_ERR_NOMEM;
     // the scratch was carved for nbuf_cap slots per group; any smaller nbuf fits

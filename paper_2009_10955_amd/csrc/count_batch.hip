@@ -26,17 +26,16 @@ constexpr int KMAX = GP_BATCH_KMAX;
 constexpr int LEAF = GP_BATCH_LEAF;  // 1, or 3 (flattened where possible, else as 1)
 
 template <int K>
-__device__ __forceinline__ void batch_roots(const GpPlanDesc& d, const Ctx<G>& c, const int2* roots,
-                                            int64_t t0, int64_t t1, int leaf, uint64_t& acc, bool& ovf) {
+__device__ __forceinline__ void batch_roots(const GpPlanDesc& d, Ctx<G>& c, const BatchPlan& bp, int64_t t0,
+                                            int64_t t1, uint64_t& acc, bool& ovf) {
     if constexpr (K > KMAX) {
         return;
     } else if constexpr (K <= 3) {
-        (void)leaf;
-        // lanes take different roots
+        // lanes take different roots (never split)
         for (int64_t base = t0; base < t1; base += G) {
             const int64_t r = base + c.g.gl;
             if (r < t1) {
-                const int2 e = roots[r];
+                const int2 e = bp.roots[bp.task_offset + r];
                 uint64_t cnt = 1;
                 if constexpr (K == 3) {
                     int32_t w[K] = {e.x, e.y, 0};
@@ -46,8 +45,9 @@ __device__ __forceinline__ void batch_roots(const GpPlanDesc& d, const Ctx<G>& c
             }
         }
     } else {
-        for (int64_t r = t0; r < t1; ++r) {
-            int2 e = roots[r];
+        for (int64_t t = t0; t < t1; ++t) {
+            const int64_t r = task_root(bp.task_offset + t, bp.split_roots, bp.split_ways, c.sj, c.sJ);
+            int2 e = bp.roots[r];
             e.x = uni<G>(e.x);
             e.y = uni<G>(e.y);
             int32_t v[K];
@@ -111,13 +111,13 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
             bool ovf = false;
             const int64_t l0 = tt - bp.task_begin, l1 = piece_end - bp.task_begin;
             switch (d.k) {
-                case 2: batch_roots<2>(d, c, bp.roots, l0, l1, bp.leaf, acc, ovf); break;
-                case 3: batch_roots<3>(d, c, bp.roots, l0, l1, bp.leaf, acc, ovf); break;
-                case 4: batch_roots<4>(d, c, bp.roots, l0, l1, bp.leaf, acc, ovf); break;
-                case 5: batch_roots<5>(d, c, bp.roots, l0, l1, bp.leaf, acc, ovf); break;
-                case 6: batch_roots<6>(d, c, bp.roots, l0, l1, bp.leaf, acc, ovf); break;
-                case 7: batch_roots<7>(d, c, bp.roots, l0, l1, bp.leaf, acc, ovf); break;
-                case 8: batch_roots<8>(d, c, bp.roots, l0, l1, bp.leaf, acc, ovf); break;
+                case 2: batch_roots<2>(d, c, bp, l0, l1, acc, ovf); break;
+                case 3: batch_roots<3>(d, c, bp, l0, l1, acc, ovf); break;
+                case 4: batch_roots<4>(d, c, bp, l0, l1, acc, ovf); break;
+                case 5: batch_roots<5>(d, c, bp, l0, l1, acc, ovf); break;
+                case 6: batch_roots<6>(d, c, bp, l0, l1, acc, ovf); break;
+                case 7: batch_roots<7>(d, c, bp, l0, l1, acc, ovf); break;
+                case 8: batch_roots<8>(d, c, bp, l0, l1, acc, ovf); break;
                 default: break;
             }
             // group sum with carry detection, into the wave's LDS counter

@@ -79,12 +79,30 @@ typedef void (*KernelFn)(GpPlanDesc, CountArgs);
 constexpr int kBatchMaxPlans = 64;
 
 struct BatchPlan {
-    const int2* roots;   // this plan's root array (cut already applied)
-    int64_t n_tasks;     // roots of this plan in the launch
-    int64_t task_begin;  // first global task index of this plan
-    int32_t leaf;        // 1 or 3 (flattened last two levels)
-    int32_t pad;
+    const int2* roots;    // this plan's whole root array (cut already applied)
+    int64_t n_tasks;      // tasks of this plan in the launch
+    int64_t task_begin;   // first global task index of this plan
+    int64_t task_offset;  // where in the plan's own task space the launch starts
+    int64_t split_roots;  // as in CountArgs: the first split_roots roots run as
+    int32_t split_ways;   // split_ways tasks each
+    int32_t leaf;         // 1 or 3 (flattened last two levels)
 };
+
+// Root of task t, and the level-2 slice it binds: the first split_roots roots
+// are split_ways tasks each, the rest one task each.
+__device__ __forceinline__ int64_t task_root(int64_t t, int64_t split_roots, int32_t split_ways, int32_t& sj,
+                                             int32_t& sJ) {
+    const int64_t split_tasks = split_roots * (int64_t)split_ways;
+    if (t < split_tasks) {
+        const int64_t r = t / split_ways;
+        sj = (int32_t)(t - r * split_ways);
+        sJ = split_ways;
+        return r;
+    }
+    sj = 0;
+    sJ = 1;
+    return t - split_tasks + split_roots;
+}
 
 struct BatchArgs {
     const int64_t* row_ptr;
@@ -578,7 +596,6 @@ __global__ __launch_bounds__(kBlock) void count_kernel(GpPlanDesc d, CountArgs a
     uint64_t acc = 0;
     bool ovf = false;
     const int64_t chunk = a.chunk;
-    const int64_t split_tasks = a.split_roots * (int64_t)a.split_ways;
 
     for (;;) {
         unsigned long long t0 = 0;
@@ -635,16 +652,7 @@ __global__ __launch_bounds__(kBlock) void count_kernel(GpPlanDesc d, CountArgs a
             }
         } else {
             for (int64_t t = (int64_t)t0; t < t1; ++t) {
-                int64_t r = t;
-                if (t < split_tasks) {
-                    r = t / a.split_ways;
-                    c.sj = (int32_t)(t - r * a.split_ways);
-                    c.sJ = a.split_ways;
-                } else {
-                    r = t - split_tasks + a.split_roots;
-                    c.sj = 0;
-                    c.sJ = 1;
-                }
+                const int64_t r = task_root(t, a.split_roots, a.split_ways, c.sj, c.sJ);
                 int2 e = a.roots[a.root_offset + r * a.root_stride];
                 e.x = uni<G>(e.x);
                 e.y = uni<G>(e.y);

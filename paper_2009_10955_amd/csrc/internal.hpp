@@ -107,6 +107,8 @@ gp_status batch_enqueue(const DeviceGraph& g, const BatchState& st, hipStream_t 
 void batch_release(BatchState* st);
 // Number of root tasks of a descriptor (its cut picks the root array).
 int64_t root_task_count(const DeviceGraph& g, const GpPlanDesc& d);
+// Tasks of plan d over g with cfg's root splitting (no sampling).
+int64_t task_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCfg& cfg);
 
 // Launch defaults for a plan descriptor, and overriding them with the
 // non-zero fields of a caller's gp_launch.

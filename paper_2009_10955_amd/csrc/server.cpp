@@ -4,7 +4,11 @@
 // A worker thread owns the device side. Queries are planned off the submit
 // path (plans are cached per graph and edge list); a query whose predicted
 // cost (the model of Section IV-C) exceeds the cap is rejected with
-// GP_ERR_BUDGET. Admitted queries join the active set of their graph as
+// GP_ERR_BUDGET. The model ranks configurations of one pattern well but
+// predicts run time across patterns poorly (on power-law graphs it misses
+// the hubs), so with max_query_ms the first query of each (graph, pattern)
+// also counts a strided root sample whose wavefront busy time gives a
+// full-run estimate, and queries estimated above the limit are rejected too. Admitted queries join the active set of their graph as
 // batch slots (at most 64 per launch: the batched kernel keeps per-plan
 // counters in LDS) and HBM scratch allow.
 //
@@ -78,6 +82,8 @@ struct gp_server {
     std::vector<std::deque<Query*>> waiting;
     std::vector<std::vector<Query*>> active;
     std::map<std::pair<int, std::vector<int32_t>>, gp_plan*> plan_cache;
+    std::map<const gp_plan*, double> est_ms;  // measured full-run estimates (max_query_ms)
+    std::vector<unsigned long long*> est_res;  // per graph: 5 device words for the estimate
 };
 
 namespace {
@@ -91,6 +97,18 @@ void finish(gp_server* S, Query* q, gp_status st) {
     else if (st == GP_ERR_BUDGET) ++S->stats.rejected;
     else ++S->stats.failed;
     S->cv_done.notify_all();
+}
+
+// Launch shape of every batched launch of the server (its kernels, its task space).
+gpint::LaunchCfg server_launch(const gp_server* S) {
+    gpint::LaunchCfg cfg;
+    cfg.group = S->opts.group;
+    cfg.leaf = S->opts.leaf_mode;
+    cfg.waves_per_cu = S->opts.waves_per_cu;
+    cfg.chunk = 4;
+    cfg.split_ways = 16;
+    cfg.split_vertices = 256;
+    return cfg;
 }
 
 gp_status plan_query(gp_server* S, Query* q) {
@@ -120,7 +138,24 @@ gp_status plan_query(gp_server* S, Query* q) {
         it = S->plan_cache.emplace(ck, p).first;
     }
     q->plan = it->second;
-    q->n_tasks = gpint::root_task_count(S->graphs[q->graph]->dg, q->plan->desc);
+    // slices cut the query's task space, in which a split root counts once per task
+    q->n_tasks = gpint::task_count(S->graphs[q->graph]->dg, q->plan->desc, server_launch(S));
+    if (S->opts.max_query_ms > 0 && q->n_tasks > 0) {
+        auto e = S->est_ms.find(q->plan);
+        if (e == S->est_ms.end()) {
+            const int g = q->graph;
+            if (!S->est_res[g] &&
+                hipMalloc((void**)&S->est_res[g], 5 * sizeof(unsigned long long)) != hipSuccess)
+                return GP_ERR_NOMEM;
+            gpint::LaunchCfg cfg = server_launch(S);
+            cfg.waves_per_cu = 32;
+            const double est = gpint::estimate_full_ms(S->graphs[g]->dg, q->plan->desc, cfg,
+                                                       S->opts.max_query_ms, S->streams[g], S->est_res[g]);
+            if (est < 0) return GP_ERR_HIP;
+            e = S->est_ms.emplace(q->plan, est).first;
+        }
+        if (e->second > S->opts.max_query_ms) return GP_ERR_BUDGET;
+    }
     return GP_OK;
 }
 
@@ -129,12 +164,7 @@ gp_status ensure_arena(gp_server* S, int g, int nbuf) {
     if (a.st.queue && a.nbuf_cap >= nbuf) return GP_OK;
     const int want = std::max(nbuf, std::max(a.nbuf_cap * 2, 4));
     gpint::arena_release(&a);
-    gpint::LaunchCfg cfg;
-    cfg.group = S->opts.group;
-    cfg.leaf = S->opts.leaf_mode;
-    cfg.waves_per_cu = S->opts.waves_per_cu;
-    cfg.chunk = 4;
-    return gpint::arena_create(S->graphs[g]->dg, std::min(want, GP_DESC_MAX_BUILDS), cfg, &a);
+    return gpint::arena_create(S->graphs[g]->dg, std::min(want, GP_DESC_MAX_BUILDS), server_launch(S), &a);
 }
 
 void worker_main(gp_server* S) {
@@ -144,6 +174,7 @@ void worker_main(gp_server* S) {
     S->streams.assign(ng, nullptr);
     S->waiting.assign(ng, {});
     S->active.assign(ng, {});
+    S->est_res.assign(ng, nullptr);
     for (int g = 0; g < ng; ++g) {
         if (hipStreamCreateWithFlags(&S->streams[g], hipStreamNonBlocking) != hipSuccess) {
             std::lock_guard<std::mutex> lk(S->mu);
@@ -297,6 +328,7 @@ void worker_main(gp_server* S) {
             (void)hipStreamDestroy(S->streams[g]);
         }
         gpint::arena_release(&S->arenas[g]);
+        if (S->est_res[g]) (void)hipFree(S->est_res[g]);
     }
 }
 
@@ -330,6 +362,7 @@ gp_status gp_server_create(const gp_graph* const* graphs, int32_t ng, const gp_s
     if (o.group != 64 && o.group != 32) o.group = 64;
     if (o.leaf_mode != 1 && o.leaf_mode != 3) o.leaf_mode = 3;
     if (o.waves_per_cu <= 0 || o.waves_per_cu > 32) o.waves_per_cu = 16;
+    if (o.max_query_ms < 0 || o.cost_cap < 0) return GP_ERR_ARG;
     gp_server* S = new (std::nothrow) gp_server;
     if (!S) return GP_ERR_NOMEM;
     S->graphs.assign(graphs, graphs + ng);

@@ -30,6 +30,26 @@ LaunchCfg launch_for_plan(const gp_plan* p, const gp_launch* l, const DeviceGrap
     return apply_launch(p->launch, l);
 }
 
+double estimate_full_ms(const DeviceGraph& g, const GpPlanDesc& d, LaunchCfg cfg, double budget_ms,
+                        hipStream_t s, unsigned long long* res, uint64_t* sample_count, int64_t* sample_stride) {
+    const int64_t roots = std::max<int64_t>(1, root_task_count(g, d));
+    const int64_t stride = std::max<int64_t>(1, roots / 4096);
+    if (sample_stride) *sample_stride = stride;
+    cfg.root_stride = stride;
+    cfg.root_offset = stride / 2;
+    cfg.budget_ms = budget_ms;
+    unsigned long long h[5] = {0, 0, 0, 0, 0};
+    if (launch_count(g, d, cfg, s, res, nullptr, false, res + 2) != GP_OK ||
+        hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return -1;
+    if (sample_count) *sample_count = h[0];
+    if (h[1] & 4ull) return 1e300;  // a wavefront of the sample alone ran past the budget
+    const double busy = (double)h[2] / g.wall_khz, chunk = (double)h[4] / g.wall_khz;
+    const double resident = (double)g.num_cus * resident_waves_per_cu(d, cfg);
+    return std::max(busy * (double)stride / resident, chunk);
+}
+
 }  // namespace gpint
 
 namespace {
@@ -265,6 +285,7 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
             gpint::LaunchCfg cfg = base;
             cfg.root_stride = s0;
             cfg.root_offset = s0 / 2;
+            cfg.budget_ms = budget_ms;  // a sample that runs past it still gives a lower bound
             Timing t = time_launch(g->dg, p->desc, cfg, s, res);
             if (t.wall < 0) st = GP_ERR_HIP;
             spent += std::max(0.0, t.wall);
@@ -416,6 +437,33 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
     in.plan_seconds = p->info.plan_seconds + (now_seconds() - t0);
     *out = np;
     return GP_OK;
+}
+
+gp_status gp_estimate(const gp_graph* g, const gp_plan* p, const gp_launch* launch, double budget_ms,
+                      void* stream, double* est_ms, uint64_t* sample_count, int64_t* sample_stride) {
+    if (!g || !p || !est_ms || budget_ms < 0) return GP_ERR_ARG;
+    if (p->desc.iep) return GP_ERR_UNSUPPORTED;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    if (prev != g->dg.device) (void)hipSetDevice(g->dg.device);
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long* res = nullptr;
+    gp_status st = GP_OK;
+    if (hipMallocAsync((void**)&res, 5 * sizeof(unsigned long long), s) != hipSuccess) {
+        st = GP_ERR_NOMEM;
+    } else {
+        gpint::LaunchCfg cfg = gpint::launch_for_plan(p, launch, g->dg);
+        cfg.root_stride = 1;
+        cfg.root_offset = 0;
+        const double e = gpint::estimate_full_ms(g->dg, p->desc, cfg, budget_ms, s, res, sample_count,
+                                                 sample_stride);
+        if (e < 0) st = GP_ERR_HIP;
+        else *est_ms = e;
+        (void)hipFreeAsync(res, s);
+        (void)hipStreamSynchronize(s);
+    }
+    if (prev >= 0 && prev != g->dg.device) (void)hipSetDevice(prev);
+    return st;
 }
 
 }  // extern "C"

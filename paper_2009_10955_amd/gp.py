@@ -69,7 +69,7 @@ class ServerOpts(ctypes.Structure):
     _fields_ = [("max_active", ctypes.c_int32), ("target_ms", ctypes.c_double),
                 ("cost_cap", ctypes.c_double), ("initial_slice", ctypes.c_int64),
                 ("group", ctypes.c_int32), ("leaf_mode", ctypes.c_int32),
-                ("waves_per_cu", ctypes.c_int32)]
+                ("waves_per_cu", ctypes.c_int32), ("max_query_ms", ctypes.c_double)]
 
 
 class ServerStats(ctypes.Structure):
@@ -120,6 +120,9 @@ SIGNATURES = {
     "gp_count_per_root": (_I32, [_P, _P, ctypes.POINTER(Launch), _P, _P,
                                  ctypes.POINTER(ctypes.c_uint64)]),
     "gp_count_batch": (_I32, [_P, _P, _I32, ctypes.POINTER(Launch), _P, _P]),
+    "gp_estimate": (_I32, [_P, _P, ctypes.POINTER(Launch), ctypes.c_double, _P,
+                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64),
+                           ctypes.POINTER(_I64)]),
     "gp_count_traffic": (_I32, [_P, _P, ctypes.POINTER(Launch), _P,
                                 ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]),
     "gp_batch_create": (_I32, [_P, _P, _I32, ctypes.POINTER(Launch), _P, ctypes.POINTER(_P)]),
@@ -402,6 +405,22 @@ def count_traffic(graph: Graph, plan: Plan, stream=None, **launch) -> tuple[int,
     return out.value, b.value
 
 
+def estimate(graph: Graph, plan: Plan, budget_ms: float = 0.0, stream=None, **launch) -> dict:
+    """Full-run time estimate of a count from a strided root sample
+    (see gp_estimate): {"ms", "sample_count", "sample_stride"}; ms is inf when
+    the sample ran past budget_ms."""
+    ms = ctypes.c_double()
+    cnt = ctypes.c_uint64()
+    stride = ctypes.c_int64()
+    lp = _launch(**launch)
+    _check(_lib().gp_estimate(graph.handle, plan.handle, ctypes.byref(lp), float(budget_ms),
+                              _stream_handle(stream), ctypes.byref(ms), ctypes.byref(cnt),
+                              ctypes.byref(stride)), "gp_estimate")
+    v = ms.value
+    return {"ms": float("inf") if v >= 1e299 else v, "sample_count": cnt.value,
+            "sample_stride": stride.value}
+
+
 def count_batch(graph: Graph, plans: Sequence[Plan], stream=None, **launch) -> list[int]:
     """Counts of several plans in one persistent launch (blocking)."""
     arr = (ctypes.c_void_p * len(plans))(*[p.handle for p in plans])
@@ -447,14 +466,14 @@ class Server:
 
     def __init__(self, graphs: Sequence[Graph], max_active: int = 0, target_ms: float = 0.0,
                  cost_cap: float = 0.0, initial_slice: int = 0, group: int = 0, leaf_mode: int = 0,
-                 waves_per_cu: int = 0):
+                 waves_per_cu: int = 0, max_query_ms: float = 0.0):
         self.graphs = list(graphs)
         o = ServerOpts()
         _lib().gp_server_opts_default(ctypes.byref(o))
         for name, val in (("max_active", max_active), ("target_ms", target_ms),
                           ("cost_cap", cost_cap), ("initial_slice", initial_slice),
                           ("group", group), ("leaf_mode", leaf_mode),
-                          ("waves_per_cu", waves_per_cu)):
+                          ("waves_per_cu", waves_per_cu), ("max_query_ms", max_query_ms)):
             if val:
                 setattr(o, name, val)
         arr = (ctypes.c_void_p * len(graphs))(*[g.handle for g in graphs])

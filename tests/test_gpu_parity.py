@@ -439,6 +439,61 @@ def test_serving_rejects_over_budget_and_reports_overflow_free():
     assert out[0][1] == 157
 
 
+def test_serving_measured_admission():
+    """max_query_ms: with a generous limit every query runs and equals its
+    solo count; with a tiny limit on a hub-heavy graph the heavy pattern is
+    rejected (GP_ERR_BUDGET) while the light one still completes."""
+    g2 = I.config_graph(2)
+    graphs = [gp.Graph.from_csr(I.config_graph(0)), gp.Graph.from_csr(g2)]
+    pats = [P["triangle"], P["house"], P["5-cycle"]]
+    srv = gp.Server(graphs, max_query_ms=60_000)
+    t = [(gi, p, srv.submit(gi, *p)) for gi in (0, 1) for p in pats]
+    out = [(gi, p, srv.wait(x)) for gi, p, x in t]
+    srv.close()
+    for gi, p, (st, c, _) in out:
+        assert st == 0
+        assert c == gp.count(graphs[gi], gp.Plan(*p, stats=graphs[gi].stats()))
+    srv = gp.Server(graphs, max_query_ms=1e-3)
+    st_heavy = srv.wait(srv.submit(1, *P["5-cycle"]))[0]
+    srv.close()
+    assert st_heavy == -10
+
+
+def test_estimate_is_sane():
+    """gp_estimate: positive, finite without a budget, and its sample count
+    times the stride is within 3x of the full count on a power-law graph."""
+    g = I.config_graph(2)
+    graph = gp.Graph.from_csr(g, device=True)
+    for pname in ["house", "4-clique", "5-cycle"]:
+        plan = gp.Plan(*P[pname], stats=graph.stats())
+        e = gp.estimate(graph, plan)
+        assert 0 < e["ms"] < 1e6 and e["sample_stride"] >= 1
+        full = gp.count(graph, plan)
+        assert full / 3 <= e["sample_count"] * e["sample_stride"] <= full * 3, pname
+        e2 = gp.estimate(graph, plan, budget_ms=1e-4)
+        assert e2["ms"] == float("inf") or e2["ms"] > 0
+    iep = gp.Plan(*P["house"], stats=graph.stats(), iep=True)
+    with pytest.raises(gp.GpError) as ei:
+        gp.estimate(graph, iep)
+    assert ei.value.status == -12
+
+
+def test_batch_with_split_roots_equals_plain():
+    g = I.config_graph(2)
+    graph = gp.Graph.from_csr(g, device=True)
+    plans = [gp.Plan(*P[n], stats=graph.stats()) for n in ["house", "5-cycle", "4-clique", "triangle"]]
+    want = [gp.count(graph, p, split_ways=1) for p in plans]
+    for ways, verts in [(1, 0), (16, 256), (7, 1 << 20)]:
+        for grp, leaf in [(64, 3), (32, 1)]:
+            got = gp.count_batch(graph, plans, group=grp, leaf_mode=leaf, split_ways=ways,
+                                 split_vertices=verts)
+            assert got == want, (ways, verts, grp, leaf)
+    b = gp.Batch(graph, plans, split_ways=5, split_vertices=1 << 20)
+    for _ in range(3):
+        assert b.run() == want
+    b.close()
+
+
 # --------------------------------------------------------------------- IEP
 
 @pytest.mark.parametrize("pname", ["house", "diamond", "tailed-triangle", "4-path", "3-star",

@@ -80,7 +80,7 @@ def parse_args():
     ap.add_argument("--batch-leaf", type=int, default=3)
     ap.add_argument("--queries", type=int, default=2000, help="serve: stream length")
     ap.add_argument("--qps", type=float, default=50.0, help="serve: mean arrival rate")
-    ap.add_argument("--max-query-ms", type=float, default=1000.0,
+    ap.add_argument("--max-query-ms", type=float, default=20.0,
                     help="serve: reject queries whose measured estimate exceeds this")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
@@ -454,7 +454,11 @@ def serve_main(args, desc):
     # every completed count against a solo count of the same (graph, pattern)
     solo = {}
     bad = 0
+    t_last = time.perf_counter()
     for r in res:
+        if time.perf_counter() - t_last > 10.0:
+            t_last = time.perf_counter()
+            note(f"solo checks: {len(solo)} distinct queries counted")
         if r["status"] != 0:
             continue
         key = (r["graph"], r["pattern"])

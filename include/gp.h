@@ -284,8 +284,8 @@ gp_status gp_count_traffic(const gp_graph* g, const gp_plan* p, const gp_launch*
                            void* stream, uint64_t* out, uint64_t* alg_bytes);
 
 /* Estimate the run time of a full gp_count before running it, from a strided
- * sample of about 4096 root tasks (every root_tasks/4096-th, from the middle of
- * the first stride): the summed active time of the wavefronts, scaled by the
+ * sample of about 4096 root tasks (every root_tasks/4096-th, starting with the
+ * first, which is the heaviest): the summed active time of the wavefronts, scaled by the
  * stride and divided by the wavefronts the device keeps resident, or the
  * longest chunk of tasks, whichever is longer (one heavy hub root can decide
  * the run). launch as in gp_count. budget_ms > 0 stops the sample once a

@@ -46,4 +46,12 @@ LaunchCfg launch_for_plan(const gp_plan* p, const gp_launch* l, const DeviceGrap
 double estimate_full_ms(const DeviceGraph& g, const GpPlanDesc& d, LaunchCfg cfg, double budget_ms,
                         hipStream_t s, unsigned long long* res, uint64_t* sample_count = nullptr,
                         int64_t* sample_stride = nullptr);
+
+// The same in two halves, for callers that overlap the sample with other
+// work: estimate_begin enqueues the sample on s (results in res[0..4]);
+// estimate_end turns a host copy h of those five words into the estimate.
+gp_status estimate_begin(const DeviceGraph& g, const GpPlanDesc& d, LaunchCfg cfg, double budget_ms,
+                         hipStream_t s, unsigned long long* res, int64_t* stride_out);
+double estimate_end(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCfg& cfg,
+                    const unsigned long long* h, int64_t stride);
 }  // namespace gpint

@@ -164,7 +164,7 @@ struct Ctx {
     int64_t hub_words;
     int32_t n_hubs;
     int32_t sj, sJ;     // level-2 slice of the current task: candidates sj, sj + sJ, ...
-    uint64_t deadline;  // clock tick after which level-2 loops stop (0: none)
+    uint64_t deadline;  // clock tick after which every search loop stops (0: none)
     Group<G> g;
 
     __device__ __forceinline__ bool expired() const {
@@ -410,8 +410,7 @@ __device__ void flat_leaf(const GpPlanDesc& d, const Ctx<G>& c, const int32_t (&
     constexpr int L = K - 3;
     const GpLevel& l2 = d.lv[K - 2];
     for (int32_t base = 0; base < S.n; base += G) {
-        if constexpr (L == 2)
-            if (c.expired()) break;
+        if (c.expired()) break;
         const int32_t i = base + c.g.gl;
         int32_t x2 = 0;
         Set C{nullptr, 0, nullptr};
@@ -490,8 +489,7 @@ __device__ void search(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], ui
         // last outer level: every candidate adds its inclusion-exclusion count
         if (d.build_begin[L] == d.build_end[L]) {
             for (int32_t base = 0; base < S.n; base += G) {
-                if constexpr (L == 2)
-                    if (c.expired()) break;
+                if (c.expired()) break;
                 const int32_t i = base + c.g.gl;
                 if (i < S.n) {
                     const int32_t x = S.p[(int64_t)i * st];
@@ -506,8 +504,7 @@ __device__ void search(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], ui
             }
         } else {
             for (int32_t t = 0; t < S.n; ++t) {
-                if constexpr (L == 2)
-                    if (c.expired()) break;
+                if (c.expired()) break;
                 const int32_t x = uni<G>(S.p[(int64_t)t * st]);
                 if (inj_hit<K>(lv.inj, v, x)) continue;
                 v[L] = x;
@@ -519,8 +516,7 @@ __device__ void search(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], ui
     } else if constexpr (L == K - 2) {
         if constexpr (LEAF != 2) {
             for (int32_t base = 0; base < S.n; base += G) {
-                if constexpr (L == 2)
-                    if (c.expired()) break;
+                if (c.expired()) break;
                 int32_t i = base + c.g.gl;
                 if (i < S.n) {
                     int32_t x = S.p[(int64_t)i * st];
@@ -535,8 +531,7 @@ __device__ void search(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], ui
             }
         } else {
             for (int32_t t = 0; t < S.n; ++t) {
-                if constexpr (L == 2)
-                    if (c.expired()) break;
+                if (c.expired()) break;
                 const int32_t x = uni<G>(S.p[(int64_t)t * st]);
                 if (inj_hit<K>(lv.inj, v, x)) continue;
                 v[K - 2] = x;
@@ -552,8 +547,7 @@ __device__ void search(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], ui
             }
         }
         for (int32_t t = 0; t < S.n; ++t) {
-            if constexpr (L == 2)
-                if (c.expired()) break;
+            if (c.expired()) break;
             const int32_t x = uni<G>(S.p[(int64_t)t * st]);
             if (inj_hit<K>(lv.inj, v, x)) continue;
             v[L] = x;

@@ -83,7 +83,21 @@ struct gp_server {
     std::vector<std::vector<Query*>> active;
     std::map<std::pair<int, std::vector<int32_t>>, gp_plan*> plan_cache;
     std::map<const gp_plan*, double> est_ms;  // measured full-run estimates (max_query_ms)
-    std::vector<unsigned long long*> est_res;  // per graph: 5 device words for the estimate
+    // estimates run on side streams while iterations go on; queries of a
+    // (graph, pattern) whose estimate is not known yet wait on it
+    struct Estimate {
+        int graph = 0;
+        const gp_plan* plan = nullptr;
+        hipStream_t stream = nullptr;
+        hipEvent_t done = nullptr;
+        unsigned long long* dev = nullptr;   // 5 words
+        unsigned long long* host = nullptr;  // pinned, 5 words
+        int64_t stride = 1;
+        std::vector<Query*> queries;
+    };
+    std::vector<Estimate*> est_live, est_idle;
+    std::deque<Estimate*> est_queue;
+    std::map<const gp_plan*, Estimate*> est_by_plan;
 };
 
 namespace {
@@ -140,23 +154,106 @@ gp_status plan_query(gp_server* S, Query* q) {
     q->plan = it->second;
     // slices cut the query's task space, in which a split root counts once per task
     q->n_tasks = gpint::task_count(S->graphs[q->graph]->dg, q->plan->desc, server_launch(S));
-    if (S->opts.max_query_ms > 0 && q->n_tasks > 0) {
+    return GP_OK;
+}
+
+constexpr size_t kMaxLiveEstimates = 8;
+
+// Route a planned query: reject, wait for a batch slot, or wait for the
+// estimate of its (graph, pattern).
+void route_query(gp_server* S, Query* q) {
+    if (q->n_tasks == 0) {
+        finish(S, q, GP_OK);
+        return;
+    }
+    if (S->opts.max_query_ms > 0) {
         auto e = S->est_ms.find(q->plan);
         if (e == S->est_ms.end()) {
-            const int g = q->graph;
-            if (!S->est_res[g] &&
-                hipMalloc((void**)&S->est_res[g], 5 * sizeof(unsigned long long)) != hipSuccess)
-                return GP_ERR_NOMEM;
+            auto& slot = S->est_by_plan[q->plan];
+            if (!slot) {
+                if (!S->est_idle.empty()) {
+                    slot = S->est_idle.back();
+                    S->est_idle.pop_back();
+                } else {
+                    slot = new (std::nothrow) gp_server::Estimate;
+                    if (!slot) {
+                        S->est_by_plan.erase(q->plan);
+                        finish(S, q, GP_ERR_NOMEM);
+                        return;
+                    }
+                }
+                slot->graph = q->graph;
+                slot->plan = q->plan;
+                slot->queries.clear();
+                S->est_queue.push_back(slot);
+            }
+            slot->queries.push_back(q);
+            return;
+        }
+        if (e->second > S->opts.max_query_ms) {
+            finish(S, q, GP_ERR_BUDGET);
+            return;
+        }
+    }
+    q->state = Q_WAITING;
+    S->waiting[q->graph].push_back(q);
+}
+
+void fail_estimate(gp_server* S, gp_server::Estimate* x, gp_status rc) {
+    for (Query* q : x->queries) finish(S, q, rc);
+    x->queries.clear();
+    S->est_by_plan.erase(x->plan);
+}
+
+// Start queued estimates, collect finished ones, and route their queries.
+void poll_estimates(gp_server* S) {
+    while (!S->est_queue.empty() && S->est_live.size() < kMaxLiveEstimates) {
+        gp_server::Estimate* x = S->est_queue.front();
+        S->est_queue.pop_front();
+        bool ok = true;
+        if (!x->stream)
+            ok = hipStreamCreateWithFlags(&x->stream, hipStreamNonBlocking) == hipSuccess &&
+                 hipEventCreateWithFlags(&x->done, hipEventDisableTiming) == hipSuccess &&
+                 hipMalloc((void**)&x->dev, 5 * sizeof(unsigned long long)) == hipSuccess &&
+                 hipHostMalloc((void**)&x->host, 5 * sizeof(unsigned long long), hipHostMallocDefault) ==
+                     hipSuccess;
+        gpint::LaunchCfg cfg = server_launch(S);
+        cfg.waves_per_cu = 32;
+        ok = ok &&
+             gpint::estimate_begin(S->graphs[x->graph]->dg, x->plan->desc, cfg, S->opts.max_query_ms, x->stream,
+                                   x->dev, &x->stride) == GP_OK &&
+             hipMemcpyAsync(x->host, x->dev, 5 * sizeof(unsigned long long), hipMemcpyDeviceToHost, x->stream) ==
+                 hipSuccess &&
+             hipEventRecord(x->done, x->stream) == hipSuccess;
+        if (!ok) {
+            fail_estimate(S, x, GP_ERR_HIP);
+            S->est_idle.push_back(x);
+            continue;
+        }
+        S->est_live.push_back(x);
+    }
+    std::vector<gp_server::Estimate*> still;
+    for (gp_server::Estimate* x : S->est_live) {
+        const hipError_t r = hipEventQuery(x->done);
+        if (r == hipErrorNotReady) {
+            still.push_back(x);
+            continue;
+        }
+        if (r != hipSuccess) {
+            fail_estimate(S, x, GP_ERR_HIP);
+        } else {
             gpint::LaunchCfg cfg = server_launch(S);
             cfg.waves_per_cu = 32;
-            const double est = gpint::estimate_full_ms(S->graphs[g]->dg, q->plan->desc, cfg,
-                                                       S->opts.max_query_ms, S->streams[g], S->est_res[g]);
-            if (est < 0) return GP_ERR_HIP;
-            e = S->est_ms.emplace(q->plan, est).first;
+            const double est = gpint::estimate_end(S->graphs[x->graph]->dg, x->plan->desc, cfg, x->host, x->stride);
+            S->est_ms[x->plan] = est;
+            std::vector<Query*> qs;
+            qs.swap(x->queries);
+            S->est_by_plan.erase(x->plan);
+            for (Query* q : qs) route_query(S, q);
         }
-        if (e->second > S->opts.max_query_ms) return GP_ERR_BUDGET;
+        S->est_idle.push_back(x);
     }
-    return GP_OK;
+    S->est_live.swap(still);
 }
 
 gp_status ensure_arena(gp_server* S, int g, int nbuf) {
@@ -174,7 +271,6 @@ void worker_main(gp_server* S) {
     S->streams.assign(ng, nullptr);
     S->waiting.assign(ng, {});
     S->active.assign(ng, {});
-    S->est_res.assign(ng, nullptr);
     for (int g = 0; g < ng; ++g) {
         if (hipStreamCreateWithFlags(&S->streams[g], hipStreamNonBlocking) != hipSuccess) {
             std::lock_guard<std::mutex> lk(S->mu);
@@ -187,11 +283,12 @@ void worker_main(gp_server* S) {
         bool idle = true;
         for (int g = 0; g < ng; ++g)
             if (!S->active[g].empty() || !S->waiting[g].empty()) idle = false;
+        const bool estimating = !S->est_live.empty() || !S->est_queue.empty();
         {
             std::unique_lock<std::mutex> lk(S->mu);
             if (idle && S->inbox.empty()) {
-                if (S->stop) break;
-                S->cv_work.wait_for(lk, std::chrono::milliseconds(50));
+                if (S->stop && !estimating) break;
+                S->cv_work.wait_for(lk, std::chrono::milliseconds(estimating ? 1 : 50));
             }
             fresh.assign(S->inbox.begin(), S->inbox.end());
             S->inbox.clear();
@@ -214,13 +311,9 @@ void worker_main(gp_server* S) {
                 finish(S, q, rc);
                 continue;
             }
-            if (q->n_tasks == 0) {
-                finish(S, q, GP_OK);
-                continue;
-            }
-            q->state = Q_WAITING;
-            S->waiting[q->graph].push_back(q);
+            route_query(S, q);
         }
+        poll_estimates(S);
         // admission: free slots and scratch
         bool any = false;
         for (int g = 0; g < ng; ++g) {
@@ -235,6 +328,14 @@ void worker_main(gp_server* S) {
                 q->state = Q_ACTIVE;
                 q->t_admit = now_s();
                 q->slice = S->opts.initial_slice;
+                // with a measured estimate, the first slice aims at a quarter of the target
+                // iteration (tasks run heaviest first, so the first slice is the slowest)
+                auto e = S->est_ms.find(q->plan);
+                if (e != S->est_ms.end() && e->second > 0) {
+                    const double share = S->opts.target_ms / std::max(e->second, S->opts.target_ms) / 4.0;
+                    const double want = std::max(16.0, (double)q->n_tasks * share);
+                    q->slice = std::min<int64_t>(S->opts.initial_slice, (int64_t)want);
+                }
                 bool midflight = false;
                 for (Query* o : S->active[g])
                     if (o->progress > 0) midflight = true;
@@ -328,8 +429,22 @@ void worker_main(gp_server* S) {
             (void)hipStreamDestroy(S->streams[g]);
         }
         gpint::arena_release(&S->arenas[g]);
-        if (S->est_res[g]) (void)hipFree(S->est_res[g]);
     }
+    for (gp_server::Estimate* x : S->est_live) S->est_idle.push_back(x);
+    for (gp_server::Estimate* x : S->est_queue) S->est_idle.push_back(x);
+    for (gp_server::Estimate* x : S->est_idle) {
+        if (x->stream) {
+            (void)hipStreamSynchronize(x->stream);
+            (void)hipStreamDestroy(x->stream);
+        }
+        if (x->done) (void)hipEventDestroy(x->done);
+        if (x->dev) (void)hipFree(x->dev);
+        if (x->host) (void)hipHostFree(x->host);
+        delete x;
+    }
+    S->est_live.clear();
+    S->est_queue.clear();
+    S->est_idle.clear();
 }
 
 }  // namespace

@@ -23,6 +23,15 @@
 
 #include "api_internal.hpp"
 
+namespace {
+// Sampling strides are odd: the all-orientations root array interleaves (u, v)
+// and (v, u), so an even stride would sample one orientation only.
+int64_t odd_stride(int64_t s) {
+    return s <= 1 ? 1 : (s | 1);
+}
+
+}  // namespace
+
 namespace gpint {
 
 LaunchCfg launch_for_plan(const gp_plan* p, const gp_launch* l, const DeviceGraph& g) {
@@ -30,24 +39,36 @@ LaunchCfg launch_for_plan(const gp_plan* p, const gp_launch* l, const DeviceGrap
     return apply_launch(p->launch, l);
 }
 
-double estimate_full_ms(const DeviceGraph& g, const GpPlanDesc& d, LaunchCfg cfg, double budget_ms,
-                        hipStream_t s, unsigned long long* res, uint64_t* sample_count, int64_t* sample_stride) {
+gp_status estimate_begin(const DeviceGraph& g, const GpPlanDesc& d, LaunchCfg cfg, double budget_ms,
+                         hipStream_t s, unsigned long long* res, int64_t* stride_out) {
     const int64_t roots = std::max<int64_t>(1, root_task_count(g, d));
-    const int64_t stride = std::max<int64_t>(1, roots / 4096);
-    if (sample_stride) *sample_stride = stride;
+    const int64_t stride = odd_stride(std::max<int64_t>(1, roots / 4096));
+    *stride_out = stride;
     cfg.root_stride = stride;
-    cfg.root_offset = stride / 2;
+    cfg.root_offset = 0;  // the first root is the heaviest: its tail shows
     cfg.budget_ms = budget_ms;
-    unsigned long long h[5] = {0, 0, 0, 0, 0};
-    if (launch_count(g, d, cfg, s, res, nullptr, false, res + 2) != GP_OK ||
-        hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-        return -1;
-    if (sample_count) *sample_count = h[0];
+    return launch_count(g, d, cfg, s, res, nullptr, false, res + 2);
+}
+
+double estimate_end(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCfg& cfg,
+                    const unsigned long long* h, int64_t stride) {
     if (h[1] & 4ull) return 1e300;  // a wavefront of the sample alone ran past the budget
     const double busy = (double)h[2] / g.wall_khz, chunk = (double)h[4] / g.wall_khz;
     const double resident = (double)g.num_cus * resident_waves_per_cu(d, cfg);
     return std::max(busy * (double)stride / resident, chunk);
+}
+
+double estimate_full_ms(const DeviceGraph& g, const GpPlanDesc& d, LaunchCfg cfg, double budget_ms,
+                        hipStream_t s, unsigned long long* res, uint64_t* sample_count, int64_t* sample_stride) {
+    int64_t stride = 1;
+    unsigned long long h[5] = {0, 0, 0, 0, 0};
+    if (estimate_begin(g, d, cfg, budget_ms, s, res, &stride) != GP_OK ||
+        hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return -1;
+    if (sample_stride) *sample_stride = stride;
+    if (sample_count) *sample_count = h[0];
+    return estimate_end(g, d, cfg, h, stride);
 }
 
 }  // namespace gpint
@@ -249,8 +270,9 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
                 str = std::max<int64_t>(1, std::min<int64_t>(str, roots / std::max<int64_t>(1, 2 * groups)));
                 cfg.chunk = 1;
             }
+            str = odd_stride(str);
             cfg.root_stride = str;
-            cfg.root_offset = str / 2;
+            cfg.root_offset = 0;  // the first root is the heaviest: its tail shows
             cfg.budget_ms = best_est < inf ? std::max(20.0, 3.0 * best_est) : 0.0;
             Timing t = time_launch(g->dg, d, cfg, s, res);
             if (t.wall < 0) {
@@ -281,10 +303,10 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
         int64_t stride = o.sample_stride;
         if (stride <= 0) {
             const int64_t roots = std::max<int64_t>(1, gpint::root_task_count(g->dg, p->desc));
-            const int64_t s0 = std::max<int64_t>(1, roots / 4096);
+            const int64_t s0 = odd_stride(std::max<int64_t>(1, roots / 4096));
             gpint::LaunchCfg cfg = base;
             cfg.root_stride = s0;
-            cfg.root_offset = s0 / 2;
+            cfg.root_offset = 0;
             cfg.budget_ms = budget_ms;  // a sample that runs past it still gives a lower bound
             Timing t = time_launch(g->dg, p->desc, cfg, s, res);
             if (t.wall < 0) st = GP_ERR_HIP;
@@ -333,9 +355,17 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
         };
         std::vector<Pick> picks;
         const int n_shape = o.tune_launch >= 0 ? 2 : 1;
-        for (size_t r = 0; st == GP_OK && r < fine.size() && (int)r < n_shape; ++r) {
-            const size_t c = fine[r].second;
-            Pick pk{fine[r].first, c, base};
+        // the two best, and the planner's own configuration (candidate 0) as well
+        std::vector<std::pair<double, size_t>> shape_set(fine.begin(),
+                                                         fine.begin() + std::min<size_t>(fine.size(), n_shape));
+        bool has0 = false;
+        for (auto& f : shape_set) has0 |= f.second == 0;
+        if (!has0 && o.tune_launch >= 0)
+            for (auto& f : coarse)
+                if (f.second == 0) shape_set.push_back({f.first, 0});
+        for (size_t r = 0; st == GP_OK && r < shape_set.size(); ++r) {
+            const size_t c = shape_set[r].second;
+            Pick pk{shape_set[r].first, c, base};
             if (o.tune_launch >= 0) {
                 best_est = inf;
                 pk.est = measure(cands[c].desc, base, stride, "shape", c, true);
@@ -373,7 +403,9 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
             }
             picks.push_back(pk);
         }
-        // 5. the two finalists once more on a sample 4x denser
+        // 5. the finalists once more on a sample 4x denser; then, when the
+        //    two best fit the budget, in full: estimates miss tails that the
+        //    sample did not contain, a full run does not
         if (st == GP_OK && picks.size() > 1 && spent < 3.0 * budget_ms && stride >= 4) {
             best_est = inf;
             for (auto& pk : picks) {
@@ -381,6 +413,16 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
                                    true);
                 if (t < 0) break;
                 pk.est = t;
+            }
+        }
+        std::stable_sort(picks.begin(), picks.end(), [](const Pick& a, const Pick& b) { return a.est < b.est; });
+        if (st == GP_OK && picks.size() > 1 && picks[0].est < inf && stride > 1 &&
+            picks[0].est + picks[1].est < budget_ms) {
+            best_est = inf;
+            for (size_t r = 0; r < 2 && st == GP_OK; ++r) {
+                double t = measure(cands[picks[r].c].desc, picks[r].launch, 1, "full", picks[r].c);
+                if (t < 0) break;
+                picks[r].est = t;
             }
         }
         size_t best = fine.empty() ? 0 : fine[0].second;

@@ -24,8 +24,20 @@ def run_stream(server, stream, patterns, time_scale: float = 1.0, note=None) -> 
         if note and (i + 1) % 500 == 0:
             note(f"submitted {i + 1}/{len(stream)}")
     out = []
-    for (t, g, p), tk in zip(stream, tickets):
-        st, c, lat = server.wait(tk)
+    last = time.perf_counter()
+    for i, ((t, g, p), tk) in enumerate(zip(stream, tickets)):
+        while True:
+            try:
+                st, c, lat = server.wait(tk, 5.0)
+                break
+            except RuntimeError as e:  # GP_ERR_TIMEOUT: still running; report progress
+                if getattr(e, "status", None) != -13:
+                    raise
+                if note:
+                    note(f"waiting: {i}/{len(stream)} collected, {server.stats()}")
+        if note and time.perf_counter() - last > 10.0:
+            last = time.perf_counter()
+            note(f"collected {i + 1}/{len(stream)}")
         out.append({"graph": g, "pattern": p, "status": st, "count": c, "latency_s": lat})
     wall = time.perf_counter() - t0
     for r in out:

@@ -76,7 +76,8 @@ def parse_args():
     ap.add_argument("--max-pattern-s", type=float, default=30.0,
                     help="batched workloads: patterns whose full run is estimated above this are "
                          "reported with their extrapolation instead of run")
-    ap.add_argument("--batch-group", type=int, default=64)
+    ap.add_argument("--batch-group", type=int, default=0,
+                    help="lanes per group of the batched launch (0: measured by gp_batch_tune)")
     ap.add_argument("--batch-leaf", type=int, default=3)
     ap.add_argument("--queries", type=int, default=2000, help="serve: stream length")
     ap.add_argument("--qps", type=float, default=50.0, help="serve: mean arrival rate")
@@ -344,7 +345,11 @@ def batched_main(args, desc, g, graph, st, names, plans, launches, base_plans, p
     base_plans = [base_plans[i] for i in keep]
     if not plans:
         raise SystemExit("no pattern of the workload is feasible within --max-pattern-s")
-    blaunch = dict(group=args.batch_group, leaf_mode=args.batch_leaf)
+    if args.batch_group > 0:
+        blaunch = dict(group=args.batch_group, leaf_mode=args.batch_leaf)
+    else:
+        blaunch, bms = gp.batch_tune(graph, plans, stream)
+        note(f"batch shape {blaunch}: {bms:.1f} ms")
     batch = gp.Batch(graph, plans, stream, **blaunch)
 
     plain_each = [[] for _ in plans]

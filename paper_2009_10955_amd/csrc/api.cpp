@@ -621,6 +621,53 @@ gp_status gp_batch_run(gp_batch* b, void* stream, uint64_t* out) {
     return GP_OK;
 }
 
+gp_status gp_batch_tune(const gp_graph* g, const gp_plan* const* plans, int32_t np, void* stream,
+                        gp_launch* out, double* best_ms) {
+    if (!g || !out) return GP_ERR_ARG;
+    std::vector<GpPlanDesc> descs;
+    std::vector<int> leafs;
+    gp_status st = batch_inputs(plans, np, &descs, &leafs);
+    if (st != GP_OK) return st;
+    DeviceGuard dgd(g->dg.device);
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        if (a) (void)hipEventDestroy(a);
+        return GP_ERR_HIP;
+    }
+    double best = -1;
+    gp_launch pick{};
+    for (int grp : {64, 32, 16}) {
+        for (int lm : {1, 3}) {
+            gp_launch l{};
+            l.group = grp;
+            l.leaf_mode = lm;
+            gpint::LaunchCfg cfg = gpint::launch_for_plan(plans[0], &l, g->dg);
+            gpint::BatchState bs;
+            st = gpint::batch_prepare(g->dg, descs.data(), leafs.data(), nullptr, nullptr, np, cfg, s, &bs);
+            if (st != GP_OK) break;
+            float ms = 0;
+            if (hipEventRecord(a, s) != hipSuccess || gpint::batch_enqueue(g->dg, bs, s) != GP_OK ||
+                hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                hipEventElapsedTime(&ms, a, b) != hipSuccess)
+                st = GP_ERR_HIP;
+            gpint::batch_release(&bs);
+            if (st != GP_OK) break;
+            if (best < 0 || ms < best) {
+                best = ms;
+                pick = l;
+            }
+        }
+        if (st != GP_OK) break;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (st != GP_OK) return st;
+    *out = pick;
+    if (best_ms) *best_ms = best;
+    return GP_OK;
+}
+
 void gp_free_batch(gp_batch* b) {
     if (!b) return;
     DeviceGuard dgd(b->g->dg.device);

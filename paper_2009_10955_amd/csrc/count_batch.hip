@@ -8,7 +8,7 @@
 // the plan its task belongs to; per-plan counts (and the wall-clock time
 // groups spent on each plan, for the serving scheduler) are reduced per group
 // into LDS and flushed once per wavefront at the end. Built once per group size,
-// largest pattern size and leaf mode (-DGP_BATCH_G=64/32, -DGP_BATCH_KMAX=
+// largest pattern size and leaf mode (-DGP_BATCH_G=64/32/16, -DGP_BATCH_KMAX=
 // 5/6/8, -DGP_BATCH_LEAF=1/3), so a batch carries only the register
 // footprint of its own shapes.
 #include "count_kernel.hpp"

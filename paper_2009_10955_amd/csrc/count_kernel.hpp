@@ -563,8 +563,18 @@ __device__ __forceinline__ int64_t entry_index(const int64_t* row_ptr, const int
     return b + lower_bound(col + b, (int32_t)(row_ptr[v0 + 1] - b), v1);
 }
 
+// Wavefronts per SIMD the compiler is asked to keep resident (it trims
+// registers, spilling a few if it must). The searches are bound by the
+// latency of scattered loads, so more resident wavefronts pay even against
+// some spills; measured on R-MAT 17 for k = 5 (64-lane groups with lanes on
+// separate candidates: 8, others 6). Larger patterns keep the compiler's
+// choice, where the same targets spill tens of registers.
+constexpr int occupancy_target(int K, int G, int LEAF) {
+    return K > 5 ? 1 : (G == 64 && LEAF == 1 ? 8 : 6);
+}
+
 template <int K, int G, int LEAF, int MODE, bool IEP>
-__global__ __launch_bounds__(kBlock) void count_kernel(GpPlanDesc d, CountArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(occupancy_target(K, G, LEAF)))) void count_kernel(GpPlanDesc d, CountArgs a) {
     constexpr bool PER_ROOT = MODE == MODE_PER_ROOT;
     __shared__ int32_t s_len[kBlock / G][GP_DESC_MAX_BUILDS];
     Ctx<G> c;

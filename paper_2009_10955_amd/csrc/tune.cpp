@@ -354,6 +354,7 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
             gpint::LaunchCfg launch;
         };
         std::vector<Pick> picks;
+        std::vector<Pick> tried;  // every (configuration, shape) measured on the full sample
         const int n_shape = o.tune_launch >= 0 ? 2 : 1;
         // the two best, and the planner's own configuration (candidate 0) as well
         std::vector<std::pair<double, size_t>> shape_set(fine.begin(),
@@ -363,45 +364,61 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
         if (!has0 && o.tune_launch >= 0)
             for (auto& f : coarse)
                 if (f.second == 0) shape_set.push_back({f.first, 0});
+        auto leaf_ok = [&](const GpPlanDesc& bd, int lm) {
+            if (lm == 2) return !bd.iep && (k <= 3 || bd.lv[k - 1].last_list >= 0);
+            if (lm == 3) return k >= 5 && !bd.iep && bd.build_begin[k - 3] == bd.build_end[k - 3];
+            return true;
+        };
+        // pass A: every leaf mode with 64-lane groups, for each configuration
         for (size_t r = 0; st == GP_OK && r < shape_set.size(); ++r) {
             const size_t c = shape_set[r].second;
             Pick pk{shape_set[r].first, c, base};
             if (o.tune_launch >= 0) {
-                best_est = inf;
-                pk.est = measure(cands[c].desc, base, stride, "shape", c, true);
-                if (pk.est < 0) break;
                 const GpPlanDesc& bd = cands[c].desc;
-                const GpLevel& leaf = bd.lv[k - 1];
-                const bool leaf_intersects = !bd.iep && (k <= 3 || leaf.last_list >= 0);
-                const bool can_flatten = k >= 5 && !bd.iep && bd.build_begin[k - 3] == bd.build_end[k - 3];
-                for (int grp : {64, 32, 16, 8}) {
-                    if (bd.iep && grp < 32) continue;
-                    double best_g = inf;
-                    for (int lm : {1, 2, 3}) {
-                        if (lm == 2 && !leaf_intersects) continue;
-                        if (lm == 3 && !can_flatten) continue;
-                        if (spent > 2.5 * budget_ms) break;
-                        gpint::LaunchCfg cfg = base;
-                        cfg.group = grp;
-                        cfg.leaf = lm;
-                        if (grp == base.group && lm == base.leaf) {
-                            best_g = std::min(best_g, pk.est);
-                            continue;
-                        }
-                        double t = measure(bd, cfg, stride, "shape", c, true);
-                        if (t < 0) break;
-                        best_g = std::min(best_g, t);
-                        if (t < pk.est) {
-                            pk.est = t;
-                            pk.launch = cfg;
-                        }
+                best_est = inf;
+                pk.est = measure(bd, base, stride, "shape", c, true);
+                if (pk.est < 0) break;
+                tried.push_back(pk);
+                for (int lm : {2, 3}) {
+                    if (!leaf_ok(bd, lm) || spent > 2.5 * budget_ms) continue;
+                    gpint::LaunchCfg cfg = base;
+                    cfg.leaf = lm;
+                    double t = measure(bd, cfg, stride, "shape", c, true);
+                    if (t < 0) break;
+                    tried.push_back(Pick{t, c, cfg});
+                    if (t < pk.est) {
+                        pk.est = t;
+                        pk.launch = cfg;
                     }
-                    if (st != GP_OK) break;
-                    // narrower groups only get slower once they lose by 1.5x
-                    if (best_g > 1.5 * pk.est) break;
                 }
             }
             picks.push_back(pk);
+        }
+        std::stable_sort(picks.begin(), picks.end(), [](const Pick& a, const Pick& b) { return a.est < b.est; });
+        // pass B: narrower groups for the two best, while they stay within 1.5x
+        for (size_t r = 0; st == GP_OK && o.tune_launch >= 0 && r < picks.size() && r < 2; ++r) {
+            Pick& pk = picks[r];
+            const GpPlanDesc& bd = cands[pk.c].desc;
+            best_est = pk.est;
+            for (int grp : {32, 16, 8}) {
+                if (bd.iep && grp < 32) continue;
+                double best_g = inf;
+                for (int lm : {1, 2, 3}) {
+                    if (!leaf_ok(bd, lm) || spent > 2.5 * budget_ms) continue;
+                    gpint::LaunchCfg cfg = base;
+                    cfg.group = grp;
+                    cfg.leaf = lm;
+                    double t = measure(bd, cfg, stride, "shape", pk.c, true);
+                    if (t < 0) break;
+                    tried.push_back(Pick{t, pk.c, cfg});
+                    best_g = std::min(best_g, t);
+                    if (t < pk.est) {
+                        pk.est = t;
+                        pk.launch = cfg;
+                    }
+                }
+                if (st != GP_OK || best_g > 1.5 * pk.est) break;
+            }
         }
         // 5. the finalists once more on a sample 4x denser; then, when the
         //    two best fit the budget, in full: estimates miss tails that the
@@ -415,14 +432,47 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
                 pk.est = t;
             }
         }
+        // full runs of the best (configuration, shape) pairs while they fit
+        // twice the budget, no pair twice
         std::stable_sort(picks.begin(), picks.end(), [](const Pick& a, const Pick& b) { return a.est < b.est; });
-        if (st == GP_OK && picks.size() > 1 && picks[0].est < inf && stride > 1 &&
-            picks[0].est + picks[1].est < budget_ms) {
-            best_est = inf;
-            for (size_t r = 0; r < 2 && st == GP_OK; ++r) {
-                double t = measure(cands[picks[r].c].desc, picks[r].launch, 1, "full", picks[r].c);
-                if (t < 0) break;
-                picks[r].est = t;
+        std::stable_sort(tried.begin(), tried.end(), [](const Pick& a, const Pick& b) { return a.est < b.est; });
+        // the best configuration at its best leaf mode for every group width
+        // measured (sample estimates rank widths within their noise), then
+        // the runner-up configuration's best pair
+        std::vector<Pick> full;
+        auto add_full = [&](const Pick& pk) {
+            for (const Pick& f : full)
+                if (f.c == pk.c && f.launch.group == pk.launch.group && f.launch.leaf == pk.launch.leaf) return;
+            if (pk.est < inf) full.push_back(pk);
+        };
+        if (!picks.empty()) {
+            add_full(picks[0]);
+            for (int grp : {64, 32, 16, 8})
+                for (const Pick& pk : tried)  // sorted: the first of a width is its best
+                    if (pk.c == picks[0].c && pk.launch.group == grp) {
+                        add_full(pk);
+                        break;
+                    }
+            for (const Pick& pk : picks)
+                if (pk.c != picks[0].c) {
+                    add_full(pk);
+                    break;
+                }
+        }
+        if (st == GP_OK && stride > 1 && full.size() > 1) {
+            std::stable_sort(full.begin(), full.end(), [](const Pick& a, const Pick& b) { return a.est < b.est; });
+            double planned = 0;
+            size_t n_full = 0;
+            while (n_full < full.size() && planned + full[n_full].est < 2.0 * budget_ms) planned += full[n_full++].est;
+            if (n_full > 1) {
+                best_est = inf;
+                for (size_t r = 0; r < n_full && st == GP_OK; ++r) {
+                    double t = measure(cands[full[r].c].desc, full[r].launch, 1, "full", full[r].c);
+                    if (t < 0) break;
+                    full[r].est = t;
+                }
+                full.resize(n_full);
+                picks = full;
             }
         }
         size_t best = fine.empty() ? 0 : fine[0].second;

@@ -126,6 +126,7 @@ SIGNATURES = {
     "gp_count_traffic": (_I32, [_P, _P, ctypes.POINTER(Launch), _P,
                                 ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]),
     "gp_batch_create": (_I32, [_P, _P, _I32, ctypes.POINTER(Launch), _P, ctypes.POINTER(_P)]),
+    "gp_batch_tune": (_I32, [_P, _P, _I32, _P, ctypes.POINTER(Launch), ctypes.POINTER(ctypes.c_double)]),
     "gp_batch_run": (_I32, [_P, _P, _P]),
     "gp_free_batch": (None, [_P]),
     "gp_server_opts_default": (None, [ctypes.POINTER(ServerOpts)]),
@@ -429,6 +430,17 @@ def count_batch(graph: Graph, plans: Sequence[Plan], stream=None, **launch) -> l
     _check(_lib().gp_count_batch(graph.handle, arr, len(plans), ctypes.byref(lp),
                                  _stream_handle(stream), out), "gp_count_batch")
     return list(out)
+
+
+def batch_tune(graph: Graph, plans: Sequence[Plan], stream=None) -> tuple[dict, float]:
+    """Fastest batched launch shape for these plans (gp_batch_tune): ({group,
+    leaf_mode}, its time in ms)."""
+    arr = (ctypes.c_void_p * len(plans))(*[p.handle for p in plans])
+    lp = Launch()
+    ms = ctypes.c_double()
+    _check(_lib().gp_batch_tune(graph.handle, arr, len(plans), _stream_handle(stream), ctypes.byref(lp),
+                                ctypes.byref(ms)), "gp_batch_tune")
+    return {"group": lp.group, "leaf_mode": lp.leaf_mode}, ms.value
 
 
 class Batch:

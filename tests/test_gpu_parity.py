@@ -478,6 +478,19 @@ def test_estimate_is_sane():
     assert ei.value.status == -12
 
 
+def test_batch_tune_picks_a_shape_with_the_same_counts():
+    g = I.config_graph(2)
+    graph = gp.Graph.from_csr(g, device=True)
+    plans = [gp.Plan(*P[n], stats=graph.stats()) for n in ["house", "4-clique", "prism"]]
+    want = [gp.count(graph, p) for p in plans]
+    shape, ms = gp.batch_tune(graph, plans)
+    assert shape["group"] in (64, 32, 16) and shape["leaf_mode"] in (1, 3) and ms > 0
+    assert gp.count_batch(graph, plans, **shape) == want
+    for grp in (16, 32, 64):
+        for leaf in (1, 3):
+            assert gp.count_batch(graph, plans, group=grp, leaf_mode=leaf) == want, (grp, leaf)
+
+
 def test_batch_with_split_roots_equals_plain():
     g = I.config_graph(2)
     graph = gp.Graph.from_csr(g, device=True)

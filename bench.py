@@ -81,6 +81,7 @@ def parse_args():
     ap.add_argument("--batch-leaf", type=int, default=3)
     ap.add_argument("--queries", type=int, default=2000, help="serve: stream length")
     ap.add_argument("--qps", type=float, default=50.0, help="serve: mean arrival rate")
+    ap.add_argument("--serve-leaf", type=int, default=1, help="serve: leaf mode of the batched launches")
     ap.add_argument("--max-query-ms", type=float, default=20.0,
                     help="serve: reject queries whose measured estimate exceeds this")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -386,6 +387,19 @@ def batched_main(args, desc, g, graph, st, names, plans, launches, base_plans, p
         note(f"step {s + 1}/{args.steps}: batched {b_ms[-1]:.1f} ms, plain {p_ms[-1]:.1f} ms")
     if counts_b != counts_p:
         raise RuntimeError(f"batched counts {counts_b} differ from plain counts {counts_p}")
+    # like for like: one launch per pattern at the batch's own launch shape
+    same_ms = []
+    for s in range(args.steps):
+        a, b = ev(), ev()
+        torch.cuda.synchronize()
+        a.record(stream)
+        counts_s = [gp.count(graph, p, stream, **dict(l, **blaunch)) for p, l in zip(plans, launches)]
+        b.record(stream)
+        torch.cuda.synchronize()
+        same_ms.append(a.elapsed_time(b))
+    if counts_s != counts_b:
+        raise RuntimeError("plain counts at the batch's shape differ")
+    note(f"plain at the batch's shape: {sum(same_ms) / len(same_ms):.1f} ms per step")
     ms_b = sum(b_ms) / len(b_ms)
     ms_p = sum(p_ms) / len(p_ms)
     value = sum(counts_b) / (ms_b / 1e3)
@@ -414,6 +428,8 @@ def batched_main(args, desc, g, graph, st, names, plans, launches, base_plans, p
                    "batch_launch": blaunch},
         "counts": dict(zip(names, counts_b)),
         "plain_ms_per_step": ms_p,
+        "plain_same_shape_ms_per_step": sum(same_ms) / len(same_ms),
+        "batched_speedup_same_shape": (sum(same_ms) / len(same_ms)) / ms_b,
         "plain_ms_per_pattern": {n: round(sum(x[-args.steps:]) / len(x[-args.steps:]), 3)
                                  for n, x in zip(names, plain_each)},
         "batched_speedup": ms_p / ms_b,
@@ -450,28 +466,37 @@ def serve_main(args, desc):
         del g
     classes = I.connected_patterns(3, 6)
     stream = I.poisson_stream(args.queries, args.qps, len(graphs), len(classes), seed=5)
-    server = gp.Server(graphs, max_query_ms=args.max_query_ms)
+    server = gp.Server(graphs, max_query_ms=args.max_query_ms, leaf_mode=args.serve_leaf)
     res = SV.run_stream(server, stream, classes, note=note)
     stats = server.stats()
     server.close()
     summ = SV.summarise(res)
     note(f"stream done: {summ}")
-    # every completed count against a solo count of the same (graph, pattern)
+    # every completed query again, alone: one launch and synchronisation
+    # each, in arrival order; its count must equal the served one
+    import torch
     solo = {}
+    plans_solo = {}
     bad = 0
+    solo_s = 0.0
     t_last = time.perf_counter()
     for r in res:
         if time.perf_counter() - t_last > 10.0:
             t_last = time.perf_counter()
-            note(f"solo checks: {len(solo)} distinct queries counted")
+            note(f"solo runs: {len(solo)} distinct queries counted")
         if r["status"] != 0:
             continue
         key = (r["graph"], r["pattern"])
-        if key not in solo:
+        G = graphs[r["graph"]]
+        if key not in plans_solo:
             k, e = classes[r["pattern"]]
-            G = graphs[r["graph"]]
-            solo[key] = gp.count(G, gp.Plan(k, e, stats=G.stats()))
-        bad += solo[key] != r["count"]
+            plans_solo[key] = gp.Plan(k, e, stats=G.stats())
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        c = gp.count(G, plans_solo[key])
+        solo_s += time.perf_counter() - t
+        solo[key] = c
+        bad += c != r["count"]
     note(f"checked {sum(r['status'] == 0 for r in res)} completed counts against "
          f"{len(solo)} solo counts: {bad} mismatches")
     if bad:
@@ -482,10 +507,13 @@ def serve_main(args, desc):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": desc, "graphs": meta, "queries": args.queries, "qps": args.qps,
-                   "max_query_ms": args.max_query_ms, "parallelism": "single GPU"},
+                   "max_query_ms": args.max_query_ms, "leaf_mode": args.serve_leaf,
+                   "parallelism": "single GPU"},
         "latency": summ,
         "server": stats,
         "solo_checked": len(solo), "mismatches": bad,
+        "solo_total_s": solo_s,
+        "served_gpu_s": stats["busy_seconds"],
         "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)

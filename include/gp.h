@@ -350,13 +350,15 @@ typedef struct {
                                this with GP_ERR_BUDGET (0 = no cap) */
     int64_t initial_slice;  /* root tasks a query gets in its first iteration (0 = 8192) */
     int32_t group;          /* lanes per group of the batched kernel: 64, 32 or 16 (0 = 64) */
-    int32_t leaf_mode;      /* 1 or 3 (0 = 3) */
-    int32_t waves_per_cu;   /* 0 = 16 */
+    int32_t leaf_mode;      /* 1 or 3 (0 = 1) */
+    int32_t waves_per_cu;   /* 0 = 32 */
     double max_query_ms;    /* > 0: the first query of each (graph, pattern) counts a strided
                                sample of its root tasks first; a query whose full run is then
                                estimated above max_query_ms (summed wavefront busy time scaled
                                to all tasks over the resident wavefronts, or the longest task
-                               chunk if longer) is rejected with GP_ERR_BUDGET (0 = off) */
+                               chunk if longer) is rejected with GP_ERR_BUDGET, and so is
+                               one whose sample has a wavefront run past max_query_ms / 4
+                               (0 = off) */
 } gp_server_opts;
 
 typedef struct {

@@ -61,7 +61,7 @@ __device__ __forceinline__ void batch_roots(const GpPlanDesc& d, Ctx<G>& c, cons
     }
 }
 
-__global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(occupancy_target(KMAX, G, LEAF)))) void batch_kernel(BatchArgs a) {
     __shared__ int32_t s_len[kBlock / G][GP_DESC_MAX_BUILDS];
     __shared__ unsigned long long s_cnt[kBlock / 64][kBatchMaxPlans];
     __shared__ unsigned s_ovf[kBlock / 64][kBatchMaxPlans];

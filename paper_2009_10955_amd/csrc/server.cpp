@@ -8,18 +8,24 @@
 // predicts run time across patterns poorly (on power-law graphs it misses
 // the hubs), so with max_query_ms the first query of each (graph, pattern)
 // also counts a strided root sample whose wavefront busy time gives a
-// full-run estimate, and queries estimated above the limit are rejected too. Admitted queries join the active set of their graph as
+// full-run estimate, and queries estimated above the limit are rejected too.
+// The sample stops once a wavefront has run a quarter of the limit (such a
+// query is rejected): a sample of a heavy pattern would otherwise hold every
+// wavefront of the device for the whole limit. Admitted queries join the active set of their graph as
 // batch slots (at most 64 per launch: the batched kernel keeps per-plan
 // counters in LDS) and HBM scratch allow.
 //
 // Work proceeds in iterations. Each iteration launches, per graph with active
 // queries, ONE batched persistent kernel over a slice of every active query's
 // remaining root tasks (graphs on their own streams, so their launches
-// overlap on the device). A query finishes when its last slice has run; new
-// queries join at the next iteration, so a short query arriving behind a long
-// one waits at most one iteration. Slices adapt: the kernel reports the wall
-// time its groups spent on each query, which gives each query's task rate,
-// and the next slice aims at an equal share of the target iteration time.
+// overlap on the device). Two launches per graph are kept in flight on two
+// streams: the next is enqueued before the previous one is collected, so its
+// wavefronts take the device as the previous launch's tail drains. A query
+// finishes when its last slice has been collected; new queries join at the
+// next launch, so a short query arriving behind a long one waits about one
+// iteration. Slices adapt: the kernel reports the wall time its groups spent
+// on each query, which gives each query's task rate, and the next slice aims
+// at an equal share of the target iteration time.
 // Counts are exact: slices partition each query's root tasks.
 #include <hip/hip_runtime.h>
 
@@ -52,7 +58,9 @@ struct Query {
     int k = 0;
     std::vector<int32_t> edges;
     const gp_plan* plan = nullptr;  // owned by the plan cache
-    int64_t n_tasks = 0, progress = 0, slice = 0, last_slice = 0;
+    int64_t n_tasks = 0, progress = 0, slice = 0;
+    int64_t launched = 0;  // tasks handed to launches (progress: tasks collected)
+    int inflight = 0;      // launches in flight that hold a slice of this query
     uint64_t count = 0;
     bool ovf = false;
     QState state = Q_QUEUED;
@@ -76,9 +84,18 @@ struct gp_server {
     gp_status fatal = GP_OK;
     gp_server_stats stats{};
     std::thread worker;
-    // worker-owned
-    std::vector<gpint::BatchArena> arenas;
-    std::vector<hipStream_t> streams;
+    // worker-owned. Two launch slots per graph (arena + stream each): the
+    // next iteration is enqueued before the previous one is collected, so its
+    // wavefronts fill the device while the previous launch's tail drains.
+    std::vector<gpint::BatchArena> arenas;  // [graph * 2 + slot]
+    std::vector<hipStream_t> streams;       // [graph * 2 + slot]
+    struct Launch {
+        int graph = 0, slot = 0;
+        std::vector<Query*> qs;
+        std::vector<int64_t> slices;
+    };
+    std::deque<Launch> inflight;
+    std::vector<int> slot_busy;  // [graph * 2 + slot]
     std::vector<std::deque<Query*>> waiting;
     std::vector<std::vector<Query*>> active;
     std::map<std::pair<int, std::vector<int32_t>>, gp_plan*> plan_cache;
@@ -220,8 +237,8 @@ void poll_estimates(gp_server* S) {
         gpint::LaunchCfg cfg = server_launch(S);
         cfg.waves_per_cu = 32;
         ok = ok &&
-             gpint::estimate_begin(S->graphs[x->graph]->dg, x->plan->desc, cfg, S->opts.max_query_ms, x->stream,
-                                   x->dev, &x->stride) == GP_OK &&
+             gpint::estimate_begin(S->graphs[x->graph]->dg, x->plan->desc, cfg, S->opts.max_query_ms / 4.0,
+                                   x->stream, x->dev, &x->stride) == GP_OK &&
              hipMemcpyAsync(x->host, x->dev, 5 * sizeof(unsigned long long), hipMemcpyDeviceToHost, x->stream) ==
                  hipSuccess &&
              hipEventRecord(x->done, x->stream) == hipSuccess;
@@ -256,31 +273,46 @@ void poll_estimates(gp_server* S) {
     S->est_live.swap(still);
 }
 
+bool arena_fits(const gp_server* S, int g, int nbuf) {
+    const gpint::BatchArena& a = S->arenas[2 * g];
+    return a.st.queue && a.nbuf_cap >= nbuf;
+}
+
+// Both launch slots of graph g with room for nbuf buffer slots per group.
+// Only while neither slot is in flight.
 gp_status ensure_arena(gp_server* S, int g, int nbuf) {
-    gpint::BatchArena& a = S->arenas[g];
-    if (a.st.queue && a.nbuf_cap >= nbuf) return GP_OK;
-    const int want = std::max(nbuf, std::max(a.nbuf_cap * 2, 4));
-    gpint::arena_release(&a);
-    return gpint::arena_create(S->graphs[g]->dg, std::min(want, GP_DESC_MAX_BUILDS), server_launch(S), &a);
+    if (arena_fits(S, g, nbuf)) return GP_OK;
+    const int want = std::max(nbuf, std::max(S->arenas[2 * g].nbuf_cap * 2, 4));
+    for (int slot = 0; slot < 2; ++slot) {
+        gpint::BatchArena& a = S->arenas[2 * g + slot];
+        gpint::arena_release(&a);
+        gp_status rc =
+            gpint::arena_create(S->graphs[g]->dg, std::min(want, GP_DESC_MAX_BUILDS), server_launch(S), &a);
+        if (rc != GP_OK) return rc;
+    }
+    return GP_OK;
 }
 
 void worker_main(gp_server* S) {
     (void)hipSetDevice(S->device);
     const int ng = (int)S->graphs.size();
-    S->arenas.assign(ng, gpint::BatchArena{});
-    S->streams.assign(ng, nullptr);
+    S->arenas.assign(2 * ng, gpint::BatchArena{});
+    S->streams.assign(2 * ng, nullptr);
+    S->slot_busy.assign(2 * ng, 0);
     S->waiting.assign(ng, {});
     S->active.assign(ng, {});
-    for (int g = 0; g < ng; ++g) {
-        if (hipStreamCreateWithFlags(&S->streams[g], hipStreamNonBlocking) != hipSuccess) {
+    for (int i = 0; i < 2 * ng; ++i) {
+        if (hipStreamCreateWithFlags(&S->streams[i], hipStreamNonBlocking) != hipSuccess) {
             std::lock_guard<std::mutex> lk(S->mu);
             S->fatal = GP_ERR_HIP;
         }
     }
     const double target = S->opts.target_ms / 1e3;
+    const gpint::LaunchCfg lcfg = server_launch(S);
+    double busy_since = -1;  // wall time the device last went from idle to busy
     for (;;) {
         std::vector<Query*> fresh;
-        bool idle = true;
+        bool idle = S->inflight.empty();
         for (int g = 0; g < ng; ++g)
             if (!S->active[g].empty() || !S->waiting[g].empty()) idle = false;
         const bool estimating = !S->est_live.empty() || !S->est_queue.empty();
@@ -319,10 +351,14 @@ void worker_main(gp_server* S) {
         for (int g = 0; g < ng; ++g) {
             while ((int)S->active[g].size() < S->opts.max_active && !S->waiting[g].empty()) {
                 Query* q = S->waiting[g].front();
-                if (ensure_arena(S, g, q->plan->desc.nbuf) != GP_OK) {
-                    S->waiting[g].pop_front();
-                    finish(S, q, GP_ERR_NOMEM);
-                    continue;
+                if (!arena_fits(S, g, q->plan->desc.nbuf)) {
+                    // growing the arenas waits until this graph has nothing in flight
+                    if (S->slot_busy[2 * g] || S->slot_busy[2 * g + 1]) break;
+                    if (ensure_arena(S, g, q->plan->desc.nbuf) != GP_OK) {
+                        S->waiting[g].pop_front();
+                        finish(S, q, GP_ERR_NOMEM);
+                        continue;
+                    }
                 }
                 S->waiting[g].pop_front();
                 q->state = Q_ACTIVE;
@@ -338,7 +374,7 @@ void worker_main(gp_server* S) {
                 }
                 bool midflight = false;
                 for (Query* o : S->active[g])
-                    if (o->progress > 0) midflight = true;
+                    if (o->launched > 0) midflight = true;
                 S->active[g].push_back(q);
                 std::lock_guard<std::mutex> lk(S->mu);
                 if (midflight) ++S->stats.joined_midflight;
@@ -346,89 +382,108 @@ void worker_main(gp_server* S) {
             }
             if (!S->active[g].empty()) any = true;
         }
-        if (!any) continue;
+        if (!any && S->inflight.empty()) continue;
 
-        // one iteration: a batched launch per graph, all graphs overlapping
-        const double t0 = now_s();
-        std::vector<int> launched(ng, 0);
         for (int g = 0; g < ng; ++g) {
             auto& act = S->active[g];
-            if (act.empty()) continue;
-            std::vector<GpPlanDesc> descs(act.size());
-            std::vector<int64_t> offs(act.size()), cnts(act.size());
-            for (size_t i = 0; i < act.size(); ++i) {
-                descs[i] = act[i]->plan->desc;
-                offs[i] = act[i]->progress;
-                cnts[i] = std::min(act[i]->slice, act[i]->n_tasks - act[i]->progress);
-                act[i]->last_slice = cnts[i];
-            }
-            gp_status rc = gpint::arena_launch(S->graphs[g]->dg, &S->arenas[g], descs.data(), offs.data(),
-                                               cnts.data(), (int)act.size(), S->streams[g]);
-            if (rc != GP_OK) {
-                for (Query* q : act) finish(S, q, rc);
-                act.clear();
-                continue;
-            }
-            launched[g] = 1;
+            act.erase(std::remove_if(act.begin(), act.end(), [](Query* q) { return q->state == Q_DONE; }),
+                      act.end());
         }
-        int n_active = 0;
+        // launch: per graph, a slice of every active query's remaining tasks
+        // into a free slot (at most one new launch per graph per pass)
+        bool launched_any = false;
         for (int g = 0; g < ng; ++g) {
-            if (!launched[g]) continue;
-            if (hipStreamSynchronize(S->streams[g]) != hipSuccess) {
-                for (Query* q : S->active[g]) finish(S, q, GP_ERR_HIP);
-                S->active[g].clear();
-                launched[g] = 0;
+            int slot = !S->slot_busy[2 * g] ? 0 : (!S->slot_busy[2 * g + 1] ? 1 : -1);
+            if (slot < 0) continue;
+            gp_server::Launch L;
+            L.graph = g;
+            L.slot = slot;
+            std::vector<GpPlanDesc> descs;
+            std::vector<int64_t> offs;
+            for (Query* q : S->active[g]) {
+                if (q->launched >= q->n_tasks || q->state == Q_DONE) continue;
+                const int64_t c = std::min(q->slice, q->n_tasks - q->launched);
+                descs.push_back(q->plan->desc);
+                offs.push_back(q->launched);
+                L.qs.push_back(q);
+                L.slices.push_back(c);
+            }
+            if (L.qs.empty()) continue;
+            const int idx = 2 * g + slot;
+            gp_status rc = gpint::arena_launch(S->graphs[g]->dg, &S->arenas[idx], descs.data(), offs.data(),
+                                               L.slices.data(), (int)L.qs.size(), S->streams[idx]);
+            if (rc != GP_OK) {
+                for (Query* q : L.qs) finish(S, q, rc);
                 continue;
             }
-            n_active += (int)S->active[g].size();
+            for (size_t i = 0; i < L.qs.size(); ++i) {
+                L.qs[i]->launched += L.slices[i];
+                ++L.qs[i]->inflight;
+            }
+            S->slot_busy[idx] = 1;
+            if (S->inflight.empty()) busy_since = now_s();
+            S->inflight.push_back(std::move(L));
+            launched_any = true;
+            std::lock_guard<std::mutex> lk(S->mu);
+            ++S->stats.launches;
         }
-        const double T = std::max(1e-6, now_s() - t0);
+        // collect the oldest launch once nothing more can be launched
+        if (launched_any || S->inflight.empty()) continue;
+        gp_server::Launch L = std::move(S->inflight.front());
+        S->inflight.pop_front();
+        const int idx = 2 * L.graph + L.slot;
+        const bool ok = hipStreamSynchronize(S->streams[idx]) == hipSuccess;
+        S->slot_busy[idx] = 0;
+        if (S->inflight.empty() && busy_since >= 0) {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->stats.busy_seconds += now_s() - busy_since;
+            busy_since = -1;
+        }
         {
             std::lock_guard<std::mutex> lk(S->mu);
             ++S->stats.iterations;
-            S->stats.busy_seconds += T;
-            for (int g = 0; g < ng; ++g) S->stats.launches += launched[g];
         }
-        // collect, retire finished queries, and size the next slices
+        const unsigned long long* r = S->arenas[idx].h_result;
+        int n_active = 0;
+        for (int g = 0; g < ng; ++g) n_active += (int)S->active[g].size();
         const double fair = target / std::max(1, n_active);
-        for (int g = 0; g < ng; ++g) {
-            if (!launched[g]) continue;
-            auto& act = S->active[g];
-            const unsigned long long* r = S->arenas[g].h_result;
-            double busy_sum = 0;
-            for (size_t i = 0; i < act.size(); ++i) busy_sum += (double)r[3 * i + 2];
-            std::vector<Query*> keep;
-            for (size_t i = 0; i < act.size(); ++i) {
-                Query* q = act[i];
-                const uint64_t c = r[3 * i];
-                const uint64_t s = q->count + c;
-                if (s < q->count || r[3 * i + 1]) q->ovf = true;
-                q->count = s;
-                q->progress += q->last_slice;
-                ++q->iterations;
-                if (q->progress >= q->n_tasks) {
-                    finish(S, q, q->ovf ? GP_ERR_OVERFLOW : GP_OK);
-                    continue;
-                }
-                // this query's share of the iteration, from the groups' busy time
-                const double share = busy_sum > 0 ? (double)r[3 * i + 2] / busy_sum : 1.0 / act.size();
-                const double t_q = std::max(1e-6, T * share);
-                const double rate = (double)q->last_slice / t_q;
-                double next = rate * fair;
-                next = std::min(next, 4.0 * (double)q->last_slice + 1);
-                next = std::max(next, 64.0);
-                q->slice = (int64_t)std::min(next, 1e12);
-                keep.push_back(q);
+        // GPU seconds a query's slice used: its groups' busy clock ticks over
+        // the groups the device keeps resident
+        const double groups = (double)S->graphs[L.graph]->dg.num_cus * lcfg.waves_per_cu * (64.0 / lcfg.group);
+        const double tick_s = 1.0 / (S->graphs[L.graph]->dg.wall_khz * 1e3);
+        for (size_t i = 0; i < L.qs.size(); ++i) {
+            Query* q = L.qs[i];
+            --q->inflight;
+            if (q->state == Q_DONE) continue;
+            if (!ok) {
+                finish(S, q, GP_ERR_HIP);
+                continue;
             }
-            act.swap(keep);
+            const uint64_t c = r[3 * i];
+            const uint64_t sum = q->count + c;
+            if (sum < q->count || r[3 * i + 1]) q->ovf = true;
+            q->count = sum;
+            q->progress += L.slices[i];
+            ++q->iterations;
+            if (q->progress >= q->n_tasks && q->inflight == 0) {
+                finish(S, q, q->ovf ? GP_ERR_OVERFLOW : GP_OK);
+                continue;
+            }
+            // next slice: this query's task rate times its fair share of the target
+            const double t_q = std::max(1e-7, (double)r[3 * i + 2] * tick_s / groups);
+            const double rate = (double)L.slices[i] / t_q;
+            double next = rate * fair;
+            next = std::min(next, 4.0 * (double)L.slices[i] + 1);
+            next = std::max(next, 64.0);
+            q->slice = (int64_t)std::min(next, 1e12);
         }
     }
-    for (int g = 0; g < ng; ++g) {
-        if (S->streams[g]) {
-            (void)hipStreamSynchronize(S->streams[g]);
-            (void)hipStreamDestroy(S->streams[g]);
+    for (int i = 0; i < 2 * ng; ++i) {
+        if (S->streams[i]) {
+            (void)hipStreamSynchronize(S->streams[i]);
+            (void)hipStreamDestroy(S->streams[i]);
         }
-        gpint::arena_release(&S->arenas[g]);
+        gpint::arena_release(&S->arenas[i]);
     }
     for (gp_server::Estimate* x : S->est_live) S->est_idle.push_back(x);
     for (gp_server::Estimate* x : S->est_queue) S->est_idle.push_back(x);
@@ -458,8 +513,8 @@ void gp_server_opts_default(gp_server_opts* o) {
     o->target_ms = 25.0;
     o->initial_slice = 8192;
     o->group = 64;
-    o->leaf_mode = 3;
-    o->waves_per_cu = 16;
+    o->leaf_mode = 1;
+    o->waves_per_cu = 32;
 }
 
 gp_status gp_server_create(const gp_graph* const* graphs, int32_t ng, const gp_server_opts* opts,
@@ -475,8 +530,8 @@ gp_status gp_server_create(const gp_graph* const* graphs, int32_t ng, const gp_s
     if (o.target_ms <= 0) o.target_ms = 25.0;
     if (o.initial_slice <= 0) o.initial_slice = 8192;
     if (o.group != 64 && o.group != 32 && o.group != 16) o.group = 64;
-    if (o.leaf_mode != 1 && o.leaf_mode != 3) o.leaf_mode = 3;
-    if (o.waves_per_cu <= 0 || o.waves_per_cu > 32) o.waves_per_cu = 16;
+    if (o.leaf_mode != 1 && o.leaf_mode != 3) o.leaf_mode = 1;
+    if (o.waves_per_cu <= 0 || o.waves_per_cu > 32) o.waves_per_cu = 32;
     if (o.max_query_ms < 0 || o.cost_cap < 0) return GP_ERR_ARG;
     gp_server* S = new (std::nothrow) gp_server;
     if (!S) return GP_ERR_NOMEM;

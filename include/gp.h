@@ -121,7 +121,10 @@ typedef struct {
     int32_t leaf_mode;     /* 0 auto, 1: lanes take different second-to-last candidates and
                               count the last level alone, 2: the group counts each one together,
                               3: the last two enumerated levels are flattened into one
-                              load-balanced batch of (x, y) pairs (k >= 5; else as 1) */
+                              load-balanced batch of (x, y) pairs (k >= 5; else as 1),
+                              4: as 1, but where the last level is a group-uniform hub
+                              bitmap intersected with N(x), a long N(x) is walked by the
+                              whole group (coalesced loads; else as 1) */
     int32_t root_stride;   /* count only every root_stride-th root task (0 or 1 = all), */
     int32_t root_offset;   /* starting at root_offset: a seeded root sample for tuning */
     int32_t split_ways;    /* 0 auto, 1 none, else: each heavy root edge runs as split_ways

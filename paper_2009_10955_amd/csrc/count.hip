@@ -156,7 +156,7 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
                        hipStream_t stream, unsigned long long* result_dev,
                        unsigned long long* per_root, bool account, unsigned long long* busy) {
     if (cfg.group != 64 && cfg.group != 32 && cfg.group != 16 && cfg.group != 8) return GP_ERR_ARG;
-    if (cfg.leaf < 1 || cfg.leaf > 3) return GP_ERR_ARG;
+    if (cfg.leaf < 1 || cfg.leaf > 4) return GP_ERR_ARG;
     if (cfg.waves_per_cu < 1 || cfg.waves_per_cu > 32 || cfg.chunk < 1) return GP_ERR_ARG;
     const int mode = account ? MODE_ACCOUNT : (per_root ? MODE_PER_ROOT : MODE_PLAIN);
     const bool iep = d.iep != 0;

@@ -23,6 +23,8 @@ template <int K, int G>
 KernelFn pick_leaf(int leaf, int mode) {
     if (leaf == 2) return pick_mode<K, G, 2>(mode);
     if (leaf == 3 && K >= 5) return pick_mode<K, G, (K >= 5 ? 3 : 1)>(mode);
+    // leaf mode 4 counts the same work as leaf mode 1, so byte accounting uses 1
+    if (leaf == 4 && K >= 4 && mode != MODE_ACCOUNT) return pick_mode<K, G, (K >= 4 ? 4 : 1)>(mode);
     return pick_mode<K, G, 1>(mode);
 }
 }  // namespace

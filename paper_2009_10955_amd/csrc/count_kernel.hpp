@@ -288,6 +288,10 @@ __device__ __forceinline__ uint32_t leaf_serial(const GpPlanDesc& d, const Ctx<G
     const uint32_t inj = lv.inj;
     auto skip = [&](int32_t x) { return inj_hit<K>(inj, v, x); };
     // a hub operand is tested by bits, so only the other operand is cut
+    if constexpr (MODE != MODE_ACCOUNT) {
+        if (B.bits && A.n <= kShortList && A.n * 4 <= B.n) return count_bits_range(A, lo, hi, B.bits, skip);
+        if (A.bits && B.n <= kShortList && B.n * 4 <= A.n) return count_bits_range(B, lo, hi, A.bits, skip);
+    }
     if (B.bits) {
         const Set Ac = trim(A, lo, hi);
         if (Ac.n * 4 <= B.n) {
@@ -466,6 +470,73 @@ __device__ void flat_leaf(const GpPlanDesc& d, const Ctx<G>& c, const int32_t (&
     }
 }
 
+// Leaf mode 4: lanes take different second-to-last candidates x as in leaf
+// mode 1, except that where the last level is pre & N(x) with a group-uniform
+// pre that is a hub bitmap, a long N(x) (more than kCoopList elements after the
+// cut) is walked by the whole group: one hub candidate otherwise keeps one
+// lane busy for thousands of elements while the other lanes of its wavefront
+// idle. The group takes the long lists one after another (ballot), each lane
+// every G-th element (coalesced loads), and each element costs one bit test
+// in the shared bitmap. Returns false (nothing done) when the last level has
+// another form; the caller then counts it as in leaf mode 1.
+constexpr int32_t kCoopList = 64;
+
+template <int K, int G, int MODE>
+__device__ bool coop_bits_leaf(const GpPlanDesc& d, const Ctx<G>& c, const int32_t (&v)[K], Set S, int32_t st,
+                               uint32_t inj_l, uint64_t& acc, bool& ovf) {
+    const GpLevel& ll = d.lv[K - 1];
+    if (ll.last_list != K - 2) return false;
+    const Set A = ll.pre_buf >= 0 ? c.buf_u(ll.pre_buf) : c.nbr_u(pick<K>(v, ll.pre_list));
+    if (!A.bits) return false;
+    const uint32_t* bits = A.bits;
+    for (int32_t base = 0; base < S.n; base += G) {
+        if (c.expired()) break;
+        const int32_t i = base + c.g.gl;
+        int32_t x = -1;
+        Set B{nullptr, 0, nullptr};
+        bool longl = false;
+        if (i < S.n) {
+            x = S.p[(int64_t)i * st];
+            if (!inj_hit<K>(inj_l, v, x)) {
+                int32_t w[K];
+#pragma unroll
+                for (int j = 0; j < K; ++j) w[j] = v[j];
+                w[K - 2] = x;
+                int32_t lo, hi;
+                bounds<K>(ll.hi_src, ll.lo_src, w, lo, hi);
+                auto skip = [&](int32_t y) { return inj_hit<K>(ll.inj, w, y); };
+                B = c.nbr(x);
+                if (B.n <= kShortList) {
+                    add_count(acc, count_bits_range(B, lo, hi, bits, skip), ovf);
+                } else {
+                    B = trim(B, lo, hi);
+                    if (B.n <= kCoopList) add_count(acc, count_bits(B, bits, skip), ovf);
+                    else longl = true;
+                }
+            }
+        }
+        uint64_t m = c.g.ballot(longl);
+        while (m) {
+            const int o = __builtin_ctzll(m);
+            m &= m - 1;
+            const int32_t ox = __shfl(x, o, G);
+            const int32_t on = __shfl(B.n, o, G);
+            const int32_t* op = (const int32_t*)__shfl((long long)B.p, o, G);
+            int32_t w[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) w[j] = v[j];
+            w[K - 2] = ox;
+            uint32_t cnt = 0;
+            for (int32_t j = c.g.gl; j < on; j += G) {
+                const int32_t y = op[j];
+                if ((bits[y >> 5] >> (y & 31)) & 1u) cnt += !inj_hit<K>(ll.inj, w, y);
+            }
+            add_count(acc, cnt, ovf);
+        }
+    }
+    return true;
+}
+
 template <int K, int L, int G, int LEAF, int MODE, bool IEP>
 __device__ void search(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], uint64_t& acc,
                        bool& ovf) {
@@ -514,6 +585,8 @@ __device__ void search(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], ui
             }
         }
     } else if constexpr (L == K - 2) {
+        if constexpr (LEAF == 4 && MODE != MODE_ACCOUNT)
+            if (coop_bits_leaf<K, G, MODE>(d, c, v, S, st, lv.inj, acc, ovf)) return;
         if constexpr (LEAF != 2) {
             for (int32_t base = 0; base < S.n; base += G) {
                 if (c.expired()) break;
@@ -570,7 +643,7 @@ __device__ __forceinline__ int64_t entry_index(const int64_t* row_ptr, const int
 // separate candidates: 8, others 6). Larger patterns keep the compiler's
 // choice, where the same targets spill tens of registers.
 constexpr int occupancy_target(int K, int G, int LEAF) {
-    return K > 5 ? 1 : (G == 64 && LEAF == 1 ? 8 : 6);
+    return K > 5 ? 1 : (G == 64 && (LEAF == 1 || LEAF == 4) ? 8 : 6);
 }
 
 template <int K, int G, int LEAF, int MODE, bool IEP>

@@ -80,6 +80,33 @@ __device__ __forceinline__ uint32_t count_bits(Set a, const uint32_t* bits, Skip
     return c;
 }
 
+// The same for a short list A not yet cut to [lo, hi): every element is
+// loaded and range-tested. Independent loads instead of the two dependent
+// chains of binary searches that cutting would take.
+constexpr int32_t kShortList = 32;
+
+template <typename Skip>
+__device__ __forceinline__ uint32_t count_bits_range(Set a, int32_t lo, int32_t hi, const uint32_t* bits,
+                                                     Skip skip) {
+    uint32_t c = 0;
+    int32_t i = 0;
+    for (; i + 4 <= a.n; i += 4) {
+        const int32_t x0 = a.p[i], x1 = a.p[i + 1], x2 = a.p[i + 2], x3 = a.p[i + 3];
+        if (x0 >= hi) break;
+        const uint32_t w0 = bits[x0 >> 5], w1 = bits[x1 >> 5], w2 = bits[x2 >> 5], w3 = bits[x3 >> 5];
+        if (x0 >= lo && ((w0 >> (x0 & 31)) & 1u)) c += !skip(x0);
+        if (x1 >= lo && x1 < hi && ((w1 >> (x1 & 31)) & 1u)) c += !skip(x1);
+        if (x2 >= lo && x2 < hi && ((w2 >> (x2 & 31)) & 1u)) c += !skip(x2);
+        if (x3 >= lo && x3 < hi && ((w3 >> (x3 & 31)) & 1u)) c += !skip(x3);
+    }
+    for (; i < a.n; ++i) {
+        const int32_t x = a.p[i];
+        if (x >= hi) break;
+        if (x >= lo && ((bits[x >> 5] >> (x & 31)) & 1u)) c += !skip(x);
+    }
+    return c;
+}
+
 // |A ∩ B| by one lane, not counting elements x with skip(x).
 template <typename Skip>
 __device__ __forceinline__ uint32_t intersect_count_serial(Set a, Set b, Skip skip) {

@@ -367,6 +367,7 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
         auto leaf_ok = [&](const GpPlanDesc& bd, int lm) {
             if (lm == 2) return !bd.iep && (k <= 3 || bd.lv[k - 1].last_list >= 0);
             if (lm == 3) return k >= 5 && !bd.iep && bd.build_begin[k - 3] == bd.build_end[k - 3];
+            if (lm == 4) return k >= 4 && !bd.iep && bd.lv[k - 1].last_list == k - 2;
             return true;
         };
         // pass A: every leaf mode with 64-lane groups, for each configuration
@@ -379,7 +380,7 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
                 pk.est = measure(bd, base, stride, "shape", c, true);
                 if (pk.est < 0) break;
                 tried.push_back(pk);
-                for (int lm : {2, 3}) {
+                for (int lm : {2, 3, 4}) {
                     if (!leaf_ok(bd, lm) || spent > 2.5 * budget_ms) continue;
                     gpint::LaunchCfg cfg = base;
                     cfg.leaf = lm;
@@ -403,7 +404,7 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
             for (int grp : {32, 16, 8}) {
                 if (bd.iep && grp < 32) continue;
                 double best_g = inf;
-                for (int lm : {1, 2, 3}) {
+                for (int lm : {1, 2, 3, 4}) {
                     if (!leaf_ok(bd, lm) || spent > 2.5 * budget_ms) continue;
                     gpint::LaunchCfg cfg = base;
                     cfg.group = grp;

@@ -13,7 +13,7 @@ from paper_2009_10955_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 P = I.PATTERNS
-VARIANTS = [dict(group=g, leaf_mode=l) for g in (64, 32, 16, 8) for l in (1, 2, 3)]
+VARIANTS = [dict(group=g, leaf_mode=l) for g in (64, 32, 16, 8) for l in (1, 2, 3, 4)]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -80,6 +80,61 @@ def test_config0_counts(pname):
     want = O.count(g, k, e)
     for v in VARIANTS:
         assert _count(graph, k, e, **v) == want, v
+
+
+# ------------------------------------------------------- leaf mode 4
+
+@pytest.mark.parametrize("pname", ["4-cycle", "diamond", "house", "5-cycle", "6-cycle-chord", "prism",
+                                   "k4-path", "5-wheel", "6-cycle"])
+def test_flat_bitmap_leaf_every_set(pname):
+    """Leaf mode 4 (long last-level lists walked by the whole group against a
+    shared hub bitmap) on a graph where every vertex has a bitmap: every
+    emitted restriction set with two schedules, each group width, plain, split
+    and sampled, equals the oracle."""
+    g = I.er(48, 0.3, seed=21)
+    graph = gp.Graph.from_csr(g, hub_bitmaps="dense")
+    k, e = P[pname]
+    want = O.count(g, k, e)
+    base = gp.Plan(k, e)
+    scheds = base.schedules()
+    rng = np.random.default_rng(1)
+    for si in range(min(base.info().n_sets, 8)):
+        for o in [scheds[int(x)] for x in rng.choice(len(scheds), min(2, len(scheds)), replace=False)]:
+            plan = gp.Plan(k, e, force_order=o, force_set=si)
+            for grp in (64, 32, 16, 8):
+                assert gp.count(graph, plan, group=grp, leaf_mode=4) == want, (o, si, grp)
+            assert gp.count(graph, plan, group=32, leaf_mode=4, split_ways=5,
+                            split_vertices=1 << 20) == want
+            parts = [gp.count(graph, plan, group=16, leaf_mode=4, root_stride=3, root_offset=r)
+                     for r in range(3)]
+            assert sum(parts) == want
+
+
+@pytest.mark.parametrize("pname", ["4-cycle", "diamond", "tailed-triangle", "4-clique"])
+def test_coop_leaf_long_lists(pname):
+    """Leaf mode 4 where last-level lists are longer than a group walks
+    alone (degree ~72, every vertex a hub), against the oracle."""
+    g = I.er(120, 0.6, seed=5)
+    graph = gp.Graph.from_csr(g, hub_bitmaps="dense")
+    k, e = P[pname]
+    want = O.count(g, k, e)
+    base = gp.Plan(k, e)
+    for si in range(min(base.info().n_sets, 4)):
+        plan = gp.Plan(k, e, force_set=si)
+        for grp in (64, 32, 16, 8):
+            assert gp.count(graph, plan, group=grp, leaf_mode=4) == want, (si, grp)
+
+
+def test_flat_bitmap_leaf_per_root_on_hub_graph():
+    g = I.config_graph(2)
+    graph = gp.Graph.from_csr(g, device=True)
+    for pname in ["house", "5-cycle", "4-cycle"]:
+        plan = gp.Plan(*P[pname], stats=graph.stats())
+        want = gp.count(graph, plan, leaf_mode=1)
+        assert gp.count(graph, plan, leaf_mode=4, group=32) == want, pname
+        assert gp.count(graph, plan, leaf_mode=4, group=64) == want, pname
+        total, per = gp.count_per_root(graph, plan, leaf_mode=4, group=16)
+        assert total == want and int(per.sum().item()) == want
 
 
 # ------------------------------------------------------- split root tasks
@@ -178,7 +233,7 @@ def test_hub_star_ragged(hubs):
     for pname in ["triangle", "4-cycle", "tailed-triangle", "diamond", "4-clique"]:
         k, e = P[pname]
         want = O.count(g, k, e)
-        for v in VARIANTS[::3]:
+        for v in VARIANTS[::3] + [dict(group=64, leaf_mode=4), dict(group=8, leaf_mode=4)]:
             assert _count(graph, k, e, **v) == want, (pname, v)
     # stars: closed form sum over vertices of C(deg, 3)
     star = sum(math.comb(int(d), 3) for d in g.degrees())

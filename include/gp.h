@@ -306,7 +306,7 @@ gp_status gp_estimate(const gp_graph* g, const gp_plan* p, const gp_launch* laun
  * persistent launch: the task space is the concatenation of the plans' root
  * edges, handed out in chunks from one atomic queue, so plans of uneven cost
  * fill each other's tails (Section IV-E's task partitioning across patterns).
- * The lanes per group (64, 32 or 16) and leaf mode (1, or 3 where the plan allows
+ * The lanes per group (64, 32 or 16) and leaf mode (1, 3 or 4 where the plan allows
  * it) come from `launch`, else from the first plan's launch. Plans counted
  * with IEP are not supported here (GP_ERR_UNSUPPORTED). out[i] = count of plans[i]
  * (host memory). Blocking. Counts equal gp_count's bit for bit.
@@ -331,10 +331,10 @@ gp_status gp_batch_run(gp_batch* b, void* stream, uint64_t* out);
 
 /*
  * Pick the launch shape of a batch of these plans on g by measurement: one full
- * batched run per shape (64, 32 or 16 lanes per group x leaf mode 1 or 3),
+ * batched run per shape (64, 32 or 16 lanes per group x leaf mode 1, 3 or 4),
  * timed with HIP events on stream. *out receives the fastest shape (group and
  * leaf_mode set, other fields zero) for gp_count_batch / gp_batch_create;
- * *best_ms (may be null) its time. Blocking; costs six full runs. Errors as
+ * *best_ms (may be null) its time. Blocking; costs nine full runs. Errors as
  * gp_count_batch.
  */
 gp_status gp_batch_tune(const gp_graph* g, const gp_plan* const* plans, int32_t np, void* stream,
@@ -353,7 +353,7 @@ typedef struct {
                                this with GP_ERR_BUDGET (0 = no cap) */
     int64_t initial_slice;  /* root tasks a query gets in its first iteration (0 = 8192) */
     int32_t group;          /* lanes per group of the batched kernel: 64, 32 or 16 (0 = 64) */
-    int32_t leaf_mode;      /* 1 or 3 (0 = 1) */
+    int32_t leaf_mode;      /* 1, 3 or 4 (0 = 1) */
     int32_t waves_per_cu;   /* 0 = 32 */
     double max_query_ms;    /* > 0: the first query of each (graph, pattern) counts a strided
                                sample of its root tasks first; a query whose full run is then

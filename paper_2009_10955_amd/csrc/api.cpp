@@ -638,7 +638,7 @@ gp_status gp_batch_tune(const gp_graph* g, const gp_plan* const* plans, int32_t 
     double best = -1;
     gp_launch pick{};
     for (int grp : {64, 32, 16}) {
-        for (int lm : {1, 3}) {
+        for (int lm : {1, 3, 4}) {
             gp_launch l{};
             l.group = grp;
             l.leaf_mode = lm;

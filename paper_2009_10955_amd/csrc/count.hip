@@ -22,10 +22,18 @@ GP_DECL_BATCH(64, 5, 3) GP_DECL_BATCH(64, 6, 3) GP_DECL_BATCH(64, 8, 3)
 GP_DECL_BATCH(32, 5, 3) GP_DECL_BATCH(32, 6, 3) GP_DECL_BATCH(32, 8, 3)
 GP_DECL_BATCH(16, 5, 1) GP_DECL_BATCH(16, 6, 1) GP_DECL_BATCH(16, 8, 1)
 GP_DECL_BATCH(16, 5, 3) GP_DECL_BATCH(16, 6, 3) GP_DECL_BATCH(16, 8, 3)
+GP_DECL_BATCH(64, 5, 4) GP_DECL_BATCH(64, 6, 4) GP_DECL_BATCH(64, 8, 4)
+GP_DECL_BATCH(32, 5, 4) GP_DECL_BATCH(32, 6, 4) GP_DECL_BATCH(32, 8, 4)
+GP_DECL_BATCH(16, 5, 4) GP_DECL_BATCH(16, 6, 4) GP_DECL_BATCH(16, 8, 4)
 #undef GP_DECL_BATCH
 
 BatchFn pick_batch_kernel(int group, int kmax, int leaf) {
     const int km = kmax <= 5 ? 5 : (kmax <= 6 ? 6 : 8);
+    if (leaf == 4) {
+        if (group == 64) return km == 5 ? batch_kernel_g64_k5_l4() : (km == 6 ? batch_kernel_g64_k6_l4() : batch_kernel_g64_k8_l4());
+        if (group == 16) return km == 5 ? batch_kernel_g16_k5_l4() : (km == 6 ? batch_kernel_g16_k6_l4() : batch_kernel_g16_k8_l4());
+        return km == 5 ? batch_kernel_g32_k5_l4() : (km == 6 ? batch_kernel_g32_k6_l4() : batch_kernel_g32_k8_l4());
+    }
     if (leaf == 3) {
         if (group == 64) return km == 5 ? batch_kernel_g64_k5_l3() : (km == 6 ? batch_kernel_g64_k6_l3() : batch_kernel_g64_k8_l3());
         if (group == 16) return km == 5 ? batch_kernel_g16_k5_l3() : (km == 6 ? batch_kernel_g16_k6_l3() : batch_kernel_g16_k8_l3());
@@ -310,7 +318,7 @@ gp_status batch_prepare(const DeviceGraph& g, const GpPlanDesc* descs, const int
     if (np < 1 || np > kBatchMaxPlans) return GP_ERR_ARG;
     BatchState b;
     b.group = cfg.group >= 64 ? 64 : (cfg.group >= 32 || cfg.group <= 0 ? 32 : 16);
-    b.leaf = cfg.leaf == 3 ? 3 : 1;
+    b.leaf = cfg.leaf == 3 || cfg.leaf == 4 ? cfg.leaf : 1;
     b.chunk = std::max(1, cfg.chunk);
     b.cap = std::max<int64_t>(1, g.deg2);
     std::vector<BatchPlan> plans;
@@ -371,7 +379,7 @@ gp_status arena_create(const DeviceGraph& g, int nbuf_cap, const LaunchCfg& cfg,
     a.cfg = cfg;
     BatchState& b = a.st;
     b.group = cfg.group >= 64 ? 64 : (cfg.group >= 32 || cfg.group <= 0 ? 32 : 16);
-    b.leaf = cfg.leaf == 3 ? 3 : 1;
+    b.leaf = cfg.leaf == 3 || cfg.leaf == 4 ? cfg.leaf : 1;
     b.chunk = std::max(1, cfg.chunk);
     b.cap = std::max<int64_t>(1, g.deg2);
     a.nbuf_cap = std::max(0, std::min(nbuf_cap, GP_DESC_MAX_BUILDS));

@@ -9,7 +9,7 @@
 // groups spent on each plan, for the serving scheduler) are reduced per group
 // into LDS and flushed once per wavefront at the end. Built once per group size,
 // largest pattern size and leaf mode (-DGP_BATCH_G=64/32/16, -DGP_BATCH_KMAX=
-// 5/6/8, -DGP_BATCH_LEAF=1/3), so a batch carries only the register
+// 5/6/8, -DGP_BATCH_LEAF=1/3/4), so a batch carries only the register
 // footprint of its own shapes.
 #include "count_kernel.hpp"
 
@@ -23,7 +23,7 @@ namespace {
 
 constexpr int G = GP_BATCH_G;
 constexpr int KMAX = GP_BATCH_KMAX;
-constexpr int LEAF = GP_BATCH_LEAF;  // 1, or 3 (flattened where possible, else as 1)
+constexpr int LEAF = GP_BATCH_LEAF;  // 1, 3 (flattened where possible) or 4 (long lists by the group)
 
 template <int K>
 __device__ __forceinline__ void batch_roots(const GpPlanDesc& d, Ctx<G>& c, const BatchPlan& bp, int64_t t0,

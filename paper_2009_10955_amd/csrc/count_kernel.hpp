@@ -10,8 +10,10 @@
 // How it maps to the machine:
 //   * Tasks are root edges (v0, v1) = the first two loops fused, taken from a
 //     device-wide atomic queue in chunks (the fine-grained task partitioning
-//     of Section IV-E, as a lock-free queue instead of a master thread). Roots
-//     are in CSR order of the degree-sorted layout, so hubs go first.
+//     of Section IV-E, as a lock-free queue instead of a master thread). Root
+//     arrays are ordered by their smaller (higher-degree) endpoint, so hubs
+//     go first, and the heaviest roots can be split over their level-2
+//     candidates into several tasks.
 //   * A group of G lanes (G in {64, 32, 16, 8}) of one wavefront shares one
 //     search path. Intersections are group-cooperative (each lane
 //     binary-searches one element of the smaller list in the larger one;
@@ -20,8 +22,13 @@
 //   * Intersection results ("tmp" sets) live in a per-group scratch region in
 //     HBM; they are written and re-read while hot in L2.
 //   * The second-to-last level is spread over the lanes (leaf mode 1: each
-//     lane counts the last level for its own candidate) or walked with the
-//     group counting each last level together (leaf mode 2).
+//     lane counts the last level for its own candidate), walked with the
+//     group counting each last level together (leaf mode 2), flattened with
+//     the level above it into one balanced batch (leaf mode 3), or spread over
+//     the lanes with long hub-tested lists walked by the whole group (leaf
+//     mode 4).
+//   * Hub vertices carry dense neighbor bitmaps: a membership test against a
+//     hub's list is one word load.
 //   * The last level is never enumerated: its count is
 //     |C ∩ [lo, hi)| minus the earlier bound vertices that fall in it.
 //   * Counts: uint64 per lane, wavefront tree reduction with carry detection,

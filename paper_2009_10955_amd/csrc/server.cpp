@@ -530,7 +530,7 @@ gp_status gp_server_create(const gp_graph* const* graphs, int32_t ng, const gp_s
     if (o.target_ms <= 0) o.target_ms = 25.0;
     if (o.initial_slice <= 0) o.initial_slice = 8192;
     if (o.group != 64 && o.group != 32 && o.group != 16) o.group = 64;
-    if (o.leaf_mode != 1 && o.leaf_mode != 3) o.leaf_mode = 1;
+    if (o.leaf_mode != 1 && o.leaf_mode != 3 && o.leaf_mode != 4) o.leaf_mode = 1;
     if (o.waves_per_cu <= 0 || o.waves_per_cu > 32) o.waves_per_cu = 32;
     if (o.max_query_ms < 0 || o.cost_cap < 0) return GP_ERR_ARG;
     gp_server* S = new (std::nothrow) gp_server;

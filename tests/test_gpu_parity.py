@@ -333,11 +333,13 @@ def test_per_root_counts_config2(pname):
 
 @pytest.mark.parametrize("pname", I.CONFIG_PATTERNS[1])
 def test_per_root_counts_config1_full_size(pname):
-    """R-MAT scale 17 at full size, default launch: per-root counts on sampled
-    roots (random, nonzero, and the heaviest) equal the oracle's pinned counts."""
+    """R-MAT scale 17 at full size, default launch and leaf mode 4: per-root
+    counts on sampled roots (random, nonzero, and the heaviest) equal the
+    oracle's pinned counts."""
     g = I.config_graph(1)
     graph = gp.Graph.from_csr(g, device=True)
     _per_root_check(g, graph, pname, 6, 2)
+    _per_root_check(g, graph, pname, 3, 3, group=64, leaf_mode=4)
 
 
 def test_config2_small_patterns_full_count():
@@ -443,7 +445,8 @@ def test_tuned_plans_count_the_same():
 
 # ------------------------------------------------------------------ serving
 
-def test_serving_counts_equal_solo_counts():
+@pytest.mark.parametrize("leaf", [1, 4])
+def test_serving_counts_equal_solo_counts(leaf):
     """A Poisson stream of random connected 3-5-vertex patterns over two
     resident graphs, with tiny slices so queries span several iterations and
     newcomers join launches already under way: every count equals the solo
@@ -451,10 +454,10 @@ def test_serving_counts_equal_solo_counts():
     from paper_2009_10955_amd import serve
     g0 = I.config_graph(0)
     g1 = I.er(300, 0.06, seed=13)
-    graphs = [gp.Graph.from_csr(g0), gp.Graph.from_csr(g1)]
+    graphs = [gp.Graph.from_csr(g0), gp.Graph.from_csr(g1, hub_bitmaps="dense")]
     pats = I.connected_patterns(3, 5)
     stream = I.poisson_stream(150, 2000.0, 2, len(pats), seed=7)
-    srv = gp.Server(graphs, target_ms=2.0, initial_slice=32)
+    srv = gp.Server(graphs, target_ms=2.0, initial_slice=32, leaf_mode=leaf)
     res = serve.run_stream(srv, stream, pats)
     stats = srv.stats()
     srv.close()
@@ -539,10 +542,10 @@ def test_batch_tune_picks_a_shape_with_the_same_counts():
     plans = [gp.Plan(*P[n], stats=graph.stats()) for n in ["house", "4-clique", "prism"]]
     want = [gp.count(graph, p) for p in plans]
     shape, ms = gp.batch_tune(graph, plans)
-    assert shape["group"] in (64, 32, 16) and shape["leaf_mode"] in (1, 3) and ms > 0
+    assert shape["group"] in (64, 32, 16) and shape["leaf_mode"] in (1, 3, 4) and ms > 0
     assert gp.count_batch(graph, plans, **shape) == want
     for grp in (16, 32, 64):
-        for leaf in (1, 3):
+        for leaf in (1, 3, 4):
             assert gp.count_batch(graph, plans, group=grp, leaf_mode=leaf) == want, (grp, leaf)
 
 

@@ -646,11 +646,11 @@ __device__ __forceinline__ int64_t entry_index(const int64_t* row_ptr, const int
 // Wavefronts per SIMD the compiler is asked to keep resident (it trims
 // registers, spilling a few if it must). The searches are bound by the
 // latency of scattered loads, so more resident wavefronts pay even against
-// some spills; measured on R-MAT 17 for k = 5 (64-lane groups with lanes on
-// separate candidates: 8, others 6). Larger patterns keep the compiler's
-// choice, where the same targets spill tens of registers.
+// some spills. Measured on R-MAT 17 for k = 5 (64-lane groups with lanes on
+// separate candidates: 8, others 6) and on Chung-Lu 7000 for k = 6 (64-lane
+// groups 6, others 5); k >= 7 keeps the compiler's choice.
 constexpr int occupancy_target(int K, int G, int LEAF) {
-    return K > 5 ? 1 : (G == 64 && (LEAF == 1 || LEAF == 4) ? 8 : 6);
+    return K > 6 ? 1 : K == 6 ? (G == 64 ? 6 : 5) : (G == 64 && (LEAF == 1 || LEAF == 4) ? 8 : 6);
 }
 
 template <int K, int G, int LEAF, int MODE, bool IEP>

@@ -218,11 +218,14 @@ gp_status gp_plan_model_cost(const gp_plan* p, int32_t idx_s, int32_t idx_r,
 
 typedef struct {
     int32_t max_configs;    /* distinct configurations to time (0 = 24) */
-    int32_t sample_stride;  /* time roots[offset + t * stride] only (0 = auto, aiming at
-                               ~40 ms per run) */
-    int32_t tune_launch;    /* 1 (default): also pick lanes per group, leaf mode and waves per
-                               CU for the chosen configuration; -1: keep the defaults */
-    double budget_seconds;  /* stop timing once this much GPU time is spent (0 = 20 s) */
+    int32_t sample_stride;  /* time every stride-th root task only (0 = auto, aiming at
+                               about 8 ms of balanced work per sample) */
+    int32_t tune_launch;    /* 1 (default): also pick lanes per group, leaf mode and, for
+                               k >= 4 when the winner was timed in full, the tasks taken per
+                               queue grab (4, 2 or 1); -1: keep the defaults */
+    double budget_seconds;  /* GPU time for timing sampled configurations (0 = 20 s); the
+                               launch-shape, full-run and queue-grab stages that follow may
+                               bring the total to at most about 4 times this */
 } gp_tune_opts;
 
 void gp_tune_opts_default(gp_tune_opts* o);

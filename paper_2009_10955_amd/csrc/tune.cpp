@@ -460,6 +460,7 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
                     break;
                 }
         }
+        bool timed_full = stride == 1;  // picks hold full-run times
         if (st == GP_OK && stride > 1 && full.size() > 1) {
             std::stable_sort(full.begin(), full.end(), [](const Pick& a, const Pick& b) { return a.est < b.est; });
             double planned = 0;
@@ -474,16 +475,38 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
                 }
                 full.resize(n_full);
                 picks = full;
+                timed_full = true;
             }
         }
         size_t best = fine.empty() ? 0 : fine[0].second;
         gpint::LaunchCfg best_launch = base;
+        double best_ms = inf;
         if (!picks.empty()) {
             const Pick* bp = &picks[0];
             for (auto& pk : picks)
                 if (pk.est < bp->est) bp = &pk;
             best = bp->c;
             best_launch = bp->launch;
+            best_ms = bp->est;
+        }
+        // 6. tasks per grab of the queue counter, in full runs of the winner:
+        //    single roots per grab shorten the tail of long patterns, while
+        //    short ones can lose to the extra grabs; a smaller grab must win
+        //    by 2% to count as more than noise
+        if (st == GP_OK && timed_full && k >= 4 && best_ms < inf && o.tune_launch >= 0) {
+            const gpint::LaunchCfg won = best_launch;
+            for (int ch : {2, 1}) {
+                if (ch >= won.chunk || spent + best_ms > 4.0 * budget_ms) continue;
+                gpint::LaunchCfg cfg = won;
+                cfg.chunk = ch;
+                best_est = best_ms;  // a run past three times the winner stops
+                double t = measure(cands[best].desc, cfg, 1, "chunk", best);
+                if (t < 0) break;
+                if (t < 0.98 * best_ms) {
+                    best_ms = t;
+                    best_launch = cfg;
+                }
+            }
         }
         best_launch.root_stride = 1;
         best_launch.root_offset = 0;

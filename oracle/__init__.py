@@ -26,6 +26,10 @@ Contents and what each follows:
 * ``alg2_components``, ``alg2_cardinality``, ``iep_injective_tuples``,
   ``iep_count`` -- counting with the Inclusion-Exclusion Principle
   (Section IV-D, Algorithm 2).
+* ``list_subgraphs`` -- the embeddings themselves (Section II-A: the problem
+  is to find every subgraph that is an image of the pattern): each distinct
+  subgraph once, as the set of its edges. Pure-Python backtracking, small
+  graphs only.
 * ``relabel_by_degree`` -- vertex relabelling by descending degree (ties by
   ascending id), the layout the GPU library uses; counts are invariant under it.
 
@@ -173,6 +177,43 @@ def brute_force_maps(g, k: int, edges, restr=()) -> int:
         if all((t[a], t[b]) in adj for a, b in edges) and all(t[a] > t[b] for a, b in restr):
             total += 1
     return total
+
+
+def list_subgraphs(g, k: int, edges) -> set:
+    """Every distinct subgraph of g that is the image of an injective map
+    sending each pattern edge onto a data edge (Section II-A), as a frozenset
+    of its edges, each edge a (smaller id, larger id) pair. Two maps give the
+    same subgraph exactly when they differ by an automorphism, so the result
+    has maps / |Aut(P)| elements. Plain backtracking over pattern vertices
+    0..k-1: a vertex with an earlier pattern neighbor ranges over the data
+    neighbors of that neighbor's image, any other over all of V, and a
+    partial map is dropped as soon as it repeats a vertex or misses a pattern
+    edge to a bound vertex. Small graphs only."""
+    row_ptr = np.asarray(g.row_ptr, dtype=np.int64)
+    col = np.asarray(g.col, dtype=np.int64)
+    n = row_ptr.shape[0] - 1
+    nbr = [set(col[row_ptr[v]:row_ptr[v + 1]].tolist()) for v in range(n)]
+    earlier = [[b for a, b in edges if a == u and b < u] + [a for a, b in edges if b == u and a < u]
+               for u in range(k)]
+    found = set()
+    img = [0] * k
+
+    def rec(u: int) -> None:
+        if u == k:
+            found.add(frozenset((min(img[a], img[b]), max(img[a], img[b])) for a, b in edges))
+            return
+        # a later vertex with an earlier pattern neighbor can only be one of
+        # that neighbor's data neighbors; the rest range over all of V
+        cands = sorted(nbr[img[earlier[u][0]]]) if earlier[u] else range(n)
+        for x in cands:
+            if x in img[:u]:
+                continue
+            if all(img[w] in nbr[x] for w in earlier[u]):
+                img[u] = x
+                rec(u + 1)
+
+    rec(0)
+    return found
 
 
 def relabel_by_degree(g):

@@ -375,3 +375,70 @@ def test_iep_paper_divisor_differs_from_the_multiplicity():
     assert O.iep_divisor(k, e, order, r, 2) == 3
     g = I.er(12, 0.5, seed=4)
     assert O.iep_count(g, k, e, order, r, 2) == O.count(g, k, e)
+
+
+# ------------------------------------------------------------ listing (II-A)
+
+def _edge_sets_by_permutations(g, k, edges):
+    """Image edge sets of every injective k-tuple that maps each pattern edge
+    onto a data edge, by exhaustive enumeration of tuples (tiny graphs)."""
+    n = g.row_ptr.shape[0] - 1
+    adj = {(v, int(w)) for v in range(n) for w in g.col[g.row_ptr[v]:g.row_ptr[v + 1]]}
+    out = set()
+    for t in itertools.permutations(range(n), k):
+        if all((t[a], t[b]) in adj for a, b in edges):
+            out.add(frozenset((min(t[a], t[b]), max(t[a], t[b])) for a, b in edges))
+    return out
+
+
+@pytest.mark.parametrize("k", [2, 3, 4, 5])
+def test_listing_cliques_of_complete_graph(k):
+    """K_6: the k-cliques are the C(6, k) vertex subsets, each with all its pairs."""
+    edges = list(itertools.combinations(range(k), 2))
+    got = O.list_subgraphs(I.complete(6), k, edges)
+    want = {frozenset(itertools.combinations(s, 2)) for s in itertools.combinations(range(6), k)}
+    assert got == want and len(got) == math.comb(6, k)
+
+
+def test_listing_four_cycles_of_k4_and_wedges_of_a_star():
+    """K_4 holds exactly its 3 Hamiltonian cycles; a star with s leaves holds
+    C(s, 2) wedges, each two spokes."""
+    c4 = O.list_subgraphs(I.complete(4), 4, P["4-cycle"][1])
+    assert c4 == {frozenset({(0, 1), (1, 2), (2, 3), (0, 3)}), frozenset({(0, 1), (1, 3), (2, 3), (0, 2)}),
+                  frozenset({(0, 2), (1, 2), (1, 3), (0, 3)})}
+    s = 7
+    wedges = O.list_subgraphs(I.star(s), 3, [(0, 1), (1, 2)])
+    assert wedges == {frozenset({(0, i), (0, j)}) for i, j in itertools.combinations(range(1, s + 1), 2)}
+
+
+@pytest.mark.parametrize("m", [4, 5, 6])
+def test_listing_cycle_graph_is_itself(m):
+    g = I.cycle_graph(m)
+    edges = [(i, (i + 1) % m) for i in range(m)]
+    got = O.list_subgraphs(g, m, edges)
+    assert got == {frozenset((min(i, (i + 1) % m), max(i, (i + 1) % m)) for i in range(m))}
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+@pytest.mark.parametrize("pname", ["triangle", "4-cycle", "diamond", "house", "5-cycle", "tailed-triangle"])
+def test_listing_matches_exhaustive_tuples_and_count(seed, pname):
+    """On random 8-vertex graphs the listing equals the image sets of every
+    injective tuple, and its size equals the (separately pinned) count."""
+    if pname not in P:
+        pytest.skip(f"no pattern {pname}")
+    k, e = P[pname]
+    g = I.gnm_small(8, 0.6, seed)
+    got = O.list_subgraphs(g, k, e)
+    assert got == _edge_sets_by_permutations(g, k, e)
+    assert len(got) == O.count(g, k, e)
+    for s in got:
+        assert len(s) == len(e)
+
+
+def test_listing_size_equals_count_on_sparse_graph():
+    g = I.er(200, 0.05, seed=3)
+    for pname in ["house", "4-clique", "6-cycle"]:
+        if pname not in P:
+            continue
+        k, e = P[pname]
+        assert len(O.list_subgraphs(g, k, e)) == O.count(g, k, e), pname

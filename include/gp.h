@@ -289,6 +289,30 @@ gp_status gp_count_per_root(const gp_graph* g, const gp_plan* p, const gp_launch
 gp_status gp_count_traffic(const gp_graph* g, const gp_plan* p, const gp_launch* launch,
                            void* stream, uint64_t* out, uint64_t* alg_bytes);
 
+/*
+ * List the embeddings of plan p in graph g: every distinct subgraph that is
+ * an image of the pattern (the problem as Section II-A states it; gp_count
+ * returns how many there are). The search is gp_count's with its last level
+ * enumerated; the restriction closure lets exactly one map reach each
+ * subgraph (Section IV-A), and that map is written out.
+ *   out       device memory, caller-owned: capacity rows of k int32. Row r
+ *             is one embedding: out[r*k + u] = original id of the data vertex
+ *             that pattern vertex u maps to. Rows come in no fixed order.
+ *   capacity  rows that out can hold (0: count only, out may be null).
+ *   n_found   host: the number of embeddings (gp_count's value). When it
+ *             exceeds capacity, capacity of them are written (which ones is
+ *             unspecified) and the call still returns GP_OK: compare the two
+ *             and call again with a larger buffer, or page.
+ *   launch    waves_per_cu, chunk, root_stride and root_offset as in
+ *             gp_count; the searches run in 64-lane groups whatever `group`
+ *             says. Paging: calls with root_stride s and root_offset
+ *             0 .. s-1 list disjoint sets of embeddings whose union is all of them.
+ * Blocking (synchronises `stream`). GP_ERR_UNSUPPORTED for a plan counted
+ * with inclusion-exclusion (its last two levels are never enumerated).
+ */
+gp_status gp_list(const gp_graph* g, const gp_plan* p, const gp_launch* launch, void* stream, int32_t* out,
+                  uint64_t capacity, uint64_t* n_found);
+
 /* Estimate the run time of a full gp_count before running it, from a strided
  * sample of about 4096 root tasks (every root_tasks/4096-th, starting with the
  * first, which is the heaviest): the summed active time of the wavefronts, scaled by the

@@ -522,6 +522,29 @@ gp_status gp_count_traffic(const gp_graph* g, const gp_plan* p, const gp_launch*
     return count_to_host(g, p->desc, cfg, (hipStream_t)stream, nullptr, out, alg_bytes);
 }
 
+gp_status gp_list(const gp_graph* g, const gp_plan* p, const gp_launch* launch, void* stream, int32_t* out,
+                  uint64_t capacity, uint64_t* n_found) {
+    if (!g || !p || !n_found || (capacity > 0 && !out)) return GP_ERR_ARG;
+    const int k = p->desc.k;
+    if (k < 2 || k > GP_MAX_K || capacity > (uint64_t)INT64_MAX / (uint64_t)k) return GP_ERR_ARG;
+    if (p->desc.iep) return GP_ERR_UNSUPPORTED;
+    DeviceGuard dgd(g->dg.device);
+    hipStream_t s = (hipStream_t)stream;
+    gpint::LaunchCfg cfg = gpint::launch_for_plan(p, launch, g->dg);
+    int32_t order[GP_MAX_K] = {};
+    for (int i = 0; i < k; ++i) order[i] = p->order[i];
+    unsigned long long* res = nullptr;
+    GP_HIP_TRY(hipMallocAsync((void**)&res, 2 * sizeof(unsigned long long), s));
+    gp_status st = gpint::launch_list(g->dg, p->desc, order, cfg, s, res, out, (int64_t)capacity);
+    unsigned long long h[2] = {0, 0};
+    if (st == GP_OK && hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, s) != hipSuccess) st = GP_ERR_HIP;
+    (void)hipFreeAsync(res, s);
+    if (hipStreamSynchronize(s) != hipSuccess && st == GP_OK) st = GP_ERR_HIP;
+    if (st != GP_OK) return st;
+    *n_found = h[0];
+    return GP_OK;
+}
+
 namespace {
 // Device descriptors and per-plan leaf modes of a batch.
 gp_status batch_inputs(const gp_plan* const* plans, int32_t np, std::vector<GpPlanDesc>* descs,

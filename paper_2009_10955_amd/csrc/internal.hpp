@@ -58,6 +58,13 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
                        unsigned long long* per_root, bool account = false,
                        unsigned long long* busy = nullptr);
 
+// Enqueue a listing of plan d over g on `stream`: found_dev (2 device words)
+// receives {embeddings found, 0}; the first out_cap of them are written to out
+// as rows of k int32 original vertex ids, column order[i] holding schedule
+// level i. Scratch is allocated stream-ordered and released after the kernel.
+gp_status launch_list(const DeviceGraph& g, const GpPlanDesc& d, const int32_t* order, const LaunchCfg& cfg,
+                      hipStream_t stream, unsigned long long* found_dev, int32_t* out, int64_t out_cap);
+
 // Device state of one batched launch: descriptors, per-plan task ranges,
 // scratch, queue and results, all allocated up front so that the launch
 // itself allocates nothing (it can be captured in a hipGraph and replayed).

@@ -123,6 +123,8 @@ SIGNATURES = {
     "gp_estimate": (_I32, [_P, _P, ctypes.POINTER(Launch), ctypes.c_double, _P,
                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64),
                            ctypes.POINTER(_I64)]),
+    "gp_list": (_I32, [_P, _P, ctypes.POINTER(Launch), _P, _P, ctypes.c_uint64,
+                       ctypes.POINTER(ctypes.c_uint64)]),
     "gp_count_traffic": (_I32, [_P, _P, ctypes.POINTER(Launch), _P,
                                 ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]),
     "gp_batch_create": (_I32, [_P, _P, _I32, ctypes.POINTER(Launch), _P, ctypes.POINTER(_P)]),
@@ -393,6 +395,32 @@ def count_per_root(graph: Graph, plan: Plan, stream=None, **launch):
                                     _stream_handle(stream), per.data_ptr(), ctypes.byref(out)),
            "gp_count_per_root")
     return out.value, per[:2 * s.m]
+
+
+def list_embeddings(graph: Graph, plan: Plan, capacity: int | None = None, out=None, stream=None,
+                    **launch):
+    """(rows, total): the embeddings as a CUDA int32 tensor of shape
+    (min(total, capacity), k), row r holding the original vertex id that each
+    pattern vertex maps to, and the number of embeddings. capacity None: the
+    count is taken first and every embedding is returned. out: an optional
+    CUDA int32 tensor of at least capacity * k elements to write into."""
+    import torch
+    k = plan.k
+    if capacity is None:
+        capacity = count(graph, plan, stream=stream)
+    capacity = int(capacity)
+    if capacity < 0:
+        raise ValueError("capacity must be >= 0")
+    if out is None:
+        out = torch.empty((max(1, capacity), k), dtype=torch.int32, device="cuda")
+    elif out.dtype != torch.int32 or not out.is_cuda or out.numel() < capacity * k or not out.is_contiguous():
+        raise ValueError("out must be a contiguous CUDA int32 tensor of at least capacity * k elements")
+    total = ctypes.c_uint64()
+    lp = _launch(**launch)
+    _check(_lib().gp_list(graph.handle, plan.handle, ctypes.byref(lp), _stream_handle(stream),
+                          out.data_ptr() if capacity > 0 else None, capacity, ctypes.byref(total)), "gp_list")
+    n = min(total.value, capacity)
+    return out.reshape(-1)[:n * k].view(n, k), total.value
 
 
 def count_traffic(graph: Graph, plan: Plan, stream=None, **launch) -> tuple[int, int]:

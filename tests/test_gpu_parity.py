@@ -155,7 +155,8 @@ def test_split_roots_equal_oracle(pname):
     want = O.count(g, k, e)
     for sp in SPLITS:
         for v in (dict(group=64, leaf_mode=1), dict(group=16, leaf_mode=2),
-                  dict(group=32, leaf_mode=3, chunk=1), dict(group=8, leaf_mode=1, chunk=3)):
+                  dict(group=32, leaf_mode=3, chunk=1), dict(group=8, leaf_mode=1, chunk=3),
+                  dict(group=64, leaf_mode=4, chunk=1)):
             assert _count(graph, k, e, **sp, **v) == want, (sp, v)
 
 
@@ -169,6 +170,9 @@ def test_split_roots_with_hubs_and_sampling():
         want = gp.count(graph, plan, split_ways=1)
         for ways, verts in [(16, 256), (5, 1 << 20), (128, 4)]:
             assert gp.count(graph, plan, split_ways=ways, split_vertices=verts) == want, (pname, ways)
+            for ch in (1, 2):
+                assert gp.count(graph, plan, group=64, leaf_mode=4, chunk=ch, split_ways=ways,
+                                split_vertices=verts) == want, (pname, ways, ch)
         parts = [gp.count(graph, plan, root_stride=5, root_offset=o, split_ways=9,
                           split_vertices=1 << 20) for o in range(5)]
         assert sum(parts) == want, pname

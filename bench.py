@@ -43,6 +43,10 @@ WORKLOADS = {
                "R-MAT scale 22, edge factor 8, (0.57,0.19,0.19,0.05), seed 4; 4-clique, house, "
                "5-cycle, 6-cycle+chord in one persistent launch against one launch per pattern "
                "(patterns estimated above --max-pattern-s are reported, not run)", "batched"),
+    "list-rmat17": (1, ["5-clique"],
+                    "R-MAT scale 17, edge factor 8, (0.57,0.19,0.19,0.05), seed 2; every 5-clique "
+                    "listed (original vertex ids, one row per subgraph) into a buffer resident in HBM",
+                    "list"),
     "serve": (None, None,
               "serving: R-MAT-17, Chung-Lu 7000 and R-MAT-22 resident; Poisson stream of 2,000 "
               "queries at 50 QPS, seed 5, each a uniform draw from the 141 connected 3-6-vertex "
@@ -195,6 +199,8 @@ def main():
     tune_s = time.perf_counter() - t_tune
     if mode == "batched":
         return batched_main(args, desc, g, graph, st, names, plans, launches, base_plans, plan_s, tune_s)
+    if mode == "list":
+        return list_main(args, desc, g, graph, st, names, plans, launches, base_plans, plan_s, tune_s)
     stream = torch.cuda.current_stream()
     dev_out = torch.zeros(2 * len(plans), dtype=torch.int64, device="cuda")
 
@@ -306,6 +312,105 @@ def main():
                       "launch": l, "model_order": list(b.order),
                       "model_restrictions": [list(x) for x in b.restrictions]}
                   for n, p, b, l in zip(names, plans, base_plans, launches)},
+        "preprocessing_s": {"load": st.load_seconds, "plan": plan_s, "tune": tune_s},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def list_main(args, desc, g, graph, st, names, plans, launches, base_plans, plan_s, tune_s):
+    """Listing: every embedding written as a row of k original vertex ids into
+    one preallocated device buffer; a step is one gp_list call per pattern."""
+    import numpy as np
+    import torch
+    from paper_2009_10955_amd import gp
+    stream = torch.cuda.current_stream()
+    counts = [gp.count(graph, p, **l) for p, l in zip(plans, launches)]
+    bufs = [torch.empty((max(1, c), p.k), dtype=torch.int32, device="cuda") for p, c in zip(plans, counts)]
+    note("listing " + ", ".join(f"{n}: {c} rows ({c * p.k * 4 / 1e9:.2f} GB)"
+                                for n, p, c in zip(names, plans, counts)))
+    lists = [dict(l, group=0, leaf_mode=0) for l in launches]
+
+    def step(events=None):
+        for i, (p, l) in enumerate(zip(plans, lists)):
+            if events is not None:
+                events[i][0].record(stream)
+            _, total = gp.list_embeddings(graph, p, capacity=counts[i], out=bufs[i], stream=stream, **l)
+            if total != counts[i]:
+                raise RuntimeError(f"{names[i]}: listed {total}, counted {counts[i]}")
+            if events is not None:
+                events[i][1].record(stream)
+
+    for w in range(args.warmup):
+        step()
+        note(f"warmup step {w + 1}/{args.warmup} done")
+    evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for _ in plans] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(evs[s])
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    per = [[evs[s][i][0].elapsed_time(evs[s][i][1]) for s in range(args.steps)] for i in range(len(plans))]
+    avg_ms = [sum(x) / len(x) for x in per]
+    note(f"{args.steps} timed steps done: {ms_per_step:.1f} ms/step")
+
+    # sampled validity of the rows of the last step: injective, every pattern
+    # edge on a data edge (original ids)
+    rng = np.random.default_rng(0)
+    n = g.row_ptr.shape[0] - 1
+    adj = np.repeat(np.arange(n, dtype=np.int64), np.diff(g.row_ptr)) * n + np.asarray(g.col, np.int64)
+    for i, (name, p) in enumerate(zip(names, plans)):
+        if counts[i] == 0:
+            continue
+        idx = torch.from_numpy(rng.integers(0, counts[i], 100_000)).cuda()
+        rows = bufs[i][idx].cpu().numpy().astype(np.int64)
+        assert (np.diff(np.sort(rows, axis=1), axis=1) > 0).all(), name
+        for a, b in p.edges:
+            assert np.isin(rows[:, a] * n + rows[:, b], adj).all(), name
+
+    dom = max(range(len(plans)), key=lambda i: avg_ms[i])
+    roofline = None
+    alg = {}
+    if not args.no_traffic:
+        for i, (name, p, l) in enumerate(zip(names, plans, launches)):
+            c, b = gp.count_traffic(graph, p, **l)
+            assert c == counts[i]
+            alg[name] = b + 4 * p.k * counts[i]
+            note(f"algorithmic bytes {name}: search {b:.4e} + rows {4 * p.k * counts[i]:.4e}")
+        achieved = alg[names[dom]] / (avg_ms[dom] / 1e3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                    "kernel": f"list_kernel ({names[dom]})", "alg_bytes_per_launch": alg[names[dom]],
+                    "avg_launch_ms": round(avg_ms[dom], 3),
+                    "rows_GBps": round(4 * plans[dom].k * counts[dom] / (avg_ms[dom] / 1e3) / 1e9, 2)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(g, plans, names, args.cpu_seconds)
+        cpu["sample"] += " (counted, not listed)"
+        note(f"cpu baseline: {cpu['value']:.4e} embeddings/s on {cpu['cores']} threads")
+    out = {
+        "metric": "embeddings listed/s",
+        "value": sum(counts) / (ms_per_step / 1e3),
+        "unit": "embeddings/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": desc, "graph": {"n": st.n, "m": st.m, "max_degree": st.max_degree,
+                                               "sha256": g.sha256()},
+                   "patterns": names, "parallelism": "single GPU"},
+        "counts": dict(zip(names, counts)),
+        "kernel_ms": {name: round(a, 3) for name, a in zip(names, avg_ms)},
+        "plans": {name: {"order": list(p.order), "restrictions": [list(x) for x in p.restrictions],
+                         "launch": l} for name, p, l in zip(names, plans, lists)},
         "preprocessing_s": {"load": st.load_seconds, "plan": plan_s, "tune": tune_s},
         "roofline": roofline,
         "cpu_baseline": cpu,

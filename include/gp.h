@@ -294,15 +294,19 @@ gp_status gp_count_traffic(const gp_graph* g, const gp_plan* p, const gp_launch*
  * an image of the pattern (the problem as Section II-A states it; gp_count
  * returns how many there are). The search is gp_count's with its last level
  * enumerated; the restriction closure lets exactly one map reach each
- * subgraph (Section IV-A), and that map is written out.
+ * subgraph (Section IV-A), and that map is written out. Two passes of the
+ * search: one counts the embeddings of every root edge, the other writes
+ * them at offsets from a scan of those counts.
  *   out       device memory, caller-owned: capacity rows of k int32. Row r
  *             is one embedding: out[r*k + u] = original id of the data vertex
- *             that pattern vertex u maps to. Rows come in no fixed order.
+ *             that pattern vertex u maps to. Rows are ordered by root edge
+ *             (in the library's root order), then by search order: the same
+ *             for the same graph, plan and launch.
  *   capacity  rows that out can hold (0: count only, out may be null).
  *   n_found   host: the number of embeddings (gp_count's value). When it
- *             exceeds capacity, capacity of them are written (which ones is
- *             unspecified) and the call still returns GP_OK: compare the two
- *             and call again with a larger buffer, or page.
+ *             exceeds capacity, the first capacity rows are written and the
+ *             call still returns GP_OK: compare the two and call again with a
+ *             larger buffer, or page.
  *   launch    waves_per_cu, chunk, root_stride and root_offset as in
  *             gp_count; the searches run in 64-lane groups whatever `group`
  *             says. Paging: calls with root_stride s and root_offset

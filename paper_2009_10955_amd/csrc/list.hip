@@ -12,12 +12,19 @@
 //   * one 64-lane group walks one search path; the levels above the last bind
 //     one candidate at a time, and the last level is tested 64 candidates at
 //     once, one per lane;
-//   * the lanes that hold an embedding are compacted with a ballot, and one
-//     atomic per 64 candidates reserves consecutive output rows;
+//   * two passes of the same search: the first stores how many embeddings
+//     each root task has, an exclusive scan turns these into row offsets, and
+//     the second writes each task's rows from its offset on. The lanes that
+//     hold an embedding are compacted with a ballot, and the group keeps its
+//     running row in a scalar register: no atomics on the output, and the
+//     rows come out in a fixed order (root task, then search order);
 //   * a row holds the original vertex ids, indexed by pattern vertex.
 #include <hip/hip_runtime.h>
 
+#include <hipcub/hipcub.hpp>
+
 #include <algorithm>
+#include <vector>
 
 #include "count_kernel.hpp"
 
@@ -41,7 +48,8 @@ struct ListArgs {
     int32_t* scratch;
     int64_t buf_cap;
     unsigned long long* queue;
-    unsigned long long* found;  // embeddings found so far = next output row
+    // count pass: embeddings of root task t; write pass: its first row
+    unsigned long long* task_rows;
     int32_t* out;               // out_cap rows of k int32
     int64_t out_cap;
     const int32_t* orig;        // layout id -> original id
@@ -49,33 +57,33 @@ struct ListArgs {
     int32_t chunk;
 };
 
-// Write out the lanes whose `ok` is set: the first K-1 levels are bound to
-// v[0..K-2] (the same in every lane, or per lane for K = 2) and the last to x.
-template <int K>
+// Lanes whose `ok` is set hold an embedding: v[0..K-2] bound above (the same
+// in every lane) and x at the last level. The write pass stores them as rows
+// pos, pos + 1, ... in lane order; both passes advance pos (group-uniform).
+template <int K, bool WRITE>
 __device__ __forceinline__ void emit(const Group<G>& g, const ListArgs& a, const int32_t (&v)[K], bool ok,
-                                     int32_t x) {
+                                     int32_t x, uint64_t& pos) {
     const uint64_t m = g.ballot(ok);
-    if (m == 0) return;
-    unsigned long long base = 0;
-    if (g.gl == 0) base = atomicAdd(a.found, (unsigned long long)__popcll(m));
-    base = g.bcast(base, 0);
-    if (ok) {
-        const uint64_t row = base + g.below_mask_count(m);
-        if (row < (uint64_t)a.out_cap) {
-            int32_t* o = a.out + (int64_t)row * K;
+    if constexpr (WRITE) {
+        if (ok) {
+            const uint64_t row = pos + g.below_mask_count(m);
+            if (row < (uint64_t)a.out_cap) {
+                int32_t* o = a.out + (int64_t)row * K;
 #pragma unroll
-            for (int j = 0; j < K - 1; ++j) o[a.col_of[j]] = a.orig[v[j]];
-            o[a.col_of[K - 1]] = a.orig[x];
+                for (int j = 0; j < K - 1; ++j) o[a.col_of[j]] = a.orig[v[j]];
+                o[a.col_of[K - 1]] = a.orig[x];
+            }
         }
     }
+    pos += (uint64_t)__popcll(m);
 }
 
 // Last level for bound v[0..K-2]: its candidate set is one list or buffer, or
 // the intersection of a prefix set with the list of the level before it; cut
 // to the restriction bounds, earlier images excluded.
-template <int K>
+template <int K, bool WRITE>
 __device__ void list_last(const GpPlanDesc& d, const gpcount::Ctx<G>& c, const ListArgs& a,
-                          const int32_t (&v)[K]) {
+                          const int32_t (&v)[K], uint64_t& pos) {
     const GpLevel& lv = d.lv[K - 1];
     int32_t lo, hi;
     gpcount::bounds<K>(lv.hi_src, lv.lo_src, v, lo, hi);
@@ -104,14 +112,87 @@ __device__ void list_last(const GpPlanDesc& d, const gpcount::Ctx<G>& c, const L
             x = S.p[i];
             ok = !gpcount::inj_hit<K>(lv.inj, v, x) && (!two || member(T, x));
         }
-        emit<K>(c.g, a, v, ok, x);
+        emit<K, WRITE>(c.g, a, v, ok, x, pos);
     }
 }
 
-template <int K, int L>
-__device__ void list_search(const GpPlanDesc& d, const gpcount::Ctx<G>& c, const ListArgs& a, int32_t (&v)[K]) {
+// The last level for one lane's own bound values w[0..K-2], by that lane
+// alone: the number of embeddings, and with WRITE their rows from `row` on.
+template <int K, bool WRITE>
+__device__ uint32_t last_serial(const GpPlanDesc& d, const gpcount::Ctx<G>& c, const ListArgs& a,
+                                const int32_t (&w)[K], uint64_t row) {
+    const GpLevel& lv = d.lv[K - 1];
+    int32_t lo, hi;
+    gpcount::bounds<K>(lv.hi_src, lv.lo_src, w, lo, hi);
+    uint32_t n = 0;
+    auto put = [&](int32_t x) {
+        if constexpr (WRITE) {
+            if (row + n < (uint64_t)a.out_cap) {
+                int32_t* o = a.out + (int64_t)(row + n) * K;
+#pragma unroll
+                for (int j = 0; j < K - 1; ++j) o[a.col_of[j]] = a.orig[w[j]];
+                o[a.col_of[K - 1]] = a.orig[x];
+            }
+        }
+        ++n;
+    };
+    if (lv.last_list < 0) {
+        const Set S = trim(lv.list >= 0 ? c.nbr(gpcount::pick<K>(w, lv.list)) : c.buf(lv.buf), lo, hi);
+        for (int32_t i = 0; i < S.n; ++i) {
+            const int32_t x = S.p[i];
+            if (!gpcount::inj_hit<K>(lv.inj, w, x)) put(x);
+        }
+    } else {
+        Set A = trim(lv.pre_buf >= 0 ? c.buf(lv.pre_buf) : c.nbr(gpcount::pick<K>(w, lv.pre_list)), lo, hi);
+        Set B = trim(c.nbr(gpcount::pick<K>(w, lv.last_list)), lo, hi);
+        if (A.n > B.n) {
+            const Set t = A;
+            A = B;
+            B = t;
+        }
+        for (int32_t i = 0; i < A.n; ++i) {
+            const int32_t x = A.p[i];
+            if (member(B, x) && !gpcount::inj_hit<K>(lv.inj, w, x)) put(x);
+        }
+    }
+    return n;
+}
+
+template <int K, int L, bool WRITE>
+__device__ void list_search(const GpPlanDesc& d, const gpcount::Ctx<G>& c, const ListArgs& a, int32_t (&v)[K],
+                            uint64_t& pos) {
     if constexpr (L == K - 1) {
-        list_last<K>(d, c, a, v);
+        list_last<K, WRITE>(d, c, a, v, pos);
+    } else if constexpr (L == K - 2) {
+        // lanes take different candidates of the second-to-last level and
+        // walk the last level alone; a prefix sum over the lanes' counts
+        // gives each lane its first row
+        const GpLevel& lv = d.lv[L];
+        int32_t lo, hi;
+        gpcount::bounds<K>(lv.hi_src, lv.lo_src, v, lo, hi);
+        Set S = lv.list >= 0 ? c.nbr_u(gpcount::pick<K>(v, lv.list)) : c.buf_u(lv.buf);
+        S = gpcount::trim_u<G>(S, lo, hi);
+        for (int32_t base = 0; base < S.n; base += G) {
+            const int32_t i = base + c.g.gl;
+            int32_t w[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) w[j] = v[j];
+            bool have = false;
+            if (i < S.n) {
+                w[L] = S.p[i];
+                have = !gpcount::inj_hit<K>(lv.inj, v, w[L]);
+            }
+            const uint32_t mine = have ? last_serial<K, false>(d, c, a, w, 0) : 0u;
+            uint32_t incl = mine;
+#pragma unroll
+            for (int off = 1; off < G; off <<= 1) {
+                const uint32_t t = __shfl_up(incl, off, G);
+                if (c.g.gl >= off) incl += t;
+            }
+            if constexpr (WRITE)
+                if (have && mine) (void)last_serial<K, true>(d, c, a, w, pos + (incl - mine));
+            pos += (uint64_t)gpcount::uni<G>((int32_t)__shfl(incl, G - 1, G));
+        }
     } else {
         const GpLevel& lv = d.lv[L];
         int32_t lo, hi;
@@ -123,12 +204,14 @@ __device__ void list_search(const GpPlanDesc& d, const gpcount::Ctx<G>& c, const
             if (gpcount::inj_hit<K>(lv.inj, v, x)) continue;
             v[L] = x;
             gpcount::run_builds<K, G, gpcount::MODE_PLAIN>(d, c, L, v);
-            list_search<K, L + 1>(d, c, a, v);
+            list_search<K, L + 1, WRITE>(d, c, a, v, pos);
         }
     }
 }
 
-template <int K>
+// WRITE = false: task_rows[t] = embeddings of root task t. WRITE = true:
+// task rows written from task_rows[t] on (K = 2: root t is row t).
+template <int K, bool WRITE>
 __global__ __launch_bounds__(kBlock) void list_kernel(GpPlanDesc d, ListArgs a) {
     __shared__ int32_t s_len[kBlock / G][GP_DESC_MAX_BUILDS];
     gpcount::Ctx<G> c;
@@ -155,13 +238,15 @@ __global__ __launch_bounds__(kBlock) void list_kernel(GpPlanDesc d, ListArgs a) 
         const int64_t t1 = min((int64_t)t0 + chunk, a.n_roots);
         if constexpr (K == 2) {
             // every root edge is an embedding: lanes take different roots
+            static_assert(WRITE, "edges need no count pass");
             for (int64_t base = (int64_t)t0; base < t1; base += G) {
                 const int64_t r = base + c.g.gl;
-                const bool ok = r < t1;
-                int2 e = make_int2(0, 0);
-                if (ok) e = a.roots[a.root_offset + r * a.root_stride];
-                const int32_t v[2] = {e.x, 0};
-                emit<2>(c.g, a, v, ok, e.y);
+                if (r < t1 && r < a.out_cap) {
+                    const int2 e = a.roots[a.root_offset + r * a.root_stride];
+                    int32_t* o = a.out + r * 2;
+                    o[a.col_of[0]] = a.orig[e.x];
+                    o[a.col_of[1]] = a.orig[e.y];
+                }
             }
         } else {
             for (int64_t t = (int64_t)t0; t < t1; ++t) {
@@ -171,8 +256,11 @@ __global__ __launch_bounds__(kBlock) void list_kernel(GpPlanDesc d, ListArgs a) 
                 for (int j = 0; j < K; ++j) v[j] = 0;
                 v[0] = gpcount::uni<G>(e.x);
                 v[1] = gpcount::uni<G>(e.y);
+                uint64_t pos = WRITE ? (uint64_t)gpcount::uni64<G>((int64_t)a.task_rows[t]) : 0;
                 gpcount::run_builds<K, G, gpcount::MODE_PLAIN>(d, c, 1, v);
-                list_search<K, 2>(d, c, a, v);
+                list_search<K, 2, WRITE>(d, c, a, v, pos);
+                if constexpr (!WRITE)
+                    if (c.g.gl == 0) a.task_rows[t] = pos;
             }
         }
     }
@@ -187,17 +275,33 @@ __global__ void zero_words(unsigned long long* p, int n) {
     if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
 }
 
+// found = {total rows, 0}: the last offset plus the last task's count
+__global__ void list_total(const unsigned long long* cnt, const unsigned long long* off, int64_t n,
+                           unsigned long long* found) {
+    if (threadIdx.x == 0) {
+        found[0] = n > 0 ? off[n - 1] + cnt[n - 1] : 0;
+        found[1] = 0;
+    }
+}
+
+__global__ void set_total(unsigned long long* found, int64_t n) {
+    if (threadIdx.x == 0) {
+        found[0] = (unsigned long long)n;
+        found[1] = 0;
+    }
+}
+
 typedef void (*ListFn)(GpPlanDesc, ListArgs);
 
-ListFn pick_list_kernel(int k) {
+ListFn pick_list_kernel(int k, bool write) {
     switch (k) {
-        case 2: return list_kernel<2>;
-        case 3: return list_kernel<3>;
-        case 4: return list_kernel<4>;
-        case 5: return list_kernel<5>;
-        case 6: return list_kernel<6>;
-        case 7: return list_kernel<7>;
-        case 8: return list_kernel<8>;
+        case 2: return write ? list_kernel<2, true> : nullptr;
+        case 3: return write ? list_kernel<3, true> : list_kernel<3, false>;
+        case 4: return write ? list_kernel<4, true> : list_kernel<4, false>;
+        case 5: return write ? list_kernel<5, true> : list_kernel<5, false>;
+        case 6: return write ? list_kernel<6, true> : list_kernel<6, false>;
+        case 7: return write ? list_kernel<7, true> : list_kernel<7, false>;
+        case 8: return write ? list_kernel<8, true> : list_kernel<8, false>;
         default: return nullptr;
     }
 }
@@ -213,8 +317,8 @@ gp_status launch_list(const DeviceGraph& g, const GpPlanDesc& d, const int32_t* 
     if (out_cap < 0 || (out_cap > 0 && !out) || !found_dev) return GP_ERR_ARG;
     if (cfg.waves_per_cu < 1 || cfg.waves_per_cu > 32 || cfg.chunk < 1) return GP_ERR_ARG;
     if (cfg.root_stride < 1 || cfg.root_offset < 0) return GP_ERR_ARG;
-    ListFn fn = pick_list_kernel(d.k);
-    if (!fn) return GP_ERR_UNSUPPORTED;
+    ListFn count_fn = pick_list_kernel(d.k, false), write_fn = pick_list_kernel(d.k, true);
+    if (!write_fn || (d.k > 2 && !count_fn)) return GP_ERR_UNSUPPORTED;
 
     // the plan's restriction between levels 0 and 1 picks the root array
     int64_t all_roots = g.nnz;
@@ -241,22 +345,35 @@ gp_status launch_list(const DeviceGraph& g, const GpPlanDesc& d, const int32_t* 
     const int64_t need = (n_roots + cfg.chunk - 1) / cfg.chunk;
     blocks = std::min(blocks, std::max<int64_t>(1, (need + groups_per_block - 1) / groups_per_block));
 
+    // stream-ordered allocations, all released after the kernels
+    std::vector<void*> owned;
+    auto get = [&](void** p, size_t bytes) {
+        if (hipMallocAsync(p, std::max<size_t>(bytes, 8), stream) != hipSuccess) return false;
+        owned.push_back(*p);
+        return true;
+    };
+    auto release = [&]() {
+        for (void* p : owned) (void)hipFreeAsync(p, stream);
+    };
     int32_t* scratch = nullptr;
     int32_t* orig = nullptr;
-    unsigned long long* queue = nullptr;
+    unsigned long long *queue = nullptr, *cnt = nullptr, *off = nullptr;
+    void* scan_tmp = nullptr;
+    size_t scan_bytes = 0;
     const size_t scratch_bytes = d.nbuf > 0 ? (size_t)(blocks * groups_per_block * d.nbuf * cap * 4) : 0;
-    GP_HIP_TRY(hipMallocAsync((void**)&queue, sizeof(unsigned long long), stream));
-    if (hipMallocAsync((void**)&orig, sizeof(int32_t) * std::max<int64_t>(1, g.n), stream) != hipSuccess) {
-        (void)hipFreeAsync(queue, stream);
+    const bool two_pass = d.k > 2 && n_roots > 0;
+    if (two_pass && n_roots > (int64_t)INT32_MAX) return GP_ERR_UNSUPPORTED;  // the scan counts in int
+    if (two_pass &&
+        hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, (unsigned long long*)nullptr,
+                                         (unsigned long long*)nullptr, (int)n_roots, stream) != hipSuccess)
+        return GP_ERR_HIP;
+    if (!get((void**)&queue, sizeof(unsigned long long)) || !get((void**)&orig, sizeof(int32_t) * g.n) ||
+        (scratch_bytes && !get((void**)&scratch, scratch_bytes)) ||
+        (two_pass && (!get((void**)&cnt, sizeof(unsigned long long) * n_roots) ||
+                      !get((void**)&off, sizeof(unsigned long long) * n_roots) || !get(&scan_tmp, scan_bytes)))) {
+        release();
         return GP_ERR_NOMEM;
     }
-    if (scratch_bytes && hipMallocAsync((void**)&scratch, scratch_bytes, stream) != hipSuccess) {
-        (void)hipFreeAsync(orig, stream);
-        (void)hipFreeAsync(queue, stream);
-        return GP_ERR_NOMEM;
-    }
-    hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, stream, queue, 1);
-    hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, stream, found_dev, 2);
     if (g.n > 0)
         hipLaunchKernelGGL(invert_ids, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, stream, g.new_id, g.n,
                            orig);
@@ -274,17 +391,35 @@ gp_status launch_list(const DeviceGraph& g, const GpPlanDesc& d, const int32_t* 
     a.scratch = scratch;
     a.buf_cap = cap;
     a.queue = queue;
-    a.found = found_dev;
+    a.task_rows = nullptr;
     a.out = out;
     a.out_cap = out_cap;
     a.orig = orig;
     for (int i = 0; i < GP_DESC_MAX_K; ++i) a.col_of[i] = i < d.k ? order[i] : 0;
     a.chunk = cfg.chunk;
-    if (n_roots > 0) hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kBlock), 0, stream, d, a);
+    if (two_pass) {
+        // rows per root task, their offsets, the total; then the rows
+        a.task_rows = cnt;
+        hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, stream, queue, 1);
+        hipLaunchKernelGGL(count_fn, dim3((unsigned)blocks), dim3(kBlock), 0, stream, d, a);
+        if (hipcub::DeviceScan::ExclusiveSum(scan_tmp, scan_bytes, cnt, off, (int)n_roots, stream) != hipSuccess) {
+            release();
+            return GP_ERR_HIP;
+        }
+        hipLaunchKernelGGL(list_total, dim3(1), dim3(64), 0, stream, cnt, off, n_roots, found_dev);
+        a.task_rows = off;
+        hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, stream, queue, 1);
+        hipLaunchKernelGGL(write_fn, dim3((unsigned)blocks), dim3(kBlock), 0, stream, d, a);
+    } else if (n_roots > 0) {
+        // edges: root t is row t
+        hipLaunchKernelGGL(set_total, dim3(1), dim3(64), 0, stream, found_dev, n_roots);
+        hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, stream, queue, 1);
+        hipLaunchKernelGGL(write_fn, dim3((unsigned)blocks), dim3(kBlock), 0, stream, d, a);
+    } else {
+        hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, stream, found_dev, 2);
+    }
     const hipError_t le = hipGetLastError();
-    if (scratch) (void)hipFreeAsync(scratch, stream);
-    (void)hipFreeAsync(orig, stream);
-    (void)hipFreeAsync(queue, stream);
+    release();
     return le == hipSuccess ? GP_OK : GP_ERR_HIP;
 }
 

@@ -9,13 +9,15 @@
 //   * the task queue, root arrays, candidate sets, intersections ("tmp"
 //     buffers built by the same schedule of builds) and restriction cuts are
 //     those of the counting kernel;
-//   * one 64-lane group walks one search path; the levels above the last bind
-//     one candidate at a time, and the last level is tested 64 candidates at
-//     once, one per lane;
+//   * one 64-lane group walks one search path; the levels above the
+//     second-to-last bind one candidate at a time, then the lanes take
+//     different second-to-last candidates and walk their last levels (k = 3:
+//     the group tests the last level 64 candidates at once);
 //   * two passes of the same search: the first stores how many embeddings
 //     each root task has, an exclusive scan turns these into row offsets, and
-//     the second writes each task's rows from its offset on. The lanes that
-//     hold an embedding are compacted with a ballot, and the group keeps its
+//     the second writes each task's rows from its offset on, the lanes
+//     stepping through their last levels in lockstep. The lanes that hold an
+//     embedding at a step are compacted with a ballot, and the group keeps its
 //     running row in a scalar register: no atomics on the output, and the
 //     rows come out in a fixed order (root task, then search order);
 //   * a row holds the original vertex ids, indexed by pattern vertex.
@@ -117,30 +119,18 @@ __device__ void list_last(const GpPlanDesc& d, const gpcount::Ctx<G>& c, const L
 }
 
 // The last level for one lane's own bound values w[0..K-2], by that lane
-// alone: the number of embeddings, and with WRITE their rows from `row` on.
-template <int K, bool WRITE>
-__device__ uint32_t last_serial(const GpPlanDesc& d, const gpcount::Ctx<G>& c, const ListArgs& a,
-                                const int32_t (&w)[K], uint64_t row) {
+// alone: the number of embeddings (count pass).
+template <int K>
+__device__ uint32_t last_count(const GpPlanDesc& d, const gpcount::Ctx<G>& c, const int32_t (&w)[K]) {
     const GpLevel& lv = d.lv[K - 1];
     int32_t lo, hi;
     gpcount::bounds<K>(lv.hi_src, lv.lo_src, w, lo, hi);
     uint32_t n = 0;
-    auto put = [&](int32_t x) {
-        if constexpr (WRITE) {
-            if (row + n < (uint64_t)a.out_cap) {
-                int32_t* o = a.out + (int64_t)(row + n) * K;
-#pragma unroll
-                for (int j = 0; j < K - 1; ++j) o[a.col_of[j]] = a.orig[w[j]];
-                o[a.col_of[K - 1]] = a.orig[x];
-            }
-        }
-        ++n;
-    };
     if (lv.last_list < 0) {
         const Set S = trim(lv.list >= 0 ? c.nbr(gpcount::pick<K>(w, lv.list)) : c.buf(lv.buf), lo, hi);
         for (int32_t i = 0; i < S.n; ++i) {
             const int32_t x = S.p[i];
-            if (!gpcount::inj_hit<K>(lv.inj, w, x)) put(x);
+            n += !gpcount::inj_hit<K>(lv.inj, w, x);
         }
     } else {
         Set A = trim(lv.pre_buf >= 0 ? c.buf(lv.pre_buf) : c.nbr(gpcount::pick<K>(w, lv.pre_list)), lo, hi);
@@ -152,10 +142,56 @@ __device__ uint32_t last_serial(const GpPlanDesc& d, const gpcount::Ctx<G>& c, c
         }
         for (int32_t i = 0; i < A.n; ++i) {
             const int32_t x = A.p[i];
-            if (member(B, x) && !gpcount::inj_hit<K>(lv.inj, w, x)) put(x);
+            n += member(B, x) && !gpcount::inj_hit<K>(lv.inj, w, x);
         }
     }
     return n;
+}
+
+// Write pass of last_count: every lane walks its own last level one candidate
+// per step, and a ballot per step places the step's embeddings at rows pos,
+// pos + 1, ... in lane order (one walk, no count first). Lanes without a
+// binding (have false) only join the ballots.
+template <int K>
+__device__ void last_lockstep(const GpPlanDesc& d, const gpcount::Ctx<G>& c, const ListArgs& a,
+                              const int32_t (&w)[K], bool have, uint64_t& pos) {
+    const GpLevel& lv = d.lv[K - 1];
+    int32_t lo, hi;
+    gpcount::bounds<K>(lv.hi_src, lv.lo_src, w, lo, hi);
+    const bool two = lv.last_list >= 0;
+    Set A{nullptr, 0, nullptr}, B{nullptr, 0, nullptr};
+    if (have) {
+        if (!two) {
+            A = trim(lv.list >= 0 ? c.nbr(gpcount::pick<K>(w, lv.list)) : c.buf(lv.buf), lo, hi);
+        } else {
+            A = trim(lv.pre_buf >= 0 ? c.buf(lv.pre_buf) : c.nbr(gpcount::pick<K>(w, lv.pre_list)), lo, hi);
+            B = trim(c.nbr(gpcount::pick<K>(w, lv.last_list)), lo, hi);
+            if (A.n > B.n) {
+                const Set t = A;
+                A = B;
+                B = t;
+            }
+        }
+    }
+    for (int32_t i = 0; c.g.ballot(i < A.n) != 0; ++i) {
+        bool ok = false;
+        int32_t x = 0;
+        if (i < A.n) {
+            x = A.p[i];
+            ok = (!two || member(B, x)) && !gpcount::inj_hit<K>(lv.inj, w, x);
+        }
+        const uint64_t m = c.g.ballot(ok);
+        if (ok) {
+            const uint64_t row = pos + c.g.below_mask_count(m);
+            if (row < (uint64_t)a.out_cap) {
+                int32_t* o = a.out + (int64_t)row * K;
+#pragma unroll
+                for (int j = 0; j < K - 1; ++j) o[a.col_of[j]] = a.orig[w[j]];
+                o[a.col_of[K - 1]] = a.orig[x];
+            }
+        }
+        pos += (uint64_t)__popcll(m);
+    }
 }
 
 template <int K, int L, bool WRITE>
@@ -165,8 +201,7 @@ __device__ void list_search(const GpPlanDesc& d, const gpcount::Ctx<G>& c, const
         list_last<K, WRITE>(d, c, a, v, pos);
     } else if constexpr (L == K - 2) {
         // lanes take different candidates of the second-to-last level and
-        // walk the last level alone; a prefix sum over the lanes' counts
-        // gives each lane its first row
+        // walk the last level alone
         const GpLevel& lv = d.lv[L];
         int32_t lo, hi;
         gpcount::bounds<K>(lv.hi_src, lv.lo_src, v, lo, hi);
@@ -182,16 +217,12 @@ __device__ void list_search(const GpPlanDesc& d, const gpcount::Ctx<G>& c, const
                 w[L] = S.p[i];
                 have = !gpcount::inj_hit<K>(lv.inj, v, w[L]);
             }
-            const uint32_t mine = have ? last_serial<K, false>(d, c, a, w, 0) : 0u;
-            uint32_t incl = mine;
-#pragma unroll
-            for (int off = 1; off < G; off <<= 1) {
-                const uint32_t t = __shfl_up(incl, off, G);
-                if (c.g.gl >= off) incl += t;
+            if constexpr (WRITE) {
+                last_lockstep<K>(d, c, a, w, have, pos);
+            } else {
+                const uint32_t mine = have ? last_count<K>(d, c, w) : 0u;
+                pos += c.g.sum(mine);
             }
-            if constexpr (WRITE)
-                if (have && mine) (void)last_serial<K, true>(d, c, a, w, pos + (incl - mine));
-            pos += (uint64_t)gpcount::uni<G>((int32_t)__shfl(incl, G - 1, G));
         }
     } else {
         const GpLevel& lv = d.lv[L];

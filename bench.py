@@ -47,6 +47,10 @@ WORKLOADS = {
                     "R-MAT scale 17, edge factor 8, (0.57,0.19,0.19,0.05), seed 2; every 5-clique "
                     "listed (original vertex ids, one row per subgraph) into a buffer resident in HBM",
                     "list"),
+    "iep-rmat17": (1, ["k4-path", "house"],
+                   "R-MAT scale 17, edge factor 8, (0.57,0.19,0.19,0.05), seed 2; K4 plus a pendant "
+                   "path and house counted with inclusion-exclusion over the last two levels, one "
+                   "launch each, against plain counting", "iep"),
     "serve": (None, None,
               "serving: R-MAT-17, Chung-Lu 7000 and R-MAT-22 resident; Poisson stream of 2,000 "
               "queries at 50 QPS, seed 5, each a uniform draw from the 141 connected 3-6-vertex "
@@ -75,6 +79,8 @@ def parse_args():
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_rmat17.json"),
                     help="HBM bytes per launch from rocprofv3 counters (used only while the "
                          "kernel sources it was taken from are unchanged)")
+    ap.add_argument("--no-try-iep", action="store_true",
+                    help="plain workloads: tune without inclusion-exclusion configurations")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the model's configurations and the default launch shape")
     ap.add_argument("--max-pattern-s", type=float, default=30.0,
@@ -179,13 +185,15 @@ def main():
     graph = gp.Graph.from_csr(g, device=True)
     st = graph.stats()
     t_plan = time.perf_counter()
-    base_plans = [gp.Plan(*I.PATTERNS[n], stats=st) for n in names]
+    base_plans = [gp.Plan(*I.PATTERNS[n], stats=st, iep=(mode == "iep")) for n in names]
     plan_s = time.perf_counter() - t_plan
     t_tune = time.perf_counter()
     if args.plans_json:
         prev = json.loads(open(args.plans_json).read().strip().splitlines()[-1])["plans"]
         plans = [gp.Plan(*I.PATTERNS[n], stats=st, force_order=prev[n]["order"],
-                         force_restr=[tuple(x) for x in prev[n]["restrictions"]]) for n in names]
+                         force_restr=[tuple(x) for x in prev[n]["restrictions"]],
+                         iep=bool(prev[n].get("iep", mode == "iep")))
+                 for n in names]
         launches = [dict(prev[n]["launch"]) for n in names]
     elif args.no_tune:
         plans = base_plans
@@ -193,7 +201,8 @@ def main():
     else:
         plans = []
         for n, p in zip(names, base_plans):
-            plans.append(p.tuned(graph, budget_seconds=args.tune_seconds))
+            plans.append(p.tuned(graph, budget_seconds=args.tune_seconds,
+                                 try_iep=(mode == "plain" and not args.no_try_iep)))
             note(f"tuned {n}")
         launches = [p.launch() for p in plans]
     tune_s = time.perf_counter() - t_tune
@@ -262,7 +271,7 @@ def main():
         tr = profiling.load_traffic(args.traffic_json)
         dom_plan = {"order": list(plans[dom].order),
                     "restrictions": [list(x) for x in plans[dom].restrictions],
-                    "launch": launches[dom]}
+                    "launch": launches[dom], "iep": bool(plans[dom].info().iep)}
         l2 = None
         if (tr is not None and tr["pattern"] == names[dom] and tr["workload"] == args.workload
                 and profiling.same_plan(tr.get("plan"), dom_plan)):
@@ -283,13 +292,37 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
 
+    plain = None
+    if mode == "iep":
+        # the same patterns counted without inclusion-exclusion, each tuned
+        plain = {}
+        for i, (n, b) in enumerate(zip(names, base_plans)):
+            pp = gp.Plan(*I.PATTERNS[n], stats=st)
+            if not args.no_tune and not args.plans_json:
+                pp = pp.tuned(graph, budget_seconds=args.tune_seconds)
+            pl = pp.launch()
+            ts = []
+            for _ in range(3):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                gp.count_async(graph, pp, dev_out[2 * i:2 * i + 2], stream, **pl)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            c = int(dev_out[2 * i].item())
+            if c != counts[i]:
+                raise RuntimeError(f"{n}: plain count {c} != IEP count {counts[i]}")
+            plain[n] = {"kernel_ms": round(min(ts), 3), "iep_speedup": round(min(ts) / avg_ms[i], 3),
+                        "iep": bool(plans[i].info().iep), "launch": pl}
+            note(f"plain {n}: {min(ts):.2f} ms (IEP {avg_ms[i]:.2f} ms)")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(g, plans, names, args.cpu_seconds)
         note(f"cpu baseline: {cpu['value']:.4e} embeddings/s on {cpu['cores']} threads")
 
     out = {
-        "metric": METRIC,
+        "metric": METRIC if mode != "iep" else "embeddings/s counted with inclusion-exclusion",
         "value": value,
         "unit": "embeddings/s",
         "n_gpus": 1,
@@ -309,13 +342,15 @@ def main():
         "intersection_GBps": {n: round(alg[n] / (a / 1e3) / 1e9, 2) for n, a in zip(names, avg_ms)}
         if alg else None,
         "plans": {n: {"order": list(p.order), "restrictions": [list(x) for x in p.restrictions],
-                      "launch": l, "model_order": list(b.order),
+                      "launch": l, "iep": bool(p.info().iep), "model_order": list(b.order),
                       "model_restrictions": [list(x) for x in b.restrictions]}
                   for n, p, b, l in zip(names, plans, base_plans, launches)},
         "preprocessing_s": {"load": st.load_seconds, "plan": plan_s, "tune": tune_s},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if plain is not None:
+        out["plain"] = plain
     print(json.dumps(out), flush=True)
 
 

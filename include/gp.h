@@ -226,6 +226,12 @@ typedef struct {
     double budget_seconds;  /* GPU time for timing sampled configurations (0 = 20 s); the
                                launch-shape, full-run and queue-grab stages that follow may
                                bring the total to at most about 4 times this */
+    int32_t try_iep;        /* 1: for a plan that counts without IEP, also time each
+                               candidate configuration counted with inclusion-exclusion
+                               over its last two levels (Section IV-D) where the pattern
+                               allows it, and keep whichever is fastest. The tuned plan may
+                               then be an IEP plan, which gp_list, gp_estimate and batches
+                               refuse (GP_ERR_UNSUPPORTED). 0 (default): the plan's mode */
 } gp_tune_opts;
 
 void gp_tune_opts_default(gp_tune_opts* o);

@@ -187,7 +187,9 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
     for (auto& e : edges)
         if (e.first > e.second) std::swap(e.first, e.second);
     std::sort(edges.begin(), edges.end());
-    auto key = std::make_tuple(g->dg.stats.hash, (int64_t)g->dg.n_hubs * 2 + (p->desc.iep ? 1 : 0), k, edges);
+    const bool try_iep = o.try_iep > 0 && !p->desc.iep;
+    auto key = std::make_tuple(g->dg.stats.hash,
+                               (int64_t)g->dg.n_hubs * 4 + (p->desc.iep ? 1 : 0) + (try_iep ? 2 : 0), k, edges);
     {
         std::lock_guard<std::mutex> lk(g_cache_mu);
         auto it = g_cache.find(key);
@@ -226,18 +228,17 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
                          [](const Ranked& a, const Ranked& b) { return a.cost < b.cost; });
         std::vector<Cfg> cands;
         std::vector<gp::Perm> auts = gp::automorphisms(p->pattern);
-        auto add = [&](const gp::Perm& order, gp::Rel rel) {
-            if ((int)cands.size() >= max_configs) return;
-            // a mirrored set is valid whenever the original is; check anyway
-            if (!gp::acyclic(rel, k) || !gp::validate(rel, k, p->aut)) return;
-            for (size_t q = 1; q < auts.size(); ++q)
-                if (gp::no_conflict(auts[q], rel, k)) return;
+        // with try_iep every configuration may come twice: counted plainly
+        // and with inclusion-exclusion over its last two levels
+        const int cap = try_iep ? 2 * max_configs : max_configs;
+        auto add_one = [&](const gp::Perm& order, gp::Rel rel, bool iep) {
+            if ((int)cands.size() >= cap) return;
             Cfg c;
             c.order = order;
             c.rel = rel;
             gp::Rel kept = 0;
             int div = 0;
-            if (p->desc.iep) {
+            if (iep) {
                 div = gp::iep_setup(p->pattern, auts, order, rel, &kept);
                 if (div <= 0) return;
             }
@@ -246,10 +247,19 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
                 if (std::memcmp(&x.desc, &c.desc, sizeof c.desc) == 0) return;
             cands.push_back(c);
         };
+        auto add = [&](const gp::Perm& order, gp::Rel rel) {
+            if ((int)cands.size() >= cap) return;
+            // a mirrored set is valid whenever the original is; check anyway
+            if (!gp::acyclic(rel, k) || !gp::validate(rel, k, p->aut)) return;
+            for (size_t q = 1; q < auts.size(); ++q)
+                if (gp::no_conflict(auts[q], rel, k)) return;
+            add_one(order, rel, p->desc.iep != 0);
+            if (try_iep) add_one(order, rel, true);
+        };
         add(p->order, p->set);
         add(p->order, mirror(p->set, k));
         for (auto& r : ranked) {
-            if ((int)cands.size() >= max_configs) break;
+            if ((int)cands.size() >= cap) break;
             add(reps[r.i], p->sets[r.j]);
             add(reps[r.i], mirror(p->sets[r.j], k));
         }

@@ -62,7 +62,8 @@ class Launch(ctypes.Structure):
 
 class TuneOpts(ctypes.Structure):
     _fields_ = [("max_configs", ctypes.c_int32), ("sample_stride", ctypes.c_int32),
-                ("tune_launch", ctypes.c_int32), ("budget_seconds", ctypes.c_double)]
+                ("tune_launch", ctypes.c_int32), ("budget_seconds", ctypes.c_double),
+                ("try_iep", ctypes.c_int32)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -338,9 +339,12 @@ class Plan:
         return c.value
 
     def tuned(self, graph: "Graph", max_configs: int = 0, sample_stride: int = 0,
-              tune_launch: bool = True, budget_seconds: float = 0.0, stream=None) -> "Plan":
-        """A new plan whose configuration and launch shape were timed on graph."""
-        o = TuneOpts(max_configs, sample_stride, 1 if tune_launch else -1, budget_seconds)
+              tune_launch: bool = True, budget_seconds: float = 0.0, stream=None,
+              try_iep: bool = False) -> "Plan":
+        """A new plan whose configuration and launch shape were timed on graph;
+        try_iep: IEP configurations compete too (the result may count with IEP)."""
+        o = TuneOpts(max_configs, sample_stride, 1 if tune_launch else -1, budget_seconds,
+                     1 if try_iep else 0)
         h = ctypes.c_void_p()
         _check(_lib().gp_plan_tune(graph.handle, self._h, ctypes.byref(o), _stream_handle(stream),
                                    ctypes.byref(h)), "gp_plan_tune")

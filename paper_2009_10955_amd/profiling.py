@@ -101,12 +101,13 @@ def traffic_summary(fetch_glob: str, write_glob: str, kernel_match: str, copy_by
 
 
 def same_plan(a: dict | None, b: dict | None) -> bool:
-    """Whether two recorded configurations (order, restrictions, launch) agree."""
+    """Whether two recorded configurations (order, restrictions, launch, and
+    whether the last two levels are counted with inclusion-exclusion) agree."""
     if not a or not b:
         return False
     keys = ("order", "restrictions", "launch")
-    return all(json.dumps(a.get(k), sort_keys=True) == json.dumps(b.get(k), sort_keys=True)
-               for k in keys)
+    return (all(json.dumps(a.get(k), sort_keys=True) == json.dumps(b.get(k), sort_keys=True) for k in keys)
+            and bool(a.get("iep", False)) == bool(b.get("iep", False)))
 
 
 def main(argv):
@@ -123,7 +124,7 @@ def main(argv):
     if a.plans:
         with open(a.plans) as f:
             plan = json.loads(f.read().strip().splitlines()[-1])["plans"][a.pattern]
-        plan = {k: plan[k] for k in ("order", "restrictions", "launch")}
+        plan = {k: plan[k] for k in ("order", "restrictions", "launch")} | {"iep": bool(plan.get("iep", False))}
     s = traffic_summary(a.fetch_glob, a.write_glob, a.kernel_match, int(a.copy_mib) << 20, a.pattern,
                         a.workload, plan, a.l2)
     with open(a.out, "w") as f:

@@ -447,6 +447,27 @@ def test_tuned_plans_count_the_same():
         assert again.order == tuned.order and again.restrictions == tuned.restrictions
 
 
+def test_tuning_with_iep_candidates_counts_the_same():
+    """With IEP configurations in the race the tuned plan (plain or IEP)
+    still gives the oracle's count; an IEP winner is refused by listing."""
+    g = I.config_graph(0)
+    graph = gp.Graph.from_csr(g, device=True)
+    for pname in ["3-star", "4-path", "house", "k4-path", "5-cycle", "tailed-triangle"]:
+        k, e = P[pname]
+        plan = gp.Plan(k, e, stats=graph.stats())
+        tuned = plan.tuned(graph, budget_seconds=1.0, try_iep=True)
+        want = O.count(g, k, e)
+        assert gp.count(graph, tuned) == want, pname
+        for grp in (64, 32):
+            assert gp.count(graph, tuned, group=grp) == want, (pname, grp)
+        if tuned.info().iep:
+            assert tuned.info().iep_div >= 1
+            with pytest.raises(gp.GpError):
+                gp.list_embeddings(graph, tuned, capacity=1)
+        plain = plan.tuned(graph, budget_seconds=1.0)
+        assert not plain.info().iep and gp.count(graph, plain) == want, pname
+
+
 # ------------------------------------------------------------------ serving
 
 @pytest.mark.parametrize("leaf", [1, 4])

@@ -63,6 +63,23 @@ KernelFn pick_kernel(int k, int group, int leaf, int mode, bool iep) {
     }
 }
 
+__global__ void zero_u64(unsigned long long* p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// Whether leaf mode 4 may keep its last-level counts per root: the last
+// level is pre & N(v[k-2]) with pre the list of a root level, its cut comes
+// from the root levels only, and every earlier image it must avoid is a
+// parent of level k-2.
+bool memo_eligible(const GpPlanDesc& d) {
+    if (d.k < 4 || d.iep) return false;
+    const GpLevel& ll = d.lv[d.k - 1];
+    if (ll.last_list != d.k - 2 || ll.pre_buf >= 0 || ll.pre_list < 0 || ll.pre_list > 1) return false;
+    if ((ll.hi_src | ll.lo_src) & ~3u) return false;
+    return (ll.inj & ~(uint32_t)d.lv[d.k - 2].parents) == 0;
+}
+
 // Divide an IEP total by its over-count; flag 2 if it does not divide.
 __global__ void iep_divide(unsigned long long* result, unsigned long long div) {
     if (threadIdx.x == 0 && div > 0) {
@@ -205,13 +222,27 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
 
     int32_t* scratch = nullptr;
     unsigned long long* queue = nullptr;
+    unsigned long long* memo = nullptr;
     size_t scratch_bytes = d.nbuf > 0 ? (size_t)(blocks * groups_per_block * d.nbuf * cap * 4) : 0;
+    // leaf mode 4's per-task memo: one word per hub per group, within 4 GiB
+    const int64_t memo_words = blocks * groups_per_block * (int64_t)g.n_hubs;
+    const bool use_memo = cfg.leaf == 4 && mode != MODE_ACCOUNT && !iep && g.n_hubs > 0 && memo_eligible(d) &&
+                          n_tasks < (int64_t(1) << 31) && memo_words * 8 <= (int64_t(4) << 30);
     GP_HIP_TRY(hipMallocAsync((void**)&queue, sizeof(unsigned long long) * 2, stream));
     if (scratch_bytes) {
         if (hipMallocAsync((void**)&scratch, scratch_bytes, stream) != hipSuccess) {
             (void)hipFreeAsync(queue, stream);
             return GP_ERR_NOMEM;
         }
+    }
+    if (use_memo) {
+        if (hipMallocAsync((void**)&memo, (size_t)memo_words * 8, stream) != hipSuccess) {
+            if (scratch) (void)hipFreeAsync(scratch, stream);
+            (void)hipFreeAsync(queue, stream);
+            return GP_ERR_NOMEM;
+        }
+        hipLaunchKernelGGL(zero_u64, dim3((unsigned)std::min<int64_t>(4096, (memo_words + 255) / 256)), dim3(256), 0,
+                           stream, memo, memo_words);
     }
     hipLaunchKernelGGL(init_counters, dim3(1), dim3(64), 0, stream, queue, 1);
     hipLaunchKernelGGL(init_counters, dim3(1), dim3(64), 0, stream, result_dev, account ? 3 : 2);
@@ -237,12 +268,14 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
     a.result = result_dev;
     a.per_root = per_root;
     a.busy = busy;
+    a.memo = memo;
     a.chunk = cfg.chunk;
     if (n_tasks > 0) hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kBlock), 0, stream, d, a);
     if (iep)
         hipLaunchKernelGGL(iep_divide, dim3(1), dim3(64), 0, stream, result_dev, (unsigned long long)d.iep_div);
     hipError_t le = hipGetLastError();
     if (scratch) (void)hipFreeAsync(scratch, stream);
+    if (memo) (void)hipFreeAsync(memo, stream);
     (void)hipFreeAsync(queue, stream);
     if (le != hipSuccess) return GP_ERR_HIP;
     return GP_OK;

@@ -90,6 +90,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(occupanc
     c.sj = 0;
     c.sJ = 1;
     c.deadline = 0;
+    c.memo = nullptr;
+    c.tag = 0;
     const int64_t chunk = a.chunk;
 
     for (;;) {

@@ -77,6 +77,9 @@ struct CountArgs {
     // with busy: stop taking tasks once a wavefront has run this many clock
     // ticks (0: no limit); the count is then incomplete and flagged (bit 2)
     uint64_t budget_ticks;
+    // optional (leaf mode 4, plans the host found eligible): per group,
+    // n_hubs words {root tag, |N(x) & pre & cut|} for hub candidates x
+    unsigned long long* memo;
     int32_t chunk;
 };
 
@@ -172,6 +175,8 @@ struct Ctx {
     int32_t n_hubs;
     int32_t sj, sJ;     // level-2 slice of the current task: candidates sj, sj + sJ, ...
     uint64_t deadline;  // clock tick after which every search loop stops (0: none)
+    unsigned long long* memo;  // this group's last-level memo (null: none)
+    uint32_t tag;              // current root + 1, the memo's validity tag
     Group<G> g;
 
     __device__ __forceinline__ bool expired() const {
@@ -486,6 +491,15 @@ __device__ void flat_leaf(const GpPlanDesc& d, const Ctx<G>& c, const int32_t (&
 // every G-th element (coalesced loads), and each element costs one bit test
 // in the shared bitmap. Returns false (nothing done) when the last level has
 // another form; the caller then counts it as in leaf mode 1.
+//
+// With a memo (c.memo), the count |N(x) & pre & [lo, hi)| of a hub candidate
+// x is kept per root edge: the host enables it only when pre and the cut come
+// from the two root levels, so for one root they are fixed and the count
+// depends on x alone, however the levels between were bound (split tasks of
+// one root that a group takes in a row share it). The earlier
+// images the last level must avoid are then all parents of x, so each lies
+// in N(x), and whether it falls in the set is its pre bit and the cut: they
+// are subtracted per lane.
 constexpr int32_t kCoopList = 64;
 
 template <int K, int G, int MODE>
@@ -512,13 +526,37 @@ __device__ bool coop_bits_leaf(const GpPlanDesc& d, const Ctx<G>& c, const int32
                 int32_t lo, hi;
                 bounds<K>(ll.hi_src, ll.lo_src, w, lo, hi);
                 auto skip = [&](int32_t y) { return inj_hit<K>(ll.inj, w, y); };
-                B = c.nbr(x);
-                if (B.n <= kShortList) {
-                    add_count(acc, count_bits_range(B, lo, hi, bits, skip), ovf);
+                if (c.memo && x < c.n_hubs) {
+                    // earlier images in the set: parents of x, so in N(x)
+                    uint32_t corr = 0;
+#pragma unroll
+                    for (int j = 0; j < K - 1; ++j)
+                        if ((ll.inj >> j) & 1u) {
+                            const int32_t y = w[j];
+                            corr += (y >= lo && y < hi && ((bits[y >> 5] >> (y & 31)) & 1u)) ? 1u : 0u;
+                        }
+                    const unsigned long long e = c.memo[x];
+                    if ((uint32_t)(e >> 32) == c.tag) {
+                        add_count(acc, (uint32_t)e - corr, ovf);
+                    } else {
+                        B = trim(c.nbr(x), lo, hi);
+                        if (B.n <= kCoopList) {
+                            const uint32_t all = count_bits(B, bits, [](int32_t) { return false; });
+                            c.memo[x] = ((unsigned long long)c.tag << 32) | all;
+                            add_count(acc, all - corr, ovf);
+                        } else {
+                            longl = true;
+                        }
+                    }
                 } else {
-                    B = trim(B, lo, hi);
-                    if (B.n <= kCoopList) add_count(acc, count_bits(B, bits, skip), ovf);
-                    else longl = true;
+                    B = c.nbr(x);
+                    if (B.n <= kShortList) {
+                        add_count(acc, count_bits_range(B, lo, hi, bits, skip), ovf);
+                    } else {
+                        B = trim(B, lo, hi);
+                        if (B.n <= kCoopList) add_count(acc, count_bits(B, bits, skip), ovf);
+                        else longl = true;
+                    }
                 }
             }
         }
@@ -533,12 +571,20 @@ __device__ bool coop_bits_leaf(const GpPlanDesc& d, const Ctx<G>& c, const int32
 #pragma unroll
             for (int j = 0; j < K; ++j) w[j] = v[j];
             w[K - 2] = ox;
-            uint32_t cnt = 0;
+            uint32_t cnt = 0, all = 0;
             for (int32_t j = c.g.gl; j < on; j += G) {
                 const int32_t y = op[j];
-                if ((bits[y >> 5] >> (y & 31)) & 1u) cnt += !inj_hit<K>(ll.inj, w, y);
+                if ((bits[y >> 5] >> (y & 31)) & 1u) {
+                    ++all;
+                    cnt += !inj_hit<K>(ll.inj, w, y);
+                }
             }
             add_count(acc, cnt, ovf);
+            if (c.memo && ox < c.n_hubs) {
+                // the long list of a hub candidate: keep its whole count
+                const uint32_t tot = (uint32_t)c.g.sum(all);
+                if (c.g.gl == 0) c.memo[ox] = ((unsigned long long)c.tag << 32) | tot;
+            }
         }
     }
     return true;
@@ -672,6 +718,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(occupanc
     c.bytes = &bytes;
     c.sj = 0;
     c.sJ = 1;
+    c.memo = a.memo ? a.memo + group_id * (int64_t)a.n_hubs : nullptr;
+    c.tag = 0;
     const uint64_t t_begin = a.busy ? wall_clock64() : 0;
     c.deadline = a.busy && a.budget_ticks ? t_begin + a.budget_ticks : 0;
     uint64_t chunk_max = 0;
@@ -737,6 +785,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(occupanc
         } else {
             for (int64_t t = (int64_t)t0; t < t1; ++t) {
                 const int64_t r = task_root(t, a.split_roots, a.split_ways, c.sj, c.sJ);
+                c.tag = (uint32_t)(r + 1);
                 int2 e = a.roots[a.root_offset + r * a.root_stride];
                 e.x = uni<G>(e.x);
                 e.y = uni<G>(e.y);

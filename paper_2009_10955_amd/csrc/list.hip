@@ -260,6 +260,8 @@ __global__ __launch_bounds__(kBlock) void list_kernel(GpPlanDesc d, ListArgs a) 
     c.sj = 0;
     c.sJ = 1;
     c.deadline = 0;
+    c.memo = nullptr;
+    c.tag = 0;
     const int64_t chunk = a.chunk;
     for (;;) {
         unsigned long long t0 = 0;

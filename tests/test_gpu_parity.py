@@ -160,6 +160,27 @@ def test_split_roots_equal_oracle(pname):
             assert _count(graph, k, e, **sp, **v) == want, (sp, v)
 
 
+def test_leaf4_memo_on_an_eligible_plan():
+    """The 5-cycle configuration whose last level keeps per-root counts of
+    hub candidates (leaf mode 4 memo): with every vertex a hub and with hubs
+    by degree, every queue grab (split tasks of one root sharing a group's
+    memo or not), split, group width and per-root count equals the oracle."""
+    g = I.er(120, 0.3, seed=5)
+    k, e = P["5-cycle"]
+    want = O.count(g, k, e)
+    plan = gp.Plan(k, e, force_order=[0, 1, 2, 3, 4], force_restr=[(1, 0), (1, 2), (1, 3), (1, 4), (2, 0)])
+    for hub in ("dense", "auto"):
+        graph = gp.Graph.from_csr(g, device=True, hub_bitmaps=hub)
+        for ch in (1, 4, 16):
+            for sw, sv in ((1, 0), (16, 1 << 20), (3, 8)):
+                for grp in (64, 32, 16):
+                    got = gp.count(graph, plan, group=grp, leaf_mode=4, chunk=ch, split_ways=sw, split_vertices=sv)
+                    assert got == want, (hub, ch, sw, sv, grp)
+        tot4, per4 = gp.count_per_root(graph, plan, group=64, leaf_mode=4)
+        tot1, per1 = gp.count_per_root(graph, plan, group=64, leaf_mode=1)
+        assert tot4 == tot1 == want and bool((per4 == per1).all()), hub
+
+
 def test_split_roots_with_hubs_and_sampling():
     """A hub-heavy graph (hub bitmaps on): split counts equal unsplit ones,
     and strided root samples of a split launch still partition the count."""

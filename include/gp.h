@@ -221,8 +221,9 @@ typedef struct {
     int32_t sample_stride;  /* time every stride-th root task only (0 = auto, aiming at
                                about 8 ms of balanced work per sample) */
     int32_t tune_launch;    /* 1 (default): also pick lanes per group, leaf mode and, for
-                               k >= 4 when the winner was timed in full, the tasks taken per
-                               queue grab (4, 2 or 1); -1: keep the defaults */
+                               k >= 4 when the winner was timed in full, the ways heavy
+                               roots are split (16, 4 or 1) and the tasks taken per queue
+                               grab (1, 2, 4, 8 or 16); -1: keep the defaults */
     double budget_seconds;  /* GPU time for timing sampled configurations (0 = 20 s); the
                                launch-shape, full-run and queue-grab stages that follow may
                                bring the total to at most about 4 times this */

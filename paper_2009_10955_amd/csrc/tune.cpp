@@ -499,23 +499,37 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
             best_launch = bp->launch;
             best_ms = bp->est;
         }
-        // 6. tasks per grab of the queue counter, in full runs of the winner:
-        //    single roots per grab shorten the tail of long patterns, while
-        //    short ones can lose to the extra grabs; a smaller grab must win
-        //    by 2% to count as more than noise
+        // 6. root splitting, then tasks per grab of the queue counter, in full
+        //    runs of the winner, one change at a time. Splitting shortens the
+        //    tail that single hub roots leave, but the split tasks of a root
+        //    then run in different groups, which cannot share leaf mode 4's
+        //    per-root memo. Single roots per grab shorten the tail of long
+        //    patterns; longer grabs keep neighbouring roots (and the split
+        //    tasks of one root) in one group. A change must win by 2% to count
+        //    as more than noise.
         if (st == GP_OK && timed_full && k >= 4 && best_ms < inf && o.tune_launch >= 0) {
-            const gpint::LaunchCfg won = best_launch;
-            for (int ch : {2, 1}) {
-                if (ch >= won.chunk || spent + best_ms > 4.0 * budget_ms) continue;
-                gpint::LaunchCfg cfg = won;
-                cfg.chunk = ch;
+            auto try_cfg = [&](const gpint::LaunchCfg& cfg) {
+                if (st != GP_OK || spent + best_ms > 4.0 * budget_ms) return;
                 best_est = best_ms;  // a run past three times the winner stops
-                double t = measure(cands[best].desc, cfg, 1, "chunk", best);
-                if (t < 0) break;
-                if (t < 0.98 * best_ms) {
+                const double t = measure(cands[best].desc, cfg, 1, "grab", best);
+                if (t >= 0 && t < 0.98 * best_ms) {
                     best_ms = t;
                     best_launch = cfg;
                 }
+            };
+            const gpint::LaunchCfg won = best_launch;
+            for (int ways : {4, 1}) {
+                if (ways == won.split_ways) continue;
+                gpint::LaunchCfg cfg = best_launch;
+                cfg.split_ways = ways;
+                try_cfg(cfg);
+            }
+            const int chunk0 = best_launch.chunk;
+            for (int ch : {2, 1, 8, 16}) {
+                if (ch == chunk0) continue;
+                gpint::LaunchCfg cfg = best_launch;
+                cfg.chunk = ch;
+                try_cfg(cfg);
             }
         }
         best_launch.root_stride = 1;

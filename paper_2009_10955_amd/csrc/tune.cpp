@@ -356,8 +356,9 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
 
         // 4. launch shape for the two best configurations: group width and
         //    leaf mode change which configuration is fastest. Root splitting
-        //    stays on: the tail it removes comes from the few heaviest roots,
-        //    which a strided sample mostly misses, and it costs little
+        //    stays at its default here: the tail it removes comes from the few
+        //    heaviest roots, which a strided sample mostly misses; the last
+        //    stage sets it from full runs
         struct Pick {
             double est;
             size_t c;

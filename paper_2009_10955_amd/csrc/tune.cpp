@@ -470,6 +470,17 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
                     add_full(pk);
                     break;
                 }
+            // the other finalists, at their best measured shape or the default
+            // one: sample estimates rank configurations only within their noise
+            for (const auto& f : fine) {
+                const Pick* bp = nullptr;
+                for (const Pick& pk : tried)  // sorted: the first of a configuration is its best
+                    if (pk.c == f.second) {
+                        bp = &pk;
+                        break;
+                    }
+                add_full(bp ? *bp : Pick{f.first, f.second, base});
+            }
         }
         bool timed_full = stride == 1;  // picks hold full-run times
         if (st == GP_OK && stride > 1 && full.size() > 1) {

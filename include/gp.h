@@ -153,9 +153,11 @@ typedef struct {
     double cost_cap;             /* if > 0: GP_ERR_BUDGET when the best predicted cost exceeds it */
     double max_seconds;          /* Algorithm 1 stops exploring after this long once a valid set
                                     exists (0 = 20 s) */
-    int32_t iep;                 /* 1: count the last two levels with inclusion-exclusion
-                                    (Section IV-D) when a configuration allows it; see
-                                    gp_plan_info.iep */
+    int32_t iep;                 /* counting with inclusion-exclusion (Section IV-D) over the
+                                    innermost pairwise non-adjacent levels of the schedule,
+                                    when a configuration allows it (see gp_plan_info.iep):
+                                    0 off; 1: as many levels as the schedule allows (at most
+                                    4, and not the root edge); 2..4: at most that many */
 } gp_plan_opts;
 
 /* Fill opts with the defaults (nothing forced, no cap). */
@@ -192,15 +194,21 @@ typedef struct {
     int32_t set_index;         /* index of the chosen set in emission order (-1 if forced pairs) */
     double plan_seconds;       /* host wall time of gp_plan_create (plus gp_plan_tune) */
     int32_t tuned;             /* 1 if the configuration and launch were measured by gp_plan_tune */
-    int32_t iep;               /* 1 if the last two levels are counted with inclusion-exclusion:
-                                  the best-ranked configuration whose last two schedule vertices
-                                  are non-adjacent and over which IEP counts every embedding the
-                                  same number of times, iep_div (restrictions between the two
-                                  are dropped, and if needed all checked in them); the kernel
-                                  divides its total by iep_div */
+    int32_t iep;               /* number of innermost levels counted with inclusion-exclusion
+                                  (0: none; 2..4): the best-ranked configuration whose last iep
+                                  schedule vertices are pairwise non-adjacent and over which IEP
+                                  counts every embedding the same number of times, iep_div
+                                  (restrictions between two inner levels are dropped, and if
+                                  needed all checked in them); for each binding of the outer
+                                  levels the kernel adds the number of tuples of distinct
+                                  elements of the inner levels' candidate sets, and divides the
+                                  128-bit total by iep_div */
     int32_t iep_div;
     int32_t n_measured;        /* configurations timed by gp_plan_tune */
     gp_launch launch;          /* launch shape used when the caller passes none */
+    double tuned_ms;           /* gp_plan_tune: full-run time of the chosen configuration and
+                                  launch (measured, or estimated from samples); 0 if untuned.
+                                  Batches run longer plans first */
 } gp_plan_info;
 
 gp_status gp_plan_get(const gp_plan* p, gp_plan_info* out);
@@ -229,10 +237,10 @@ typedef struct {
                                bring the total to at most about 4 times this */
     int32_t try_iep;        /* 1: for a plan that counts without IEP, also time each
                                candidate configuration counted with inclusion-exclusion
-                               over its last two levels (Section IV-D) where the pattern
-                               allows it, and keep whichever is fastest. The tuned plan may
-                               then be an IEP plan, which gp_list, gp_estimate and batches
-                               refuse (GP_ERR_UNSUPPORTED). 0 (default): the plan's mode */
+                               over its last 2, 3 or 4 levels (Section IV-D) where the
+                               schedule allows it, and keep whichever is fastest. The tuned
+                               plan may then be an IEP plan, which gp_list refuses
+                               (GP_ERR_UNSUPPORTED). 0 (default): the plan's mode */
 } gp_tune_opts;
 
 void gp_tune_opts_default(gp_tune_opts* o);
@@ -297,6 +305,21 @@ gp_status gp_count_traffic(const gp_graph* g, const gp_plan* p, const gp_launch*
                            void* stream, uint64_t* out, uint64_t* alg_bytes);
 
 /*
+ * Verification of the exact accumulation (Section II-A defines the count as
+ * an integer; counts above 2^64 are reported, never wrapped): the n values
+ * (host memory) are added on the device exactly as the counting kernels add
+ * their lanes' counts (64-bit lane totals with carries counted, an exact
+ * 128-bit wavefront sum, a 128-bit device total), then finished as every
+ * count is: divided by div (>= 1; the IEP over-count of an IEP plan, 1
+ * otherwise). *out = the quotient's low 64 bits; *flags bit 0: the quotient
+ * does not fit in 64 bits (gp_count's GP_ERR_OVERFLOW), bit 1: div does not
+ * divide the sum (GP_ERR_INTERNAL). Blocking. For tests of the carry and
+ * division paths with values that no graph here reaches.
+ */
+gp_status gp_check_sum(const uint64_t* values, int64_t n, uint64_t div, void* stream, uint64_t* out,
+                       uint32_t* flags);
+
+/*
  * List the embeddings of plan p in graph g: every distinct subgraph that is
  * an image of the pattern (the problem as Section II-A states it; gp_count
  * returns how many there are). The search is gp_count's with its last level
@@ -333,21 +356,26 @@ gp_status gp_list(const gp_graph* g, const gp_plan* p, const gp_launch* launch, 
  * wavefront has run that long; *est_ms is then 1e300 (the full run is at
  * least that slow). Writes the sample's count and stride when the pointers
  * are non-null: count * stride is a rough estimate of the full count (not
- * exact; for planning only). Blocks on stream. GP_ERR_UNSUPPORTED for IEP
- * plans. Used for admission by gp_server (max_query_ms) and for feasibility
- * reports. */
+ * exact; for planning only; for an IEP plan the sample's total is divided by
+ * iep_div without a divisibility check). Blocks on stream. Used for admission
+ * by gp_server (max_query_ms) and for feasibility reports. */
 gp_status gp_estimate(const gp_graph* g, const gp_plan* p, const gp_launch* launch, double budget_ms,
                       void* stream, double* est_ms, uint64_t* sample_count, int64_t* sample_stride);
 
 /*
- * Count several plans (1..64, any pattern sizes) over one graph in ONE
- * persistent launch: the task space is the concatenation of the plans' root
- * edges, handed out in chunks from one atomic queue, so plans of uneven cost
- * fill each other's tails (Section IV-E's task partitioning across patterns).
- * The lanes per group (64, 32 or 16) and leaf mode (1, 3 or 4 where the plan allows
- * it) come from `launch`, else from the first plan's launch. Plans counted
- * with IEP are not supported here (GP_ERR_UNSUPPORTED). out[i] = count of plans[i]
- * (host memory). Blocking. Counts equal gp_count's bit for bit.
+ * Count several plans (1..64, any pattern sizes, counted plainly or with
+ * IEP) over one graph in ONE persistent launch (Section IV-E's task
+ * partitioning, across patterns). Every plan keeps its own task cursor and
+ * its own launch shape: lanes per group (64, 32 or 16; IEP plans 64 or 32),
+ * leaf mode (1, 3 or 4 where the plan allows it) and tasks per grab come
+ * from the plan's launch (its tuned one after gp_plan_tune), with every
+ * non-zero field of `launch` (may be null) overriding them for all plans.
+ * Wavefronts take the plans longest-first by gp_plan_info.tuned_ms (untuned
+ * plans after, in the given order) and move to the next plan when one's
+ * tasks are all handed out, so the plans fill each other's tails. Totals are
+ * exact 128-bit sums, divided by each plan's IEP over-count on the host.
+ * out[i] = count of plans[i] (host memory); GP_ERR_OVERFLOW if one does not
+ * fit in 64 bits. Blocking. Counts equal gp_count's bit for bit.
  */
 gp_status gp_count_batch(const gp_graph* g, const gp_plan* const* plans, int32_t np,
                          const gp_launch* launch, void* stream, uint64_t* out);
@@ -368,12 +396,13 @@ gp_status gp_batch_create(const gp_graph* g, const gp_plan* const* plans, int32_
 gp_status gp_batch_run(gp_batch* b, void* stream, uint64_t* out);
 
 /*
- * Pick the launch shape of a batch of these plans on g by measurement: one full
- * batched run per shape (64, 32 or 16 lanes per group x leaf mode 1, 3 or 4),
- * timed with HIP events on stream. *out receives the fastest shape (group and
- * leaf_mode set, other fields zero) for gp_count_batch / gp_batch_create;
- * *best_ms (may be null) its time. Blocking; costs nine full runs. Errors as
- * gp_count_batch.
+ * Pick the launch shape of a batch of these plans on g by measurement: one
+ * full batched run with every plan at its own launch shape, then one per
+ * common shape (64, 32 or 16 lanes per group x leaf mode 1, 3 or 4), timed
+ * with HIP events on stream. *out receives the fastest (all fields zero:
+ * each plan's own shape; else group and leaf_mode set) for gp_count_batch /
+ * gp_batch_create; *best_ms (may be null) its time. Blocking; costs ten
+ * full runs. Errors as gp_count_batch.
  */
 gp_status gp_batch_tune(const gp_graph* g, const gp_plan* const* plans, int32_t np, void* stream,
                         gp_launch* out, double* best_ms);
@@ -400,6 +429,9 @@ typedef struct {
                                chunk if longer) is rejected with GP_ERR_BUDGET, and so is
                                one whose sample has a wavefront run past max_query_ms / 4
                                (0 = off) */
+    int32_t iep;            /* queries are planned with gp_plan_opts.iep = iep: counting with
+                               inclusion-exclusion (Section IV-D) where a configuration allows
+                               it, which makes stars and trees cheap (default 1; 0 off) */
 } gp_server_opts;
 
 typedef struct {

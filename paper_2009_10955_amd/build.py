@@ -16,12 +16,12 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libgp.so")
 
 # (source, extra defines, object name): the counting kernel is instantiated
-# once per pattern size k in its own unit so the variants build in parallel
+# once per pattern size k, the batched kernel once per largest pattern size,
+# each in its own unit so the variants build in parallel
 SOURCES = [("api.cpp", [], "api.o"), ("planner.cpp", [], "planner.o"), ("tune.cpp", [], "tune.o"), ("server.cpp", [], "server.o"),
            ("graph.hip", [], "graph.o"), ("count.hip", [], "count.o"), ("list.hip", [], "list.o")] + [
     ("count_inst.hip", [f"-DGP_INST_K={k}"], f"count_k{k}.o") for k in range(2, 9)] + [
-    ("count_batch.hip", [f"-DGP_BATCH_G={g}", f"-DGP_BATCH_KMAX={k}", f"-DGP_BATCH_LEAF={l}"],
-     f"count_batch_g{g}_k{k}_l{l}.o") for g in (64, 32, 16) for k in (5, 6, 8) for l in (1, 3, 4)]
+    ("count_batch.hip", [f"-DGP_BATCH_KMAX={k}"], f"count_batch_k{k}.o") for k in (5, 6, 8)]
 ARCH = os.environ.get("GP_OFFLOAD_ARCH", "gfx950")
 
 

@@ -245,7 +245,7 @@ gp_status gp_plan_create(const int32_t* edges, int32_t k, int32_t e, const gp_st
     gp::Pattern pat;
     int rc = gp::parse_pattern(edges, k, e, &pat);
     if (rc) return rc;
-    if (o.max_states < 0 || o.max_sets < 0) return GP_ERR_ARG;
+    if (o.max_states < 0 || o.max_sets < 0 || o.iep < 0 || o.iep > GP_IEP_MAX_INNER) return GP_ERR_ARG;
     const int64_t max_states = o.max_states ? o.max_states : 4000000;
     const int32_t max_sets = o.max_sets ? o.max_sets : 100000;
 
@@ -342,7 +342,7 @@ gp_status gp_plan_create(const int32_t* edges, int32_t k, int32_t e, const gp_st
     size_t bo = 0, bs = 0;
     bool have = false;
     gp::Rel best_kept = 0;
-    int best_div = 0;
+    int best_div = 0, best_nin = 0;
     for (size_t i = 0; i < cand_orders.size(); ++i) {
         for (size_t j = 0; j < cand_sets.size(); ++j) {
             double c = gp::model_cost(pat, cand_orders[i], cand_sets[j], gs);
@@ -357,10 +357,16 @@ gp_status gp_plan_create(const int32_t* edges, int32_t k, int32_t e, const gp_st
                 else better = cuts > best_cuts;  // schedules/sets visited in order: earlier wins ties
             }
             gp::Rel kept = 0;
-            int div = 0;
+            int div = 0, nin = 0;
             if (better && o.iep) {
-                // IEP: only configurations whose over-count is the same for every embedding
-                div = gp::iep_setup(pat, auts, cand_orders[i], cand_sets[j], &kept);
+                // IEP over as many innermost levels as asked for and the
+                // schedule allows, fewer if needed: only configurations whose
+                // over-count is the same for every embedding
+                const int want = o.iep == 1 ? GP_IEP_MAX_INNER : o.iep;
+                for (int n = std::min(want, gp::iep_max_inner(pat, cand_orders[i])); n >= 2 && div <= 0; --n) {
+                    div = gp::iep_setup(pat, auts, cand_orders[i], cand_sets[j], n, &kept);
+                    nin = n;
+                }
                 if (div <= 0) better = false;
             }
             if (better) {
@@ -370,6 +376,7 @@ gp_status gp_plan_create(const int32_t* edges, int32_t k, int32_t e, const gp_st
                 bs = j;
                 best_kept = kept;
                 best_div = div;
+                best_nin = nin;
                 have = true;
             }
         }
@@ -397,7 +404,7 @@ gp_status gp_plan_create(const int32_t* edges, int32_t k, int32_t e, const gp_st
     }
     p->order = cand_orders[bo];
     p->set = cand_sets[bs];
-    rc = gp::compile_plan(pat, p->order, p->set, &p->desc, best_kept, best_div);
+    rc = gp::compile_plan(pat, p->order, p->set, &p->desc, best_kept, best_div, best_nin);
     if (rc) {
         delete p;
         return rc;
@@ -522,6 +529,12 @@ gp_status gp_count_traffic(const gp_graph* g, const gp_plan* p, const gp_launch*
     return count_to_host(g, p->desc, cfg, (hipStream_t)stream, nullptr, out, alg_bytes);
 }
 
+gp_status gp_check_sum(const uint64_t* values, int64_t n, uint64_t div, void* stream, uint64_t* out,
+                       uint32_t* flags) {
+    if (!out || !flags) return GP_ERR_ARG;
+    return gpint::check_sum(values, n, div, (hipStream_t)stream, out, flags);
+}
+
 gp_status gp_list(const gp_graph* g, const gp_plan* p, const gp_launch* launch, void* stream, int32_t* out,
                   uint64_t capacity, uint64_t* n_found) {
     if (!g || !p || !n_found || (capacity > 0 && !out)) return GP_ERR_ARG;
@@ -546,18 +559,46 @@ gp_status gp_list(const gp_graph* g, const gp_plan* p, const gp_launch* launch, 
 }
 
 namespace {
-// Device descriptors and per-plan leaf modes of a batch.
-gp_status batch_inputs(const gp_plan* const* plans, int32_t np, std::vector<GpPlanDesc>* descs,
-                       std::vector<int>* leafs) {
+// Device descriptors and per-plan launch shapes of a batch, in the order the
+// batch runs them: by measured (tuned) run time, longest first, so the light
+// plans fill the tail of the heavy ones; untimed plans keep their order after
+// the timed ones. slot[i] is where the caller's plan i runs.
+gp_status batch_inputs(const gp_graph* g, const gp_plan* const* plans, int32_t np, const gp_launch* launch,
+                       std::vector<GpPlanDesc>* descs, std::vector<gpint::LaunchCfg>* cfgs,
+                       std::vector<int>* slot, int* waves_per_cu) {
     if (!plans || np < 1 || np > 64) return GP_ERR_ARG;
-    descs->resize(np);
-    leafs->resize(np);
+    std::vector<int> ord(np);
     for (int i = 0; i < np; ++i) {
         if (!plans[i]) return GP_ERR_ARG;
-        if (plans[i]->desc.iep) return GP_ERR_UNSUPPORTED;  // the batched kernel enumerates every level
-        (*descs)[i] = plans[i]->desc;
-        (*leafs)[i] = plans[i]->launch.leaf;
+        ord[i] = i;
     }
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](int a, int b) { return plans[a]->tuned_ms > plans[b]->tuned_ms; });
+    descs->resize(np);
+    cfgs->resize(np);
+    slot->resize(np);
+    for (int r = 0; r < np; ++r) {
+        const int i = ord[r];
+        (*descs)[r] = plans[i]->desc;
+        (*cfgs)[r] = gpint::launch_for_plan(plans[i], launch, g->dg);
+        (*slot)[i] = r;
+    }
+    *waves_per_cu = launch && launch->waves_per_cu ? launch->waves_per_cu : 32;
+    if (*waves_per_cu < 1 || *waves_per_cu > 32) return GP_ERR_ARG;
+    return GP_OK;
+}
+
+// Counts of a finished batch from its result words (4 per plan, batch order).
+gp_status batch_counts(const std::vector<GpPlanDesc>& descs, const std::vector<int>& slot,
+                       const unsigned long long* res, uint64_t* out) {
+    const int np = (int)slot.size();
+    std::vector<uint64_t> tmp(np);
+    for (int i = 0; i < np; ++i) {
+        const int r = slot[i];
+        gp_status st = gpint::batch_result(descs[r], res + 4 * r, &tmp[i]);
+        if (st != GP_OK) return st;
+    }
+    for (int i = 0; i < np; ++i) out[i] = tmp[i];
     return GP_OK;
 }
 }  // namespace
@@ -566,36 +607,36 @@ gp_status gp_count_batch(const gp_graph* g, const gp_plan* const* plans, int32_t
                          const gp_launch* launch, void* stream, uint64_t* out) {
     if (!g || !out) return GP_ERR_ARG;
     std::vector<GpPlanDesc> descs;
-    std::vector<int> leafs;
-    gp_status st = batch_inputs(plans, np, &descs, &leafs);
+    std::vector<gpint::LaunchCfg> cfgs;
+    std::vector<int> slot;
+    int wpc = 32;
+    gp_status st = batch_inputs(g, plans, np, launch, &descs, &cfgs, &slot, &wpc);
     if (st != GP_OK) return st;
     DeviceGuard dgd(g->dg.device);
     hipStream_t s = (hipStream_t)stream;
-    gpint::LaunchCfg cfg = gpint::launch_for_plan(plans[0], launch, g->dg);
     gpint::BatchState bs;
-    st = gpint::batch_prepare(g->dg, descs.data(), leafs.data(), nullptr, nullptr, np, cfg, s, &bs);
+    st = gpint::batch_prepare(g->dg, descs.data(), cfgs.data(), nullptr, nullptr, np, wpc, s, &bs);
     if (st != GP_OK) return st;
-    std::vector<unsigned long long> h(3 * np, 0);
+    std::vector<unsigned long long> h(4 * np, 0);
     st = gpint::batch_enqueue(g->dg, bs, s);
     if (st == GP_OK &&
-        hipMemcpyAsync(h.data(), bs.result, sizeof(unsigned long long) * 3 * np, hipMemcpyDeviceToHost, s) !=
+        hipMemcpyAsync(h.data(), bs.result, sizeof(unsigned long long) * 4 * np, hipMemcpyDeviceToHost, s) !=
             hipSuccess)
         st = GP_ERR_HIP;
     if (hipStreamSynchronize(s) != hipSuccess && st == GP_OK) st = GP_ERR_HIP;
     gpint::batch_release(&bs);
     if (st != GP_OK) return st;
-    for (int i = 0; i < np; ++i)
-        if (h[3 * i + 1]) return GP_ERR_OVERFLOW;
-    for (int i = 0; i < np; ++i) out[i] = h[3 * i];
-    return GP_OK;
+    return batch_counts(descs, slot, h.data(), out);
 }
 
 gp_status gp_batch_create(const gp_graph* g, const gp_plan* const* plans, int32_t np,
                           const gp_launch* launch, void* stream, gp_batch** out) {
     if (!g || !out) return GP_ERR_ARG;
     std::vector<GpPlanDesc> descs;
-    std::vector<int> leafs;
-    gp_status st = batch_inputs(plans, np, &descs, &leafs);
+    std::vector<gpint::LaunchCfg> cfgs;
+    std::vector<int> slot;
+    int wpc = 32;
+    gp_status st = batch_inputs(g, plans, np, launch, &descs, &cfgs, &slot, &wpc);
     if (st != GP_OK) return st;
     DeviceGuard dgd(g->dg.device);
     hipStream_t s = (hipStream_t)stream;
@@ -603,21 +644,22 @@ gp_status gp_batch_create(const gp_graph* g, const gp_plan* const* plans, int32_
     if (!b) return GP_ERR_NOMEM;
     b->g = g;
     b->np = np;
-    gpint::LaunchCfg cfg = gpint::launch_for_plan(plans[0], launch, g->dg);
-    st = gpint::batch_prepare(g->dg, descs.data(), leafs.data(), nullptr, nullptr, np, cfg, s, &b->st);
+    b->descs = descs;
+    b->slot = slot;
+    st = gpint::batch_prepare(g->dg, descs.data(), cfgs.data(), nullptr, nullptr, np, wpc, s, &b->st);
     if (st != GP_OK) {
         delete b;
         return st;
     }
-    bool ok = hipHostMalloc((void**)&b->host_res, 3 * sizeof(unsigned long long) * np,
+    bool ok = hipHostMalloc((void**)&b->host_res, 4 * sizeof(unsigned long long) * np,
                             hipHostMallocDefault) == hipSuccess &&
               hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) == hipSuccess;
     if (ok) {
-        // capture: counter reset (fill kernels, no memset nodes) -> kernel -> D2H
+        // capture: counter and memo reset (fill kernels, no memset nodes) -> kernel -> D2H
         ok = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
         if (ok) {
             gp_status est = gpint::batch_enqueue(g->dg, b->st, b->cap_stream);
-            hipError_t ce = hipMemcpyAsync(b->host_res, b->st.result, 3 * sizeof(unsigned long long) * np,
+            hipError_t ce = hipMemcpyAsync(b->host_res, b->st.result, 4 * sizeof(unsigned long long) * np,
                                            hipMemcpyDeviceToHost, b->cap_stream);
             hipError_t ee = hipStreamEndCapture(b->cap_stream, &b->graph);
             ok = est == GP_OK && ce == hipSuccess && ee == hipSuccess &&
@@ -638,19 +680,12 @@ gp_status gp_batch_run(gp_batch* b, void* stream, uint64_t* out) {
     hipStream_t s = (hipStream_t)stream;
     GP_HIP_TRY(hipGraphLaunch(b->exec, s));
     GP_HIP_TRY(hipStreamSynchronize(s));
-    for (int i = 0; i < b->np; ++i)
-        if (b->host_res[3 * i + 1]) return GP_ERR_OVERFLOW;
-    for (int i = 0; i < b->np; ++i) out[i] = b->host_res[3 * i];
-    return GP_OK;
+    return batch_counts(b->descs, b->slot, b->host_res, out);
 }
 
 gp_status gp_batch_tune(const gp_graph* g, const gp_plan* const* plans, int32_t np, void* stream,
                         gp_launch* out, double* best_ms) {
     if (!g || !out) return GP_ERR_ARG;
-    std::vector<GpPlanDesc> descs;
-    std::vector<int> leafs;
-    gp_status st = batch_inputs(plans, np, &descs, &leafs);
-    if (st != GP_OK) return st;
     DeviceGuard dgd(g->dg.device);
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t a = nullptr, b = nullptr;
@@ -658,30 +693,39 @@ gp_status gp_batch_tune(const gp_graph* g, const gp_plan* const* plans, int32_t 
         if (a) (void)hipEventDestroy(a);
         return GP_ERR_HIP;
     }
+    gp_status st = GP_OK;
     double best = -1;
     gp_launch pick{};
-    for (int grp : {64, 32, 16}) {
+    // each plan at its own shape (all fields zero), then one shape for all
+    std::vector<gp_launch> shapes(1, gp_launch{});
+    for (int grp : {64, 32, 16})
         for (int lm : {1, 3, 4}) {
             gp_launch l{};
             l.group = grp;
             l.leaf_mode = lm;
-            gpint::LaunchCfg cfg = gpint::launch_for_plan(plans[0], &l, g->dg);
-            gpint::BatchState bs;
-            st = gpint::batch_prepare(g->dg, descs.data(), leafs.data(), nullptr, nullptr, np, cfg, s, &bs);
-            if (st != GP_OK) break;
-            float ms = 0;
-            if (hipEventRecord(a, s) != hipSuccess || gpint::batch_enqueue(g->dg, bs, s) != GP_OK ||
-                hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
-                hipEventElapsedTime(&ms, a, b) != hipSuccess)
-                st = GP_ERR_HIP;
-            gpint::batch_release(&bs);
-            if (st != GP_OK) break;
-            if (best < 0 || ms < best) {
-                best = ms;
-                pick = l;
-            }
+            shapes.push_back(l);
         }
+    for (const gp_launch& l : shapes) {
+        std::vector<GpPlanDesc> descs;
+        std::vector<gpint::LaunchCfg> cfgs;
+        std::vector<int> slot;
+        int wpc = 32;
+        st = batch_inputs(g, plans, np, &l, &descs, &cfgs, &slot, &wpc);
         if (st != GP_OK) break;
+        gpint::BatchState bs;
+        st = gpint::batch_prepare(g->dg, descs.data(), cfgs.data(), nullptr, nullptr, np, wpc, s, &bs);
+        if (st != GP_OK) break;
+        float ms = 0;
+        if (hipEventRecord(a, s) != hipSuccess || gpint::batch_enqueue(g->dg, bs, s) != GP_OK ||
+            hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+            hipEventElapsedTime(&ms, a, b) != hipSuccess)
+            st = GP_ERR_HIP;
+        gpint::batch_release(&bs);
+        if (st != GP_OK) break;
+        if (best < 0 || ms < best) {
+            best = ms;
+            pick = l;
+        }
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);

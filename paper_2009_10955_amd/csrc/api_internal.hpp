@@ -20,6 +20,7 @@ struct gp_plan {
     GpPlanDesc desc{};
     gp_plan_info info{};
     bool tuned = false;          // launch below was measured on a graph
+    double tuned_ms = 0;         // its measured (or estimated) full-run time
     gpint::LaunchCfg launch{};
 };
 
@@ -27,7 +28,9 @@ struct gp_batch {
     const gp_graph* g = nullptr;
     int np = 0;
     gpint::BatchState st;
-    unsigned long long* host_res = nullptr;  // pinned, 3*np
+    std::vector<GpPlanDesc> descs;           // in the caller's order
+    std::vector<int> slot;                   // caller's plan i runs as batch plan slot[i]
+    unsigned long long* host_res = nullptr;  // pinned, 4*np
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;

@@ -15,33 +15,15 @@ KernelFn pick_kernel_k5(int group, int leaf, int mode, bool iep);
 KernelFn pick_kernel_k6(int group, int leaf, int mode, bool iep);
 KernelFn pick_kernel_k7(int group, int leaf, int mode, bool iep);
 KernelFn pick_kernel_k8(int group, int leaf, int mode, bool iep);
-#define GP_DECL_BATCH(g, k, l) BatchFn batch_kernel_g##g##_k##k##_l##l();
-GP_DECL_BATCH(64, 5, 1) GP_DECL_BATCH(64, 6, 1) GP_DECL_BATCH(64, 8, 1)
-GP_DECL_BATCH(32, 5, 1) GP_DECL_BATCH(32, 6, 1) GP_DECL_BATCH(32, 8, 1)
-GP_DECL_BATCH(64, 5, 3) GP_DECL_BATCH(64, 6, 3) GP_DECL_BATCH(64, 8, 3)
-GP_DECL_BATCH(32, 5, 3) GP_DECL_BATCH(32, 6, 3) GP_DECL_BATCH(32, 8, 3)
-GP_DECL_BATCH(16, 5, 1) GP_DECL_BATCH(16, 6, 1) GP_DECL_BATCH(16, 8, 1)
-GP_DECL_BATCH(16, 5, 3) GP_DECL_BATCH(16, 6, 3) GP_DECL_BATCH(16, 8, 3)
-GP_DECL_BATCH(64, 5, 4) GP_DECL_BATCH(64, 6, 4) GP_DECL_BATCH(64, 8, 4)
-GP_DECL_BATCH(32, 5, 4) GP_DECL_BATCH(32, 6, 4) GP_DECL_BATCH(32, 8, 4)
-GP_DECL_BATCH(16, 5, 4) GP_DECL_BATCH(16, 6, 4) GP_DECL_BATCH(16, 8, 4)
-#undef GP_DECL_BATCH
+BatchFn batch_kernel_k5();
+BatchFn batch_kernel_k6();
+BatchFn batch_kernel_k8();
 
-BatchFn pick_batch_kernel(int group, int kmax, int leaf) {
-    const int km = kmax <= 5 ? 5 : (kmax <= 6 ? 6 : 8);
-    if (leaf == 4) {
-        if (group == 64) return km == 5 ? batch_kernel_g64_k5_l4() : (km == 6 ? batch_kernel_g64_k6_l4() : batch_kernel_g64_k8_l4());
-        if (group == 16) return km == 5 ? batch_kernel_g16_k5_l4() : (km == 6 ? batch_kernel_g16_k6_l4() : batch_kernel_g16_k8_l4());
-        return km == 5 ? batch_kernel_g32_k5_l4() : (km == 6 ? batch_kernel_g32_k6_l4() : batch_kernel_g32_k8_l4());
-    }
-    if (leaf == 3) {
-        if (group == 64) return km == 5 ? batch_kernel_g64_k5_l3() : (km == 6 ? batch_kernel_g64_k6_l3() : batch_kernel_g64_k8_l3());
-        if (group == 16) return km == 5 ? batch_kernel_g16_k5_l3() : (km == 6 ? batch_kernel_g16_k6_l3() : batch_kernel_g16_k8_l3());
-        return km == 5 ? batch_kernel_g32_k5_l3() : (km == 6 ? batch_kernel_g32_k6_l3() : batch_kernel_g32_k8_l3());
-    }
-    if (group == 64) return km == 5 ? batch_kernel_g64_k5_l1() : (km == 6 ? batch_kernel_g64_k6_l1() : batch_kernel_g64_k8_l1());
-    if (group == 16) return km == 5 ? batch_kernel_g16_k5_l1() : (km == 6 ? batch_kernel_g16_k6_l1() : batch_kernel_g16_k8_l1());
-    return km == 5 ? batch_kernel_g32_k5_l1() : (km == 6 ? batch_kernel_g32_k6_l1() : batch_kernel_g32_k8_l1());
+BatchFn pick_batch_kernel(int kmax) {
+    if (kmax <= 5) return batch_kernel_k5();
+    if (kmax <= 6) return batch_kernel_k6();
+    if (kmax <= 8) return batch_kernel_k8();
+    return nullptr;
 }
 
 namespace {
@@ -80,13 +62,30 @@ bool memo_eligible(const GpPlanDesc& d) {
     return (ll.inj & ~(uint32_t)d.lv[d.k - 2].parents) == 0;
 }
 
-// Divide an IEP total by its over-count; flag 2 if it does not divide.
-__global__ void iep_divide(unsigned long long* result, unsigned long long div) {
-    if (threadIdx.x == 0 && div > 0) {
-        const unsigned long long t = result[0];
-        if (t % div) result[1] |= 2ull;
-        result[0] = t / div;
+// The count's last step: the 128-bit total (queue[1], result[0]) divided by
+// the IEP over-count (1 for plain counts), with the overflow flag set only if
+// the quotient does not fit in 64 bits; check: flag a remainder (a whole
+// count must divide exactly).
+__global__ void finish_count(unsigned long long* result, const unsigned long long* queue, unsigned long long div,
+                             int check) {
+    if (threadIdx.x == 0) {
+        const unsigned long long flags = result[1];
+        finish128(&result[0], &result[1], queue[1], div);
+        if (!check) result[1] = (result[1] & ~2ull) | (flags & 2ull);
     }
+}
+
+// The counting kernels' accumulation on given values: each lane adds its
+// share with add_count (carries counted), the wavefronts sum exactly in 128
+// bits and publish into w[2] (low word) and w[1] (high word), as a count's
+// wavefronts publish into result[0] and queue[1].
+__global__ void sum_check_kernel(const unsigned long long* vals, int64_t n, unsigned long long* w) {
+    uint64_t acc = 0, carry = 0;
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step)
+        add_count(acc, vals[i], carry);
+    wave_sum128(acc, carry);
+    if (__lane_id() == 0) publish128(&w[2], &w[1], acc, carry);
 }
 }  // namespace
 }  // namespace gpcount
@@ -146,8 +145,8 @@ static const int2* pick_roots(const DeviceGraph& g, int root_cut, int64_t* n) {
 
 // Roots split into several tasks: the first `roots` of the (sampled) root
 // array, whose smaller endpoint is below 2^floor(log2(split_vertices)).
-// Per-root and byte-accounting counts stay one task per root, and so do
-// patterns with no level-2 loop (k <= 3, IEP at k = 4).
+// Per-root counts stay one task per root, and so do patterns with no level-2
+// loop (k <= 3, or IEP over every level after the root).
 struct SplitPlan {
     int64_t roots = 0;
     int ways = 1;
@@ -156,8 +155,8 @@ struct SplitPlan {
 static SplitPlan split_plan(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCfg& cfg, int mode,
                             int64_t n_roots, int64_t stride, int64_t offset) {
     SplitPlan sp;
-    const bool iep = d.iep != 0;
-    if (mode != MODE_PLAIN || d.k < 4 || (iep && d.k == 4) || cfg.split_ways <= 1 || cfg.split_vertices <= 0)
+    if (mode == MODE_PER_ROOT || d.k < 4 || (d.iep && d.iep == d.k - 2) || cfg.split_ways <= 1 ||
+        cfg.split_vertices <= 0)
         return sp;
     int i = 0;
     while (i < 31 && (int64_t(1) << (i + 1)) <= cfg.split_vertices) ++i;
@@ -168,8 +167,6 @@ static SplitPlan split_plan(const DeviceGraph& g, const GpPlanDesc& d, const Lau
     return sp;
 }
 
-static const int2* pick_roots(const DeviceGraph& g, int root_cut, int64_t* n);
-
 int64_t task_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCfg& cfg) {
     int64_t n = 0;
     (void)pick_roots(g, d.root_cut, &n);
@@ -177,9 +174,15 @@ int64_t task_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCfg& c
     return n + sp.roots * (sp.ways - 1);
 }
 
+namespace {
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+}  // namespace
+
 gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCfg& cfg,
                        hipStream_t stream, unsigned long long* result_dev,
-                       unsigned long long* per_root, bool account, unsigned long long* busy) {
+                       unsigned long long* per_root, bool account, unsigned long long* busy,
+                       const Workspace* ws) {
     if (cfg.group != 64 && cfg.group != 32 && cfg.group != 16 && cfg.group != 8) return GP_ERR_ARG;
     if (cfg.leaf < 1 || cfg.leaf > 4) return GP_ERR_ARG;
     if (cfg.waves_per_cu < 1 || cfg.waves_per_cu > 32 || cfg.chunk < 1) return GP_ERR_ARG;
@@ -207,44 +210,57 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
     const int waves_per_block = kBlock / 64;
     int64_t blocks = std::max<int64_t>(1, (int64_t)g.num_cus * cfg.waves_per_cu / waves_per_block);
     const int64_t groups_per_block = kBlock / group;
-    int64_t cap = std::max<int64_t>(1, g.deg2);
-    // keep scratch within a fixed budget: fewer resident groups if needed
-    const int64_t budget = int64_t(16) << 30;
-    if (d.nbuf > 0) {
-        int64_t per_block = groups_per_block * d.nbuf * cap * 4;
-        int64_t max_blocks = std::max<int64_t>(1, budget / per_block);
-        blocks = std::min(blocks, max_blocks);
+    const int64_t cap = std::max<int64_t>(1, g.deg2);
+    const int64_t per_block = d.nbuf > 0 ? groups_per_block * d.nbuf * cap * 4 : 0;
+    // keep scratch within a fixed budget (or the caller's workspace): fewer
+    // resident groups if needed
+    const int64_t budget = ws ? (int64_t)ws->bytes - (int64_t)kAlign : int64_t(16) << 30;
+    if (ws && budget < 0) return GP_ERR_ARG;
+    if (per_block > 0) {
+        if (ws && per_block > budget) return GP_ERR_NOMEM;  // not even one block's buffers fit
+        blocks = std::min(blocks, std::max<int64_t>(1, budget / per_block));
     }
     // a grid larger than the number of root tasks only adds idle groups
     int64_t need = (n_tasks + cfg.chunk - 1) / cfg.chunk;
     int64_t need_blocks = std::max<int64_t>(1, (need + groups_per_block - 1) / groups_per_block);
     blocks = std::min(blocks, need_blocks);
 
+    const size_t scratch_bytes = (size_t)(blocks * per_block);
+    // leaf mode 4's per-task memo: one word per hub per group, within 4 GiB
+    // (within what the workspace has left)
+    const int64_t memo_words = blocks * groups_per_block * (int64_t)g.n_hubs;
+    const int64_t memo_cap = ws ? budget - (int64_t)align_up(scratch_bytes) : (int64_t(4) << 30);
+    const bool use_memo = cfg.leaf == 4 && mode != MODE_PER_ROOT && !iep && g.n_hubs > 0 && memo_eligible(d) &&
+                          n_tasks < (int64_t(1) << 31) && memo_words * 8 <= memo_cap;
+
     int32_t* scratch = nullptr;
     unsigned long long* queue = nullptr;
     unsigned long long* memo = nullptr;
-    size_t scratch_bytes = d.nbuf > 0 ? (size_t)(blocks * groups_per_block * d.nbuf * cap * 4) : 0;
-    // leaf mode 4's per-task memo: one word per hub per group, within 4 GiB
-    const int64_t memo_words = blocks * groups_per_block * (int64_t)g.n_hubs;
-    const bool use_memo = cfg.leaf == 4 && mode != MODE_ACCOUNT && !iep && g.n_hubs > 0 && memo_eligible(d) &&
-                          n_tasks < (int64_t(1) << 31) && memo_words * 8 <= (int64_t(4) << 30);
-    GP_HIP_TRY(hipMallocAsync((void**)&queue, sizeof(unsigned long long) * 2, stream));
-    if (scratch_bytes) {
-        if (hipMallocAsync((void**)&scratch, scratch_bytes, stream) != hipSuccess) {
-            (void)hipFreeAsync(queue, stream);
-            return GP_ERR_NOMEM;
+    if (ws) {
+        char* base = (char*)ws->base;
+        queue = (unsigned long long*)base;
+        if (scratch_bytes) scratch = (int32_t*)(base + kAlign);
+        if (use_memo) memo = (unsigned long long*)(base + kAlign + align_up(scratch_bytes));
+    } else {
+        GP_HIP_TRY(hipMallocAsync((void**)&queue, sizeof(unsigned long long) * 2, stream));
+        if (scratch_bytes) {
+            if (hipMallocAsync((void**)&scratch, scratch_bytes, stream) != hipSuccess) {
+                (void)hipFreeAsync(queue, stream);
+                return GP_ERR_NOMEM;
+            }
+        }
+        if (use_memo) {
+            if (hipMallocAsync((void**)&memo, (size_t)memo_words * 8, stream) != hipSuccess) {
+                if (scratch) (void)hipFreeAsync(scratch, stream);
+                (void)hipFreeAsync(queue, stream);
+                return GP_ERR_NOMEM;
+            }
         }
     }
-    if (use_memo) {
-        if (hipMallocAsync((void**)&memo, (size_t)memo_words * 8, stream) != hipSuccess) {
-            if (scratch) (void)hipFreeAsync(scratch, stream);
-            (void)hipFreeAsync(queue, stream);
-            return GP_ERR_NOMEM;
-        }
+    if (use_memo)
         hipLaunchKernelGGL(zero_u64, dim3((unsigned)std::min<int64_t>(4096, (memo_words + 255) / 256)), dim3(256), 0,
                            stream, memo, memo_words);
-    }
-    hipLaunchKernelGGL(init_counters, dim3(1), dim3(64), 0, stream, queue, 1);
+    hipLaunchKernelGGL(init_counters, dim3(1), dim3(64), 0, stream, queue, 2);
     hipLaunchKernelGGL(init_counters, dim3(1), dim3(64), 0, stream, result_dev, account ? 3 : 2);
     if (busy) hipLaunchKernelGGL(init_counters, dim3(1), dim3(64), 0, stream, busy, 3);
 
@@ -271,13 +287,41 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
     a.memo = memo;
     a.chunk = cfg.chunk;
     if (n_tasks > 0) hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kBlock), 0, stream, d, a);
-    if (iep)
-        hipLaunchKernelGGL(iep_divide, dim3(1), dim3(64), 0, stream, result_dev, (unsigned long long)d.iep_div);
+    // a sample's total need not be a multiple of the over-count: its quotient
+    // is an estimate, not checked
+    const bool whole = cfg.root_stride == 1 && cfg.root_offset == 0 && !(busy && cfg.budget_ms > 0);
+    hipLaunchKernelGGL(finish_count, dim3(1), dim3(64), 0, stream, result_dev, queue,
+                       (unsigned long long)(iep ? d.iep_div : 1), whole ? 1 : 0);
     hipError_t le = hipGetLastError();
-    if (scratch) (void)hipFreeAsync(scratch, stream);
-    if (memo) (void)hipFreeAsync(memo, stream);
-    (void)hipFreeAsync(queue, stream);
+    if (!ws) {
+        if (scratch) (void)hipFreeAsync(scratch, stream);
+        if (memo) (void)hipFreeAsync(memo, stream);
+        (void)hipFreeAsync(queue, stream);
+    }
     if (le != hipSuccess) return GP_ERR_HIP;
+    return GP_OK;
+}
+
+gp_status check_sum(const uint64_t* values, int64_t n, uint64_t div, hipStream_t stream, uint64_t* out,
+                    uint32_t* flags) {
+    if (n < 0 || (n > 0 && !values) || div < 1) return GP_ERR_ARG;
+    unsigned long long* w = nullptr;  // {cursor (unused), high word, low word, flags}, then the values
+    GP_HIP_TRY(hipMallocAsync((void**)&w, sizeof(unsigned long long) * (4 + (size_t)n), stream));
+    unsigned long long h[4] = {0, 0, 0, 0};
+    hipError_t e = hipSuccess;
+    hipLaunchKernelGGL(init_counters, dim3(1), dim3(64), 0, stream, w, 4);
+    if (n > 0)
+        e = hipMemcpyAsync(w + 4, values, sizeof(unsigned long long) * (size_t)n, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(sum_check_kernel, dim3(4), dim3(kBlock), 0, stream, w + 4, n, w);
+        hipLaunchKernelGGL(finish_count, dim3(1), dim3(64), 0, stream, w + 2, w, (unsigned long long)div, 1);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(h, w, sizeof h, hipMemcpyDeviceToHost, stream);
+    (void)hipFreeAsync(w, stream);
+    if (hipStreamSynchronize(stream) != hipSuccess || e != hipSuccess) return GP_ERR_HIP;
+    *out = h[2];
+    *flags = (uint32_t)h[3];
     return GP_OK;
 }
 
@@ -291,80 +335,106 @@ void batch_release(BatchState* st) {
     (void)hipFree(st->descs);
     (void)hipFree(st->plans);
     (void)hipFree(st->scratch);
-    (void)hipFree(st->queue);
+    (void)hipFree(st->memo);
+    (void)hipFree(st->queues);
     (void)hipFree(st->result);
     *st = BatchState{};
 }
 
-// Per-plan task ranges and the launch geometry for np plans.
-static gp_status batch_layout(const DeviceGraph& g, const GpPlanDesc* descs, const int64_t* offsets,
-                              const int64_t* counts, int np, const LaunchCfg& cfg, BatchState* b,
+// A plan's shape inside a batch: IEP plans run in 64- or 32-lane groups,
+// others in 64, 32 or 16; leaf modes 1, 3 or 4 (2 runs as 1).
+static void batch_shape(const GpPlanDesc& d, const LaunchCfg& c, BatchPlan* bp) {
+    if (d.iep) bp->group = c.group >= 64 ? 64 : 32;
+    else bp->group = c.group >= 64 ? 64 : (c.group >= 32 ? 32 : 16);
+    bp->leaf = d.iep ? 1 : (c.leaf == 3 || c.leaf == 4 ? c.leaf : 1);
+    bp->chunk = std::max(1, c.chunk);
+}
+
+// Per-plan task ranges, shapes and the launch geometry for np plans.
+static gp_status batch_layout(const DeviceGraph& g, const GpPlanDesc* descs, const LaunchCfg* cfgs,
+                              const int64_t* offsets, const int64_t* counts, int np, BatchState* b,
                               std::vector<BatchPlan>* plans) {
     plans->resize(np);
-    int64_t total = 0;
     int32_t nbuf = 0;
+    int min_group = 64;
     b->kmax = 2;
+    int64_t tag_next = 1;  // memo tags of the eligible plans: disjoint ranges
+    bool any_memo = false;
     for (int i = 0; i < np; ++i) {
         int64_t n_all = 0;
         const int2* roots = pick_roots(g, descs[i].root_cut, &n_all);
         // offsets and counts are in the plan's task space (split roots count once per task)
-        const SplitPlan sp = descs[i].iep ? SplitPlan{} : split_plan(g, descs[i], cfg, MODE_PLAIN, n_all, 1, 0);
+        const SplitPlan sp = split_plan(g, descs[i], cfgs[i], MODE_PLAIN, n_all, 1, 0);
         const int64_t n_tasks = n_all + sp.roots * (sp.ways - 1);
         int64_t off = offsets ? offsets[i] : 0;
         int64_t cnt = counts ? counts[i] : n_tasks;
         if (off < 0 || cnt < 0) return GP_ERR_ARG;
         off = std::min(off, n_tasks);
         cnt = std::min(cnt, n_tasks - off);
-        (*plans)[i].roots = roots;
-        (*plans)[i].n_tasks = cnt;
-        (*plans)[i].task_begin = total;
-        (*plans)[i].task_offset = off;
-        (*plans)[i].split_roots = sp.roots;
-        (*plans)[i].split_ways = sp.ways;
-        (*plans)[i].leaf = b->leaf;
-        total += cnt;
+        BatchPlan& bp = (*plans)[i];
+        std::memset(&bp, 0, sizeof bp);
+        bp.roots = roots;
+        bp.n_tasks = cnt;
+        bp.task_offset = off;
+        bp.split_roots = sp.roots;
+        bp.split_ways = sp.ways;
+        batch_shape(descs[i], cfgs[i], &bp);
+        bp.tag_base = 0;
+        if (bp.leaf == 4 && !descs[i].iep && g.n_hubs > 0 && memo_eligible(descs[i]) &&
+            tag_next + n_all < (int64_t(1) << 32) - 1) {
+            bp.tag_base = (uint32_t)tag_next - 1;  // tags tag_base + root + 1 >= tag_next
+            tag_next += n_all;
+            any_memo = true;
+        }
+        min_group = std::min(min_group, bp.group);
         nbuf = std::max(nbuf, descs[i].nbuf);
         b->kmax = std::max(b->kmax, (int)descs[i].k);
     }
     b->np = np;
-    b->total_tasks = total;
     b->nbuf = nbuf;
+    b->slots_per_wave = 64 / min_group;
+    b->use_memo = any_memo;
     return GP_OK;
 }
 
-static int64_t batch_blocks(const DeviceGraph& g, const BatchState& b, int waves_per_cu, int32_t nbuf,
-                            int64_t total) {
-    const int64_t groups_per_block = kBlock / b.group;
-    int64_t blocks = std::max<int64_t>(1, (int64_t)g.num_cus * waves_per_cu / (kBlock / 64));
+// Wavefront-resident blocks: the device's share, within the scratch and memo
+// budgets. Scratch per wavefront: slots_per_wave groups x nbuf x cap int32.
+static int64_t batch_blocks(const DeviceGraph& g, int waves_per_cu, int slots_per_wave, int32_t nbuf, int64_t cap,
+                            bool memo) {
+    const int waves_per_block = kBlock / 64;
+    int64_t blocks = std::max<int64_t>(1, (int64_t)g.num_cus * waves_per_cu / waves_per_block);
     if (nbuf > 0) {
         const int64_t budget = int64_t(16) << 30;
-        blocks = std::min(blocks, std::max<int64_t>(1, budget / (groups_per_block * nbuf * b.cap * 4)));
+        blocks = std::min(blocks, std::max<int64_t>(1, budget / ((int64_t)waves_per_block * slots_per_wave * nbuf *
+                                                                  cap * 4)));
     }
-    const int64_t need = (total + b.chunk - 1) / b.chunk;
-    return std::min(blocks, std::max<int64_t>(1, (need + groups_per_block - 1) / groups_per_block));
+    if (memo && g.n_hubs > 0) {
+        const int64_t budget = int64_t(4) << 30;
+        blocks = std::min(blocks, std::max<int64_t>(1, budget / ((int64_t)waves_per_block * slots_per_wave *
+                                                                  g.n_hubs * 8)));
+    }
+    return blocks;
 }
 
-gp_status batch_prepare(const DeviceGraph& g, const GpPlanDesc* descs, const int* leafs,
-                        const int64_t* offsets, const int64_t* counts, int np,
-                        const LaunchCfg& cfg, hipStream_t stream, BatchState* st) {
-    (void)leafs;
+gp_status batch_prepare(const DeviceGraph& g, const GpPlanDesc* descs, const LaunchCfg* cfgs,
+                        const int64_t* offsets, const int64_t* counts, int np, int waves_per_cu,
+                        hipStream_t stream, BatchState* st) {
     if (np < 1 || np > kBatchMaxPlans) return GP_ERR_ARG;
     BatchState b;
-    b.group = cfg.group >= 64 ? 64 : (cfg.group >= 32 || cfg.group <= 0 ? 32 : 16);
-    b.leaf = cfg.leaf == 3 || cfg.leaf == 4 ? cfg.leaf : 1;
-    b.chunk = std::max(1, cfg.chunk);
     b.cap = std::max<int64_t>(1, g.deg2);
     std::vector<BatchPlan> plans;
-    gp_status rc = batch_layout(g, descs, offsets, counts, np, cfg, &b, &plans);
+    gp_status rc = batch_layout(g, descs, cfgs, offsets, counts, np, &b, &plans);
     if (rc != GP_OK) return rc;
-    const int64_t groups_per_block = kBlock / b.group;
-    b.blocks = batch_blocks(g, b, cfg.waves_per_cu, b.nbuf, b.total_tasks);
+    b.blocks = batch_blocks(g, waves_per_cu, b.slots_per_wave, b.nbuf, b.cap, b.use_memo);
+    const int64_t waves = b.blocks * (kBlock / 64);
+    b.memo_words = b.use_memo ? waves * b.slots_per_wave * (int64_t)g.n_hubs : 0;
     if (hipMalloc(&b.descs, sizeof(GpPlanDesc) * np) != hipSuccess ||
         hipMalloc(&b.plans, sizeof(BatchPlan) * np) != hipSuccess ||
-        hipMalloc((void**)&b.queue, sizeof(unsigned long long)) != hipSuccess ||
-        hipMalloc((void**)&b.result, 3 * sizeof(unsigned long long) * np) != hipSuccess ||
+        hipMalloc((void**)&b.queues, sizeof(unsigned long long) * np) != hipSuccess ||
+        hipMalloc((void**)&b.result, 4 * sizeof(unsigned long long) * np) != hipSuccess ||
         (b.nbuf > 0 &&
-         hipMalloc((void**)&b.scratch, (size_t)(b.blocks * groups_per_block * b.nbuf * b.cap * 4)) != hipSuccess))
+         hipMalloc((void**)&b.scratch, (size_t)(waves * b.slots_per_wave * b.nbuf * b.cap * 4)) != hipSuccess) ||
+        (b.memo_words > 0 && hipMalloc((void**)&b.memo, (size_t)b.memo_words * 8) != hipSuccess))
         rc = GP_ERR_NOMEM;
     if (rc == GP_OK &&
         (hipMemcpyAsync(b.descs, descs, sizeof(GpPlanDesc) * np, hipMemcpyHostToDevice, stream) != hipSuccess ||
@@ -381,54 +451,59 @@ gp_status batch_prepare(const DeviceGraph& g, const GpPlanDesc* descs, const int
 }
 
 gp_status batch_enqueue(const DeviceGraph& g, const BatchState& st, hipStream_t stream) {
-    BatchFn fn = pick_batch_kernel(st.group, st.kmax, st.leaf);
-    hipLaunchKernelGGL(init_counters, dim3(1), dim3(64), 0, stream, st.queue, 1);
-    for (int i = 0; i < 3 * st.np; i += 64)
+    BatchFn fn = pick_batch_kernel(st.kmax);
+    if (!fn) return GP_ERR_UNSUPPORTED;
+    for (int i = 0; i < st.np; i += 64)
+        hipLaunchKernelGGL(init_counters, dim3(1), dim3(64), 0, stream, st.queues + i, std::min(64, st.np - i));
+    for (int i = 0; i < 4 * st.np; i += 64)
         hipLaunchKernelGGL(init_counters, dim3(1), dim3(64), 0, stream, st.result + i,
-                           std::min(64, 3 * st.np - i));
+                           std::min(64, 4 * st.np - i));
+    if (st.memo_words > 0)
+        hipLaunchKernelGGL(zero_u64, dim3((unsigned)std::min<int64_t>(4096, (st.memo_words + 255) / 256)), dim3(256),
+                           0, stream, st.memo, st.memo_words);
     BatchArgs a;
     a.row_ptr = g.row_ptr;
     a.col = g.col;
     a.descs = (const GpPlanDesc*)st.descs;
     a.plans = (const BatchPlan*)st.plans;
     a.np = st.np;
-    a.total_tasks = st.total_tasks;
     a.hub_bits = g.hub_bits;
     a.hub_words = g.hub_words;
     a.n_hubs = g.n_hubs;
     a.scratch = st.scratch;
     a.buf_cap = st.cap;
     a.nbuf = st.nbuf;
-    a.queue = st.queue;
+    a.slots_per_wave = st.slots_per_wave;
+    a.memo = st.memo_words > 0 ? st.memo : nullptr;
+    a.queues = st.queues;
     a.result = st.result;
-    a.chunk = st.chunk;
-    if (st.total_tasks > 0)
-        hipLaunchKernelGGL(fn, dim3((unsigned)st.blocks), dim3(kBlock), 0, stream, a);
+    hipLaunchKernelGGL(fn, dim3((unsigned)st.blocks), dim3(kBlock), 0, stream, a);
     return hipGetLastError() == hipSuccess ? GP_OK : GP_ERR_HIP;
 }
 
-gp_status arena_create(const DeviceGraph& g, int nbuf_cap, const LaunchCfg& cfg, BatchArena* ar) {
+gp_status arena_create(const DeviceGraph& g, int nbuf_cap, int waves_per_cu, int min_group, BatchArena* ar) {
     BatchArena a;
-    a.cfg = cfg;
+    a.waves_per_cu = waves_per_cu;
     BatchState& b = a.st;
-    b.group = cfg.group >= 64 ? 64 : (cfg.group >= 32 || cfg.group <= 0 ? 32 : 16);
-    b.leaf = cfg.leaf == 3 || cfg.leaf == 4 ? cfg.leaf : 1;
-    b.chunk = std::max(1, cfg.chunk);
     b.cap = std::max<int64_t>(1, g.deg2);
+    a.min_group = min_group >= 64 ? 64 : (min_group >= 32 ? 32 : 16);
     a.nbuf_cap = std::max(0, std::min(nbuf_cap, GP_DESC_MAX_BUILDS));
-    a.blocks_cap = batch_blocks(g, b, cfg.waves_per_cu, a.nbuf_cap, INT64_MAX / 4);
-    const int64_t groups_per_block = kBlock / b.group;
+    // room for the smallest group width and for the memo of leaf-4 plans
+    a.blocks_cap = batch_blocks(g, waves_per_cu, 64 / a.min_group, a.nbuf_cap, b.cap, true);
+    const int64_t waves = a.blocks_cap * (kBlock / 64);
+    a.memo_words_cap = g.n_hubs > 0 ? waves * (64 / a.min_group) * (int64_t)g.n_hubs : 0;
     bool ok = hipMalloc(&b.descs, sizeof(GpPlanDesc) * kBatchMaxPlans) == hipSuccess &&
               hipMalloc(&b.plans, sizeof(BatchPlan) * kBatchMaxPlans) == hipSuccess &&
-              hipMalloc((void**)&b.queue, sizeof(unsigned long long)) == hipSuccess &&
-              hipMalloc((void**)&b.result, 3 * sizeof(unsigned long long) * kBatchMaxPlans) == hipSuccess &&
+              hipMalloc((void**)&b.queues, sizeof(unsigned long long) * kBatchMaxPlans) == hipSuccess &&
+              hipMalloc((void**)&b.result, 4 * sizeof(unsigned long long) * kBatchMaxPlans) == hipSuccess &&
               (a.nbuf_cap == 0 ||
                hipMalloc((void**)&b.scratch,
-                         (size_t)(a.blocks_cap * groups_per_block * a.nbuf_cap * b.cap * 4)) == hipSuccess) &&
+                         (size_t)(waves * (64 / a.min_group) * a.nbuf_cap * b.cap * 4)) == hipSuccess) &&
+              (a.memo_words_cap == 0 || hipMalloc((void**)&b.memo, (size_t)a.memo_words_cap * 8) == hipSuccess) &&
               hipHostMalloc((void**)&a.h_descs, sizeof(GpPlanDesc) * kBatchMaxPlans, hipHostMallocDefault) ==
                   hipSuccess &&
               hipHostMalloc(&a.h_plans, sizeof(BatchPlan) * kBatchMaxPlans, hipHostMallocDefault) == hipSuccess &&
-              hipHostMalloc((void**)&a.h_result, 3 * sizeof(unsigned long long) * kBatchMaxPlans,
+              hipHostMalloc((void**)&a.h_result, 4 * sizeof(unsigned long long) * kBatchMaxPlans,
                             hipHostMallocDefault) == hipSuccess;
     if (!ok) {
         arena_release(&a);
@@ -438,20 +513,28 @@ gp_status arena_create(const DeviceGraph& g, int nbuf_cap, const LaunchCfg& cfg,
     return GP_OK;
 }
 
-gp_status arena_launch(const DeviceGraph& g, BatchArena* ar, const GpPlanDesc* descs, const int64_t* offsets,
-                       const int64_t* counts, int np, hipStream_t stream) {
+gp_status arena_launch(const DeviceGraph& g, BatchArena* ar, const GpPlanDesc* descs, const LaunchCfg* cfgs,
+                       const int64_t* offsets, const int64_t* counts, int np, hipStream_t stream) {
     if (np < 1 || np > kBatchMaxPlans) return GP_ERR_ARG;
     BatchState& b = ar->st;
     std::vector<BatchPlan> plans;
-    gp_status rc = batch_layout(g, descs, offsets, counts, np, ar->cfg, &b, &plans);
+    gp_status rc = batch_layout(g, descs, cfgs, offsets, counts, np, &b, &plans);
     if (rc != GP_OK) return rc;
     if (b.nbuf > ar->nbuf_cap) return GP_ERR_NOMEM;
-    // the scratch was carved for nbuf_cap slots per group; any smaller nbuf fits
-    b.blocks = std::min(ar->blocks_cap, batch_blocks(g, b, ar->cfg.waves_per_cu, b.nbuf, b.total_tasks));
+    if (b.slots_per_wave > 64 / ar->min_group) return GP_ERR_ARG;
+    // the scratch and memo were carved for the arena's largest shape; any smaller one fits
+    b.slots_per_wave = 64 / ar->min_group;
+    b.blocks = std::min(ar->blocks_cap, batch_blocks(g, ar->waves_per_cu, b.slots_per_wave, b.nbuf, b.cap, b.use_memo));
     if (b.nbuf > 0) {
-        const int64_t groups_per_block = kBlock / b.group;
-        const int64_t fit = ar->blocks_cap * groups_per_block * ar->nbuf_cap / (groups_per_block * b.nbuf);
+        const int64_t fit = ar->blocks_cap * ar->nbuf_cap / b.nbuf;
         b.blocks = std::min(b.blocks, std::max<int64_t>(1, fit));
+    }
+    const int64_t waves = b.blocks * (kBlock / 64);
+    b.memo_words = b.use_memo ? std::min(ar->memo_words_cap, waves * b.slots_per_wave * (int64_t)g.n_hubs) : 0;
+    if (b.use_memo && b.memo_words < waves * b.slots_per_wave * (int64_t)g.n_hubs) {
+        // no room for every wave's table: run the leaf-4 plans without the memo
+        for (auto& bp : plans) bp.tag_base = 0;
+        b.memo_words = 0;
     }
     std::memcpy(ar->h_descs, descs, sizeof(GpPlanDesc) * np);
     std::memcpy(ar->h_plans, plans.data(), sizeof(BatchPlan) * np);
@@ -459,8 +542,20 @@ gp_status arena_launch(const DeviceGraph& g, BatchArena* ar, const GpPlanDesc* d
     GP_HIP_TRY(hipMemcpyAsync(b.plans, ar->h_plans, sizeof(BatchPlan) * np, hipMemcpyHostToDevice, stream));
     rc = batch_enqueue(g, b, stream);
     if (rc != GP_OK) return rc;
-    GP_HIP_TRY(hipMemcpyAsync(ar->h_result, b.result, 3 * sizeof(unsigned long long) * np, hipMemcpyDeviceToHost,
+    GP_HIP_TRY(hipMemcpyAsync(ar->h_result, b.result, 4 * sizeof(unsigned long long) * np, hipMemcpyDeviceToHost,
                               stream));
+    return GP_OK;
+}
+
+gp_status batch_result(const GpPlanDesc& d, const unsigned long long* r, uint64_t* out) {
+    unsigned __int128 t = ((unsigned __int128)r[3] << 64) | (unsigned __int128)r[0];
+    const uint64_t div = d.iep ? (uint64_t)d.iep_div : 1;
+    if (div > 1) {
+        if (t % div) return GP_ERR_INTERNAL;
+        t /= div;
+    }
+    if (t >> 64) return GP_ERR_OVERFLOW;
+    *out = (uint64_t)t;
     return GP_OK;
 }
 

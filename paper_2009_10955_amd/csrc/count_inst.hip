@@ -23,8 +23,7 @@ template <int K, int G>
 KernelFn pick_leaf(int leaf, int mode) {
     if (leaf == 2) return pick_mode<K, G, 2>(mode);
     if (leaf == 3 && K >= 5) return pick_mode<K, G, (K >= 5 ? 3 : 1)>(mode);
-    // leaf mode 4 counts the same work as leaf mode 1, so byte accounting uses 1
-    if (leaf == 4 && K >= 4 && mode != MODE_ACCOUNT) return pick_mode<K, G, (K >= 4 ? 4 : 1)>(mode);
+    if (leaf == 4 && K >= 4) return pick_mode<K, G, (K >= 4 ? 4 : 1)>(mode);
     return pick_mode<K, G, 1>(mode);
 }
 }  // namespace
@@ -34,7 +33,7 @@ KernelFn pick_leaf(int leaf, int mode) {
 
 KernelFn GP_CAT(pick_kernel_k, GP_INST_K)(int group, int leaf, int mode, bool iep) {
     if (iep) {
-        // IEP stops at level k-3, so the leaf mode does not apply
+        // an IEP search stops at the last outer level, so the leaf mode does not apply
         if constexpr (GP_INST_K >= 4) {
             return group == 64 ? pick_mode<GP_INST_K, 64, 1, true>(mode)
                                : pick_mode<GP_INST_K, 32, 1, true>(mode);

@@ -5,7 +5,9 @@
 // of Section II-B / IV-B with candidate sets formed by intersecting sorted
 // neighbor lists and cut by the restrictions (the generated code of Fig.
 // pseudocode_performance), with every level's injectivity enforced
-// (Section II-A requires a bijection).
+// (Section II-A requires a bijection). Optionally the innermost 2 to 4
+// pairwise non-adjacent levels are not enumerated but counted by
+// inclusion-exclusion (Section IV-D, Algorithm 2).
 //
 // How it maps to the machine:
 //   * Tasks are root edges (v0, v1) = the first two loops fused, taken from a
@@ -31,8 +33,13 @@
 //     hub's list is one word load.
 //   * The last level is never enumerated: its count is
 //     |C ∩ [lo, hi)| minus the earlier bound vertices that fall in it.
-//   * Counts: uint64 per lane, wavefront tree reduction with carry detection,
-//     one atomic per wavefront; wrap-around sets the overflow flag.
+//   * Counts: a 64-bit total and a carry count per lane, an exact 128-bit
+//     wavefront sum, one pair of atomics per wavefront into a 128-bit device
+//     total; a last step divides it by the IEP over-count and flags a
+//     quotient that does not fit in 64 bits.
+//   * Byte accounting (MODE_ACCOUNT) is the same search, leaf mode and memo
+//     with a per-lane byte counter added where memory is touched: it measures
+//     the bytes of the path the timed launch takes.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -45,9 +52,12 @@ using namespace gpdev;
 
 constexpr int kBlock = 256;
 
-// Kernel modes: plain count, per-root counts, or accounting of the
-// algorithmic bytes of the paper's cost model (never timed).
+// Kernel modes: plain count, per-root counts, or accounting of the bytes the
+// search reads and writes (never timed).
 enum { MODE_PLAIN = 0, MODE_PER_ROOT = 1, MODE_ACCOUNT = 2 };
+
+// Inclusion-exclusion over at most this many innermost levels.
+constexpr int kIepMaxN = GP_IEP_MAX_INNER;
 
 struct CountArgs {
     const int64_t* row_ptr;
@@ -68,8 +78,8 @@ struct CountArgs {
     int32_t n_hubs;
     int32_t* scratch;
     int64_t buf_cap;
-    unsigned long long* queue;
-    unsigned long long* result;    // {count, overflow, algorithmic bytes}
+    unsigned long long* queue;     // {task cursor, high word of the 128-bit total}
+    unsigned long long* result;    // {count (low word), flags, bytes}
     unsigned long long* per_root;  // optional, indexed by CSR entry of (v0, v1)
     // optional {sum over wavefronts of active clock ticks, wavefronts, longest
     // chunk of tasks in ticks}: the balanced run time of a sample and its tail
@@ -85,17 +95,50 @@ struct CountArgs {
 
 typedef void (*KernelFn)(GpPlanDesc, CountArgs);
 
-// Batched launch: one entry per plan, in task order.
+// Batched launch: one entry per plan. Each plan has its own launch shape
+// (lanes per group, leaf mode, tasks per grab) and its own task cursor.
 constexpr int kBatchMaxPlans = 64;
 
 struct BatchPlan {
     const int2* roots;    // this plan's whole root array (cut already applied)
     int64_t n_tasks;      // tasks of this plan in the launch
-    int64_t task_begin;   // first global task index of this plan
     int64_t task_offset;  // where in the plan's own task space the launch starts
     int64_t split_roots;  // as in CountArgs: the first split_roots roots run as
     int32_t split_ways;   // split_ways tasks each
-    int32_t leaf;         // 1 or 3 (flattened last two levels)
+    int32_t group;        // lanes per group: 64, 32 or 16
+    int32_t leaf;         // 1, 3 or 4
+    int32_t chunk;        // tasks per group per grab
+    uint32_t tag_base;    // leaf-4 memo tags are tag_base + root + 1; 0: no memo
+    int32_t pad;
+};
+
+struct BatchArgs {
+    const int64_t* row_ptr;
+    const int32_t* col;
+    const GpPlanDesc* descs;  // device, np entries
+    const BatchPlan* plans;   // device, np entries, in the order waves take them
+    int32_t np;
+    const uint32_t* hub_bits;
+    int64_t hub_words;
+    int32_t n_hubs;
+    int32_t* scratch;        // per wavefront: slots_per_wave groups x nbuf slots x buf_cap
+    int64_t buf_cap;
+    int32_t nbuf;            // buffer slots per group (max over plans)
+    int32_t slots_per_wave;  // 64 / (the smallest group of any plan)
+    unsigned long long* memo;     // per wavefront: slots_per_wave x n_hubs words (or null)
+    unsigned long long* queues;   // np task cursors
+    unsigned long long* result;   // per plan {count low word, flags, busy clock ticks, high word}
+};
+
+typedef void (*BatchFn)(BatchArgs);
+
+// Where a group's root tasks come from.
+struct TaskSpace {
+    const int2* roots;
+    int64_t offset, stride;  // root r is roots[offset + r * stride]
+    int64_t split_roots;     // task -> root as in CountArgs
+    int32_t split_ways;
+    uint32_t tag_base;       // memo tag of root r: tag_base + r + 1
 };
 
 // Root of task t, and the level-2 slice it binds: the first split_roots roots
@@ -113,26 +156,6 @@ __device__ __forceinline__ int64_t task_root(int64_t t, int64_t split_roots, int
     sJ = 1;
     return t - split_tasks + split_roots;
 }
-
-struct BatchArgs {
-    const int64_t* row_ptr;
-    const int32_t* col;
-    const GpPlanDesc* descs;  // device, np entries
-    const BatchPlan* plans;   // device, np entries
-    int32_t np;
-    int64_t total_tasks;
-    const uint32_t* hub_bits;
-    int64_t hub_words;
-    int32_t n_hubs;
-    int32_t* scratch;
-    int64_t buf_cap;
-    int32_t nbuf;  // buffer slots per group (max over plans)
-    unsigned long long* queue;
-    unsigned long long* result;  // {count, overflow, busy clock ticks} per plan
-    int32_t chunk;
-};
-
-typedef void (*BatchFn)(BatchArgs);
 
 // Values equal in every lane of a group. With 64-lane groups they are
 // wavefront-uniform: readfirstlane lets the compiler keep them, and what is
@@ -169,14 +192,14 @@ struct Ctx {
     int32_t* bufs;
     int64_t cap;
     int32_t* lens;  // LDS: length per buffer slot
-    uint64_t* bytes;  // accounting mode: per-lane algorithmic bytes
+    uint64_t* bytes;  // accounting mode: per-lane bytes
     const uint32_t* hub_bits;
     int64_t hub_words;
     int32_t n_hubs;
     int32_t sj, sJ;     // level-2 slice of the current task: candidates sj, sj + sJ, ...
     uint64_t deadline;  // clock tick after which every search loop stops (0: none)
     unsigned long long* memo;  // this group's last-level memo (null: none)
-    uint32_t tag;              // current root + 1, the memo's validity tag
+    uint32_t tag;              // memo validity tag of the current root
     Group<G> g;
 
     __device__ __forceinline__ bool expired() const {
@@ -230,15 +253,104 @@ __device__ __forceinline__ bool inj_hit(uint32_t inj, const int32_t (&v)[K], int
     return hit;
 }
 
-__device__ __forceinline__ void add_count(uint64_t& acc, uint64_t c, bool& ovf) {
-    uint64_t s = acc + c;
-    ovf |= (s < acc);
+// acc += c, counting wrap-arounds of the low word in carry: (carry, acc) is
+// the lane's exact 128-bit total.
+__device__ __forceinline__ void add_count(uint64_t& acc, uint64_t c, uint64_t& carry) {
+    const uint64_t s = acc + c;
+    carry += (s < acc) ? 1u : 0u;
     acc = s;
 }
 
-// Algorithmic bytes of one binary search in a sorted list of n int32.
+// (carry, acc) += (hi, lo).
+__device__ __forceinline__ void add_count128(uint64_t& acc, uint64_t& carry, uint64_t lo, uint64_t hi) {
+    const uint64_t s = acc + lo;
+    carry += hi + ((s < acc) ? 1u : 0u);
+    acc = s;
+}
+
+// Wavefront sum of the lanes' 128-bit totals (hi, lo); every lane gets it.
+__device__ __forceinline__ void wave_sum128(uint64_t& lo, uint64_t& hi) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const uint64_t tlo = __shfl_xor(lo, off, 64);
+        const uint64_t thi = __shfl_xor(hi, off, 64);
+        const uint64_t u = lo + tlo;
+        hi += thi + (u < lo ? 1u : 0u);
+        lo = u;
+    }
+}
+
+// Add a 128-bit value to a device-wide total held as two words: the low word
+// at *lo_word, the high word at *hi_word. Called by one lane.
+__device__ __forceinline__ void publish128(unsigned long long* lo_word, unsigned long long* hi_word, uint64_t lo,
+                                           uint64_t hi) {
+    if (lo) {
+        const unsigned long long old = atomicAdd(lo_word, (unsigned long long)lo);
+        hi += (old + lo < old) ? 1u : 0u;
+    }
+    if (hi) atomicAdd(hi_word, (unsigned long long)hi);
+}
+
+// The end of every count: the 128-bit total (hi, *lo_word) divided by div
+// (the IEP over-count, 1 otherwise). *lo_word receives the quotient's low 64
+// bits; flags: bit 0 if the quotient does not fit in 64 bits, bit 1 if div
+// does not divide the total (an internal error). Shift-and-subtract long
+// division by one lane: it runs once per count.
+__device__ __forceinline__ void finish128(unsigned long long* lo_word, unsigned long long* flags, uint64_t hi,
+                                          uint64_t div) {
+    const uint64_t lo = *lo_word;
+    if (div <= 1) {
+        if (hi) *flags |= 1ull;
+        return;
+    }
+    uint64_t qhi = 0, qlo = 0, r = 0;
+    for (int i = 127; i >= 0; --i) {
+        const uint64_t bit = i >= 64 ? (hi >> (i - 64)) & 1u : (lo >> i) & 1u;
+        const bool top = (r >> 63) != 0;  // r < div < 2^64, so 2r + bit may need 65 bits
+        r = (r << 1) | bit;
+        if (top || r >= div) {
+            r -= div;
+            if (i >= 64) qhi |= 1ull << (i - 64);
+            else qlo |= 1ull << i;
+        }
+    }
+    if (r) *flags |= 2ull;
+    if (qhi) *flags |= 1ull;
+    *lo_word = qlo;
+}
+
+// Bytes read by one binary search in a sorted list of n int32.
 __device__ __forceinline__ uint64_t probe_bytes(int32_t n) {
     return 4ull * (uint64_t)(32 - __clz(n > 0 ? n : 1));
+}
+// Bytes of one membership test in s: a bitmap word, or a binary search.
+__device__ __forceinline__ uint64_t test_bytes(const Set& s) {
+    return s.bits ? 4ull : probe_bytes(s.n);
+}
+// Bytes of cutting s to [lo, hi): one binary search per bound applied.
+__device__ __forceinline__ uint64_t cut_bytes(const Set& s, int32_t lo, int32_t hi) {
+    return probe_bytes(s.n) * (uint64_t)((lo > 0) + (hi < 0x7fffffff));
+}
+// Bytes of a test-based intersection (group or galloping): every element of
+// the smaller operand read and tested in the larger one.
+__device__ __forceinline__ uint64_t probe_isect_bytes(Set a, Set b) {
+    if (a.n > b.n) {
+        const Set t = a;
+        a = b;
+        b = t;
+    }
+    return (uint64_t)a.n * (4ull + test_bytes(b));
+}
+// Bytes of intersect_count_serial: bitmap tests, galloping or a merge.
+__device__ __forceinline__ uint64_t serial_isect_bytes(Set a, Set b) {
+    if (a.n > b.n) {
+        const Set t = a;
+        a = b;
+        b = t;
+    }
+    if (a.n == 0) return 0;
+    if (b.bits || a.n * 16 < b.n) return probe_isect_bytes(a, b);
+    return 4ull * (uint64_t)(a.n + b.n);
 }
 
 __device__ __forceinline__ void group_fence() {
@@ -257,11 +369,13 @@ __device__ __forceinline__ void run_builds(const GpPlanDesc& d, const Ctx<G>& c,
         bounds<K>(b.hi_src, b.lo_src, v, lo, hi);
         Set A = b.src_buf >= 0 ? c.buf_u(b.src_buf) : c.nbr_u(pick<K>(v, b.src_list));
         Set B = c.nbr_u(pick<K>(v, b.with_list));
+        uint64_t cb = 0;
+        if constexpr (MODE == MODE_ACCOUNT) cb = cut_bytes(A, lo, hi) + cut_bytes(B, lo, hi);
         A = trim_u<G>(A, lo, hi);
         B = trim_u<G>(B, lo, hi);
-        if constexpr (MODE == MODE_ACCOUNT)
-            if (c.g.gl == 0) *c.bytes += 4ull * (uint64_t)(A.n + B.n);
         int32_t n = uni<G>(intersect_into<G>(c.g, A, B, c.bufs + (int64_t)b.dst * c.cap));
+        if constexpr (MODE == MODE_ACCOUNT)
+            if (c.g.gl == 0) *c.bytes += cb + probe_isect_bytes(A, B) + 4ull * (uint64_t)n;
         group_fence();
         c.lens[b.dst] = n;
         group_fence();
@@ -277,8 +391,7 @@ __device__ __forceinline__ uint32_t leaf_serial(const GpPlanDesc& d, const Ctx<G
     bounds<K>(lv.hi_src, lv.lo_src, v, lo, hi);
     if (lv.last_list < 0) {
         Set S = lv.list >= 0 ? c.nbr(pick<K>(v, lv.list)) : c.buf(lv.buf);
-        if constexpr (MODE == MODE_ACCOUNT)
-            *c.bytes += probe_bytes(S.n) * (uint64_t)((lo > 0) + (hi < 0x7fffffff));
+        if constexpr (MODE == MODE_ACCOUNT) *c.bytes += cut_bytes(S, lo, hi);
         S = trim(S, lo, hi);
         uint32_t cnt = (uint32_t)S.n;
 #pragma unroll
@@ -286,7 +399,7 @@ __device__ __forceinline__ uint32_t leaf_serial(const GpPlanDesc& d, const Ctx<G
             if ((lv.inj >> j) & 1u) {
                 int32_t y = v[j];
                 if (y >= lo && y < hi) {
-                    if constexpr (MODE == MODE_ACCOUNT) *c.bytes += probe_bytes(S.n);
+                    if constexpr (MODE == MODE_ACCOUNT) *c.bytes += test_bytes(S);
                     if (member(S, y)) --cnt;
                 }
             }
@@ -299,27 +412,33 @@ __device__ __forceinline__ uint32_t leaf_serial(const GpPlanDesc& d, const Ctx<G
     // image are not counted
     const uint32_t inj = lv.inj;
     auto skip = [&](int32_t x) { return inj_hit<K>(inj, v, x); };
-    // a hub operand is tested by bits, so only the other operand is cut
-    if constexpr (MODE != MODE_ACCOUNT) {
-        if (B.bits && A.n <= kShortList && A.n * 4 <= B.n) return count_bits_range(A, lo, hi, B.bits, skip);
-        if (A.bits && B.n <= kShortList && B.n * 4 <= A.n) return count_bits_range(B, lo, hi, A.bits, skip);
+    // a hub operand is tested by bits, so only the other operand is cut; a
+    // short list is range-tested element by element instead of cut
+    if (B.bits && A.n <= kShortList && A.n * 4 <= B.n) {
+        if constexpr (MODE == MODE_ACCOUNT) *c.bytes += 8ull * (uint64_t)A.n;
+        return count_bits_range(A, lo, hi, B.bits, skip);
+    }
+    if (A.bits && B.n <= kShortList && B.n * 4 <= A.n) {
+        if constexpr (MODE == MODE_ACCOUNT) *c.bytes += 8ull * (uint64_t)B.n;
+        return count_bits_range(B, lo, hi, A.bits, skip);
     }
     if (B.bits) {
         const Set Ac = trim(A, lo, hi);
         if (Ac.n * 4 <= B.n) {
-            if constexpr (MODE == MODE_ACCOUNT) *c.bytes += 4ull * (uint64_t)(Ac.n + trim(B, lo, hi).n);
+            if constexpr (MODE == MODE_ACCOUNT) *c.bytes += cut_bytes(A, lo, hi) + 8ull * (uint64_t)Ac.n;
             return count_bits(Ac, B.bits, skip);
         }
     } else if (A.bits) {
         const Set Bc = trim(B, lo, hi);
         if (Bc.n * 4 <= A.n) {
-            if constexpr (MODE == MODE_ACCOUNT) *c.bytes += 4ull * (uint64_t)(Bc.n + trim(A, lo, hi).n);
+            if constexpr (MODE == MODE_ACCOUNT) *c.bytes += cut_bytes(B, lo, hi) + 8ull * (uint64_t)Bc.n;
             return count_bits(Bc, A.bits, skip);
         }
     }
+    if constexpr (MODE == MODE_ACCOUNT) *c.bytes += cut_bytes(A, lo, hi) + cut_bytes(B, lo, hi);
     A = trim(A, lo, hi);
     B = trim(B, lo, hi);
-    if constexpr (MODE == MODE_ACCOUNT) *c.bytes += 4ull * (uint64_t)(A.n + B.n);
+    if constexpr (MODE == MODE_ACCOUNT) *c.bytes += serial_isect_bytes(A, B);
     return intersect_count_serial(A, B, skip);
 }
 
@@ -341,76 +460,149 @@ __device__ __forceinline__ uint32_t leaf_group(const GpPlanDesc& d, const Ctx<G>
     bounds<K>(lv.hi_src, lv.lo_src, v, lo, hi);
     Set A = lv.pre_buf >= 0 ? c.buf_u(lv.pre_buf) : c.nbr_u(pick<K>(v, lv.pre_list));
     Set B = c.nbr_u(pick<K>(v, lv.last_list));
+    uint64_t cb = 0;
+    if constexpr (MODE == MODE_ACCOUNT) cb = cut_bytes(A, lo, hi) + cut_bytes(B, lo, hi);
     A = trim_u<G>(A, lo, hi);
     B = trim_u<G>(B, lo, hi);
     if constexpr (MODE == MODE_ACCOUNT)
-        if (c.g.gl == 0) *c.bytes += 4ull * (uint64_t)(A.n + B.n);
+        if (c.g.gl == 0) *c.bytes += cb + probe_isect_bytes(A, B);
     const uint32_t inj = lv.inj;
     return intersect_count_group<G>(c.g, A, B, [&](int32_t x) { return inj_hit<K>(inj, v, x); });
 }
 
-// Counting with inclusion-exclusion over the last two levels (Section IV-D,
-// k = 2 inner sets): for bound values v[0..K-3], the number of pairs (y, z)
-// with y in S1, z in S2, y != z, where S1, S2 are the candidate sets of
-// levels K-2 and K-1 (outer images removed): |S1| |S2| - |S1 & S2|. By one
-// lane.
-template <int K, int G, int MODE>
-__device__ __forceinline__ uint64_t iep_leaf_serial(const GpPlanDesc& d, const Ctx<G>& c,
-                                                    const int32_t (&v)[K]) {
-    const GpLevel& l1 = d.lv[K - 2];
-    const GpLevel& l2 = d.lv[K - 1];
-    int32_t lo1, hi1, lo2, hi2;
-    bounds<K>(l1.hi_src, l1.lo_src, v, lo1, hi1);
-    bounds<K>(l2.hi_src, l2.lo_src, v, lo2, hi2);
-    const Set S1 = l1.list >= 0 ? c.nbr(pick<K>(v, l1.list)) : c.buf(l1.buf);
-    const Set S2 = l2.list >= 0 ? c.nbr(pick<K>(v, l2.list)) : c.buf(l2.buf);
-    const Set A = trim(S1, lo1, hi1);
-    const Set B = trim(S2, lo2, hi2);
-    uint64_t c1 = (uint64_t)A.n, c2 = (uint64_t)B.n;
+// Counting with inclusion-exclusion over the N innermost levels (Section
+// IV-D). For bound values v[0..K-N-1] every inner level j has a candidate set
+// S_j: its parents' common neighbors (all parents are outer levels: the inner
+// pattern vertices are pairwise non-adjacent), cut by the restrictions to
+// outer levels and without the outer images. The number of N-tuples with
+// y_j in S_j and all y_j distinct is the inclusion-exclusion sum over the
+// "y_a = y_b" conditions; Algorithm 2 evaluates each term as a product over
+// the components of the conditions' graph of |intersection of the
+// component's sets|. Terms whose graphs have the same components are
+// collected here: a partition of the N levels into blocks contributes
+// prod over blocks B of (-1)^(|B|-1) (|B|-1)! |∩_{j in B} S_j| (the sum of
+// (-1)^edges over the connected graphs on |B| vertices). GRP: computed by the
+// whole group (same value in every lane), else by one lane. The value fits
+// in 128 bits (each |S_j| < 2^31, N <= 4).
+template <int K, int G, int MODE, int N, bool GRP>
+__device__ __forceinline__ unsigned __int128 iep_value(const GpPlanDesc& d, const Ctx<G>& c,
+                                                       const int32_t (&v)[K]) {
+    static_assert(N >= 2 && N <= kIepMaxN && N <= K - 2, "IEP inner levels");
+    constexpr int F = K - N;  // first inner level
+    Set T[N];
+    int32_t lo[N], hi[N];
+    uint32_t inj[N];
+    uint64_t bytes = 0;
 #pragma unroll
-    for (int j = 0; j < K - 2; ++j) {
-        const int32_t y = v[j];
-        if (((l1.inj >> j) & 1u) && y >= lo1 && y < hi1 && member(A, y)) --c1;
-        if (((l2.inj >> j) & 1u) && y >= lo2 && y < hi2 && member(B, y)) --c2;
+    for (int j = 0; j < N; ++j) {
+        const GpLevel& lv = d.lv[F + j];
+        bounds<K>(lv.hi_src, lv.lo_src, v, lo[j], hi[j]);
+        inj[j] = lv.inj;
+        Set S;
+        if constexpr (GRP) S = lv.list >= 0 ? c.nbr_u(pick<K>(v, lv.list)) : c.buf_u(lv.buf);
+        else S = lv.list >= 0 ? c.nbr(pick<K>(v, lv.list)) : c.buf(lv.buf);
+        if constexpr (MODE == MODE_ACCOUNT) bytes += cut_bytes(S, lo[j], hi[j]);
+        if constexpr (GRP) T[j] = trim_u<G>(S, lo[j], hi[j]);
+        else T[j] = trim(S, lo[j], hi[j]);
     }
-    const int32_t lo = max(lo1, lo2), hi = min(hi1, hi2);
-    const Set A12 = trim(A, lo, hi), B12 = trim(B, lo, hi);
-    const uint32_t inj = (uint32_t)l1.inj | (uint32_t)l2.inj;
-    const uint32_t c12 = intersect_count_serial(A12, B12, [&](int32_t x) { return inj_hit<K>(inj, v, x); });
-    if constexpr (MODE == MODE_ACCOUNT)
-        *c.bytes += 2 * probe_bytes(S1.n) + 2 * probe_bytes(S2.n) + 4ull * (uint64_t)(A12.n + B12.n);
-    return c1 * c2 - c12;
-}
-
-// The same computed by the whole group (same value in every lane).
-template <int K, int G, int MODE>
-__device__ __forceinline__ uint64_t iep_leaf_group(const GpPlanDesc& d, const Ctx<G>& c,
-                                                   const int32_t (&v)[K]) {
-    const GpLevel& l1 = d.lv[K - 2];
-    const GpLevel& l2 = d.lv[K - 1];
-    int32_t lo1, hi1, lo2, hi2;
-    bounds<K>(l1.hi_src, l1.lo_src, v, lo1, hi1);
-    bounds<K>(l2.hi_src, l2.lo_src, v, lo2, hi2);
-    const Set S1 = l1.list >= 0 ? c.nbr_u(pick<K>(v, l1.list)) : c.buf_u(l1.buf);
-    const Set S2 = l2.list >= 0 ? c.nbr_u(pick<K>(v, l2.list)) : c.buf_u(l2.buf);
-    const Set A = trim_u<G>(S1, lo1, hi1);
-    const Set B = trim_u<G>(S2, lo2, hi2);
-    uint64_t c1 = (uint64_t)A.n, c2 = (uint64_t)B.n;
+    uint64_t cnt[1 << N];
+    cnt[0] = 0;
 #pragma unroll
-    for (int j = 0; j < K - 2; ++j) {
-        const int32_t y = v[j];
-        if (((l1.inj >> j) & 1u) && y >= lo1 && y < hi1 && member(A, y)) --c1;
-        if (((l2.inj >> j) & 1u) && y >= lo2 && y < hi2 && member(B, y)) --c2;
+    for (int m = 1; m < (1 << N); ++m) {
+        if ((m & (m - 1)) == 0) {
+            // one set: its size without the outer images in it
+            const int j = __builtin_ctz(m);
+            uint64_t c1 = (uint64_t)T[j].n;
+#pragma unroll
+            for (int o = 0; o < F; ++o) {
+                if ((inj[j] >> o) & 1u) {
+                    const int32_t y = v[o];
+                    if (y >= lo[j] && y < hi[j]) {
+                        if constexpr (MODE == MODE_ACCOUNT) bytes += test_bytes(T[j]);
+                        if (member(T[j], y)) --c1;
+                    }
+                }
+            }
+            cnt[m] = c1;
+            continue;
+        }
+        // several sets: cut all to the common range, walk the smallest and
+        // test its elements in the others
+        int32_t L = 0, H = 0x7fffffff;
+        uint32_t im = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+            if ((m >> j) & 1) {
+                L = max(L, lo[j]);
+                H = min(H, hi[j]);
+                im |= inj[j];
+            }
+        Set X[N];
+        int s = -1;
+        int32_t sn = 0x7fffffff;
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+            if ((m >> j) & 1) {
+                if constexpr (MODE == MODE_ACCOUNT) bytes += cut_bytes(T[j], L, H);
+                if constexpr (GRP) X[j] = trim_u<G>(T[j], L, H);
+                else X[j] = trim(T[j], L, H);
+                if (X[j].n < sn) {
+                    sn = X[j].n;
+                    s = j;
+                }
+            }
+        Set Sm{nullptr, 0, nullptr};
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+            if (((m >> j) & 1) && j == s) Sm = X[j];
+        auto in_all = [&](int32_t x) {
+            bool ok = !inj_hit<K>(im, v, x);
+#pragma unroll
+            for (int j = 0; j < N; ++j)
+                if (((m >> j) & 1) && j != s) ok = ok && member(X[j], x);
+            return ok;
+        };
+        if constexpr (MODE == MODE_ACCOUNT) {
+            uint64_t per = 4;
+#pragma unroll
+            for (int j = 0; j < N; ++j)
+                if (((m >> j) & 1) && j != s) per += test_bytes(X[j]);
+            bytes += (uint64_t)Sm.n * per;
+        }
+        uint64_t cm = 0;
+        if constexpr (GRP) {
+            for (int32_t base = 0; base < Sm.n; base += G) {
+                const int32_t i = base + c.g.gl;
+                bool ok = false;
+                if (i < Sm.n) ok = in_all(Sm.p[i]);
+                cm += (uint64_t)__popcll(c.g.ballot(ok));
+            }
+        } else {
+            for (int32_t i = 0; i < Sm.n; ++i) cm += in_all(Sm.p[i]) ? 1u : 0u;
+        }
+        cnt[m] = cm;
     }
-    const int32_t lo = max(lo1, lo2), hi = min(hi1, hi2);
-    const Set A12 = trim_u<G>(A, lo, hi), B12 = trim_u<G>(B, lo, hi);
-    const uint32_t inj = (uint32_t)l1.inj | (uint32_t)l2.inj;
-    const uint32_t c12 =
-        intersect_count_group<G>(c.g, A12, B12, [&](int32_t x) { return inj_hit<K>(inj, v, x); });
-    if constexpr (MODE == MODE_ACCOUNT)
-        if (c.g.gl == 0)
-            *c.bytes += 2 * probe_bytes(S1.n) + 2 * probe_bytes(S2.n) + 4ull * (uint64_t)(A12.n + B12.n);
-    return c1 * c2 - c12;
+    if constexpr (MODE == MODE_ACCOUNT) {
+        if constexpr (GRP) {
+            if (c.g.gl == 0) *c.bytes += bytes;
+        } else {
+            *c.bytes += bytes;
+        }
+    }
+    typedef unsigned __int128 u128;
+    auto P = [&](int a) { return (u128)cnt[a]; };
+    if constexpr (N == 2) {
+        return P(1) * P(2) - P(3);
+    } else if constexpr (N == 3) {
+        return P(1) * P(2) * P(4) - P(3) * P(4) - P(5) * P(2) - P(6) * P(1) + 2 * P(7);
+    } else {
+        // blocks: singles 1 2 4 8; pairs 3 5 9 6 10 12; triples 7 11 13 14; all 15
+        return P(1) * P(2) * P(4) * P(8) -
+               (P(3) * P(4) * P(8) + P(5) * P(2) * P(8) + P(9) * P(2) * P(4) + P(6) * P(1) * P(8) +
+                P(10) * P(1) * P(4) + P(12) * P(1) * P(2)) +
+               (P(3) * P(12) + P(5) * P(10) + P(9) * P(6)) +
+               2 * (P(7) * P(8) + P(11) * P(4) + P(13) * P(2) + P(14) * P(1)) - 6 * P(15);
+    }
 }
 
 // The last two enumerated levels flattened into one load-balanced batch
@@ -422,7 +614,7 @@ __device__ __forceinline__ uint64_t iep_leaf_group(const GpPlanDesc& d, const Ct
 // runs after level K-3 is bound.
 template <int K, int G, int MODE>
 __device__ void flat_leaf(const GpPlanDesc& d, const Ctx<G>& c, const int32_t (&v)[K], Set S,
-                          int32_t st, uint32_t inj_l, uint64_t& acc, bool& ovf) {
+                          int32_t st, uint32_t inj_l, uint64_t& acc, uint64_t& carry) {
     constexpr int L = K - 3;
     const GpLevel& l2 = d.lv[K - 2];
     for (int32_t base = 0; base < S.n; base += G) {
@@ -440,6 +632,7 @@ __device__ void flat_leaf(const GpPlanDesc& d, const Ctx<G>& c, const int32_t (&
                 int32_t lo, hi;
                 bounds<K>(l2.hi_src, l2.lo_src, w, lo, hi);
                 C = l2.list >= 0 ? c.nbr(pick<K>(w, l2.list)) : c.buf(l2.buf);
+                if constexpr (MODE == MODE_ACCOUNT) *c.bytes += cut_bytes(C, lo, hi);
                 C = trim(C, lo, hi);
             }
         }
@@ -475,7 +668,7 @@ __device__ void flat_leaf(const GpPlanDesc& d, const Ctx<G>& c, const int32_t (&
                 w[L] = ox;
                 if (!inj_hit<K>(l2.inj, w, y)) {
                     w[K - 2] = y;
-                    add_count(acc, leaf_serial<K, G, MODE>(d, c, w), ovf);
+                    add_count(acc, leaf_serial<K, G, MODE>(d, c, w), carry);
                 }
             }
         }
@@ -504,7 +697,7 @@ constexpr int32_t kCoopList = 64;
 
 template <int K, int G, int MODE>
 __device__ bool coop_bits_leaf(const GpPlanDesc& d, const Ctx<G>& c, const int32_t (&v)[K], Set S, int32_t st,
-                               uint32_t inj_l, uint64_t& acc, bool& ovf) {
+                               uint32_t inj_l, uint64_t& acc, uint64_t& carry) {
     const GpLevel& ll = d.lv[K - 1];
     if (ll.last_list != K - 2) return false;
     const Set A = ll.pre_buf >= 0 ? c.buf_u(ll.pre_buf) : c.nbr_u(pick<K>(v, ll.pre_list));
@@ -533,17 +726,24 @@ __device__ bool coop_bits_leaf(const GpPlanDesc& d, const Ctx<G>& c, const int32
                     for (int j = 0; j < K - 1; ++j)
                         if ((ll.inj >> j) & 1u) {
                             const int32_t y = w[j];
-                            corr += (y >= lo && y < hi && ((bits[y >> 5] >> (y & 31)) & 1u)) ? 1u : 0u;
+                            if (y >= lo && y < hi) {
+                                if constexpr (MODE == MODE_ACCOUNT) *c.bytes += 4;
+                                corr += ((bits[y >> 5] >> (y & 31)) & 1u) ? 1u : 0u;
+                            }
                         }
                     const unsigned long long e = c.memo[x];
+                    if constexpr (MODE == MODE_ACCOUNT) *c.bytes += 8;
                     if ((uint32_t)(e >> 32) == c.tag) {
-                        add_count(acc, (uint32_t)e - corr, ovf);
+                        add_count(acc, (uint32_t)e - corr, carry);
                     } else {
-                        B = trim(c.nbr(x), lo, hi);
+                        const Set Bn = c.nbr(x);
+                        if constexpr (MODE == MODE_ACCOUNT) *c.bytes += cut_bytes(Bn, lo, hi);
+                        B = trim(Bn, lo, hi);
                         if (B.n <= kCoopList) {
                             const uint32_t all = count_bits(B, bits, [](int32_t) { return false; });
                             c.memo[x] = ((unsigned long long)c.tag << 32) | all;
-                            add_count(acc, all - corr, ovf);
+                            if constexpr (MODE == MODE_ACCOUNT) *c.bytes += 8ull * (uint64_t)B.n + 8;
+                            add_count(acc, all - corr, carry);
                         } else {
                             longl = true;
                         }
@@ -551,11 +751,17 @@ __device__ bool coop_bits_leaf(const GpPlanDesc& d, const Ctx<G>& c, const int32
                 } else {
                     B = c.nbr(x);
                     if (B.n <= kShortList) {
-                        add_count(acc, count_bits_range(B, lo, hi, bits, skip), ovf);
+                        if constexpr (MODE == MODE_ACCOUNT) *c.bytes += 8ull * (uint64_t)B.n;
+                        add_count(acc, count_bits_range(B, lo, hi, bits, skip), carry);
                     } else {
+                        if constexpr (MODE == MODE_ACCOUNT) *c.bytes += cut_bytes(B, lo, hi);
                         B = trim(B, lo, hi);
-                        if (B.n <= kCoopList) add_count(acc, count_bits(B, bits, skip), ovf);
-                        else longl = true;
+                        if (B.n <= kCoopList) {
+                            if constexpr (MODE == MODE_ACCOUNT) *c.bytes += 8ull * (uint64_t)B.n;
+                            add_count(acc, count_bits(B, bits, skip), carry);
+                        } else {
+                            longl = true;
+                        }
                     }
                 }
             }
@@ -579,106 +785,135 @@ __device__ bool coop_bits_leaf(const GpPlanDesc& d, const Ctx<G>& c, const int32
                     cnt += !inj_hit<K>(ll.inj, w, y);
                 }
             }
-            add_count(acc, cnt, ovf);
+            if constexpr (MODE == MODE_ACCOUNT)
+                if (c.g.gl == 0) *c.bytes += 8ull * (uint64_t)on;
+            add_count(acc, cnt, carry);
             if (c.memo && ox < c.n_hubs) {
                 // the long list of a hub candidate: keep its whole count
                 const uint32_t tot = (uint32_t)c.g.sum(all);
-                if (c.g.gl == 0) c.memo[ox] = ((unsigned long long)c.tag << 32) | tot;
+                if (c.g.gl == 0) {
+                    c.memo[ox] = ((unsigned long long)c.tag << 32) | tot;
+                    if constexpr (MODE == MODE_ACCOUNT) *c.bytes += 8;
+                }
             }
         }
     }
     return true;
 }
 
-template <int K, int L, int G, int LEAF, int MODE, bool IEP>
-__device__ void search(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], uint64_t& acc,
-                       bool& ovf) {
-    const GpLevel& lv = d.lv[L];
-    int32_t lo, hi;
-    bounds<K>(lv.hi_src, lv.lo_src, v, lo, hi);
-    Set S = lv.list >= 0 ? c.nbr_u(pick<K>(v, lv.list)) : c.buf_u(lv.buf);
-    S = trim_u<G>(S, lo, hi);
-    if constexpr (MODE == MODE_ACCOUNT)
-        if (c.g.gl == 0) *c.bytes += 4ull * (uint64_t)S.n;
-    // a split task binds only its slice of the level-2 candidates
-    int32_t st = 1;
-    if constexpr (L == 2) {
-        if (c.sJ > 1) {
-            S.n = S.n > c.sj ? (S.n - c.sj + c.sJ - 1) / c.sJ : 0;
-            S.p += c.sj;
-            st = c.sJ;
+// The IEP leaf at the last outer level L (inner levels L+1 .. K-1): every
+// candidate x of level L adds its inclusion-exclusion value. Lanes take
+// different candidates when no build runs after level L is bound; otherwise
+// the group binds one candidate at a time, runs the builds and computes the
+// value together.
+template <int K, int L, int G, int MODE>
+__device__ void iep_level(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], Set S, int32_t st,
+                          uint32_t inj_l, uint64_t& acc, uint64_t& carry) {
+    constexpr int N = K - 1 - L;
+    if (d.build_begin[L] == d.build_end[L]) {
+        for (int32_t base = 0; base < S.n; base += G) {
+            if (c.expired()) break;
+            const int32_t i = base + c.g.gl;
+            if (i < S.n) {
+                const int32_t x = S.p[(int64_t)i * st];
+                if (!inj_hit<K>(inj_l, v, x)) {
+                    int32_t w[K];
+#pragma unroll
+                    for (int j = 0; j < K; ++j) w[j] = v[j];
+                    w[L] = x;
+                    const unsigned __int128 val = iep_value<K, G, MODE, N, false>(d, c, w);
+                    add_count128(acc, carry, (uint64_t)val, (uint64_t)(val >> 64));
+                }
+            }
+        }
+    } else {
+        for (int32_t t = 0; t < S.n; ++t) {
+            if (c.expired()) break;
+            const int32_t x = uni<G>(S.p[(int64_t)t * st]);
+            if (inj_hit<K>(inj_l, v, x)) continue;
+            v[L] = x;
+            run_builds<K, G, MODE>(d, c, L, v);
+            const unsigned __int128 val = iep_value<K, G, MODE, N, true>(d, c, v);
+            if (c.g.gl == 0) add_count128(acc, carry, (uint64_t)val, (uint64_t)(val >> 64));
         }
     }
-    if constexpr (IEP && L == K - 3) {
-        // last outer level: every candidate adds its inclusion-exclusion count
-        if (d.build_begin[L] == d.build_end[L]) {
-            for (int32_t base = 0; base < S.n; base += G) {
-                if (c.expired()) break;
-                const int32_t i = base + c.g.gl;
-                if (i < S.n) {
-                    const int32_t x = S.p[(int64_t)i * st];
-                    if (!inj_hit<K>(lv.inj, v, x)) {
-                        int32_t w[K];
+}
+
+template <int K, int L, int G, int LEAF, int MODE, bool IEP>
+__device__ void search(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], uint64_t& acc,
+                       uint64_t& carry) {
+    if constexpr (IEP && L >= K - 2) {
+        return;  // an IEP search ends at the last outer level, at most K-3
+    } else {
+        const GpLevel& lv = d.lv[L];
+        int32_t lo, hi;
+        bounds<K>(lv.hi_src, lv.lo_src, v, lo, hi);
+        Set S = lv.list >= 0 ? c.nbr_u(pick<K>(v, lv.list)) : c.buf_u(lv.buf);
+        if constexpr (MODE == MODE_ACCOUNT)
+            if (c.g.gl == 0) *c.bytes += cut_bytes(S, lo, hi);
+        S = trim_u<G>(S, lo, hi);
+        // a split task binds only its slice of the level-2 candidates
+        int32_t st = 1;
+        if constexpr (L == 2) {
+            if (c.sJ > 1) {
+                S.n = S.n > c.sj ? (S.n - c.sj + c.sJ - 1) / c.sJ : 0;
+                S.p += c.sj;
+                st = c.sJ;
+            }
+        }
+        if constexpr (MODE == MODE_ACCOUNT)
+            if (c.g.gl == 0) *c.bytes += 4ull * (uint64_t)S.n;
+        if constexpr (IEP) {
+            if constexpr (K - 1 - L <= kIepMaxN) {
+                if (d.iep == K - 1 - L) {
+                    iep_level<K, L, G, MODE>(d, c, v, S, st, lv.inj, acc, carry);
+                    return;
+                }
+            }
+        }
+        if constexpr (L == K - 2) {
+            if constexpr (LEAF == 4)
+                if (coop_bits_leaf<K, G, MODE>(d, c, v, S, st, lv.inj, acc, carry)) return;
+            if constexpr (LEAF != 2) {
+                for (int32_t base = 0; base < S.n; base += G) {
+                    if (c.expired()) break;
+                    int32_t i = base + c.g.gl;
+                    if (i < S.n) {
+                        int32_t x = S.p[(int64_t)i * st];
+                        if (!inj_hit<K>(lv.inj, v, x)) {
+                            int32_t w[K];
 #pragma unroll
-                        for (int j = 0; j < K; ++j) w[j] = v[j];
-                        w[L] = x;
-                        add_count(acc, iep_leaf_serial<K, G, MODE>(d, c, w), ovf);
+                            for (int j = 0; j < K; ++j) w[j] = v[j];
+                            w[K - 2] = x;
+                            add_count(acc, leaf_serial<K, G, MODE>(d, c, w), carry);
+                        }
                     }
+                }
+            } else {
+                for (int32_t t = 0; t < S.n; ++t) {
+                    if (c.expired()) break;
+                    const int32_t x = uni<G>(S.p[(int64_t)t * st]);
+                    if (inj_hit<K>(lv.inj, v, x)) continue;
+                    v[K - 2] = x;
+                    uint32_t cnt = leaf_group<K, G, MODE>(d, c, v);
+                    if (c.g.gl == 0) add_count(acc, cnt, carry);
                 }
             }
         } else {
+            if constexpr (LEAF == 3 && L == K - 3 && !IEP) {
+                if (d.build_begin[L] == d.build_end[L]) {
+                    flat_leaf<K, G, MODE>(d, c, v, S, st, lv.inj, acc, carry);
+                    return;
+                }
+            }
             for (int32_t t = 0; t < S.n; ++t) {
                 if (c.expired()) break;
                 const int32_t x = uni<G>(S.p[(int64_t)t * st]);
                 if (inj_hit<K>(lv.inj, v, x)) continue;
                 v[L] = x;
                 run_builds<K, G, MODE>(d, c, L, v);
-                const uint64_t cnt = iep_leaf_group<K, G, MODE>(d, c, v);
-                if (c.g.gl == 0) add_count(acc, cnt, ovf);
+                search<K, L + 1, G, LEAF, MODE, IEP>(d, c, v, acc, carry);
             }
-        }
-    } else if constexpr (L == K - 2) {
-        if constexpr (LEAF == 4 && MODE != MODE_ACCOUNT)
-            if (coop_bits_leaf<K, G, MODE>(d, c, v, S, st, lv.inj, acc, ovf)) return;
-        if constexpr (LEAF != 2) {
-            for (int32_t base = 0; base < S.n; base += G) {
-                if (c.expired()) break;
-                int32_t i = base + c.g.gl;
-                if (i < S.n) {
-                    int32_t x = S.p[(int64_t)i * st];
-                    if (!inj_hit<K>(lv.inj, v, x)) {
-                        int32_t w[K];
-#pragma unroll
-                        for (int j = 0; j < K; ++j) w[j] = v[j];
-                        w[K - 2] = x;
-                        add_count(acc, leaf_serial<K, G, MODE>(d, c, w), ovf);
-                    }
-                }
-            }
-        } else {
-            for (int32_t t = 0; t < S.n; ++t) {
-                if (c.expired()) break;
-                const int32_t x = uni<G>(S.p[(int64_t)t * st]);
-                if (inj_hit<K>(lv.inj, v, x)) continue;
-                v[K - 2] = x;
-                uint32_t cnt = leaf_group<K, G, MODE>(d, c, v);
-                if (c.g.gl == 0) add_count(acc, cnt, ovf);
-            }
-        }
-    } else {
-        if constexpr (LEAF == 3 && L == K - 3 && !IEP) {
-            if (d.build_begin[L] == d.build_end[L]) {
-                flat_leaf<K, G, MODE>(d, c, v, S, st, lv.inj, acc, ovf);
-                return;
-            }
-        }
-        for (int32_t t = 0; t < S.n; ++t) {
-            if (c.expired()) break;
-            const int32_t x = uni<G>(S.p[(int64_t)t * st]);
-            if (inj_hit<K>(lv.inj, v, x)) continue;
-            v[L] = x;
-            run_builds<K, G, MODE>(d, c, L, v);
-            search<K, L + 1, G, LEAF, MODE, IEP>(d, c, v, acc, ovf);
         }
     }
 }
@@ -687,6 +922,110 @@ __device__ __forceinline__ int64_t entry_index(const int64_t* row_ptr, const int
                                                int32_t v0, int32_t v1) {
     int64_t b = row_ptr[v0];
     return b + lower_bound(col + b, (int32_t)(row_ptr[v0 + 1] - b), v1);
+}
+
+// One group's root tasks [t0, t1) of task space ts: every task binds its root
+// edge (levels 0 and 1) and searches the rest. Patterns whose search ends at
+// the root (k <= 3, or IEP over all k-2 levels after it) take different roots
+// in different lanes. per_root (MODE_PER_ROOT): each root's count at the CSR
+// entry of the root edge.
+template <int K, int G, int LEAF, int MODE, bool IEP>
+__device__ __forceinline__ void run_tasks(const GpPlanDesc& d, Ctx<G>& c, const TaskSpace& ts, int64_t t0,
+                                          int64_t t1, uint64_t& acc, uint64_t& carry,
+                                          unsigned long long* per_root) {
+    constexpr bool PER_ROOT = MODE == MODE_PER_ROOT;
+    if constexpr (IEP && K - 2 <= kIepMaxN) {
+        if (d.iep == K - 2) {
+            // the root is the last outer level
+            if (d.build_begin[1] == d.build_end[1]) {
+                for (int64_t base = t0; base < t1; base += G) {
+                    const int64_t r = base + c.g.gl;
+                    if (r < t1) {
+                        const int2 e = ts.roots[ts.offset + r * ts.stride];
+                        if constexpr (MODE == MODE_ACCOUNT) *c.bytes += 8;
+                        int32_t w[K];
+#pragma unroll
+                        for (int j = 0; j < K; ++j) w[j] = 0;
+                        w[0] = e.x;
+                        w[1] = e.y;
+                        const unsigned __int128 val = iep_value<K, G, MODE, K - 2, false>(d, c, w);
+                        add_count128(acc, carry, (uint64_t)val, (uint64_t)(val >> 64));
+                        if constexpr (PER_ROOT)
+                            per_root[entry_index(c.row_ptr, c.col, e.x, e.y)] = (unsigned long long)val;
+                    }
+                }
+            } else {
+                for (int64_t r = t0; r < t1; ++r) {
+                    int2 e = ts.roots[ts.offset + r * ts.stride];
+                    e.x = uni<G>(e.x);
+                    e.y = uni<G>(e.y);
+                    if constexpr (MODE == MODE_ACCOUNT)
+                        if (c.g.gl == 0) *c.bytes += 8;
+                    int32_t v[K];
+#pragma unroll
+                    for (int j = 0; j < K; ++j) v[j] = 0;
+                    v[0] = e.x;
+                    v[1] = e.y;
+                    run_builds<K, G, MODE>(d, c, 1, v);
+                    const unsigned __int128 val = iep_value<K, G, MODE, K - 2, true>(d, c, v);
+                    if (c.g.gl == 0) {
+                        add_count128(acc, carry, (uint64_t)val, (uint64_t)(val >> 64));
+                        if constexpr (PER_ROOT)
+                            per_root[entry_index(c.row_ptr, c.col, e.x, e.y)] = (unsigned long long)val;
+                    }
+                }
+            }
+            return;
+        }
+    }
+    if constexpr (K <= 3 && LEAF != 2) {
+        // lanes take different roots
+        for (int64_t base = t0; base < t1; base += G) {
+            int64_t r = base + c.g.gl;
+            if (r < t1) {
+                int2 e = ts.roots[ts.offset + r * ts.stride];
+                uint64_t cnt = 1;
+                if constexpr (MODE == MODE_ACCOUNT) *c.bytes += 8;
+                if constexpr (K == 3) {
+                    int32_t w[K] = {e.x, e.y, 0};
+                    cnt = leaf_serial<K, G, MODE>(d, c, w);
+                }
+                add_count(acc, cnt, carry);
+                if constexpr (PER_ROOT) per_root[entry_index(c.row_ptr, c.col, e.x, e.y)] = cnt;
+            }
+        }
+    } else {
+        for (int64_t t = t0; t < t1; ++t) {
+            const int64_t r = task_root(t, ts.split_roots, ts.split_ways, c.sj, c.sJ);
+            c.tag = ts.tag_base + (uint32_t)(r + 1);
+            int2 e = ts.roots[ts.offset + r * ts.stride];
+            e.x = uni<G>(e.x);
+            e.y = uni<G>(e.y);
+            const uint64_t before = acc;
+            if constexpr (MODE == MODE_ACCOUNT)
+                if (c.g.gl == 0) *c.bytes += 8;
+            if constexpr (K <= 3) {
+                uint64_t cnt = 1;
+                if constexpr (K == 3) {
+                    int32_t w[K] = {e.x, e.y, 0};
+                    cnt = leaf_group<K, G, MODE>(d, c, w);
+                }
+                if (c.g.gl == 0) add_count(acc, cnt, carry);
+            } else {
+                int32_t v[K];
+#pragma unroll
+                for (int j = 0; j < K; ++j) v[j] = 0;
+                v[0] = e.x;
+                v[1] = e.y;
+                run_builds<K, G, MODE>(d, c, 1, v);
+                search<K, 2, G, LEAF, MODE, IEP>(d, c, v, acc, carry);
+            }
+            if constexpr (PER_ROOT) {
+                uint64_t mine = c.g.sum(acc - before);
+                if (c.g.gl == 0) per_root[entry_index(c.row_ptr, c.col, e.x, e.y)] = mine;
+            }
+        }
+    }
 }
 
 // Wavefronts per SIMD the compiler is asked to keep resident (it trims
@@ -701,7 +1040,6 @@ constexpr int occupancy_target(int K, int G, int LEAF) {
 
 template <int K, int G, int LEAF, int MODE, bool IEP>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(occupancy_target(K, G, LEAF)))) void count_kernel(GpPlanDesc d, CountArgs a) {
-    constexpr bool PER_ROOT = MODE == MODE_PER_ROOT;
     __shared__ int32_t s_len[kBlock / G][GP_DESC_MAX_BUILDS];
     Ctx<G> c;
     c.row_ptr = a.row_ptr;
@@ -724,9 +1062,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(occupanc
     c.deadline = a.busy && a.budget_ticks ? t_begin + a.budget_ticks : 0;
     uint64_t chunk_max = 0;
     bool stopped = false;
+    TaskSpace ts;
+    ts.roots = a.roots;
+    ts.offset = a.root_offset;
+    ts.stride = a.root_stride;
+    ts.split_roots = a.split_roots;
+    ts.split_ways = a.split_ways;
+    ts.tag_base = 0;
 
-    uint64_t acc = 0;
-    bool ovf = false;
+    uint64_t acc = 0, carry = 0;
     const int64_t chunk = a.chunk;
 
     for (;;) {
@@ -736,84 +1080,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(occupanc
         if ((int64_t)t0 >= a.n_tasks) break;
         const int64_t t1 = min((int64_t)t0 + chunk, a.n_tasks);
         const uint64_t t_chunk = a.busy ? wall_clock64() : 0;
-        if constexpr (IEP && K == 4) {
-            // the root is the last outer level
-            if (d.build_begin[1] == d.build_end[1]) {
-                for (int64_t base = (int64_t)t0; base < t1; base += G) {
-                    const int64_t r = base + c.g.gl;
-                    if (r < t1) {
-                        const int2 e = a.roots[a.root_offset + r * a.root_stride];
-                        if constexpr (MODE == MODE_ACCOUNT) bytes += 8;
-                        int32_t w[K] = {e.x, e.y, 0, 0};
-                        const uint64_t cnt = iep_leaf_serial<K, G, MODE>(d, c, w);
-                        add_count(acc, cnt, ovf);
-                        if constexpr (PER_ROOT) a.per_root[entry_index(a.row_ptr, a.col, e.x, e.y)] = cnt;
-                    }
-                }
-            } else {
-                for (int64_t r = (int64_t)t0; r < t1; ++r) {
-                    int2 e = a.roots[a.root_offset + r * a.root_stride];
-                    e.x = uni<G>(e.x);
-                    e.y = uni<G>(e.y);
-                    if constexpr (MODE == MODE_ACCOUNT)
-                        if (c.g.gl == 0) bytes += 8;
-                    int32_t v[K] = {e.x, e.y, 0, 0};
-                    run_builds<K, G, MODE>(d, c, 1, v);
-                    const uint64_t cnt = iep_leaf_group<K, G, MODE>(d, c, v);
-                    if (c.g.gl == 0) add_count(acc, cnt, ovf);
-                    if constexpr (PER_ROOT)
-                        if (c.g.gl == 0) a.per_root[entry_index(a.row_ptr, a.col, e.x, e.y)] = cnt;
-                }
-            }
-        } else if constexpr (K <= 3 && LEAF != 2) {
-            // lanes take different roots
-            for (int64_t base = (int64_t)t0; base < t1; base += G) {
-                int64_t r = base + c.g.gl;
-                if (r < t1) {
-                    int2 e = a.roots[a.root_offset + r * a.root_stride];
-                    uint64_t cnt = 1;
-                    if constexpr (MODE == MODE_ACCOUNT) bytes += 8;
-                    if constexpr (K == 3) {
-                        int32_t w[K] = {e.x, e.y, 0};
-                        cnt = leaf_serial<K, G, MODE>(d, c, w);
-                    }
-                    add_count(acc, cnt, ovf);
-                    if constexpr (PER_ROOT)
-                        a.per_root[entry_index(a.row_ptr, a.col, e.x, e.y)] = cnt;
-                }
-            }
-        } else {
-            for (int64_t t = (int64_t)t0; t < t1; ++t) {
-                const int64_t r = task_root(t, a.split_roots, a.split_ways, c.sj, c.sJ);
-                c.tag = (uint32_t)(r + 1);
-                int2 e = a.roots[a.root_offset + r * a.root_stride];
-                e.x = uni<G>(e.x);
-                e.y = uni<G>(e.y);
-                const uint64_t before = acc;
-                if constexpr (MODE == MODE_ACCOUNT)
-                    if (c.g.gl == 0) bytes += 8;
-                if constexpr (K <= 3) {
-                    uint64_t cnt = 1;
-                    if constexpr (K == 3) {
-                        int32_t w[K] = {e.x, e.y, 0};
-                        cnt = leaf_group<K, G, MODE>(d, c, w);
-                    }
-                    if (c.g.gl == 0) add_count(acc, cnt, ovf);
-                } else {
-                    int32_t v[K];
-#pragma unroll
-                    for (int j = 0; j < K; ++j) v[j] = 0;
-                    v[0] = e.x;
-                    v[1] = e.y;
-                    run_builds<K, G, MODE>(d, c, 1, v);
-                    search<K, 2, G, LEAF, MODE, IEP>(d, c, v, acc, ovf);
-                }
-                if constexpr (PER_ROOT) {
-                    uint64_t mine = c.g.sum(acc - before);
-                    if (c.g.gl == 0) a.per_root[entry_index(a.row_ptr, a.col, e.x, e.y)] = mine;
-                }
-            }
-        }
+        run_tasks<K, G, LEAF, MODE, IEP>(d, c, ts, (int64_t)t0, t1, acc, carry, a.per_root);
         if (a.busy) {
             const uint64_t now = wall_clock64();
             chunk_max = max(chunk_max, now - t_chunk);
@@ -824,16 +1091,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(occupanc
         }
     }
 
-    // wavefront reduction with carry detection, one atomic per wavefront
-    uint64_t s = acc;
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        uint64_t t = __shfl_xor(s, off, 64);
-        uint64_t u = s + t;
-        ovf |= (u < s);
-        s = u;
-    }
-    const bool any_ovf = __ballot(ovf) != 0;
+    // exact 128-bit wavefront sum, one pair of atomics per wavefront
+    uint64_t s = acc, s_hi = carry;
+    wave_sum128(s, s_hi);
     if constexpr (MODE == MODE_ACCOUNT) {
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) bytes += __shfl_xor(bytes, off, 64);
@@ -843,8 +1103,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(occupanc
     for (int off = 32; off >= 1; off >>= 1) cm = max(cm, (uint64_t)__shfl_xor(cm, off, 64));
     const bool any_stop = __ballot(stopped) != 0;
     if (__lane_id() == 0) {
-        unsigned long long old = atomicAdd(&a.result[0], (unsigned long long)s);
-        if (any_ovf || old + s < old) atomicOr(&a.result[1], 1ull);
+        publish128(&a.result[0], &a.queue[1], s, s_hi);
         if (any_stop) atomicOr(&a.result[1], 4ull);
         if constexpr (MODE == MODE_ACCOUNT) atomicAdd(&a.result[2], (unsigned long long)bytes);
         if (a.busy) {

@@ -46,17 +46,25 @@ struct LaunchCfg {
     double budget_ms = 0;  // time limit per wavefront (measurement only; 0: none)
 };
 
-// Launch one count of plan d over g on `stream`. result_dev: {count,
-// overflow flag} (plus algorithmic bytes when `account`), zeroed by this call
-// on the stream. per_root may be null. Scratch is allocated stream-ordered
-// and released after the kernel.
+// Device memory a launch may use instead of allocating its own: the task
+// cursor and high count word, the per-group candidate buffers and, when room
+// is left, leaf mode 4's memo. The grid shrinks so the buffers fit.
+struct Workspace {
+    void* base = nullptr;  // 256-byte aligned
+    size_t bytes = 0;
+};
+
 // Wavefronts per compute unit that a launch of d with cfg keeps resident.
 int resident_waves_per_cu(const GpPlanDesc& d, const LaunchCfg& cfg);
 
+// Launch one count of plan d over g on `stream`. result_dev: {count,
+// flags} (plus bytes when `account`), zeroed by this call on the stream.
+// per_root may be null. Scratch is allocated stream-ordered and released
+// after the kernel, or carved from ws when given (then nothing is allocated).
 gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCfg& cfg,
                        hipStream_t stream, unsigned long long* result_dev,
                        unsigned long long* per_root, bool account = false,
-                       unsigned long long* busy = nullptr);
+                       unsigned long long* busy = nullptr, const Workspace* ws = nullptr);
 
 // Enqueue a listing of plan d over g on `stream`: found_dev (2 device words)
 // receives {embeddings found, 0}; the first out_cap of them are written to out
@@ -65,53 +73,66 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
 gp_status launch_list(const DeviceGraph& g, const GpPlanDesc& d, const int32_t* order, const LaunchCfg& cfg,
                       hipStream_t stream, unsigned long long* found_dev, int32_t* out, int64_t out_cap);
 
-// Device state of one batched launch: descriptors, per-plan task ranges,
-// scratch, queue and results, all allocated up front so that the launch
-// itself allocates nothing (it can be captured in a hipGraph and replayed).
+// Device state of one batched launch: descriptors, per-plan task ranges and
+// shapes, scratch, memo, task cursors and results, all allocated up front so
+// that the launch itself allocates nothing (it can be captured in a hipGraph
+// and replayed).
 struct BatchState {
     int np = 0;
     int kmax = 2;
-    int leaf = 1;
-    int group = 64;
+    int slots_per_wave = 1;  // groups per wavefront of the narrowest plan
+    bool use_memo = false;
     int64_t blocks = 0;
-    int64_t total_tasks = 0;
     int32_t nbuf = 0;
     int64_t cap = 0;
-    int32_t chunk = 4;
+    int64_t memo_words = 0;
     void* descs = nullptr;   // GpPlanDesc[np]
-    void* plans = nullptr;   // per-plan task ranges
+    void* plans = nullptr;   // per-plan task ranges and shapes
     int32_t* scratch = nullptr;
-    unsigned long long* queue = nullptr;
-    unsigned long long* result = nullptr;  // 3*np: count, overflow flag, busy clock ticks
+    unsigned long long* memo = nullptr;
+    unsigned long long* queues = nullptr;  // np task cursors
+    unsigned long long* result = nullptr;  // 4*np: count low word, flags, busy clock ticks, count high word
 };
 
 // A reusable batch for repeated launches with changing plans and task
-// ranges (the serving loop): device buffers for 64 plans and a scratch
-// region for nbuf_cap slots per group are allocated once; each launch copies
-// descriptors and ranges from pinned staging memory and reads results back
-// into pinned memory (h_result, valid once the stream has passed the launch).
+// ranges (the serving loop): device buffers for 64 plans, a scratch region
+// for nbuf_cap slots per group at the narrowest group width, and a memo, are
+// allocated once; each launch copies descriptors and ranges from pinned
+// staging memory and reads results back into pinned memory (h_result, valid
+// once the stream has passed the launch).
 struct BatchArena {
     BatchState st;
-    LaunchCfg cfg;
+    int waves_per_cu = 32;
+    int min_group = 64;
     int nbuf_cap = 0;
     int64_t blocks_cap = 0;
+    int64_t memo_words_cap = 0;
     GpPlanDesc* h_descs = nullptr;
     void* h_plans = nullptr;
     unsigned long long* h_result = nullptr;
 };
-gp_status arena_create(const DeviceGraph& g, int nbuf_cap, const LaunchCfg& cfg, BatchArena* a);
-gp_status arena_launch(const DeviceGraph& g, BatchArena* a, const GpPlanDesc* descs, const int64_t* offsets,
-                       const int64_t* counts, int np, hipStream_t stream);
+gp_status arena_create(const DeviceGraph& g, int nbuf_cap, int waves_per_cu, int min_group, BatchArena* a);
+gp_status arena_launch(const DeviceGraph& g, BatchArena* a, const GpPlanDesc* descs, const LaunchCfg* cfgs,
+                       const int64_t* offsets, const int64_t* counts, int np, hipStream_t stream);
 void arena_release(BatchArena* a);
 
-// Plan i covers roots[offset_i + t], t < count_i of its own root array;
-// offsets/counts null = every root. leafs: 1 or 3 per plan.
-gp_status batch_prepare(const DeviceGraph& g, const GpPlanDesc* descs, const int* leafs,
-                        const int64_t* offsets, const int64_t* counts, int np,
-                        const LaunchCfg& cfg, hipStream_t stream, BatchState* st);
+// Plan i runs with launch shape cfgs[i] (group, leaf, chunk, root splitting)
+// and covers its tasks [offset_i, offset_i + count_i); offsets/counts null =
+// every task.
+gp_status batch_prepare(const DeviceGraph& g, const GpPlanDesc* descs, const LaunchCfg* cfgs,
+                        const int64_t* offsets, const int64_t* counts, int np, int waves_per_cu,
+                        hipStream_t stream, BatchState* st);
 // Enqueue counter reset + the batched kernel on `stream` (no allocation).
 gp_status batch_enqueue(const DeviceGraph& g, const BatchState& st, hipStream_t stream);
 void batch_release(BatchState* st);
+// A plan's 128-bit batch total {low, flags, busy, high} divided by its IEP
+// over-count: GP_OK and *out, or GP_ERR_OVERFLOW.
+gp_status batch_result(const GpPlanDesc& d, const unsigned long long* r4, uint64_t* out);
+// The counting kernels' accumulation and final step applied to n given
+// values (host memory): *out = (sum / div) mod 2^64, *flags bit 0 if the
+// quotient does not fit in 64 bits, bit 1 if div does not divide the sum.
+gp_status check_sum(const uint64_t* values, int64_t n, uint64_t div, hipStream_t stream, uint64_t* out,
+                    uint32_t* flags);
 // Number of root tasks of a descriptor (its cut picks the root array).
 int64_t root_task_count(const DeviceGraph& g, const GpPlanDesc& d);
 // Tasks of plan d over g with cfg's root splitting (no sampling).

@@ -16,7 +16,7 @@
 // Restrictions (id(a) > id(b), Section II-B) become bounds on v_i: hi_src
 // lists levels j with v_i < v_j, lo_src levels j with v_i > v_j. The kernel
 // applies them as binary-search cuts on sorted sets (the paper's `break`).
-// With IEP, restrictions between the two last levels are dropped (and, when
+// With IEP, restrictions between two inner levels are dropped (and, when
 // needed, every restriction checked in them), so those levels' bounds come
 // from the restrictions that remain.
 #pragma once
@@ -24,6 +24,8 @@
 
 #define GP_DESC_MAX_K 8
 #define GP_DESC_MAX_BUILDS 24
+// inclusion-exclusion over at most this many innermost levels
+#define GP_IEP_MAX_INNER 4
 
 struct GpBuild {
     int8_t h;          // runs right after level h is bound
@@ -56,10 +58,12 @@ struct GpPlanDesc {
     int32_t root_cut;  // 0: every directed edge, 1: only v1 < v0, 2: only v1 > v0
     int32_t nbuild;
     int32_t nbuf;
-    // Counting with inclusion-exclusion (Section IV-D): the last two levels
-    // are pairwise non-adjacent and are not enumerated; for each binding of
-    // levels 0..k-3 the kernel adds |S1| |S2| - |S1 & S2|, and the total is
-    // divided by iep_div, the number of times IEP counts every embedding.
+    // Counting with inclusion-exclusion (Section IV-D): iep > 0 is the number
+    // of innermost levels (2 .. GP_IEP_MAX_INNER, pairwise non-adjacent) that
+    // are not enumerated; for each binding of the outer levels the kernel adds
+    // the number of tuples of distinct elements of their candidate sets, and
+    // the total is divided by iep_div, the number of times IEP counts every
+    // embedding.
     int32_t iep;
     int32_t iep_div;
     GpLevel lv[GP_DESC_MAX_K];

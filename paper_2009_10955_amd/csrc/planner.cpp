@@ -419,27 +419,43 @@ static int orbit_multiplicity(const std::vector<Perm>& auts, Rel kept, int k) {
     return mult < 0 ? 0 : mult;
 }
 
-int iep_setup(const Pattern& p, const std::vector<Perm>& auts, const Perm& order, Rel r, Rel* kept) {
+int iep_max_inner(const Pattern& p, const Perm& order) {
     const int k = p.k;
-    if (k < 4) return 0;
-    const int a = order[k - 2], b = order[k - 1];
-    if (p.adj[a] & (1u << b)) return 0;  // the two last levels must be non-adjacent
-    // 1) drop only the restrictions between the two last levels
-    Rel k1 = r & ~(rel_bit(a, b) | rel_bit(b, a));
+    // inner levels come after the root edge (levels 0 and 1)
+    const int cap = std::min(GP_IEP_MAX_INNER, k - 2);
+    int n = 0;
+    unsigned inner = 0;
+    while (n < cap) {
+        const int u = order[k - 1 - n];
+        if (p.adj[u] & inner) break;
+        inner |= 1u << u;
+        ++n;
+    }
+    return n >= 2 ? n : 0;
+}
+
+int iep_setup(const Pattern& p, const std::vector<Perm>& auts, const Perm& order, Rel r, int n_in, Rel* kept) {
+    const int k = p.k;
+    if (n_in < 2 || n_in > iep_max_inner(p, order)) return 0;
+    unsigned inner = 0;
+    for (int i = k - n_in; i < k; ++i) inner |= 1u << order[i];
+    // 1) drop only the restrictions between two inner levels
+    Rel k1 = 0, k2 = 0;
+    Rel rest = r;
+    while (rest) {
+        int bit = __builtin_ctzll(rest);
+        rest &= rest - 1;
+        const int u = bit >> 3, w = bit & 7;
+        const bool iu = (inner >> u) & 1u, iw = (inner >> w) & 1u;
+        if (!(iu && iw)) k1 |= rel_bit(u, w);
+        if (!iu && !iw) k2 |= rel_bit(u, w);
+    }
     int m = orbit_multiplicity(auts, k1, k);
     if (m > 0) {
         *kept = k1;
         return m;
     }
-    // 2) drop every restriction checked in the two last loops
-    Rel k2 = 0;
-    Rel rest = r;
-    while (rest) {
-        int bit = __builtin_ctzll(rest);
-        rest &= rest - 1;
-        int u = bit >> 3, w = bit & 7;
-        if (u != a && u != b && w != a && w != b) k2 |= rel_bit(u, w);
-    }
+    // 2) drop every restriction checked in the inner levels
     m = orbit_multiplicity(auts, k2, k);
     if (m > 0) {
         *kept = k2;
@@ -448,10 +464,14 @@ int iep_setup(const Pattern& p, const std::vector<Perm>& auts, const Perm& order
     return 0;
 }
 
-int compile_plan(const Pattern& p, const Perm& order, Rel r, GpPlanDesc* out, Rel iep_kept, int iep_div) {
+int compile_plan(const Pattern& p, const Perm& order, Rel r, GpPlanDesc* out, Rel iep_kept, int iep_div,
+                 int iep_n) {
     const int k = p.k;
     if (!phase1_ok(p, order)) return GP_ERR_ARG;
     const bool iep = iep_div > 0;
+    if (iep && (iep_n < 2 || iep_n > iep_max_inner(p, order))) return GP_ERR_ARG;
+    const int first_inner = iep ? k - iep_n : k;
+    const unsigned inner_mask = iep ? ((1u << k) - 1) & ~((1u << first_inner) - 1) : 0u;
     GpPlanDesc d;
     std::memset(&d, 0, sizeof d);
     d.k = k;
@@ -462,18 +482,18 @@ int compile_plan(const Pattern& p, const Perm& order, Rel r, GpPlanDesc* out, Re
     for (int i = 0; i < k; ++i) {
         par[i] = hi[i] = lo[i] = 0;
         int u = order[i];
-        // the two IEP levels are bounded only by the restrictions that remain
-        const Rel rr = (iep && i >= k - 2) ? iep_kept : r;
+        // the inner IEP levels are bounded only by the restrictions that remain
+        const Rel rr = i >= first_inner ? iep_kept : r;
         for (int j = 0; j < i; ++j) {
             int w = order[j];
             if (p.adj[u] & (1u << w)) par[i] |= 1u << j;
             if (rel_has(rr, w, u)) hi[i] |= 1u << j;  // id(w) > id(u): v_i < v_j
             if (rel_has(rr, u, w)) lo[i] |= 1u << j;  // id(u) > id(w): v_i > v_j
         }
-        if (iep && i == k - 1) {
-            // the other IEP level is not a bound source or injectivity partner
-            hi[i] &= ~(1u << (k - 2));
-            lo[i] &= ~(1u << (k - 2));
+        if (i >= first_inner) {
+            // the other inner levels are never bound: not bound sources
+            hi[i] &= ~inner_mask;
+            lo[i] &= ~inner_mask;
         }
     }
     d.root_cut = (hi[1] & 1u) ? 1 : ((lo[1] & 1u) ? 2 : 0);
@@ -524,7 +544,7 @@ int compile_plan(const Pattern& p, const Perm& order, Rel r, GpPlanDesc* out, Re
         L.hi_src = uint8_t(hi[i]);
         L.lo_src = uint8_t(lo[i]);
         L.inj = uint8_t(((1u << i) - 1) & ~par[i] & ~hi[i] & ~lo[i]);
-        if (iep && i == k - 1) L.inj &= uint8_t(~(1u << (k - 2)));
+        if (i >= first_inner) L.inj &= uint8_t(~inner_mask);  // distinct inner images: the IEP sum
         L.list = L.buf = L.pre_buf = L.pre_list = L.last_list = -1;
         if (i == 0) continue;
         int np = __builtin_popcount(par[i]);
@@ -558,7 +578,7 @@ int compile_plan(const Pattern& p, const Perm& order, Rel r, GpPlanDesc* out, Re
         d.build_begin[h] = uint8_t(b0);
         d.build_end[h] = uint8_t(b1);
     }
-    d.iep = iep ? 1 : 0;
+    d.iep = iep ? iep_n : 0;
     d.iep_div = iep ? iep_div : 0;
     *out = d;
     return 0;

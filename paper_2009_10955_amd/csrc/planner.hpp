@@ -65,18 +65,25 @@ double model_cost(const Pattern& p, const Perm& order, Rel r, const GraphStats& 
 int upper_cuts(const Perm& order, Rel r, int k);
 
 // Compile (schedule, closure) into the kernel descriptor. Returns 0 or an error.
-// With iep_kept != 0 the last two levels are compiled for counting with
-// inclusion-exclusion: their bounds come from iep_kept (the restrictions that
-// remain) and iep_div is the over-count.
+// With iep_div > 0 the last iep_n levels (pairwise non-adjacent) are compiled
+// for counting with inclusion-exclusion: their bounds come from iep_kept (the
+// restrictions that remain), they are neither bound sources nor injectivity
+// partners of each other, and iep_div is the over-count.
 int compile_plan(const Pattern& p, const Perm& order, Rel r, GpPlanDesc* out, Rel iep_kept = 0,
-                 int iep_div = 0);
+                 int iep_div = 0, int iep_n = 0);
 
-// IEP over the last two levels of (order, r): the restrictions that remain
+// The most innermost levels of `order` that IEP may count: the longest run
+// of pairwise non-adjacent pattern vertices at the end of the schedule, at
+// most GP_IEP_MAX_INNER and at most k - 2 (the root edge is enumerated); 0
+// if fewer than 2.
+int iep_max_inner(const Pattern& p, const Perm& order);
+
+// IEP over the last n_in levels of (order, r): the restrictions that remain
 // and the exact over-count (how many relative orders of each Aut-orbit obey
 // them; it must be the same for every orbit). First try dropping only the
-// restrictions between the two last levels, then every restriction checked
-// in them. Returns the over-count (and *kept), or 0 when the configuration
-// cannot be counted with IEP.
-int iep_setup(const Pattern& p, const std::vector<Perm>& auts, const Perm& order, Rel r, Rel* kept);
+// restrictions between two inner levels, then every restriction checked in
+// the inner levels. Returns the over-count (and *kept), or 0 when the
+// configuration cannot be counted with IEP over n_in levels.
+int iep_setup(const Pattern& p, const std::vector<Perm>& auts, const Perm& order, Rel r, int n_in, Rel* kept);
 
 }  // namespace gp

@@ -62,7 +62,7 @@ struct Query {
     int64_t launched = 0;  // tasks handed to launches (progress: tasks collected)
     int inflight = 0;      // launches in flight that hold a slice of this query
     uint64_t count = 0;
-    bool ovf = false;
+    uint64_t raw_lo = 0, raw_hi = 0;  // 128-bit total of the collected slices (before the IEP division)
     QState state = Q_QUEUED;
     gp_status status = GP_OK;
     double t_submit = 0, t_admit = 0, t_done = 0;
@@ -163,6 +163,7 @@ gp_status plan_query(gp_server* S, Query* q) {
         gp_plan_opts o;
         gp_plan_opts_default(&o);
         o.cost_cap = S->opts.cost_cap;
+        o.iep = S->opts.iep;
         gp_plan* p = nullptr;
         gp_status rc = gp_plan_create(q->edges.data(), q->k, (int32_t)(q->edges.size() / 2), &st, &o, &p);
         if (rc != GP_OK) return rc;
@@ -275,7 +276,7 @@ void poll_estimates(gp_server* S) {
 
 bool arena_fits(const gp_server* S, int g, int nbuf) {
     const gpint::BatchArena& a = S->arenas[2 * g];
-    return a.st.queue && a.nbuf_cap >= nbuf;
+    return a.st.queues && a.nbuf_cap >= nbuf;
 }
 
 // Both launch slots of graph g with room for nbuf buffer slots per group.
@@ -286,8 +287,9 @@ gp_status ensure_arena(gp_server* S, int g, int nbuf) {
     for (int slot = 0; slot < 2; ++slot) {
         gpint::BatchArena& a = S->arenas[2 * g + slot];
         gpint::arena_release(&a);
+        const gpint::LaunchCfg lc = server_launch(S);
         gp_status rc =
-            gpint::arena_create(S->graphs[g]->dg, std::min(want, GP_DESC_MAX_BUILDS), server_launch(S), &a);
+            gpint::arena_create(S->graphs[g]->dg, std::min(want, GP_DESC_MAX_BUILDS), lc.waves_per_cu, lc.group, &a);
         if (rc != GP_OK) return rc;
     }
     return GP_OK;
@@ -399,19 +401,21 @@ void worker_main(gp_server* S) {
             L.graph = g;
             L.slot = slot;
             std::vector<GpPlanDesc> descs;
+            std::vector<gpint::LaunchCfg> cfgs;
             std::vector<int64_t> offs;
             for (Query* q : S->active[g]) {
                 if (q->launched >= q->n_tasks || q->state == Q_DONE) continue;
                 const int64_t c = std::min(q->slice, q->n_tasks - q->launched);
                 descs.push_back(q->plan->desc);
+                cfgs.push_back(lcfg);
                 offs.push_back(q->launched);
                 L.qs.push_back(q);
                 L.slices.push_back(c);
             }
             if (L.qs.empty()) continue;
             const int idx = 2 * g + slot;
-            gp_status rc = gpint::arena_launch(S->graphs[g]->dg, &S->arenas[idx], descs.data(), offs.data(),
-                                               L.slices.data(), (int)L.qs.size(), S->streams[idx]);
+            gp_status rc = gpint::arena_launch(S->graphs[g]->dg, &S->arenas[idx], descs.data(), cfgs.data(),
+                                               offs.data(), L.slices.data(), (int)L.qs.size(), S->streams[idx]);
             if (rc != GP_OK) {
                 for (Query* q : L.qs) finish(S, q, rc);
                 continue;
@@ -459,18 +463,20 @@ void worker_main(gp_server* S) {
                 finish(S, q, GP_ERR_HIP);
                 continue;
             }
-            const uint64_t c = r[3 * i];
-            const uint64_t sum = q->count + c;
-            if (sum < q->count || r[3 * i + 1]) q->ovf = true;
-            q->count = sum;
+            // 128-bit sum of the slices' 128-bit totals; divided once at the end
+            const uint64_t lo = q->raw_lo + r[4 * i];
+            q->raw_hi += r[4 * i + 3] + (lo < q->raw_lo ? 1u : 0u);
+            q->raw_lo = lo;
             q->progress += L.slices[i];
             ++q->iterations;
             if (q->progress >= q->n_tasks && q->inflight == 0) {
-                finish(S, q, q->ovf ? GP_ERR_OVERFLOW : GP_OK);
+                const unsigned long long w[4] = {q->raw_lo, 0, 0, q->raw_hi};
+                const gp_status fs = gpint::batch_result(q->plan->desc, w, &q->count);
+                finish(S, q, fs);
                 continue;
             }
             // next slice: this query's task rate times its fair share of the target
-            const double t_q = std::max(1e-7, (double)r[3 * i + 2] * tick_s / groups);
+            const double t_q = std::max(1e-7, (double)r[4 * i + 2] * tick_s / groups);
             const double rate = (double)L.slices[i] / t_q;
             double next = rate * fair;
             next = std::min(next, 4.0 * (double)L.slices[i] + 1);
@@ -515,6 +521,7 @@ void gp_server_opts_default(gp_server_opts* o) {
     o->group = 64;
     o->leaf_mode = 1;
     o->waves_per_cu = 32;
+    o->iep = 1;
 }
 
 gp_status gp_server_create(const gp_graph* const* graphs, int32_t ng, const gp_server_opts* opts,
@@ -532,7 +539,7 @@ gp_status gp_server_create(const gp_graph* const* graphs, int32_t ng, const gp_s
     if (o.group != 64 && o.group != 32 && o.group != 16) o.group = 64;
     if (o.leaf_mode != 1 && o.leaf_mode != 3 && o.leaf_mode != 4) o.leaf_mode = 1;
     if (o.waves_per_cu <= 0 || o.waves_per_cu > 32) o.waves_per_cu = 32;
-    if (o.max_query_ms < 0 || o.cost_cap < 0) return GP_ERR_ARG;
+    if (o.max_query_ms < 0 || o.cost_cap < 0 || o.iep < 0 || o.iep > GP_IEP_MAX_INNER) return GP_ERR_ARG;
     gp_server* S = new (std::nothrow) gp_server;
     if (!S) return GP_ERR_NOMEM;
     S->graphs.assign(graphs, graphs + ng);

@@ -100,6 +100,7 @@ struct Cached {
     GpPlanDesc desc;
     gpint::LaunchCfg launch;
     int measured;
+    double ms;
 };
 
 std::mutex g_cache_mu;
@@ -200,6 +201,7 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
             np->tuned = true;
             np->desc = it->second.desc;
             np->info.n_measured = it->second.measured;
+            np->tuned_ms = it->second.ms;
         }
     }
 
@@ -228,21 +230,21 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
                          [](const Ranked& a, const Ranked& b) { return a.cost < b.cost; });
         std::vector<Cfg> cands;
         std::vector<gp::Perm> auts = gp::automorphisms(p->pattern);
-        // with try_iep every configuration may come twice: counted plainly
-        // and with inclusion-exclusion over its last two levels
-        const int cap = try_iep ? 2 * max_configs : max_configs;
-        auto add_one = [&](const gp::Perm& order, gp::Rel rel, bool iep) {
+        // with try_iep every configuration may come several times: counted
+        // plainly and with inclusion-exclusion over its 2, 3 or 4 last levels
+        const int cap = try_iep ? 3 * max_configs : max_configs;
+        auto add_one = [&](const gp::Perm& order, gp::Rel rel, int n_in) {
             if ((int)cands.size() >= cap) return;
             Cfg c;
             c.order = order;
             c.rel = rel;
             gp::Rel kept = 0;
             int div = 0;
-            if (iep) {
-                div = gp::iep_setup(p->pattern, auts, order, rel, &kept);
+            if (n_in > 0) {
+                div = gp::iep_setup(p->pattern, auts, order, rel, n_in, &kept);
                 if (div <= 0) return;
             }
-            if (gp::compile_plan(p->pattern, order, rel, &c.desc, kept, div) != 0) return;
+            if (gp::compile_plan(p->pattern, order, rel, &c.desc, kept, div, n_in) != 0) return;
             for (auto& x : cands)
                 if (std::memcmp(&x.desc, &c.desc, sizeof c.desc) == 0) return;
             cands.push_back(c);
@@ -253,8 +255,12 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
             if (!gp::acyclic(rel, k) || !gp::validate(rel, k, p->aut)) return;
             for (size_t q = 1; q < auts.size(); ++q)
                 if (gp::no_conflict(auts[q], rel, k)) return;
-            add_one(order, rel, p->desc.iep != 0);
-            if (try_iep) add_one(order, rel, true);
+            // the plan's own mode (its number of IEP levels, where this
+            // configuration allows as many), then with try_iep every IEP depth
+            const int nmax = gp::iep_max_inner(p->pattern, order);
+            add_one(order, rel, p->desc.iep ? std::min<int>(p->desc.iep, nmax) : 0);
+            if (try_iep)
+                for (int n = nmax; n >= 2; --n) add_one(order, rel, n);
         };
         add(p->order, p->set);
         add(p->order, mirror(p->set, k));
@@ -543,6 +549,26 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
                 cfg.chunk = ch;
                 try_cfg(cfg);
             }
+            // the heavy-root threshold T (roots whose hub endpoint is below it
+            // are split), where roots are split at all
+            if (best_launch.split_ways > 1) {
+                const int64_t t0v = best_launch.split_vertices;
+                for (int64_t tv : {64, 1024, 4096}) {
+                    if (tv == t0v) continue;
+                    gpint::LaunchCfg cfg = best_launch;
+                    cfg.split_vertices = tv;
+                    try_cfg(cfg);
+                }
+            }
+            // fewer resident wavefronts per compute unit: less contention for
+            // the caches on graphs larger than them
+            const int w0 = best_launch.waves_per_cu;
+            for (int w : {16, 24}) {
+                if (w >= w0) continue;
+                gpint::LaunchCfg cfg = best_launch;
+                cfg.waves_per_cu = w;
+                try_cfg(cfg);
+            }
         }
         best_launch.root_stride = 1;
         best_launch.root_offset = 0;
@@ -553,9 +579,10 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
             np->desc = cands[best].desc;
             np->launch = best_launch;
             np->tuned = true;
+            np->tuned_ms = best_ms < inf ? best_ms : 0;
             np->info.n_measured = measured;
             std::lock_guard<std::mutex> lk(g_cache_mu);
-            g_cache[key] = Cached{np->order, np->set, np->desc, np->launch, measured};
+            g_cache[key] = Cached{np->order, np->set, np->desc, np->launch, measured, np->tuned_ms};
         }
         (void)hipFreeAsync(res, s);
         (void)hipStreamSynchronize(s);
@@ -586,6 +613,7 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
     in.tuned = 1;
     in.iep = np->desc.iep;
     in.iep_div = np->desc.iep_div;
+    in.tuned_ms = np->tuned_ms;
     in.plan_seconds = p->info.plan_seconds + (now_seconds() - t0);
     *out = np;
     return GP_OK;
@@ -594,7 +622,6 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
 gp_status gp_estimate(const gp_graph* g, const gp_plan* p, const gp_launch* launch, double budget_ms,
                       void* stream, double* est_ms, uint64_t* sample_count, int64_t* sample_stride) {
     if (!g || !p || !est_ms || budget_ms < 0) return GP_ERR_ARG;
-    if (p->desc.iep) return GP_ERR_UNSUPPORTED;
     int prev = -1;
     (void)hipGetDevice(&prev);
     if (prev != g->dg.device) (void)hipSetDevice(g->dg.device);

@@ -70,7 +70,8 @@ class ServerOpts(ctypes.Structure):
     _fields_ = [("max_active", ctypes.c_int32), ("target_ms", ctypes.c_double),
                 ("cost_cap", ctypes.c_double), ("initial_slice", ctypes.c_int64),
                 ("group", ctypes.c_int32), ("leaf_mode", ctypes.c_int32),
-                ("waves_per_cu", ctypes.c_int32), ("max_query_ms", ctypes.c_double)]
+                ("waves_per_cu", ctypes.c_int32), ("max_query_ms", ctypes.c_double),
+                ("iep", ctypes.c_int32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -89,7 +90,7 @@ class PlanInfo(ctypes.Structure):
                 ("k_eff", ctypes.c_int32), ("set_index", ctypes.c_int32),
                 ("plan_seconds", ctypes.c_double), ("tuned", ctypes.c_int32),
                 ("iep", ctypes.c_int32), ("iep_div", ctypes.c_int32),
-                ("n_measured", ctypes.c_int32), ("launch", Launch)]
+                ("n_measured", ctypes.c_int32), ("launch", Launch), ("tuned_ms", ctypes.c_double)]
 
 
 
@@ -128,6 +129,8 @@ SIGNATURES = {
                        ctypes.POINTER(ctypes.c_uint64)]),
     "gp_count_traffic": (_I32, [_P, _P, ctypes.POINTER(Launch), _P,
                                 ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]),
+    "gp_check_sum": (_I32, [_P, _I64, ctypes.c_uint64, _P, ctypes.POINTER(ctypes.c_uint64),
+                            ctypes.POINTER(ctypes.c_uint32)]),
     "gp_batch_create": (_I32, [_P, _P, _I32, ctypes.POINTER(Launch), _P, ctypes.POINTER(_P)]),
     "gp_batch_tune": (_I32, [_P, _P, _I32, _P, ctypes.POINTER(Launch), ctypes.POINTER(ctypes.c_double)]),
     "gp_batch_run": (_I32, [_P, _P, _P]),
@@ -268,7 +271,7 @@ class Plan:
     def __init__(self, k: int, edges: Sequence[tuple[int, int]], stats: Stats | None = None,
                  force_order: Sequence[int] | None = None, force_set: int | None = None,
                  force_restr: Sequence[tuple[int, int]] | None = None, max_states: int = 0,
-                 max_sets: int = 0, cost_cap: float = 0.0, iep: bool = False):
+                 max_sets: int = 0, cost_cap: float = 0.0, iep: int | bool = False):
         lib = _lib()
         e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1))
         o = PlanOpts()
@@ -276,7 +279,8 @@ class Plan:
         o.max_states = max_states
         o.max_sets = max_sets
         o.cost_cap = cost_cap
-        o.iep = 1 if iep else 0
+        # True: as many innermost levels as the schedule allows; 2..4: at most that many
+        o.iep = int(iep) if not isinstance(iep, bool) else (1 if iep else 0)
         if force_order is not None:
             for i, v in enumerate(force_order):
                 o.force_order[i] = v
@@ -510,10 +514,12 @@ class Server:
 
     def __init__(self, graphs: Sequence[Graph], max_active: int = 0, target_ms: float = 0.0,
                  cost_cap: float = 0.0, initial_slice: int = 0, group: int = 0, leaf_mode: int = 0,
-                 waves_per_cu: int = 0, max_query_ms: float = 0.0):
+                 waves_per_cu: int = 0, max_query_ms: float = 0.0, iep: int | None = None):
         self.graphs = list(graphs)
         o = ServerOpts()
         _lib().gp_server_opts_default(ctypes.byref(o))
+        if iep is not None:
+            o.iep = int(iep)
         for name, val in (("max_active", max_active), ("target_ms", target_ms),
                           ("cost_cap", cost_cap), ("initial_slice", initial_slice),
                           ("group", group), ("leaf_mode", leaf_mode),
@@ -565,6 +571,17 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def check_sum(values, div: int = 1, stream=None) -> tuple[int, int]:
+    """(quotient mod 2^64, flags) of the exact device accumulation of the
+    uint64 values divided by div (see gp_check_sum)."""
+    v = np.ascontiguousarray(np.asarray(values, dtype=np.uint64).reshape(-1))
+    out = ctypes.c_uint64()
+    flags = ctypes.c_uint32()
+    _check(_lib().gp_check_sum(v.ctypes.data if v.size else None, v.size, int(div), _stream_handle(stream),
+                               ctypes.byref(out), ctypes.byref(flags)), "gp_check_sum")
+    return out.value, flags.value
 
 
 def version() -> str:

@@ -228,6 +228,11 @@ PATTERNS = {
     "tailed-triangle": (4, [(0, 1), (1, 2), (2, 0), (2, 3)]),
     "diamond": (4, [(0, 1), (1, 2), (2, 3), (3, 0), (0, 2)]),
     "edge": (2, [(0, 1)]),
+    "4-star": (5, [(0, 1), (0, 2), (0, 3), (0, 4)]),
+    "5-star": (6, [(0, 1), (0, 2), (0, 3), (0, 4), (0, 5)]),
+    "6-star": (7, [(0, i) for i in range(1, 7)]),
+    "5-path": (5, [(0, 1), (1, 2), (2, 3), (3, 4)]),
+    "spider": (6, [(0, 1), (0, 2), (0, 3), (1, 4), (2, 5)]),
 }
 
 CONFIG_PATTERNS = {

@@ -146,31 +146,45 @@ def test_cost_cap():
 
 # ------------------------------------------------------------------- IEP
 
-def _kept_rule(k, e, order, r):
-    """The library's rule for the restrictions kept with IEP over the last two
-    levels: drop those between the two; if the over-count then differs between
-    orbits, drop every restriction checked in them."""
-    a, b = order[k - 2], order[k - 1]
-    k1 = [(x, y) for x, y in r if not ({x, y} == {a, b})]
+def _kept_rule(k, e, order, r, n):
+    """The library's rule for the restrictions kept with IEP over the last n
+    levels: drop those between two inner levels; if the over-count then
+    differs between orbits, drop every restriction checked in them."""
+    inner = set(order[k - n:])
+    k1 = [(x, y) for x, y in r if not (x in inner and y in inner)]
     m = O.orbit_multiplicities(k, e, k1)
     if len(m) == 1:
         return k1, m.pop()
-    k2 = [(x, y) for x, y in r if x not in (a, b) and y not in (a, b)]
+    k2 = [(x, y) for x, y in r if x not in inner and y not in inner]
     m = O.orbit_multiplicities(k, e, k2)
     return (k2, m.pop()) if len(m) == 1 else (None, 0)
 
 
+def _trailing_independent(k, e, order):
+    adj = O._adj(k, e)
+    n = 0
+    while n < min(4, k - 2) and all(not adj[order[k - 1 - n]][order[k - 1 - j]] for j in range(n)):
+        n += 1
+    return n
+
+
 @pytest.mark.parametrize("pname", ["house", "diamond", "tailed-triangle", "4-path", "3-star",
-                                   "prism", "6-cycle-chord", "k4-path", "5-wheel"])
-def test_iep_plans_use_the_exact_over_count(pname):
+                                   "prism", "6-cycle-chord", "k4-path", "5-wheel", "4-star", "5-star",
+                                   "5-path", "6-star"])
+@pytest.mark.parametrize("cap", [1, 2, 3])
+def test_iep_plans_use_the_exact_over_count(pname, cap):
     k, e = P[pname]
-    plan = gp.Plan(k, e, iep=True)
+    plan = gp.Plan(k, e, iep=cap if cap > 1 else True)
     inf = plan.info()
-    assert inf.iep == 1
+    n = inf.iep
+    assert 2 <= n <= (4 if cap == 1 else cap)
     order = plan.order
     adj = O._adj(k, e)
-    assert not adj[order[k - 2]][order[k - 1]]
-    kept, m = _kept_rule(k, e, order, plan.restrictions)
+    # the inner levels: pairwise non-adjacent, after the root edge
+    assert n <= k - 2
+    assert all(not adj[a][b] for a, b in itertools.combinations(order[k - n:], 2))
+    assert n <= _trailing_independent(k, e, order)
+    kept, m = _kept_rule(k, e, order, plan.restrictions, n)
     assert kept is not None and inf.iep_div == m
 
 

@@ -18,8 +18,7 @@ Contents and what each follows:
 * ``automorphisms`` -- all vertex permutations that map the edge set onto
   itself (Section IV-A, Algorithm 1, first step).
 * ``no_conflict``, ``validate``, ``restriction_sets`` -- Algorithm 1 (2-cycle
-  based automorphism elimination), in the paper's order, with the readings
-  listed below.
+  based automorphism elimination), with the readings listed below.
 * ``phase1_ok``, ``efficient_schedules`` -- the 2-phase schedule filter
   (Section IV-B).
 * ``model_cost`` -- the nested performance model (Section IV-C).
@@ -40,10 +39,13 @@ Readings of the paper used here (the paper is silent or garbled on these):
   but are 1-cycles). The pair added is (v, perm[v]) (the listing's ``p`` is
   read as ``perm``).
 * A pair (a, b) means id(a) > id(b), drawn as the directed edge a -> b.
-* Memo: ``generate`` is called once per transitive closure of the current set.
+* Closures: each restriction set is explored once per transitive closure.
   This is sound because whether a permutation conflicts with a set, and how
-  many orders satisfy the set, depend only on its closure; the output is the
-  list of distinct valid closures.
+  many orders satisfy the set, depend only on its closure. The surviving
+  automorphisms of a set are recomputed from all of Aut(P); that equals
+  filtering the parent's survivors, since a permutation that conflicts with a
+  set conflicts with every superset. The output is the list of distinct
+  valid closures, sorted by size, then by their sorted pairs.
 * ``validate`` runs the paper's check literally: count maps of the pattern into
   the complete graph K_k with and without the restrictions and require
   with * |Aut| == without.
@@ -308,34 +310,46 @@ def validate(k: int, edges, res_set, auts=None) -> bool:
     return with_r * len(auts) == without
 
 
+def _two_cycle_pairs(perm: Sequence[int]) -> list[tuple[int, int]]:
+    """(v, perm[v]) for every vertex v that perm swaps with another vertex."""
+    return [(v, perm[v]) for v in range(len(perm)) if perm[v] != v and perm[perm[v]] == v]
+
+
 def restriction_sets(k: int, edges, max_states: int | None = None) -> list[frozenset]:
-    """Algorithm 1 (res_set_generation / generate). Returns the distinct valid
-    restriction sets, each as its transitive closure, in discovery order."""
+    """Section IV-A (Algorithm 1): restriction sets that eliminate every
+    automorphism but the identity.
+
+    Starting from the empty set, a set R grows by one pair (v, perm[v]) at a
+    time, where perm is an automorphism that R has not yet eliminated
+    (no_conflict(perm, R) holds) and v lies on a 2-cycle of perm. A set at
+    which the identity alone survives is a candidate, kept if validate
+    accepts it. Sets are handled as their transitive closures (reading in the
+    module header), the reachable closures are explored once each from a
+    worklist, and the distinct valid closures are returned sorted by size and
+    then by their sorted pairs (the paper fixes no order)."""
     auts = automorphisms(k, edges)
-    found: list[frozenset] = []
-    found_set: set = set()
-    visited: set = set()
-
-    def generate(pg: list, res_set: frozenset) -> None:
-        if len(pg) > 1:
-            for perm in pg:
-                for v in range(k):
-                    if perm[perm[v]] == v and perm[v] != v:   # a 2-cycle is found
-                        new_set = closure(res_set | {(v, perm[v])}, k)
-                        if new_set in visited:
-                            continue
-                        if max_states is not None and len(visited) >= max_states:
-                            return
-                        visited.add(new_set)
-                        remaining = [p for p in pg if no_conflict(p, new_set)]
-                        generate(remaining, new_set)
-        else:
-            if validate(k, edges, res_set, auts) and res_set not in found_set:
-                found_set.add(res_set)
-                found.append(res_set)
-
-    generate(auts, frozenset())
-    return found
+    start = frozenset()
+    seen = {start}
+    work = [start]
+    valid: set = set()
+    while work:
+        rel = work.pop()
+        alive = [p for p in auts if no_conflict(p, rel)]
+        if len(alive) <= 1:
+            # the identity alone survives (or nothing does: a cyclic set)
+            if alive and validate(k, edges, rel, auts):
+                valid.add(rel)
+            continue
+        for perm in alive:
+            for pair in _two_cycle_pairs(perm):
+                grown = closure(rel | {pair}, k)
+                if grown in seen:
+                    continue
+                if max_states is not None and len(seen) >= max_states:
+                    continue
+                seen.add(grown)
+                work.append(grown)
+    return sorted(valid, key=lambda r: (len(r), sorted(r)))
 
 
 # --------------------------------------------- schedules (Section IV-B)

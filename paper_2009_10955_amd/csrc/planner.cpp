@@ -2,7 +2,8 @@
 //
 //   automorphisms        Section IV-A (all permutations preserving the edge set)
 //   restriction_sets     Section IV-A, Algorithm 1 (2-cycle based automorphism
-//                        elimination: generate / no_conflict / validate)
+//                        elimination: sets grown by 2-cycle pairs, no_conflict,
+//                        validate)
 //   efficient_schedules  Section IV-B (Phase 1: prefix-connected orders;
 //                        Phase 2: last k searched vertices pairwise non-adjacent)
 //   model_cost           Section IV-C (nested cost model with the cardinality
@@ -12,8 +13,9 @@
 // Readings where the paper is silent or garbled:
 //   * 2-cycle test: perm[perm[v]] == v and perm[v] != v; the pair added is
 //     (v, perm[v]), meaning id(v) > id(perm[v]).
-//   * generate() runs once per transitive closure (sound: conflicts and the
-//     validate count depend only on the closure); results are closures.
+//   * each restriction set is explored once per transitive closure (sound:
+//     conflicts and the validate count depend only on the closure); results
+//     are closures, sorted by size, then by their sorted pairs.
 //   * validate uses the closed form of the paper's K_k check: on the complete
 //     graph K_k every bijection is a map, so the restricted count is the
 //     number of rank vectors obeying the set; valid iff that times |Aut| = k!.
@@ -146,48 +148,25 @@ double now_s() {
     return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
-struct Gen {
-    double deadline = 0;
-    const Pattern* p;
-    const std::vector<Perm>* auts;
-    int64_t max_states;
-    int32_t max_sets;
-    std::unordered_set<Rel> visited;
-    std::unordered_set<Rel> found_set;
-    RestrictionSets out;
-
-    void generate(const std::vector<int>& pg, Rel res_set) {
-        const int k = p->k;
-        if (pg.size() > 1) {
-            for (int pi : pg) {
-                const Perm& perm = (*auts)[pi];
-                for (int v = 0; v < k; ++v) {
-                    if (!(perm[perm[v]] == v && perm[v] != v)) continue;  // 2-cycle
-                    Rel new_set = closure(res_set | rel_bit(v, perm[v]), k);
-                    if (visited.count(new_set)) continue;
-                    if ((int64_t)visited.size() >= max_states ||
-                        (int32_t)out.sets.size() >= max_sets ||
-                        (deadline > 0 && (visited.size() & 1023) == 0 && now_s() > deadline &&
-                         !out.sets.empty())) {
-                        out.truncated = true;
-                        return;
-                    }
-                    visited.insert(new_set);
-                    std::vector<int> remaining;
-                    remaining.reserve(pg.size());
-                    for (int qi : pg)
-                        if (no_conflict((*auts)[qi], new_set, k)) remaining.push_back(qi);
-                    generate(remaining, new_set);
-                }
-            }
-        } else {
-            if (validate(res_set, k, auts->size()) && !found_set.count(res_set)) {
-                found_set.insert(res_set);
-                out.sets.push_back(res_set);
-            }
-        }
+// Lexicographic order of the sorted (a, b) pair lists of two relations.
+bool pairs_less(Rel x, Rel y) {
+    while (x && y) {
+        const int bx = __builtin_ctzll(x), by = __builtin_ctzll(y);  // bit a*8+b: ascending (a, b)
+        if (bx != by) return bx < by;
+        x &= x - 1;
+        y &= y - 1;
     }
-};
+    return !x && y;
+}
+
+// The valid closures first by size, then by their sorted pairs.
+void sort_sets(std::vector<Rel>* sets) {
+    std::sort(sets->begin(), sets->end(), [](Rel a, Rel b) {
+        const int na = __builtin_popcountll(a), nb = __builtin_popcountll(b);
+        if (na != nb) return na < nb;
+        return pairs_less(a, b);
+    });
+}
 }  // namespace
 
 RestrictionSets restriction_sets(const Pattern& p, const std::vector<Perm>& auts,
@@ -195,7 +174,7 @@ RestrictionSets restriction_sets(const Pattern& p, const std::vector<Perm>& auts
     const int k = p.k;
     // Complete pattern, k >= 6: every valid set is a total order (one orbit,
     // one obeying order per orbit) and Algorithm 1 reaches all k! of them, so
-    // emit them directly, in lexicographic order of the ranking.
+    // emit them directly (then sorted like every other result).
     bool complete = true;
     for (int v = 0; v < k; ++v)
         if (__builtin_popcount(p.adj[v]) != k - 1) complete = false;
@@ -213,20 +192,57 @@ RestrictionSets restriction_sets(const Pattern& p, const std::vector<Perm>& auts
                 for (int j = i + 1; j < k; ++j) r |= rel_bit(rank[i], rank[j]);
             out.sets.push_back(r);
         } while (std::next_permutation(rank.begin(), rank.begin() + k));
+        sort_sets(&out.sets);
         out.states = (int64_t)out.sets.size();
         return out;
     }
-    Gen g;
-    g.deadline = max_seconds > 0 ? now_s() + max_seconds : 0;
-    g.p = &p;
-    g.auts = &auts;
-    g.max_states = max_states;
-    g.max_sets = max_sets;
-    std::vector<int> pg(auts.size());
-    for (size_t i = 0; i < auts.size(); ++i) pg[i] = int(i);
-    g.generate(pg, 0);
-    g.out.states = int64_t(g.visited.size());
-    return g.out;
+    // Worklist over closures: a closure grows by one pair (v, perm[v]) per
+    // automorphism perm it does not yet eliminate and vertex v on a 2-cycle
+    // of perm; a closure at which the identity alone survives is kept if
+    // valid. Survivors are recomputed from all automorphisms (filtering the
+    // parent's survivors gives the same: a conflict persists in supersets).
+    RestrictionSets out;
+    const double deadline = max_seconds > 0 ? now_s() + max_seconds : 0;
+    std::unordered_set<Rel> seen;
+    std::unordered_set<Rel> valid;
+    std::vector<Rel> work;
+    seen.insert(0);
+    work.push_back(0);
+    while (!work.empty()) {
+        if ((int32_t)valid.size() >= max_sets ||
+            (deadline > 0 && (seen.size() & 1023) == 0 && now_s() > deadline && !valid.empty())) {
+            out.truncated = true;
+            break;
+        }
+        const Rel rel = work.back();
+        work.pop_back();
+        std::vector<int> alive;
+        for (size_t i = 0; i < auts.size(); ++i)
+            if (no_conflict(auts[i], rel, k)) alive.push_back(int(i));
+        if (alive.size() <= 1) {
+            // the identity alone survives (or nothing: a cyclic set)
+            if (!alive.empty() && validate(rel, k, auts.size())) valid.insert(rel);
+            continue;
+        }
+        for (int pi : alive) {
+            const Perm& perm = auts[pi];
+            for (int v = 0; v < k; ++v) {
+                if (perm[v] == v || perm[perm[v]] != v) continue;  // v is not on a 2-cycle
+                const Rel grown = closure(rel | rel_bit(v, perm[v]), k);
+                if (seen.count(grown)) continue;
+                if ((int64_t)seen.size() >= max_states) {
+                    out.truncated = true;
+                    continue;
+                }
+                seen.insert(grown);
+                work.push_back(grown);
+            }
+        }
+    }
+    out.sets.assign(valid.begin(), valid.end());
+    sort_sets(&out.sets);
+    out.states = int64_t(seen.size());
+    return out;
 }
 
 bool phase1_ok(const Pattern& p, const Perm& order) {

@@ -207,6 +207,17 @@ def induced_subgraph(g: CSR, keep: np.ndarray) -> CSR:
     return csr_from_edges(keep.size, new_id[src[sel]], new_id[dst[sel]])
 
 
+def core_subgraph(g: CSR, hubs: int, rest: int, seed: int) -> CSR:
+    """Seeded induced subgraph that keeps the `hubs` highest-degree vertices
+    (ties: lower id first) and `rest` vertices drawn without replacement from
+    the others (PCG64 default_rng(seed)), relabelled in ascending original id:
+    a small piece of a power-law graph with its dense core."""
+    order = np.argsort(-g.degrees(), kind="stable")
+    rng = np.random.default_rng(seed)
+    keep = np.sort(np.concatenate([order[:hubs], rng.choice(order[hubs:], rest, replace=False)]))
+    return induced_subgraph(g, keep)
+
+
 # ---------------------------------------------------------------- patterns
 # Edge lists over vertices 0..k-1, as used by the evaluation configurations.
 

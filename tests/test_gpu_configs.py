@@ -1,0 +1,252 @@
+"""Parity on the evaluation configurations at their real sizes.
+
+* R-MAT scale 22 (configs[3]): oracle counts of seeded induced subgraphs
+  (tests/golden/rmat22_induced.json, written by the oracle alone) against
+  plain, IEP, tuned and batched GPU counts; on the full graph, per-root
+  counts of sampled roots against the oracle's pinned counts.
+* Chung-Lu 7000 (configs[2]): the six 6-vertex patterns with tuned plans,
+  per-root on sampled roots against the oracle, batched == plain.
+* The benchmark's own configurations (profiles/plans_*.json: schedule,
+  restrictions, IEP, launch with splits, grabs and leaf mode 4's memo) on
+  strided root samples at full size, against the oracle's pinned counts of
+  the same roots, heavy hub roots included.
+"""
+import concurrent.futures as cf
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2009_10955_amd import gp
+from paper_2009_10955_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+P = I.PATTERNS
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+THREADS = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    yield
+
+
+@pytest.fixture(scope="module")
+def rmat22():
+    return I.config_graph(3)
+
+
+def _oracle_view(g):
+    rp, col, _ = O.relabel_by_degree(g)
+    return O._CSRView(rp, col), rp, col
+
+
+def _root_array(rp, col, root_cut):
+    """The library's root order (its documented layout): entries with v0 < v1
+    in CSR order, their reversals in the same order, or both interleaved."""
+    src = np.repeat(np.arange(len(rp) - 1, dtype=np.int64), np.diff(rp))
+    up = col.astype(np.int64) > src
+    upper = np.stack([src[up], col[up].astype(np.int64)], axis=1)
+    if root_cut == 2:
+        return upper
+    lower = upper[:, ::-1]
+    if root_cut == 1:
+        return lower
+    out = np.empty((2 * len(upper), 2), dtype=np.int64)
+    out[0::2] = upper
+    out[1::2] = lower
+    return out
+
+
+def _pinned(lay, k, e, restr, order, roots):
+    """Oracle counts of maps with the first two schedule vertices pinned to
+    each root, roots spread over threads (each oracle call single-threaded)."""
+    def one(r):
+        return O.count_maps(lay, k, e, restr=restr, pins=[(order[0], int(r[0])), (order[1], int(r[1]))],
+                            threads=1)
+    with cf.ThreadPoolExecutor(THREADS) as ex:
+        return list(ex.map(one, roots))
+
+
+# ------------------------------------------------------------ R-MAT scale 22
+
+GOLD22 = json.load(open(os.path.join(HERE, "golden", "rmat22_induced.json")))
+
+
+@pytest.mark.parametrize("case", GOLD22["cases"], ids=lambda c: c["name"])
+def test_rmat22_induced_subgraphs(rmat22, case):
+    h = I.core_subgraph(rmat22, case["hubs"], case["rest"], case["seed"])
+    assert h.sha256() == case["sha256"] and (h.n, h.m) == (case["n"], case["m"])
+    graph = gp.Graph.from_csr(h, device=True)
+    st = graph.stats()
+    names = list(case["counts"])
+    want = [case["counts"][n] for n in names]
+    plain = [gp.Plan(*P[n], stats=st) for n in names]
+    iep = [gp.Plan(*P[n], stats=st, iep=True) for n in names]
+    tuned = [gp.Plan(*P[n], stats=st).tuned(graph, budget_seconds=0.3, try_iep=True) for n in names]
+    for ps, what in ((plain, "plain"), (iep, "iep"), (tuned, "tuned")):
+        assert [gp.count(graph, p) for p in ps] == want, what
+    assert gp.count_batch(graph, plain + iep + tuned) == want * 3
+    b = gp.Batch(graph, tuned + plain)
+    assert b.run() == want * 2
+    b.close()
+    graph.close()
+
+
+def test_rmat22_full_size_4clique_per_root(rmat22):
+    """The full graph: the tuned 4-clique equals its per-root sum and the
+    batched count; sampled roots (random, and the heaviest the oracle redoes
+    in seconds) equal the oracle's pinned counts."""
+    g = rmat22
+    graph = gp.Graph.from_csr(g, device=True)
+    st = graph.stats()
+    k, e = P["4-clique"]
+    plan = gp.Plan(k, e, stats=st).tuned(graph, budget_seconds=1.0)
+    total = gp.count(graph, plan)
+    assert gp.count_batch(graph, [plan]) == [total]
+    t2, per = gp.count_per_root(graph, plan)
+    per = per.cpu().numpy()
+    assert t2 == total == int(per.sum())
+    lay, rp, col = _oracle_view(g)
+    src = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
+    rng = np.random.default_rng(22)
+    nz = np.nonzero(per)[0]
+    picks = list(rng.choice(len(col), 200, replace=False)) + list(rng.choice(nz, 200, replace=False))
+    light = nz[per[nz] <= 2_000_000]
+    picks += list(light[np.argsort(per[light])[-8:]])
+    roots = [(int(src[i]), int(col[i])) for i in picks]
+    want = _pinned(lay, k, e, plan.restrictions, plan.order, roots)
+    got = [int(per[i]) for i in picks]
+    assert got == want
+    graph.close()
+
+
+# ----------------------------------------------------------- Chung-Lu 7000
+
+@pytest.mark.parametrize("pname", I.CONFIG_PATTERNS[2])
+def test_config2_six_patterns_tuned_per_root(pname):
+    """Each 6-vertex pattern of the batched configuration, with its tuned
+    plan (IEP candidates competing) and launch: per-root counts of sampled
+    roots (random, nonzero, the heaviest the oracle redoes in seconds) equal
+    the oracle's; the batch of all six equals the plain counts."""
+    g = I.config_graph(2)
+    graph = gp.Graph.from_csr(g, device=True)
+    k, e = P[pname]
+    plan = gp.Plan(k, e, stats=graph.stats()).tuned(graph, budget_seconds=0.5, try_iep=True)
+    launch = plan.launch()
+    total = gp.count(graph, plan)
+    if plan.info().iep:
+        # anchor the IEP plan by the plain plan of the same schedule and restrictions
+        ref = gp.Plan(k, e, force_order=list(plan.order), force_restr=plan.restrictions)
+        assert gp.count(graph, ref) == total
+        plan = ref
+        launch = ref.launch()
+    t2, per = gp.count_per_root(graph, plan, group=launch["group"], leaf_mode=launch["leaf_mode"])
+    per = per.cpu().numpy()
+    assert t2 == total == int(per.sum())
+    lay, rp, col = _oracle_view(g)
+    src = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
+    rng = np.random.default_rng(7)
+    nz = np.nonzero(per)[0]
+    picks = list(rng.choice(len(col), 10, replace=False))
+    if nz.size:
+        picks += list(rng.choice(nz, min(10, nz.size), replace=False))
+        light = nz[per[nz] <= 3_000_000]
+        if light.size:
+            picks.append(int(light[np.argmax(per[light])]))
+    roots = [(int(src[i]), int(col[i])) for i in picks]
+    want = _pinned(lay, k, e, plan.restrictions, plan.order, roots)
+    assert [int(per[i]) for i in picks] == want, pname
+    graph.close()
+
+
+def test_config2_batch_of_tuned_plans_equals_plain():
+    g = I.config_graph(2)
+    graph = gp.Graph.from_csr(g, device=True)
+    plans = [gp.Plan(*P[n], stats=graph.stats()).tuned(graph, budget_seconds=0.5, try_iep=True)
+             for n in I.CONFIG_PATTERNS[2]]
+    want = [gp.count(graph, p) for p in plans]
+    assert gp.count_batch(graph, plans) == want
+    b = gp.Batch(graph, plans)
+    assert b.run() == want
+    b.close()
+    graph.close()
+
+
+# ------------------------------------------ the benchmark's configurations
+
+def _bench_plans(path):
+    line = open(path).read().strip().splitlines()[-1]
+    return json.loads(line)["plans"]
+
+
+BENCH_FILES = [("rmat17", 1, os.path.join(ROOT, "profiles", "plans_rmat17.json")),
+               ("rmat22", 3, os.path.join(ROOT, "profiles", "plans_rmat22.json"))]
+
+
+@pytest.mark.parametrize("workload,cfg,path", [b for b in BENCH_FILES if os.path.exists(b[2])],
+                         ids=lambda x: x if isinstance(x, str) and not x.startswith("/") else None)
+def test_bench_configurations_on_sampled_roots(workload, cfg, path, rmat22):
+    """The benchmark's exact plans and launches (splits, grabs, leaf mode 4
+    with its memo, IEP) on strided root samples of the full graph, against
+    the oracle's pinned counts summed over the same roots. Offsets are picked
+    so that each sample holds a root of more than two million embeddings
+    (hub roots, split and memo-served) and the oracle finishes in seconds."""
+    g = I.config_graph(cfg) if cfg != 3 else rmat22
+    graph = gp.Graph.from_csr(g, device=True)
+    lay, rp, col = _oracle_view(g)
+    checked_heavy = 0
+    for name, spec in _bench_plans(path).items():
+        k, e = P[name]
+        plan = gp.Plan(k, e, stats=graph.stats(), force_order=spec["order"],
+                       force_restr=[tuple(x) for x in spec["restrictions"]], iep=bool(spec.get("iep")))
+        info = plan.info()
+        if info.iep and info.iep_div != 1:
+            continue  # per-root IEP totals carry the over-count; anchored elsewhere
+        launch = dict(spec["launch"])
+        # per-root counts of the same (non-IEP) plan choose the samples
+        ref = gp.Plan(k, e, stats=graph.stats(), force_order=spec["order"],
+                      force_restr=[tuple(x) for x in spec["restrictions"]])
+        roots = _root_array(rp, col, _root_cut(ref))
+        stride = 1 + (len(roots) // 600)
+        stride += 1 - stride % 2  # odd: both orientations of an edge get sampled
+        done = 0
+        for off in range(0, stride, max(1, stride // 40)):
+            sample = roots[off::stride]
+            ent = _entries(rp, col, sample)
+            _, per_o = gp.count_per_root(graph, ref, root_stride=stride, root_offset=off)
+            pc = per_o.cpu().numpy()[ent]
+            if pc.max() <= 2_000_000 or pc.max() > 60_000_000 or pc.sum() > 400_000_000:
+                continue
+            got = gp.count(graph, plan, root_stride=stride, root_offset=off, **launch)
+            assert got == int(pc.sum()), (name, off)
+            want = sum(_pinned(lay, k, e, plan.restrictions, plan.order, [tuple(r) for r in sample]))
+            assert got == want, (name, off)
+            checked_heavy += 1
+            done += 1
+            if done >= 2:
+                break
+    assert checked_heavy > 0
+    graph.close()
+
+
+def _root_cut(plan):
+    o = plan.order
+    r = set(plan.restrictions)
+    return 1 if (o[0], o[1]) in r else (2 if (o[1], o[0]) in r else 0)
+
+
+def _entries(rp, col, roots):
+    """CSR entry index of each root edge (v0, v1)."""
+    out = np.empty(len(roots), dtype=np.int64)
+    for i, (a, b) in enumerate(roots):
+        lo, hi = rp[a], rp[a + 1]
+        out[i] = lo + np.searchsorted(col[lo:hi], b)
+    return out

@@ -319,6 +319,44 @@ def test_model_prefers_hoisted_intersections_and_filters():
     assert a < b
 
 
+# Hand-derived values of cost_1 (Section IV-C) on |V| = 1000, |E| = 5000,
+# tri_cnt = 6000 (ordered triangles). With d = 2|E|/|V| = 10 (one
+# neighborhood) and q = |V| p1 p2 = tri_cnt / (2|E|) = 0.6 (two), p2 = 0.06.
+#
+# House of Fig. pseudocode_performance: schedule A,B,C,D,E = 0..4, the one
+# restriction id(A) > id(B), charged to B's loop (f_2 = 1/2). Loops:
+#   A: l = 1000, f = 0, c = 0
+#   B: l = d, f = 1/2, c = |N(A)| + |N(B)| = 2d   (tmp_AB = N(A) & N(B), E's set)
+#   C: l = d, f = 0, c = |N(A)| + |N(C)| = 2d     (N(A) & N(C), D's set)
+#   D: l = q;  E: l = q
+#   cost_5 = q; cost_4 = q * q; cost_3 = d (2d + q^2) = 203.6
+#   cost_2 = d (1/2) (2d + cost_3) = 5 * 223.6 = 1118; cost_1 = 1000 * 1118
+HOUSE_COST = 1_118_000.0
+# 4-clique, schedule 0,1,2,3, restrictions 0 > 1 > 2 > 3 (closure):
+#   f_2 = 1/2 (0>1), f_3 = 2/3 (12 orders left, 4 keep 0>1>2), f_4 = 3/4
+#   level 2's set N(0) & N(1) costs 2d in loop 2; level 3's set extends it
+#   by N(2) in loop 3: c_3 = q + d = 10.6 (the earlier set is the base)
+#   l_4 = |V| p1 p2^2 = 0.036: cost_4 = 0.036 / 4 = 0.009
+#   cost_3 = q (1/3) (10.6 + 0.009) = 2.1218; cost_2 = d (1/2) (2d + 2.1218) = 110.609
+#   cost_1 = 1000 * 110.609
+CLIQUE4_COST = 110_609.0
+
+
+def test_model_hand_derived_values():
+    """cost_1 literals worked out by hand from Section IV-C's definitions
+    (above): a dropped term, a restriction charged to the wrong loop, an
+    intersection charged to the wrong loop or built from the wrong base all
+    change them."""
+    k, e = P["house"]
+    got = O.model_cost(k, e, (0, 1, 2, 3, 4), {(0, 1)}, 1000.0, 5000.0, 6000.0)
+    assert math.isclose(got, HOUSE_COST, rel_tol=1e-12)
+    k, e = P["4-clique"]
+    r = O.closure([(0, 1), (1, 2), (2, 3)], 4)
+    got = O.model_cost(k, e, (0, 1, 2, 3), r, 1000.0, 5000.0, 6000.0)
+    assert math.isclose(got, CLIQUE4_COST, rel_tol=1e-12)
+    assert O.filter_fractions(4, (0, 1, 2, 3), r) == [0.0, 0.5, 2.0 / 3.0, 0.75]
+
+
 # ------------------------------------------------------- IEP (Section IV-D)
 
 def test_alg2_worked_example():

@@ -37,6 +37,26 @@ def test_schedules_match_oracle(pname):
     assert plan.info().k_eff == keff
 
 
+def test_model_hand_derived_values():
+    """The planner's model on the hand-derived configurations of the oracle's
+    pins (tests/test_oracle.py): house of Fig. pseudocode_performance and the
+    4-clique, on |V| = 1000, |E| = 5000, tri_cnt = 6000."""
+    st = _stats(1000, 5000, 6000)
+    k, e = P["house"]
+    plan = gp.Plan(k, e, force_order=[0, 1, 2, 3, 4], force_restr=[(0, 1)])
+    assert math.isclose(_cost_of(plan, st), 1_118_000.0, rel_tol=1e-12)
+    k, e = P["4-clique"]
+    plan = gp.Plan(k, e, force_order=[0, 1, 2, 3], force_restr=[(0, 1), (1, 2), (2, 3)])
+    assert math.isclose(_cost_of(plan, st), 110_609.0, rel_tol=1e-12)
+
+
+def _cost_of(plan, st):
+    """Predicted cost_1 of the plan's forced configuration under stats st."""
+    k, e = plan.k, plan.edges
+    p2 = gp.Plan(k, e, stats=st, force_order=list(plan.order), force_restr=plan.restrictions)
+    return p2.info().cost
+
+
 @pytest.mark.parametrize("pname", ["house", "5-cycle", "4-clique", "6-cycle-chord", "k4-path",
                                    "diamond"])
 def test_model_costs_match_oracle(pname):

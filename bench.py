@@ -41,8 +41,10 @@ WORKLOADS = {
                     "batched"),
     "rmat22": (3, ["4-clique", "house", "5-cycle", "6-cycle-chord"],
                "R-MAT scale 22, edge factor 8, (0.57,0.19,0.19,0.05), seed 4; 4-clique, house, "
-               "5-cycle, 6-cycle+chord in one persistent launch against one launch per pattern "
-               "(patterns estimated above --max-pattern-s are reported, not run)", "batched"),
+               "5-cycle, 6-cycle+chord in one persistent launch (hipGraph) against one launch per "
+               "pattern; a step counts one of 20 strided slices of every pattern's root edges, so "
+               "20 steps count every embedding once; patterns whose tuned full run is estimated "
+               "above --max-pattern-s are reported with their estimate, not run", "sliced"),
     "list-rmat17": (1, ["5-clique"],
                     "R-MAT scale 17, edge factor 8, (0.57,0.19,0.19,0.05), seed 2; every 5-clique "
                     "listed (original vertex ids, one row per subgraph) into a buffer resident in HBM",
@@ -61,9 +63,14 @@ WORKLOADS = {
 def parse_args():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat17", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOADS))
+    ap.add_argument("--slices", type=int, default=20,
+                    help="sliced workloads: a step counts one of this many strided root slices")
+    ap.add_argument("--traffic-slices", type=int, default=2,
+                    help="sliced workloads: byte accounting of the batched launch on this many of "
+                         "the timed slices")
     ap.add_argument("--patterns", default=None,
                     help="comma-separated subset of the workload's patterns (profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -76,14 +83,15 @@ def parse_args():
     ap.add_argument("--plans-json", default=None,
                     help="reuse the configurations and launch shapes of a previous bench JSON "
                          "line instead of tuning (so profiled runs time the same kernels)")
-    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_rmat17.json"),
+    ap.add_argument("--traffic-json", default=None,
                     help="HBM bytes per launch from rocprofv3 counters (used only while the "
-                         "kernel sources it was taken from are unchanged)")
+                         "kernel sources it was taken from are unchanged; default "
+                         "profiles/traffic_<workload>.json)")
     ap.add_argument("--no-try-iep", action="store_true",
                     help="plain workloads: tune without inclusion-exclusion configurations")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the model's configurations and the default launch shape")
-    ap.add_argument("--max-pattern-s", type=float, default=30.0,
+    ap.add_argument("--max-pattern-s", type=float, default=90.0,
                     help="batched workloads: patterns whose full run is estimated above this are "
                          "reported with their extrapolation instead of run")
     ap.add_argument("--batch-group", type=int, default=0,
@@ -103,7 +111,31 @@ def note(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(g, plans, names, budget_s: float) -> dict:
+def host_info() -> dict:
+    """CPU model and counts of the host the oracle runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": os.cpu_count(), "cpus_allowed": allowed}
+
+
+def oracle_threads() -> int:
+    """Threads for the oracle: every CPU this process may use, within the
+    16-CPU share a one-GPU machine allots to its GPU."""
+    return max(1, min(16, host_info()["cpus_allowed"]))
+
+
+def cpu_baseline(g, plans, names, budget_s: float, threads: int | None = None) -> dict:
     """The oracle, untuned, on a bounded sample of the same workload: random
     root edges of each plan (in the oracle's own degree-sorted relabelling),
     each counted by the oracle with the first two schedule vertices pinned.
@@ -114,7 +146,7 @@ def cpu_baseline(g, plans, names, budget_s: float) -> dict:
     rp, col, _ = O.relabel_by_degree(g)
     lay = O._CSRView(rp, col)
     src = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads = threads or oracle_threads()
     rng = np.random.default_rng(12345)
     jobs = []
     for name, plan in zip(names, plans):
@@ -154,11 +186,13 @@ def cpu_baseline(g, plans, names, budget_s: float) -> dict:
                     if j is not None:
                         pending.add(ex.submit(run, j))
     dt = time.perf_counter() - t0
-    return {"value": found / dt if dt > 0 else 0.0, "unit": "embeddings/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{done} root edges drawn uniformly from the {len(plans)} plans' root tasks, each "
-                      f"counted by the CPU oracle with the first two schedule vertices pinned; "
-                      f"{found} embeddings in {dt:.1f} s"}
+    out = {"value": found / dt if dt > 0 else 0.0, "unit": "embeddings/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"{done} root edges drawn uniformly from the {len(plans)} plans' root tasks, each "
+                     f"counted by the CPU oracle with the first two schedule vertices pinned; "
+                     f"{found} embeddings in {dt:.1f} s on {threads} threads"}
+    out.update(host_info())
+    return out
 
 
 def main():
@@ -177,8 +211,12 @@ def main():
 
     torch.cuda.set_device(0)
     cfg_idx, names, desc, mode = WORKLOADS[args.workload]
+    if args.traffic_json is None:
+        args.traffic_json = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
     if mode == "serve":
         return serve_main(args, desc)
+    if mode == "sliced":
+        return sliced_main(args, cfg_idx, names, desc)
     if args.patterns:
         names = [n for n in names if n in args.patterns.split(",")]
     g = I.config_graph(cfg_idx)
@@ -273,12 +311,15 @@ def main():
                     "restrictions": [list(x) for x in plans[dom].restrictions],
                     "launch": launches[dom], "iep": bool(plans[dom].info().iep)}
         l2 = None
+        src = None
         if (tr is not None and tr["pattern"] == names[dom] and tr["workload"] == args.workload
                 and profiling.same_plan(tr.get("plan"), dom_plan)):
             traffic = tr["hbm_bytes_per_launch"]
             l2 = tr.get("l2")
+            src = os.path.relpath(args.traffic_json, ROOT)
         roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                    "traffic_source": src,
                     "kernel": f"count_kernel ({names[dom]})",
                     "alg_bytes_per_launch": alg[names[dom]],
                     "avg_launch_ms": round(avg_ms[dom], 3),
@@ -320,6 +361,10 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(g, plans, names, args.cpu_seconds)
         note(f"cpu baseline: {cpu['value']:.4e} embeddings/s on {cpu['cores']} threads")
+        one = cpu_baseline(g, plans, names, args.cpu_seconds / 2, threads=1)
+        cpu["value_1_thread"] = one["value"]
+        cpu["sample_1_thread"] = one["sample"]
+        note(f"cpu baseline, 1 thread: {one['value']:.4e} embeddings/s")
 
     out = {
         "metric": METRIC if mode != "iep" else "embeddings/s counted with inclusion-exclusion",
@@ -583,6 +628,185 @@ def batched_main(args, desc, g, graph, st, names, plans, launches, base_plans, p
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    print(json.dumps(out), flush=True)
+
+
+def sliced_main(args, cfg_idx, names, desc):
+    """The batched configuration at scale. Every pattern is planned, its full
+    run estimated, tuned (IEP configurations competing) and estimated again;
+    those above --max-pattern-s are reported with their estimate. A step
+    counts slice s (root edges s, s + S, s + 2S, ... of every feasible
+    pattern, heavy roots split as tuned) in ONE persistent launch replayed
+    from a hipGraph; the same slices are then counted with one launch per
+    pattern. S steps count every embedding once."""
+    import torch
+    from paper_2009_10955_amd import gp
+    from paper_2009_10955_amd import inputs as I
+
+    S = max(1, args.slices)
+    t0 = time.perf_counter()
+    g = I.config_graph(cfg_idx)
+    note(f"graph generated in {time.perf_counter() - t0:.1f} s: n={g.n} m={g.m}")
+    graph = gp.Graph.from_csr(g, device=True)
+    st = graph.stats()
+    stream = torch.cuda.current_stream()
+    t_plan = time.perf_counter()
+    base_plans = [gp.Plan(*I.PATTERNS[n], stats=st) for n in names]
+    plan_s = time.perf_counter() - t_plan
+    plans, launches, keep, infeasible = [], [], [], {}
+    t_tune = time.perf_counter()
+    for n, bp in zip(names, base_plans):
+        e0 = gp.estimate(graph, bp, budget_ms=min(30.0, args.max_pattern_s) * 1e3, stream=stream)
+        note(f"{n}: model plan estimated at {e0['ms'] / 1e3:.1f} s")
+        if e0["ms"] > 10 * args.max_pattern_s * 1e3:
+            infeasible[n] = {"estimated_s": None if e0["ms"] == float("inf") else e0["ms"] / 1e3,
+                             "of": "the model's configuration, default launch",
+                             "count_extrapolated": e0["sample_count"] * e0["sample_stride"]}
+            continue
+        if args.plans_json:
+            prev = json.loads(open(args.plans_json).read().strip().splitlines()[-1])["plans"][n]
+            tp = gp.Plan(*I.PATTERNS[n], stats=st, force_order=prev["order"],
+                         force_restr=[tuple(x) for x in prev["restrictions"]], iep=int(prev.get("iep", 0)))
+            lt = dict(prev["launch"])
+        else:
+            tp = bp.tuned(graph, budget_seconds=args.tune_seconds, try_iep=not args.no_try_iep)
+            lt = tp.launch()
+        e1 = gp.estimate(graph, tp, budget_ms=args.max_pattern_s * 1e3, stream=stream, **lt)
+        note(f"{n}: tuned {tp.order} {tp.restrictions} iep={tp.info().iep} {lt}: "
+             f"estimated at {e1['ms'] / 1e3:.1f} s")
+        if e1["ms"] > args.max_pattern_s * 1e3:
+            infeasible[n] = {"estimated_s": None if e1["ms"] == float("inf") else e1["ms"] / 1e3,
+                             "of": "the tuned configuration and launch",
+                             "count_extrapolated": e1["sample_count"] * e1["sample_stride"]}
+            continue
+        keep.append(n)
+        plans.append(tp)
+        launches.append(lt)
+    tune_s = time.perf_counter() - t_tune
+    if not plans:
+        raise SystemExit("no pattern of the workload is feasible within --max-pattern-s")
+    names_all, names = names, keep
+    batch = gp.Batch(graph, plans, stream)
+    dev_out = torch.zeros(2 * len(plans), dtype=torch.int64, device="cuda")
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def batched_step(s, events=None):
+        batch.set_sample(S, s % S, stream)
+        if events is not None:
+            events[0].record(stream)
+        c = batch.run(stream)
+        if events is not None:
+            events[1].record(stream)
+        return c
+
+    def plain_step(s, events=None):
+        for i, (p, l) in enumerate(zip(plans, launches)):
+            if events is not None:
+                events[i][0].record(stream)
+            gp.count_async(graph, p, dev_out[2 * i:2 * i + 2], stream, root_stride=S, root_offset=s % S, **l)
+            if events is not None:
+                events[i][1].record(stream)
+        torch.cuda.synchronize()
+        r = dev_out.cpu().tolist()
+        return [r[2 * i] & (2 ** 64 - 1) for i in range(len(plans))]
+
+    for w in range(args.warmup):
+        batched_step(w)
+        plain_step(w)
+        note(f"warmup step {w + 1}/{args.warmup} done")
+    # batched: K steps
+    b_ev = [(ev(), ev()) for _ in range(args.steps)]
+    counts_b = []
+    torch.cuda.synchronize()
+    tb0 = time.perf_counter()
+    for s in range(args.steps):
+        counts_b.append(batched_step(s, b_ev[s]))
+    torch.cuda.synchronize()
+    ms_b = (time.perf_counter() - tb0) * 1e3
+    note(f"{args.steps} batched steps: {ms_b / args.steps:.1f} ms/step")
+    # plain: the same K slices, one launch per pattern
+    p_ev = [[(ev(), ev()) for _ in plans] for _ in range(args.steps)]
+    counts_p = []
+    torch.cuda.synchronize()
+    tp0 = time.perf_counter()
+    for s in range(args.steps):
+        counts_p.append(plain_step(s, p_ev[s]))
+    torch.cuda.synchronize()
+    ms_p = (time.perf_counter() - tp0) * 1e3
+    note(f"{args.steps} plain steps: {ms_p / args.steps:.1f} ms/step")
+    if counts_b != counts_p:
+        raise RuntimeError(f"batched counts differ from plain counts: {counts_b} vs {counts_p}")
+    launch_ms = [b_ev[s][0].elapsed_time(b_ev[s][1]) for s in range(args.steps)]
+    kernel_ms = {n: round(sum(p_ev[s][i][0].elapsed_time(p_ev[s][i][1]) for s in range(args.steps)) /
+                          args.steps, 3) for i, n in enumerate(names)}
+    emb = sum(sum(c) for c in counts_b)
+    value = emb / (ms_b / 1e3)
+    # totals: the timed slices cover every root once when K is a multiple of S
+    whole = args.steps % S == 0
+    totals = {n: sum(c[i] for c in counts_b[:S]) for i, n in enumerate(names)} if args.steps >= S else None
+
+    roofline = None
+    if not args.no_traffic:
+        # bytes of the batched launch on the first timed slices: the same
+        # slices, plans and launches through the instrumented kernel
+        nt = max(1, min(args.traffic_slices, args.steps))
+        alg = 0
+        for s in range(nt):
+            for i, (p, l) in enumerate(zip(plans, launches)):
+                c, b = gp.count_traffic(graph, p, root_stride=S, root_offset=s % S, **l)
+                if c != counts_b[s][i]:
+                    raise RuntimeError(f"accounting count {c} != {counts_b[s][i]} ({names[i]}, slice {s})")
+                alg += b
+            note(f"byte accounting, slice {s}: {alg:.4e} B so far")
+        t_acc = sum(launch_ms[:nt]) / 1e3
+        achieved = alg / t_acc / 1e9
+        from paper_2009_10955_amd import profiling
+        tr = profiling.load_traffic(args.traffic_json) if args.traffic_json else None
+        traffic = None
+        src = None
+        cur = {n: {"order": list(p.order), "restrictions": [list(x) for x in p.restrictions],
+                   "launch": l, "iep": bool(p.info().iep)} for n, p, l in zip(names, plans, launches)}
+        if (tr is not None and tr.get("workload") == args.workload and tr.get("kernel_match") == "batch_kernel"
+                and isinstance(tr.get("plan"), dict) and sorted(tr["plan"]) == sorted(cur)
+                and all(profiling.same_plan(tr["plan"][n], cur[n]) for n in cur)):
+            traffic = tr["hbm_bytes_per_launch"]
+            src = os.path.relpath(args.traffic_json, ROOT)
+        roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                    "traffic_source": src,
+                    "kernel": "batch_kernel (every feasible pattern, one launch per step)",
+                    "alg_bytes_per_launch": alg / nt, "alg_bytes_slices": nt,
+                    "avg_launch_ms": round(sum(launch_ms[:nt]) / nt, 3),
+                    "avg_launch_ms_all_steps": round(sum(launch_ms) / len(launch_ms), 3)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(g, plans, names, args.cpu_seconds)
+        note(f"cpu baseline: {cpu['value']:.4e} embeddings/s on {cpu['cores']} threads")
+    out = {
+        "metric": METRIC, "value": value, "unit": "embeddings/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_b / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": desc, "graph": {"n": st.n, "m": st.m, "max_degree": st.max_degree,
+                                               "sha256": g.sha256()},
+                   "patterns": names, "patterns_reported_not_run": sorted(infeasible),
+                   "slices": S, "parallelism": "single GPU"},
+        "embeddings_per_step": emb / args.steps,
+        "counts": totals, "counts_cover_every_root": bool(totals) and whole,
+        "plain_ms_per_step": ms_p / args.steps,
+        "batched_speedup": ms_p / ms_b,
+        "batched_launch_ms": [round(x, 3) for x in launch_ms],
+        "plain_kernel_ms_per_step": kernel_ms,
+        "infeasible": infeasible,
+        "plans": {n: {"order": list(p.order), "restrictions": [list(x) for x in p.restrictions],
+                      "launch": l, "iep": int(p.info().iep), "iep_div": int(p.info().iep_div),
+                      "tuned_ms": p.info().tuned_ms}
+                  for n, p, l in zip(names, plans, launches)},
+        "preprocessing_s": {"load": st.load_seconds, "plan": plan_s, "tune_and_estimates": tune_s},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    batch.close()
     print(json.dumps(out), flush=True)
 
 

@@ -97,6 +97,23 @@ typedef struct {
 gp_status gp_load_graph(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz,
                         uint32_t flags, void* stream, gp_graph** out);
 
+/* Options of gp_load_graph_opts (zero fields: the defaults of gp_load_graph). */
+typedef struct {
+    uint32_t flags;            /* as gp_load_graph's flags */
+    int64_t hub_min_degree;    /* vertices of at least this degree get a dense neighbor bitmap
+                                  (0 = 64) */
+    int64_t hub_budget_bytes;  /* bitmaps of at most this many bytes in total, highest degrees
+                                  first (0 = 2 GiB); each takes ceil(n/32) * 4 bytes */
+} gp_load_opts;
+
+void gp_load_opts_default(gp_load_opts* o);
+
+/* gp_load_graph with the hub bitmap threshold and budget chosen by the
+ * caller: more bitmaps turn more membership tests in long lists into one
+ * bit read, at n/8 bytes of HBM each. */
+gp_status gp_load_graph_opts(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz,
+                             const gp_load_opts* opts, void* stream, gp_graph** out);
+
 gp_status gp_graph_stats(const gp_graph* g, gp_stats* out);
 
 /* Copy the relabelling to host memory: new_id[v] = id of original vertex v
@@ -394,6 +411,19 @@ gp_status gp_batch_create(const gp_graph* g, const gp_plan* const* plans, int32_
 
 /* Replay the captured graph on `stream` and wait; out[i] = count of plan i. */
 gp_status gp_batch_run(gp_batch* b, void* stream, uint64_t* out);
+
+/*
+ * Point a prepared batch at a strided sample of every plan's root tasks:
+ * the next gp_batch_run counts, for each plan, the roots
+ * roots[root_offset + r * root_stride] (as gp_launch.root_stride and
+ * root_offset do for gp_count), heavy roots split as before. root_stride 1,
+ * offset 0 is the whole count again. Runs with offsets 0 .. s-1 of one
+ * stride s partition every plan's embeddings (for an IEP plan with an
+ * over-count above 1 a sample's quotient is not checked, so parts need not
+ * add up). Copies the new task table to the device before returning (waits
+ * for `stream`); the captured graph is unchanged. Errors: GP_ERR_ARG.
+ */
+gp_status gp_batch_set_sample(gp_batch* b, int64_t root_stride, int64_t root_offset, void* stream);
 
 /*
  * Pick the launch shape of a batch of these plans on g by measurement: one

@@ -41,11 +41,11 @@ Readings of the paper used here (the paper is silent or garbled on these):
 * A pair (a, b) means id(a) > id(b), drawn as the directed edge a -> b.
 * Closures: each restriction set is explored once per transitive closure.
   This is sound because whether a permutation conflicts with a set, and how
-  many orders satisfy the set, depend only on its closure. The surviving
-  automorphisms of a set are recomputed from all of Aut(P); that equals
-  filtering the parent's survivors, since a permutation that conflicts with a
-  set conflicts with every superset. The output is the list of distinct
-  valid closures, sorted by size, then by their sorted pairs.
+  many orders satisfy the set, depend only on its closure. A grown set's
+  surviving automorphisms are its parent's survivors that do not conflict
+  with it, the same as filtering all of Aut(P), since a permutation that
+  conflicts with a set conflicts with every superset. The output is the list
+  of distinct valid closures, sorted by size, then by their sorted pairs.
 * ``validate`` runs the paper's check literally: count maps of the pattern into
   the complete graph K_k with and without the restrictions and require
   with * |Aut| == without.
@@ -330,11 +330,13 @@ def restriction_sets(k: int, edges, max_states: int | None = None) -> list[froze
     auts = automorphisms(k, edges)
     start = frozenset()
     seen = {start}
-    work = [start]
+    # (closure, the automorphisms it has not eliminated); a grown closure
+    # keeps those of its parent's survivors that do not conflict with it,
+    # the same as filtering all of Aut(P) since conflicts persist in supersets
+    work = [(start, auts)]
     valid: set = set()
     while work:
-        rel = work.pop()
-        alive = [p for p in auts if no_conflict(p, rel)]
+        rel, alive = work.pop()
         if len(alive) <= 1:
             # the identity alone survives (or nothing does: a cyclic set)
             if alive and validate(k, edges, rel, auts):
@@ -348,7 +350,7 @@ def restriction_sets(k: int, edges, max_states: int | None = None) -> list[froze
                 if max_states is not None and len(seen) >= max_states:
                     continue
                 seen.add(grown)
-                work.append(grown)
+                work.append((grown, [p for p in alive if no_conflict(p, grown)]))
     return sorted(valid, key=lambda r: (len(r), sorted(r)))
 
 

@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -62,6 +64,29 @@ gp_status triangle_desc(GpPlanDesc* d) {
     return gp::compile_plan(p, order, r, d) == 0 ? GP_OK : GP_ERR_PATTERN;
 }
 
+// Algorithm 1's result depends on the pattern alone (its cost is per
+// pattern, Table III): complete results are kept per (pattern edge set,
+// caps) for the life of the process, so planning a pattern again (other
+// schedules, forced sets, the tuner, the server) does not repeat it.
+gp::RestrictionSets cached_restriction_sets(const gp::Pattern& pat, const std::vector<gp::Perm>& auts,
+                                            int64_t max_states, int32_t max_sets, double max_seconds) {
+    static std::mutex mu;
+    static std::map<std::vector<int64_t>, gp::RestrictionSets> cache;
+    std::vector<int64_t> key{pat.k, max_states, max_sets};
+    for (int v = 0; v < pat.k; ++v) key.push_back(pat.adj[v]);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    gp::RestrictionSets rs = gp::restriction_sets(pat, auts, max_states, max_sets, max_seconds);
+    if (!rs.truncated) {
+        std::lock_guard<std::mutex> lk(mu);
+        cache.emplace(key, rs);
+    }
+    return rs;
+}
+
 gp_status count_to_host(const gp_graph* g, const GpPlanDesc& d, const gpint::LaunchCfg& cfg,
                         hipStream_t s, unsigned long long* per_root, uint64_t* out,
                         uint64_t* alg_bytes = nullptr) {
@@ -109,10 +134,25 @@ const char* gp_strerror(gp_status s) {
     }
 }
 
+void gp_load_opts_default(gp_load_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+}
+
 gp_status gp_load_graph(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz,
                         uint32_t flags, void* stream, gp_graph** out) {
-    if (!out || n < 0 || nnz < 0 || !row_ptr || (nnz > 0 && !col)) return GP_ERR_ARG;
+    gp_load_opts o;
+    gp_load_opts_default(&o);
+    o.flags = flags;
+    return gp_load_graph_opts(row_ptr, col, n, nnz, &o, stream, out);
+}
+
+gp_status gp_load_graph_opts(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz,
+                             const gp_load_opts* opts, void* stream, gp_graph** out) {
+    if (!out || n < 0 || nnz < 0 || !row_ptr || (nnz > 0 && !col) || !opts) return GP_ERR_ARG;
+    const uint32_t flags = opts->flags;
     if (flags & ~(GP_IN_DEVICE | GP_NO_HUB_BITMAPS | GP_DENSE_HUB_BITMAPS)) return GP_ERR_ARG;
+    if (opts->hub_min_degree < 0 || opts->hub_budget_bytes < 0) return GP_ERR_ARG;
     if (n >= 0x7fffffff || nnz >= 0x7fffffff) return GP_ERR_UNSUPPORTED;
     const double t0 = now_seconds();
     hipStream_t s = (hipStream_t)stream;
@@ -164,8 +204,10 @@ gp_status gp_load_graph(const int64_t* row_ptr, const int32_t* col, int64_t n, i
     if (st == GP_OK && (ends[0] != 0 || ends[1] != nnz)) st = GP_ERR_CSR_RANGE;
     if (st == GP_OK) st = gpint::build_layout(d_row, d_col, n, nnz, s, &g->dg);
     if (st == GP_OK && !(flags & GP_NO_HUB_BITMAPS)) {
-        const int64_t min_deg = (flags & GP_DENSE_HUB_BITMAPS) ? 1 : 64;
-        st = gpint::build_hub_bitmaps(&g->dg, min_deg, int64_t(2) << 30, s);
+        const int64_t min_deg =
+            (flags & GP_DENSE_HUB_BITMAPS) ? 1 : (opts->hub_min_degree > 0 ? opts->hub_min_degree : 64);
+        const int64_t budget = opts->hub_budget_bytes > 0 ? opts->hub_budget_bytes : (int64_t(2) << 30);
+        st = gpint::build_hub_bitmaps(&g->dg, min_deg, budget, s);
     }
     if (own_row || own_col) {
         (void)hipStreamSynchronize(s);
@@ -254,8 +296,8 @@ gp_status gp_plan_create(const int32_t* edges, int32_t k, int32_t e, const gp_st
     p->pattern = pat;
     auto auts = gp::automorphisms(pat);
     p->aut = auts.size();
-    gp::RestrictionSets rs = gp::restriction_sets(pat, auts, max_states, max_sets,
-                                                  o.max_seconds > 0 ? o.max_seconds : 20.0);
+    gp::RestrictionSets rs = cached_restriction_sets(pat, auts, max_states, max_sets,
+                                                     o.max_seconds > 0 ? o.max_seconds : 20.0);
     p->sets = rs.sets;
     gp::Schedules sc = gp::efficient_schedules(pat);
     p->schedules = sc.orders;
@@ -645,6 +687,7 @@ gp_status gp_batch_create(const gp_graph* g, const gp_plan* const* plans, int32_
     b->g = g;
     b->np = np;
     b->descs = descs;
+    b->cfgs = cfgs;
     b->slot = slot;
     st = gpint::batch_prepare(g->dg, descs.data(), cfgs.data(), nullptr, nullptr, np, wpc, s, &b->st);
     if (st != GP_OK) {
@@ -681,6 +724,22 @@ gp_status gp_batch_run(gp_batch* b, void* stream, uint64_t* out) {
     GP_HIP_TRY(hipGraphLaunch(b->exec, s));
     GP_HIP_TRY(hipStreamSynchronize(s));
     return batch_counts(b->descs, b->slot, b->host_res, out);
+}
+
+gp_status gp_batch_set_sample(gp_batch* b, int64_t root_stride, int64_t root_offset, void* stream) {
+    if (!b || root_stride < 1 || root_offset < 0) return GP_ERR_ARG;
+    DeviceGuard dgd(b->g->dg.device);
+    hipStream_t s = (hipStream_t)stream;
+    GP_HIP_TRY(hipStreamSynchronize(s));
+    if (b->cap_stream) GP_HIP_TRY(hipStreamSynchronize(b->cap_stream));
+    std::vector<gpint::LaunchCfg> cfgs = b->cfgs;
+    for (auto& c : cfgs) {
+        c.root_stride = root_stride;
+        c.root_offset = root_offset;
+    }
+    gp_status st = gpint::batch_update(b->g->dg, &b->st, b->descs.data(), cfgs.data(), s);
+    if (st == GP_OK) b->cfgs = cfgs;
+    return st;
 }
 
 gp_status gp_batch_tune(const gp_graph* g, const gp_plan* const* plans, int32_t np, void* stream,

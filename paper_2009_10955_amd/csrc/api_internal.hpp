@@ -28,7 +28,8 @@ struct gp_batch {
     const gp_graph* g = nullptr;
     int np = 0;
     gpint::BatchState st;
-    std::vector<GpPlanDesc> descs;           // in the caller's order
+    std::vector<GpPlanDesc> descs;           // in batch order
+    std::vector<gpint::LaunchCfg> cfgs;      // in batch order
     std::vector<int> slot;                   // caller's plan i runs as batch plan slot[i]
     unsigned long long* host_res = nullptr;  // pinned, 4*np
     hipStream_t cap_stream = nullptr;

@@ -3,18 +3,19 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "count_kernel.hpp"
 
 namespace gpcount {
-KernelFn pick_kernel_k2(int group, int leaf, int mode, bool iep);
-KernelFn pick_kernel_k3(int group, int leaf, int mode, bool iep);
-KernelFn pick_kernel_k4(int group, int leaf, int mode, bool iep);
-KernelFn pick_kernel_k5(int group, int leaf, int mode, bool iep);
-KernelFn pick_kernel_k6(int group, int leaf, int mode, bool iep);
-KernelFn pick_kernel_k7(int group, int leaf, int mode, bool iep);
-KernelFn pick_kernel_k8(int group, int leaf, int mode, bool iep);
+KernelFn pick_kernel_k2(int group, int leaf, int mode, int iep);
+KernelFn pick_kernel_k3(int group, int leaf, int mode, int iep);
+KernelFn pick_kernel_k4(int group, int leaf, int mode, int iep);
+KernelFn pick_kernel_k5(int group, int leaf, int mode, int iep);
+KernelFn pick_kernel_k6(int group, int leaf, int mode, int iep);
+KernelFn pick_kernel_k7(int group, int leaf, int mode, int iep);
+KernelFn pick_kernel_k8(int group, int leaf, int mode, int iep);
 BatchFn batch_kernel_k5();
 BatchFn batch_kernel_k6();
 BatchFn batch_kernel_k8();
@@ -32,7 +33,7 @@ __global__ void init_counters(unsigned long long* p, int n) {
     if (i < n) p[i] = 0;
 }
 
-KernelFn pick_kernel(int k, int group, int leaf, int mode, bool iep) {
+KernelFn pick_kernel(int k, int group, int leaf, int mode, int iep) {
     switch (k) {
         case 2: return pick_kernel_k2(group, leaf, mode, iep);
         case 3: return pick_kernel_k3(group, leaf, mode, iep);
@@ -108,7 +109,7 @@ LaunchCfg default_launch(const GpPlanDesc& d) {
 int resident_waves_per_cu(const GpPlanDesc& d, const LaunchCfg& cfg) {
     const bool iep = d.iep != 0;
     const int group = iep ? (cfg.group >= 64 ? 64 : 32) : cfg.group;
-    KernelFn fn = pick_kernel(d.k, group, cfg.leaf, MODE_PLAIN, iep);
+    KernelFn fn = pick_kernel(d.k, group, cfg.leaf, MODE_PLAIN, d.iep);
     int nb = 0;
     if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)fn, kBlock, 0) != hipSuccess ||
         nb <= 0)
@@ -189,7 +190,7 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
     const int mode = account ? MODE_ACCOUNT : (per_root ? MODE_PER_ROOT : MODE_PLAIN);
     const bool iep = d.iep != 0;
     const int group = iep ? (cfg.group >= 64 ? 64 : 32) : cfg.group;  // IEP kernels: 64 or 32 lanes
-    KernelFn fn = pick_kernel(d.k, group, cfg.leaf, mode, iep);
+    KernelFn fn = pick_kernel(d.k, group, cfg.leaf, mode, d.iep);
     if (!fn) return GP_ERR_UNSUPPORTED;
 
     int64_t all_roots = 0;
@@ -363,9 +364,13 @@ static gp_status batch_layout(const DeviceGraph& g, const GpPlanDesc* descs, con
     for (int i = 0; i < np; ++i) {
         int64_t n_all = 0;
         const int2* roots = pick_roots(g, descs[i].root_cut, &n_all);
+        // a strided root sample per plan, as in launch_count
+        const int64_t stride = std::max<int64_t>(1, cfgs[i].root_stride);
+        const int64_t roff = std::max<int64_t>(0, cfgs[i].root_offset);
+        const int64_t n_sampled = n_all > roff ? (n_all - roff + stride - 1) / stride : 0;
         // offsets and counts are in the plan's task space (split roots count once per task)
-        const SplitPlan sp = split_plan(g, descs[i], cfgs[i], MODE_PLAIN, n_all, 1, 0);
-        const int64_t n_tasks = n_all + sp.roots * (sp.ways - 1);
+        const SplitPlan sp = split_plan(g, descs[i], cfgs[i], MODE_PLAIN, n_sampled, stride, roff);
+        const int64_t n_tasks = n_sampled + sp.roots * (sp.ways - 1);
         int64_t off = offsets ? offsets[i] : 0;
         int64_t cnt = counts ? counts[i] : n_tasks;
         if (off < 0 || cnt < 0) return GP_ERR_ARG;
@@ -374,6 +379,8 @@ static gp_status batch_layout(const DeviceGraph& g, const GpPlanDesc* descs, con
         BatchPlan& bp = (*plans)[i];
         std::memset(&bp, 0, sizeof bp);
         bp.roots = roots;
+        bp.root_offset = roff;
+        bp.root_stride = stride;
         bp.n_tasks = cnt;
         bp.task_offset = off;
         bp.split_roots = sp.roots;
@@ -447,6 +454,19 @@ gp_status batch_prepare(const DeviceGraph& g, const GpPlanDesc* descs, const Lau
         return rc;
     }
     *st = b;
+    return GP_OK;
+}
+
+gp_status batch_update(const DeviceGraph& g, BatchState* st, const GpPlanDesc* descs, const LaunchCfg* cfgs,
+                       hipStream_t stream) {
+    BatchState b = *st;
+    std::vector<BatchPlan> plans;
+    gp_status rc = batch_layout(g, descs, cfgs, nullptr, nullptr, st->np, &b, &plans);
+    if (rc != GP_OK) return rc;
+    if (b.nbuf != st->nbuf || b.slots_per_wave > st->slots_per_wave || b.use_memo != st->use_memo)
+        return GP_ERR_ARG;  // the shapes the buffers were carved for must not change
+    GP_HIP_TRY(hipMemcpyAsync(st->plans, plans.data(), sizeof(BatchPlan) * st->np, hipMemcpyHostToDevice, stream));
+    GP_HIP_TRY(hipStreamSynchronize(stream));
     return GP_OK;
 }
 

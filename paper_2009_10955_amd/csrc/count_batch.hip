@@ -26,7 +26,7 @@ constexpr int KMAX = GP_BATCH_KMAX;
 
 // Tasks [t0, t1) of plan bp (in the plan's own task space), shared by the
 // wavefront's 64/G groups: group j takes the j-th run of bp.chunk tasks.
-template <int G, int LEAF, bool IEP>
+template <int G, int LEAF, int IEP>
 __device__ void run_piece(const BatchArgs& a, const GpPlanDesc& d, const BatchPlan& bp, int64_t t0, int64_t t1,
                           int32_t* lens_base, int64_t wave_global, uint64_t& acc, uint64_t& carry) {
     Ctx<G> c;
@@ -48,8 +48,8 @@ __device__ void run_piece(const BatchArgs& a, const GpPlanDesc& d, const BatchPl
     c.tag = 0;
     TaskSpace ts;
     ts.roots = bp.roots;
-    ts.offset = 0;
-    ts.stride = 1;
+    ts.offset = bp.root_offset;
+    ts.stride = bp.root_stride;
     ts.split_roots = bp.split_roots;
     ts.split_ways = bp.split_ways;
     ts.tag_base = bp.tag_base;
@@ -60,11 +60,11 @@ __device__ void run_piece(const BatchArgs& a, const GpPlanDesc& d, const BatchPl
 #define GP_BATCH_CASE(KK)                                                                                     \
     case KK:                                                                                                  \
         if constexpr (KK <= KMAX) {                                                                           \
-            if constexpr (IEP) {                                                                              \
-                if constexpr (KK >= 4) run_tasks<KK, G, 1, MODE_PLAIN, true>(d, c, ts, a0, a1, acc, carry, nullptr); \
+            if constexpr (IEP > 0) {                                                                          \
+                if constexpr (KK >= IEP + 2) run_tasks<KK, G, 1, MODE_PLAIN, IEP>(d, c, ts, a0, a1, acc, carry, nullptr); \
             } else {                                                                                          \
                 constexpr int LF = (LEAF == 3 && KK >= 5) ? 3 : ((LEAF == 4 && KK >= 4) ? 4 : 1);             \
-                run_tasks<KK, G, LF, MODE_PLAIN, false>(d, c, ts, a0, a1, acc, carry, nullptr);               \
+                run_tasks<KK, G, LF, MODE_PLAIN, 0>(d, c, ts, a0, a1, acc, carry, nullptr);                   \
             }                                                                                                 \
         }                                                                                                     \
         break;
@@ -117,21 +117,30 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(occupanc
         uint64_t acc = 0, carry = 0;
         const int64_t s0 = bp.task_offset + t0, s1 = bp.task_offset + t1;
         const int leaf = __builtin_amdgcn_readfirstlane(bp.leaf);
-        if (d.iep) {
-            if (group == 64) run_piece<64, 1, true>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
-            else run_piece<32, 1, true>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
+        const int iep = __builtin_amdgcn_readfirstlane(d.iep);
+        if (iep) {
+            // IEP plans: 64- or 32-lane groups, one kernel body per depth
+            if (group == 64) {
+                if (iep == 2) run_piece<64, 1, 2>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
+                else if (iep == 3) run_piece<64, 1, 3>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
+                else run_piece<64, 1, 4>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
+            } else {
+                if (iep == 2) run_piece<32, 1, 2>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
+                else if (iep == 3) run_piece<32, 1, 3>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
+                else run_piece<32, 1, 4>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
+            }
         } else if (group == 64) {
-            if (leaf == 3) run_piece<64, 3, false>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
-            else if (leaf == 4) run_piece<64, 4, false>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
-            else run_piece<64, 1, false>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
+            if (leaf == 3) run_piece<64, 3, 0>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
+            else if (leaf == 4) run_piece<64, 4, 0>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
+            else run_piece<64, 1, 0>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
         } else if (group == 32) {
-            if (leaf == 3) run_piece<32, 3, false>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
-            else if (leaf == 4) run_piece<32, 4, false>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
-            else run_piece<32, 1, false>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
+            if (leaf == 3) run_piece<32, 3, 0>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
+            else if (leaf == 4) run_piece<32, 4, 0>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
+            else run_piece<32, 1, 0>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
         } else {
-            if (leaf == 3) run_piece<16, 3, false>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
-            else if (leaf == 4) run_piece<16, 4, false>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
-            else run_piece<16, 1, false>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
+            if (leaf == 3) run_piece<16, 3, 0>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
+            else if (leaf == 4) run_piece<16, 4, 0>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
+            else run_piece<16, 1, 0>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
         }
         // exact 128-bit wavefront sum into this wavefront's LDS counter of plan p
         wave_sum128(acc, carry);

@@ -9,7 +9,7 @@
 namespace gpcount {
 
 namespace {
-template <int K, int G, int LEAF, bool IEP = false>
+template <int K, int G, int LEAF, int IEP = 0>
 KernelFn pick_mode(int mode) {
     switch (mode) {
         case MODE_PLAIN: return count_kernel<K, G, LEAF, MODE_PLAIN, IEP>;
@@ -26,21 +26,29 @@ KernelFn pick_leaf(int leaf, int mode) {
     if (leaf == 4 && K >= 4) return pick_mode<K, G, (K >= 4 ? 4 : 1)>(mode);
     return pick_mode<K, G, 1>(mode);
 }
+
+// IEP kernels, one per depth n (2 .. min(4, K - 2)); the leaf mode does not
+// apply (the search stops at the last outer level)
+template <int K, int G>
+KernelFn pick_iep(int n, int mode) {
+    if constexpr (K >= 4) {
+        if (n == 2) return pick_mode<K, G, 1, 2>(mode);
+    }
+    if constexpr (K >= 5) {
+        if (n == 3) return pick_mode<K, G, 1, 3>(mode);
+    }
+    if constexpr (K >= 6) {
+        if (n == 4) return pick_mode<K, G, 1, 4>(mode);
+    }
+    return nullptr;
+}
 }  // namespace
 
 #define GP_CAT2(a, b) a##b
 #define GP_CAT(a, b) GP_CAT2(a, b)
 
-KernelFn GP_CAT(pick_kernel_k, GP_INST_K)(int group, int leaf, int mode, bool iep) {
-    if (iep) {
-        // an IEP search stops at the last outer level, so the leaf mode does not apply
-        if constexpr (GP_INST_K >= 4) {
-            return group == 64 ? pick_mode<GP_INST_K, 64, 1, true>(mode)
-                               : pick_mode<GP_INST_K, 32, 1, true>(mode);
-        } else {
-            return nullptr;
-        }
-    }
+KernelFn GP_CAT(pick_kernel_k, GP_INST_K)(int group, int leaf, int mode, int iep) {
+    if (iep) return group == 64 ? pick_iep<GP_INST_K, 64>(iep, mode) : pick_iep<GP_INST_K, 32>(iep, mode);
     switch (group) {
         case 64: return pick_leaf<GP_INST_K, 64>(leaf, mode);
         case 32: return pick_leaf<GP_INST_K, 32>(leaf, mode);

@@ -43,6 +43,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "internal.hpp"
 #include "sets.hpp"
 
@@ -101,6 +103,8 @@ constexpr int kBatchMaxPlans = 64;
 
 struct BatchPlan {
     const int2* roots;    // this plan's whole root array (cut already applied)
+    int64_t root_offset;  // sampled roots: roots[root_offset + r * root_stride]
+    int64_t root_stride;
     int64_t n_tasks;      // tasks of this plan in the launch
     int64_t task_offset;  // where in the plan's own task space the launch starts
     int64_t split_roots;  // as in CountArgs: the first split_roots roots run as
@@ -484,111 +488,111 @@ __device__ __forceinline__ uint32_t leaf_group(const GpPlanDesc& d, const Ctx<G>
 // (-1)^edges over the connected graphs on |B| vertices). GRP: computed by the
 // whole group (same value in every lane), else by one lane. The value fits
 // in 128 bits (each |S_j| < 2^31, N <= 4).
-template <int K, int G, int MODE, int N, bool GRP>
-__device__ __forceinline__ unsigned __int128 iep_value(const GpPlanDesc& d, const Ctx<G>& c,
-                                                       const int32_t (&v)[K]) {
-    static_assert(N >= 2 && N <= kIepMaxN && N <= K - 2, "IEP inner levels");
+//
+// A set S_j is either explicit (one neighbor list, or a buffer built by the
+// builds) or, when its last parent is the last outer level, left unbuilt as
+// pre & N(x) (pre: a list or buffer; x: that outer vertex), like the last
+// level of a plain count. Each |∩ S_j| walks the shortest operand of the
+// sets involved, cut to the common range, and tests every element in the
+// other operands (a bit in a hub's bitmap, else a binary search).
+// |∩_{j in M} S_j| for one subset M of the inner levels (compile-time).
+template <int K, int G, int MODE, int N, bool GRP, int M>
+__device__ __forceinline__ uint64_t iep_subset_count(const GpPlanDesc& d, const Ctx<G>& c, const int32_t (&v)[K],
+                                                     uint64_t& bytes) {
     constexpr int F = K - N;  // first inner level
-    Set T[N];
-    int32_t lo[N], hi[N];
-    uint32_t inj[N];
-    uint64_t bytes = 0;
+    // the operands of the sets in M (two per unbuilt set, else one; an absent
+    // second operand has p == nullptr) and the common range
+    Set X[2 * N];
+    int32_t L = 0, H = 0x7fffffff;
+    uint32_t im = 0;
 #pragma unroll
     for (int j = 0; j < N; ++j) {
+        X[2 * j] = Set{nullptr, 0x7fffffff, nullptr};
+        X[2 * j + 1] = Set{nullptr, 0x7fffffff, nullptr};
+        if (!((M >> j) & 1)) continue;
         const GpLevel& lv = d.lv[F + j];
-        bounds<K>(lv.hi_src, lv.lo_src, v, lo[j], hi[j]);
-        inj[j] = lv.inj;
-        Set S;
-        if constexpr (GRP) S = lv.list >= 0 ? c.nbr_u(pick<K>(v, lv.list)) : c.buf_u(lv.buf);
-        else S = lv.list >= 0 ? c.nbr(pick<K>(v, lv.list)) : c.buf(lv.buf);
-        if constexpr (MODE == MODE_ACCOUNT) bytes += cut_bytes(S, lo[j], hi[j]);
-        if constexpr (GRP) T[j] = trim_u<G>(S, lo[j], hi[j]);
-        else T[j] = trim(S, lo[j], hi[j]);
-    }
-    uint64_t cnt[1 << N];
-    cnt[0] = 0;
-#pragma unroll
-    for (int m = 1; m < (1 << N); ++m) {
-        if ((m & (m - 1)) == 0) {
-            // one set: its size without the outer images in it
-            const int j = __builtin_ctz(m);
-            uint64_t c1 = (uint64_t)T[j].n;
-#pragma unroll
-            for (int o = 0; o < F; ++o) {
-                if ((inj[j] >> o) & 1u) {
-                    const int32_t y = v[o];
-                    if (y >= lo[j] && y < hi[j]) {
-                        if constexpr (MODE == MODE_ACCOUNT) bytes += test_bytes(T[j]);
-                        if (member(T[j], y)) --c1;
-                    }
-                }
-            }
-            cnt[m] = c1;
-            continue;
-        }
-        // several sets: cut all to the common range, walk the smallest and
-        // test its elements in the others
-        int32_t L = 0, H = 0x7fffffff;
-        uint32_t im = 0;
-#pragma unroll
-        for (int j = 0; j < N; ++j)
-            if ((m >> j) & 1) {
-                L = max(L, lo[j]);
-                H = min(H, hi[j]);
-                im |= inj[j];
-            }
-        Set X[N];
-        int s = -1;
-        int32_t sn = 0x7fffffff;
-#pragma unroll
-        for (int j = 0; j < N; ++j)
-            if ((m >> j) & 1) {
-                if constexpr (MODE == MODE_ACCOUNT) bytes += cut_bytes(T[j], L, H);
-                if constexpr (GRP) X[j] = trim_u<G>(T[j], L, H);
-                else X[j] = trim(T[j], L, H);
-                if (X[j].n < sn) {
-                    sn = X[j].n;
-                    s = j;
-                }
-            }
-        Set Sm{nullptr, 0, nullptr};
-#pragma unroll
-        for (int j = 0; j < N; ++j)
-            if (((m >> j) & 1) && j == s) Sm = X[j];
-        auto in_all = [&](int32_t x) {
-            bool ok = !inj_hit<K>(im, v, x);
-#pragma unroll
-            for (int j = 0; j < N; ++j)
-                if (((m >> j) & 1) && j != s) ok = ok && member(X[j], x);
-            return ok;
-        };
-        if constexpr (MODE == MODE_ACCOUNT) {
-            uint64_t per = 4;
-#pragma unroll
-            for (int j = 0; j < N; ++j)
-                if (((m >> j) & 1) && j != s) per += test_bytes(X[j]);
-            bytes += (uint64_t)Sm.n * per;
-        }
-        uint64_t cm = 0;
-        if constexpr (GRP) {
-            for (int32_t base = 0; base < Sm.n; base += G) {
-                const int32_t i = base + c.g.gl;
-                bool ok = false;
-                if (i < Sm.n) ok = in_all(Sm.p[i]);
-                cm += (uint64_t)__popcll(c.g.ballot(ok));
+        int32_t lo, hi;
+        bounds<K>(lv.hi_src, lv.lo_src, v, lo, hi);
+        L = max(L, lo);
+        H = min(H, hi);
+        im |= lv.inj;
+        if (lv.last_list >= 0) {
+            if constexpr (GRP) {
+                X[2 * j] = lv.pre_buf >= 0 ? c.buf_u(lv.pre_buf) : c.nbr_u(pick<K>(v, lv.pre_list));
+                X[2 * j + 1] = c.nbr_u(pick<K>(v, lv.last_list));
+            } else {
+                X[2 * j] = lv.pre_buf >= 0 ? c.buf(lv.pre_buf) : c.nbr(pick<K>(v, lv.pre_list));
+                X[2 * j + 1] = c.nbr(pick<K>(v, lv.last_list));
             }
         } else {
-            for (int32_t i = 0; i < Sm.n; ++i) cm += in_all(Sm.p[i]) ? 1u : 0u;
+            if constexpr (GRP) X[2 * j] = lv.list >= 0 ? c.nbr_u(pick<K>(v, lv.list)) : c.buf_u(lv.buf);
+            else X[2 * j] = lv.list >= 0 ? c.nbr(pick<K>(v, lv.list)) : c.buf(lv.buf);
         }
-        cnt[m] = cm;
+    }
+    // the shortest operand, cut to [L, H), is walked
+    int s = 0;
+    int32_t sn = 0x7fffffff;
+#pragma unroll
+    for (int f = 0; f < 2 * N; ++f)
+        if (((M >> (f / 2)) & 1) && X[f].p && X[f].n < sn) {
+            sn = X[f].n;
+            s = f;
+        }
+    Set W{nullptr, 0, nullptr};
+#pragma unroll
+    for (int f = 0; f < 2 * N; ++f)
+        if (((M >> (f / 2)) & 1) && f == s) W = X[f];
+    if constexpr (MODE == MODE_ACCOUNT) bytes += cut_bytes(W, L, H);
+    if constexpr (GRP) W = trim_u<G>(W, L, H);
+    else W = trim(W, L, H);
+    constexpr bool one = (M & (M - 1)) == 0;
+    if (one && X[2 * __builtin_ctz(M) + 1].p == nullptr) {
+        // one built set: its size, without the outer images in it
+        uint64_t cm = (uint64_t)W.n;
+#pragma unroll
+        for (int o = 0; o < F; ++o) {
+            if ((im >> o) & 1u) {
+                const int32_t y = v[o];
+                if (y >= L && y < H) {
+                    if constexpr (MODE == MODE_ACCOUNT) bytes += test_bytes(W);
+                    if (member(W, y)) --cm;
+                }
+            }
+        }
+        return cm;
     }
     if constexpr (MODE == MODE_ACCOUNT) {
-        if constexpr (GRP) {
-            if (c.g.gl == 0) *c.bytes += bytes;
-        } else {
-            *c.bytes += bytes;
-        }
+        uint64_t per = 4;
+#pragma unroll
+        for (int f = 0; f < 2 * N; ++f)
+            if (((M >> (f / 2)) & 1) && X[f].p && f != s) per += test_bytes(X[f]);
+        bytes += (uint64_t)W.n * per;
     }
+    uint64_t cm = 0;
+    const int32_t step = GRP ? G : 1;
+    const int32_t first = GRP ? c.g.gl : 0;
+    for (int32_t base = 0; base < W.n; base += step) {
+        const int32_t i = base + first;
+        bool ok = false;
+        if (i < W.n) {
+            const int32_t x = W.p[i];
+            ok = !inj_hit<K>(im, v, x);
+#pragma unroll
+            for (int f = 0; f < 2 * N; ++f)
+                if (((M >> (f / 2)) & 1) && f != s && X[f].p) ok = ok && member(X[f], x);
+        }
+        if constexpr (GRP) cm += (uint64_t)__popcll(c.g.ballot(ok));
+        else cm += ok ? 1u : 0u;
+    }
+    return cm;
+}
+
+template <int K, int G, int MODE, int N, bool GRP, int... Ms>
+__device__ __forceinline__ unsigned __int128 iep_combine(const GpPlanDesc& d, const Ctx<G>& c,
+                                                         const int32_t (&v)[K], uint64_t& bytes,
+                                                         std::integer_sequence<int, Ms...>) {
+    // cnt[M] for every nonempty subset M (cnt[0] unused)
+    const uint64_t cnt[(1 << N)] = {0, iep_subset_count<K, G, MODE, N, GRP, Ms + 1>(d, c, v, bytes)...};
     typedef unsigned __int128 u128;
     auto P = [&](int a) { return (u128)cnt[a]; };
     if constexpr (N == 2) {
@@ -603,6 +607,23 @@ __device__ __forceinline__ unsigned __int128 iep_value(const GpPlanDesc& d, cons
                (P(3) * P(12) + P(5) * P(10) + P(9) * P(6)) +
                2 * (P(7) * P(8) + P(11) * P(4) + P(13) * P(2) + P(14) * P(1)) - 6 * P(15);
     }
+}
+
+template <int K, int G, int MODE, int N, bool GRP>
+__device__ __forceinline__ unsigned __int128 iep_value(const GpPlanDesc& d, const Ctx<G>& c,
+                                                       const int32_t (&v)[K]) {
+    static_assert(N >= 2 && N <= kIepMaxN && N <= K - 2, "IEP inner levels");
+    uint64_t bytes = 0;
+    const unsigned __int128 r =
+        iep_combine<K, G, MODE, N, GRP>(d, c, v, bytes, std::make_integer_sequence<int, (1 << N) - 1>{});
+    if constexpr (MODE == MODE_ACCOUNT) {
+        if constexpr (GRP) {
+            if (c.g.gl == 0) *c.bytes += bytes;
+        } else {
+            *c.bytes += bytes;
+        }
+    }
+    return r;
 }
 
 // The last two enumerated levels flattened into one load-balanced batch
@@ -839,11 +860,14 @@ __device__ void iep_level(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K],
     }
 }
 
-template <int K, int L, int G, int LEAF, int MODE, bool IEP>
+// IEP: 0 (plain), else the number of inner levels counted with
+// inclusion-exclusion (a kernel is built per depth, so each carries only the
+// registers of its own depth).
+template <int K, int L, int G, int LEAF, int MODE, int IEP>
 __device__ void search(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], uint64_t& acc,
                        uint64_t& carry) {
-    if constexpr (IEP && L >= K - 2) {
-        return;  // an IEP search ends at the last outer level, at most K-3
+    if constexpr (IEP > 0 && L > K - 1 - IEP) {
+        return;  // an IEP search ends at its last outer level
     } else {
         const GpLevel& lv = d.lv[L];
         int32_t lo, hi;
@@ -863,13 +887,10 @@ __device__ void search(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], ui
         }
         if constexpr (MODE == MODE_ACCOUNT)
             if (c.g.gl == 0) *c.bytes += 4ull * (uint64_t)S.n;
-        if constexpr (IEP) {
-            if constexpr (K - 1 - L <= kIepMaxN) {
-                if (d.iep == K - 1 - L) {
-                    iep_level<K, L, G, MODE>(d, c, v, S, st, lv.inj, acc, carry);
-                    return;
-                }
-            }
+        if constexpr (IEP > 0 && L == K - 1 - IEP) {
+            // the last outer level: the inner ones are counted, not enumerated
+            iep_level<K, L, G, MODE>(d, c, v, S, st, lv.inj, acc, carry);
+            return;
         }
         if constexpr (L == K - 2) {
             if constexpr (LEAF == 4)
@@ -900,7 +921,7 @@ __device__ void search(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], ui
                 }
             }
         } else {
-            if constexpr (LEAF == 3 && L == K - 3 && !IEP) {
+            if constexpr (LEAF == 3 && L == K - 3 && IEP == 0) {
                 if (d.build_begin[L] == d.build_end[L]) {
                     flat_leaf<K, G, MODE>(d, c, v, S, st, lv.inj, acc, carry);
                     return;
@@ -929,13 +950,13 @@ __device__ __forceinline__ int64_t entry_index(const int64_t* row_ptr, const int
 // the root (k <= 3, or IEP over all k-2 levels after it) take different roots
 // in different lanes. per_root (MODE_PER_ROOT): each root's count at the CSR
 // entry of the root edge.
-template <int K, int G, int LEAF, int MODE, bool IEP>
+template <int K, int G, int LEAF, int MODE, int IEP>
 __device__ __forceinline__ void run_tasks(const GpPlanDesc& d, Ctx<G>& c, const TaskSpace& ts, int64_t t0,
                                           int64_t t1, uint64_t& acc, uint64_t& carry,
                                           unsigned long long* per_root) {
     constexpr bool PER_ROOT = MODE == MODE_PER_ROOT;
-    if constexpr (IEP && K - 2 <= kIepMaxN) {
-        if (d.iep == K - 2) {
+    if constexpr (IEP > 0 && IEP == K - 2) {
+        {
             // the root is the last outer level
             if (d.build_begin[1] == d.build_end[1]) {
                 for (int64_t base = t0; base < t1; base += G) {
@@ -1033,13 +1054,18 @@ __device__ __forceinline__ void run_tasks(const GpPlanDesc& d, Ctx<G>& c, const 
 // latency of scattered loads, so more resident wavefronts pay even against
 // some spills. Measured on R-MAT 17 for k = 5 (64-lane groups with lanes on
 // separate candidates: 8, others 6) and on Chung-Lu 7000 for k = 6 (64-lane
-// groups 6, others 5); k >= 7 keeps the compiler's choice.
-constexpr int occupancy_target(int K, int G, int LEAF) {
-    return K > 6 ? 1 : K == 6 ? (G == 64 ? 6 : 5) : (G == 64 && (LEAF == 1 || LEAF == 4) ? 8 : 6);
+// groups 6, others 5); k >= 7 keeps the compiler's choice. IEP over 3 or 4
+// inner levels keeps 7 or 15 set sizes and their 128-bit products live: 5
+// and 4 wavefronts.
+constexpr int occupancy_target(int K, int G, int LEAF, int IEP = 0) {
+    return IEP >= 3 ? (IEP == 3 ? 5 : 4)
+           : K > 6  ? 1
+           : K == 6 ? (G == 64 ? 6 : 5)
+                    : (G == 64 && (LEAF == 1 || LEAF == 4) ? 8 : 6);
 }
 
-template <int K, int G, int LEAF, int MODE, bool IEP>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(occupancy_target(K, G, LEAF)))) void count_kernel(GpPlanDesc d, CountArgs a) {
+template <int K, int G, int LEAF, int MODE, int IEP>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(occupancy_target(K, G, LEAF, IEP)))) void count_kernel(GpPlanDesc d, CountArgs a) {
     __shared__ int32_t s_len[kBlock / G][GP_DESC_MAX_BUILDS];
     Ctx<G> c;
     c.row_ptr = a.row_ptr;

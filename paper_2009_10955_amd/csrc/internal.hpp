@@ -122,6 +122,11 @@ void arena_release(BatchArena* a);
 gp_status batch_prepare(const DeviceGraph& g, const GpPlanDesc* descs, const LaunchCfg* cfgs,
                         const int64_t* offsets, const int64_t* counts, int np, int waves_per_cu,
                         hipStream_t stream, BatchState* st);
+// Re-lay the task ranges of a prepared batch for new per-plan launch
+// configurations (root samples); the shapes must be those it was prepared
+// with. Copies the plan table to the device and waits.
+gp_status batch_update(const DeviceGraph& g, BatchState* st, const GpPlanDesc* descs, const LaunchCfg* cfgs,
+                       hipStream_t stream);
 // Enqueue counter reset + the batched kernel on `stream` (no allocation).
 gp_status batch_enqueue(const DeviceGraph& g, const BatchState& st, hipStream_t stream);
 void batch_release(BatchState* st);

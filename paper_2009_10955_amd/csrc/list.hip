@@ -17,9 +17,10 @@
 //     each root task has, an exclusive scan turns these into row offsets, and
 //     the second writes each task's rows from its offset on, the lanes
 //     stepping through their last levels in lockstep. The lanes that hold an
-//     embedding at a step are compacted with a ballot, and the group keeps its
-//     running row in a scalar register: no atomics on the output, and the
-//     rows come out in a fixed order (root task, then search order);
+//     embedding at a step are compacted with a ballot into a stage of rows in
+//     LDS, which goes out in contiguous blocks (coalesced stores); the group
+//     keeps its running row in a scalar register: no atomics on the output,
+//     and the rows come out in a fixed order (root task, then search order);
 //   * a row holds the original vertex ids, indexed by pattern vertex.
 #include <hip/hip_runtime.h>
 
@@ -59,25 +60,50 @@ struct ListArgs {
     int32_t chunk;
 };
 
-// Lanes whose `ok` is set hold an embedding: v[0..K-2] bound above (the same
-// in every lane) and x at the last level. The write pass stores them as rows
-// pos, pos + 1, ... in lane order; both passes advance pos (group-uniform).
+// Rows of the write pass are staged in LDS and stored in contiguous runs:
+// a group's rows of one root task are consecutive in the output, so kStage
+// rows at a time go out as one block, lane i storing words i, i + G, ...
+// (coalesced) instead of each lane storing its own row of K words at a
+// K-word stride.
+constexpr int kStage = 128;
+
+struct Stage {
+    int32_t* rows;  // LDS: kStage rows of K int32, in output column order
+    uint64_t base;  // output row of staged row 0
+    int32_t n;      // rows staged
+};
+
+template <int K>
+__device__ __forceinline__ void flush(const Group<G>& g, const ListArgs& a, Stage& st) {
+    gpcount::group_fence();
+    const int64_t words = (int64_t)st.n * K;
+    int32_t* o = a.out + (int64_t)st.base * K;
+    for (int64_t i = g.gl; i < words; i += G)
+        if (st.base + (uint64_t)(i / K) < (uint64_t)a.out_cap) o[i] = st.rows[i];
+    gpcount::group_fence();
+    st.base += (uint64_t)st.n;
+    st.n = 0;
+}
+
+// Lanes whose `ok` is set hold an embedding: w[0..K-2] bound and x at the
+// last level. The write pass places them as rows pos, pos + 1, ... in lane
+// order (through the stage); both passes advance pos (group-uniform).
 template <int K, bool WRITE>
-__device__ __forceinline__ void emit(const Group<G>& g, const ListArgs& a, const int32_t (&v)[K], bool ok,
-                                     int32_t x, uint64_t& pos) {
+__device__ __forceinline__ void emit(const Group<G>& g, const ListArgs& a, const int32_t (&w)[K], bool ok,
+                                     int32_t x, uint64_t& pos, Stage& st) {
     const uint64_t m = g.ballot(ok);
+    const int32_t cnt = (int32_t)__popcll(m);
     if constexpr (WRITE) {
+        if (st.n + cnt > kStage) flush<K>(g, a, st);
         if (ok) {
-            const uint64_t row = pos + g.below_mask_count(m);
-            if (row < (uint64_t)a.out_cap) {
-                int32_t* o = a.out + (int64_t)row * K;
+            int32_t* r = st.rows + (int64_t)(st.n + (int32_t)g.below_mask_count(m)) * K;
 #pragma unroll
-                for (int j = 0; j < K - 1; ++j) o[a.col_of[j]] = a.orig[v[j]];
-                o[a.col_of[K - 1]] = a.orig[x];
-            }
+            for (int j = 0; j < K - 1; ++j) r[a.col_of[j]] = a.orig[w[j]];
+            r[a.col_of[K - 1]] = a.orig[x];
         }
+        st.n += cnt;
     }
-    pos += (uint64_t)__popcll(m);
+    pos += (uint64_t)cnt;
 }
 
 // Last level for bound v[0..K-2]: its candidate set is one list or buffer, or
@@ -85,7 +111,7 @@ __device__ __forceinline__ void emit(const Group<G>& g, const ListArgs& a, const
 // to the restriction bounds, earlier images excluded.
 template <int K, bool WRITE>
 __device__ void list_last(const GpPlanDesc& d, const gpcount::Ctx<G>& c, const ListArgs& a,
-                          const int32_t (&v)[K], uint64_t& pos) {
+                          const int32_t (&v)[K], uint64_t& pos, Stage& st) {
     const GpLevel& lv = d.lv[K - 1];
     int32_t lo, hi;
     gpcount::bounds<K>(lv.hi_src, lv.lo_src, v, lo, hi);
@@ -114,7 +140,7 @@ __device__ void list_last(const GpPlanDesc& d, const gpcount::Ctx<G>& c, const L
             x = S.p[i];
             ok = !gpcount::inj_hit<K>(lv.inj, v, x) && (!two || member(T, x));
         }
-        emit<K, WRITE>(c.g, a, v, ok, x, pos);
+        emit<K, WRITE>(c.g, a, v, ok, x, pos, st);
     }
 }
 
@@ -154,7 +180,7 @@ __device__ uint32_t last_count(const GpPlanDesc& d, const gpcount::Ctx<G>& c, co
 // binding (have false) only join the ballots.
 template <int K>
 __device__ void last_lockstep(const GpPlanDesc& d, const gpcount::Ctx<G>& c, const ListArgs& a,
-                              const int32_t (&w)[K], bool have, uint64_t& pos) {
+                              const int32_t (&w)[K], bool have, uint64_t& pos, Stage& st) {
     const GpLevel& lv = d.lv[K - 1];
     int32_t lo, hi;
     gpcount::bounds<K>(lv.hi_src, lv.lo_src, w, lo, hi);
@@ -180,25 +206,15 @@ __device__ void last_lockstep(const GpPlanDesc& d, const gpcount::Ctx<G>& c, con
             x = A.p[i];
             ok = (!two || member(B, x)) && !gpcount::inj_hit<K>(lv.inj, w, x);
         }
-        const uint64_t m = c.g.ballot(ok);
-        if (ok) {
-            const uint64_t row = pos + c.g.below_mask_count(m);
-            if (row < (uint64_t)a.out_cap) {
-                int32_t* o = a.out + (int64_t)row * K;
-#pragma unroll
-                for (int j = 0; j < K - 1; ++j) o[a.col_of[j]] = a.orig[w[j]];
-                o[a.col_of[K - 1]] = a.orig[x];
-            }
-        }
-        pos += (uint64_t)__popcll(m);
+        emit<K, true>(c.g, a, w, ok, x, pos, st);
     }
 }
 
 template <int K, int L, bool WRITE>
 __device__ void list_search(const GpPlanDesc& d, const gpcount::Ctx<G>& c, const ListArgs& a, int32_t (&v)[K],
-                            uint64_t& pos) {
+                            uint64_t& pos, Stage& st) {
     if constexpr (L == K - 1) {
-        list_last<K, WRITE>(d, c, a, v, pos);
+        list_last<K, WRITE>(d, c, a, v, pos, st);
     } else if constexpr (L == K - 2) {
         // lanes take different candidates of the second-to-last level and
         // walk the last level alone
@@ -218,7 +234,7 @@ __device__ void list_search(const GpPlanDesc& d, const gpcount::Ctx<G>& c, const
                 have = !gpcount::inj_hit<K>(lv.inj, v, w[L]);
             }
             if constexpr (WRITE) {
-                last_lockstep<K>(d, c, a, w, have, pos);
+                last_lockstep<K>(d, c, a, w, have, pos, st);
             } else {
                 const uint32_t mine = have ? last_count<K>(d, c, w) : 0u;
                 pos += c.g.sum(mine);
@@ -235,7 +251,7 @@ __device__ void list_search(const GpPlanDesc& d, const gpcount::Ctx<G>& c, const
             if (gpcount::inj_hit<K>(lv.inj, v, x)) continue;
             v[L] = x;
             gpcount::run_builds<K, G, gpcount::MODE_PLAIN>(d, c, L, v);
-            list_search<K, L + 1, WRITE>(d, c, a, v, pos);
+            list_search<K, L + 1, WRITE>(d, c, a, v, pos, st);
         }
     }
 }
@@ -245,6 +261,7 @@ __device__ void list_search(const GpPlanDesc& d, const gpcount::Ctx<G>& c, const
 template <int K, bool WRITE>
 __global__ __launch_bounds__(kBlock) void list_kernel(GpPlanDesc d, ListArgs a) {
     __shared__ int32_t s_len[kBlock / G][GP_DESC_MAX_BUILDS];
+    __shared__ int32_t s_stage[WRITE ? kBlock / G : 1][WRITE ? kStage * K : 1];
     gpcount::Ctx<G> c;
     c.row_ptr = a.row_ptr;
     c.col = a.col;
@@ -290,8 +307,10 @@ __global__ __launch_bounds__(kBlock) void list_kernel(GpPlanDesc d, ListArgs a) 
                 v[0] = gpcount::uni<G>(e.x);
                 v[1] = gpcount::uni<G>(e.y);
                 uint64_t pos = WRITE ? (uint64_t)gpcount::uni64<G>((int64_t)a.task_rows[t]) : 0;
+                Stage st{WRITE ? &s_stage[grp][0] : nullptr, pos, 0};
                 gpcount::run_builds<K, G, gpcount::MODE_PLAIN>(d, c, 1, v);
-                list_search<K, 2, WRITE>(d, c, a, v, pos);
+                list_search<K, 2, WRITE>(d, c, a, v, pos, st);
+                if constexpr (WRITE) flush<K>(c.g, a, st);
                 if constexpr (!WRITE)
                     if (c.g.gl == 0) a.task_rows[t] = pos;
             }

@@ -45,8 +45,9 @@ struct GpLevel {
     uint8_t inj;       // earlier levels v_i must differ from explicitly
     int8_t list;       // single parent: level whose neighbor list is the candidate set
     int8_t buf;        // several parents, fully built before level i: buffer slot
-    // last level only, when its last parent is the level just before it:
-    // count |pre & N(v[last_list]) & cuts| without building it.
+    // the last level when its last parent is the level just before it, or an
+    // IEP inner level whose last parent is the last outer level: the set
+    // pre & N(v[last_list]) & cuts is counted where it is used, never built.
     int8_t pre_buf;    // prefix operand: buffer slot, or -1 for N(v[pre_list])
     int8_t pre_list;
     int8_t last_list;  // -1 when the last level reads `list` or `buf`

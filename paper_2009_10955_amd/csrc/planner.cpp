@@ -199,43 +199,52 @@ RestrictionSets restriction_sets(const Pattern& p, const std::vector<Perm>& auts
     // Worklist over closures: a closure grows by one pair (v, perm[v]) per
     // automorphism perm it does not yet eliminate and vertex v on a 2-cycle
     // of perm; a closure at which the identity alone survives is kept if
-    // valid. Survivors are recomputed from all automorphisms (filtering the
-    // parent's survivors gives the same: a conflict persists in supersets).
+    // valid. A grown closure's survivors are its parent's survivors that do
+    // not conflict with it (a conflict persists in every superset, so this
+    // equals filtering all automorphisms).
     RestrictionSets out;
     const double deadline = max_seconds > 0 ? now_s() + max_seconds : 0;
     std::unordered_set<Rel> seen;
     std::unordered_set<Rel> valid;
-    std::vector<Rel> work;
+    struct Item {
+        Rel rel;
+        std::vector<int> alive;
+    };
+    std::vector<Item> work;
+    Item start;
+    start.rel = 0;
+    for (size_t i = 0; i < auts.size(); ++i) start.alive.push_back(int(i));
     seen.insert(0);
-    work.push_back(0);
+    work.push_back(std::move(start));
     while (!work.empty()) {
         if ((int32_t)valid.size() >= max_sets ||
             (deadline > 0 && (seen.size() & 1023) == 0 && now_s() > deadline && !valid.empty())) {
             out.truncated = true;
             break;
         }
-        const Rel rel = work.back();
+        Item it = std::move(work.back());
         work.pop_back();
-        std::vector<int> alive;
-        for (size_t i = 0; i < auts.size(); ++i)
-            if (no_conflict(auts[i], rel, k)) alive.push_back(int(i));
-        if (alive.size() <= 1) {
+        if (it.alive.size() <= 1) {
             // the identity alone survives (or nothing: a cyclic set)
-            if (!alive.empty() && validate(rel, k, auts.size())) valid.insert(rel);
+            if (!it.alive.empty() && validate(it.rel, k, auts.size())) valid.insert(it.rel);
             continue;
         }
-        for (int pi : alive) {
+        for (int pi : it.alive) {
             const Perm& perm = auts[pi];
             for (int v = 0; v < k; ++v) {
                 if (perm[v] == v || perm[perm[v]] != v) continue;  // v is not on a 2-cycle
-                const Rel grown = closure(rel | rel_bit(v, perm[v]), k);
+                const Rel grown = closure(it.rel | rel_bit(v, perm[v]), k);
                 if (seen.count(grown)) continue;
                 if ((int64_t)seen.size() >= max_states) {
                     out.truncated = true;
                     continue;
                 }
                 seen.insert(grown);
-                work.push_back(grown);
+                Item next;
+                next.rel = grown;
+                for (int qi : it.alive)
+                    if (no_conflict(auts[qi], grown, k)) next.alive.push_back(qi);
+                work.push_back(std::move(next));
             }
         }
     }
@@ -567,6 +576,16 @@ int compile_plan(const Pattern& p, const Perm& order, Rel r, GpPlanDesc* out, Re
         int h = 31 - __builtin_clz(par[i]);
         if (np == 1) {
             L.list = int8_t(h);
+        } else if (i >= first_inner && h == first_inner - 1) {
+            // an IEP inner set whose last parent is the last outer level: left
+            // unbuilt as pre & N(v_h), counted where it is used
+            unsigned prefix = par[i] & ~(1u << h);
+            if (__builtin_popcount(prefix) == 1) {
+                L.pre_list = int8_t(__builtin_ctz(prefix));
+            } else {
+                L.pre_buf = int8_t(ensure_chain(prefix, i));
+            }
+            L.last_list = int8_t(h);
         } else if (i < k - 1 || h < k - 2) {
             L.buf = int8_t(ensure_chain(par[i], i));
         } else {

@@ -44,6 +44,11 @@ class Stats(ctypes.Structure):
                 ("hub_bitmap_bytes", ctypes.c_int64)]
 
 
+class LoadOpts(ctypes.Structure):
+    _fields_ = [("flags", ctypes.c_uint32), ("hub_min_degree", ctypes.c_int64),
+                ("hub_budget_bytes", ctypes.c_int64)]
+
+
 class PlanOpts(ctypes.Structure):
     _fields_ = [("max_states", ctypes.c_int64), ("max_sets", ctypes.c_int32),
                 ("force_order", ctypes.c_int32 * MAX_K), ("force_set", ctypes.c_int32),
@@ -101,6 +106,8 @@ _I32 = ctypes.c_int32
 _I64 = ctypes.c_int64
 SIGNATURES = {
     "gp_load_graph": (_I32, [_P, _P, _I64, _I64, ctypes.c_uint32, _P, ctypes.POINTER(_P)]),
+    "gp_load_opts_default": (None, [ctypes.POINTER(LoadOpts)]),
+    "gp_load_graph_opts": (_I32, [_P, _P, _I64, _I64, ctypes.POINTER(LoadOpts), _P, ctypes.POINTER(_P)]),
     "gp_graph_stats": (_I32, [_P, ctypes.POINTER(Stats)]),
     "gp_graph_new_id": (_I32, [_P, _P]),
     "gp_graph_layout": (_I32, [_P, _P, _P]),
@@ -134,6 +141,7 @@ SIGNATURES = {
     "gp_batch_create": (_I32, [_P, _P, _I32, ctypes.POINTER(Launch), _P, ctypes.POINTER(_P)]),
     "gp_batch_tune": (_I32, [_P, _P, _I32, _P, ctypes.POINTER(Launch), ctypes.POINTER(ctypes.c_double)]),
     "gp_batch_run": (_I32, [_P, _P, _P]),
+    "gp_batch_set_sample": (_I32, [_P, _I64, _I64, _P]),
     "gp_free_batch": (None, [_P]),
     "gp_server_opts_default": (None, [ctypes.POINTER(ServerOpts)]),
     "gp_server_create": (_I32, [_P, _I32, ctypes.POINTER(ServerOpts), ctypes.POINTER(_P)]),
@@ -194,10 +202,16 @@ def _launch(group=0, waves_per_cu=0, chunk=0, leaf_mode=0, root_stride=0, root_o
 class Graph:
     """A data graph resident on the current GPU, owned by the library."""
 
-    def __init__(self, row_ptr, col, stream=None, hub_bitmaps: str = "auto"):
-        """hub_bitmaps: "auto" (degree >= 64), "none", or "dense" (every vertex)."""
+    def __init__(self, row_ptr, col, stream=None, hub_bitmaps: str = "auto", hub_min_degree: int = 0,
+                 hub_budget_bytes: int = 0):
+        """hub_bitmaps: "auto" (degree >= hub_min_degree, default 64, within
+        hub_budget_bytes, default 2 GiB), "none", or "dense" (every vertex)."""
         lib = _lib()
         extra = {"auto": 0, "none": GP_NO_HUB_BITMAPS, "dense": GP_DENSE_HUB_BITMAPS}[hub_bitmaps]
+        o = LoadOpts()
+        lib.gp_load_opts_default(ctypes.byref(o))
+        o.hub_min_degree = int(hub_min_degree)
+        o.hub_budget_bytes = int(hub_budget_bytes)
         self._h = ctypes.c_void_p()
         try:
             import torch
@@ -210,26 +224,28 @@ class Graph:
             row_ptr = row_ptr.contiguous()
             col = col.contiguous()
             n = row_ptr.numel() - 1
-            st = lib.gp_load_graph(row_ptr.data_ptr(), col.data_ptr(), n, col.numel(),
-                                   GP_IN_DEVICE | extra, _stream_handle(stream), ctypes.byref(self._h))
+            o.flags = GP_IN_DEVICE | extra
+            st = lib.gp_load_graph_opts(row_ptr.data_ptr(), col.data_ptr(), n, col.numel(), ctypes.byref(o),
+                                        _stream_handle(stream), ctypes.byref(self._h))
         else:
             rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
             cl = np.ascontiguousarray(col, dtype=np.int32)
             n = rp.shape[0] - 1
-            st = lib.gp_load_graph(rp.ctypes.data, cl.ctypes.data if cl.size else None, n, cl.size,
-                                   extra, _stream_handle(stream), ctypes.byref(self._h))
-        _check(st, "gp_load_graph")
+            o.flags = extra
+            st = lib.gp_load_graph_opts(rp.ctypes.data, cl.ctypes.data if cl.size else None, n, cl.size,
+                                        ctypes.byref(o), _stream_handle(stream), ctypes.byref(self._h))
+        _check(st, "gp_load_graph_opts")
 
     @classmethod
-    def from_csr(cls, g, device: bool = False, stream=None, hub_bitmaps: str = "auto") -> "Graph":
+    def from_csr(cls, g, device: bool = False, stream=None, hub_bitmaps: str = "auto", **opts) -> "Graph":
         """From an object with numpy ``row_ptr`` / ``col``; device=True uploads
         them as torch tensors first and loads from device memory."""
         if device:
             import torch
             rp = torch.from_numpy(np.asarray(g.row_ptr, dtype=np.int64)).cuda()
             cl = torch.from_numpy(np.asarray(g.col, dtype=np.int32)).cuda()
-            return cls(rp, cl, stream, hub_bitmaps)
-        return cls(g.row_ptr, g.col, stream, hub_bitmaps)
+            return cls(rp, cl, stream, hub_bitmaps, **opts)
+        return cls(g.row_ptr, g.col, stream, hub_bitmaps, **opts)
 
     @property
     def handle(self):
@@ -496,6 +512,12 @@ class Batch:
         out = (ctypes.c_uint64 * len(self.plans))()
         _check(_lib().gp_batch_run(self._h, _stream_handle(stream), out), "gp_batch_run")
         return list(out)
+
+    def set_sample(self, root_stride: int, root_offset: int, stream=None) -> None:
+        """Count every plan's roots[root_offset + r * root_stride] from the next
+        run on (see gp_batch_set_sample)."""
+        _check(_lib().gp_batch_set_sample(self._h, int(root_stride), int(root_offset),
+                                          _stream_handle(stream)), "gp_batch_set_sample")
 
     def close(self) -> None:
         if self._h:

@@ -18,7 +18,7 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ["csrc/count_kernel.hpp", "csrc/sets.hpp", "csrc/count_inst.hip", "csrc/count.hip",
-                  "csrc/plan_desc.h"]
+                  "csrc/count_batch.hip", "csrc/plan_desc.h"]
 
 
 def kernel_source_hash() -> str:
@@ -123,8 +123,12 @@ def main(argv):
     plan = None
     if a.plans:
         with open(a.plans) as f:
-            plan = json.loads(f.read().strip().splitlines()[-1])["plans"][a.pattern]
-        plan = {k: plan[k] for k in ("order", "restrictions", "launch")} | {"iep": bool(plan.get("iep", False))}
+            plans = json.loads(f.read().strip().splitlines()[-1])["plans"]
+
+        def pick(p):
+            return {k: p[k] for k in ("order", "restrictions", "launch")} | {"iep": bool(p.get("iep", False))}
+        # PATTERN "all": a batched launch of every plan of the run
+        plan = {n: pick(p) for n, p in plans.items()} if a.pattern == "all" else pick(plans[a.pattern])
     s = traffic_summary(a.fetch_glob, a.write_glob, a.kernel_match, int(a.copy_mib) << 20, a.pattern,
                         a.workload, plan, a.l2)
     with open(a.out, "w") as f:

@@ -192,7 +192,7 @@ BENCH_FILES = [("rmat17", 1, os.path.join(ROOT, "profiles", "plans_rmat17.json")
 
 
 @pytest.mark.parametrize("workload,cfg,path", [b for b in BENCH_FILES if os.path.exists(b[2])],
-                         ids=lambda x: x if isinstance(x, str) and not x.startswith("/") else None)
+                         ids=[b[0] for b in BENCH_FILES if os.path.exists(b[2])])
 def test_bench_configurations_on_sampled_roots(workload, cfg, path, rmat22):
     """The benchmark's exact plans and launches (splits, grabs, leaf mode 4
     with its memo, IEP) on strided root samples of the full graph, against
@@ -226,6 +226,8 @@ def test_bench_configurations_on_sampled_roots(workload, cfg, path, rmat22):
             if pc.max() <= 2_000_000 or pc.max() > 60_000_000 or pc.sum() > 400_000_000:
                 continue
             got = gp.count(graph, plan, root_stride=stride, root_offset=off, **launch)
+            print(f"[{workload} {name}] offset {off}/{stride}: {len(sample)} roots, heaviest "
+                  f"{int(pc.max())}, sample count {got}", flush=True)
             assert got == int(pc.sum()), (name, off)
             want = sum(_pinned(lay, k, e, plan.restrictions, plan.order, [tuple(r) for r in sample]))
             assert got == want, (name, off)

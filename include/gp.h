@@ -299,6 +299,25 @@ gp_status gp_count_async(const gp_graph* g, const gp_plan* p, const gp_launch* l
                          void* stream, uint64_t* dev_out);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): gp_count_async
+ * that allocates nothing. The task cursor, the per-group candidate buffers
+ * and, when room is left, leaf mode 4's memo come from one static device
+ * workspace of 32 MiB that every GPU the library runs on holds until the
+ * process ends; the grid shrinks so the buffers fit it. dev_out (device
+ * memory, 2 uint64, caller-owned) receives {count, flags} as in
+ * gp_count_async. GP_ERR_NOMEM when the plan's candidate buffers for one
+ * block of groups alone exceed the workspace (a graph whose second-largest
+ * degree is too high for the plan and group width). Every call on a GPU
+ * shares that GPU's workspace: calls that overlap on one GPU (different
+ * streams, threads) race and must be serialised by the caller. The first
+ * call on a device looks the workspace up (no allocation). No host
+ * synchronisation.
+ */
+gp_status gp_count_noalloc(const gp_graph* g, const gp_plan* p, const gp_launch* launch, void* stream,
+                           uint64_t* dev_out);
+
+/*
  * Per-root counts, for verification: dev_per_root (device memory, one uint64
  * per directed CSR entry of the device layout, nnz entries) receives, at the
  * index of the layout entry (v0, v1), the number of embeddings whose first

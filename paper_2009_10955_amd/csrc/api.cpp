@@ -553,6 +553,15 @@ gp_status gp_count_async(const gp_graph* g, const gp_plan* p, const gp_launch* l
                                reinterpret_cast<unsigned long long*>(dev_out), nullptr);
 }
 
+gp_status gp_count_noalloc(const gp_graph* g, const gp_plan* p, const gp_launch* launch, void* stream,
+                           uint64_t* dev_out) {
+    if (!g || !p || !dev_out) return GP_ERR_ARG;
+    DeviceGuard dgd(g->dg.device);
+    gpint::LaunchCfg cfg = gpint::launch_for_plan(p, launch, g->dg);
+    return gpint::launch_count_noalloc(g->dg, p->desc, cfg, (hipStream_t)stream,
+                                       reinterpret_cast<unsigned long long*>(dev_out));
+}
+
 gp_status gp_count_per_root(const gp_graph* g, const gp_plan* p, const gp_launch* launch, void* stream,
                             uint64_t* dev_per_root, uint64_t* out) {
     if (!g || !p || !dev_per_root || !out) return GP_ERR_ARG;

@@ -326,6 +326,42 @@ gp_status check_sum(const uint64_t* values, int64_t n, uint64_t div, hipStream_t
     return GP_OK;
 }
 
+// Workspace of launch_count_noalloc: every GPU the library runs on holds one
+// copy of this array until the process ends. In host code its name is only a
+// stand-in; the device address of each GPU's copy comes from
+// hipGetSymbolAddress, taken once per device.
+static __device__ __align__(256) unsigned char scratch[kNoallocWorkspaceBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+}  // namespace
+
+// The device address of this GPU's copy of `scratch` (the device must be
+// current), looked up on the first call per device.
+static gp_status scratch_address(int device, void** ptr) {
+    if (device < 0 || device >= 64) return GP_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return GP_ERR_HIP;
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = g_scratch_ptr[device];
+    return GP_OK;
+}
+
+gp_status launch_count_noalloc(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCfg& cfg,
+                               hipStream_t stream, unsigned long long* result_dev) {
+    void* base = nullptr;
+    const gp_status st = scratch_address(g.device, &base);
+    if (st != GP_OK) return st;
+    Workspace ws;
+    ws.base = base;
+    ws.bytes = kNoallocWorkspaceBytes;
+    return launch_count(g, d, cfg, stream, result_dev, nullptr, false, nullptr, &ws);
+}
+
 int64_t root_task_count(const DeviceGraph& g, const GpPlanDesc& d) {
     int64_t n = 0;
     (void)pick_roots(g, d.root_cut, &n);

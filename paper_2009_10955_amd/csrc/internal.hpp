@@ -66,6 +66,14 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
                        unsigned long long* per_root, bool account = false,
                        unsigned long long* busy = nullptr, const Workspace* ws = nullptr);
 
+// launch_count without allocating: the task cursor, candidate buffers and
+// memo come from one static device array of kNoallocWorkspaceBytes per GPU
+// (the grid shrinks so they fit; GP_ERR_NOMEM when not even one block's
+// buffers fit). Calls that overlap on one GPU share that array and race.
+constexpr size_t kNoallocWorkspaceBytes = size_t(32) << 20;
+gp_status launch_count_noalloc(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCfg& cfg,
+                               hipStream_t stream, unsigned long long* result_dev);
+
 // Enqueue a listing of plan d over g on `stream`: found_dev (2 device words)
 // receives {embeddings found, 0}; the first out_cap of them are written to out
 // as rows of k int32 original vertex ids, column order[i] holding schedule

@@ -126,6 +126,7 @@ SIGNATURES = {
     "gp_launch_default": (None, [ctypes.POINTER(Launch)]),
     "gp_count": (_I32, [_P, _P, ctypes.POINTER(Launch), _P, ctypes.POINTER(ctypes.c_uint64)]),
     "gp_count_async": (_I32, [_P, _P, ctypes.POINTER(Launch), _P, _P]),
+    "gp_count_noalloc": (_I32, [_P, _P, ctypes.POINTER(Launch), _P, _P]),
     "gp_count_per_root": (_I32, [_P, _P, ctypes.POINTER(Launch), _P, _P,
                                  ctypes.POINTER(ctypes.c_uint64)]),
     "gp_count_batch": (_I32, [_P, _P, _I32, ctypes.POINTER(Launch), _P, _P]),
@@ -406,6 +407,14 @@ def count_async(graph: Graph, plan: Plan, dev_out, stream=None, **launch) -> Non
     lp = _launch(**launch)
     _check(_lib().gp_count_async(graph.handle, plan.handle, ctypes.byref(lp), _stream_handle(stream),
                                  dev_out.data_ptr()), "gp_count_async")
+
+
+def count_noalloc(graph: Graph, plan: Plan, dev_out, stream=None, **launch) -> None:
+    """As count_async, with no device allocation (the library's static
+    workspace; see gp_count_noalloc)."""
+    lp = _launch(**launch)
+    _check(_lib().gp_count_noalloc(graph.handle, plan.handle, ctypes.byref(lp), _stream_handle(stream),
+                                   dev_out.data_ptr()), "gp_count_noalloc")
 
 
 def count_per_root(graph: Graph, plan: Plan, stream=None, **launch):

@@ -1,21 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark of the exact embedding-counting path on one MI355X.
 
-Workload (default): R-MAT scale 17 (131,072 vertices, edge factor 8,
-a=0.57 b=0.19 c=0.19 d=0.05, seed 2; symmetrised, no self-loops or
-duplicates), patterns house, 5-cycle and 5-clique, one persistent launch per
-pattern. A step counts all three patterns once; inputs (graph layout, plans)
+Workload (default): R-MAT scale 22 (4,194,304 vertices, edge factor 8,
+a=0.57 b=0.19 c=0.19 d=0.05, seed 4; symmetrised, no self-loops or
+duplicates) with the patterns 4-clique, house, 5-cycle and 6-cycle+chord.
+Every pattern is planned, estimated and tuned first; those whose tuned full
+run is estimated within --max-pattern-s are timed. A step counts one of 20
+strided slices of every timed pattern's root edges with the batched launches
+(one hipGraph), and the same slices are counted again with one launch per
+pattern; 20 steps count every embedding once. Inputs (graph layout, plans)
 are resident before timing starts, as the paper times only the matching
 (graph loading and preprocessing excluded).
 
-Prints ONE JSON line: embeddings/s over the timed steps, the dominant
-kernel's algorithmic bytes per second against the HBM roofline, and the CPU
+Prints ONE JSON line: embeddings/s over the timed steps, the batched
+launch's algorithmic bytes per second against the HBM roofline, and the CPU
 oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
 import argparse
-import concurrent.futures as cf
 import json
 import os
 import sys
@@ -107,8 +110,11 @@ def parse_args():
     return ap.parse_args()
 
 
+_T0 = time.perf_counter()
+
+
 def note(msg: str) -> None:
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+    print(f"[bench +{time.perf_counter() - _T0:.0f}s] {msg}", file=sys.stderr, flush=True)
 
 
 def host_info() -> dict:
@@ -135,62 +141,135 @@ def oracle_threads() -> int:
     return max(1, min(16, host_info()["cpus_allowed"]))
 
 
-def cpu_baseline(g, plans, names, budget_s: float, threads: int | None = None) -> dict:
+def oracle_worker(folder: str) -> None:
+    """Child process of cpu_baseline: counts the jobs read from stdin (one JSON
+    list per line) with the oracle on one thread, one line out per job."""
+    import numpy as np
+    import oracle as O
+
+    lay = O._CSRView(np.load(os.path.join(folder, "row_ptr.npy"), mmap_mode="r"),
+                     np.load(os.path.join(folder, "col.npy"), mmap_mode="r"))
+    print("ready", flush=True)
+    for line in sys.stdin:
+        k, e, restr, pins = json.loads(line)
+        t = time.perf_counter()
+        c = O.count_maps(lay, k, [tuple(x) for x in e], restr=[tuple(x) for x in restr],
+                         pins=[tuple(x) for x in pins], threads=1)
+        print(f"{c} {time.perf_counter() - t:.6f}", flush=True)
+
+
+def cpu_baseline(g, plans, names, budget_s: float, threads: int | None = None,
+                 job_limit_s: float | None = None) -> dict:
     """The oracle, untuned, on a bounded sample of the same workload: random
     root edges of each plan (in the oracle's own degree-sorted relabelling),
-    each counted by the oracle with the first two schedule vertices pinned.
-    Embeddings found / wall time."""
+    each counted by the oracle with the first two schedule vertices pinned, in
+    `threads` worker processes. New jobs start until the budget is spent; a job
+    still running after job_limit_s is abandoned (its process killed), since
+    one hub root can hold more work than the whole budget. The rate is the
+    embeddings of the finished jobs over their summed one-thread time, times
+    the threads."""
+    import selectors
+    import subprocess
+    import tempfile
     import numpy as np
     import oracle as O
 
     rp, col, _ = O.relabel_by_degree(g)
-    lay = O._CSRView(rp, col)
     src = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
     threads = threads or oracle_threads()
+    job_limit_s = job_limit_s or max(1.0, budget_s / 2)
     rng = np.random.default_rng(12345)
     jobs = []
     for name, plan in zip(names, plans):
         order = plan.order
-        restr = plan.restrictions
-        k, e = plan.k, plan.edges
-        cut = 1 if (order[0], order[1]) in restr else (2 if (order[1], order[0]) in restr else 0)
+        restr = [list(x) for x in plan.restrictions]
+        k, e = plan.k, [list(x) for x in plan.edges]
+        cut = 1 if (order[0], order[1]) in plan.restrictions else (2 if (order[1], order[0]) in plan.restrictions else 0)
         ok = np.ones(len(col), bool) if cut == 0 else ((col < src) if cut == 1 else (col > src))
         cand = np.nonzero(ok)[0]
         for idx in rng.choice(cand, size=min(4000, cand.size), replace=False):
-            jobs.append((name, k, e, restr, order, int(src[idx]), int(col[idx])))
+            jobs.append([k, e, restr, [[order[0], int(src[idx])], [order[1], int(col[idx])]]])
     rng.shuffle(jobs)
 
-    def run(job):
-        name, k, e, restr, order, v0, v1 = job
-        return O.count_maps(lay, k, e, restr=restr, pins=[(order[0], v0), (order[1], v1)],
-                            threads=1)
+    folder = tempfile.mkdtemp(prefix="gp_oracle_")
+    np.save(os.path.join(folder, "row_ptr.npy"), np.asarray(rp, dtype=np.int64))
+    np.save(os.path.join(folder, "col.npy"), np.asarray(col, dtype=np.int32))
+    del src
+    sel = selectors.DefaultSelector()
+    workers = {}  # pid -> [proc, job start time or None]
 
-    found = 0
-    done = 0
-    t0 = time.perf_counter()
-    deadline = t0 + budget_s
-    with cf.ThreadPoolExecutor(threads) as ex:
-        it = iter(jobs)
-        pending = set()
+    def spawn():
+        p = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--oracle-worker", folder],
+                             stdin=subprocess.PIPE, stdout=subprocess.PIPE, text=True, bufsize=1,
+                             env=dict(os.environ, OMP_NUM_THREADS="1"))
+        if p.stdout.readline().strip() != "ready":
+            p.kill()
+            p.wait()
+            raise RuntimeError("oracle worker failed to start")
+        workers[p.pid] = [p, None]
+        sel.register(p.stdout, selectors.EVENT_READ, p.pid)
+        return p
+
+    def stop(pid, kill):
+        p = workers.pop(pid)[0]
+        sel.unregister(p.stdout)
+        if kill:
+            p.kill()
+        else:
+            p.stdin.close()
+        p.wait()
+
+    found = done = abandoned = 0
+    busy = 0.0
+    it = iter(jobs)
+    try:
         for _ in range(threads):
-            j = next(it, None)
-            if j is not None:
-                pending.add(ex.submit(run, j))
-        while pending:
-            fin, pending = cf.wait(pending, return_when=cf.FIRST_COMPLETED)
-            for f in fin:
-                found += f.result()
+            spawn()
+        t0 = time.perf_counter()
+        deadline = t0 + budget_s
+
+        def feed(pid):
+            j = next(it, None) if time.perf_counter() < deadline else None
+            if j is None:
+                stop(pid, kill=False)
+                return
+            workers[pid][0].stdin.write(json.dumps(j) + "\n")
+            workers[pid][0].stdin.flush()
+            workers[pid][1] = time.perf_counter()
+
+        for pid in list(workers):
+            feed(pid)
+        while workers:
+            for key, _ in sel.select(timeout=0.2):
+                pid = key.data
+                line = workers[pid][0].stdout.readline().split()
+                if len(line) != 2:
+                    raise RuntimeError("oracle worker ended early")
+                found += int(line[0])
+                busy += float(line[1])
                 done += 1
-                if time.perf_counter() < deadline:
-                    j = next(it, None)
-                    if j is not None:
-                        pending.add(ex.submit(run, j))
-    dt = time.perf_counter() - t0
-    out = {"value": found / dt if dt > 0 else 0.0, "unit": "embeddings/s", "cores": threads,
-           "kind": "oracle",
+                feed(pid)
+            now = time.perf_counter()
+            for pid in [q for q, (_, ts) in workers.items() if ts is not None and now - ts > job_limit_s]:
+                stop(pid, kill=True)
+                abandoned += 1
+                if now < deadline:
+                    feed(spawn().pid)
+        wall = time.perf_counter() - t0
+    finally:
+        for pid in list(workers):
+            stop(pid, kill=True)
+        for f in ("row_ptr.npy", "col.npy"):
+            os.remove(os.path.join(folder, f))
+        os.rmdir(folder)
+    value = found / busy * threads if busy > 0 else 0.0
+    out = {"value": value, "unit": "embeddings/s", "cores": threads, "kind": "oracle",
            "sample": f"{done} root edges drawn uniformly from the {len(plans)} plans' root tasks, each "
-                     f"counted by the CPU oracle with the first two schedule vertices pinned; "
-                     f"{found} embeddings in {dt:.1f} s on {threads} threads"}
+                     f"counted by the CPU oracle (one thread per job) with the first two schedule "
+                     f"vertices pinned; {found} embeddings in {busy:.1f} s of summed job time, "
+                     f"rate x {threads} worker processes ({wall:.1f} s wall); {abandoned} jobs "
+                     f"abandoned after {job_limit_s:g} s each and left out of both sums",
+           "jobs_done": done, "jobs_abandoned": abandoned, "wall_s": wall}
     out.update(host_info())
     return out
 
@@ -793,6 +872,9 @@ def sliced_main(args, cfg_idx, names, desc):
                    "slices": S, "parallelism": "single GPU"},
         "embeddings_per_step": emb / args.steps,
         "counts": totals, "counts_cover_every_root": bool(totals) and whole,
+        # an IEP plan's slice counts are its slice totals divided by the
+        # over-count, rounded down: their sum may fall short by under one per slice
+        "counts_rounded_per_slice": [n for n, p in zip(names, plans) if p.info().iep_div > 1],
         "plain_ms_per_step": ms_p / args.steps,
         "batched_speedup": ms_p / ms_b,
         "batched_launch_ms": [round(x, 3) for x in launch_ms],
@@ -884,4 +966,7 @@ def serve_main(args, desc):
 
 
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) == 3 and sys.argv[1] == "--oracle-worker":
+        oracle_worker(sys.argv[2])
+    else:
+        main()

@@ -150,6 +150,10 @@ typedef struct {
     int32_t split_vertices;/* heavy roots: those whose smaller endpoint in the degree-sorted
                               layout is below split_vertices, rounded down to a power of
                               two (0 = auto) */
+    int32_t lds_buffers;   /* 1: the candidate buffers (intersection results) of a block's
+                              groups live in its LDS when they fit 64 KiB (graphs whose
+                              second-largest degree is small), -1: always in HBM scratch,
+                              0: the plan's own (HBM unless tuned otherwise) */
 } gp_launch;
 
 void gp_launch_default(gp_launch* l);
@@ -247,8 +251,10 @@ typedef struct {
                                about 8 ms of balanced work per sample) */
     int32_t tune_launch;    /* 1 (default): also pick lanes per group, leaf mode and, for
                                k >= 4 when the winner was timed in full, the ways heavy
-                               roots are split (16, 4 or 1) and the tasks taken per queue
-                               grab (1, 2, 4, 8 or 16); -1: keep the defaults */
+                               roots are split (16, 4 or 1), the tasks taken per queue grab
+                               (1, 2, 4, 8 or 16), the heavy-root threshold (64, 256, 1024
+                               or 4096), candidate buffers in LDS (where they fit) and 16 or
+                               24 resident wavefronts per CU; -1: keep the defaults */
     double budget_seconds;  /* GPU time for timing sampled configurations (0 = 20 s); the
                                launch-shape, full-run and queue-grab stages that follow may
                                bring the total to at most about 4 times this */
@@ -275,6 +281,18 @@ void gp_tune_opts_default(gp_tune_opts* o);
  */
 gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* opts, void* stream,
                        gp_plan** out);
+
+/*
+ * A copy of plan p (same configuration, counts and tuning record) whose
+ * default launch shape takes every non-zero field of `launch` (root_stride
+ * and root_offset excepted: they belong to a call). The shape a plan takes
+ * in a batch is its default launch, so plans of one batch can run at
+ * different shapes (Section IV-E's task partitioning across patterns).
+ * GP_ERR_ARG on a field out of range (group not 64/32/16/8, leaf_mode not
+ * 1..4, waves_per_cu not 1..32, negative chunk, split_ways or
+ * split_vertices); *out is then untouched. Free with gp_free_plan.
+ */
+gp_status gp_plan_with_launch(const gp_plan* p, const gp_launch* launch, gp_plan** out);
 
 void gp_free_plan(gp_plan* p);
 
@@ -438,8 +456,9 @@ gp_status gp_batch_run(gp_batch* b, void* stream, uint64_t* out);
  * root_offset do for gp_count), heavy roots split as before. root_stride 1,
  * offset 0 is the whole count again. Runs with offsets 0 .. s-1 of one
  * stride s partition every plan's embeddings (for an IEP plan with an
- * over-count above 1 a sample's quotient is not checked, so parts need not
- * add up). Copies the new task table to the device before returning (waits
+ * over-count above 1 a sample's raw total is divided with the quotient
+ * rounded down, so its parts may add up to less, by under one per part).
+ * Copies the new task table to the device before returning (waits
  * for `stream`); the captured graph is unchanged. Errors: GP_ERR_ARG.
  */
 gp_status gp_batch_set_sample(gp_batch* b, int64_t root_stride, int64_t root_offset, void* stream);

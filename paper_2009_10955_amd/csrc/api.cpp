@@ -491,6 +491,7 @@ gp_status gp_plan_get(const gp_plan* p, gp_plan_info* out) {
     out->launch.root_offset = 0;
     out->launch.split_ways = p->launch.split_ways;
     out->launch.split_vertices = (int32_t)std::min<int64_t>(p->launch.split_vertices, INT32_MAX);
+    out->launch.lds_buffers = p->launch.lds > 0 ? 1 : -1;
     return GP_OK;
 }
 
@@ -527,6 +528,23 @@ gp_status gp_plan_model_cost(const gp_plan* p, int32_t idx_s, int32_t idx_r, con
         gs.tri_cnt = double(stats->tri_cnt);
     }
     *cost = gp::model_cost(p->pattern, p->schedules[idx_s], p->sets[idx_r], gs);
+    return GP_OK;
+}
+
+gp_status gp_plan_with_launch(const gp_plan* p, const gp_launch* launch, gp_plan** out) {
+    if (!p || !launch || !out) return GP_ERR_ARG;
+    const gp_launch& l = *launch;
+    if ((l.group && l.group != 64 && l.group != 32 && l.group != 16 && l.group != 8) ||
+        (l.leaf_mode && (l.leaf_mode < 1 || l.leaf_mode > 4)) || (l.waves_per_cu && (l.waves_per_cu < 1 || l.waves_per_cu > 32)) ||
+        l.chunk < 0 || l.split_ways < 0 || l.split_vertices < 0)
+        return GP_ERR_ARG;
+    gp_plan* q = new (std::nothrow) gp_plan(*p);
+    if (!q) return GP_ERR_NOMEM;
+    gp_launch f = l;
+    f.root_stride = 0;
+    f.root_offset = 0;
+    q->launch = gpint::apply_launch(q->launch, &f);
+    *out = q;
     return GP_OK;
 }
 
@@ -611,27 +629,45 @@ gp_status gp_list(const gp_graph* g, const gp_plan* p, const gp_launch* launch, 
 
 namespace {
 // Device descriptors and per-plan launch shapes of a batch, in the order the
-// batch runs them: by measured (tuned) run time, longest first, so the light
-// plans fill the tail of the heavy ones; untimed plans keep their order after
-// the timed ones. slot[i] is where the caller's plan i runs.
+// batch runs them. Plans of one launch shape run together in one launch
+// (shapes in the order of their longest measured plan); within a shape, by
+// measured (tuned) run time, longest first, so the light plans fill the tail
+// of the heavy ones; untimed plans keep their order after the timed ones.
+// slot[i] is where the caller's plan i runs.
 gp_status batch_inputs(const gp_graph* g, const gp_plan* const* plans, int32_t np, const gp_launch* launch,
                        std::vector<GpPlanDesc>* descs, std::vector<gpint::LaunchCfg>* cfgs,
                        std::vector<int>* slot, int* waves_per_cu) {
     if (!plans || np < 1 || np > 64) return GP_ERR_ARG;
     std::vector<int> ord(np);
+    std::vector<gpint::LaunchCfg> cfg(np);
+    std::vector<int> key(np);
     for (int i = 0; i < np; ++i) {
         if (!plans[i]) return GP_ERR_ARG;
         ord[i] = i;
+        cfg[i] = gpint::launch_for_plan(plans[i], launch, g->dg);
+        key[i] = gpint::batch_shape_key(plans[i]->desc, cfg[i], 8);
     }
-    std::stable_sort(ord.begin(), ord.end(),
-                     [&](int a, int b) { return plans[a]->tuned_ms > plans[b]->tuned_ms; });
+    // a shape's rank: its longest plan
+    std::map<int, double> shape_ms;
+    for (int i = 0; i < np; ++i) {
+        auto it = shape_ms.find(key[i]);
+        if (it == shape_ms.end()) shape_ms[key[i]] = plans[i]->tuned_ms;
+        else it->second = std::max(it->second, plans[i]->tuned_ms);
+    }
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+        if (key[a] != key[b]) {
+            const double ma = shape_ms[key[a]], mb = shape_ms[key[b]];
+            return ma != mb ? ma > mb : key[a] < key[b];
+        }
+        return plans[a]->tuned_ms > plans[b]->tuned_ms;
+    });
     descs->resize(np);
     cfgs->resize(np);
     slot->resize(np);
     for (int r = 0; r < np; ++r) {
         const int i = ord[r];
         (*descs)[r] = plans[i]->desc;
-        (*cfgs)[r] = gpint::launch_for_plan(plans[i], launch, g->dg);
+        (*cfgs)[r] = cfg[i];
         (*slot)[i] = r;
     }
     *waves_per_cu = launch && launch->waves_per_cu ? launch->waves_per_cu : 32;
@@ -640,13 +676,16 @@ gp_status batch_inputs(const gp_graph* g, const gp_plan* const* plans, int32_t n
 }
 
 // Counts of a finished batch from its result words (4 per plan, batch order).
-gp_status batch_counts(const std::vector<GpPlanDesc>& descs, const std::vector<int>& slot,
-                       const unsigned long long* res, uint64_t* out) {
+// A plan whose launch counts a root sample (stride above 1 or an offset) is
+// not whole: its IEP quotient is rounded down, not checked.
+gp_status batch_counts(const std::vector<GpPlanDesc>& descs, const std::vector<gpint::LaunchCfg>& cfgs,
+                       const std::vector<int>& slot, const unsigned long long* res, uint64_t* out) {
     const int np = (int)slot.size();
     std::vector<uint64_t> tmp(np);
     for (int i = 0; i < np; ++i) {
         const int r = slot[i];
-        gp_status st = gpint::batch_result(descs[r], res + 4 * r, &tmp[i]);
+        const bool whole = cfgs[r].root_stride <= 1 && cfgs[r].root_offset == 0;
+        gp_status st = gpint::batch_result(descs[r], res + 4 * r, &tmp[i], whole);
         if (st != GP_OK) return st;
     }
     for (int i = 0; i < np; ++i) out[i] = tmp[i];
@@ -677,7 +716,7 @@ gp_status gp_count_batch(const gp_graph* g, const gp_plan* const* plans, int32_t
     if (hipStreamSynchronize(s) != hipSuccess && st == GP_OK) st = GP_ERR_HIP;
     gpint::batch_release(&bs);
     if (st != GP_OK) return st;
-    return batch_counts(descs, slot, h.data(), out);
+    return batch_counts(descs, cfgs, slot, h.data(), out);
 }
 
 gp_status gp_batch_create(const gp_graph* g, const gp_plan* const* plans, int32_t np,
@@ -732,7 +771,7 @@ gp_status gp_batch_run(gp_batch* b, void* stream, uint64_t* out) {
     hipStream_t s = (hipStream_t)stream;
     GP_HIP_TRY(hipGraphLaunch(b->exec, s));
     GP_HIP_TRY(hipStreamSynchronize(s));
-    return batch_counts(b->descs, b->slot, b->host_res, out);
+    return batch_counts(b->descs, b->cfgs, b->slot, b->host_res, out);
 }
 
 gp_status gp_batch_set_sample(gp_batch* b, int64_t root_stride, int64_t root_offset, void* stream) {

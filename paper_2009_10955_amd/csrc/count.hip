@@ -16,14 +16,14 @@ KernelFn pick_kernel_k5(int group, int leaf, int mode, int iep);
 KernelFn pick_kernel_k6(int group, int leaf, int mode, int iep);
 KernelFn pick_kernel_k7(int group, int leaf, int mode, int iep);
 KernelFn pick_kernel_k8(int group, int leaf, int mode, int iep);
-BatchFn batch_kernel_k5();
-BatchFn batch_kernel_k6();
-BatchFn batch_kernel_k8();
+BatchFn batch_kernel_k5(int group, int leaf, int iep);
+BatchFn batch_kernel_k6(int group, int leaf, int iep);
+BatchFn batch_kernel_k8(int group, int leaf, int iep);
 
-BatchFn pick_batch_kernel(int kmax) {
-    if (kmax <= 5) return batch_kernel_k5();
-    if (kmax <= 6) return batch_kernel_k6();
-    if (kmax <= 8) return batch_kernel_k8();
+BatchFn pick_batch_kernel(int kmax, int group, int leaf, int iep) {
+    if (kmax <= 5) return batch_kernel_k5(group, leaf, iep);
+    if (kmax <= 6) return batch_kernel_k6(group, leaf, iep);
+    if (kmax <= 8) return batch_kernel_k8(group, leaf, iep);
     return nullptr;
 }
 
@@ -106,12 +106,20 @@ LaunchCfg default_launch(const GpPlanDesc& d) {
     return cfg;
 }
 
-int resident_waves_per_cu(const GpPlanDesc& d, const LaunchCfg& cfg) {
+int64_t lds_buffer_bytes(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCfg& cfg) {
+    if (cfg.lds <= 0 || d.nbuf <= 0) return 0;
+    const int group = d.iep ? (cfg.group >= 64 ? 64 : 32) : cfg.group;
+    const int64_t bytes = (int64_t)(kBlock / group) * d.nbuf * std::max<int64_t>(1, g.deg2) * 4;
+    return bytes <= kLdsBufferBytes ? bytes : 0;
+}
+
+int resident_waves_per_cu(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCfg& cfg) {
     const bool iep = d.iep != 0;
     const int group = iep ? (cfg.group >= 64 ? 64 : 32) : cfg.group;
     KernelFn fn = pick_kernel(d.k, group, cfg.leaf, MODE_PLAIN, d.iep);
     int nb = 0;
-    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)fn, kBlock, 0) != hipSuccess ||
+    const int64_t lds = lds_buffer_bytes(g, d, cfg);
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)fn, kBlock, (size_t)lds) != hipSuccess ||
         nb <= 0)
         return cfg.waves_per_cu;
     return std::min(cfg.waves_per_cu, nb * (kBlock / 64));
@@ -127,6 +135,7 @@ LaunchCfg apply_launch(LaunchCfg cfg, const gp_launch* l) {
         cfg.root_offset = l->root_offset;
         if (l->split_ways) cfg.split_ways = l->split_ways;
         if (l->split_vertices) cfg.split_vertices = l->split_vertices;
+        if (l->lds_buffers) cfg.lds = l->lds_buffers > 0 ? 1 : 0;
     }
     return cfg;
 }
@@ -226,7 +235,16 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
     int64_t need_blocks = std::max<int64_t>(1, (need + groups_per_block - 1) / groups_per_block);
     blocks = std::min(blocks, need_blocks);
 
-    const size_t scratch_bytes = (size_t)(blocks * per_block);
+    // candidate buffers in LDS when the block's fit (then no scratch)
+    const int64_t lds_bytes = lds_buffer_bytes(g, d, cfg);
+    if (lds_bytes > 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)fn, kBlock, (size_t)lds_bytes) ==
+                hipSuccess &&
+            nb > 0)
+            blocks = std::min<int64_t>(blocks, std::max<int64_t>(1, (int64_t)g.num_cus * nb));
+    }
+    const size_t scratch_bytes = lds_bytes > 0 ? 0 : (size_t)(blocks * per_block);
     // leaf mode 4's per-task memo: one word per hub per group, within 4 GiB
     // (within what the workspace has left)
     const int64_t memo_words = blocks * groups_per_block * (int64_t)g.n_hubs;
@@ -287,7 +305,9 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
     a.busy = busy;
     a.memo = memo;
     a.chunk = cfg.chunk;
-    if (n_tasks > 0) hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kBlock), 0, stream, d, a);
+    a.lds_bufs = lds_bytes > 0 ? 1 : 0;
+    if (n_tasks > 0)
+        hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kBlock), (uint32_t)lds_bytes, stream, d, a);
     // a sample's total need not be a multiple of the over-count: its quotient
     // is an estimate, not checked
     const bool whole = cfg.root_stride == 1 && cfg.root_offset == 0 && !(busy && cfg.budget_ms > 0);
@@ -379,21 +399,29 @@ void batch_release(BatchState* st) {
 }
 
 // A plan's shape inside a batch: IEP plans run in 64- or 32-lane groups,
-// others in 64, 32 or 16; leaf modes 1, 3 or 4 (2 runs as 1).
-static void batch_shape(const GpPlanDesc& d, const LaunchCfg& c, BatchPlan* bp) {
-    if (d.iep) bp->group = c.group >= 64 ? 64 : 32;
-    else bp->group = c.group >= 64 ? 64 : (c.group >= 32 ? 32 : 16);
+// others in 64, 32, 16 or 8 (floored at min_group); leaf modes 1, 3 or 4 (2
+// runs as 1).
+static void batch_shape(const GpPlanDesc& d, const LaunchCfg& c, int min_group, BatchPlan* bp) {
+    const int want = std::max(c.group, min_group);
+    if (d.iep) bp->group = want >= 64 ? 64 : 32;
+    else bp->group = want >= 64 ? 64 : (want >= 32 ? 32 : (want >= 16 ? 16 : 8));
     bp->leaf = d.iep ? 1 : (c.leaf == 3 || c.leaf == 4 ? c.leaf : 1);
     bp->chunk = std::max(1, c.chunk);
 }
 
+int batch_shape_key(const GpPlanDesc& d, const LaunchCfg& c, int min_group) {
+    BatchPlan bp;
+    batch_shape(d, c, min_group, &bp);
+    return (bp.group << 8) | (bp.leaf << 4) | d.iep;
+}
+
 // Per-plan task ranges, shapes and the launch geometry for np plans.
 static gp_status batch_layout(const DeviceGraph& g, const GpPlanDesc* descs, const LaunchCfg* cfgs,
-                              const int64_t* offsets, const int64_t* counts, int np, BatchState* b,
-                              std::vector<BatchPlan>* plans) {
+                              const int64_t* offsets, const int64_t* counts, int np, int min_group_floor,
+                              BatchState* b, std::vector<BatchPlan>* plans) {
     plans->resize(np);
+    b->runs.clear();
     int32_t nbuf = 0;
-    int min_group = 64;
     b->kmax = 2;
     int64_t tag_next = 1;  // memo tags of the eligible plans: disjoint ranges
     bool any_memo = false;
@@ -421,7 +449,21 @@ static gp_status batch_layout(const DeviceGraph& g, const GpPlanDesc* descs, con
         bp.task_offset = off;
         bp.split_roots = sp.roots;
         bp.split_ways = sp.ways;
-        batch_shape(descs[i], cfgs[i], &bp);
+        batch_shape(descs[i], cfgs[i], min_group_floor, &bp);
+        // consecutive plans of one shape share a launch
+        const int iep_depth = descs[i].iep;
+        if (b->runs.empty() || b->runs.back().group != bp.group || b->runs.back().leaf != bp.leaf ||
+            b->runs.back().iep != iep_depth) {
+            BatchRun r;
+            r.p0 = i;
+            r.group = bp.group;
+            r.leaf = bp.leaf;
+            r.iep = iep_depth;
+            b->runs.push_back(r);
+        }
+        b->runs.back().p1 = i + 1;
+        b->runs.back().kmax = std::max(b->runs.back().kmax, (int)descs[i].k);
+        b->runs.back().waves_per_cu = std::max(b->runs.back().waves_per_cu, cfgs[i].waves_per_cu);
         bp.tag_base = 0;
         if (bp.leaf == 4 && !descs[i].iep && g.n_hubs > 0 && memo_eligible(descs[i]) &&
             tag_next + n_all < (int64_t(1) << 32) - 1) {
@@ -429,13 +471,11 @@ static gp_status batch_layout(const DeviceGraph& g, const GpPlanDesc* descs, con
             tag_next += n_all;
             any_memo = true;
         }
-        min_group = std::min(min_group, bp.group);
         nbuf = std::max(nbuf, descs[i].nbuf);
         b->kmax = std::max(b->kmax, (int)descs[i].k);
     }
     b->np = np;
     b->nbuf = nbuf;
-    b->slots_per_wave = 64 / min_group;
     b->use_memo = any_memo;
     return GP_OK;
 }
@@ -459,6 +499,9 @@ static int64_t batch_blocks(const DeviceGraph& g, int waves_per_cu, int slots_pe
     return blocks;
 }
 
+// Group slots (scratch and memo tables) a run's launch addresses.
+static int64_t run_group_slots(const BatchRun& r) { return r.blocks * (kBlock / 64) * (64 / r.group); }
+
 gp_status batch_prepare(const DeviceGraph& g, const GpPlanDesc* descs, const LaunchCfg* cfgs,
                         const int64_t* offsets, const int64_t* counts, int np, int waves_per_cu,
                         hipStream_t stream, BatchState* st) {
@@ -466,17 +509,20 @@ gp_status batch_prepare(const DeviceGraph& g, const GpPlanDesc* descs, const Lau
     BatchState b;
     b.cap = std::max<int64_t>(1, g.deg2);
     std::vector<BatchPlan> plans;
-    gp_status rc = batch_layout(g, descs, cfgs, offsets, counts, np, &b, &plans);
+    gp_status rc = batch_layout(g, descs, cfgs, offsets, counts, np, 8, &b, &plans);
     if (rc != GP_OK) return rc;
-    b.blocks = batch_blocks(g, waves_per_cu, b.slots_per_wave, b.nbuf, b.cap, b.use_memo);
-    const int64_t waves = b.blocks * (kBlock / 64);
-    b.memo_words = b.use_memo ? waves * b.slots_per_wave * (int64_t)g.n_hubs : 0;
+    // every run at its own width and residency; the regions fit the largest
+    int64_t slots = 0;
+    for (BatchRun& r : b.runs) {
+        r.blocks = batch_blocks(g, std::min(waves_per_cu, r.waves_per_cu), 64 / r.group, b.nbuf, b.cap, b.use_memo);
+        slots = std::max(slots, run_group_slots(r));
+    }
+    b.memo_words = b.use_memo ? slots * (int64_t)g.n_hubs : 0;
     if (hipMalloc(&b.descs, sizeof(GpPlanDesc) * np) != hipSuccess ||
         hipMalloc(&b.plans, sizeof(BatchPlan) * np) != hipSuccess ||
         hipMalloc((void**)&b.queues, sizeof(unsigned long long) * np) != hipSuccess ||
         hipMalloc((void**)&b.result, 4 * sizeof(unsigned long long) * np) != hipSuccess ||
-        (b.nbuf > 0 &&
-         hipMalloc((void**)&b.scratch, (size_t)(waves * b.slots_per_wave * b.nbuf * b.cap * 4)) != hipSuccess) ||
+        (b.nbuf > 0 && hipMalloc((void**)&b.scratch, (size_t)(slots * b.nbuf * b.cap * 4)) != hipSuccess) ||
         (b.memo_words > 0 && hipMalloc((void**)&b.memo, (size_t)b.memo_words * 8) != hipSuccess))
         rc = GP_ERR_NOMEM;
     if (rc == GP_OK &&
@@ -497,18 +543,23 @@ gp_status batch_update(const DeviceGraph& g, BatchState* st, const GpPlanDesc* d
                        hipStream_t stream) {
     BatchState b = *st;
     std::vector<BatchPlan> plans;
-    gp_status rc = batch_layout(g, descs, cfgs, nullptr, nullptr, st->np, &b, &plans);
+    gp_status rc = batch_layout(g, descs, cfgs, nullptr, nullptr, st->np, 8, &b, &plans);
     if (rc != GP_OK) return rc;
-    if (b.nbuf != st->nbuf || b.slots_per_wave > st->slots_per_wave || b.use_memo != st->use_memo)
-        return GP_ERR_ARG;  // the shapes the buffers were carved for must not change
+    bool same = b.nbuf == st->nbuf && b.use_memo == st->use_memo && b.runs.size() == st->runs.size();
+    for (size_t i = 0; same && i < b.runs.size(); ++i)
+        same = b.runs[i].p0 == st->runs[i].p0 && b.runs[i].p1 == st->runs[i].p1 &&
+               b.runs[i].group == st->runs[i].group && b.runs[i].leaf == st->runs[i].leaf &&
+               b.runs[i].iep == st->runs[i].iep;
+    if (!same) return GP_ERR_ARG;  // the shapes the buffers were carved for must not change
     GP_HIP_TRY(hipMemcpyAsync(st->plans, plans.data(), sizeof(BatchPlan) * st->np, hipMemcpyHostToDevice, stream));
     GP_HIP_TRY(hipStreamSynchronize(stream));
     return GP_OK;
 }
 
 gp_status batch_enqueue(const DeviceGraph& g, const BatchState& st, hipStream_t stream) {
-    BatchFn fn = pick_batch_kernel(st.kmax);
-    if (!fn) return GP_ERR_UNSUPPORTED;
+    if (st.runs.empty()) return GP_ERR_ARG;
+    for (const BatchRun& r : st.runs)
+        if (!pick_batch_kernel(r.kmax, r.group, r.leaf, r.iep) || r.blocks < 1) return GP_ERR_UNSUPPORTED;
     for (int i = 0; i < st.np; i += 64)
         hipLaunchKernelGGL(init_counters, dim3(1), dim3(64), 0, stream, st.queues + i, std::min(64, st.np - i));
     for (int i = 0; i < 4 * st.np; i += 64)
@@ -517,23 +568,29 @@ gp_status batch_enqueue(const DeviceGraph& g, const BatchState& st, hipStream_t 
     if (st.memo_words > 0)
         hipLaunchKernelGGL(zero_u64, dim3((unsigned)std::min<int64_t>(4096, (st.memo_words + 255) / 256)), dim3(256),
                            0, stream, st.memo, st.memo_words);
-    BatchArgs a;
-    a.row_ptr = g.row_ptr;
-    a.col = g.col;
-    a.descs = (const GpPlanDesc*)st.descs;
-    a.plans = (const BatchPlan*)st.plans;
-    a.np = st.np;
-    a.hub_bits = g.hub_bits;
-    a.hub_words = g.hub_words;
-    a.n_hubs = g.n_hubs;
-    a.scratch = st.scratch;
-    a.buf_cap = st.cap;
-    a.nbuf = st.nbuf;
-    a.slots_per_wave = st.slots_per_wave;
-    a.memo = st.memo_words > 0 ? st.memo : nullptr;
-    a.queues = st.queues;
-    a.result = st.result;
-    hipLaunchKernelGGL(fn, dim3((unsigned)st.blocks), dim3(kBlock), 0, stream, a);
+    // one persistent launch per run of same-shape plans, in batch order. The
+    // runs share the scratch and memo regions: launches on one stream never
+    // overlap, and memo tags are disjoint per plan.
+    for (const BatchRun& r : st.runs) {
+        BatchArgs a;
+        a.row_ptr = g.row_ptr;
+        a.col = g.col;
+        a.descs = (const GpPlanDesc*)st.descs + r.p0;
+        a.plans = (const BatchPlan*)st.plans + r.p0;
+        a.np = r.p1 - r.p0;
+        a.hub_bits = g.hub_bits;
+        a.hub_words = g.hub_words;
+        a.n_hubs = g.n_hubs;
+        a.scratch = st.scratch;
+        a.buf_cap = st.cap;
+        a.nbuf = st.nbuf;
+        a.slots_per_wave = 64 / r.group;
+        a.memo = st.memo_words > 0 ? st.memo : nullptr;
+        a.queues = st.queues + r.p0;
+        a.result = st.result + 4 * r.p0;
+        hipLaunchKernelGGL(pick_batch_kernel(r.kmax, r.group, r.leaf, r.iep), dim3((unsigned)r.blocks), dim3(kBlock),
+                           0, stream, a);
+    }
     return hipGetLastError() == hipSuccess ? GP_OK : GP_ERR_HIP;
 }
 
@@ -542,19 +599,18 @@ gp_status arena_create(const DeviceGraph& g, int nbuf_cap, int waves_per_cu, int
     a.waves_per_cu = waves_per_cu;
     BatchState& b = a.st;
     b.cap = std::max<int64_t>(1, g.deg2);
-    a.min_group = min_group >= 64 ? 64 : (min_group >= 32 ? 32 : 16);
+    a.min_group = min_group >= 64 ? 64 : (min_group >= 32 ? 32 : (min_group >= 16 ? 16 : 8));
     a.nbuf_cap = std::max(0, std::min(nbuf_cap, GP_DESC_MAX_BUILDS));
     // room for the smallest group width and for the memo of leaf-4 plans
     a.blocks_cap = batch_blocks(g, waves_per_cu, 64 / a.min_group, a.nbuf_cap, b.cap, true);
-    const int64_t waves = a.blocks_cap * (kBlock / 64);
-    a.memo_words_cap = g.n_hubs > 0 ? waves * (64 / a.min_group) * (int64_t)g.n_hubs : 0;
+    a.slots_cap = a.blocks_cap * (kBlock / 64) * (64 / a.min_group);
+    a.memo_words_cap = g.n_hubs > 0 ? a.slots_cap * (int64_t)g.n_hubs : 0;
     bool ok = hipMalloc(&b.descs, sizeof(GpPlanDesc) * kBatchMaxPlans) == hipSuccess &&
               hipMalloc(&b.plans, sizeof(BatchPlan) * kBatchMaxPlans) == hipSuccess &&
               hipMalloc((void**)&b.queues, sizeof(unsigned long long) * kBatchMaxPlans) == hipSuccess &&
               hipMalloc((void**)&b.result, 4 * sizeof(unsigned long long) * kBatchMaxPlans) == hipSuccess &&
               (a.nbuf_cap == 0 ||
-               hipMalloc((void**)&b.scratch,
-                         (size_t)(waves * (64 / a.min_group) * a.nbuf_cap * b.cap * 4)) == hipSuccess) &&
+               hipMalloc((void**)&b.scratch, (size_t)(a.slots_cap * a.nbuf_cap * b.cap * 4)) == hipSuccess) &&
               (a.memo_words_cap == 0 || hipMalloc((void**)&b.memo, (size_t)a.memo_words_cap * 8) == hipSuccess) &&
               hipHostMalloc((void**)&a.h_descs, sizeof(GpPlanDesc) * kBatchMaxPlans, hipHostMallocDefault) ==
                   hipSuccess &&
@@ -574,20 +630,23 @@ gp_status arena_launch(const DeviceGraph& g, BatchArena* ar, const GpPlanDesc* d
     if (np < 1 || np > kBatchMaxPlans) return GP_ERR_ARG;
     BatchState& b = ar->st;
     std::vector<BatchPlan> plans;
-    gp_status rc = batch_layout(g, descs, cfgs, offsets, counts, np, &b, &plans);
+    gp_status rc = batch_layout(g, descs, cfgs, offsets, counts, np, ar->min_group, &b, &plans);
     if (rc != GP_OK) return rc;
     if (b.nbuf > ar->nbuf_cap) return GP_ERR_NOMEM;
-    if (b.slots_per_wave > 64 / ar->min_group) return GP_ERR_ARG;
-    // the scratch and memo were carved for the arena's largest shape; any smaller one fits
-    b.slots_per_wave = 64 / ar->min_group;
-    b.blocks = std::min(ar->blocks_cap, batch_blocks(g, ar->waves_per_cu, b.slots_per_wave, b.nbuf, b.cap, b.use_memo));
-    if (b.nbuf > 0) {
-        const int64_t fit = ar->blocks_cap * ar->nbuf_cap / b.nbuf;
-        b.blocks = std::min(b.blocks, std::max<int64_t>(1, fit));
+    // each run within the regions carved at creation: group slots x nbuf
+    // buffers of scratch, group slots x n_hubs memo words
+    int64_t room = b.nbuf > 0 ? ar->slots_cap * ar->nbuf_cap / b.nbuf : ar->slots_cap;
+    if (b.use_memo) room = std::min(room, ar->slots_cap);
+    int64_t slots = 0;
+    for (BatchRun& r : b.runs) {
+        const int64_t per_block = (kBlock / 64) * (64 / r.group);
+        r.blocks = batch_blocks(g, std::min(ar->waves_per_cu, r.waves_per_cu), 64 / r.group, b.nbuf, b.cap,
+                                b.use_memo);
+        r.blocks = std::max<int64_t>(1, std::min(r.blocks, room / per_block));
+        slots = std::max(slots, run_group_slots(r));
     }
-    const int64_t waves = b.blocks * (kBlock / 64);
-    b.memo_words = b.use_memo ? std::min(ar->memo_words_cap, waves * b.slots_per_wave * (int64_t)g.n_hubs) : 0;
-    if (b.use_memo && b.memo_words < waves * b.slots_per_wave * (int64_t)g.n_hubs) {
+    b.memo_words = b.use_memo ? slots * (int64_t)g.n_hubs : 0;
+    if (b.memo_words > ar->memo_words_cap) {
         // no room for every wave's table: run the leaf-4 plans without the memo
         for (auto& bp : plans) bp.tag_base = 0;
         b.memo_words = 0;
@@ -603,11 +662,12 @@ gp_status arena_launch(const DeviceGraph& g, BatchArena* ar, const GpPlanDesc* d
     return GP_OK;
 }
 
-gp_status batch_result(const GpPlanDesc& d, const unsigned long long* r, uint64_t* out) {
+gp_status batch_result(const GpPlanDesc& d, const unsigned long long* r, uint64_t* out, bool whole) {
     unsigned __int128 t = ((unsigned __int128)r[3] << 64) | (unsigned __int128)r[0];
     const uint64_t div = d.iep ? (uint64_t)d.iep_div : 1;
     if (div > 1) {
-        if (t % div) return GP_ERR_INTERNAL;
+        // a whole count is a multiple of the over-count; a sample's need not be
+        if (whole && t % div) return GP_ERR_INTERNAL;
         t /= div;
     }
     if (t >> 64) return GP_ERR_OVERFLOW;

@@ -1,17 +1,21 @@
-// Batched persistent kernel: several plans (patterns or configurations of
+// Batched persistent kernels: several plans (patterns or configurations of
 // uneven cost, any k, counted plainly or with inclusion-exclusion) over one
-// graph in ONE launch.
+// graph, captured together in one hipGraph.
 //
-// Every plan has its own task cursor and its own launch shape: lanes per
-// group (64, 32 or 16), leaf mode (1, 3 or 4) and tasks per grab, as tuned for
-// it alone. Wavefronts take the plans in order: a wavefront grabs a piece of
-// the current plan's tasks (its groups' share), runs it at that plan's shape
-// (the wavefront splits into 64/G groups for it), and moves to the next plan
-// once the current one's cursor is exhausted, so plans of uneven cost fill
-// each other's tails (Section IV-E's task partitioning, across patterns).
-// Per-plan 128-bit counts (and the wall-clock time spent on each plan, for
-// the serving scheduler) are summed per wavefront in LDS and published once at
-// the end. Built once per largest pattern size (-DGP_BATCH_KMAX=5/6/8).
+// Every plan keeps the launch shape tuned for it alone: lanes per group (64,
+// 32, 16 or 8), leaf mode (1, 3 or 4) and inclusion-exclusion depth, plus its
+// tasks per grab. The plans of one shape share ONE persistent launch of a
+// kernel compiled for that shape only, with a task cursor per plan:
+// wavefronts take the plans in order, grab a piece of the current plan's
+// tasks (64/G groups, bp.chunk tasks each), and move to the next plan once
+// its cursor is exhausted, so plans of uneven cost fill each other's tails
+// (Section IV-E's task partitioning, across patterns). One kernel per shape,
+// not one kernel for all shapes: a body that branches over several shapes
+// keeps the register allocation of their union, and the spills that follow
+// cost more than a launch. Per-plan 128-bit counts (and the wall-clock time
+// spent on each plan, for the serving scheduler) are summed per wavefront in
+// LDS and published once at the end. Built once per largest pattern size
+// (-DGP_BATCH_KMAX=5/6/8).
 #include "count_kernel.hpp"
 
 #if !defined(GP_BATCH_KMAX)
@@ -81,8 +85,9 @@ __device__ void run_piece(const BatchArgs& a, const GpPlanDesc& d, const BatchPl
     }
 }
 
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(occupancy_target(KMAX, 64, 1)))) void batch_kernel(BatchArgs a) {
-    __shared__ int32_t s_len[kBlock / 16][GP_DESC_MAX_BUILDS];
+template <int G, int LEAF, int IEP>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(occupancy_target(KMAX, G, LEAF, IEP)))) void batch_kernel(BatchArgs a) {
+    __shared__ int32_t s_len[kBlock / G][GP_DESC_MAX_BUILDS];
     __shared__ unsigned long long s_lo[kBlock / 64][kBatchMaxPlans];
     __shared__ unsigned long long s_hi[kBlock / 64][kBatchMaxPlans];
     __shared__ unsigned long long s_busy[kBlock / 64][kBatchMaxPlans];
@@ -96,13 +101,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(occupanc
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     const int64_t wave_global = (int64_t)blockIdx.x * (kBlock / 64) + wave;
-    int32_t* lens_base = &s_len[wave * 4][0];
+    int32_t* lens_base = &s_len[wave * (64 / G)][0];
+    constexpr int64_t kGroups = 64 / G;
 
     int p = 0;
     while (p < a.np) {
         const BatchPlan& bp = a.plans[p];
-        const int group = __builtin_amdgcn_readfirstlane(bp.group);
-        const int64_t W = (int64_t)(64 / group) * bp.chunk;
+        const int64_t W = kGroups * bp.chunk;
         unsigned long long q = 0;
         if (lane == 0) q = atomicAdd(&a.queues[p], (unsigned long long)W);
         const int64_t t0 = uni64<64>((int64_t)__shfl(q, 0, 64));
@@ -115,33 +120,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(occupanc
         const GpPlanDesc& d = a.descs[p];
         const uint64_t clk0 = wall_clock64();
         uint64_t acc = 0, carry = 0;
-        const int64_t s0 = bp.task_offset + t0, s1 = bp.task_offset + t1;
-        const int leaf = __builtin_amdgcn_readfirstlane(bp.leaf);
-        const int iep = __builtin_amdgcn_readfirstlane(d.iep);
-        if (iep) {
-            // IEP plans: 64- or 32-lane groups, one kernel body per depth
-            if (group == 64) {
-                if (iep == 2) run_piece<64, 1, 2>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
-                else if (iep == 3) run_piece<64, 1, 3>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
-                else run_piece<64, 1, 4>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
-            } else {
-                if (iep == 2) run_piece<32, 1, 2>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
-                else if (iep == 3) run_piece<32, 1, 3>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
-                else run_piece<32, 1, 4>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
-            }
-        } else if (group == 64) {
-            if (leaf == 3) run_piece<64, 3, 0>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
-            else if (leaf == 4) run_piece<64, 4, 0>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
-            else run_piece<64, 1, 0>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
-        } else if (group == 32) {
-            if (leaf == 3) run_piece<32, 3, 0>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
-            else if (leaf == 4) run_piece<32, 4, 0>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
-            else run_piece<32, 1, 0>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
-        } else {
-            if (leaf == 3) run_piece<16, 3, 0>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
-            else if (leaf == 4) run_piece<16, 4, 0>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
-            else run_piece<16, 1, 0>(a, d, bp, s0, s1, lens_base, wave_global, acc, carry);
-        }
+        run_piece<G, LEAF, IEP>(a, d, bp, bp.task_offset + t0, bp.task_offset + t1, lens_base, wave_global, acc,
+                                carry);
         // exact 128-bit wavefront sum into this wavefront's LDS counter of plan p
         wave_sum128(acc, carry);
         if (lane == 0) {
@@ -165,6 +145,33 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(occupanc
 #define GP_CAT2(a, b) a##b
 #define GP_CAT(a, b) GP_CAT2(a, b)
 
-BatchFn GP_CAT(batch_kernel_k, GP_BATCH_KMAX)() { return batch_kernel; }
+// The kernel of one batch shape: group width 64/32/16/8 with leaf mode 1, 3 or
+// 4 (IEP depth 0), or group width 64/32 with IEP depth 2..4 (leaf mode 1);
+// null for any other shape.
+BatchFn GP_CAT(batch_kernel_k, GP_BATCH_KMAX)(int group, int leaf, int iep) {
+    if (iep) {
+        if (leaf != 1 || (group != 64 && group != 32)) return nullptr;
+#define GP_IEP_CASE(D)                                                                \
+    if (iep == D) return group == 64 ? batch_kernel<64, 1, D> : batch_kernel<32, 1, D>;
+        GP_IEP_CASE(2)
+        GP_IEP_CASE(3)
+        GP_IEP_CASE(4)
+#undef GP_IEP_CASE
+        return nullptr;
+    }
+#define GP_PLAIN_CASE(GG)                                                       \
+    if (group == GG) {                                                          \
+        if (leaf == 1) return batch_kernel<GG, 1, 0>;                           \
+        if (leaf == 3) return batch_kernel<GG, 3, 0>;                           \
+        if (leaf == 4) return batch_kernel<GG, 4, 0>;                           \
+        return nullptr;                                                         \
+    }
+    GP_PLAIN_CASE(64)
+    GP_PLAIN_CASE(32)
+    GP_PLAIN_CASE(16)
+    GP_PLAIN_CASE(8)
+#undef GP_PLAIN_CASE
+    return nullptr;
+}
 
 }  // namespace gpcount

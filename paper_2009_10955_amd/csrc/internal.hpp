@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "gp.h"
 #include "plan_desc.h"
 
@@ -44,7 +46,11 @@ struct LaunchCfg {
     int split_ways = 1;
     int64_t split_vertices = 0;
     double budget_ms = 0;  // time limit per wavefront (measurement only; 0: none)
+    int lds = 0;           // 1: candidate buffers in LDS when a block's fit kLdsBufferBytes
 };
+
+// Largest LDS a block's candidate buffers may take (dynamic shared memory).
+constexpr int64_t kLdsBufferBytes = 64 << 10;
 
 // Device memory a launch may use instead of allocating its own: the task
 // cursor and high count word, the per-group candidate buffers and, when room
@@ -55,7 +61,10 @@ struct Workspace {
 };
 
 // Wavefronts per compute unit that a launch of d with cfg keeps resident.
-int resident_waves_per_cu(const GpPlanDesc& d, const LaunchCfg& cfg);
+int resident_waves_per_cu(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCfg& cfg);
+// Dynamic LDS of one block whose candidate buffers live in LDS (0: they
+// live in scratch: not asked for, or more than kLdsBufferBytes).
+int64_t lds_buffer_bytes(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCfg& cfg);
 
 // Launch one count of plan d over g on `stream`. result_dev: {count,
 // flags} (plus bytes when `account`), zeroed by this call on the stream.
@@ -81,16 +90,24 @@ gp_status launch_count_noalloc(const DeviceGraph& g, const GpPlanDesc& d, const 
 gp_status launch_list(const DeviceGraph& g, const GpPlanDesc& d, const int32_t* order, const LaunchCfg& cfg,
                       hipStream_t stream, unsigned long long* found_dev, int32_t* out, int64_t out_cap);
 
-// Device state of one batched launch: descriptors, per-plan task ranges and
-// shapes, scratch, memo, task cursors and results, all allocated up front so
-// that the launch itself allocates nothing (it can be captured in a hipGraph
-// and replayed).
+// Consecutive batch plans [p0, p1) of one launch shape: one persistent launch
+// of the kernel compiled for that shape.
+struct BatchRun {
+    int p0 = 0, p1 = 0;
+    int group = 64, leaf = 1, iep = 0;
+    int kmax = 2;
+    int waves_per_cu = 1;  // the largest of its plans'
+    int64_t blocks = 0;    // grid of its launch
+};
+
+// Device state of one batch: descriptors, per-plan task ranges and shapes,
+// scratch, memo, task cursors and results, all allocated up front so that the
+// launches themselves allocate nothing (they can be captured in a hipGraph and
+// replayed).
 struct BatchState {
     int np = 0;
     int kmax = 2;
-    int slots_per_wave = 1;  // groups per wavefront of the narrowest plan
     bool use_memo = false;
-    int64_t blocks = 0;
     int32_t nbuf = 0;
     int64_t cap = 0;
     int64_t memo_words = 0;
@@ -100,6 +117,7 @@ struct BatchState {
     unsigned long long* memo = nullptr;
     unsigned long long* queues = nullptr;  // np task cursors
     unsigned long long* result = nullptr;  // 4*np: count low word, flags, busy clock ticks, count high word
+    std::vector<BatchRun> runs;            // host: the launches, in batch order
 };
 
 // A reusable batch for repeated launches with changing plans and task
@@ -114,6 +132,7 @@ struct BatchArena {
     int min_group = 64;
     int nbuf_cap = 0;
     int64_t blocks_cap = 0;
+    int64_t slots_cap = 0;  // group slots of the scratch region (nbuf_cap buffers each)
     int64_t memo_words_cap = 0;
     GpPlanDesc* h_descs = nullptr;
     void* h_plans = nullptr;
@@ -126,7 +145,8 @@ void arena_release(BatchArena* a);
 
 // Plan i runs with launch shape cfgs[i] (group, leaf, chunk, root splitting)
 // and covers its tasks [offset_i, offset_i + count_i); offsets/counts null =
-// every task.
+// every task. Consecutive plans of one shape share a launch, so callers
+// order plans by shape (batch_shape_key) to launch each shape once.
 gp_status batch_prepare(const DeviceGraph& g, const GpPlanDesc* descs, const LaunchCfg* cfgs,
                         const int64_t* offsets, const int64_t* counts, int np, int waves_per_cu,
                         hipStream_t stream, BatchState* st);
@@ -135,12 +155,16 @@ gp_status batch_prepare(const DeviceGraph& g, const GpPlanDesc* descs, const Lau
 // with. Copies the plan table to the device and waits.
 gp_status batch_update(const DeviceGraph& g, BatchState* st, const GpPlanDesc* descs, const LaunchCfg* cfgs,
                        hipStream_t stream);
-// Enqueue counter reset + the batched kernel on `stream` (no allocation).
+// The launch shape a plan takes in a batch (group width, leaf mode, IEP
+// depth; group widths floored at min_group) as one comparable key.
+int batch_shape_key(const GpPlanDesc& d, const LaunchCfg& c, int min_group);
+// Enqueue counter reset + one launch per run on `stream` (no allocation).
 gp_status batch_enqueue(const DeviceGraph& g, const BatchState& st, hipStream_t stream);
 void batch_release(BatchState* st);
 // A plan's 128-bit batch total {low, flags, busy, high} divided by its IEP
-// over-count: GP_OK and *out, or GP_ERR_OVERFLOW.
-gp_status batch_result(const GpPlanDesc& d, const unsigned long long* r4, uint64_t* out);
+// over-count (rounded down): GP_OK and *out, or GP_ERR_OVERFLOW. whole: the
+// total covers every root task, so a remainder is GP_ERR_INTERNAL.
+gp_status batch_result(const GpPlanDesc& d, const unsigned long long* r4, uint64_t* out, bool whole);
 // The counting kernels' accumulation and final step applied to n given
 // values (host memory): *out = (sum / div) mod 2^64, *flags bit 0 if the
 // quotient does not fit in 64 bits, bit 1 if div does not divide the sum.

@@ -403,8 +403,16 @@ void worker_main(gp_server* S) {
             std::vector<GpPlanDesc> descs;
             std::vector<gpint::LaunchCfg> cfgs;
             std::vector<int64_t> offs;
-            for (Query* q : S->active[g]) {
-                if (q->launched >= q->n_tasks || q->state == Q_DONE) continue;
+            // queries of one launch shape side by side: each shape is one launch
+            std::vector<Query*> ready;
+            for (Query* q : S->active[g])
+                if (q->launched < q->n_tasks && q->state != Q_DONE) ready.push_back(q);
+            const int min_group = S->arenas[2 * g + slot].min_group;
+            std::stable_sort(ready.begin(), ready.end(), [&](const Query* a, const Query* b) {
+                return gpint::batch_shape_key(a->plan->desc, lcfg, min_group) <
+                       gpint::batch_shape_key(b->plan->desc, lcfg, min_group);
+            });
+            for (Query* q : ready) {
                 const int64_t c = std::min(q->slice, q->n_tasks - q->launched);
                 descs.push_back(q->plan->desc);
                 cfgs.push_back(lcfg);
@@ -471,7 +479,7 @@ void worker_main(gp_server* S) {
             ++q->iterations;
             if (q->progress >= q->n_tasks && q->inflight == 0) {
                 const unsigned long long w[4] = {q->raw_lo, 0, 0, q->raw_hi};
-                const gp_status fs = gpint::batch_result(q->plan->desc, w, &q->count);
+                const gp_status fs = gpint::batch_result(q->plan->desc, w, &q->count, true);
                 finish(S, q, fs);
                 continue;
             }

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -54,7 +55,7 @@ double estimate_end(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCfg& 
                     const unsigned long long* h, int64_t stride) {
     if (h[1] & 4ull) return 1e300;  // a wavefront of the sample alone ran past the budget
     const double busy = (double)h[2] / g.wall_khz, chunk = (double)h[4] / g.wall_khz;
-    const double resident = (double)g.num_cus * resident_waves_per_cu(d, cfg);
+    const double resident = (double)g.num_cus * resident_waves_per_cu(g, d, cfg);
     return std::max(busy * (double)stride / resident, chunk);
 }
 
@@ -280,7 +281,7 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
                 // comparing launch shapes: the sample must keep every resident
                 // group of this shape busy (about two tasks each, one per grab),
                 // or narrower groups run with less contention than they will
-                const int64_t groups = (int64_t)g->dg.num_cus * gpint::resident_waves_per_cu(d, cfg) *
+                const int64_t groups = (int64_t)g->dg.num_cus * gpint::resident_waves_per_cu(g->dg, d, cfg) *
                                        (64 / std::max(1, cfg.group));
                 const int64_t roots = gpint::root_task_count(g->dg, d);
                 str = std::max<int64_t>(1, std::min<int64_t>(str, roots / std::max<int64_t>(1, 2 * groups)));
@@ -296,7 +297,7 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
                 return -1;
             }
             spent += t.wall;
-            const double resident = (double)g->dg.num_cus * gpint::resident_waves_per_cu(d, cfg);
+            const double resident = (double)g->dg.num_cus * gpint::resident_waves_per_cu(g->dg, d, cfg);
             // a sample of stride 1 is the full run: its wall time is the answer
             const double est = t.stopped ? inf
                                : str == 1 ? t.wall
@@ -327,7 +328,7 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
             Timing t = time_launch(g->dg, p->desc, cfg, s, res);
             if (t.wall < 0) st = GP_ERR_HIP;
             spent += std::max(0.0, t.wall);
-            const double resident = (double)g->dg.num_cus * gpint::resident_waves_per_cu(p->desc, base);
+            const double resident = (double)g->dg.num_cus * gpint::resident_waves_per_cu(g->dg, p->desc, base);
             const double full_ms = t.busy * (double)s0 / resident;
             stride = std::max<int64_t>(1, (int64_t)(full_ms / 8.0));
             stride = std::min(stride, s0);
@@ -506,6 +507,35 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
                 timed_full = true;
             }
         }
+        // 5b. finalists too slow to time in full: the two best distinct
+        //     configurations once more on a dense sample (about half the
+        //     budget each). A sparse sample runs with less contention than a
+        //     full run and underestimates it, not by the same factor for
+        //     every configuration; the choice is then between these two.
+        if (st == GP_OK && !timed_full && stride > 1 && picks.size() > 1 && spent < 3.0 * budget_ms) {
+            std::stable_sort(picks.begin(), picks.end(), [](const Pick& a, const Pick& b) { return a.est < b.est; });
+            std::vector<Pick> two;
+            for (const Pick& pk : picks) {
+                bool dup = false;
+                for (const Pick& q : two) dup |= q.c == pk.c;
+                if (!dup && pk.est < inf) two.push_back(pk);
+                if (two.size() == 2) break;
+            }
+            const int64_t sd = two.empty() ? 0 : std::max<int64_t>(1, (int64_t)std::ceil(two[0].est / (0.5 * budget_ms)));
+            if (two.size() == 2 && two[1].est < 2.0 * two[0].est && sd < stride / 4) {
+                best_est = inf;
+                bool ok = true;
+                for (Pick& pk : two) {
+                    const double t = measure(cands[pk.c].desc, pk.launch, sd, "dense", pk.c);
+                    if (t < 0) {
+                        ok = false;
+                        break;
+                    }
+                    pk.est = t;
+                }
+                if (ok) picks = two;
+            }
+        }
         size_t best = fine.empty() ? 0 : fine[0].second;
         gpint::LaunchCfg best_launch = base;
         double best_ms = inf;
@@ -559,6 +589,12 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
                     cfg.split_vertices = tv;
                     try_cfg(cfg);
                 }
+            }
+            // candidate buffers in LDS, where a block's fit
+            {
+                gpint::LaunchCfg cfg = best_launch;
+                cfg.lds = 1;
+                if (best_launch.lds == 0 && gpint::lds_buffer_bytes(g->dg, cands[best].desc, cfg) > 0) try_cfg(cfg);
             }
             // fewer resident wavefronts per compute unit: less contention for
             // the caches on graphs larger than them

@@ -62,7 +62,8 @@ class Launch(ctypes.Structure):
     _fields_ = [("group", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("leaf_mode", ctypes.c_int32),
                 ("root_stride", ctypes.c_int32), ("root_offset", ctypes.c_int32),
-                ("split_ways", ctypes.c_int32), ("split_vertices", ctypes.c_int32)]
+                ("split_ways", ctypes.c_int32), ("split_vertices", ctypes.c_int32),
+                ("lds_buffers", ctypes.c_int32)]
 
 
 class TuneOpts(ctypes.Structure):
@@ -123,6 +124,7 @@ SIGNATURES = {
     "gp_free_plan": (None, [_P]),
     "gp_tune_opts_default": (None, [ctypes.POINTER(TuneOpts)]),
     "gp_plan_tune": (_I32, [_P, _P, ctypes.POINTER(TuneOpts), _P, ctypes.POINTER(_P)]),
+    "gp_plan_with_launch": (_I32, [_P, ctypes.POINTER(Launch), ctypes.POINTER(_P)]),
     "gp_launch_default": (None, [ctypes.POINTER(Launch)]),
     "gp_count": (_I32, [_P, _P, ctypes.POINTER(Launch), _P, ctypes.POINTER(ctypes.c_uint64)]),
     "gp_count_async": (_I32, [_P, _P, ctypes.POINTER(Launch), _P, _P]),
@@ -195,9 +197,9 @@ def _stream_handle(stream) -> int:
 
 
 def _launch(group=0, waves_per_cu=0, chunk=0, leaf_mode=0, root_stride=0, root_offset=0,
-            split_ways=0, split_vertices=0) -> Launch:
+            split_ways=0, split_vertices=0, lds_buffers=0) -> Launch:
     return Launch(group, waves_per_cu, chunk, leaf_mode, root_stride, root_offset, split_ways,
-                  split_vertices)
+                  split_vertices, lds_buffers)
 
 
 class Graph:
@@ -375,10 +377,21 @@ class Plan:
         p.edges = list(self.edges)
         return p
 
+    def with_launch(self, **launch) -> "Plan":
+        """A copy of this plan whose default launch shape (the one it takes in
+        a batch) has the given non-zero fields."""
+        q = Plan.__new__(Plan)
+        q.k = self.k
+        q.edges = list(self.edges)
+        q._h = ctypes.c_void_p()
+        _check(_lib().gp_plan_with_launch(self._h, ctypes.byref(_launch(**launch)), ctypes.byref(q._h)),
+               "gp_plan_with_launch")
+        return q
+
     def launch(self) -> dict:
         l = self.info().launch
         return dict(group=l.group, waves_per_cu=l.waves_per_cu, chunk=l.chunk, leaf_mode=l.leaf_mode,
-                    split_ways=l.split_ways, split_vertices=l.split_vertices)
+                    split_ways=l.split_ways, split_vertices=l.split_vertices, lds_buffers=l.lds_buffers)
 
     def close(self) -> None:
         if self._h:

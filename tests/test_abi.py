@@ -49,7 +49,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     compiler, equal the ctypes mirrors in the binding."""
     structs = {"gp_stats": gp.Stats, "gp_plan_opts": gp.PlanOpts, "gp_plan_info": gp.PlanInfo,
                "gp_launch": gp.Launch, "gp_tune_opts": gp.TuneOpts,
-               "gp_server_opts": gp.ServerOpts, "gp_server_stats": gp.ServerStats}
+               "gp_server_opts": gp.ServerOpts, "gp_server_stats": gp.ServerStats,
+               "gp_load_opts": gp.LoadOpts}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gp.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -80,3 +81,21 @@ def test_argument_errors_need_no_device():
     assert lib.gp_load_graph(None, None, -1, 0, 0, None, ctypes.byref(h)) == -1
     assert lib.gp_count(None, None, None, None, None) == -1
     assert lib.gp_count_batch(None, None, 0, None, None, None) == -1
+
+
+def test_plan_with_launch_is_host_only_and_validated():
+    """A plan's default launch shape can be set on a copy (host only); bad
+    fields are refused and leave the output untouched."""
+    from paper_2009_10955_amd import inputs as I
+    p = gp.Plan(*I.PATTERNS["house"])
+    q = p.with_launch(group=8, leaf_mode=3, chunk=4, split_ways=4)
+    lq, lp = q.launch(), p.launch()
+    assert (lq["group"], lq["leaf_mode"], lq["chunk"], lq["split_ways"]) == (8, 3, 4, 4)
+    assert (q.order, q.restrictions) == (p.order, p.restrictions)
+    assert lp["waves_per_cu"] == lq["waves_per_cu"]
+    lib = gp.library()
+    h = ctypes.c_void_p(7)
+    for bad in (dict(group=12), dict(leaf_mode=5), dict(waves_per_cu=33), dict(chunk=-1)):
+        assert lib.gp_plan_with_launch(p.handle, ctypes.byref(gp._launch(**bad)), ctypes.byref(h)) == -1
+        assert h.value == 7
+    assert lib.gp_plan_with_launch(None, ctypes.byref(gp._launch()), ctypes.byref(h)) == -1

@@ -618,6 +618,87 @@ def test_batch_with_split_roots_equals_plain():
     b.close()
 
 
+@pytest.mark.parametrize("hubs", ["auto", "dense"])
+def test_batch_per_plan_shapes_equal_oracle(hubs):
+    """Plans of one batch at different launch shapes (every group width, leaf
+    modes 1/3/4, IEP depths 2 and 3, several plans per shape and shapes
+    interleaved in the caller's order): one launch per shape, counts equal to
+    the oracle, eager and replayed from the captured hipGraph."""
+    import torch
+    g = I.er(160, 0.1, seed=12)
+    graph = gp.Graph.from_csr(g, device=True, hub_bitmaps=hubs)
+    st = graph.stats()
+    spec = [("triangle", dict(group=8, leaf_mode=1)), ("house", dict(group=64, leaf_mode=4)),
+            ("4-cycle", dict(group=16, leaf_mode=3)), ("5-cycle", dict(group=32, leaf_mode=1)),
+            ("house", dict(group=32, leaf_mode=1), 2), ("prism", dict(group=8, leaf_mode=4)),
+            ("4-star", dict(group=64), 3), ("6-cycle-chord", dict(group=16, leaf_mode=4)),
+            ("diamond", dict(group=8, leaf_mode=1)), ("4-clique", dict(group=64, leaf_mode=4)),
+            ("4-path", dict(group=64), 2), ("5-wheel", dict(group=32, leaf_mode=3))]
+    plans, want = [], []
+    for item in spec:
+        name, launch = item[0], item[1]
+        iep = item[2] if len(item) > 2 else False
+        p = gp.Plan(*P[name], stats=st, iep=iep).with_launch(**launch)
+        if iep:
+            assert p.info().iep == iep, name
+        plans.append(p)
+        want.append(O.count(g, *P[name]))
+    assert [gp.count(graph, p) for p in plans] == want
+    assert gp.count_batch(graph, plans) == want
+    b = gp.Batch(graph, plans)
+    for rep in range(3):
+        assert b.run() == want, rep
+        assert gp.count(graph, plans[rep]) == want[rep]
+        torch.cuda.synchronize()
+    # strided samples of the same batch add up to the counts; an IEP plan's
+    # sample quotients are rounded down, so its parts fall short by under one
+    # per part
+    parts = []
+    for r in range(3):
+        b.set_sample(3, r)
+        parts.append(b.run())
+    for i, (p, x) in enumerate(zip(plans, zip(*parts))):
+        if p.info().iep_div > 1:
+            assert want[i] - 3 < sum(x) <= want[i], (spec[i], x)
+        else:
+            assert sum(x) == want[i], (spec[i], x)
+    b.set_sample(1, 0)
+    assert b.run() == want
+    b.close()
+
+
+@pytest.mark.parametrize("pname", ["4-clique", "house", "5-clique", "6-cycle-chord", "prism", "5-wheel"])
+def test_lds_buffers_equal_oracle(pname):
+    """Candidate buffers in the block's LDS (graphs whose second-largest
+    degree lets a block's buffers fit) give the oracle's count at every group
+    width and leaf mode, plain, split and sampled; where they cannot fit the
+    launch keeps them in HBM and counts the same."""
+    k, e = P[pname]
+    for g in (I.er(200, 0.08, seed=41), I.config_graph(0)):
+        graph = gp.Graph.from_csr(g)
+        want = O.count(g, k, e)
+        plan = gp.Plan(k, e, stats=graph.stats())
+        for grp in (64, 32, 16, 8):
+            for leaf in (1, 3, 4):
+                assert gp.count(graph, plan, group=grp, leaf_mode=leaf, lds_buffers=1) == want, (grp, leaf)
+        assert gp.count(graph, plan, group=16, lds_buffers=1, split_ways=3, split_vertices=1 << 20) == want
+        assert sum(gp.count(graph, plan, group=32, lds_buffers=1, root_stride=4, root_offset=r)
+                   for r in range(4)) == want
+    # two hubs of degree 1200 (disjoint leaves) over a sparse graph: the
+    # buffers of a block of 8- or 16-lane groups cannot fit LDS, and the
+    # option falls back to HBM
+    rng = np.random.default_rng(42)
+    n = 2402
+    src = [0] * 1200 + [1] * 1200 + list(rng.integers(2, n, 4000))
+    dst = list(range(2, n)) + list(rng.integers(2, n, 4000))
+    g = I.csr_from_edges(n, np.array(src), np.array(dst))
+    graph = gp.Graph.from_csr(g)
+    plan = gp.Plan(k, e, stats=graph.stats())
+    want = O.count(g, k, e)
+    for grp in (16, 8):
+        assert gp.count(graph, plan, group=grp, lds_buffers=1) == want, grp
+
+
 # --------------------------------------------------------------------- IEP
 
 @pytest.mark.parametrize("pname", ["house", "diamond", "tailed-triangle", "4-path", "3-star",

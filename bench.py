@@ -294,10 +294,10 @@ def main():
         args.traffic_json = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
     if mode == "serve":
         return serve_main(args, desc)
-    if mode == "sliced":
-        return sliced_main(args, cfg_idx, names, desc)
     if args.patterns:
         names = [n for n in names if n in args.patterns.split(",")]
+    if mode == "sliced":
+        return sliced_main(args, cfg_idx, names, desc)
     g = I.config_graph(cfg_idx)
     graph = gp.Graph.from_csr(g, device=True)
     st = graph.stats()
@@ -307,11 +307,12 @@ def main():
     t_tune = time.perf_counter()
     if args.plans_json:
         prev = json.loads(open(args.plans_json).read().strip().splitlines()[-1])["plans"]
+        launches = [dict(prev[n]["launch"]) for n in names]
+        # each plan carries its recorded launch shape (the one a batch runs it at)
         plans = [gp.Plan(*I.PATTERNS[n], stats=st, force_order=prev[n]["order"],
                          force_restr=[tuple(x) for x in prev[n]["restrictions"]],
-                         iep=bool(prev[n].get("iep", mode == "iep")))
-                 for n in names]
-        launches = [dict(prev[n]["launch"]) for n in names]
+                         iep=int(prev[n].get("iep", mode == "iep"))).with_launch(**l)
+                 for n, l in zip(names, launches)]
     elif args.no_tune:
         plans = base_plans
         launches = [p.launch() for p in plans]
@@ -744,9 +745,10 @@ def sliced_main(args, cfg_idx, names, desc):
             continue
         if args.plans_json:
             prev = json.loads(open(args.plans_json).read().strip().splitlines()[-1])["plans"][n]
-            tp = gp.Plan(*I.PATTERNS[n], stats=st, force_order=prev["order"],
-                         force_restr=[tuple(x) for x in prev["restrictions"]], iep=int(prev.get("iep", 0)))
             lt = dict(prev["launch"])
+            tp = gp.Plan(*I.PATTERNS[n], stats=st, force_order=prev["order"],
+                         force_restr=[tuple(x) for x in prev["restrictions"]],
+                         iep=int(prev.get("iep", 0))).with_launch(**lt)
         else:
             tp = bp.tuned(graph, budget_seconds=args.tune_seconds, try_iep=not args.no_try_iep)
             lt = tp.launch()
@@ -793,6 +795,14 @@ def sliced_main(args, cfg_idx, names, desc):
         batched_step(w)
         plain_step(w)
         note(f"warmup step {w + 1}/{args.warmup} done")
+    if args.copy_mib > 0:
+        # a plain device copy of known size: calibrates the traffic counters
+        x = torch.empty(args.copy_mib << 18, dtype=torch.int32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     # batched: K steps
     b_ev = [(ev(), ev()) for _ in range(args.steps)]
     counts_b = []
@@ -850,10 +860,14 @@ def sliced_main(args, cfg_idx, names, desc):
                 and all(profiling.same_plan(tr["plan"][n], cur[n]) for n in cur)):
             traffic = tr["hbm_bytes_per_launch"]
             src = os.path.relpath(args.traffic_json, ROOT)
+        l2 = tr.get("l2") if traffic is not None else None
+        avg_ms = sum(launch_ms[:nt]) / nt
         roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                     "traffic_source": src,
-                    "kernel": "batch_kernel (every feasible pattern, one launch per step)",
+                    "dram_GBps": round(traffic / (avg_ms / 1e3) / 1e9, 2) if traffic else None,
+                    "l2_hit_rate": round(l2["hit_rate"], 5) if l2 else None,
+                    "kernel": "batch_kernel (every feasible pattern; one launch per plan shape per step)",
                     "alg_bytes_per_launch": alg / nt, "alg_bytes_slices": nt,
                     "avg_launch_ms": round(sum(launch_ms[:nt]) / nt, 3),
                     "avg_launch_ms_all_steps": round(sum(launch_ms) / len(launch_ms), 3)}

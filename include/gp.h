@@ -154,6 +154,14 @@ typedef struct {
                               groups live in its LDS when they fit 64 KiB (graphs whose
                               second-largest degree is small), -1: always in HBM scratch,
                               0: the plan's own (HBM unless tuned otherwise) */
+    int32_t xcd_tasks;     /* task order over the XCDs, each with its own L2 (0 = the
+                              plan's own, one cursor unless set): > 0 deals the task space
+                              to the 8 XCDs in blocks of this many tasks (rounded up to a
+                              multiple of chunk), so one XCD's groups work on neighbouring
+                              root edges, which share their hub endpoint; an XCD that runs
+                              out helps the others. -1: one task cursor for the whole
+                              device (all XCDs walk the same stretch of root edges, which
+                              the shared last-level cache then holds once) */
 } gp_launch;
 
 void gp_launch_default(gp_launch* l);

@@ -492,6 +492,7 @@ gp_status gp_plan_get(const gp_plan* p, gp_plan_info* out) {
     out->launch.split_ways = p->launch.split_ways;
     out->launch.split_vertices = (int32_t)std::min<int64_t>(p->launch.split_vertices, INT32_MAX);
     out->launch.lds_buffers = p->launch.lds > 0 ? 1 : -1;
+    out->launch.xcd_tasks = (int32_t)std::max<int64_t>(-1, std::min<int64_t>(p->launch.xcd, INT32_MAX));
     return GP_OK;
 }
 
@@ -536,7 +537,7 @@ gp_status gp_plan_with_launch(const gp_plan* p, const gp_launch* launch, gp_plan
     const gp_launch& l = *launch;
     if ((l.group && l.group != 64 && l.group != 32 && l.group != 16 && l.group != 8) ||
         (l.leaf_mode && (l.leaf_mode < 1 || l.leaf_mode > 4)) || (l.waves_per_cu && (l.waves_per_cu < 1 || l.waves_per_cu > 32)) ||
-        l.chunk < 0 || l.split_ways < 0 || l.split_vertices < 0)
+        l.chunk < 0 || l.split_ways < 0 || l.split_vertices < 0 || l.xcd_tasks < -1)
         return GP_ERR_ARG;
     gp_plan* q = new (std::nothrow) gp_plan(*p);
     if (!q) return GP_ERR_NOMEM;

@@ -125,6 +125,14 @@ int resident_waves_per_cu(const DeviceGraph& g, const GpPlanDesc& d, const Launc
     return std::min(cfg.waves_per_cu, nb * (kBlock / 64));
 }
 
+int64_t xcd_block_tasks(const DeviceGraph& g, const LaunchCfg& cfg, int group) {
+    (void)g;
+    (void)group;
+    if (cfg.xcd <= 0) return 0;  // the default: one cursor (measured faster)
+    const int64_t chunk = std::max(1, cfg.chunk);
+    return (cfg.xcd + chunk - 1) / chunk * chunk;
+}
+
 LaunchCfg apply_launch(LaunchCfg cfg, const gp_launch* l) {
     if (l) {
         if (l->group) cfg.group = l->group;
@@ -136,6 +144,7 @@ LaunchCfg apply_launch(LaunchCfg cfg, const gp_launch* l) {
         if (l->split_ways) cfg.split_ways = l->split_ways;
         if (l->split_vertices) cfg.split_vertices = l->split_vertices;
         if (l->lds_buffers) cfg.lds = l->lds_buffers > 0 ? 1 : 0;
+        if (l->xcd_tasks) cfg.xcd = l->xcd_tasks;
     }
     return cfg;
 }
@@ -261,7 +270,7 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
         if (scratch_bytes) scratch = (int32_t*)(base + kAlign);
         if (use_memo) memo = (unsigned long long*)(base + kAlign + align_up(scratch_bytes));
     } else {
-        GP_HIP_TRY(hipMallocAsync((void**)&queue, sizeof(unsigned long long) * 2, stream));
+        GP_HIP_TRY(hipMallocAsync((void**)&queue, sizeof(unsigned long long) * kQueueWords, stream));
         if (scratch_bytes) {
             if (hipMallocAsync((void**)&scratch, scratch_bytes, stream) != hipSuccess) {
                 (void)hipFreeAsync(queue, stream);
@@ -279,7 +288,7 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
     if (use_memo)
         hipLaunchKernelGGL(zero_u64, dim3((unsigned)std::min<int64_t>(4096, (memo_words + 255) / 256)), dim3(256), 0,
                            stream, memo, memo_words);
-    hipLaunchKernelGGL(init_counters, dim3(1), dim3(64), 0, stream, queue, 2);
+    hipLaunchKernelGGL(init_counters, dim3(1), dim3(64), 0, stream, queue, kQueueWords);
     hipLaunchKernelGGL(init_counters, dim3(1), dim3(64), 0, stream, result_dev, account ? 3 : 2);
     if (busy) hipLaunchKernelGGL(init_counters, dim3(1), dim3(64), 0, stream, busy, 3);
 
@@ -306,6 +315,7 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
     a.memo = memo;
     a.chunk = cfg.chunk;
     a.lds_bufs = lds_bytes > 0 ? 1 : 0;
+    a.xcd_block = xcd_block_tasks(g, cfg, group);
     if (n_tasks > 0)
         hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kBlock), (uint32_t)lds_bytes, stream, d, a);
     // a sample's total need not be a multiple of the over-count: its quotient

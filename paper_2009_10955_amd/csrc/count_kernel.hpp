@@ -81,7 +81,9 @@ struct CountArgs {
     int32_t n_hubs;
     int32_t* scratch;
     int64_t buf_cap;
-    unsigned long long* queue;     // {task cursor, high word of the 128-bit total}
+    // {task cursor, high word of the 128-bit total, then with xcd_block > 0
+    // one task cursor per XCD}
+    unsigned long long* queue;
     unsigned long long* result;    // {count (low word), flags, bytes}
     unsigned long long* per_root;  // optional, indexed by CSR entry of (v0, v1)
     // optional {sum over wavefronts of active clock ticks, wavefronts, longest
@@ -95,6 +97,11 @@ struct CountArgs {
     unsigned long long* memo;
     int32_t chunk;
     int32_t lds_bufs;  // 1: the candidate buffers are in the block's dynamic LDS, not scratch
+    // > 0: the task space is dealt to the XCDs in blocks of xcd_block tasks
+    // (a multiple of chunk): block b goes to XCD b mod kXcds, each XCD takes
+    // its blocks in order from its own cursor and then helps the others; 0:
+    // one cursor for the device
+    int64_t xcd_block;
 };
 
 typedef void (*KernelFn)(GpPlanDesc, CountArgs);
@@ -1059,6 +1066,59 @@ __device__ __forceinline__ void run_tasks(const GpPlanDesc& d, Ctx<G>& c, const 
 // groups 6, others 5); k >= 7 keeps the compiler's choice. IEP over 3 or 4
 // inner levels keeps 7 or 15 set sizes and their 128-bit products live: 5
 // and 4 wavefronts.
+// XCDs of the device; workgroups are dealt to them round robin in launch
+// order, so block b of a grid runs on XCD b mod kXcds.
+constexpr int kXcds = 8;
+// Words of a launch's queue: cursor, high count word, one cursor per XCD.
+constexpr int kQueueWords = 2 + kXcds;
+
+// Tasks of XCD x when n tasks are dealt in blocks of B tasks, block b to
+// XCD b mod kXcds.
+__device__ __forceinline__ int64_t xcd_tasks(int64_t n, int64_t B, int x) {
+    const int64_t round = (int64_t)kXcds * B;
+    const int64_t full = n / round, rem = n - full * round;
+    return full * B + min(max(rem - (int64_t)x * B, (int64_t)0), B);
+}
+
+// Global task of XCD x's j-th task.
+__device__ __forceinline__ int64_t xcd_task(int64_t j, int64_t B, int x) {
+    const int64_t b = j / B;
+    return (b * kXcds + x) * B + (j - b * B);
+}
+
+// Next grab of a group: `chunk` tasks [*t0, *t1) from one cursor, or false
+// once every cursor is exhausted. With XCD blocks the group starts at its
+// own XCD's cursor (*q = 0) and moves on to the next XCD's when it runs dry;
+// it never comes back to one that was dry.
+template <int G>
+__device__ __forceinline__ bool grab_tasks(const Group<G>& grp, unsigned long long* queue, int64_t n_tasks,
+                                           int64_t chunk, int64_t xcd_block, int* q, int64_t* t0, int64_t* t1) {
+    if (xcd_block <= 0) {
+        unsigned long long v = 0;
+        if (grp.gl == 0) v = atomicAdd(queue, (unsigned long long)chunk);
+        const int64_t a = uni64<G>((int64_t)grp.bcast(v, 0));
+        if (a >= n_tasks) return false;
+        *t0 = a;
+        *t1 = min(a + chunk, n_tasks);
+        return true;
+    }
+    const int home = (int)(blockIdx.x % kXcds);
+    while (*q < kXcds) {
+        const int x = (home + *q) % kXcds;
+        const int64_t nx = xcd_tasks(n_tasks, xcd_block, x);
+        unsigned long long v = 0;
+        if (grp.gl == 0) v = atomicAdd(&queue[2 + x], (unsigned long long)chunk);
+        const int64_t j = uni64<G>((int64_t)grp.bcast(v, 0));
+        if (j < nx) {
+            *t0 = xcd_task(j, xcd_block, x);
+            *t1 = *t0 + min(chunk, nx - j);
+            return true;
+        }
+        ++*q;
+    }
+    return false;
+}
+
 constexpr int occupancy_target(int K, int G, int LEAF, int IEP = 0) {
     return IEP >= 3 ? (IEP == 3 ? 5 : 4)
            : K > 6  ? 1
@@ -1103,14 +1163,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(occupanc
     uint64_t acc = 0, carry = 0;
     const int64_t chunk = a.chunk;
 
+    int q = 0;
     for (;;) {
-        unsigned long long t0 = 0;
-        if (c.g.gl == 0) t0 = atomicAdd(a.queue, (unsigned long long)chunk);
-        t0 = (unsigned long long)uni64<G>((int64_t)c.g.bcast(t0, 0));
-        if ((int64_t)t0 >= a.n_tasks) break;
-        const int64_t t1 = min((int64_t)t0 + chunk, a.n_tasks);
+        int64_t t0 = 0, t1 = 0;
+        if (!grab_tasks<G>(c.g, a.queue, a.n_tasks, chunk, a.xcd_block, &q, &t0, &t1)) break;
         const uint64_t t_chunk = a.busy ? wall_clock64() : 0;
-        run_tasks<K, G, LEAF, MODE, IEP>(d, c, ts, (int64_t)t0, t1, acc, carry, a.per_root);
+        run_tasks<K, G, LEAF, MODE, IEP>(d, c, ts, t0, t1, acc, carry, a.per_root);
         if (a.busy) {
             const uint64_t now = wall_clock64();
             chunk_max = max(chunk_max, now - t_chunk);

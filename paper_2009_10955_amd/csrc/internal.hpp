@@ -47,7 +47,14 @@ struct LaunchCfg {
     int64_t split_vertices = 0;
     double budget_ms = 0;  // time limit per wavefront (measurement only; 0: none)
     int lds = 0;           // 1: candidate buffers in LDS when a block's fit kLdsBufferBytes
+    // tasks per XCD block (the task space dealt to the XCDs in blocks); 0 or
+    // -1: one cursor for the device
+    int64_t xcd = 0;
 };
+
+// Tasks per XCD block of a launch: cfg.xcd rounded up to a multiple of the
+// grab, or 0 for one cursor (the default).
+int64_t xcd_block_tasks(const DeviceGraph& g, const LaunchCfg& cfg, int group);
 
 // Largest LDS a block's candidate buffers may take (dynamic shared memory).
 constexpr int64_t kLdsBufferBytes = 64 << 10;

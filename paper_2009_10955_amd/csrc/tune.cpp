@@ -507,25 +507,45 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
                 timed_full = true;
             }
         }
-        // 5b. finalists too slow to time in full: the two best distinct
-        //     configurations once more on a dense sample (about half the
-        //     budget each). A sparse sample runs with less contention than a
-        //     full run and underestimates it, not by the same factor for
-        //     every configuration; the choice is then between these two.
-        if (st == GP_OK && !timed_full && stride > 1 && picks.size() > 1 && spent < 3.0 * budget_ms) {
+        // 5b. finalists too slow to time in full: the best one, the runner-up
+        //     configuration (if within 2x) and the best one's other counting
+        //     mode (plain vs inclusion-exclusion, same schedule and set) once
+        //     more on a dense sample of about a quarter of the budget each.
+        //     On skewed graphs a sparse sample holds few of the roots that
+        //     carry the work and runs with less contention than a full run,
+        //     and it misjudges configurations by different factors; IEP and
+        //     plain counting differ most in how they treat those roots.
+        if (st == GP_OK && !timed_full && stride > 1 && !picks.empty() && spent < 4.0 * budget_ms) {
             std::stable_sort(picks.begin(), picks.end(), [](const Pick& a, const Pick& b) { return a.est < b.est; });
-            std::vector<Pick> two;
-            for (const Pick& pk : picks) {
-                bool dup = false;
-                for (const Pick& q : two) dup |= q.c == pk.c;
-                if (!dup && pk.est < inf) two.push_back(pk);
-                if (two.size() == 2) break;
+            std::vector<Pick> dense;
+            if (picks[0].est < inf) dense.push_back(picks[0]);
+            for (const Pick& pk : picks)
+                if (!dense.empty() && pk.c != dense[0].c && pk.est < 2.0 * dense[0].est) {
+                    dense.push_back(pk);
+                    break;
+                }
+            if (try_iep && !dense.empty()) {
+                const Cfg& w = cands[dense[0].c];
+                size_t other = cands.size();
+                for (size_t c = 0; c < cands.size(); ++c)
+                    if (cands[c].order == w.order && cands[c].rel == w.rel && (cands[c].desc.iep > 0) != (w.desc.iep > 0) &&
+                        (other == cands.size() || cands[c].desc.iep > cands[other].desc.iep))
+                        other = c;
+                if (other < cands.size()) {
+                    gpint::LaunchCfg cfg = dense[0].launch;
+                    if (cands[other].desc.iep) {
+                        cfg.group = cfg.group >= 64 ? 64 : 32;
+                        cfg.leaf = 1;
+                    }
+                    dense.push_back(Pick{inf, other, cfg});
+                }
             }
-            const int64_t sd = two.empty() ? 0 : std::max<int64_t>(1, (int64_t)std::ceil(two[0].est / (0.5 * budget_ms)));
-            if (two.size() == 2 && two[1].est < 2.0 * two[0].est && sd < stride / 4) {
+            const int64_t sd =
+                dense.empty() ? 0 : std::max<int64_t>(1, (int64_t)std::ceil(dense[0].est / (0.25 * budget_ms)));
+            if (dense.size() > 1 && sd < stride / 4) {
                 best_est = inf;
                 bool ok = true;
-                for (Pick& pk : two) {
+                for (Pick& pk : dense) {
                     const double t = measure(cands[pk.c].desc, pk.launch, sd, "dense", pk.c);
                     if (t < 0) {
                         ok = false;
@@ -533,7 +553,7 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
                     }
                     pk.est = t;
                 }
-                if (ok) picks = two;
+                if (ok) picks = dense;
             }
         }
         size_t best = fine.empty() ? 0 : fine[0].second;

@@ -45,10 +45,29 @@ def _rows(path_glob: str):
             yield from csv.DictReader(f)
 
 
+def _db_rows(path_glob: str, counter: str):
+    """(dispatch id, kernel name, value) rows of one counter from rocprofv3's
+    SQLite output (its counters_collection view)."""
+    import sqlite3
+    for path in sorted(glob.glob(path_glob, recursive=True)):
+        con = sqlite3.connect(f"file:{path}?mode=ro", uri=True)
+        try:
+            yield from con.execute("SELECT dispatch_id, kernel_name, value FROM counters_collection "
+                                   "WHERE counter_name = ?", (counter,))
+        finally:
+            con.close()
+
+
 def counter_per_dispatch(path_glob: str, counter: str) -> list:
     """[(dispatch id, kernel name, value)] for one counter from rocprofv3
-    counter_collection CSV files (values summed over the counter's instances)."""
+    counter_collection CSV files or its SQLite databases (*.db), values
+    summed over the counter's instances."""
     acc: dict = {}
+    if path_glob.endswith(".db"):
+        for did, kern, val in _db_rows(path_glob, counter):
+            key = (int(did), kern)
+            acc[key] = acc.get(key, 0.0) + float(val)
+        return [(d, k, v) for (d, k), v in sorted(acc.items())]
     for r in _rows(path_glob):
         name = r.get("Counter_Name") or r.get("counter_name")
         if name != counter:

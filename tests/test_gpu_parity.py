@@ -667,6 +667,27 @@ def test_batch_per_plan_shapes_equal_oracle(hubs):
     b.close()
 
 
+@pytest.mark.parametrize("pname", ["triangle", "4-clique", "house", "5-cycle"])
+def test_xcd_task_blocks_equal_oracle(pname):
+    """Tasks dealt to the XCDs in blocks (any block size, rounded up to the
+    grab; ragged last round; XCDs that run dry help the others) count every
+    task once: plain, sampled, split, per root and with byte accounting."""
+    g = I.er(400, 0.04, seed=17)
+    graph = gp.Graph.from_csr(g, device=True)
+    k, e = P[pname]
+    want = O.count(g, k, e)
+    plan = gp.Plan(k, e, stats=graph.stats())
+    for xt in (1, 7, 64, 500, 1 << 20):
+        for grp, chunk in ((64, 4), (16, 3), (8, 1)):
+            assert gp.count(graph, plan, group=grp, chunk=chunk, xcd_tasks=xt) == want, (xt, grp, chunk)
+        assert sum(gp.count(graph, plan, xcd_tasks=xt, root_stride=5, root_offset=r) for r in range(5)) == want
+        assert gp.count(graph, plan, xcd_tasks=xt, split_ways=7, split_vertices=1 << 20) == want
+    total, per = gp.count_per_root(graph, plan, xcd_tasks=64)
+    assert total == want and int(per.cpu().numpy().sum()) == want * (plan.info().iep_div or 1)
+    c, b = gp.count_traffic(graph, plan, xcd_tasks=64)
+    assert c == want and b == gp.count_traffic(graph, plan, xcd_tasks=-1)[1]
+
+
 @pytest.mark.parametrize("pname", ["4-clique", "house", "5-clique", "6-cycle-chord", "prism", "5-wheel"])
 def test_lds_buffers_equal_oracle(pname):
     """Candidate buffers in the block's LDS (graphs whose second-largest

@@ -90,7 +90,7 @@ typedef struct {
  * On the device the graph is validated (GP_ERR_CSR_* on failure), relabelled
  * by descending degree (ties by ascending id), each list re-sorted, and its
  * triangle count computed for the cost model. The highest-degree vertices
- * (degree >= 64, at most 2 GiB in total) also get a dense n-bit neighbor
+ * (degree >= 64, at most 8 GiB in total) also get a dense n-bit neighbor
  * bitmap, so that a membership test in their lists is one bit read. Blocking
  * on `stream`.
  */
@@ -103,7 +103,7 @@ typedef struct {
     int64_t hub_min_degree;    /* vertices of at least this degree get a dense neighbor bitmap
                                   (0 = 64) */
     int64_t hub_budget_bytes;  /* bitmaps of at most this many bytes in total, highest degrees
-                                  first (0 = 2 GiB); each takes ceil(n/32) * 4 bytes */
+                                  first (0 = 8 GiB); each takes ceil(n/32) * 4 bytes */
 } gp_load_opts;
 
 void gp_load_opts_default(gp_load_opts* o);

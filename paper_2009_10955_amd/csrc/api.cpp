@@ -206,7 +206,7 @@ gp_status gp_load_graph_opts(const int64_t* row_ptr, const int32_t* col, int64_t
     if (st == GP_OK && !(flags & GP_NO_HUB_BITMAPS)) {
         const int64_t min_deg =
             (flags & GP_DENSE_HUB_BITMAPS) ? 1 : (opts->hub_min_degree > 0 ? opts->hub_min_degree : 64);
-        const int64_t budget = opts->hub_budget_bytes > 0 ? opts->hub_budget_bytes : (int64_t(2) << 30);
+        const int64_t budget = opts->hub_budget_bytes > 0 ? opts->hub_budget_bytes : (int64_t(8) << 30);
         st = gpint::build_hub_bitmaps(&g->dg, min_deg, budget, s);
     }
     if (own_row || own_col) {

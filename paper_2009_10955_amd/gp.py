@@ -208,7 +208,7 @@ class Graph:
     def __init__(self, row_ptr, col, stream=None, hub_bitmaps: str = "auto", hub_min_degree: int = 0,
                  hub_budget_bytes: int = 0):
         """hub_bitmaps: "auto" (degree >= hub_min_degree, default 64, within
-        hub_budget_bytes, default 2 GiB), "none", or "dense" (every vertex)."""
+        hub_budget_bytes, default 8 GiB), "none", or "dense" (every vertex)."""
         lib = _lib()
         extra = {"auto": 0, "none": GP_NO_HUB_BITMAPS, "dense": GP_DENSE_HUB_BITMAPS}[hub_bitmaps]
         o = LoadOpts()

@@ -38,7 +38,17 @@ def test_connected_pattern_classes():
             best = min(tuple(sorted(tuple(sorted((p[a], p[b]))) for a, b in e))
                        for p in itertools.permutations(range(k)))
             forms.add(best)
-            assert O.phase1_ok(list(range(k)), O._adj(k, e)) or True
+            # connected: a search from vertex 0 reaches every vertex
+            seen, todo = {0}, [0]
+            while todo:
+                u = todo.pop()
+                for a, b in e:
+                    for x, y in ((a, b), (b, a)):
+                        if x == u and y not in seen:
+                            seen.add(y)
+                            todo.append(y)
+            assert seen == set(range(k)), e
+            assert len(es) == len(e)
         assert len(forms) == len(group)
 
 

@@ -836,6 +836,53 @@ __device__ bool coop_bits_leaf(const GpPlanDesc& d, const Ctx<G>& c, const int32
 // different candidates when no build runs after level L is bound; otherwise
 // the group binds one candidate at a time, runs the builds and computes the
 // value together.
+// A lane's walk for the IEP value of its own binding: the longest of its
+// unbuilt inner sets' shorter operands (the single-set counts walk them; the
+// intersections walk no more). Lanes whose walk exceeds kIepLaneWork leave
+// their binding to the whole group (iep_group_pass), so one hub binding does
+// not hold a wavefront's other lanes idle for thousands of steps.
+constexpr int32_t kIepLaneWork = 128;
+
+template <int K, int N, int G>
+__device__ __forceinline__ int64_t iep_lane_work_g(const GpPlanDesc& d, const Ctx<G>& c, const int32_t (&w)[K]) {
+    constexpr int F = K - N;
+    int64_t work = 0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const GpLevel& lv = d.lv[F + j];
+        if (lv.last_list < 0) continue;
+        const int32_t a = pick<K>(w, lv.last_list);
+        const int64_t na = c.row_ptr[a + 1] - c.row_ptr[a];
+        int64_t np;
+        if (lv.pre_buf >= 0) {
+            np = c.lens[lv.pre_buf];
+        } else {
+            const int32_t b = pick<K>(w, lv.pre_list);
+            np = c.row_ptr[b + 1] - c.row_ptr[b];
+        }
+        work = max(work, min(na, np));
+    }
+    return work;
+}
+
+// The bindings of the lanes flagged in `m` (a group ballot; x is each lane's
+// level-L vertex), one at a time, each by the whole group.
+template <int K, int L, int G, int MODE>
+__device__ __forceinline__ void iep_group_pass(const GpPlanDesc& d, const Ctx<G>& c, const int32_t (&v)[K],
+                                               uint64_t m, int32_t x, uint64_t& acc, uint64_t& carry) {
+    constexpr int N = K - 1 - L;
+    while (m) {
+        const int src = __builtin_ctzll(m);
+        m &= m - 1;
+        int32_t w[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) w[j] = v[j];
+        w[L] = uni<G>(c.g.bcast(x, src));
+        const unsigned __int128 val = iep_value<K, G, MODE, N, true>(d, c, w);
+        if (c.g.gl == 0) add_count128(acc, carry, (uint64_t)val, (uint64_t)(val >> 64));
+    }
+}
+
 template <int K, int L, int G, int MODE>
 __device__ void iep_level(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K], Set S, int32_t st,
                           uint32_t inj_l, uint64_t& acc, uint64_t& carry) {
@@ -844,17 +891,24 @@ __device__ void iep_level(const GpPlanDesc& d, const Ctx<G>& c, int32_t (&v)[K],
         for (int32_t base = 0; base < S.n; base += G) {
             if (c.expired()) break;
             const int32_t i = base + c.g.gl;
+            int32_t x = 0;
+            bool longw = false;
             if (i < S.n) {
-                const int32_t x = S.p[(int64_t)i * st];
+                x = S.p[(int64_t)i * st];
                 if (!inj_hit<K>(inj_l, v, x)) {
                     int32_t w[K];
 #pragma unroll
                     for (int j = 0; j < K; ++j) w[j] = v[j];
                     w[L] = x;
-                    const unsigned __int128 val = iep_value<K, G, MODE, N, false>(d, c, w);
-                    add_count128(acc, carry, (uint64_t)val, (uint64_t)(val >> 64));
+                    if (iep_lane_work_g<K, N, G>(d, c, w) > kIepLaneWork) {
+                        longw = true;
+                    } else {
+                        const unsigned __int128 val = iep_value<K, G, MODE, N, false>(d, c, w);
+                        add_count128(acc, carry, (uint64_t)val, (uint64_t)(val >> 64));
+                    }
                 }
             }
+            iep_group_pass<K, L, G, MODE>(d, c, v, c.g.ballot(longw), x, acc, carry);
         }
     } else {
         for (int32_t t = 0; t < S.n; ++t) {
@@ -970,18 +1024,41 @@ __device__ __forceinline__ void run_tasks(const GpPlanDesc& d, Ctx<G>& c, const 
             if (d.build_begin[1] == d.build_end[1]) {
                 for (int64_t base = t0; base < t1; base += G) {
                     const int64_t r = base + c.g.gl;
+                    int2 e = make_int2(0, 0);
+                    bool longw = false;
                     if (r < t1) {
-                        const int2 e = ts.roots[ts.offset + r * ts.stride];
+                        e = ts.roots[ts.offset + r * ts.stride];
                         if constexpr (MODE == MODE_ACCOUNT) *c.bytes += 8;
                         int32_t w[K];
 #pragma unroll
                         for (int j = 0; j < K; ++j) w[j] = 0;
                         w[0] = e.x;
                         w[1] = e.y;
-                        const unsigned __int128 val = iep_value<K, G, MODE, K - 2, false>(d, c, w);
-                        add_count128(acc, carry, (uint64_t)val, (uint64_t)(val >> 64));
-                        if constexpr (PER_ROOT)
-                            per_root[entry_index(c.row_ptr, c.col, e.x, e.y)] = (unsigned long long)val;
+                        if (iep_lane_work_g<K, K - 2, G>(d, c, w) > kIepLaneWork) {
+                            longw = true;
+                        } else {
+                            const unsigned __int128 val = iep_value<K, G, MODE, K - 2, false>(d, c, w);
+                            add_count128(acc, carry, (uint64_t)val, (uint64_t)(val >> 64));
+                            if constexpr (PER_ROOT)
+                                per_root[entry_index(c.row_ptr, c.col, e.x, e.y)] = (unsigned long long)val;
+                        }
+                    }
+                    // roots with long inner walks: the whole group, one at a time
+                    uint64_t m = c.g.ballot(longw);
+                    while (m) {
+                        const int src = __builtin_ctzll(m);
+                        m &= m - 1;
+                        int32_t w[K];
+#pragma unroll
+                        for (int j = 0; j < K; ++j) w[j] = 0;
+                        w[0] = uni<G>(c.g.bcast(e.x, src));
+                        w[1] = uni<G>(c.g.bcast(e.y, src));
+                        const unsigned __int128 val = iep_value<K, G, MODE, K - 2, true>(d, c, w);
+                        if (c.g.gl == 0) {
+                            add_count128(acc, carry, (uint64_t)val, (uint64_t)(val >> 64));
+                            if constexpr (PER_ROOT)
+                                per_root[entry_index(c.row_ptr, c.col, w[0], w[1])] = (unsigned long long)val;
+                        }
                     }
                 }
             } else {

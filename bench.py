@@ -855,7 +855,8 @@ def sliced_main(args, cfg_idx, names, desc):
         src = None
         cur = {n: {"order": list(p.order), "restrictions": [list(x) for x in p.restrictions],
                    "launch": l, "iep": bool(p.info().iep)} for n, p, l in zip(names, plans, launches)}
-        if (tr is not None and tr.get("workload") == args.workload and tr.get("kernel_match") == "batch_kernel"
+        if (tr is not None and tr.get("workload") == args.workload
+                and tr.get("kernel_match") in ("batch_kernel", "count_kernel")
                 and isinstance(tr.get("plan"), dict) and sorted(tr["plan"]) == sorted(cur)
                 and all(profiling.same_plan(tr["plan"][n], cur[n]) for n in cur)):
             traffic = tr["hbm_bytes_per_launch"]
@@ -867,7 +868,8 @@ def sliced_main(args, cfg_idx, names, desc):
                     "traffic_source": src,
                     "dram_GBps": round(traffic / (avg_ms / 1e3) / 1e9, 2) if traffic else None,
                     "l2_hit_rate": round(l2["hit_rate"], 5) if l2 else None,
-                    "kernel": "batch_kernel (every feasible pattern; one launch per plan shape per step)",
+                    "kernel": "the batched step's launches (one per plan shape; a shape with one plan "
+                              "runs count_kernel, several share batch_kernel)",
                     "alg_bytes_per_launch": alg / nt, "alg_bytes_slices": nt,
                     "avg_launch_ms": round(sum(launch_ms[:nt]) / nt, 3),
                     "avg_launch_ms_all_steps": round(sum(launch_ms) / len(launch_ms), 3)}

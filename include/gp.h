@@ -150,10 +150,6 @@ typedef struct {
     int32_t split_vertices;/* heavy roots: those whose smaller endpoint in the degree-sorted
                               layout is below split_vertices, rounded down to a power of
                               two (0 = auto) */
-    int32_t lds_buffers;   /* 1: the candidate buffers (intersection results) of a block's
-                              groups live in its LDS when they fit 64 KiB (graphs whose
-                              second-largest degree is small), -1: always in HBM scratch,
-                              0: the plan's own (HBM unless tuned otherwise) */
     int32_t xcd_tasks;     /* task order over the XCDs, each with its own L2 (0 = the
                               plan's own, one cursor unless set): > 0 deals the task space
                               to the 8 XCDs in blocks of this many tasks (rounded up to a
@@ -261,8 +257,8 @@ typedef struct {
                                k >= 4 when the winner was timed in full, the ways heavy
                                roots are split (16, 4 or 1), the tasks taken per queue grab
                                (1, 2, 4, 8 or 16), the heavy-root threshold (64, 256, 1024
-                               or 4096), candidate buffers in LDS (where they fit) and 16 or
-                               24 resident wavefronts per CU; -1: keep the defaults */
+                               or 4096) and 16 or 24 resident wavefronts per CU; -1: keep
+                               the defaults */
     double budget_seconds;  /* GPU time for timing sampled configurations (0 = 20 s); the
                                launch-shape, full-run and queue-grab stages that follow may
                                bring the total to at most about 4 times this */

@@ -21,7 +21,8 @@ LIB = os.path.join(PKG, "libgp.so")
 SOURCES = [("api.cpp", [], "api.o"), ("planner.cpp", [], "planner.o"), ("tune.cpp", [], "tune.o"), ("server.cpp", [], "server.o"),
            ("graph.hip", [], "graph.o"), ("count.hip", [], "count.o"), ("list.hip", [], "list.o")] + [
     ("count_inst.hip", [f"-DGP_INST_K={k}"], f"count_k{k}.o") for k in range(2, 9)] + [
-    ("count_batch.hip", [f"-DGP_BATCH_KMAX={k}"], f"count_batch_k{k}.o") for k in (5, 6, 8)]
+    ("count_batch.hip", [f"-DGP_BATCH_KMIN={a}", f"-DGP_BATCH_KMAX={b}"], f"count_batch_k{a}_{b}.o")
+    for a, b in ((2, 2), (3, 3), (4, 4), (5, 5), (6, 6), (7, 8))]
 ARCH = os.environ.get("GP_OFFLOAD_ARCH", "gfx950")
 
 

@@ -491,7 +491,6 @@ gp_status gp_plan_get(const gp_plan* p, gp_plan_info* out) {
     out->launch.root_offset = 0;
     out->launch.split_ways = p->launch.split_ways;
     out->launch.split_vertices = (int32_t)std::min<int64_t>(p->launch.split_vertices, INT32_MAX);
-    out->launch.lds_buffers = p->launch.lds > 0 ? 1 : -1;
     out->launch.xcd_tasks = (int32_t)std::max<int64_t>(-1, std::min<int64_t>(p->launch.xcd, INT32_MAX));
     return GP_OK;
 }
@@ -720,6 +719,25 @@ gp_status gp_count_batch(const gp_graph* g, const gp_plan* const* plans, int32_t
     return batch_counts(descs, cfgs, slot, h.data(), out);
 }
 
+namespace {
+// Capture the batch's work into its hipGraph (replacing an earlier one):
+// counter and memo reset (fill kernels, no memset nodes) -> the runs' launches
+// -> D2H of the result words.
+bool capture_batch(gp_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+    gp_status est = gpint::batch_enqueue(b->g->dg, b->st, b->cap_stream);
+    hipError_t ce = hipMemcpyAsync(b->host_res, b->st.result, 4 * sizeof(unsigned long long) * b->np,
+                                   hipMemcpyDeviceToHost, b->cap_stream);
+    hipError_t ee = hipStreamEndCapture(b->cap_stream, &b->graph);
+    return est == GP_OK && ce == hipSuccess && ee == hipSuccess &&
+           hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) == hipSuccess;
+}
+}  // namespace
+
 gp_status gp_batch_create(const gp_graph* g, const gp_plan* const* plans, int32_t np,
                           const gp_launch* launch, void* stream, gp_batch** out) {
     if (!g || !out) return GP_ERR_ARG;
@@ -745,19 +763,8 @@ gp_status gp_batch_create(const gp_graph* g, const gp_plan* const* plans, int32_
     }
     bool ok = hipHostMalloc((void**)&b->host_res, 4 * sizeof(unsigned long long) * np,
                             hipHostMallocDefault) == hipSuccess &&
-              hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) == hipSuccess;
-    if (ok) {
-        // capture: counter and memo reset (fill kernels, no memset nodes) -> kernel -> D2H
-        ok = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
-        if (ok) {
-            gp_status est = gpint::batch_enqueue(g->dg, b->st, b->cap_stream);
-            hipError_t ce = hipMemcpyAsync(b->host_res, b->st.result, 4 * sizeof(unsigned long long) * np,
-                                           hipMemcpyDeviceToHost, b->cap_stream);
-            hipError_t ee = hipStreamEndCapture(b->cap_stream, &b->graph);
-            ok = est == GP_OK && ce == hipSuccess && ee == hipSuccess &&
-                 hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) == hipSuccess;
-        }
-    }
+              hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) == hipSuccess &&
+              capture_batch(b);
     if (!ok) {
         gp_free_batch(b);
         return GP_ERR_HIP;
@@ -787,7 +794,10 @@ gp_status gp_batch_set_sample(gp_batch* b, int64_t root_stride, int64_t root_off
         c.root_offset = root_offset;
     }
     gp_status st = gpint::batch_update(b->g->dg, &b->st, b->descs.data(), cfgs.data(), s);
-    if (st == GP_OK) b->cfgs = cfgs;
+    if (st == GP_OK) {
+        b->cfgs = cfgs;
+        if (!capture_batch(b)) st = GP_ERR_HIP;
+    }
     return st;
 }
 

@@ -16,14 +16,27 @@ KernelFn pick_kernel_k5(int group, int leaf, int mode, int iep);
 KernelFn pick_kernel_k6(int group, int leaf, int mode, int iep);
 KernelFn pick_kernel_k7(int group, int leaf, int mode, int iep);
 KernelFn pick_kernel_k8(int group, int leaf, int mode, int iep);
-BatchFn batch_kernel_k5(int group, int leaf, int iep);
-BatchFn batch_kernel_k6(int group, int leaf, int iep);
-BatchFn batch_kernel_k8(int group, int leaf, int iep);
+BatchFn batch_kernel_k2_2(int group, int leaf, int iep);
+BatchFn batch_kernel_k3_3(int group, int leaf, int iep);
+BatchFn batch_kernel_k4_4(int group, int leaf, int iep);
+BatchFn batch_kernel_k5_5(int group, int leaf, int iep);
+BatchFn batch_kernel_k6_6(int group, int leaf, int iep);
+BatchFn batch_kernel_k7_8(int group, int leaf, int iep);
 
-BatchFn pick_batch_kernel(int kmax, int group, int leaf, int iep) {
-    if (kmax <= 5) return batch_kernel_k5(group, leaf, iep);
-    if (kmax <= 6) return batch_kernel_k6(group, leaf, iep);
-    if (kmax <= 8) return batch_kernel_k8(group, leaf, iep);
+// The batched kernel of a run whose plans have k in [kmin, kmax]: one pattern
+// size up to 6, or sizes 7 and 8.
+BatchFn pick_batch_kernel(int kmin, int kmax, int group, int leaf, int iep) {
+    if (kmin == kmax) {
+        switch (kmin) {
+            case 2: return batch_kernel_k2_2(group, leaf, iep);
+            case 3: return batch_kernel_k3_3(group, leaf, iep);
+            case 4: return batch_kernel_k4_4(group, leaf, iep);
+            case 5: return batch_kernel_k5_5(group, leaf, iep);
+            case 6: return batch_kernel_k6_6(group, leaf, iep);
+            default: break;
+        }
+    }
+    if (kmin >= 7 && kmax <= 8) return batch_kernel_k7_8(group, leaf, iep);
     return nullptr;
 }
 
@@ -31,6 +44,11 @@ namespace {
 __global__ void init_counters(unsigned long long* p, int n) {
     int i = threadIdx.x;
     if (i < n) p[i] = 0;
+}
+
+// A solo batch run's high count word into its plan's result words.
+__global__ void move_high_word(const unsigned long long* from, unsigned long long* to) {
+    if (threadIdx.x == 0) *to = *from;
 }
 
 KernelFn pick_kernel(int k, int group, int leaf, int mode, int iep) {
@@ -106,21 +124,13 @@ LaunchCfg default_launch(const GpPlanDesc& d) {
     return cfg;
 }
 
-int64_t lds_buffer_bytes(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCfg& cfg) {
-    if (cfg.lds <= 0 || d.nbuf <= 0) return 0;
-    const int group = d.iep ? (cfg.group >= 64 ? 64 : 32) : cfg.group;
-    const int64_t bytes = (int64_t)(kBlock / group) * d.nbuf * std::max<int64_t>(1, g.deg2) * 4;
-    return bytes <= kLdsBufferBytes ? bytes : 0;
-}
-
 int resident_waves_per_cu(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCfg& cfg) {
     const bool iep = d.iep != 0;
     const int group = iep ? (cfg.group >= 64 ? 64 : 32) : cfg.group;
     KernelFn fn = pick_kernel(d.k, group, cfg.leaf, MODE_PLAIN, d.iep);
+    (void)g;
     int nb = 0;
-    const int64_t lds = lds_buffer_bytes(g, d, cfg);
-    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)fn, kBlock, (size_t)lds) != hipSuccess ||
-        nb <= 0)
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)fn, kBlock, 0) != hipSuccess || nb <= 0)
         return cfg.waves_per_cu;
     return std::min(cfg.waves_per_cu, nb * (kBlock / 64));
 }
@@ -143,7 +153,6 @@ LaunchCfg apply_launch(LaunchCfg cfg, const gp_launch* l) {
         cfg.root_offset = l->root_offset;
         if (l->split_ways) cfg.split_ways = l->split_ways;
         if (l->split_vertices) cfg.split_vertices = l->split_vertices;
-        if (l->lds_buffers) cfg.lds = l->lds_buffers > 0 ? 1 : 0;
         if (l->xcd_tasks) cfg.xcd = l->xcd_tasks;
     }
     return cfg;
@@ -244,16 +253,7 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
     int64_t need_blocks = std::max<int64_t>(1, (need + groups_per_block - 1) / groups_per_block);
     blocks = std::min(blocks, need_blocks);
 
-    // candidate buffers in LDS when the block's fit (then no scratch)
-    const int64_t lds_bytes = lds_buffer_bytes(g, d, cfg);
-    if (lds_bytes > 0) {
-        int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)fn, kBlock, (size_t)lds_bytes) ==
-                hipSuccess &&
-            nb > 0)
-            blocks = std::min<int64_t>(blocks, std::max<int64_t>(1, (int64_t)g.num_cus * nb));
-    }
-    const size_t scratch_bytes = lds_bytes > 0 ? 0 : (size_t)(blocks * per_block);
+    const size_t scratch_bytes = (size_t)(blocks * per_block);
     // leaf mode 4's per-task memo: one word per hub per group, within 4 GiB
     // (within what the workspace has left)
     const int64_t memo_words = blocks * groups_per_block * (int64_t)g.n_hubs;
@@ -314,10 +314,9 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
     a.busy = busy;
     a.memo = memo;
     a.chunk = cfg.chunk;
-    a.lds_bufs = lds_bytes > 0 ? 1 : 0;
     a.xcd_block = xcd_block_tasks(g, cfg, group);
     if (n_tasks > 0)
-        hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kBlock), (uint32_t)lds_bytes, stream, d, a);
+        hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kBlock), 0, stream, d, a);
     // a sample's total need not be a multiple of the over-count: its quotient
     // is an estimate, not checked
     const bool whole = cfg.root_stride == 1 && cfg.root_offset == 0 && !(busy && cfg.budget_ms > 0);
@@ -405,6 +404,7 @@ void batch_release(BatchState* st) {
     (void)hipFree(st->memo);
     (void)hipFree(st->queues);
     (void)hipFree(st->result);
+    (void)hipFree(st->run_queues);
     *st = BatchState{};
 }
 
@@ -422,7 +422,7 @@ static void batch_shape(const GpPlanDesc& d, const LaunchCfg& c, int min_group, 
 int batch_shape_key(const GpPlanDesc& d, const LaunchCfg& c, int min_group) {
     BatchPlan bp;
     batch_shape(d, c, min_group, &bp);
-    return (bp.group << 8) | (bp.leaf << 4) | d.iep;
+    return (std::min(d.k, 7) << 16) | (bp.group << 8) | (bp.leaf << 4) | d.iep;
 }
 
 // Per-plan task ranges, shapes and the launch geometry for np plans.
@@ -431,6 +431,8 @@ static gp_status batch_layout(const DeviceGraph& g, const GpPlanDesc* descs, con
                               BatchState* b, std::vector<BatchPlan>* plans) {
     plans->resize(np);
     b->runs.clear();
+    std::vector<int64_t> nroots(np, 0);
+    std::vector<bool> whole(np, false);
     int32_t nbuf = 0;
     b->kmax = 2;
     int64_t tag_next = 1;  // memo tags of the eligible plans: disjoint ranges
@@ -450,6 +452,8 @@ static gp_status batch_layout(const DeviceGraph& g, const GpPlanDesc* descs, con
         if (off < 0 || cnt < 0) return GP_ERR_ARG;
         off = std::min(off, n_tasks);
         cnt = std::min(cnt, n_tasks - off);
+        whole[i] = off == 0 && cnt == n_tasks;
+        nroots[i] = n_sampled;
         BatchPlan& bp = (*plans)[i];
         std::memset(&bp, 0, sizeof bp);
         bp.roots = roots;
@@ -462,16 +466,19 @@ static gp_status batch_layout(const DeviceGraph& g, const GpPlanDesc* descs, con
         batch_shape(descs[i], cfgs[i], min_group_floor, &bp);
         // consecutive plans of one shape share a launch
         const int iep_depth = descs[i].iep;
+        const int ksize = std::min((int)descs[i].k, 7);  // sizes 7 and 8 share a kernel
         if (b->runs.empty() || b->runs.back().group != bp.group || b->runs.back().leaf != bp.leaf ||
-            b->runs.back().iep != iep_depth) {
+            b->runs.back().iep != iep_depth || std::min(b->runs.back().kmin, 7) != ksize) {
             BatchRun r;
             r.p0 = i;
             r.group = bp.group;
             r.leaf = bp.leaf;
             r.iep = iep_depth;
+            r.kmin = r.kmax = descs[i].k;
             b->runs.push_back(r);
         }
         b->runs.back().p1 = i + 1;
+        b->runs.back().kmin = std::min(b->runs.back().kmin, (int)descs[i].k);
         b->runs.back().kmax = std::max(b->runs.back().kmax, (int)descs[i].k);
         b->runs.back().waves_per_cu = std::max(b->runs.back().waves_per_cu, cfgs[i].waves_per_cu);
         bp.tag_base = 0;
@@ -487,6 +494,19 @@ static gp_status batch_layout(const DeviceGraph& g, const GpPlanDesc* descs, con
     b->np = np;
     b->nbuf = nbuf;
     b->use_memo = any_memo;
+    for (BatchRun& r : b->runs) {
+        const BatchPlan& bp = (*plans)[r.p0];
+        r.solo = r.p1 - r.p0 == 1 && whole[r.p0] && bp.tag_base == 0 && r.kmin == r.kmax;
+        r.roots = bp.roots;
+        r.n_roots = nroots[r.p0];
+        r.root_offset = bp.root_offset;
+        r.root_stride = bp.root_stride;
+        r.n_tasks = bp.n_tasks;
+        r.split_roots = bp.split_roots;
+        r.split_ways = bp.split_ways;
+        r.chunk = bp.chunk;
+    }
+    b->h_descs.assign(descs, descs + np);
     return GP_OK;
 }
 
@@ -531,6 +551,7 @@ gp_status batch_prepare(const DeviceGraph& g, const GpPlanDesc* descs, const Lau
     if (hipMalloc(&b.descs, sizeof(GpPlanDesc) * np) != hipSuccess ||
         hipMalloc(&b.plans, sizeof(BatchPlan) * np) != hipSuccess ||
         hipMalloc((void**)&b.queues, sizeof(unsigned long long) * np) != hipSuccess ||
+        hipMalloc((void**)&b.run_queues, sizeof(unsigned long long) * kBatchMaxPlans * kQueueWords) != hipSuccess ||
         hipMalloc((void**)&b.result, 4 * sizeof(unsigned long long) * np) != hipSuccess ||
         (b.nbuf > 0 && hipMalloc((void**)&b.scratch, (size_t)(slots * b.nbuf * b.cap * 4)) != hipSuccess) ||
         (b.memo_words > 0 && hipMalloc((void**)&b.memo, (size_t)b.memo_words * 8) != hipSuccess))
@@ -563,13 +584,17 @@ gp_status batch_update(const DeviceGraph& g, BatchState* st, const GpPlanDesc* d
     if (!same) return GP_ERR_ARG;  // the shapes the buffers were carved for must not change
     GP_HIP_TRY(hipMemcpyAsync(st->plans, plans.data(), sizeof(BatchPlan) * st->np, hipMemcpyHostToDevice, stream));
     GP_HIP_TRY(hipStreamSynchronize(stream));
+    // solo runs take their task space as kernel arguments: the caller enqueues
+    // (or captures) the batch again
+    for (size_t i = 0; i < b.runs.size(); ++i) b.runs[i].blocks = st->runs[i].blocks;  // the carved grids
+    st->runs = b.runs;
     return GP_OK;
 }
 
 gp_status batch_enqueue(const DeviceGraph& g, const BatchState& st, hipStream_t stream) {
     if (st.runs.empty()) return GP_ERR_ARG;
     for (const BatchRun& r : st.runs)
-        if (!pick_batch_kernel(r.kmax, r.group, r.leaf, r.iep) || r.blocks < 1) return GP_ERR_UNSUPPORTED;
+        if (!pick_batch_kernel(r.kmin, r.kmax, r.group, r.leaf, r.iep) || r.blocks < 1) return GP_ERR_UNSUPPORTED;
     for (int i = 0; i < st.np; i += 64)
         hipLaunchKernelGGL(init_counters, dim3(1), dim3(64), 0, stream, st.queues + i, std::min(64, st.np - i));
     for (int i = 0; i < 4 * st.np; i += 64)
@@ -581,7 +606,46 @@ gp_status batch_enqueue(const DeviceGraph& g, const BatchState& st, hipStream_t 
     // one persistent launch per run of same-shape plans, in batch order. The
     // runs share the scratch and memo regions: launches on one stream never
     // overlap, and memo tags are disjoint per plan.
-    for (const BatchRun& r : st.runs) {
+    for (size_t ri = 0; ri < st.runs.size(); ++ri) {
+        const BatchRun& r = st.runs[ri];
+        if (r.solo) {
+            // the plain counting kernel over the plan's whole task space; its
+            // queue words are the run's own, and the high count word is moved
+            // into the plan's result words after it
+            const int p = r.p0;
+            const GpPlanDesc& d = st.h_descs[p];
+            KernelFn fn = pick_kernel(d.k, r.group, r.leaf, MODE_PLAIN, d.iep);
+            if (!fn) return GP_ERR_UNSUPPORTED;
+            unsigned long long* q = st.run_queues + ri * kQueueWords;
+            hipLaunchKernelGGL(init_counters, dim3(1), dim3(64), 0, stream, q, kQueueWords);
+            CountArgs a;
+            a.row_ptr = g.row_ptr;
+            a.col = g.col;
+            a.roots = r.roots;
+            a.n_roots = r.n_roots;
+            a.n_tasks = r.n_tasks;
+            a.split_roots = r.split_roots;
+            a.split_ways = r.split_ways;
+            a.budget_ticks = 0;
+            a.root_offset = r.root_offset;
+            a.hub_bits = g.hub_bits;
+            a.hub_words = g.hub_words;
+            a.n_hubs = g.n_hubs;
+            a.root_stride = r.root_stride;
+            a.scratch = st.scratch;
+            a.buf_cap = st.cap;
+            a.queue = q;
+            a.result = st.result + 4 * p;
+            a.per_root = nullptr;
+            a.busy = nullptr;
+            a.memo = nullptr;
+            a.chunk = r.chunk;
+            a.xcd_block = 0;
+            if (r.n_tasks > 0)
+                hipLaunchKernelGGL(fn, dim3((unsigned)r.blocks), dim3(kBlock), 0, stream, d, a);
+            hipLaunchKernelGGL(move_high_word, dim3(1), dim3(64), 0, stream, q + 1, st.result + 4 * p + 3);
+            continue;
+        }
         BatchArgs a;
         a.row_ptr = g.row_ptr;
         a.col = g.col;
@@ -598,7 +662,7 @@ gp_status batch_enqueue(const DeviceGraph& g, const BatchState& st, hipStream_t 
         a.memo = st.memo_words > 0 ? st.memo : nullptr;
         a.queues = st.queues + r.p0;
         a.result = st.result + 4 * r.p0;
-        hipLaunchKernelGGL(pick_batch_kernel(r.kmax, r.group, r.leaf, r.iep), dim3((unsigned)r.blocks), dim3(kBlock),
+        hipLaunchKernelGGL(pick_batch_kernel(r.kmin, r.kmax, r.group, r.leaf, r.iep), dim3((unsigned)r.blocks), dim3(kBlock),
                            0, stream, a);
     }
     return hipGetLastError() == hipSuccess ? GP_OK : GP_ERR_HIP;
@@ -618,6 +682,8 @@ gp_status arena_create(const DeviceGraph& g, int nbuf_cap, int waves_per_cu, int
     bool ok = hipMalloc(&b.descs, sizeof(GpPlanDesc) * kBatchMaxPlans) == hipSuccess &&
               hipMalloc(&b.plans, sizeof(BatchPlan) * kBatchMaxPlans) == hipSuccess &&
               hipMalloc((void**)&b.queues, sizeof(unsigned long long) * kBatchMaxPlans) == hipSuccess &&
+              hipMalloc((void**)&b.run_queues, sizeof(unsigned long long) * kBatchMaxPlans * kQueueWords) ==
+                  hipSuccess &&
               hipMalloc((void**)&b.result, 4 * sizeof(unsigned long long) * kBatchMaxPlans) == hipSuccess &&
               (a.nbuf_cap == 0 ||
                hipMalloc((void**)&b.scratch, (size_t)(a.slots_cap * a.nbuf_cap * b.cap * 4)) == hipSuccess) &&

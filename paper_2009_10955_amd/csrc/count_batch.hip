@@ -4,28 +4,31 @@
 //
 // Every plan keeps the launch shape tuned for it alone: lanes per group (64,
 // 32, 16 or 8), leaf mode (1, 3 or 4) and inclusion-exclusion depth, plus its
-// tasks per grab. The plans of one shape share ONE persistent launch of a
-// kernel compiled for that shape only, with a task cursor per plan:
+// tasks per grab. The plans of one shape and one pattern size (k <= 6; sizes
+// 7 and 8 share) run in ONE persistent launch of a kernel compiled for that
+// shape and size only, with a task cursor per plan:
 // wavefronts take the plans in order, grab a piece of the current plan's
 // tasks (64/G groups, bp.chunk tasks each), and move to the next plan once
 // its cursor is exhausted, so plans of uneven cost fill each other's tails
 // (Section IV-E's task partitioning, across patterns). One kernel per shape,
 // not one kernel for all shapes: a body that branches over several shapes
 // keeps the register allocation of their union, and the spills that follow
-// cost more than a launch. Per-plan 128-bit counts (and the wall-clock time
-// spent on each plan, for the serving scheduler) are summed per wavefront in
-// LDS and published once at the end. Built once per largest pattern size
-// (-DGP_BATCH_KMAX=5/6/8).
+// cost more than a launch (the same holds for pattern sizes). Per-plan
+// 128-bit counts (and the wall-clock time spent on each plan, for the serving
+// scheduler) are summed per wavefront in LDS and published once at the end.
+// Built once per pattern size k <= 6 (-DGP_BATCH_KMIN=k -DGP_BATCH_KMAX=k)
+// and once for sizes 7 and 8.
 #include "count_kernel.hpp"
 
-#if !defined(GP_BATCH_KMAX)
-#error "GP_BATCH_KMAX must be defined"
+#if !defined(GP_BATCH_KMAX) || !defined(GP_BATCH_KMIN)
+#error "GP_BATCH_KMIN and GP_BATCH_KMAX must be defined"
 #endif
 
 namespace gpcount {
 
 namespace {
 
+constexpr int KMIN = GP_BATCH_KMIN;
 constexpr int KMAX = GP_BATCH_KMAX;
 
 // Tasks [t0, t1) of plan bp (in the plan's own task space), shared by the
@@ -63,7 +66,7 @@ __device__ void run_piece(const BatchArgs& a, const GpPlanDesc& d, const BatchPl
     switch (d.k) {
 #define GP_BATCH_CASE(KK)                                                                                     \
     case KK:                                                                                                  \
-        if constexpr (KK <= KMAX) {                                                                           \
+        if constexpr (KK >= KMIN && KK <= KMAX) {                                                             \
             if constexpr (IEP > 0) {                                                                          \
                 if constexpr (KK >= IEP + 2) run_tasks<KK, G, 1, MODE_PLAIN, IEP>(d, c, ts, a0, a1, acc, carry, nullptr); \
             } else {                                                                                          \
@@ -148,7 +151,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(occupanc
 // The kernel of one batch shape: group width 64/32/16/8 with leaf mode 1, 3 or
 // 4 (IEP depth 0), or group width 64/32 with IEP depth 2..4 (leaf mode 1);
 // null for any other shape.
-BatchFn GP_CAT(batch_kernel_k, GP_BATCH_KMAX)(int group, int leaf, int iep) {
+BatchFn GP_CAT(GP_CAT(GP_CAT(batch_kernel_k, GP_BATCH_KMIN), _), GP_BATCH_KMAX)(int group, int leaf, int iep) {
     if (iep) {
         if (leaf != 1 || (group != 64 && group != 32)) return nullptr;
 #define GP_IEP_CASE(D)                                                                \

@@ -21,9 +21,10 @@
 //     binary-searches one element of the smaller list in the larger one;
 //     ballot + popcount compact the hits). G < 64 runs 64/G independent paths
 //     per wavefront, which pays on graphs whose lists are short.
-//   * Intersection results ("tmp" sets) live in a per-group region: in the
-//     block's LDS when a block's buffers fit (optional), else in HBM
-//     scratch, written and re-read while hot in L2.
+//   * Intersection results ("tmp" sets) live in a per-group scratch region in
+//     HBM; they are written and re-read while hot in L2. (A variant with the
+//     buffers in LDS was measured slower and turned every buffer access into
+//     a flat access; it is not kept.)
 //   * The second-to-last level is spread over the lanes (leaf mode 1: each
 //     lane counts the last level for its own candidate), walked with the
 //     group counting each last level together (leaf mode 2), flattened with
@@ -96,7 +97,6 @@ struct CountArgs {
     // n_hubs words {root tag, |N(x) & pre & cut|} for hub candidates x
     unsigned long long* memo;
     int32_t chunk;
-    int32_t lds_bufs;  // 1: the candidate buffers are in the block's dynamic LDS, not scratch
     // > 0: the task space is dealt to the XCDs in blocks of xcd_block tasks
     // (a multiple of chunk): block b goes to XCD b mod kXcds, each XCD takes
     // its blocks in order from its own cursor and then helps the others; 0:
@@ -1213,11 +1213,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(occupanc
     c.hub_bits = a.hub_bits;
     c.hub_words = a.hub_words;
     c.n_hubs = a.n_hubs;
-    extern __shared__ int32_t s_bufs[];  // dynamic: the block's buffers when they fit LDS
     const int grp = threadIdx.x / G;
     const int64_t group_id = (int64_t)blockIdx.x * (kBlock / G) + grp;
-    if (a.lds_bufs) c.bufs = s_bufs + (int64_t)grp * d.nbuf * a.buf_cap;
-    else c.bufs = a.scratch ? a.scratch + group_id * (int64_t)d.nbuf * a.buf_cap : nullptr;
+    c.bufs = a.scratch ? a.scratch + group_id * (int64_t)d.nbuf * a.buf_cap : nullptr;
     c.lens = s_len[grp];
     uint64_t bytes = 0;
     c.bytes = &bytes;

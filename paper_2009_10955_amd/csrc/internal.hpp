@@ -46,7 +46,6 @@ struct LaunchCfg {
     int split_ways = 1;
     int64_t split_vertices = 0;
     double budget_ms = 0;  // time limit per wavefront (measurement only; 0: none)
-    int lds = 0;           // 1: candidate buffers in LDS when a block's fit kLdsBufferBytes
     // tasks per XCD block (the task space dealt to the XCDs in blocks); 0 or
     // -1: one cursor for the device
     int64_t xcd = 0;
@@ -55,9 +54,6 @@ struct LaunchCfg {
 // Tasks per XCD block of a launch: cfg.xcd rounded up to a multiple of the
 // grab, or 0 for one cursor (the default).
 int64_t xcd_block_tasks(const DeviceGraph& g, const LaunchCfg& cfg, int group);
-
-// Largest LDS a block's candidate buffers may take (dynamic shared memory).
-constexpr int64_t kLdsBufferBytes = 64 << 10;
 
 // Device memory a launch may use instead of allocating its own: the task
 // cursor and high count word, the per-group candidate buffers and, when room
@@ -69,9 +65,6 @@ struct Workspace {
 
 // Wavefronts per compute unit that a launch of d with cfg keeps resident.
 int resident_waves_per_cu(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCfg& cfg);
-// Dynamic LDS of one block whose candidate buffers live in LDS (0: they
-// live in scratch: not asked for, or more than kLdsBufferBytes).
-int64_t lds_buffer_bytes(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCfg& cfg);
 
 // Launch one count of plan d over g on `stream`. result_dev: {count,
 // flags} (plus bytes when `account`), zeroed by this call on the stream.
@@ -102,9 +95,17 @@ gp_status launch_list(const DeviceGraph& g, const GpPlanDesc& d, const int32_t* 
 struct BatchRun {
     int p0 = 0, p1 = 0;
     int group = 64, leaf = 1, iep = 0;
-    int kmax = 2;
+    int kmin = 2, kmax = 2;  // pattern sizes of its plans (one size up to 6; 7 and 8 together)
     int waves_per_cu = 1;  // the largest of its plans'
     int64_t blocks = 0;    // grid of its launch
+    // one plan over its whole task space, without the memo: launched as the
+    // plain counting kernel (its descriptor a kernel argument), which the
+    // per-plan machinery of the batched kernel only slows down; its task
+    // space as that kernel takes it
+    bool solo = false;
+    const int2* roots = nullptr;
+    int64_t n_roots = 0, root_offset = 0, root_stride = 1, n_tasks = 0, split_roots = 0;
+    int32_t split_ways = 1, chunk = 1;
 };
 
 // Device state of one batch: descriptors, per-plan task ranges and shapes,
@@ -124,7 +125,9 @@ struct BatchState {
     unsigned long long* memo = nullptr;
     unsigned long long* queues = nullptr;  // np task cursors
     unsigned long long* result = nullptr;  // 4*np: count low word, flags, busy clock ticks, count high word
+    unsigned long long* run_queues = nullptr;  // kBatchMaxPlans * kQueueWords: solo runs' queue words
     std::vector<BatchRun> runs;            // host: the launches, in batch order
+    std::vector<GpPlanDesc> h_descs;       // host copies (solo runs pass theirs by value)
 };
 
 // A reusable batch for repeated launches with changing plans and task
@@ -159,11 +162,14 @@ gp_status batch_prepare(const DeviceGraph& g, const GpPlanDesc* descs, const Lau
                         hipStream_t stream, BatchState* st);
 // Re-lay the task ranges of a prepared batch for new per-plan launch
 // configurations (root samples); the shapes must be those it was prepared
-// with. Copies the plan table to the device and waits.
+// with. Copies the plan table to the device and waits. A captured batch must
+// be captured again afterwards: solo runs take their task space as kernel
+// arguments.
 gp_status batch_update(const DeviceGraph& g, BatchState* st, const GpPlanDesc* descs, const LaunchCfg* cfgs,
                        hipStream_t stream);
-// The launch shape a plan takes in a batch (group width, leaf mode, IEP
-// depth; group widths floored at min_group) as one comparable key.
+// The launch shape a plan takes in a batch (pattern size class, group width,
+// leaf mode, IEP depth; group widths floored at min_group) as one comparable
+// key.
 int batch_shape_key(const GpPlanDesc& d, const LaunchCfg& c, int min_group);
 // Enqueue counter reset + one launch per run on `stream` (no allocation).
 gp_status batch_enqueue(const DeviceGraph& g, const BatchState& st, hipStream_t stream);

@@ -610,12 +610,6 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
                     try_cfg(cfg);
                 }
             }
-            // candidate buffers in LDS, where a block's fit
-            {
-                gpint::LaunchCfg cfg = best_launch;
-                cfg.lds = 1;
-                if (best_launch.lds == 0 && gpint::lds_buffer_bytes(g->dg, cands[best].desc, cfg) > 0) try_cfg(cfg);
-            }
             // fewer resident wavefronts per compute unit: less contention for
             // the caches on graphs larger than them
             const int w0 = best_launch.waves_per_cu;

@@ -63,7 +63,7 @@ class Launch(ctypes.Structure):
                 ("chunk", ctypes.c_int32), ("leaf_mode", ctypes.c_int32),
                 ("root_stride", ctypes.c_int32), ("root_offset", ctypes.c_int32),
                 ("split_ways", ctypes.c_int32), ("split_vertices", ctypes.c_int32),
-                ("lds_buffers", ctypes.c_int32), ("xcd_tasks", ctypes.c_int32)]
+                ("xcd_tasks", ctypes.c_int32)]
 
 
 class TuneOpts(ctypes.Structure):
@@ -197,9 +197,9 @@ def _stream_handle(stream) -> int:
 
 
 def _launch(group=0, waves_per_cu=0, chunk=0, leaf_mode=0, root_stride=0, root_offset=0,
-            split_ways=0, split_vertices=0, lds_buffers=0, xcd_tasks=0) -> Launch:
+            split_ways=0, split_vertices=0, xcd_tasks=0) -> Launch:
     return Launch(group, waves_per_cu, chunk, leaf_mode, root_stride, root_offset, split_ways,
-                  split_vertices, lds_buffers, xcd_tasks)
+                  split_vertices, xcd_tasks)
 
 
 class Graph:
@@ -391,8 +391,7 @@ class Plan:
     def launch(self) -> dict:
         l = self.info().launch
         return dict(group=l.group, waves_per_cu=l.waves_per_cu, chunk=l.chunk, leaf_mode=l.leaf_mode,
-                    split_ways=l.split_ways, split_vertices=l.split_vertices, lds_buffers=l.lds_buffers,
-                    xcd_tasks=l.xcd_tasks)
+                    split_ways=l.split_ways, split_vertices=l.split_vertices, xcd_tasks=l.xcd_tasks)
 
     def close(self) -> None:
         if self._h:

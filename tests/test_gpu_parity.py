@@ -688,38 +688,6 @@ def test_xcd_task_blocks_equal_oracle(pname):
     assert c == want and b == gp.count_traffic(graph, plan, xcd_tasks=-1)[1]
 
 
-@pytest.mark.parametrize("pname", ["4-clique", "house", "5-clique", "6-cycle-chord", "prism", "5-wheel"])
-def test_lds_buffers_equal_oracle(pname):
-    """Candidate buffers in the block's LDS (graphs whose second-largest
-    degree lets a block's buffers fit) give the oracle's count at every group
-    width and leaf mode, plain, split and sampled; where they cannot fit the
-    launch keeps them in HBM and counts the same."""
-    k, e = P[pname]
-    for g in (I.er(200, 0.08, seed=41), I.config_graph(0)):
-        graph = gp.Graph.from_csr(g)
-        want = O.count(g, k, e)
-        plan = gp.Plan(k, e, stats=graph.stats())
-        for grp in (64, 32, 16, 8):
-            for leaf in (1, 3, 4):
-                assert gp.count(graph, plan, group=grp, leaf_mode=leaf, lds_buffers=1) == want, (grp, leaf)
-        assert gp.count(graph, plan, group=16, lds_buffers=1, split_ways=3, split_vertices=1 << 20) == want
-        assert sum(gp.count(graph, plan, group=32, lds_buffers=1, root_stride=4, root_offset=r)
-                   for r in range(4)) == want
-    # two hubs of degree 1200 (disjoint leaves) over a sparse graph: the
-    # buffers of a block of 8- or 16-lane groups cannot fit LDS, and the
-    # option falls back to HBM
-    rng = np.random.default_rng(42)
-    n = 2402
-    src = [0] * 1200 + [1] * 1200 + list(rng.integers(2, n, 4000))
-    dst = list(range(2, n)) + list(rng.integers(2, n, 4000))
-    g = I.csr_from_edges(n, np.array(src), np.array(dst))
-    graph = gp.Graph.from_csr(g)
-    plan = gp.Plan(k, e, stats=graph.stats())
-    want = O.count(g, k, e)
-    for grp in (16, 8):
-        assert gp.count(graph, plan, group=grp, lds_buffers=1) == want, grp
-
-
 # --------------------------------------------------------------------- IEP
 
 @pytest.mark.parametrize("pname", ["house", "diamond", "tailed-triangle", "4-path", "3-star",

@@ -398,8 +398,6 @@ int64_t root_task_count(const DeviceGraph& g, const GpPlanDesc& d) {
 }
 
 void batch_release(BatchState* st) {
-    (void)hipFree(st->descs);
-    (void)hipFree(st->plans);
     (void)hipFree(st->scratch);
     (void)hipFree(st->memo);
     (void)hipFree(st->queues);
@@ -423,6 +421,11 @@ int batch_shape_key(const GpPlanDesc& d, const LaunchCfg& c, int min_group) {
     BatchPlan bp;
     batch_shape(d, c, min_group, &bp);
     return (std::min(d.k, 7) << 16) | (bp.group << 8) | (bp.leaf << 4) | d.iep;
+}
+
+// The host copy of a batch's plan table (launches pass it by value).
+static void store_plans(BatchState* b, const std::vector<BatchPlan>& plans) {
+    b->h_plans.assign((const char*)plans.data(), (const char*)(plans.data() + plans.size()));
 }
 
 // Per-plan task ranges, shapes and the launch geometry for np plans.
@@ -464,11 +467,13 @@ static gp_status batch_layout(const DeviceGraph& g, const GpPlanDesc* descs, con
         bp.split_roots = sp.roots;
         bp.split_ways = sp.ways;
         batch_shape(descs[i], cfgs[i], min_group_floor, &bp);
-        // consecutive plans of one shape share a launch
+        // consecutive plans of one shape share a launch (up to kRunMaxPlans:
+        // their descriptors are its kernel arguments)
         const int iep_depth = descs[i].iep;
         const int ksize = std::min((int)descs[i].k, 7);  // sizes 7 and 8 share a kernel
         if (b->runs.empty() || b->runs.back().group != bp.group || b->runs.back().leaf != bp.leaf ||
-            b->runs.back().iep != iep_depth || std::min(b->runs.back().kmin, 7) != ksize) {
+            b->runs.back().iep != iep_depth || std::min(b->runs.back().kmin, 7) != ksize ||
+            b->runs.back().p1 - b->runs.back().p0 >= kRunMaxPlans) {
             BatchRun r;
             r.p0 = i;
             r.group = bp.group;
@@ -507,6 +512,7 @@ static gp_status batch_layout(const DeviceGraph& g, const GpPlanDesc* descs, con
         r.chunk = bp.chunk;
     }
     b->h_descs.assign(descs, descs + np);
+    store_plans(b, *plans);
     return GP_OK;
 }
 
@@ -548,20 +554,13 @@ gp_status batch_prepare(const DeviceGraph& g, const GpPlanDesc* descs, const Lau
         slots = std::max(slots, run_group_slots(r));
     }
     b.memo_words = b.use_memo ? slots * (int64_t)g.n_hubs : 0;
-    if (hipMalloc(&b.descs, sizeof(GpPlanDesc) * np) != hipSuccess ||
-        hipMalloc(&b.plans, sizeof(BatchPlan) * np) != hipSuccess ||
-        hipMalloc((void**)&b.queues, sizeof(unsigned long long) * np) != hipSuccess ||
+    if (hipMalloc((void**)&b.queues, sizeof(unsigned long long) * np) != hipSuccess ||
         hipMalloc((void**)&b.run_queues, sizeof(unsigned long long) * kBatchMaxPlans * kQueueWords) != hipSuccess ||
         hipMalloc((void**)&b.result, 4 * sizeof(unsigned long long) * np) != hipSuccess ||
         (b.nbuf > 0 && hipMalloc((void**)&b.scratch, (size_t)(slots * b.nbuf * b.cap * 4)) != hipSuccess) ||
         (b.memo_words > 0 && hipMalloc((void**)&b.memo, (size_t)b.memo_words * 8) != hipSuccess))
         rc = GP_ERR_NOMEM;
-    if (rc == GP_OK &&
-        (hipMemcpyAsync(b.descs, descs, sizeof(GpPlanDesc) * np, hipMemcpyHostToDevice, stream) != hipSuccess ||
-         hipMemcpyAsync(b.plans, plans.data(), sizeof(BatchPlan) * np, hipMemcpyHostToDevice, stream) !=
-             hipSuccess ||
-         hipStreamSynchronize(stream) != hipSuccess))
-        rc = GP_ERR_HIP;
+    if (rc == GP_OK && hipStreamSynchronize(stream) != hipSuccess) rc = GP_ERR_HIP;
     if (rc != GP_OK) {
         batch_release(&b);
         return rc;
@@ -582,12 +581,12 @@ gp_status batch_update(const DeviceGraph& g, BatchState* st, const GpPlanDesc* d
                b.runs[i].group == st->runs[i].group && b.runs[i].leaf == st->runs[i].leaf &&
                b.runs[i].iep == st->runs[i].iep;
     if (!same) return GP_ERR_ARG;  // the shapes the buffers were carved for must not change
-    GP_HIP_TRY(hipMemcpyAsync(st->plans, plans.data(), sizeof(BatchPlan) * st->np, hipMemcpyHostToDevice, stream));
-    GP_HIP_TRY(hipStreamSynchronize(stream));
-    // solo runs take their task space as kernel arguments: the caller enqueues
-    // (or captures) the batch again
+    (void)stream;
+    // launches take their task ranges as kernel arguments: the caller
+    // enqueues (or captures) the batch again
     for (size_t i = 0; i < b.runs.size(); ++i) b.runs[i].blocks = st->runs[i].blocks;  // the carved grids
     st->runs = b.runs;
+    st->h_plans = b.h_plans;
     return GP_OK;
 }
 
@@ -649,8 +648,6 @@ gp_status batch_enqueue(const DeviceGraph& g, const BatchState& st, hipStream_t 
         BatchArgs a;
         a.row_ptr = g.row_ptr;
         a.col = g.col;
-        a.descs = (const GpPlanDesc*)st.descs + r.p0;
-        a.plans = (const BatchPlan*)st.plans + r.p0;
         a.np = r.p1 - r.p0;
         a.hub_bits = g.hub_bits;
         a.hub_words = g.hub_words;
@@ -662,8 +659,14 @@ gp_status batch_enqueue(const DeviceGraph& g, const BatchState& st, hipStream_t 
         a.memo = st.memo_words > 0 ? st.memo : nullptr;
         a.queues = st.queues + r.p0;
         a.result = st.result + 4 * r.p0;
+        RunDescs rd;
+        std::memset(&rd, 0, sizeof rd);
+        for (int p = r.p0; p < r.p1; ++p) {
+            rd.d[p - r.p0] = st.h_descs[p];
+            rd.bp[p - r.p0] = reinterpret_cast<const BatchPlan*>(st.h_plans.data())[p];
+        }
         hipLaunchKernelGGL(pick_batch_kernel(r.kmin, r.kmax, r.group, r.leaf, r.iep), dim3((unsigned)r.blocks), dim3(kBlock),
-                           0, stream, a);
+                           0, stream, a, rd);
     }
     return hipGetLastError() == hipSuccess ? GP_OK : GP_ERR_HIP;
 }
@@ -679,18 +682,13 @@ gp_status arena_create(const DeviceGraph& g, int nbuf_cap, int waves_per_cu, int
     a.blocks_cap = batch_blocks(g, waves_per_cu, 64 / a.min_group, a.nbuf_cap, b.cap, true);
     a.slots_cap = a.blocks_cap * (kBlock / 64) * (64 / a.min_group);
     a.memo_words_cap = g.n_hubs > 0 ? a.slots_cap * (int64_t)g.n_hubs : 0;
-    bool ok = hipMalloc(&b.descs, sizeof(GpPlanDesc) * kBatchMaxPlans) == hipSuccess &&
-              hipMalloc(&b.plans, sizeof(BatchPlan) * kBatchMaxPlans) == hipSuccess &&
-              hipMalloc((void**)&b.queues, sizeof(unsigned long long) * kBatchMaxPlans) == hipSuccess &&
+    bool ok = hipMalloc((void**)&b.queues, sizeof(unsigned long long) * kBatchMaxPlans) == hipSuccess &&
               hipMalloc((void**)&b.run_queues, sizeof(unsigned long long) * kBatchMaxPlans * kQueueWords) ==
                   hipSuccess &&
               hipMalloc((void**)&b.result, 4 * sizeof(unsigned long long) * kBatchMaxPlans) == hipSuccess &&
               (a.nbuf_cap == 0 ||
                hipMalloc((void**)&b.scratch, (size_t)(a.slots_cap * a.nbuf_cap * b.cap * 4)) == hipSuccess) &&
               (a.memo_words_cap == 0 || hipMalloc((void**)&b.memo, (size_t)a.memo_words_cap * 8) == hipSuccess) &&
-              hipHostMalloc((void**)&a.h_descs, sizeof(GpPlanDesc) * kBatchMaxPlans, hipHostMallocDefault) ==
-                  hipSuccess &&
-              hipHostMalloc(&a.h_plans, sizeof(BatchPlan) * kBatchMaxPlans, hipHostMallocDefault) == hipSuccess &&
               hipHostMalloc((void**)&a.h_result, 4 * sizeof(unsigned long long) * kBatchMaxPlans,
                             hipHostMallocDefault) == hipSuccess;
     if (!ok) {
@@ -727,10 +725,7 @@ gp_status arena_launch(const DeviceGraph& g, BatchArena* ar, const GpPlanDesc* d
         for (auto& bp : plans) bp.tag_base = 0;
         b.memo_words = 0;
     }
-    std::memcpy(ar->h_descs, descs, sizeof(GpPlanDesc) * np);
-    std::memcpy(ar->h_plans, plans.data(), sizeof(BatchPlan) * np);
-    GP_HIP_TRY(hipMemcpyAsync(b.descs, ar->h_descs, sizeof(GpPlanDesc) * np, hipMemcpyHostToDevice, stream));
-    GP_HIP_TRY(hipMemcpyAsync(b.plans, ar->h_plans, sizeof(BatchPlan) * np, hipMemcpyHostToDevice, stream));
+    store_plans(&b, plans);
     rc = batch_enqueue(g, b, stream);
     if (rc != GP_OK) return rc;
     GP_HIP_TRY(hipMemcpyAsync(ar->h_result, b.result, 4 * sizeof(unsigned long long) * np, hipMemcpyDeviceToHost,
@@ -753,8 +748,6 @@ gp_status batch_result(const GpPlanDesc& d, const unsigned long long* r, uint64_
 
 void arena_release(BatchArena* ar) {
     batch_release(&ar->st);
-    if (ar->h_descs) (void)hipHostFree(ar->h_descs);
-    if (ar->h_plans) (void)hipHostFree(ar->h_plans);
     if (ar->h_result) (void)hipHostFree(ar->h_result);
     *ar = BatchArena{};
 }

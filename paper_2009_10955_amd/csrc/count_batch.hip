@@ -89,7 +89,7 @@ __device__ void run_piece(const BatchArgs& a, const GpPlanDesc& d, const BatchPl
 }
 
 template <int G, int LEAF, int IEP>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(occupancy_target(KMAX, G, LEAF, IEP)))) void batch_kernel(BatchArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(occupancy_target(KMAX, G, LEAF, IEP)))) void batch_kernel(BatchArgs a, RunDescs rd) {
     __shared__ int32_t s_len[kBlock / G][GP_DESC_MAX_BUILDS];
     __shared__ unsigned long long s_lo[kBlock / 64][kBatchMaxPlans];
     __shared__ unsigned long long s_hi[kBlock / 64][kBatchMaxPlans];
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(occupanc
 
     int p = 0;
     while (p < a.np) {
-        const BatchPlan& bp = a.plans[p];
+        const BatchPlan& bp = rd.bp[p];
         const int64_t W = kGroups * bp.chunk;
         unsigned long long q = 0;
         if (lane == 0) q = atomicAdd(&a.queues[p], (unsigned long long)W);
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(occupanc
             continue;
         }
         const int64_t t1 = min(t0 + W, n_tasks);
-        const GpPlanDesc& d = a.descs[p];
+        const GpPlanDesc& d = rd.d[p];
         const uint64_t clk0 = wall_clock64();
         uint64_t acc = 0, carry = 0;
         run_piece<G, LEAF, IEP>(a, d, bp, bp.task_offset + t0, bp.task_offset + t1, lens_base, wave_global, acc,

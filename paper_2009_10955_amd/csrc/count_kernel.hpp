@@ -125,11 +125,20 @@ struct BatchPlan {
     int32_t pad;
 };
 
+
+// The descriptors and task ranges of one batched launch's plans, in the order
+// waves take them, passed by value: kernel arguments live in constant memory,
+// so every field is a scalar load, where a table read from global memory costs
+// a vector load and registers at every use.
+constexpr int kRunMaxPlans = 8;
+struct RunDescs {
+    GpPlanDesc d[kRunMaxPlans];
+    BatchPlan bp[kRunMaxPlans];
+};
+
 struct BatchArgs {
     const int64_t* row_ptr;
     const int32_t* col;
-    const GpPlanDesc* descs;  // device, np entries
-    const BatchPlan* plans;   // device, np entries, in the order waves take them
     int32_t np;
     const uint32_t* hub_bits;
     int64_t hub_words;
@@ -143,7 +152,7 @@ struct BatchArgs {
     unsigned long long* result;   // per plan {count low word, flags, busy clock ticks, high word}
 };
 
-typedef void (*BatchFn)(BatchArgs);
+typedef void (*BatchFn)(BatchArgs, RunDescs);
 
 // Where a group's root tasks come from.
 struct TaskSpace {

@@ -119,15 +119,14 @@ struct BatchState {
     int32_t nbuf = 0;
     int64_t cap = 0;
     int64_t memo_words = 0;
-    void* descs = nullptr;   // GpPlanDesc[np]
-    void* plans = nullptr;   // per-plan task ranges and shapes
     int32_t* scratch = nullptr;
     unsigned long long* memo = nullptr;
     unsigned long long* queues = nullptr;  // np task cursors
     unsigned long long* result = nullptr;  // 4*np: count low word, flags, busy clock ticks, count high word
     unsigned long long* run_queues = nullptr;  // kBatchMaxPlans * kQueueWords: solo runs' queue words
     std::vector<BatchRun> runs;            // host: the launches, in batch order
-    std::vector<GpPlanDesc> h_descs;       // host copies (solo runs pass theirs by value)
+    std::vector<GpPlanDesc> h_descs;       // host copies: launches take them as kernel arguments
+    std::vector<char> h_plans;             // the per-plan task ranges and shapes, likewise
 };
 
 // A reusable batch for repeated launches with changing plans and task
@@ -144,8 +143,6 @@ struct BatchArena {
     int64_t blocks_cap = 0;
     int64_t slots_cap = 0;  // group slots of the scratch region (nbuf_cap buffers each)
     int64_t memo_words_cap = 0;
-    GpPlanDesc* h_descs = nullptr;
-    void* h_plans = nullptr;
     unsigned long long* h_result = nullptr;
 };
 gp_status arena_create(const DeviceGraph& g, int nbuf_cap, int waves_per_cu, int min_group, BatchArena* a);

@@ -398,7 +398,10 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
                 pk.est = measure(bd, base, stride, "shape", c, true);
                 if (pk.est < 0) break;
                 tried.push_back(pk);
-                for (int lm : {2, 3, 4}) {
+                // leaf 2 (a group walk per candidate) last: it rarely wins for
+                // k >= 5, and its samples are the slowest, so the budget that
+                // remains goes to it
+                for (int lm : {3, 4, 2}) {
                     if (!leaf_ok(bd, lm) || spent > 2.5 * budget_ms) continue;
                     gpint::LaunchCfg cfg = base;
                     cfg.leaf = lm;
@@ -456,8 +459,9 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
         std::stable_sort(picks.begin(), picks.end(), [](const Pick& a, const Pick& b) { return a.est < b.est; });
         std::stable_sort(tried.begin(), tried.end(), [](const Pick& a, const Pick& b) { return a.est < b.est; });
         // the best configuration at its best leaf mode for every group width
-        // measured (sample estimates rank widths within their noise), then
-        // the runner-up configuration's best pair
+        // measured (sample estimates rank widths within their noise) and at its
+        // best width for every leaf mode, then the runner-up configuration's
+        // best pair
         std::vector<Pick> full;
         auto add_full = [&](const Pick& pk) {
             for (const Pick& f : full)
@@ -469,6 +473,14 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
             for (int grp : {64, 32, 16, 8})
                 for (const Pick& pk : tried)  // sorted: the first of a width is its best
                     if (pk.c == picks[0].c && pk.launch.group == grp) {
+                        add_full(pk);
+                        break;
+                    }
+            // and at its best width for every leaf mode measured (the samples
+            // rank leaf modes within their noise as well)
+            for (int lm : {1, 2, 3, 4})
+                for (const Pick& pk : tried)
+                    if (pk.c == picks[0].c && pk.launch.leaf == lm) {
                         add_full(pk);
                         break;
                     }

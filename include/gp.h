@@ -158,6 +158,11 @@ typedef struct {
                               out helps the others. -1: one task cursor for the whole
                               device (all XCDs walk the same stretch of root edges, which
                               the shared last-level cache then holds once) */
+    int32_t batch_runs;    /* batches (gp_count_batch, gp_batch_create): 0 or 1 = consecutive
+                              plans of one launch shape and pattern size share one persistent
+                              launch with a task cursor each; 2 = every plan gets its own
+                              launch in the batch (a plan over its whole task space then
+                              runs as gp_count would). gp_batch_tune measures both */
 } gp_launch;
 
 void gp_launch_default(gp_launch* l);
@@ -294,7 +299,8 @@ gp_status gp_plan_tune(const gp_graph* g, const gp_plan* p, const gp_tune_opts* 
  * different shapes (Section IV-E's task partitioning across patterns).
  * GP_ERR_ARG on a field out of range (group not 64/32/16/8, leaf_mode not
  * 1..4, waves_per_cu not 1..32, negative chunk, split_ways or
- * split_vertices); *out is then untouched. Free with gp_free_plan.
+ * split_vertices, xcd_tasks below -1, batch_runs not 0..2); *out is then
+ * untouched. Free with gp_free_plan.
  */
 gp_status gp_plan_with_launch(const gp_plan* p, const gp_launch* launch, gp_plan** out);
 

@@ -492,6 +492,7 @@ gp_status gp_plan_get(const gp_plan* p, gp_plan_info* out) {
     out->launch.split_ways = p->launch.split_ways;
     out->launch.split_vertices = (int32_t)std::min<int64_t>(p->launch.split_vertices, INT32_MAX);
     out->launch.xcd_tasks = (int32_t)std::max<int64_t>(-1, std::min<int64_t>(p->launch.xcd, INT32_MAX));
+    out->launch.batch_runs = p->launch.batch_runs;
     return GP_OK;
 }
 
@@ -536,7 +537,8 @@ gp_status gp_plan_with_launch(const gp_plan* p, const gp_launch* launch, gp_plan
     const gp_launch& l = *launch;
     if ((l.group && l.group != 64 && l.group != 32 && l.group != 16 && l.group != 8) ||
         (l.leaf_mode && (l.leaf_mode < 1 || l.leaf_mode > 4)) || (l.waves_per_cu && (l.waves_per_cu < 1 || l.waves_per_cu > 32)) ||
-        l.chunk < 0 || l.split_ways < 0 || l.split_vertices < 0 || l.xcd_tasks < -1)
+        l.chunk < 0 || l.split_ways < 0 || l.split_vertices < 0 || l.xcd_tasks < -1 || l.batch_runs < 0 ||
+        l.batch_runs > 2)
         return GP_ERR_ARG;
     gp_plan* q = new (std::nothrow) gp_plan(*p);
     if (!q) return GP_ERR_NOMEM;
@@ -814,8 +816,10 @@ gp_status gp_batch_tune(const gp_graph* g, const gp_plan* const* plans, int32_t 
     gp_status st = GP_OK;
     double best = -1;
     gp_launch pick{};
-    // each plan at its own shape (all fields zero), then one shape for all
-    std::vector<gp_launch> shapes(1, gp_launch{});
+    // each plan at its own shape (all fields zero), sharing launches by shape
+    // and each in a launch of its own, then one shape for all
+    std::vector<gp_launch> shapes(2, gp_launch{});
+    shapes[1].batch_runs = 2;
     for (int grp : {64, 32, 16})
         for (int lm : {1, 3, 4}) {
             gp_launch l{};

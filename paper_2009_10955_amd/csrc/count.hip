@@ -154,6 +154,7 @@ LaunchCfg apply_launch(LaunchCfg cfg, const gp_launch* l) {
         if (l->split_ways) cfg.split_ways = l->split_ways;
         if (l->split_vertices) cfg.split_vertices = l->split_vertices;
         if (l->xcd_tasks) cfg.xcd = l->xcd_tasks;
+        if (l->batch_runs) cfg.batch_runs = l->batch_runs;
     }
     return cfg;
 }
@@ -473,7 +474,7 @@ static gp_status batch_layout(const DeviceGraph& g, const GpPlanDesc* descs, con
         const int ksize = std::min((int)descs[i].k, 7);  // sizes 7 and 8 share a kernel
         if (b->runs.empty() || b->runs.back().group != bp.group || b->runs.back().leaf != bp.leaf ||
             b->runs.back().iep != iep_depth || std::min(b->runs.back().kmin, 7) != ksize ||
-            b->runs.back().p1 - b->runs.back().p0 >= kRunMaxPlans) {
+            b->runs.back().p1 - b->runs.back().p0 >= kRunMaxPlans || cfgs[i].batch_runs == 2) {
             BatchRun r;
             r.p0 = i;
             r.group = bp.group;

@@ -49,6 +49,7 @@ struct LaunchCfg {
     // tasks per XCD block (the task space dealt to the XCDs in blocks); 0 or
     // -1: one cursor for the device
     int64_t xcd = 0;
+    int batch_runs = 0;  // batches: 2 = every plan its own launch
 };
 
 // Tasks per XCD block of a launch: cfg.xcd rounded up to a multiple of the

@@ -63,7 +63,7 @@ class Launch(ctypes.Structure):
                 ("chunk", ctypes.c_int32), ("leaf_mode", ctypes.c_int32),
                 ("root_stride", ctypes.c_int32), ("root_offset", ctypes.c_int32),
                 ("split_ways", ctypes.c_int32), ("split_vertices", ctypes.c_int32),
-                ("xcd_tasks", ctypes.c_int32)]
+                ("xcd_tasks", ctypes.c_int32), ("batch_runs", ctypes.c_int32)]
 
 
 class TuneOpts(ctypes.Structure):
@@ -197,9 +197,9 @@ def _stream_handle(stream) -> int:
 
 
 def _launch(group=0, waves_per_cu=0, chunk=0, leaf_mode=0, root_stride=0, root_offset=0,
-            split_ways=0, split_vertices=0, xcd_tasks=0) -> Launch:
+            split_ways=0, split_vertices=0, xcd_tasks=0, batch_runs=0) -> Launch:
     return Launch(group, waves_per_cu, chunk, leaf_mode, root_stride, root_offset, split_ways,
-                  split_vertices, xcd_tasks)
+                  split_vertices, xcd_tasks, batch_runs)
 
 
 class Graph:
@@ -391,7 +391,8 @@ class Plan:
     def launch(self) -> dict:
         l = self.info().launch
         return dict(group=l.group, waves_per_cu=l.waves_per_cu, chunk=l.chunk, leaf_mode=l.leaf_mode,
-                    split_ways=l.split_ways, split_vertices=l.split_vertices, xcd_tasks=l.xcd_tasks)
+                    split_ways=l.split_ways, split_vertices=l.split_vertices, xcd_tasks=l.xcd_tasks,
+                    batch_runs=l.batch_runs)
 
     def close(self) -> None:
         if self._h:
@@ -508,13 +509,13 @@ def count_batch(graph: Graph, plans: Sequence[Plan], stream=None, **launch) -> l
 
 def batch_tune(graph: Graph, plans: Sequence[Plan], stream=None) -> tuple[dict, float]:
     """Fastest batched launch shape for these plans (gp_batch_tune): ({group,
-    leaf_mode}, its time in ms)."""
+    leaf_mode, batch_runs}, its time in ms)."""
     arr = (ctypes.c_void_p * len(plans))(*[p.handle for p in plans])
     lp = Launch()
     ms = ctypes.c_double()
     _check(_lib().gp_batch_tune(graph.handle, arr, len(plans), _stream_handle(stream), ctypes.byref(lp),
                                 ctypes.byref(ms)), "gp_batch_tune")
-    return {"group": lp.group, "leaf_mode": lp.leaf_mode}, ms.value
+    return {"group": lp.group, "leaf_mode": lp.leaf_mode, "batch_runs": lp.batch_runs}, ms.value
 
 
 class Batch:

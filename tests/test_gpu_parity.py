@@ -740,3 +740,25 @@ def test_iep_per_root_and_config2():
         assert total == plain
         assert int(per.cpu().numpy().sum()) == plain * ip.info().iep_div
     assert gp.count(graph, gp.Plan(*P["diamond"])) == O.count(g, *P["diamond"])
+
+
+def test_batch_with_a_launch_per_plan_equals_oracle():
+    """batch_runs = 2: every plan its own launch inside the batch (the plain
+    kernel for whole plans), against the oracle and the shared-launch batch,
+    eager, replayed and sampled."""
+    g = I.er(160, 0.1, seed=13)
+    graph = gp.Graph.from_csr(g, device=True)
+    names = ["triangle", "4-cycle", "house", "5-cycle", "diamond", "prism"]
+    plans = [gp.Plan(*P[n], stats=graph.stats()) for n in names]
+    want = [O.count(g, *P[n]) for n in names]
+    assert gp.count_batch(graph, plans, batch_runs=2) == want
+    assert gp.count_batch(graph, plans, batch_runs=1) == want
+    b = gp.Batch(graph, plans, batch_runs=2)
+    for _ in range(2):
+        assert b.run() == want
+    parts = []
+    for r in range(4):
+        b.set_sample(4, r)
+        parts.append(b.run())
+    assert [sum(x) for x in zip(*parts)] == want
+    b.close()

@@ -39,12 +39,12 @@ WORKLOADS = {
     "er1000": (0, ["triangle", "4-cycle", "4-clique"],
                "G(1000, 0.01) seed 1; triangle, 4-cycle, 4-clique, one launch each", "plain"),
     "chunglu7000": (2, ["6-cycle", "6-cycle-chord", "prism", "k4-path", "5-wheel", "6-clique"],
-                    "Chung-Lu n=7000, gamma 2.1, ~100k edges, seed 3; six 6-vertex patterns in one "
-                    "persistent launch captured in a hipGraph, against one launch per pattern",
+                    "Chung-Lu n=7000, gamma 2.1, ~100k edges, seed 3; six 6-vertex patterns counted "
+                    "by one batched hipGraph replay, against one launch per pattern",
                     "batched"),
     "rmat22": (3, ["4-clique", "house", "5-cycle", "6-cycle-chord"],
                "R-MAT scale 22, edge factor 8, (0.57,0.19,0.19,0.05), seed 4; 4-clique, house, "
-               "5-cycle, 6-cycle+chord in one persistent launch (hipGraph) against one launch per "
+               "5-cycle, 6-cycle+chord counted by one batched hipGraph replay against one launch per "
                "pattern; a step counts one of 20 strided slices of every pattern's root edges, so "
                "20 steps count every embedding once; patterns whose tuned full run is estimated "
                "above --max-pattern-s are reported with their estimate, not run", "sliced"),
@@ -579,7 +579,7 @@ def list_main(args, desc, g, graph, st, names, plans, launches, base_plans, plan
 
 
 def batched_main(args, desc, g, graph, st, names, plans, launches, base_plans, plan_s, tune_s):
-    """Batched workloads: the feasible patterns in ONE persistent launch
+    """Batched workloads: the feasible patterns counted by one batch
     (replayed from a hipGraph), against one launch per pattern (each its own
     launch and synchronisation), at identical counts."""
     import torch
@@ -678,7 +678,7 @@ def batched_main(args, desc, g, graph, st, names, plans, launches, base_plans, p
         achieved = alg / (ms_b / 1e3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
-                    "kernel": "batch_kernel (all feasible patterns, one launch)",
+                    "kernel": "the batch's launches (all feasible patterns, one hipGraph replay)",
                     "alg_bytes_per_launch": alg, "avg_launch_ms": round(ms_b, 3)}
     cpu = None
     if not args.no_cpu_baseline and args.workload != "rmat22":
@@ -716,7 +716,7 @@ def sliced_main(args, cfg_idx, names, desc):
     run estimated, tuned (IEP configurations competing) and estimated again;
     those above --max-pattern-s are reported with their estimate. A step
     counts slice s (root edges s, s + S, s + 2S, ... of every feasible
-    pattern, heavy roots split as tuned) in ONE persistent launch replayed
+    pattern, heavy roots split as tuned) with the batched launches replayed
     from a hipGraph; the same slices are then counted with one launch per
     pattern. S steps count every embedding once."""
     import torch

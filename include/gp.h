@@ -428,16 +428,20 @@ gp_status gp_estimate(const gp_graph* g, const gp_plan* p, const gp_launch* laun
 
 /*
  * Count several plans (1..64, any pattern sizes, counted plainly or with
- * IEP) over one graph in ONE persistent launch (Section IV-E's task
- * partitioning, across patterns). Every plan keeps its own task cursor and
- * its own launch shape: lanes per group (64, 32 or 16; IEP plans 64 or 32),
- * leaf mode (1, 3 or 4 where the plan allows it) and tasks per grab come
- * from the plan's launch (its tuned one after gp_plan_tune), with every
- * non-zero field of `launch` (may be null) overriding them for all plans.
- * Wavefronts take the plans longest-first by gp_plan_info.tuned_ms (untuned
- * plans after, in the given order) and move to the next plan when one's
- * tasks are all handed out, so the plans fill each other's tails. Totals are
- * exact 128-bit sums, divided by each plan's IEP over-count on the host.
+ * IEP) over one graph together (Section IV-E's task partitioning, across
+ * patterns). Every plan keeps its own task cursor and its own launch shape:
+ * lanes per group (64, 32, 16 or 8; IEP plans 64 or 32), leaf mode (1, 3 or
+ * 4 where the plan allows it) and tasks per grab come from the plan's launch
+ * (its tuned one after gp_plan_tune), with every non-zero field of `launch`
+ * (may be null) overriding them for all plans. Plans of one shape and
+ * pattern size (at most 8 at a time) share ONE persistent launch of the
+ * kernel compiled for that shape: its wavefronts take the plans
+ * longest-first by gp_plan_info.tuned_ms (untuned plans after, in the given
+ * order) and move to the next plan when one's tasks are all handed out, so
+ * the plans fill each other's tails. A plan alone in its shape (or every
+ * plan, with launch->batch_runs = 2) runs as gp_count would. The shapes run
+ * one after another on `stream`. Totals are exact 128-bit sums, divided by
+ * each plan's IEP over-count on the host.
  * out[i] = count of plans[i] (host memory); GP_ERR_OVERFLOW if one does not
  * fit in 64 bits. Blocking. Counts equal gp_count's bit for bit.
  */

@@ -498,7 +498,7 @@ def estimate(graph: Graph, plan: Plan, budget_ms: float = 0.0, stream=None, **la
 
 
 def count_batch(graph: Graph, plans: Sequence[Plan], stream=None, **launch) -> list[int]:
-    """Counts of several plans in one persistent launch (blocking)."""
+    """Counts of several plans counted together (gp_count_batch; blocking)."""
     arr = (ctypes.c_void_p * len(plans))(*[p.handle for p in plans])
     out = (ctypes.c_uint64 * len(plans))()
     lp = _launch(**launch)
@@ -519,7 +519,7 @@ def batch_tune(graph: Graph, plans: Sequence[Plan], stream=None) -> tuple[dict, 
 
 
 class Batch:
-    """Several plans counted by one persistent launch captured in a hipGraph."""
+    """Several plans counted together, the launches captured in one hipGraph."""
 
     def __init__(self, graph: Graph, plans: Sequence[Plan], stream=None, **launch):
         self.graph = graph

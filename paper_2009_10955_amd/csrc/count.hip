@@ -73,6 +73,18 @@ __global__ void zero_u64(unsigned long long* p, int64_t n) {
 // level is pre & N(v[k-2]) with pre the list of a root level, its cut comes
 // from the root levels only, and every earlier image it must avoid is a
 // parent of level k-2.
+// IEP plans: some inner set is left unbuilt as N(a) & N(x) with a an outer
+// vertex's list and no cut, so its size depends on (a, x) alone and the
+// kernel keeps it per hub x (count_kernel.hpp, iep_subset_count).
+bool iep_memo_eligible(const GpPlanDesc& d) {
+    if (!d.iep) return false;
+    for (int j = d.k - d.iep; j < d.k; ++j) {
+        const GpLevel& lv = d.lv[j];
+        if (lv.last_list >= 0 && lv.pre_buf < 0 && lv.pre_list >= 0 && (lv.hi_src | lv.lo_src) == 0) return true;
+    }
+    return false;
+}
+
 bool memo_eligible(const GpPlanDesc& d) {
     if (d.k < 4 || d.iep) return false;
     const GpLevel& ll = d.lv[d.k - 1];
@@ -259,8 +271,9 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
     // (within what the workspace has left)
     const int64_t memo_words = blocks * groups_per_block * (int64_t)g.n_hubs;
     const int64_t memo_cap = ws ? budget - (int64_t)align_up(scratch_bytes) : (int64_t(4) << 30);
-    const bool use_memo = cfg.leaf == 4 && mode != MODE_PER_ROOT && !iep && g.n_hubs > 0 && memo_eligible(d) &&
-                          n_tasks < (int64_t(1) << 31) && memo_words * 8 <= memo_cap;
+    const bool leaf4_memo = cfg.leaf == 4 && mode != MODE_PER_ROOT && !iep && memo_eligible(d) &&
+                            n_tasks < (int64_t(1) << 31);
+    const bool use_memo = (leaf4_memo || iep_memo_eligible(d)) && g.n_hubs > 0 && memo_words * 8 <= memo_cap;
 
     int32_t* scratch = nullptr;
     unsigned long long* queue = nullptr;
@@ -489,11 +502,13 @@ static gp_status batch_layout(const DeviceGraph& g, const GpPlanDesc* descs, con
         b->runs.back().waves_per_cu = std::max(b->runs.back().waves_per_cu, cfgs[i].waves_per_cu);
         bp.tag_base = 0;
         if (bp.leaf == 4 && !descs[i].iep && g.n_hubs > 0 && memo_eligible(descs[i]) &&
-            tag_next + n_all < (int64_t(1) << 32) - 1) {
+            tag_next + n_all < (int64_t(1) << 31) - 1) {  // below the IEP memo's tags
             bp.tag_base = (uint32_t)tag_next - 1;  // tags tag_base + root + 1 >= tag_next
             tag_next += n_all;
             any_memo = true;
         }
+        // an IEP plan run alone keeps its inner set sizes in the same region
+        if (descs[i].iep && g.n_hubs > 0 && iep_memo_eligible(descs[i])) any_memo = true;
         nbuf = std::max(nbuf, descs[i].nbuf);
         b->kmax = std::max(b->kmax, (int)descs[i].k);
     }
@@ -638,7 +653,9 @@ gp_status batch_enqueue(const DeviceGraph& g, const BatchState& st, hipStream_t 
             a.result = st.result + 4 * p;
             a.per_root = nullptr;
             a.busy = nullptr;
-            a.memo = nullptr;
+            // the IEP memo's tags are vertices, the same in every launch: the
+            // region needs no clearing between runs
+            a.memo = st.memo_words > 0 && d.iep && iep_memo_eligible(d) ? st.memo : nullptr;
             a.chunk = r.chunk;
             a.xcd_block = 0;
             if (r.n_tasks > 0)

@@ -513,6 +513,12 @@ __device__ __forceinline__ uint32_t leaf_group(const GpPlanDesc& d, const Ctx<G>
 // level of a plain count. Each |∩ S_j| walks the shortest operand of the
 // sets involved, cut to the common range, and tests every element in the
 // other operands (a bit in a hub's bitmap, else a binary search).
+constexpr int low_bit(int m) {
+    int i = 0;
+    while (!((m >> i) & 1)) ++i;
+    return i;
+}
+
 // |∩_{j in M} S_j| for one subset M of the inner levels (compile-time).
 template <int K, int G, int MODE, int N, bool GRP, int M>
 __device__ __forceinline__ uint64_t iep_subset_count(const GpPlanDesc& d, const Ctx<G>& c, const int32_t (&v)[K],
@@ -545,6 +551,47 @@ __device__ __forceinline__ uint64_t iep_subset_count(const GpPlanDesc& d, const 
         } else {
             if constexpr (GRP) X[2 * j] = lv.list >= 0 ? c.nbr_u(pick<K>(v, lv.list)) : c.buf_u(lv.buf);
             else X[2 * j] = lv.list >= 0 ? c.nbr(pick<K>(v, lv.list)) : c.buf(lv.buf);
+        }
+    }
+    if constexpr (GRP && (M & (M - 1)) == 0) {
+        // one unbuilt set N(a) & N(x) with no cut, x a hub: its size is a
+        // function of (a, x) alone, kept in the group's memo word of x with
+        // tag a (high bit set, apart from leaf mode 4's root tags). Bindings
+        // that share a and x (roots with the same hub endpoint reach the
+        // same x through many middle vertices) then walk the lists once.
+        constexpr int jj = low_bit(M);
+        const GpLevel& lv = d.lv[F + jj];
+        if (c.memo && lv.last_list >= 0 && lv.pre_buf < 0 && (lv.hi_src | lv.lo_src) == 0) {
+            const int32_t xk = pick<K>(v, lv.last_list);
+            if (xk < c.n_hubs) {
+                const uint32_t tag = 0x80000000u | (uint32_t)(pick<K>(v, lv.pre_list) + 1);
+                const Set A0 = X[2 * jj], A1 = X[2 * jj + 1];
+                const unsigned long long e = c.memo[xk];
+                if constexpr (MODE == MODE_ACCOUNT) bytes += 8;
+                uint64_t raw;
+                if ((uint32_t)(e >> 32) == tag) {
+                    raw = (uint32_t)e;
+                } else {
+                    const Set Wm = A0.n <= A1.n ? A0 : A1, Om = A0.n <= A1.n ? A1 : A0;
+                    if constexpr (MODE == MODE_ACCOUNT) bytes += (uint64_t)Wm.n * (4 + test_bytes(Om)) + 8;
+                    raw = 0;
+                    for (int32_t base = 0; base < Wm.n; base += G) {
+                        const int32_t i = base + c.g.gl;
+                        const bool ok = i < Wm.n && member(Om, Wm.p[i]);
+                        raw += (uint64_t)__popcll(c.g.ballot(ok));
+                    }
+                    if (c.g.gl == 0) c.memo[xk] = ((unsigned long long)tag << 32) | raw;
+                }
+                // outer images in the set (distinct: the binding is injective)
+#pragma unroll
+                for (int o = 0; o < F; ++o)
+                    if ((im >> o) & 1u) {
+                        const int32_t y = v[o];
+                        if constexpr (MODE == MODE_ACCOUNT) bytes += test_bytes(A0) + test_bytes(A1);
+                        if (member(A0, y) && member(A1, y)) --raw;
+                    }
+                return raw;
+            }
         }
     }
     // the shortest operand, cut to [L, H), is walked

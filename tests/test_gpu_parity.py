@@ -762,3 +762,45 @@ def test_batch_with_a_launch_per_plan_equals_oracle():
         parts.append(b.run())
     assert [sum(x) for x in zip(*parts)] == want
     b.close()
+
+
+def test_iep_hub_memo_equals_oracle():
+    """Inner sets of IEP plans left unbuilt as N(a) & N(x) with x a hub have
+    their sizes kept per hub in the group memo: a graph of a few hubs with
+    shared neighbourhoods (many bindings reach the same hub pair) counts the
+    same as the oracle with hubs and without, per root, and in batches that
+    give each plan its own launch (the memo region shared across launches)."""
+    rng = np.random.default_rng(7)
+    n, hubs, deg = 300, 4, 150
+    src, dst = [], []
+    for h in range(hubs):
+        nb = rng.choice(np.arange(hubs, n), size=deg, replace=False)
+        src += [h] * deg
+        dst += list(nb)
+        src += [h] * (hubs - 1 - h)
+        dst += list(range(h + 1, hubs))
+    src += list(rng.integers(hubs, n, 600))
+    dst += list(rng.integers(hubs, n, 600))
+    g = I.csr_from_edges(n, np.array(src), np.array(dst))
+    names = ["house", "4-path", "tailed-triangle", "k4-path", "diamond"]
+    want = [O.count(g, *P[x]) for x in names]
+    k, e = P["house"]
+    forced = dict(force_order=(0, 1, 2, 3, 4), force_restr=[(1, 0)], iep=True)
+    for hub in ("auto", "none"):
+        graph = gp.Graph.from_csr(g, device=True, hub_bitmaps=hub)
+        st = graph.stats()
+        assert (st.hub_vertices > 0) == (hub == "auto")
+        plans = [gp.Plan(*P[x], stats=st, iep=True) for x in names]
+        plans.append(gp.Plan(k, e, stats=st, **forced))
+        ws = want + [want[0]]
+        for p, w in zip(plans, ws):
+            for grp in (64, 32):
+                assert gp.count(graph, p, group=grp, leaf_mode=1) == w, (hub, grp)
+            tot, per = gp.count_per_root(graph, p)
+            assert tot == w and int(per.cpu().numpy().sum()) == w * p.info().iep_div
+        assert gp.count_batch(graph, plans, batch_runs=2) == ws
+        b = gp.Batch(graph, plans, batch_runs=2)
+        for _ in range(3):
+            assert b.run() == ws
+        b.close()
+        graph.close()

@@ -330,8 +330,8 @@ gp_status gp_count_async(const gp_graph* g, const gp_plan* p, const gp_launch* l
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): gp_count_async
  * that allocates nothing. The task cursor, the per-group candidate buffers
- * and, when room is left, the per-group memo (leaf mode 4's per-root counts,
- * or an IEP plan's inner set sizes) come from one static device
+ * and, when room is left, the memo (leaf mode 4's per-root counts per group,
+ * or an IEP plan's shared table of inner set sizes) come from one static device
  * workspace of 32 MiB that every GPU the library runs on holds until the
  * process ends; the grid shrinks so the buffers fit it. dev_out (device
  * memory, 2 uint64, caller-owned) receives {count, flags} as in

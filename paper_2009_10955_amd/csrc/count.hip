@@ -75,7 +75,8 @@ __global__ void zero_u64(unsigned long long* p, int64_t n) {
 // parent of level k-2.
 // IEP plans: some inner set is left unbuilt as N(a) & N(x) with a an outer
 // vertex's list and no cut, so its size depends on (a, x) alone and the
-// kernel keeps it per hub x (count_kernel.hpp, iep_subset_count).
+// kernel keeps it in a table shared by the launch's groups
+// (count_kernel.hpp, iep_subset_count).
 bool iep_memo_eligible(const GpPlanDesc& d) {
     if (!d.iep) return false;
     for (int j = d.k - d.iep; j < d.k; ++j) {
@@ -83,6 +84,16 @@ bool iep_memo_eligible(const GpPlanDesc& d) {
         if (lv.last_list >= 0 && lv.pre_buf < 0 && lv.pre_list >= 0 && (lv.hi_src | lv.lo_src) == 0) return true;
     }
     return false;
+}
+
+// log2 of the IEP memo's words per hub: the most ways, up to
+// kIepMemoWaysMax, whose table of n_hubs x ways words fits words_cap
+// words; -1 if not even one way fits.
+int iep_memo_log2(int64_t n_hubs, int64_t words_cap) {
+    if (n_hubs <= 0 || words_cap < n_hubs) return -1;
+    int l = 0;
+    while ((int64_t(2) << l) <= kIepMemoWaysMax && (n_hubs << (l + 1)) <= words_cap) ++l;
+    return l;
 }
 
 bool memo_eligible(const GpPlanDesc& d) {
@@ -268,12 +279,16 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
 
     const size_t scratch_bytes = (size_t)(blocks * per_block);
     // leaf mode 4's per-task memo: one word per hub per group, within 4 GiB
-    // (within what the workspace has left)
-    const int64_t memo_words = blocks * groups_per_block * (int64_t)g.n_hubs;
+    // (within what the workspace has left); the IEP memo: one table for the
+    // launch, 2^l words per hub, within 2 GiB (or the room left)
     const int64_t memo_cap = ws ? budget - (int64_t)align_up(scratch_bytes) : (int64_t(4) << 30);
+    const int iep_log2 =
+        iep && iep_memo_eligible(d) ? iep_memo_log2(g.n_hubs, std::min(memo_cap, kIepMemoBytes) / 8) : -1;
+    const int64_t memo_words = iep ? (iep_log2 >= 0 ? (int64_t)g.n_hubs << iep_log2 : 0)
+                                   : blocks * groups_per_block * (int64_t)g.n_hubs;
     const bool leaf4_memo = cfg.leaf == 4 && mode != MODE_PER_ROOT && !iep && memo_eligible(d) &&
                             n_tasks < (int64_t(1) << 31);
-    const bool use_memo = (leaf4_memo || iep_memo_eligible(d)) && g.n_hubs > 0 && memo_words * 8 <= memo_cap;
+    const bool use_memo = (leaf4_memo || iep_log2 >= 0) && g.n_hubs > 0 && memo_words * 8 <= memo_cap;
 
     int32_t* scratch = nullptr;
     unsigned long long* queue = nullptr;
@@ -328,6 +343,7 @@ gp_status launch_count(const DeviceGraph& g, const GpPlanDesc& d, const LaunchCf
     a.busy = busy;
     a.memo = memo;
     a.chunk = cfg.chunk;
+    a.memo_ways_log2 = std::max(iep_log2, 0);
     a.xcd_block = xcd_block_tasks(g, cfg, group);
     if (n_tasks > 0)
         hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kBlock), 0, stream, d, a);
@@ -570,6 +586,13 @@ gp_status batch_prepare(const DeviceGraph& g, const GpPlanDesc* descs, const Lau
         slots = std::max(slots, run_group_slots(r));
     }
     b.memo_words = b.use_memo ? slots * (int64_t)g.n_hubs : 0;
+    // room for the IEP memo's most ways when an eligible IEP plan runs alone
+    for (const BatchRun& r : b.runs)
+        for (int p = r.p0; p < r.p1 && b.use_memo; ++p)
+            if (r.solo && descs[p].iep && iep_memo_eligible(descs[p])) {
+                const int l = iep_memo_log2(g.n_hubs, kIepMemoBytes / 8);
+                if (l >= 0) b.memo_words = std::max(b.memo_words, (int64_t)g.n_hubs << l);
+            }
     if (hipMalloc((void**)&b.queues, sizeof(unsigned long long) * np) != hipSuccess ||
         hipMalloc((void**)&b.run_queues, sizeof(unsigned long long) * kBatchMaxPlans * kQueueWords) != hipSuccess ||
         hipMalloc((void**)&b.result, 4 * sizeof(unsigned long long) * np) != hipSuccess ||
@@ -653,9 +676,13 @@ gp_status batch_enqueue(const DeviceGraph& g, const BatchState& st, hipStream_t 
             a.result = st.result + 4 * p;
             a.per_root = nullptr;
             a.busy = nullptr;
-            // the IEP memo's tags are vertices, the same in every launch: the
-            // region needs no clearing between runs
-            a.memo = st.memo_words > 0 && d.iep && iep_memo_eligible(d) ? st.memo : nullptr;
+            // the IEP memo holds sizes fixed by the graph, valid in every
+            // launch: the region needs no clearing between runs
+            const int iep_log2 = d.iep && iep_memo_eligible(d) && st.memo_words > 0
+                                     ? iep_memo_log2(g.n_hubs, std::min(st.memo_words, kIepMemoBytes / 8))
+                                     : -1;
+            a.memo = iep_log2 >= 0 ? st.memo : nullptr;
+            a.memo_ways_log2 = std::max(iep_log2, 0);
             a.chunk = r.chunk;
             a.xcd_block = 0;
             if (r.n_tasks > 0)

@@ -53,6 +53,7 @@ __device__ void run_piece(const BatchArgs& a, const GpPlanDesc& d, const BatchPl
     c.deadline = 0;
     c.memo = (a.memo && bp.tag_base) ? a.memo + slot * (int64_t)a.n_hubs : nullptr;
     c.tag = 0;
+    c.memo_log2 = 0;
     TaskSpace ts;
     ts.roots = bp.roots;
     ts.offset = bp.root_offset;

@@ -95,8 +95,11 @@ struct CountArgs {
     uint64_t budget_ticks;
     // optional (leaf mode 4, plans the host found eligible): per group,
     // n_hubs words {root tag, |N(x) & pre & cut|} for hub candidates x
+    // or (IEP plans the host found eligible) one table for the launch of
+    // n_hubs << memo_ways_log2 words {a + 1 with the high bit set, |N(a) & N(x)|}
     unsigned long long* memo;
     int32_t chunk;
+    int32_t memo_ways_log2;
     // > 0: the task space is dealt to the XCDs in blocks of xcd_block tasks
     // (a multiple of chunk): block b goes to XCD b mod kXcds, each XCD takes
     // its blocks in order from its own cursor and then helps the others; 0:
@@ -220,8 +223,9 @@ struct Ctx {
     int32_t n_hubs;
     int32_t sj, sJ;     // level-2 slice of the current task: candidates sj, sj + sJ, ...
     uint64_t deadline;  // clock tick after which every search loop stops (0: none)
-    unsigned long long* memo;  // this group's last-level memo (null: none)
+    unsigned long long* memo;  // this group's last-level memo, or the launch's IEP memo (null: none)
     uint32_t tag;              // memo validity tag of the current root
+    int32_t memo_log2;         // IEP memo: log2 of its words per hub
     Group<G> g;
 
     __device__ __forceinline__ bool expired() const {
@@ -513,6 +517,13 @@ __device__ __forceinline__ uint32_t leaf_group(const GpPlanDesc& d, const Ctx<G>
 // level of a plain count. Each |∩ S_j| walks the shortest operand of the
 // sets involved, cut to the common range, and tests every element in the
 // other operands (a bit in a hub's bitmap, else a binary search).
+// The IEP memo: one table per launch, shared by every group, of W = 2^l
+// words per hub (l = CountArgs::memo_ways_log2). Word x * W + (a mod W)
+// holds |N(a) & N(x)| tagged a. The host takes the most ways, up to
+// kIepMemoWaysMax, whose table fits kIepMemoBytes (or the room left).
+constexpr int64_t kIepMemoWaysMax = 4096;
+constexpr int64_t kIepMemoBytes = int64_t(2) << 30;
+
 constexpr int low_bit(int m) {
     int i = 0;
     while (!((m >> i) & 1)) ++i;
@@ -555,18 +566,26 @@ __device__ __forceinline__ uint64_t iep_subset_count(const GpPlanDesc& d, const 
     }
     if constexpr (GRP && (M & (M - 1)) == 0) {
         // one unbuilt set N(a) & N(x) with no cut, x a hub: its size is a
-        // function of (a, x) alone, kept in the group's memo word of x with
-        // tag a (high bit set, apart from leaf mode 4's root tags). Bindings
-        // that share a and x (roots with the same hub endpoint reach the
-        // same x through many middle vertices) then walk the lists once.
+        // function of (a, x) alone, the same for every plan, group and launch
+        // on the graph. It is kept in the launch's shared memo table, in the
+        // word of x chosen by a, tagged a (high bit set, apart from leaf mode
+        // 4's root tags). Bindings that share a and x (roots with the same
+        // hub endpoint reach the same x through many middle vertices, in
+        // every group working on that endpoint) then walk the lists once.
+        // Tag and size share one 64-bit word, written and read whole, so a
+        // word another group overwrote, or one not yet visible, only ever
+        // reads as a miss.
         constexpr int jj = low_bit(M);
         const GpLevel& lv = d.lv[F + jj];
         if (c.memo && lv.last_list >= 0 && lv.pre_buf < 0 && (lv.hi_src | lv.lo_src) == 0) {
             const int32_t xk = pick<K>(v, lv.last_list);
             if (xk < c.n_hubs) {
-                const uint32_t tag = 0x80000000u | (uint32_t)(pick<K>(v, lv.pre_list) + 1);
+                const int32_t av = pick<K>(v, lv.pre_list);
+                const uint32_t tag = 0x80000000u | (uint32_t)(av + 1);
                 const Set A0 = X[2 * jj], A1 = X[2 * jj + 1];
-                const unsigned long long e = c.memo[xk];
+                unsigned long long* const w =
+                    c.memo + ((int64_t)xk << c.memo_log2) + (av & ((int32_t(1) << c.memo_log2) - 1));
+                const unsigned long long e = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if constexpr (MODE == MODE_ACCOUNT) bytes += 8;
                 uint64_t raw;
                 if ((uint32_t)(e >> 32) == tag) {
@@ -580,7 +599,9 @@ __device__ __forceinline__ uint64_t iep_subset_count(const GpPlanDesc& d, const 
                         const bool ok = i < Wm.n && member(Om, Wm.p[i]);
                         raw += (uint64_t)__popcll(c.g.ballot(ok));
                     }
-                    if (c.g.gl == 0) c.memo[xk] = ((unsigned long long)tag << 32) | raw;
+                    if (c.g.gl == 0)
+                        __hip_atomic_store(w, ((unsigned long long)tag << 32) | raw, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
                 }
                 // outer images in the set (distinct: the binding is injective)
 #pragma unroll
@@ -1277,8 +1298,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(occupanc
     c.bytes = &bytes;
     c.sj = 0;
     c.sJ = 1;
-    c.memo = a.memo ? a.memo + group_id * (int64_t)a.n_hubs : nullptr;
+    // leaf mode 4: a table per group; IEP: one table for the launch
+    c.memo = a.memo ? (IEP > 0 ? a.memo : a.memo + group_id * (int64_t)a.n_hubs) : nullptr;
     c.tag = 0;
+    c.memo_log2 = a.memo_ways_log2;
     const uint64_t t_begin = a.busy ? wall_clock64() : 0;
     c.deadline = a.busy && a.budget_ticks ? t_begin + a.budget_ticks : 0;
     uint64_t chunk_max = 0;

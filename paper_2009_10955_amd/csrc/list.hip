@@ -279,6 +279,7 @@ __global__ __launch_bounds__(kBlock) void list_kernel(GpPlanDesc d, ListArgs a) 
     c.deadline = 0;
     c.memo = nullptr;
     c.tag = 0;
+    c.memo_log2 = 0;
     const int64_t chunk = a.chunk;
     for (;;) {
         unsigned long long t0 = 0;

@@ -766,10 +766,12 @@ def test_batch_with_a_launch_per_plan_equals_oracle():
 
 def test_iep_hub_memo_equals_oracle():
     """Inner sets of IEP plans left unbuilt as N(a) & N(x) with x a hub have
-    their sizes kept per hub in the group memo: a graph of a few hubs with
-    shared neighbourhoods (many bindings reach the same hub pair) counts the
-    same as the oracle with hubs and without, per root, and in batches that
-    give each plan its own launch (the memo region shared across launches)."""
+    their sizes kept in a table shared by every group of the launch: a graph
+    of a few hubs with shared neighbourhoods (many bindings, in many groups,
+    reach the same hub pair) counts the same as the oracle with hubs and
+    without, per root, and in batches that give each plan its own launch
+    (the table shared across launches). A second graph counted after the
+    first, on the same device, starts from a cleared table."""
     rng = np.random.default_rng(7)
     n, hubs, deg = 300, 4, 150
     src, dst = [], []
@@ -804,3 +806,8 @@ def test_iep_hub_memo_equals_oracle():
             assert b.run() == ws
         b.close()
         graph.close()
+    g2 = I.er(200, 0.08, seed=21)
+    graph = gp.Graph.from_csr(g2, device=True, hub_bitmaps="dense")
+    p2 = gp.Plan(k, e, stats=graph.stats(), **forced)
+    assert gp.count(graph, p2, group=64, leaf_mode=1) == O.count(g2, k, e)
+    graph.close()

@@ -315,7 +315,12 @@ void gp_free_plan(gp_plan* p);
  * (the first two schedule levels) from an atomic queue and search the
  * remaining levels depth first. Blocking: synchronises `stream` and writes
  * *out on the host. GP_ERR_OVERFLOW if the count does not fit in 64 bits.
- * `launch` may be null (auto).
+ * `launch` may be null (auto). Device memory, allocated stream-ordered per
+ * call and freed at its end: the groups' candidate buffers (at most 16 GiB;
+ * the grid shrinks to fit) and, for plans that can use one, a memo table
+ * (leaf mode 4: a word per hub per group, at most 4 GiB; inclusion-exclusion:
+ * one table for the launch, at most 2 GiB). GP_ERR_NOMEM when an
+ * allocation fails.
  */
 gp_status gp_count(const gp_graph* g, const gp_plan* p, const gp_launch* launch, void* stream,
                    uint64_t* out);

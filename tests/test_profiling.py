@@ -60,3 +60,51 @@ def test_traffic_summary_scales_by_the_copy_kernel(tmp_path):
     assert s["hbm_bytes_per_launch"] == 100 * 1024 * 2 + 10 * 1024
     assert s["l2"]["hit_rate"] == 0.9
     assert s["plan"] == PLAN and s["kernel_source_hash"] == profiling.kernel_source_hash()
+
+
+def _write_db(path, rows):
+    """A database shaped like rocprofv3's SQLite output: only the
+    counters_collection view's columns the summaries read."""
+    import sqlite3
+    con = sqlite3.connect(path)
+    con.execute("CREATE TABLE counters_collection (dispatch_id INTEGER, kernel_name TEXT, "
+                "counter_name TEXT, value REAL)")
+    con.executemany("INSERT INTO counters_collection VALUES (?, ?, ?, ?)", rows)
+    con.commit()
+    con.close()
+
+
+def test_traffic_summary_from_sqlite_databases(tmp_path):
+    """The same scaling from rocprofv3's SQLite output (*.db globs): values
+    of one dispatch summed over the counter's instances, the longest
+    dispatch of the kernel kept, the copy kernel calibrating each counter."""
+    mib = 1 << 20
+    k = "void gpcount::count_kernel<5, 64, 1, 0, 2>(GpPlanDesc, gpcount::CountArgs)"
+    _write_db(tmp_path / "f_results.db", [
+        (1, "__amd_rocclr_copyBuffer", "FETCH_SIZE", 300), (1, "__amd_rocclr_copyBuffer", "FETCH_SIZE", 212),
+        (2, k, "FETCH_SIZE", 60), (2, k, "FETCH_SIZE", 40), (3, k, "FETCH_SIZE", 70)])
+    _write_db(tmp_path / "w_results.db", [
+        (1, "__amd_rocclr_copyBuffer", "WRITE_SIZE", 1024), (2, k, "WRITE_SIZE", 8), (2, k, "WRITE_SIZE", 2)])
+    _write_db(tmp_path / "l_results.db", [
+        (2, k, "TCC_HIT_sum", 30), (2, k, "TCC_MISS_sum", 70)])
+    s = profiling.traffic_summary(str(tmp_path / "f_*.db"), str(tmp_path / "w_*.db"), "count_kernel", mib,
+                                  "all", "rmat22", PLAN, str(tmp_path / "l_*.db"))
+    assert s["copy_fetch_kib"] == 512 and s["fetch_scale"] == 2.0 and s["write_scale"] == 1.0
+    assert s["fetch_kib"] == 100 and s["write_kib"] == 10
+    assert s["hbm_bytes_per_launch"] == 100 * 1024 * 2 + 10 * 1024
+    assert s["l2"]["hit_rate"] == 0.3
+
+
+def test_stored_traffic_applies_only_to_the_current_kernel_sources(tmp_path):
+    """A summary is returned only while the kernel sources hash as they did
+    when its counters were taken; a missing or unreadable file gives none."""
+    import json
+    good = {"workload": "rmat22", "hbm_bytes_per_launch": 1.0,
+            "kernel_source_hash": profiling.kernel_source_hash()}
+    (tmp_path / "good.json").write_text(json.dumps(good))
+    (tmp_path / "old.json").write_text(json.dumps(dict(good, kernel_source_hash="0" * 16)))
+    (tmp_path / "bad.json").write_text("{not json")
+    assert profiling.load_traffic(str(tmp_path / "good.json")) == good
+    assert profiling.load_traffic(str(tmp_path / "old.json")) is None
+    assert profiling.load_traffic(str(tmp_path / "bad.json")) is None
+    assert profiling.load_traffic(str(tmp_path / "missing.json")) is None

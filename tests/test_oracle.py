@@ -232,6 +232,57 @@ def test_every_emitted_set_breaks_every_symmetry_exactly_once(pname):
         assert O.count_maps(g0, k, e, restr=s) * len(auts) == all_maps0
 
 
+def test_count_restricted_equals_the_subgraph_count():
+    """count_restricted (maps obeying a restriction set, no division) is the
+    subgraph count for every emitted set, on a graph checked exhaustively
+    elsewhere; brute force over all injective tuples agrees."""
+    g = I.er(9, 0.6, seed=12)
+    for pname in ["house", "5-cycle", "tailed-triangle"]:
+        k, e = P[pname]
+        want = O.count(g, k, e)
+        for s in O.restriction_sets(k, e):
+            assert O.count_restricted(g, k, e, s) == want
+            assert O.brute_force_maps(g, k, e, s) == want
+
+
+# independence numbers worked out by hand from the edge lists (a largest set
+# of pairwise non-adjacent pattern vertices is named for each)
+ALPHA = {"edge": 1, "triangle": 1, "4-clique": 1, "5-clique": 1, "6-clique": 1,
+         "4-cycle": 2,          # {0, 2}
+         "house": 2,            # {2, 4}
+         "5-cycle": 2,          # {0, 2}
+         "6-cycle": 3,          # {0, 2, 4}
+         "6-cycle-chord": 3,    # {1, 3, 5}
+         "prism": 2,            # one vertex per triangle, not matched
+         "k4-path": 2,          # {0, 4}: one K4 vertex, one of 4, 5
+         "5-wheel": 2,          # two of the rim
+         "4-path": 2, "5-path": 3,  # alternate vertices of the path
+         "3-star": 3, "4-star": 4, "5-star": 5, "6-star": 6,  # the leaves
+         "tailed-triangle": 2,  # {0, 3}
+         "diamond": 2,          # {1, 3}
+         "spider": 3}           # {3, 4, 5}
+
+
+@pytest.mark.parametrize("pname", sorted(ALPHA))
+def test_independence_number_hand_values(pname):
+    """The bound on the inner loops that Phase 2 and IEP use (Section IV-B,
+    IV-D): the largest independent set of the pattern, and no schedule ends
+    in more independent vertices than it."""
+    k, e = P[pname]
+    assert O.independence_number(k, O._adj(k, e)) == ALPHA[pname]
+    _, keff = O.efficient_schedules(k, e)
+    assert 1 <= keff <= ALPHA[pname]
+
+
+def test_iep_kept_drops_restrictions_on_the_inner_loops():
+    """With the last n_inner schedule vertices counted by inclusion-exclusion,
+    only the restrictions between outer vertices are still checked."""
+    res = [(1, 0), (4, 2), (3, 0), (2, 1)]
+    assert O.iep_kept(5, (0, 1, 2, 3, 4), res, 2) == [(1, 0), (2, 1)]
+    assert O.iep_kept(5, (4, 3, 2, 1, 0), res, 2) == [(4, 2)]
+    assert O.iep_kept(5, (0, 1, 2, 3, 4), res, 0) == res
+
+
 def test_invalid_set_is_rejected_by_validate():
     k, e = P["4-cycle"]
     assert not O.validate(k, e, [(0, 1)])                  # too few restrictions
